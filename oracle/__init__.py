@@ -1,0 +1,3 @@
+"""CPU oracle (test infrastructure only; never imported by the product path)."""
+
+from .seminaive import Fixpoint, sg, sg_batch, tc, tc_batch  # noqa: F401

@@ -1,0 +1,58 @@
+"""Write expected fixpoint summaries for the full-size workloads.
+
+Every value stored here comes from the CPU oracle (``oracle/``) run on the seeded
+inputs of ``paper_2607_17571_amd.inputs``; nothing is taken from the GPU path.
+Run from the repository root:
+
+    python tests/golden/make_golden.py [workload ...]
+
+Output: tests/golden/fixpoints.json, one record per workload with the fixpoint
+size, the iteration count, |Delta^i| per iteration, the candidate total and the
+sha256 of the result bytes (little-endian uint32 src array followed by the dst
+array, lexicographically sorted).
+"""
+
+import hashlib
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import oracle  # noqa: E402
+from paper_2607_17571_amd import inputs  # noqa: E402
+
+DEFAULT = ["tc_er_2000", "sg_er_500k", "tc_rmat_s15", "tc_rmat_s15_ids24", "tc_grid_100"]
+
+
+def summarise(r):
+    h = hashlib.sha256(r.src.astype("<u4").tobytes() + r.dst.astype("<u4").tobytes()).hexdigest()
+    return {"size": int(r.src.size), "iterations": r.iterations,
+            "delta_sizes": r.delta_sizes, "candidates": r.candidates, "sha256": h}
+
+
+def main(names):
+    path = os.path.join(HERE, "fixpoints.json")
+    data = json.load(open(path)) if os.path.exists(path) else {}
+    for name in names:
+        w = inputs.workload(name)
+        t0 = time.time()
+        r = oracle.tc(w.src, w.dst) if w.query == "tc" else oracle.sg(w.src, w.dst)
+        rec = summarise(r)
+        rec["query"] = w.query
+        rec["edges"] = int(w.src.size)
+        data[name] = rec
+        if w.query == "sg":
+            data[name + "_irreflexive"] = dict(
+                summarise(oracle.sg(w.src, w.dst, irreflexive=True)), query="sg", edges=int(w.src.size))
+        print(f"{name}: |fixpoint|={rec['size']} iterations={rec['iterations']} "
+              f"({time.time() - t0:.1f} s)", flush=True)
+        with open(path, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+            f.write("\n")
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:] or DEFAULT)
