@@ -1,0 +1,153 @@
+/*
+ * wg.h -- C ABI of the MI355X semi-naive fixpoint engine (TC and SG).
+ *
+ * The engine evaluates two Datalog programs over a directed edge relation E of
+ * (uint32 src, uint32 dst) pairs and returns the least fixpoint as a
+ * lexicographically sorted, duplicate-free pair array:
+ *
+ *   TC  T(x,y) <- E(x,y).            T(x,z) <- T(x,y), E(y,z).
+ *       (paper Section II, the running example)
+ *   SG  SG(x,y) <- E(p,x), E(p,y), x != y.
+ *       SG(x,y) <- E(a,x), SG(a,b), E(b,y).
+ *       (paper Section VI, same-generation; E is oriented parent -> child)
+ *
+ * Evaluation is semi-naive (Section II, "Semi-Naive Evaluation"): Delta^0 = Full =
+ * the base facts; iteration i joins Delta^{i-1} with E, sorts the candidates,
+ * drops duplicates and tuples already in Full, merges the survivors Delta^i into
+ * Full and stops at the first empty Delta^i.  Every stage runs in HIP kernels on
+ * one GPU and the loop stays on the device between batch boundaries
+ * (Section V-B: the host only learns when the fixpoint terminates).
+ *
+ * Conventions shared by every entry point:
+ *  - Every call returns wg_status; nothing throws, aborts or exits across the ABI.
+ *  - Pointers named d_* are device pointers on the engine's device.  Host pointers
+ *    are accepted only where a comment says so.
+ *  - `stream` is a hipStream_t of the engine's device (NULL = the null stream).
+ *    Calls are ordered on it.  Input arrays are read before the call returns.
+ *  - Input edges are a multiset in any order.  Duplicates collapse; self-loops are
+ *    ordinary edges; any uint32 id is valid (no sentinel values).  m = 0 gives an
+ *    empty result.
+ *  - Results are exact: one byte string per input, independent of batch sizes,
+ *    loop mode or launch shapes.
+ *  - On error no result is produced and *out stays NULL.  The engine stays usable
+ *    after every status except WG_ERR_DEVICE.
+ *  - An engine is not thread-safe; use one engine per host thread / stream.
+ */
+#ifndef WG_H_
+#define WG_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  WG_OK = 0,
+  WG_ERR_INVALID_ARG = 1,   /* bad pointer, size or option */
+  WG_ERR_OUT_OF_MEMORY = 2, /* the device allocator failed */
+  WG_ERR_CAPACITY = 3,      /* the fixpoint needs more device memory than mem_budget_bytes */
+  WG_ERR_DEVICE = 4,        /* a HIP call failed or a device wait expired; destroy the engine */
+  WG_ERR_ITER_LIMIT = 5,    /* max_iterations reached before the fixpoint */
+  WG_ERR_STALE = 6          /* the result belongs to an earlier solve of this engine */
+} wg_status;
+
+typedef enum { WG_QUERY_TC = 0, WG_QUERY_SG = 1 } wg_query;
+
+/* wg_options.flags */
+#define WG_SG_IRREFLEXIVE 0x1u /* SG: drop (x,x) from the final relation */
+#define WG_STAGE_TIMING 0x2u   /* time every kernel launch with HIP events (fills stage_ms) */
+
+/* wg_options.loop_mode */
+#define WG_LOOP_AUTO 0u     /* the default: batched device-resident loop */
+#define WG_LOOP_BATCHED 1u  /* K iterations per host check (Section V-B, batched recording) */
+#define WG_LOOP_HOST 2u     /* one host check per iteration (K = 1); reference mode */
+
+typedef struct {
+  uint32_t struct_size;      /* sizeof(wg_options); older sizes are accepted */
+  uint32_t flags;            /* WG_SG_IRREFLEXIVE, WG_STAGE_TIMING */
+  uint32_t batch_k;          /* iterations per host check; 0 = 30 with halving for TC,
+                                10 fixed for SG (Section V-B, adaptive batch sizing) */
+  uint32_t loop_mode;        /* WG_LOOP_* */
+  uint32_t radix_field_bits; /* 0 = from the largest id: 16, 24 or 32 (Section V-C);
+                                else 16, 24 or 32, which must cover the largest id */
+  uint32_t reserved;
+  uint64_t max_iterations;   /* 0 = unlimited */
+  uint64_t mem_budget_bytes; /* 0 = no limit beyond the device allocator */
+  uint64_t force_overflow_at_iter; /* test hook: report a capacity overflow once at this
+                                      iteration (1-based) to exercise grow-and-resume */
+} wg_options;
+
+/* Kernel kinds reported in wg_stats.stage_ms / stage_launches / stage_bytes. */
+enum {
+  WG_STAGE_JOIN_COUNT = 0, /* binary-search range lookup + count scan (Section IV-A) */
+  WG_STAGE_JOIN_EMIT = 1,  /* candidate emission into scanned slabs (Section IV-A) */
+  WG_STAGE_RADIX_HIST = 2, /* digit histograms of all passes (Section V-C) */
+  WG_STAGE_RADIX_PASS = 3, /* one stable 8-bit LSD scatter pass (Section V-C) */
+  WG_STAGE_DEDUP_DIFF = 4, /* fused dedup + set difference (Section IV-B) */
+  WG_STAGE_MERGE = 5,      /* disjoint merge-path merge (Section IV-C) */
+  WG_STAGE_PREPARE = 6,    /* max-id scan, packing, edge index, result unpack */
+  WG_NUM_STAGES = 7
+};
+
+typedef struct {
+  uint64_t iterations;      /* join rounds, including the one that found the empty delta */
+  uint64_t result_tuples;   /* |fixpoint| */
+  uint64_t base_tuples;     /* |Delta^0| */
+  uint64_t join_candidates; /* candidates summed over iterations, with multiplicity */
+  uint64_t host_syncs;      /* host waits on the device during the call */
+  uint64_t resumes;         /* grow-and-resume cycles after a capacity overflow */
+  uint32_t field_bits;      /* radix field width used (16, 24, 32) */
+  uint32_t key_bytes;       /* bytes per packed key (4 or 8) */
+  double solve_ms;          /* host wall clock of the call */
+  double stage_ms[WG_NUM_STAGES];        /* with WG_STAGE_TIMING: summed kernel time */
+  uint64_t stage_launches[WG_NUM_STAGES];
+  uint64_t stage_bytes[WG_NUM_STAGES];   /* algorithmic HBM bytes of each kernel kind */
+  uint64_t* delta_sizes;    /* optional caller HOST buffer: |Delta^0| .. |Delta^iterations| */
+  uint64_t delta_sizes_cap; /* its capacity in entries (filled up to the capacity) */
+} wg_stats;
+
+typedef struct wg_engine wg_engine; /* per device: buffers, control block, lookback state */
+typedef struct wg_result wg_result; /* a device-resident fixpoint owned by the caller */
+
+/* Create an engine on HIP device `device`.  Allocates the control block and
+ * lookback state; relation buffers grow on demand and are reused across calls. */
+wg_status wg_engine_create(int device, wg_engine** out);
+
+/* Free every device allocation of the engine.  Results of the engine become invalid. */
+void wg_engine_destroy(wg_engine* engine);
+
+/* Transitive closure of the m edges (d_src[i], d_dst[i]) (Section II; semi-naive loop,
+ * Sections IV and V).  On WG_OK *out holds the fixpoint; stats (nullable) is filled. */
+wg_status wg_tc(wg_engine* engine, const uint32_t* d_src, const uint32_t* d_dst, uint64_t m,
+                const wg_options* options, void* stream, wg_result** out, wg_stats* stats);
+
+/* Same-generation fixpoint of the m edges, E(parent, child) (Section VI). */
+wg_status wg_sg(wg_engine* engine, const uint32_t* d_src, const uint32_t* d_dst, uint64_t m,
+                const wg_options* options, void* stream, wg_result** out, wg_stats* stats);
+
+/* Number of tuples in the result (for a batch: over all instances). */
+uint64_t wg_result_size(const wg_result* result);
+
+/* Unpack the result into split arrays src_out[0..n), dst_out[0..n), n = wg_result_size,
+ * lexicographically sorted.  Both pointers are device pointers, or both host pointers
+ * (then the call waits for the copy).  capacity is the length of each array.
+ * Returns WG_ERR_STALE when the engine has started another solve since. */
+wg_status wg_result_copy(const wg_result* result, uint32_t* src_out, uint32_t* dst_out,
+                         uint64_t capacity, void* stream);
+
+/* Release a result handle (the storage belongs to the engine until its next solve). */
+void wg_result_free(wg_result* result);
+
+/* Static text for a status code. */
+const char* wg_status_string(wg_status status);
+
+/* Detail of the most recent failure on the engine ("" if none). */
+const char* wg_last_error(const wg_engine* engine);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WG_H_ */

@@ -1,0 +1,270 @@
+"""ctypes binding of the C ABI in include/wg.h.
+
+The functions named like the C entry points (``wg_tc``, ``wg_sg``, ``wg_result_copy``
+...) only marshal arguments; every step of the fixpoint runs in the HIP library.
+``tc`` / ``sg`` are conveniences over them that take and return torch tensors on the
+GPU (torch supplies device memory and the stream, nothing else).
+
+The library must be built (``python -m paper_2607_17571_amd.build``); importing this
+module does not build it, and every call fails loudly when it is missing.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_char_p, c_double, c_int, c_uint32, c_uint64, c_void_p
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libwg.so")
+
+WG_OK = 0
+WG_ERR_INVALID_ARG = 1
+WG_ERR_OUT_OF_MEMORY = 2
+WG_ERR_CAPACITY = 3
+WG_ERR_DEVICE = 4
+WG_ERR_ITER_LIMIT = 5
+WG_ERR_STALE = 6
+
+WG_SG_IRREFLEXIVE = 0x1
+WG_STAGE_TIMING = 0x2
+
+WG_LOOP_AUTO = 0
+WG_LOOP_BATCHED = 1
+WG_LOOP_HOST = 2
+
+STAGES = ["join_count", "join_emit", "radix_hist", "radix_pass", "dedup_diff", "merge", "prepare"]
+WG_NUM_STAGES = len(STAGES)
+
+
+class WgOptions(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", c_uint32),
+        ("flags", c_uint32),
+        ("batch_k", c_uint32),
+        ("loop_mode", c_uint32),
+        ("radix_field_bits", c_uint32),
+        ("reserved", c_uint32),
+        ("max_iterations", c_uint64),
+        ("mem_budget_bytes", c_uint64),
+        ("force_overflow_at_iter", c_uint64),
+    ]
+
+
+class WgStats(ctypes.Structure):
+    _fields_ = [
+        ("iterations", c_uint64),
+        ("result_tuples", c_uint64),
+        ("base_tuples", c_uint64),
+        ("join_candidates", c_uint64),
+        ("host_syncs", c_uint64),
+        ("resumes", c_uint64),
+        ("field_bits", c_uint32),
+        ("key_bytes", c_uint32),
+        ("solve_ms", c_double),
+        ("stage_ms", c_double * WG_NUM_STAGES),
+        ("stage_launches", c_uint64 * WG_NUM_STAGES),
+        ("stage_bytes", c_uint64 * WG_NUM_STAGES),
+        ("delta_sizes", POINTER(c_uint64)),
+        ("delta_sizes_cap", c_uint64),
+    ]
+
+
+class WgError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"{_status_name(status)}: {detail}")
+        self.status = status
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported entry point.
+SIGNATURES = [
+    ("wg_engine_create", c_int, [c_int, POINTER(c_void_p)]),
+    ("wg_engine_destroy", None, [c_void_p]),
+    ("wg_tc", c_int, [c_void_p, c_void_p, c_void_p, c_uint64, POINTER(WgOptions), c_void_p,
+                      POINTER(c_void_p), POINTER(WgStats)]),
+    ("wg_sg", c_int, [c_void_p, c_void_p, c_void_p, c_uint64, POINTER(WgOptions), c_void_p,
+                      POINTER(c_void_p), POINTER(WgStats)]),
+    ("wg_result_size", c_uint64, [c_void_p]),
+    ("wg_result_copy", c_int, [c_void_p, c_void_p, c_void_p, c_uint64, c_void_p]),
+    ("wg_result_free", None, [c_void_p]),
+    ("wg_status_string", c_char_p, [c_int]),
+    ("wg_last_error", c_char_p, [c_void_p]),
+]
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library missing: {LIB_PATH} (run python -m paper_2607_17571_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _status_name(status: int) -> str:
+    try:
+        return lib().wg_status_string(status).decode()
+    except Exception:  # noqa: BLE001 - only for messages
+        return f"status {status}"
+
+
+# ----------------------------------------------------------------------------
+# Entry points with the C names (argument marshalling only).
+# ----------------------------------------------------------------------------
+
+def wg_engine_create(device: int = 0) -> c_void_p:
+    eng = c_void_p()
+    st = lib().wg_engine_create(device, byref(eng))
+    if st != WG_OK:
+        raise WgError(st, f"wg_engine_create(device={device})")
+    return eng
+
+
+def wg_engine_destroy(engine) -> None:
+    lib().wg_engine_destroy(engine)
+
+
+def wg_tc(engine, d_src: int, d_dst: int, m: int, options: WgOptions | None, stream: int,
+          stats: WgStats | None = None):
+    """Returns (status, result handle)."""
+    res = c_void_p()
+    st = lib().wg_tc(engine, c_void_p(d_src), c_void_p(d_dst), m,
+                     byref(options) if options is not None else None, c_void_p(stream),
+                     byref(res), byref(stats) if stats is not None else None)
+    return st, res
+
+
+def wg_sg(engine, d_src: int, d_dst: int, m: int, options: WgOptions | None, stream: int,
+          stats: WgStats | None = None):
+    res = c_void_p()
+    st = lib().wg_sg(engine, c_void_p(d_src), c_void_p(d_dst), m,
+                     byref(options) if options is not None else None, c_void_p(stream),
+                     byref(res), byref(stats) if stats is not None else None)
+    return st, res
+
+
+def wg_result_size(result) -> int:
+    return int(lib().wg_result_size(result))
+
+
+def wg_result_copy(result, src_out: int, dst_out: int, capacity: int, stream: int) -> int:
+    return lib().wg_result_copy(result, c_void_p(src_out), c_void_p(dst_out), capacity, c_void_p(stream))
+
+
+def wg_result_free(result) -> None:
+    lib().wg_result_free(result)
+
+
+def wg_status_string(status: int) -> str:
+    return lib().wg_status_string(status).decode()
+
+
+def wg_last_error(engine) -> str:
+    return lib().wg_last_error(engine).decode()
+
+
+# ----------------------------------------------------------------------------
+# torch conveniences
+# ----------------------------------------------------------------------------
+
+def make_options(flags: int = 0, batch_k: int = 0, loop_mode: int = WG_LOOP_AUTO,
+                 radix_field_bits: int = 0, max_iterations: int = 0, mem_budget_bytes: int = 0,
+                 force_overflow_at_iter: int = 0) -> WgOptions:
+    o = WgOptions()
+    o.struct_size = ctypes.sizeof(WgOptions)
+    o.flags = flags
+    o.batch_k = batch_k
+    o.loop_mode = loop_mode
+    o.radix_field_bits = radix_field_bits
+    o.max_iterations = max_iterations
+    o.mem_budget_bytes = mem_budget_bytes
+    o.force_overflow_at_iter = force_overflow_at_iter
+    return o
+
+
+def stats_dict(s: WgStats, deltas=None) -> dict:
+    d = {
+        "iterations": int(s.iterations), "result_tuples": int(s.result_tuples),
+        "base_tuples": int(s.base_tuples), "join_candidates": int(s.join_candidates),
+        "host_syncs": int(s.host_syncs), "resumes": int(s.resumes),
+        "field_bits": int(s.field_bits), "key_bytes": int(s.key_bytes),
+        "solve_ms": float(s.solve_ms),
+        "stage_ms": {k: float(s.stage_ms[i]) for i, k in enumerate(STAGES)},
+        "stage_launches": {k: int(s.stage_launches[i]) for i, k in enumerate(STAGES)},
+        "stage_bytes": {k: int(s.stage_bytes[i]) for i, k in enumerate(STAGES)},
+    }
+    if deltas is not None:
+        d["delta_sizes"] = [int(deltas[i]) for i in range(min(int(s.iterations) + 1, len(deltas)))]
+    return d
+
+
+class Engine:
+    """One engine per device and host thread; results stay valid until its next solve."""
+
+    def __init__(self, device: int = 0):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("the fixpoint engine needs a ROCm GPU")
+        self.device = device
+        self.handle = wg_engine_create(device)
+
+    def close(self):
+        if self.handle is not None:
+            wg_engine_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+    def solve(self, query: str, src, dst, options: WgOptions | None = None, max_deltas: int = 1 << 16,
+              want_result: bool = True):
+        """Run wg_tc / wg_sg on torch uint32/int32 CUDA tensors; returns (src, dst, stats)."""
+        import torch
+
+        if src.device.type != "cuda" or dst.device.type != "cuda":
+            raise ValueError("edge tensors must live on the GPU")
+        if src.shape != dst.shape or src.dim() != 1:
+            raise ValueError("src and dst must be 1-D tensors of equal length")
+        if src.dtype not in (torch.uint32, torch.int32) or dst.dtype != src.dtype:
+            raise ValueError("edge tensors must be uint32 (or int32 bit patterns)")
+        src = src.contiguous()
+        dst = dst.contiguous()
+        stream = torch.cuda.current_stream(src.device).cuda_stream
+        stats = WgStats()
+        deltas = (c_uint64 * max_deltas)()
+        stats.delta_sizes = deltas
+        stats.delta_sizes_cap = max_deltas
+        fn = wg_tc if query == "tc" else wg_sg
+        st, res = fn(self.handle, src.data_ptr(), dst.data_ptr(), src.numel(), options, stream, stats)
+        if st != WG_OK:
+            raise WgError(st, wg_last_error(self.handle))
+        try:
+            n = wg_result_size(res)
+            out_s = out_d = None
+            if want_result:
+                out_s = torch.empty(n, dtype=torch.uint32, device=src.device)
+                out_d = torch.empty(n, dtype=torch.uint32, device=src.device)
+                if n:
+                    st = wg_result_copy(res, out_s.data_ptr(), out_d.data_ptr(), n, stream)
+                    if st != WG_OK:
+                        raise WgError(st, wg_last_error(self.handle))
+        finally:
+            wg_result_free(res)
+        return out_s, out_d, stats_dict(stats, deltas)
+
+    def tc(self, src, dst, options=None, **kw):
+        return self.solve("tc", src, dst, options, **kw)
+
+    def sg(self, src, dst, options=None, **kw):
+        return self.solve("sg", src, dst, options, **kw)

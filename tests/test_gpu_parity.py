@@ -1,0 +1,275 @@
+"""GPU fixpoints against the CPU oracle, element by element, through the C ABI.
+
+Small inputs run the oracle in the test; full-size workloads compare against the
+summaries in tests/golden/fixpoints.json, which tests/golden/make_golden.py writes
+from the oracle alone.  Results are exact integers: the bar is bit equality of the
+sorted pair arrays, the iteration count and every |Delta^i|.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2607_17571_amd import inputs
+from paper_2607_17571_amd import wg
+from tests.gpu_util import assert_same, digest, run
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "fixpoints.json")))
+
+
+# ---------------------------------------------------------------------------
+# Small cases: oracle in the loop.
+# ---------------------------------------------------------------------------
+
+def test_worked_example_chain(engine):
+    src = np.array([0, 1, 2], dtype=np.uint32)
+    dst = np.array([1, 2, 3], dtype=np.uint32)
+    s, d, st = run(engine, "tc", src, dst)
+    assert_same(s, d, st, oracle.tc(src, dst))
+    assert st["delta_sizes"] == [3, 2, 1, 0]
+
+
+@pytest.mark.parametrize("shape", ["chain200", "cycle50", "grid12", "complete40", "star300"])
+def test_tc_shapes(engine, shape):
+    src, dst = {
+        "chain200": lambda: inputs.chain(200),
+        "cycle50": lambda: inputs.cycle(50),
+        "grid12": lambda: inputs.grid_dag(12),
+        "complete40": lambda: inputs.complete_dag(40),
+        "star300": lambda: inputs.out_star(300),
+    }[shape]()
+    s, d, st = run(engine, "tc", src, dst)
+    assert_same(s, d, st, oracle.tc(src, dst))
+
+
+def test_tc_er_2000_config(engine):
+    w = inputs.workload("tc_er_2000")
+    s, d, st = run(engine, "tc", w.src, w.dst)
+    assert_same(s, d, st, oracle.tc(w.src, w.dst))
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+def test_tc_random_er(engine, seed):
+    src, dst = inputs.erdos_renyi(3000, 3300, seed=seed)
+    s, d, st = run(engine, "tc", src, dst)
+    assert_same(s, d, st, oracle.tc(src, dst))
+
+
+@pytest.mark.parametrize("scale,m", [(10, 900), (12, 3600)])
+def test_tc_rmat_small(engine, scale, m):
+    src, dst = inputs.rmat(scale, m, *inputs.RMAT_ABCD, seed=scale)
+    s, d, st = run(engine, "tc", src, dst)
+    assert_same(s, d, st, oracle.tc(src, dst))
+
+
+@pytest.mark.parametrize("bits", [22, 30, 32])
+def test_tc_wide_ids(engine, bits):
+    """24- and 32-bit radix fields (64-bit keys), ids up to 2^32 - 1."""
+    src, dst = inputs.rmat(10, 1000, *inputs.RMAT_ABCD, seed=7)
+    src, dst = inputs.scatter_ids(src, dst, bits, seed=bits)
+    s, d, st = run(engine, "tc", src, dst)
+    ref = oracle.tc(src, dst)
+    assert_same(s, d, st, ref)
+    assert st["field_bits"] == (24 if bits <= 24 else 32)
+
+
+def test_tc_extreme_ids_and_self_loops(engine):
+    top = 0xFFFFFFFF
+    src = np.array([top, 0, 5, 5, 7, top, 0], dtype=np.uint32)
+    dst = np.array([0, top, 5, 7, 5, top, top], dtype=np.uint32)
+    s, d, st = run(engine, "tc", src, dst)
+    assert_same(s, d, st, oracle.tc(src, dst))
+
+
+def test_tc_duplicates_collapse(engine):
+    src, dst = inputs.erdos_renyi(500, 450, seed=5)
+    src3 = np.concatenate([src, src[::-1], src])
+    dst3 = np.concatenate([dst, dst[::-1], dst])
+    s, d, st = run(engine, "tc", src3, dst3)
+    assert_same(s, d, st, oracle.tc(src, dst))
+
+
+def test_tc_single_edge_and_single_loop(engine):
+    for src, dst in [([3], [9]), ([4], [4])]:
+        a, b = np.array(src, np.uint32), np.array(dst, np.uint32)
+        s, d, st = run(engine, "tc", a, b)
+        assert_same(s, d, st, oracle.tc(a, b))
+
+
+def test_empty_input(engine):
+    import torch
+
+    e = torch.empty(0, dtype=torch.uint32, device="cuda")
+    for q in ("tc", "sg"):
+        s, d, st = engine.solve(q, e, e)
+        assert s.numel() == 0 and st["iterations"] == 0 and st["delta_sizes"] == [0]
+
+
+def test_hub_skew(engine):
+    """One hub with 20,000 children that each point back: tile-spanning slabs in the emit."""
+    hub = np.zeros(20000, np.uint32)
+    kids = np.arange(1, 20001, dtype=np.uint32)
+    src = np.concatenate([hub, kids[:50]])
+    dst = np.concatenate([kids, np.zeros(50, np.uint32)])
+    s, d, st = run(engine, "tc", src, dst)
+    assert_same(s, d, st, oracle.tc(src, dst))
+
+
+@pytest.mark.parametrize("seed,n,m", [(1, 300, 280), (2, 2000, 1900), (3, 20000, 18000)])
+def test_sg_random_er(engine, seed, n, m):
+    src, dst = inputs.erdos_renyi(n, m, seed=seed)
+    s, d, st = run(engine, "sg", src, dst)
+    assert_same(s, d, st, oracle.sg(src, dst))
+
+
+def test_sg_shapes(engine):
+    for src, dst in [inputs.binary_tree(6), inputs.diamond(), inputs.out_star(40), inputs.chain(30)]:
+        s, d, st = run(engine, "sg", src, dst)
+        assert_same(s, d, st, oracle.sg(src, dst))
+
+
+def test_sg_rmat(engine):
+    src, dst = inputs.rmat(9, 450, *inputs.RMAT_ABCD, seed=3)
+    s, d, st = run(engine, "sg", src, dst)
+    assert_same(s, d, st, oracle.sg(src, dst))
+
+
+def test_sg_irreflexive(engine):
+    src, dst = inputs.rmat(9, 450, *inputs.RMAT_ABCD, seed=4)
+    opts = wg.make_options(flags=wg.WG_SG_IRREFLEXIVE)
+    s, d, st = run(engine, "sg", src, dst, opts)
+    ref = oracle.sg(src, dst, irreflexive=True)
+    np.testing.assert_array_equal(s, ref.src)
+    np.testing.assert_array_equal(d, ref.dst)
+    assert np.all(s != d)
+
+
+# ---------------------------------------------------------------------------
+# Loop policies, capacity handling and errors.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("opts", [
+    dict(batch_k=1), dict(batch_k=3), dict(batch_k=64), dict(loop_mode=wg.WG_LOOP_HOST),
+    dict(radix_field_bits=32), dict(radix_field_bits=24), dict(flags=wg.WG_STAGE_TIMING),
+])
+def test_result_independent_of_loop_policy(engine, opts):
+    src, dst = inputs.rmat(11, 1800, *inputs.RMAT_ABCD, seed=9)
+    ref = oracle.tc(src, dst)
+    s, d, st = run(engine, "tc", src, dst, wg.make_options(**opts))
+    assert_same(s, d, st, ref)
+
+
+@pytest.mark.parametrize("at", [1, 3, 6])
+def test_forced_overflow_resumes_identically(engine, at):
+    src, dst = inputs.rmat(11, 1800, *inputs.RMAT_ABCD, seed=9)
+    s, d, st = run(engine, "tc", src, dst, wg.make_options(force_overflow_at_iter=at))
+    assert_same(s, d, st, oracle.tc(src, dst))
+    assert st["resumes"] >= 1
+
+
+def test_growth_from_small_buffers(engine):
+    """A fresh engine starts with small buffers; a large closure must grow and resume."""
+    eng = wg.Engine(0)
+    try:
+        src, dst = inputs.grid_dag(40)
+        s, d, st = run(eng, "tc", src, dst)
+        assert_same(s, d, st, oracle.tc(src, dst))
+    finally:
+        eng.close()
+
+
+def test_capacity_error_leaves_engine_usable(engine):
+    src, dst = inputs.grid_dag(60)
+    with pytest.raises(wg.WgError) as ei:
+        run(engine, "tc", src, dst, wg.make_options(mem_budget_bytes=64 << 20))
+    assert ei.value.status in (wg.WG_ERR_CAPACITY, wg.WG_ERR_OUT_OF_MEMORY)
+    a, b = inputs.chain(50)
+    s, d, st = run(engine, "tc", a, b)
+    assert_same(s, d, st, oracle.tc(a, b))
+
+
+def test_iteration_limit(engine):
+    a, b = inputs.chain(100)
+    with pytest.raises(wg.WgError) as ei:
+        run(engine, "tc", a, b, wg.make_options(max_iterations=10))
+    assert ei.value.status == wg.WG_ERR_ITER_LIMIT
+
+
+def test_invalid_arguments(engine):
+    st, res = wg.wg_tc(engine.handle, 0, 0, 5, None, 0)
+    assert st == wg.WG_ERR_INVALID_ARG and not res.value
+    opts = wg.make_options(radix_field_bits=20)
+    a, b = inputs.chain(5)
+    with pytest.raises(wg.WgError) as ei:
+        run(engine, "tc", a, b, opts)
+    assert ei.value.status == wg.WG_ERR_INVALID_ARG
+    src, dst = inputs.scatter_ids(*inputs.chain(5), 30, seed=1)
+    with pytest.raises(wg.WgError):
+        run(engine, "tc", src, dst, wg.make_options(radix_field_bits=16))
+
+
+def test_stale_result_is_rejected(engine):
+    import torch
+
+    from tests.gpu_util import to_gpu
+
+    a, b = inputs.chain(20)
+    st, res = wg.wg_tc(engine.handle, to_gpu(a).data_ptr(), to_gpu(b).data_ptr(), len(a), None,
+                       torch.cuda.current_stream().cuda_stream)
+    assert st == wg.WG_OK
+    run(engine, "tc", a, b)
+    out = torch.empty(1000, dtype=torch.uint32, device="cuda")
+    assert wg.wg_result_copy(res, out.data_ptr(), out.data_ptr(), 1000, 0) == wg.WG_ERR_STALE
+    wg.wg_result_free(res)
+
+
+def test_result_copy_to_host_memory(engine):
+    import ctypes
+
+    import torch
+
+    from tests.gpu_util import to_gpu
+
+    a, b = inputs.chain(30)
+    ta, tb = to_gpu(a), to_gpu(b)
+    st, res = wg.wg_tc(engine.handle, ta.data_ptr(), tb.data_ptr(), len(a), None,
+                       torch.cuda.current_stream().cuda_stream)
+    assert st == wg.WG_OK
+    n = wg.wg_result_size(res)
+    hs = (ctypes.c_uint32 * n)()
+    hd = (ctypes.c_uint32 * n)()
+    assert wg.wg_result_copy(res, ctypes.addressof(hs), ctypes.addressof(hd), n, 0) == wg.WG_OK
+    wg.wg_result_free(res)
+    ref = oracle.tc(a, b)
+    assert list(hs) == ref.src.tolist() and list(hd) == ref.dst.tolist()
+
+
+# ---------------------------------------------------------------------------
+# Full-size workloads against the oracle's stored summaries.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["tc_er_2000", "tc_rmat_s15", "tc_rmat_s15_ids24", "sg_er_500k",
+                                  "tc_grid_100"])
+def test_full_size_against_golden(engine, name):
+    if name not in GOLDEN:
+        pytest.fail(f"no golden record for {name}; run tests/golden/make_golden.py")
+    g = GOLDEN[name]
+    w = inputs.workload(name)
+    s, d, st = run(engine, w.query, w.src, w.dst)
+    assert s.size == g["size"]
+    assert st["iterations"] == g["iterations"]
+    assert st["delta_sizes"] == g["delta_sizes"]
+    assert st["join_candidates"] == g["candidates"]
+    assert digest(s, d) == g["sha256"]
+
+
+def test_sg_er_500k_irreflexive_against_golden(engine):
+    g = GOLDEN["sg_er_500k_irreflexive"]
+    w = inputs.workload("sg_er_500k")
+    s, d, st = run(engine, "sg", w.src, w.dst, wg.make_options(flags=wg.WG_SG_IRREFLEXIVE))
+    assert s.size == g["size"] and digest(s, d) == g["sha256"]
