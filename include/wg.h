@@ -72,7 +72,8 @@ typedef struct {
   uint32_t loop_mode;        /* WG_LOOP_* */
   uint32_t radix_field_bits; /* 0 = from the largest id: 16, 24 or 32 (Section V-C);
                                 else 16, 24 or 32, which must cover the largest id */
-  uint32_t reserved;
+  uint32_t timing_stages;    /* with WG_STAGE_TIMING: bitmask of WG_STAGE_* kinds to time
+                                (0 = all); events cost launch overlap, so time few kinds */
   uint64_t max_iterations;   /* 0 = unlimited */
   uint64_t mem_budget_bytes; /* 0 = no limit beyond the device allocator */
   uint64_t force_overflow_at_iter; /* test hook: report a capacity overflow once at this
@@ -83,7 +84,8 @@ typedef struct {
 enum {
   WG_STAGE_JOIN_COUNT = 0, /* binary-search range lookup + count scan (Section IV-A) */
   WG_STAGE_JOIN_EMIT = 1,  /* candidate emission into scanned slabs (Section IV-A) */
-  WG_STAGE_RADIX_HIST = 2, /* digit histograms of all passes (Section V-C) */
+  WG_STAGE_RADIX_HIST = 2, /* digit histograms (Section V-C); computed inside the kernel
+                              that produces the keys, so this kind has no launches */
   WG_STAGE_RADIX_PASS = 3, /* one stable 8-bit LSD scatter pass (Section V-C) */
   WG_STAGE_DEDUP_DIFF = 4, /* fused dedup + set difference (Section IV-B) */
   WG_STAGE_MERGE = 5,      /* disjoint merge-path merge (Section IV-C) */

@@ -44,8 +44,9 @@ struct Ctrl {
   uint32_t delta_side;   // which delta buffer holds Delta^{i-1}
   uint32_t maxid;        // largest vertex id of the input
   uint32_t force_overflow_at;  // test hook: report a candidate overflow at this iteration
-  uint32_t pad;
+  uint32_t sort_seq;     // sorts completed; its parity selects the histogram slot
   uint64_t D0;           // |Delta^0|, the seed size
+  uint64_t total;        // hand-over of a launch-wide total to the launch's last claimer
 };
 
 // A halted loop turns every later kernel of the batch into a no-op.
@@ -59,13 +60,14 @@ __device__ __forceinline__ bool halted(const Ctrl* c) {
 // A status word is  [63:62] flag | [61:40] epoch | [39:0] value.  flag 1 = tile
 // aggregate, 2 = inclusive prefix.  Words from earlier launches carry another epoch and
 // read as "not ready", so the status array never needs clearing between launches.  The
-// last block of a launch resets the tile counter and advances the epoch.
+// block that makes a launch's last tile claim resets the counter and advances the epoch.
 // ---------------------------------------------------------------------------
+constexpr int kClaimLanes = 8;
 struct LbState {
-  uint32_t tile_ctr;
-  uint32_t blocks_done;
+  uint32_t lane_ctr[kClaimLanes][64];  // one claim counter per 256-byte line
+  uint32_t lanes_done;
   uint32_t epoch;
-  uint32_t pad;
+  uint32_t pad[62];
 };
 
 constexpr uint64_t kValMask = (1ull << 40) - 1;
@@ -98,34 +100,65 @@ __device__ __forceinline__ uint64_t status_load(const uint64_t* p) {
   return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Claim the next tile (dynamic tile ids keep lookback free of deadlock: a tile only ever
-// waits on tiles claimed before it, by blocks that are already running).
-__device__ __forceinline__ uint32_t claim_tile(LbState* st, uint32_t* s_tile) {
-  if (threadIdx.x == 0) *s_tile = atomicAdd(&st->tile_ctr, 1u);
-  __syncthreads();
-  uint32_t t = *s_tile;
-  __syncthreads();
-  return t;
+// Dynamic tile claims.  A tile only ever waits on tiles claimed before it in its own
+// claim order, by blocks that are already running, so lookback cannot deadlock.  Claims
+// go through 8 independent counters ("lanes", one per 256-byte line): block b draws from
+// lane b % 8, whose k-th claim is tile 8k + lane.  Same-address atomics serialise at a
+// few tens of ns each across the XCDs, so spreading them over 8 addresses keeps claims
+// off the critical path.  The smallest unfinished tile is always either held by a running
+// block or the next tile of its lane, which a block of that lane (all of whose earlier
+// tiles are finished) claims next: progress is guaranteed.
+//
+// Every block ends with exactly one failing claim.  The last failing claim on a lane
+// resets that lane; the last lane to finish (a second counter) marks the block that
+// knows every block of the launch is done: it advances the epoch and may publish
+// launch-wide results.
+struct TileClaim {
+  uint32_t tile;   // valid when `ok`
+  bool ok;         // a tile was claimed
+  bool last;       // this block closed the launch
+};
+
+__device__ __forceinline__ uint32_t lane_tiles(uint64_t ntiles, uint32_t lane) {
+  return ntiles > lane ? (uint32_t)((ntiles - lane + kClaimLanes - 1) / kClaimLanes) : 0u;
 }
 
-// End of a lookback launch: the last block to finish resets the counters for the next
-// launch of the same kernel.  Returns true in every thread of that last block.
-__device__ __forceinline__ bool finish_launch(LbState* st, uint32_t epoch, uint32_t* s_flag) {
+__device__ __forceinline__ uint32_t lane_blocks(uint32_t lane) {
+  return (gridDim.x - lane + kClaimLanes - 1) / kClaimLanes;
+}
+
+__device__ __forceinline__ TileClaim claim_tile(LbState* st, uint64_t ntiles, uint32_t* s_buf) {
+  const uint32_t lane = blockIdx.x & (kClaimLanes - 1);
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
-    uint32_t prev = atomicAdd(&st->blocks_done, 1u);
-    uint32_t last = (prev == gridDim.x - 1) ? 1u : 0u;
-    if (last) {
-      __threadfence();
-      __hip_atomic_store(&st->blocks_done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&st->tile_ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&st->epoch, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t k = atomicAdd(&st->lane_ctr[lane][0], 1u);
+    uint32_t last = 0;
+    const uint32_t tiles = lane_tiles(ntiles, lane);
+    if (k >= tiles && k == tiles + lane_blocks(lane) - 1) {
+      // final claim on this lane: reset it, then count finished lanes
+      __hip_atomic_store(&st->lane_ctr[lane][0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t lanes = gridDim.x < (uint32_t)kClaimLanes ? gridDim.x : (uint32_t)kClaimLanes;
+      last = (atomicAdd(&st->lanes_done, 1u) == lanes - 1) ? 1u : 0u;
     }
-    *s_flag = last;
+    s_buf[0] = k;
+    s_buf[1] = last;
   }
   __syncthreads();
-  return *s_flag != 0;
+  const uint32_t k = s_buf[0];
+  TileClaim r;
+  r.ok = (uint64_t)k * kClaimLanes + lane < ntiles;
+  r.tile = k * kClaimLanes + lane;
+  r.last = s_buf[1] != 0;
+  return r;
+}
+
+// Thread 0 of the closing block: reset the lane-done counter and publish the epoch.
+__device__ __forceinline__ void release_launch(LbState* st, uint32_t epoch) {
+  __threadfence();
+  __hip_atomic_store(&st->lanes_done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&st->epoch, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __threadfence();
 }
 
 // ---------------------------------------------------------------------------
@@ -275,6 +308,89 @@ __device__ __forceinline__ uint64_t upper_bound(const T* a, uint64_t n, T v) {
     if (a[mid] <= v) lo = mid + 1; else hi = mid;
   }
   return lo;
+}
+
+// Wave-cooperative partition point: all 64 lanes of the calling wave search [lo, hi)
+// for the first index whose predicate is false (the predicate holds on a prefix).  Each
+// round probes 64 positions at once and narrows the range 65-fold, so a search over
+// 5e7 keys takes 5 rounds of parallel loads instead of 26 dependent ones.  The result
+// is uniform across the wave.
+template <typename Pred>
+__device__ __forceinline__ uint64_t wave_partition(uint64_t lo, uint64_t hi, Pred pred) {
+  const int lane = (int)(threadIdx.x & (kWave - 1));
+  while (lo < hi) {
+    const uint64_t span = hi - lo;
+    if (span <= (uint64_t)kWave) {
+      const bool t = (uint64_t)lane < span && pred(lo + (uint64_t)lane);
+      return lo + (uint64_t)__popcll(__ballot(t));
+    }
+    const uint64_t q = lo + (span * (uint64_t)(lane + 1)) / (kWave + 1);
+    const uint32_t J = (uint32_t)__popcll(__ballot(pred(q)));
+    const uint64_t q_before = lo + (span * (uint64_t)J) / (kWave + 1);
+    const uint64_t q_at = lo + (span * (uint64_t)(J + 1)) / (kWave + 1);
+    if (J > 0) lo = q_before + 1;
+    if (J < (uint32_t)kWave) hi = q_at;
+  }
+  return lo;
+}
+
+template <typename T>
+__device__ __forceinline__ uint64_t wave_lower_bound(const T* a, uint64_t n, T v) {
+  return wave_partition(0, n, [&](uint64_t i) { return a[i] < v; });
+}
+
+template <typename T>
+__device__ __forceinline__ uint64_t wave_upper_bound(const T* a, uint64_t n, T v) {
+  return wave_partition(0, n, [&](uint64_t i) { return a[i] <= v; });
+}
+
+// Branchless lower bounds of ITEMS keys at once over the same sorted array: every
+// probe step issues ITEMS independent loads, so their latencies overlap.
+template <typename T, int ITEMS>
+__device__ __forceinline__ void multi_lower_bound(const T* __restrict__ a, uint64_t n,
+                                                  const T (&v)[ITEMS], uint64_t (&out)[ITEMS]) {
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) out[k] = 0;
+  if (n == 0) return;
+  uint64_t len = n;
+  while (len > 1) {
+    const uint64_t half = len >> 1;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) out[k] = (a[out[k] + half - 1] < v[k]) ? out[k] + half : out[k];
+    len -= half;
+  }
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) out[k] += (a[out[k]] < v[k]) ? 1 : 0;
+}
+
+template <typename T, int ITEMS>
+__device__ __forceinline__ void multi_upper_bound(const T* __restrict__ a, uint64_t n,
+                                                  const T (&v)[ITEMS], uint64_t (&out)[ITEMS]) {
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) out[k] = 0;
+  if (n == 0) return;
+  uint64_t len = n;
+  while (len > 1) {
+    const uint64_t half = len >> 1;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) out[k] = (a[out[k] + half - 1] <= v[k]) ? out[k] + half : out[k];
+    len -= half;
+  }
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) out[k] += (a[out[k]] <= v[k]) ? 1 : 0;
+}
+
+// Peers of this lane: lanes of the wave whose 8-bit digit equals this lane's (and that
+// are in `active`).  Eight ballots, one per bit.
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, uint64_t active) {
+  uint64_t peers = active;
+#pragma unroll
+  for (int bit = 0; bit < 8; ++bit) {
+    const bool set = (d >> bit) & 1u;
+    const uint64_t m = __ballot(set);
+    peers &= set ? m : ~m;
+  }
+  return peers;
 }
 
 // Key field helpers.  `w` < bit width of K always holds (w = 32 only with 64-bit keys).

@@ -46,7 +46,6 @@ struct wg_engine {
   hipEvent_t ev_batch[2] = {nullptr, nullptr};
   LbState* d_lb = nullptr;
   uint32_t* d_ghist = nullptr;
-  uint32_t* d_gbase = nullptr;
   DevBuf status[kLbCount];
   DevBuf cand[2], full[2], delta[2], E, U, R, Edst, rowa, rowb, off, hist;
   size_t allocated = 0;
@@ -60,8 +59,10 @@ struct wg_engine {
   uint64_t syncs = 0;
   // stage timing
   bool timing = false;
+  uint32_t timing_mask = 0;
   std::vector<hipEvent_t> events;
   std::vector<int> event_kind;
+  std::vector<int> event_launches;
   uint32_t n_events = 0;
   hipStream_t stream = nullptr;
   // result of the latest solve
@@ -192,6 +193,10 @@ void size_buffers(wg_engine* e, bool keep, const Ctrl* c) {
   }
 }
 
+void clear_histograms(wg_engine* e) {
+  hip_check(e, hipMemsetAsync(e->d_ghist, 0, sizeof(uint32_t) * kHistWords, e->stream), "memset");
+}
+
 void refresh_epochs(wg_engine* e) {
   sync_stream(e);
   for (int s = 0; s < kLbCount; ++s)
@@ -219,7 +224,6 @@ Bufs<K> make_bufs(wg_engine* e) {
   b.lb = e->d_lb;
   for (int s = 0; s < kLbCount; ++s) b.status[s] = (uint64_t*)e->status[s].p;
   b.ghist = e->d_ghist;
-  b.gbase = e->d_gbase;
   return b;
 }
 
@@ -230,21 +234,23 @@ hipEvent_t next_event(wg_engine* e) {
     hip_check(e, hipEventCreate(&ev), "hipEventCreate");
     e->events.push_back(ev);
     e->event_kind.push_back(-1);
+    e->event_launches.push_back(1);
   }
   return e->events[e->n_events];
 }
 
-void begin(wg_engine* e) {
-  if (!e->timing || e->n_events + 2 > kMaxEvents) return;
+void begin(wg_engine* e, int kind) {
+  if (!e->timing || !((e->timing_mask >> kind) & 1u) || e->n_events + 2 > kMaxEvents) return;
   hip_check(e, hipEventRecord(next_event(e), e->stream), "hipEventRecord");
   e->event_kind[e->n_events] = -1;
   ++e->n_events;
 }
 
-void end(wg_engine* e, int kind) {
+void end(wg_engine* e, int kind, int launches = 1) {
   if (!e->timing || e->n_events == 0 || e->event_kind[e->n_events - 1] != -1) return;
   hip_check(e, hipEventRecord(next_event(e), e->stream), "hipEventRecord");
   e->event_kind[e->n_events] = kind;
+  e->event_launches[e->n_events] = launches;
   ++e->n_events;
 }
 
@@ -257,37 +263,35 @@ void collect_timing(wg_engine* e, wg_stats* st) {
     float ms = 0.f;
     hip_check(e, hipEventElapsedTime(&ms, e->events[i - 1], e->events[i]), "hipEventElapsedTime");
     st->stage_ms[k] += ms;
-    st->stage_launches[k] += 1;
+    st->stage_launches[k] += (uint64_t)e->event_launches[i];
   }
 }
 
 // ----- pipeline pieces
 template <typename K>
 void enqueue_sort(wg_engine* e, const Bufs<K>& b, const uint64_t* n_ptr, int passes) {
-  begin(e);
-  launch_radix_hist<K>(e->stream, e->grid, e->d_ctrl, n_ptr, b.cand[0], passes, b);
-  end(e, WG_STAGE_RADIX_HIST);
-  for (int p = 0; p < passes; ++p) {
-    begin(e);
+  // the digit histograms come from the kernel that produced the keys (pack or emit);
+  // one event pair brackets all passes, so stage_ms / launches is the mean pass time
+  begin(e, WG_STAGE_RADIX_PASS);
+  for (int p = 0; p < passes; ++p)
     launch_radix_pass<K>(e->stream, e->grid, e->d_ctrl, n_ptr, b.cand[p & 1], b.cand[(p + 1) & 1], p, b);
-    end(e, WG_STAGE_RADIX_PASS);
-  }
+  end(e, WG_STAGE_RADIX_PASS, passes);
   e->lb_launches += passes;
 }
 
 template <typename K>
 void enqueue_iteration(wg_engine* e, const Bufs<K>& b, int kind, int w, int passes) {
-  begin(e);
+  begin(e, WG_STAGE_JOIN_COUNT);
   launch_join_count<K>(e->stream, e->grid, kind, e->d_ctrl, b, w);
   end(e, WG_STAGE_JOIN_COUNT);
-  begin(e);
-  launch_join_emit<K>(e->stream, e->grid, kind, e->d_ctrl, b, w);
+  begin(e, WG_STAGE_JOIN_EMIT);
+  launch_join_emit<K>(e->stream, e->grid, kind, e->d_ctrl, b, w, passes);
   end(e, WG_STAGE_JOIN_EMIT);
   enqueue_sort<K>(e, b, &e->d_ctrl->C, passes);
-  begin(e);
+  begin(e, WG_STAGE_DEDUP_DIFF);
   launch_dedup_diff<K>(e->stream, e->grid, kModeIter, e->d_ctrl, &e->d_ctrl->C, b.cand[passes & 1], b);
   end(e, WG_STAGE_DEDUP_DIFF);
-  begin(e);
+  begin(e, WG_STAGE_MERGE);
   launch_merge<K>(e->stream, e->grid, e->d_ctrl, b);
   end(e, WG_STAGE_MERGE);
   e->lb_launches += 3;
@@ -323,6 +327,8 @@ void grow_and_resume(wg_engine* e, const Ctrl& c, bool hooked) {
   e->full_cap = full;
   e->dsz_cap = dsz;
   size_buffers(e, true, &c);
+  // the abandoned attempt may have accumulated digit counts for the sort it never finished
+  clear_histograms(e);
   launch_resume(e->stream, e->d_ctrl, e->cand_cap, e->full_cap, e->dsz_cap, clear_hook ? 1u : 0u);
 }
 
@@ -339,12 +345,10 @@ void bytes_model(wg_stats* st, int query, uint32_t kb, int passes, uint64_t m,
                  const std::vector<uint64_t>& N, const std::vector<uint64_t>& C, uint64_t base_cand) {
   // prepare: max scan + pack + sort + dedup of m edges + index
   add_bytes(st, WG_STAGE_PREPARE, 8.0 * m + (8.0 + kb) * m + (kb + 12.0) * m);
-  add_bytes(st, WG_STAGE_RADIX_HIST, (double)kb * m);
   add_bytes(st, WG_STAGE_RADIX_PASS, 2.0 * kb * m * passes);
   add_bytes(st, WG_STAGE_DEDUP_DIFF, (double)kb * m + (double)kb * N[0] * (query == WG_QUERY_TC ? 3 : 0));
   if (query == WG_QUERY_SG) {
     add_bytes(st, WG_STAGE_JOIN_EMIT, (double)(kb + 8) * base_cand);
-    add_bytes(st, WG_STAGE_RADIX_HIST, (double)kb * base_cand);
     add_bytes(st, WG_STAGE_RADIX_PASS, 2.0 * kb * base_cand * passes);
     add_bytes(st, WG_STAGE_DEDUP_DIFF, (double)kb * base_cand + 2.0 * kb * N[0]);
   }
@@ -355,7 +359,6 @@ void bytes_model(wg_stats* st, int query, uint32_t kb, int passes, uint64_t m,
     const double D = (double)N[i - 1], c = (double)C[i], n = (double)N[i];
     add_bytes(st, WG_STAGE_JOIN_COUNT, D * (kb + row_bytes));
     add_bytes(st, WG_STAGE_JOIN_EMIT, D * (kb + row_bytes) + c * (edst + kb));
-    add_bytes(st, WG_STAGE_RADIX_HIST, c * kb);
     add_bytes(st, WG_STAGE_RADIX_PASS, 2.0 * c * kb * passes);
     add_bytes(st, WG_STAGE_DEDUP_DIFF, (c + n) * kb);
     if (N[i] > 0) add_bytes(st, WG_STAGE_MERGE, 2.0 * ((double)F + n) * kb);
@@ -388,18 +391,19 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   c0.max_iter = (uint32_t)std::min<uint64_t>(o.max_iterations, 0xFFFFFFFFu);
   c0.force_overflow_at = (uint32_t)std::min<uint64_t>(o.force_overflow_at_iter, 0xFFFFFFFFu);
   hip_check(e, hipMemcpyAsync(e->d_ctrl, e->h_up, sizeof(Ctrl), hipMemcpyHostToDevice, e->stream), "upload");
+  clear_histograms(e);
 
   // ---- prepare: sort + dedup E, edge index, seed (Section IV-A: E sorted once)
   Bufs<K> b = make_bufs<K>(e);
-  begin(e);
-  launch_pack<K>(e->stream, e->grid, src, dst, m, w, b.cand[0]);
+  begin(e, WG_STAGE_PREPARE);
+  launch_pack<K>(e->stream, e->grid, e->d_ctrl, src, dst, m, w, b.cand[0], passes, b);
   end(e, WG_STAGE_PREPARE);
   enqueue_sort<K>(e, b, &e->d_ctrl->m_in, passes);
   const int mode = query == WG_QUERY_TC ? (kModeEdges | kModeSeed) : kModeEdges;
-  begin(e);
+  begin(e, WG_STAGE_DEDUP_DIFF);
   launch_dedup_diff<K>(e->stream, e->grid, mode, e->d_ctrl, &e->d_ctrl->m_in, b.cand[passes & 1], b);
   end(e, WG_STAGE_DEDUP_DIFF);
-  begin(e);
+  begin(e, WG_STAGE_PREPARE);
   launch_edge_index<K>(e->stream, e->grid, e->d_ctrl, b, w);
   end(e, WG_STAGE_PREPARE);
   e->lb_launches += 2;
@@ -409,14 +413,14 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
     // base rule: Delta^0 = Full = {(x, y) : E(p, x), E(p, y), x != y}, sorted + deduplicated
     for (;;) {
       b = make_bufs<K>(e);
-      begin(e);
+      begin(e, WG_STAGE_JOIN_COUNT);
       launch_join_count<K>(e->stream, e->grid, kJoinSGBase, e->d_ctrl, b, w);
       end(e, WG_STAGE_JOIN_COUNT);
-      begin(e);
-      launch_join_emit<K>(e->stream, e->grid, kJoinSGBase, e->d_ctrl, b, w);
+      begin(e, WG_STAGE_JOIN_EMIT);
+      launch_join_emit<K>(e->stream, e->grid, kJoinSGBase, e->d_ctrl, b, w, passes);
       end(e, WG_STAGE_JOIN_EMIT);
       enqueue_sort<K>(e, b, &e->d_ctrl->C, passes);
-      begin(e);
+      begin(e, WG_STAGE_DEDUP_DIFF);
       launch_dedup_diff<K>(e->stream, e->grid, kModeSeed, e->d_ctrl, &e->d_ctrl->C, b.cand[passes & 1], b);
       end(e, WG_STAGE_DEDUP_DIFF);
       e->lb_launches += 2;
@@ -442,18 +446,24 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   int slot = 0;
   uint64_t prev_D = 0;
   bool have_prev = false;
-  auto enqueue_batch = [&](uint32_t k, int sl) {
+  auto enqueue_iters = [&](uint32_t k) {
     b = make_bufs<K>(e);
     for (uint32_t i = 0; i < k; ++i) enqueue_iteration<K>(e, b, kind, w, passes);
+  };
+  auto enqueue_batch = [&](uint32_t k, int sl) {
+    enqueue_iters(k);
     read_ctrl(e, sl);
   };
   const uint64_t per_iter_launches = 3 + (uint64_t)passes;
+  constexpr uint32_t kSpec = 4;
   enqueue_batch(K_batch, slot);
   for (;;) {
-    // Double-buffered submission (Section V-B): enqueue the next batch before waiting on
-    // this one; if this one reaches the fixpoint the next is a batch of no-op launches.
-    const bool speculate = e->lb_launches + per_iter_launches * K_batch < kEpochRefresh;
-    if (speculate) enqueue_batch(K_batch, slot ^ 1);
+    // While the host waits on this batch, the device runs a short speculative batch
+    // behind it (Section V-B overlaps the next batch with the host check); after the
+    // fixpoint its launches are no-ops, so it is kept short.
+    const uint32_t spec = std::min(K_batch, kSpec);
+    const bool speculate = e->lb_launches + per_iter_launches * (K_batch + spec) < kEpochRefresh;
+    if (speculate) enqueue_iters(spec);
     c = wait_ctrl(e, slot);
     if (c.error | c.overflow | c.done | c.limit_hit) sync_stream(e);
     if (c.error) fail(e, WG_ERR_DEVICE, "device wait expired (lookback spin limit)");
@@ -461,7 +471,6 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
       grow_and_resume(e, c, hooked);
       if (st) st->resumes++;
       if (e->lb_launches > kEpochRefresh) refresh_epochs(e);
-      slot = 0;
       enqueue_batch(K_batch, slot);
       continue;
     }
@@ -473,18 +482,15 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
     }
     prev_D = c.D;
     have_prev = true;
-    if (!speculate) {
-      refresh_epochs(e);
-      enqueue_batch(K_batch, slot);
-      continue;
-    }
+    if (!speculate) refresh_epochs(e);
     slot ^= 1;
+    enqueue_batch(K_batch, slot);
   }
   if (c.limit_hit && !c.done) fail(e, WG_ERR_ITER_LIMIT, "max_iterations reached before the fixpoint");
 
   b = make_bufs<K>(e);
   if (query == WG_QUERY_SG && (o.flags & WG_SG_IRREFLEXIVE)) {
-    begin(e);
+    begin(e, WG_STAGE_PREPARE);
     launch_filter_offdiag<K>(e->stream, e->grid, e->d_ctrl, b, w);
     end(e, WG_STAGE_PREPARE);
     e->lb_launches += 1;
@@ -571,6 +577,7 @@ wg_status solve(wg_engine* e, int query, const uint32_t* d_src, const uint32_t* 
     e->syncs = 0;
     e->budget = o.mem_budget_bytes;
     e->timing = (o.flags & WG_STAGE_TIMING) != 0;
+    e->timing_mask = o.timing_stages ? o.timing_stages : 0xFFFFFFFFu;
     e->n_events = 0;
     if (m == 0) {
       if (st && st->delta_sizes && st->delta_sizes_cap) st->delta_sizes[0] = 0;
@@ -631,10 +638,9 @@ wg_status wg_engine_create(int device, wg_engine** out) {
     hip_check(e, hipHostMalloc((void**)&e->h_up, sizeof(Ctrl)), "hipHostMalloc");
     hip_check(e, hipHostMalloc((void**)&e->h_down, 2 * sizeof(Ctrl)), "hipHostMalloc");
     hip_check(e, hipMalloc((void**)&e->d_lb, sizeof(LbState) * kLbCount), "hipMalloc");
-    hip_check(e, hipMalloc((void**)&e->d_ghist, sizeof(uint32_t) * kMaxPasses * kRadix), "hipMalloc");
-    hip_check(e, hipMalloc((void**)&e->d_gbase, sizeof(uint32_t) * kMaxPasses * kRadix), "hipMalloc");
+    hip_check(e, hipMalloc((void**)&e->d_ghist, sizeof(uint32_t) * kHistWords), "hipMalloc");
     hip_check(e, hipMemset(e->d_lb, 0, sizeof(LbState) * kLbCount), "hipMemset");
-    hip_check(e, hipMemset(e->d_ghist, 0, sizeof(uint32_t) * kMaxPasses * kRadix), "hipMemset");
+    hip_check(e, hipMemset(e->d_ghist, 0, sizeof(uint32_t) * kHistWords), "hipMemset");
     hip_check(e, hipMemset(e->d_ctrl, 0, sizeof(Ctrl)), "hipMemset");
     for (int s = 0; s < 2; ++s)
       hip_check(e, hipEventCreateWithFlags(&e->ev_batch[s], hipEventDisableTiming), "hipEventCreate");
@@ -672,7 +678,6 @@ void wg_engine_destroy(wg_engine* e) {
   if (e->d_ctrl) (void)hipFree(e->d_ctrl);
   if (e->d_lb) (void)hipFree(e->d_lb);
   if (e->d_ghist) (void)hipFree(e->d_ghist);
-  if (e->d_gbase) (void)hipFree(e->d_gbase);
   if (e->h_up) (void)hipHostFree(e->h_up);
   if (e->h_down) (void)hipHostFree(e->h_down);
   for (int s = 0; s < 2; ++s)

@@ -2,7 +2,7 @@
 //
 //   join count + scan   Section IV-A, two-phase binary-search join (count phase)
 //   join emit           Section IV-A (emit phase) and Section VI (SG cross product)
-//   radix hist / pass   Section V-C, LSD radix sort, 8 bits per pass, dst field first
+//   radix pass          Section V-C, LSD radix sort, 8 bits per pass, dst field first
 //   dedup_diff          Section IV-B, fused dedup + set difference, ordered compaction
 //   merge               Section IV-C, disjoint merge-path merge
 //
@@ -10,14 +10,53 @@
 // batch of iterations is enqueued without the host knowing any intermediate size
 // (Section V-B).  Kernels that start after the loop halted return at once.
 //
-// Launch shapes: persistent grids (a few blocks per CU) that claim tiles dynamically.
-// Lookback kernels use dynamic tile ids; streaming kernels use a static grid stride.
+// Launch shapes: persistent grids (a few blocks per CU).  Lookback kernels claim tiles
+// dynamically over 8 claim lanes; streaming kernels (emit, merge) use a static grid stride.
 
 #include "wg_launch.h"
 
 namespace wg {
 
 constexpr uint32_t kNoRow = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t hist_base(uint32_t slot, uint32_t copy, int pass) {
+  return ((slot * kHistCopies + copy) * kMaxPasses + (uint32_t)pass) * kRadix;
+}
+
+// ---------------------------------------------------------------------------
+// Digit histograms of every radix pass (Section V-C), accumulated by the kernel that
+// produces the keys so the sort needs no extra read of them.  Lanes of a wave holding the
+// same digit add once (ballot peers), which keeps skewed digits from serialising on one
+// LDS address.  Blocks flush into one of 8 global copies to spread the atomics; the pass
+// kernels add the copies up.  The slot is the parity of the sort sequence; a producer
+// clears the other slot, which the previous sort used and the next sort will use.
+// ---------------------------------------------------------------------------
+template <typename K>
+__device__ __forceinline__ void hist_add(uint32_t* s_h, K key, bool valid, int passes) {
+  const uint64_t active = __ballot(valid);
+  const uint64_t lt = lanemask_lt();
+  for (int p = 0; p < passes; ++p) {
+    const uint32_t d = (uint32_t)(key >> (p * kRadixBits)) & (kRadix - 1);
+    const uint64_t peers = digit_peers(d, active);
+    if (valid && (peers & lt) == 0) atomicAdd(&s_h[p * kRadix + d], (uint32_t)__popcll(peers));
+  }
+}
+
+__device__ __forceinline__ void hist_begin(uint32_t* s_h, int passes, uint32_t* ghist, uint32_t slot) {
+  for (int j = threadIdx.x; j < passes * kRadix; j += kBlock) s_h[j] = 0;
+  uint32_t* other = ghist + (slot ^ 1u) * kHistSlotWords;
+  for (uint32_t j = blockIdx.x * kBlock + threadIdx.x; j < (uint32_t)kHistSlotWords;
+       j += gridDim.x * kBlock)
+    other[j] = 0;
+}
+
+__device__ __forceinline__ void hist_flush(const uint32_t* s_h, int passes, uint32_t* ghist,
+                                           uint32_t slot) {
+  __syncthreads();
+  const uint32_t copy = blockIdx.x & (kHistCopies - 1);
+  for (int j = threadIdx.x; j < passes * kRadix; j += kBlock)
+    if (s_h[j]) atomicAdd(&ghist[hist_base(slot, copy, j / kRadix) + (j % kRadix)], s_h[j]);
+}
 
 // ---------------------------------------------------------------------------
 // Prepare: largest id, packing.
@@ -35,33 +74,42 @@ __global__ __launch_bounds__(kBlock) void k_max_id(Ctrl* ctrl, const uint32_t* _
 }
 
 template <typename K>
-__global__ __launch_bounds__(kBlock) void k_pack(const uint32_t* __restrict__ src,
+__global__ __launch_bounds__(kBlock) void k_pack(Ctrl* ctrl, const uint32_t* __restrict__ src,
                                                  const uint32_t* __restrict__ dst, uint64_t m,
-                                                 int w, K* __restrict__ keys) {
-  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < m;
-       i += (uint64_t)gridDim.x * kBlock) {
-    keys[i] = ((K)src[i] << w) | (K)dst[i];
+                                                 int w, K* __restrict__ keys, int passes,
+                                                 Bufs<K> b) {
+  __shared__ uint32_t s_h[kMaxPasses * kRadix];
+  const uint32_t slot = ctrl->sort_seq & 1u;
+  hist_begin(s_h, passes, b.ghist, slot);
+  __syncthreads();
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  const uint64_t rounds = (m + stride - 1) / stride;
+  for (uint64_t r = 0; r < rounds; ++r) {
+    const uint64_t i = r * stride + (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = i < m;
+    K key = 0;
+    if (valid) {
+      key = ((K)src[i] << w) | (K)dst[i];
+      keys[i] = key;
+    }
+    hist_add<K>(s_h, key, valid, passes);
   }
+  hist_flush(s_h, passes, b.ghist, slot);
 }
 
 // ---------------------------------------------------------------------------
-// Join, count phase (Section IV-A).  One thread per delta tuple finds the range of
-// its join key in the edge index by binary search and counts the candidates it
-// will emit; a single-pass scan turns the counts into output offsets, so every
-// tuple owns one contiguous output slab and the emit phase needs no atomics.
-// The row ids found here are kept for the emit phase instead of searching twice.
+// Join, count phase (Section IV-A).  One thread per delta tuple finds the range of its
+// join key in the edge index by binary search and counts the candidates it will emit;
+// a single-pass scan turns the counts into output offsets, so every tuple owns one
+// contiguous output slab and the emit phase needs no atomics.  The row ids found here
+// are kept for the emit phase instead of searching twice.  Tuples are laid out
+// wave-striped (coalesced loads) and all searches of a thread run interleaved.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t find_row(const uint32_t* __restrict__ U, uint64_t nu,
-                                             uint32_t v) {
-  const uint64_t j = lower_bound(U, nu, v);
-  return (j < nu && U[j] == v) ? (uint32_t)j : kNoRow;
-}
-
 template <typename K, int Q, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_join_count(Ctrl* ctrl, Bufs<K> b, int w) {
   constexpr uint32_t T = kBlock * ITEMS;
   __shared__ TileScanShared sh;
-  __shared__ uint32_t s_tile, s_flag;
+  __shared__ uint32_t s_claim[2];
   if (halted(ctrl)) return;
   const uint64_t n = (Q == kJoinSGBase) ? ctrl->nu : ctrl->D;
   const uint64_t nu = ctrl->nu;
@@ -75,82 +123,123 @@ __global__ __launch_bounds__(kBlock) void k_join_count(Ctrl* ctrl, Bufs<K> b, in
   }
   LbState* st = b.lb + kLbJoin;
   const uint32_t epoch = launch_epoch(st);
+  const int wid = threadIdx.x / kWave;
+  const int lane = lane_id();
   for (;;) {
-    const uint32_t tile = claim_tile(st, &s_tile);
-    if (tile >= ntiles) break;
-    const uint64_t base = (uint64_t)tile * T + (uint64_t)threadIdx.x * ITEMS;
-    uint64_t cnt[ITEMS];
-    uint64_t sum = 0;
+    const TileClaim cl = claim_tile(st, ntiles, s_claim);
+    if (!cl.ok) {
+      if (cl.last && threadIdx.x == 0) release_launch(st, epoch);
+      break;
+    }
+    {
+      const uint32_t tile = cl.tile;
+      // wave `wid` owns a contiguous run of 64*ITEMS tuples
+      const uint64_t wbase = (uint64_t)tile * T + (uint64_t)wid * (kWave * ITEMS);
+      uint64_t cnt[ITEMS];
+      if (Q == kJoinSGBase) {
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      const uint64_t i = base + k;
-      uint64_t c = 0;
-      if (i < n) {
-        if (Q == kJoinTC) {
-          const uint32_t j = find_row(U, nu, tc_join_row<K>(delta[i], w));
-          b.rowb[i] = j;
-          c = (j == kNoRow) ? 0 : (uint64_t)(R[j + 1] - R[j]);
-        } else if (Q == kJoinSG) {
-          const K key = delta[i];
-          const uint32_t ja = find_row(U, nu, head_row<K>(key, w));
-          const uint32_t jb = find_row(U, nu, tc_join_row<K>(key, w));
-          b.rowa[i] = ja;
-          b.rowb[i] = jb;
-          c = (ja == kNoRow || jb == kNoRow)
-                  ? 0
-                  : (uint64_t)(R[ja + 1] - R[ja]) * (uint64_t)(R[jb + 1] - R[jb]);
-        } else {
-          const uint64_t len = R[i + 1] - R[i];
-          c = len * (len - 1);
+        for (int k = 0; k < ITEMS; ++k) {
+          const uint64_t i = wbase + (uint64_t)k * kWave + lane;
+          uint64_t len = 0;
+          if (i < n) len = R[i + 1] - R[i];
+          cnt[k] = len ? len * (len - 1) : 0;
+        }
+      } else {
+        uint32_t vb[ITEMS], va[ITEMS];
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+          const uint64_t i = wbase + (uint64_t)k * kWave + lane;
+          const K key = i < n ? delta[i] : K(0);
+          vb[k] = tc_join_row<K>(key, w);
+          va[k] = head_row<K>(key, w);
+        }
+        uint64_t jb[ITEMS];
+        multi_lower_bound<uint32_t, ITEMS>(U, nu, vb, jb);
+        uint64_t ja[ITEMS];
+        if (Q == kJoinSG) multi_lower_bound<uint32_t, ITEMS>(U, nu, va, ja);
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+          const uint64_t i = wbase + (uint64_t)k * kWave + lane;
+          uint64_t c = 0;
+          if (i < n) {
+            const uint32_t rb = (jb[k] < nu && U[jb[k]] == vb[k]) ? (uint32_t)jb[k] : kNoRow;
+            b.rowb[i] = rb;
+            if (Q == kJoinTC) {
+              c = (rb == kNoRow) ? 0 : (uint64_t)(R[rb + 1] - R[rb]);
+            } else {
+              const uint32_t ra = (ja[k] < nu && U[ja[k]] == va[k]) ? (uint32_t)ja[k] : kNoRow;
+              b.rowa[i] = ra;
+              c = (ra == kNoRow || rb == kNoRow)
+                      ? 0
+                      : (uint64_t)(R[ra + 1] - R[ra]) * (uint64_t)(R[rb + 1] - R[rb]);
+            }
+          }
+          cnt[k] = c;
         }
       }
-      cnt[k] = c;
-      sum = sat_add(sum, c);
-    }
-    uint64_t grand, tex;
-    uint64_t ex = tile_scan(sum, tile, epoch, b.status[kLbJoin], &ctrl->error, &sh, grand, tex);
+      // exclusive offsets in (k, lane) order inside the wave, then across waves and tiles
+      uint64_t ex[ITEMS];
+      uint64_t run = 0;
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      const uint64_t i = base + k;
-      if (i < n) b.off[i] = (uint32_t)ex;
-      ex = sat_add(ex, cnt[k]);
-    }
-    if (tile == ntiles - 1 && threadIdx.x == 0) {
-      ctrl->C = grand;
-      const uint32_t hook = ctrl->force_overflow_at;
-      const bool forced = Q != kJoinSGBase && hook != 0 && hook == ctrl->iter + 1;
-      if (grand > ctrl->cand_cap || forced) atomicOr(&ctrl->overflow, 1u);
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint64_t incl = wave_incl_scan<uint64_t>(cnt[k]);
+        ex[k] = run + incl - cnt[k];
+        run = sat_add(run, __shfl(incl, kWave - 1, kWave));
+      }
+      uint64_t grand, tex;
+      const uint64_t g = tile_scan(lane == 0 ? run : 0ull, tile, epoch, b.status[kLbJoin],
+                                   &ctrl->error, &sh, grand, tex);
+      const uint64_t wave_base = __shfl(g, 0, kWave);
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint64_t i = wbase + (uint64_t)k * kWave + lane;
+        if (i < n) b.off[i] = (uint32_t)sat_add(wave_base, ex[k]);
+      }
+      if (tile == ntiles - 1 && threadIdx.x == 0) {
+        ctrl->C = grand;
+        const uint32_t hook = ctrl->force_overflow_at;
+        const bool forced = Q != kJoinSGBase && hook != 0 && hook == ctrl->iter + 1;
+        if (grand > ctrl->cand_cap || forced) atomicOr(&ctrl->overflow, 1u);
+      }
     }
   }
-  finish_launch(st, epoch, &s_flag);
 }
 
 // ---------------------------------------------------------------------------
-// Join, emit phase.  Output positions are dealt out in tiles; each position finds
-// the delta tuple that owns it by binary search over the scanned offsets (a
-// load-balanced expansion, so a hub tuple with thousands of matches is spread over
-// many threads instead of serialising one).  Writes are coalesced.
+// Join, emit phase.  Output positions are dealt out in tiles; each position finds the
+// delta tuple that owns it by binary search over the scanned offsets (a load-balanced
+// expansion, so a hub tuple with thousands of matches is spread over many threads
+// instead of serialising one).  Writes are coalesced.  The radix histograms of the
+// emitted keys are accumulated on the way.
 // ---------------------------------------------------------------------------
 template <typename K, int Q, int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int w) {
+__global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int w, int passes) {
   constexpr uint32_t T = kBlock * ITEMS;
   __shared__ uint32_t s_off[T];
+  __shared__ uint32_t s_h[kMaxPasses * kRadix];
   __shared__ uint64_t s_i0, s_i1;
   if (halted(ctrl)) return;
   const uint64_t C = ctrl->C;
   const uint64_t n = (Q == kJoinSGBase) ? ctrl->nu : ctrl->D;
+  const uint32_t slot = ctrl->sort_seq & 1u;
   const K* __restrict__ delta = b.delta[ctrl->delta_side];
   const uint32_t* __restrict__ off = b.off;
   const uint32_t* __restrict__ R = b.R;
   const uint32_t* __restrict__ Edst = b.Edst;
   K* __restrict__ cand = b.cand[0];
   const uint64_t ntiles = (C + T - 1) / T;
+  const int wid = threadIdx.x / kWave;
+  hist_begin(s_h, passes, b.ghist, slot);
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const uint64_t p0 = tile * T;
     const uint64_t p1 = min(p0 + T, C);
-    if (threadIdx.x == 0) {
-      s_i0 = upper_bound(off, n, (uint32_t)p0) - 1;
-      s_i1 = upper_bound(off, n, (uint32_t)(p1 - 1)) - 1;
+    // owners of the first and last position of the tile (two waves search concurrently)
+    if (wid == 0) {
+      const uint64_t i0 = wave_upper_bound(off, n, (uint32_t)p0) - 1;
+      if (lane_id() == 0) s_i0 = i0;
+    } else if (wid == 1) {
+      const uint64_t i1 = wave_upper_bound(off, n, (uint32_t)(p1 - 1)) - 1;
+      if (lane_id() == 0) s_i1 = i1;
     }
     __syncthreads();
     const uint64_t i0 = s_i0;
@@ -160,92 +249,59 @@ __global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int
       for (uint32_t j = threadIdx.x; j < span; j += kBlock) s_off[j] = off[i0 + j];
     }
     __syncthreads();
-#pragma unroll 2
+    uint32_t pos[ITEMS];
+#pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
       const uint64_t p = p0 + (uint64_t)k * kBlock + threadIdx.x;
-      if (p >= p1) break;
-      uint64_t li;
-      uint32_t start;
-      if (in_lds) {
-        li = upper_bound(s_off, span, (uint32_t)p) - 1;
-        start = s_off[li];
-      } else {
-        li = upper_bound(off + i0, span, (uint32_t)p) - 1;
-        start = off[i0 + li];
+      pos[k] = (uint32_t)min(p, p1 - 1);
+    }
+    uint64_t li[ITEMS];
+    if (in_lds) multi_upper_bound<uint32_t, ITEMS>(s_off, span, pos, li);
+    else multi_upper_bound<uint32_t, ITEMS>(off + i0, span, pos, li);
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint64_t p = p0 + (uint64_t)k * kBlock + threadIdx.x;
+      const bool valid = p < p1;
+      K key = 0;
+      if (valid) {
+        const uint64_t i = i0 + li[k] - 1;
+        const uint32_t start = in_lds ? s_off[li[k] - 1] : off[i];
+        const uint32_t r = (uint32_t)p - start;
+        if (Q == kJoinTC) {
+          const K dk = delta[i];
+          key = ((dk >> w) << w) | (K)Edst[R[b.rowb[i]] + r];
+        } else if (Q == kJoinSG) {
+          const K dk = delta[i];
+          const uint32_t ja = b.rowa[i], jb = b.rowb[i];
+          const uint32_t lb = R[jb + 1] - R[jb];
+          const uint32_t qa = r / lb;
+          const uint32_t rb = r - qa * lb;
+          const K inst = (dk >> w) >> w;
+          key = ((((inst << w) | (K)Edst[R[ja] + qa]) << w) | (K)Edst[R[jb] + rb]);
+        } else {
+          // base rule: ordered pairs (x, y) of distinct children of row i
+          const uint32_t len1 = R[i + 1] - R[i] - 1;
+          const uint32_t qa = r / len1;
+          uint32_t qb = r - qa * len1;
+          qb += (qb >= qa) ? 1u : 0u;
+          const K inst = (K)(b.U[i] >> w);
+          key = ((((inst << w) | (K)Edst[R[i] + qa]) << w) | (K)Edst[R[i] + qb]);
+        }
+        cand[p] = key;
       }
-      const uint64_t i = i0 + li;
-      const uint32_t r = (uint32_t)p - start;
-      K key;
-      if (Q == kJoinTC) {
-        const K dk = delta[i];
-        key = ((dk >> w) << w) | (K)Edst[R[b.rowb[i]] + r];
-      } else if (Q == kJoinSG) {
-        const K dk = delta[i];
-        const uint32_t ja = b.rowa[i], jb = b.rowb[i];
-        const uint32_t lb = R[jb + 1] - R[jb];
-        const uint32_t qa = r / lb;
-        const uint32_t rb = r - qa * lb;
-        const K inst = (dk >> w) >> w;
-        key = ((((inst << w) | (K)Edst[R[ja] + qa]) << w) | (K)Edst[R[jb] + rb]);
-      } else {
-        // base rule: ordered pairs (x, y) of distinct children of row i
-        const uint32_t len1 = R[i + 1] - R[i] - 1;
-        const uint32_t qa = r / len1;
-        uint32_t qb = r - qa * len1;
-        qb += (qb >= qa) ? 1u : 0u;
-        const K inst = (K)(b.U[i] >> w);
-        key = ((((inst << w) | (K)Edst[R[i] + qa]) << w) | (K)Edst[R[i] + qb]);
-      }
-      cand[p] = key;
+      hist_add<K>(s_h, key, valid, passes);
     }
     __syncthreads();
   }
+  hist_flush(s_h, passes, b.ghist, slot);
 }
 
 // ---------------------------------------------------------------------------
-// LSD radix sort (Section V-C): one histogram launch over all passes, then one
-// onesweep launch per 8-bit pass.  Passes run from the least significant digit of
-// the dst field up through the src field, each stable, ping-ponging between the
-// two candidate buffers.
+// One stable LSD scatter pass (Section V-C).  A tile is loaded wave-striped (wave w owns
+// a contiguous run of ITEMS*64 keys), ranked within each wave with ballot-based peer
+// masks, ranked across waves and tiles by per-digit prefix sums with decoupled lookback,
+// sorted by digit in LDS and written out so consecutive lanes write consecutive addresses.
 // ---------------------------------------------------------------------------
-template <typename K>
-__global__ __launch_bounds__(kBlock) void k_radix_hist(Ctrl* ctrl, const uint64_t* n_ptr,
-                                                       const K* __restrict__ keys, int passes,
-                                                       Bufs<K> b) {
-  __shared__ uint32_t s_h[kMaxPasses * kRadix];
-  __shared__ uint32_t s_wave[kWavesPerBlock];
-  __shared__ uint32_t s_flag;
-  if (halted(ctrl)) return;
-  const uint64_t n = *n_ptr;
-  for (int j = threadIdx.x; j < passes * kRadix; j += kBlock) s_h[j] = 0;
-  __syncthreads();
-  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
-       i += (uint64_t)gridDim.x * kBlock) {
-    const K k = keys[i];
-    for (int p = 0; p < passes; ++p)
-      atomicAdd(&s_h[p * kRadix + (uint32_t)((k >> (p * kRadixBits)) & (kRadix - 1))], 1u);
-  }
-  __syncthreads();
-  for (int j = threadIdx.x; j < passes * kRadix; j += kBlock)
-    if (s_h[j]) atomicAdd(&b.ghist[j], s_h[j]);
-  LbState* st = b.lb + kLbHist;
-  if (finish_launch(st, 0, &s_flag)) {
-    for (int p = 0; p < passes; ++p) {
-      const uint32_t v = __hip_atomic_load(&b.ghist[p * kRadix + threadIdx.x], __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-      uint32_t tot;
-      const uint32_t ex = block_excl_scan<uint32_t>(v, s_wave, tot);
-      b.gbase[p * kRadix + threadIdx.x] = ex;
-      __hip_atomic_store(&b.ghist[p * kRadix + threadIdx.x], 0u, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
-}
-
-// One stable scatter pass.  A tile is loaded wave-striped (wave w owns a contiguous
-// run of ITEMS*64 keys), ranked within each wave with ballot-based peer masks, ranked
-// across waves and tiles by per-digit prefix sums with decoupled lookback, sorted by
-// digit in LDS and written out so that consecutive lanes write consecutive addresses.
 template <typename K, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_radix_pass(Ctrl* ctrl, const uint64_t* n_ptr,
                                                        const K* __restrict__ in,
@@ -255,14 +311,14 @@ __global__ __launch_bounds__(kBlock) void k_radix_pass(Ctrl* ctrl, const uint64_
   __shared__ uint32_t s_cnt[kWavesPerBlock][kRadix];
   __shared__ uint32_t s_loc[kRadix];
   __shared__ uint64_t s_glob[kRadix];
+  __shared__ uint32_t s_base[kRadix];
   __shared__ uint32_t s_wave[kWavesPerBlock];
-  __shared__ uint32_t s_tile, s_flag;
+  __shared__ uint32_t s_claim[2];
   if (halted(ctrl)) return;
   const uint64_t n = *n_ptr;
   const uint64_t ntiles = (n + T - 1) / T;
   if (ntiles == 0) return;
   const int shift = pass * kRadixBits;
-  const uint32_t* __restrict__ gbase = b.gbase + pass * kRadix;
   uint64_t* status = b.status[kLbPass];
   LbState* st = b.lb + kLbPass;
   uint32_t* err = &ctrl->error;
@@ -271,113 +327,137 @@ __global__ __launch_bounds__(kBlock) void k_radix_pass(Ctrl* ctrl, const uint64_
   const int wid = tid / kWave;
   const int lane = lane_id();
   const uint64_t lt = lanemask_lt();
-  for (;;) {
-    for (int j = tid; j < kWavesPerBlock * kRadix; j += kBlock) (&s_cnt[0][0])[j] = 0;
-    const uint32_t tile = claim_tile(st, &s_tile);
-    if (tile >= ntiles) break;
-    const uint64_t tbase = (uint64_t)tile * T;
-    const uint64_t wbase = tbase + (uint64_t)wid * (ITEMS * kWave);
-    K key[ITEMS];
-    uint32_t rank[ITEMS];
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      const uint64_t idx = wbase + (uint64_t)k * kWave + lane;
-      key[k] = idx < n ? in[idx] : K(0);
-    }
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      const uint64_t idx = wbase + (uint64_t)k * kWave + lane;
-      const bool valid = idx < n;
-      const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
-      uint64_t peers = __ballot(valid);
-#pragma unroll
-      for (int bit = 0; bit < kRadixBits; ++bit) {
-        const bool set = (d >> bit) & 1u;
-        const uint64_t mset = __ballot(set);
-        peers &= set ? mset : ~mset;
-      }
-      const uint32_t below = __popcll(peers & lt);
-      uint32_t before = 0;
-      if (valid) before = s_cnt[wid][d];
-      if (valid && below == 0) s_cnt[wid][d] = before + __popcll(peers);
-      rank[k] = before + below;
-    }
-    __syncthreads();
-    // Thread `tid` owns digit `tid`: per-wave exclusive offsets, tile total, lookback.
+  {
+    // global start of every digit bucket: exclusive scan of the summed histogram copies
+    const uint32_t slot = ctrl->sort_seq & 1u;
     uint32_t tot = 0;
 #pragma unroll
-    for (int w2 = 0; w2 < kWavesPerBlock; ++w2) {
-      const uint32_t c = s_cnt[w2][tid];
-      s_cnt[w2][tid] = tot;
-      tot += c;
+    for (int c = 0; c < kHistCopies; ++c) tot += b.ghist[hist_base(slot, c, pass) + tid];
+    uint32_t all;
+    s_base[tid] = block_excl_scan<uint32_t>(tot, s_wave, all);
+  }
+  for (;;) {
+    const TileClaim cl = claim_tile(st, ntiles, s_claim);
+    if (!cl.ok) {
+      if (cl.last && threadIdx.x == 0) release_launch(st, epoch);
+      break;
     }
     {
-      uint64_t* sw = status + (uint64_t)tile * kRadix + tid;
-      uint64_t ex = 0;
-      if (tile == 0) {
-        status_store(sw, status_word(kFlagIncl, epoch, tot));
-      } else {
-        status_store(sw, status_word(kFlagAgg, epoch, tot));
-        int64_t t = (int64_t)tile - 1;
-        while (t >= 0) {
-          uint64_t s;
-          uint32_t spins = 0;
-          for (;;) {
-            s = status_load(status + (uint64_t)t * kRadix + tid);
-            if ((s >> 62) != 0 && ((uint32_t)(s >> 40) & kEpochMask) == epoch) break;
-            if (++spins > kSpinLimit) {
-              atomicOr(err, 1u);
-              s = kFlagIncl;
-              break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-          }
-          ex += s & kValMask;
-          if ((s >> 62) == 2) break;
-          --t;
-        }
-        status_store(sw, status_word(kFlagIncl, epoch, ex + tot));
-      }
-      s_glob[tid] = (uint64_t)gbase[tid] + ex;
-    }
-    uint32_t total;
-    const uint32_t loc = block_excl_scan<uint32_t>(tot, s_wave, total);
-    s_loc[tid] = loc;
-    __syncthreads();
+      const uint32_t tile = cl.tile;
+      for (int j = tid; j < kWavesPerBlock * kRadix; j += kBlock) (&s_cnt[0][0])[j] = 0;
+      __syncthreads();
+      const uint64_t tbase = (uint64_t)tile * T;
+      const uint64_t wbase = tbase + (uint64_t)wid * (ITEMS * kWave);
+      K key[ITEMS];
+      uint32_t rank[ITEMS];
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      const uint64_t idx = wbase + (uint64_t)k * kWave + lane;
-      if (idx < n) {
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint64_t idx = wbase + (uint64_t)k * kWave + lane;
+        key[k] = idx < n ? in[idx] : K(0);
+      }
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint64_t idx = wbase + (uint64_t)k * kWave + lane;
+        const bool valid = idx < n;
         const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
-        const uint32_t pos = s_loc[d] + s_cnt[wid][d] + rank[k];
-        if (pos < T) s_keys[pos] = key[k];
+        const uint64_t peers = digit_peers(d, __ballot(valid));
+        const uint32_t below = __popcll(peers & lt);
+        uint32_t before = 0;
+        if (valid) before = s_cnt[wid][d];
+        if (valid && below == 0) s_cnt[wid][d] = before + __popcll(peers);
+        rank[k] = before + below;
       }
-    }
-    __syncthreads();
-    const uint32_t tile_n = (uint32_t)min<uint64_t>(T, n - tbase);
+      __syncthreads();
+      // Thread `tid` owns digit `tid`: per-wave exclusive offsets, tile total, lookback.
+      uint32_t tot = 0;
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      const uint32_t j = (uint32_t)k * kBlock + tid;
-      if (j < tile_n) {
-        const K kk = s_keys[j];
-        const uint32_t d = (uint32_t)(kk >> shift) & (kRadix - 1);
-        const uint64_t pos = s_glob[d] + (j - s_loc[d]);
-        if (pos < n) out[pos] = kk;
+      for (int w2 = 0; w2 < kWavesPerBlock; ++w2) {
+        const uint32_t c = s_cnt[w2][tid];
+        s_cnt[w2][tid] = tot;
+        tot += c;
       }
+      {
+        uint64_t* sw = status + (uint64_t)tile * kRadix + tid;
+        uint64_t ex = 0;
+        if (tile == 0) {
+          status_store(sw, status_word(kFlagIncl, epoch, tot));
+        } else {
+          status_store(sw, status_word(kFlagAgg, epoch, tot));
+          // look back over up to 8 predecessor tiles per round, their loads in flight together
+          constexpr int kAhead = 8;
+          int64_t t = (int64_t)tile - 1;
+          bool found = false;
+          while (!found && t >= 0) {
+            uint64_t sv[kAhead];
+#pragma unroll
+            for (int j = 0; j < kAhead; ++j)
+              sv[j] = (t - j >= 0) ? status_load(status + (uint64_t)(t - j) * kRadix + tid) : kFlagIncl;
+#pragma unroll
+            for (int j = 0; j < kAhead; ++j) {
+              if (found) break;
+              uint64_t s = sv[j];
+              uint32_t spins = 0;
+              while (t - j >= 0 && !((s >> 62) != 0 && ((uint32_t)(s >> 40) & kEpochMask) == epoch)) {
+                if (++spins > kSpinLimit) {
+                  atomicOr(err, 1u);
+                  s = kFlagIncl;
+                  break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                s = status_load(status + (uint64_t)(t - j) * kRadix + tid);
+              }
+              ex += s & kValMask;
+              if ((s >> 62) == 2) found = true;
+            }
+            t -= kAhead;
+          }
+          status_store(sw, status_word(kFlagIncl, epoch, ex + tot));
+        }
+        s_glob[tid] = (uint64_t)s_base[tid] + ex;
+      }
+      uint32_t total;
+      const uint32_t loc = block_excl_scan<uint32_t>(tot, s_wave, total);
+      s_loc[tid] = loc;
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint64_t idx = wbase + (uint64_t)k * kWave + lane;
+        if (idx < n) {
+          const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
+          const uint32_t pos = s_loc[d] + s_cnt[wid][d] + rank[k];
+          if (pos < T) s_keys[pos] = key[k];
+        }
+      }
+      __syncthreads();
+      const uint32_t tile_n = (uint32_t)min<uint64_t>(T, n - tbase);
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t j = (uint32_t)k * kBlock + tid;
+        if (j < tile_n) {
+          const K kk = s_keys[j];
+          const uint32_t d = (uint32_t)(kk >> shift) & (kRadix - 1);
+          const uint64_t pos = s_glob[d] + (j - s_loc[d]);
+          if (pos < n) out[pos] = kk;
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
-  finish_launch(st, epoch, &s_flag);
 }
 
 // ---------------------------------------------------------------------------
-// Fused dedup + set difference (Section IV-B).  A candidate survives when it is the
-// first of its run of equal keys and is absent from Full.  Each tile finds the window
-// of Full that can hold its keys with two binary searches, stages it in LDS when it is
+// Fused dedup + set difference (Section IV-B).  A candidate survives when it is the first
+// of its run of equal keys and is absent from Full.  Each tile finds the window of Full
+// that can hold its keys with two wave-parallel searches, stages it in LDS when it is
 // small, classifies its candidates, and compacts survivors in input order with a
 // single-pass scan, so the output stays sorted.
+//
+// The launch's last claimer publishes the iteration: |Delta^i|, the new Full size and the
+// flipped ping-pong sides (Section V-C), so the merge that follows reads its shape from
+// the control block and the next iteration starts from the new delta.
 // ---------------------------------------------------------------------------
-__device__ void dedup_epilogue(Ctrl* c, int mode, uint64_t cnt, uint64_t* hist) {
+__device__ void dedup_publish(Ctrl* c, int mode, uint64_t cnt, uint64_t* hist) {
+  c->sort_seq = c->sort_seq + 1;
   if (mode & kModeIter) {
     const uint64_t F = c->F;
     const uint32_t it = c->iter;
@@ -389,8 +469,16 @@ __device__ void dedup_epilogue(Ctrl* c, int mode, uint64_t cnt, uint64_t* hist) 
     hist[2 * (uint64_t)(it + 1) + 1] = c->C;
     c->total_cand += c->C;
     c->iter = it + 1;
-    if (cnt == 0) c->done = 1;
-    else if (c->max_iter != 0 && it + 1 >= c->max_iter) c->limit_hit = 1;
+    if (cnt == 0) {
+      c->done = 1;
+      return;
+    }
+    // Delta^i lives in the other delta buffer; Full' goes to the other Full buffer
+    c->F = F + cnt;
+    c->D = cnt;
+    c->full_side ^= 1u;
+    c->delta_side ^= 1u;
+    if (c->max_iter != 0 && it + 1 >= c->max_iter) c->limit_hit = 1;
     return;
   }
   if (mode & kModeEdges) c->m_unique = cnt;
@@ -418,7 +506,7 @@ __global__ __launch_bounds__(kBlock) void k_dedup_diff(Ctrl* ctrl, int mode, con
   __shared__ K s_f[T];
   __shared__ TileScanShared sh;
   __shared__ uint64_t s_flo, s_fhi;
-  __shared__ uint32_t s_tile, s_flag;
+  __shared__ uint32_t s_claim[2];
   if (halted(ctrl)) return;
   const uint64_t n = *n_ptr;
   const bool diff = (mode & kModeIter) != 0;
@@ -449,99 +537,120 @@ __global__ __launch_bounds__(kBlock) void k_dedup_diff(Ctrl* ctrl, int mode, con
   }
   const uint64_t ntiles = (n + T - 1) / T;
   if (ntiles == 0) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) dedup_epilogue(ctrl, mode, 0, b.hist);
+    if (blockIdx.x == 0 && threadIdx.x == 0) dedup_publish(ctrl, mode, 0, b.hist);
     return;
   }
   LbState* st = b.lb + kLbDedup;
   const uint32_t epoch = launch_epoch(st);
+  const int wid = threadIdx.x / kWave;
   for (;;) {
-    const uint32_t tile = claim_tile(st, &s_tile);
-    if (tile >= ntiles) break;
-    const uint64_t tbase = (uint64_t)tile * T;
-    const uint32_t tn = (uint32_t)min<uint64_t>(T, n - tbase);
-    for (uint32_t j = threadIdx.x; j < tn; j += kBlock) s_c[j + 1] = cand[tbase + j];
-    if (threadIdx.x == 0) {
-      if (tile > 0) s_c[0] = cand[tbase - 1];
-      if (diff) {
-        const uint64_t flo = lower_bound(full, F, cand[tbase]);
-        s_flo = flo;
-        s_fhi = flo + upper_bound(full + flo, F - flo, cand[tbase + tn - 1]);
+    const TileClaim cl = claim_tile(st, ntiles, s_claim);
+    if (!cl.ok) {
+      if (cl.last && threadIdx.x == 0) {
+        __threadfence();
+        const uint64_t total = __hip_atomic_load(&ctrl->total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        dedup_publish(ctrl, mode, total, b.hist);
+        release_launch(st, epoch);
       }
+      break;
     }
-    __syncthreads();
-    uint64_t flo = 0, fspan = 0;
-    bool win = false;
-    if (diff) {
-      flo = s_flo;
-      fspan = s_fhi - flo;
-      win = fspan <= T;
-      if (win) {
-        for (uint32_t j = threadIdx.x; j < fspan; j += kBlock) s_f[j] = full[flo + j];
+    {
+      const uint32_t tile = cl.tile;
+      const uint64_t tbase = (uint64_t)tile * T;
+      const uint32_t tn = (uint32_t)min<uint64_t>(T, n - tbase);
+      for (uint32_t j = threadIdx.x; j < tn; j += kBlock) s_c[j + 1] = cand[tbase + j];
+      if (threadIdx.x == 0 && tile > 0) s_c[0] = cand[tbase - 1];
+      if (diff) {
+        // window of Full that can hold this tile's keys (two waves search concurrently)
+        if (wid == 0) {
+          const uint64_t flo = wave_lower_bound(full, F, cand[tbase]);
+          if (lane_id() == 0) s_flo = flo;
+        } else if (wid == 1) {
+          const uint64_t fhi = wave_upper_bound(full, F, cand[tbase + tn - 1]);
+          if (lane_id() == 0) s_fhi = fhi;
+        }
       }
       __syncthreads();
-    }
-    uint32_t keep_mask = 0, cnt = 0;
-    const uint32_t j0 = threadIdx.x * ITEMS;
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      const uint32_t j = j0 + k;
-      if (j < tn) {
-        const K c = s_c[j + 1];
-        bool keep = (tbase + j == 0) || (c != s_c[j]);
-        if (keep && fspan > 0) {
-          if (win) {
-            const uint64_t pos = lower_bound(s_f, fspan, c);
-            if (pos < fspan && s_f[pos] == c) keep = false;
-          } else {
-            const uint64_t pos = lower_bound(full + flo, fspan, c);
-            if (pos < fspan && full[flo + pos] == c) keep = false;
-          }
+      uint64_t flo = 0, fspan = 0;
+      bool win = false;
+      if (diff) {
+        flo = s_flo;
+        fspan = s_fhi > flo ? s_fhi - flo : 0;
+        win = fspan <= T;
+        if (win) {
+          for (uint32_t j = threadIdx.x; j < fspan; j += kBlock) s_f[j] = full[flo + j];
         }
-        if (keep) {
+        __syncthreads();
+      }
+      uint32_t keep_mask = 0, cnt = 0;
+      const uint32_t j0 = threadIdx.x * ITEMS;
+      K cv[ITEMS];
+      bool dup[ITEMS];
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t j = j0 + k;
+        cv[k] = (j < tn) ? s_c[j + 1] : K(0);
+        dup[k] = (j >= tn) || !((tbase + j == 0) || (cv[k] != s_c[j]));
+      }
+      bool member[ITEMS];
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) member[k] = false;
+      if (fspan > 0) {
+        uint64_t pos[ITEMS];
+        if (win) {
+          multi_lower_bound<K, ITEMS>(s_f, fspan, cv, pos);
+#pragma unroll
+          for (int k = 0; k < ITEMS; ++k) member[k] = pos[k] < fspan && s_f[pos[k]] == cv[k];
+        } else {
+          multi_lower_bound<K, ITEMS>(full + flo, fspan, cv, pos);
+#pragma unroll
+          for (int k = 0; k < ITEMS; ++k) member[k] = pos[k] < fspan && full[flo + pos[k]] == cv[k];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        if (!dup[k] && !member[k]) {
           keep_mask |= 1u << k;
           ++cnt;
         }
       }
-    }
-    uint64_t grand, tex;
-    const uint64_t g = tile_scan(cnt, tile, epoch, b.status[kLbDedup], &ctrl->error, &sh, grand, tex);
-    // tile_scan ends with a barrier, so s_f is free to reuse for the survivors.
-    uint32_t lpos = (uint32_t)(g - tex);
+      uint64_t grand, tex;
+      const uint64_t g = tile_scan(cnt, tile, epoch, b.status[kLbDedup], &ctrl->error, &sh, grand, tex);
+      // tile_scan ends with a barrier, so s_f is free to reuse for the survivors.
+      uint32_t lpos = (uint32_t)(g - tex);
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k)
-      if ((keep_mask >> k) & 1u) s_f[lpos++] = s_c[j0 + k + 1];
-    __syncthreads();
-    const uint32_t tcount = (uint32_t)(grand - tex);
-    for (uint32_t j = threadIdx.x; j < tcount; j += kBlock) {
-      const uint64_t p = tex + j;
-      const K v = s_f[j];
-      if (p < cap1) out1[p] = v;
-      if (out2 && p < cap2) out2[p] = v;
-      if (out3 && p < cap3) out3[p] = v;
+      for (int k = 0; k < ITEMS; ++k)
+        if ((keep_mask >> k) & 1u) s_f[lpos++] = cv[k];
+      __syncthreads();
+      const uint32_t tcount = (uint32_t)(grand - tex);
+      for (uint32_t j = threadIdx.x; j < tcount; j += kBlock) {
+        const uint64_t p = tex + j;
+        const K v = s_f[j];
+        if (p < cap1) out1[p] = v;
+        if (out2 && p < cap2) out2[p] = v;
+        if (out3 && p < cap3) out3[p] = v;
+      }
+      if (tile == ntiles - 1 && threadIdx.x == 0)
+        __hip_atomic_store(&ctrl->total, grand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __syncthreads();
     }
-    if (tile == ntiles - 1 && threadIdx.x == 0) dedup_epilogue(ctrl, mode, grand, b.hist);
-    __syncthreads();
   }
-  finish_launch(st, epoch, &s_flag);
 }
 
 // ---------------------------------------------------------------------------
-// Disjoint merge (Section IV-C).  Full and the new delta are disjoint by construction,
-// so Full' has exactly |Full| + |Delta| keys and each tile's slice of both inputs is
-// fixed by a merge-path diagonal search: no atomics, no cleanup pass.  Tiles that take
-// keys from one input only are straight copies.  The last block publishes the new
-// sizes and flips the ping-pong sides (Section V-C).
+// Disjoint merge (Section IV-C).  Full and the new delta are disjoint by construction, so
+// Full' has exactly |Full| + |Delta| keys and each tile's slice of both inputs is fixed by
+// a merge-path diagonal search: no atomics, no cleanup pass.  Tiles that take keys from
+// one input only are straight copies.  The sizes and sides were published by dedup_diff:
+// Full' goes to full[full_side], the old Full is the other buffer.
 // ---------------------------------------------------------------------------
+// Number of A keys among the first `diag` keys of merge(A, B), found by the whole wave.
 template <typename K>
-__device__ __forceinline__ uint64_t merge_path(const K* A, uint64_t na, const K* B, uint64_t nb,
-                                               uint64_t diag) {
-  uint64_t lo = diag > nb ? diag - nb : 0;
-  uint64_t hi = diag < na ? diag : na;
-  while (lo < hi) {
-    const uint64_t mid = (lo + hi) >> 1;
-    if (A[mid] < B[diag - 1 - mid]) lo = mid + 1; else hi = mid;
-  }
-  return lo;
+__device__ __forceinline__ uint64_t wave_merge_path(const K* A, uint64_t na, const K* B, uint64_t nb,
+                                                    uint64_t diag) {
+  const uint64_t lo = diag > nb ? diag - nb : 0;
+  const uint64_t hi = diag < na ? diag : na;
+  return wave_partition(lo, hi, [&](uint64_t i) { return A[i] < B[diag - 1 - i]; });
 }
 
 template <typename K, int ITEMS>
@@ -550,21 +659,25 @@ __global__ __launch_bounds__(kBlock) void k_merge(Ctrl* ctrl, Bufs<K> b) {
   __shared__ K s_in[T];
   __shared__ K s_out[T];
   __shared__ uint64_t s_i0, s_i1;
-  __shared__ uint32_t s_flag;
   if (halted(ctrl)) return;
-  const uint64_t na = ctrl->F, nb = ctrl->N;
+  const uint64_t total = ctrl->F;
+  const uint64_t nb = ctrl->N;
+  const uint64_t na = total - nb;
   const uint32_t fs = ctrl->full_side, ds = ctrl->delta_side;
-  const K* __restrict__ A = b.full[fs];
-  const K* __restrict__ B = b.delta[ds ^ 1u];
-  K* __restrict__ O = b.full[fs ^ 1u];
-  const uint64_t total = na + nb;
+  const K* __restrict__ A = b.full[fs ^ 1u];
+  const K* __restrict__ B = b.delta[ds];
+  K* __restrict__ O = b.full[fs];
   const uint64_t ntiles = (total + T - 1) / T;
+  const int wid = threadIdx.x / kWave;
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const uint64_t o0 = tile * T;
     const uint64_t o1 = min(o0 + T, total);
-    if (threadIdx.x == 0) {
-      s_i0 = merge_path(A, na, B, nb, o0);
-      s_i1 = merge_path(A, na, B, nb, o1);
+    if (wid == 0) {
+      const uint64_t i0 = wave_merge_path(A, na, B, nb, o0);
+      if (lane_id() == 0) s_i0 = i0;
+    } else if (wid == 1) {
+      const uint64_t i1 = wave_merge_path(A, na, B, nb, o1);
+      if (lane_id() == 0) s_i1 = i1;
     }
     __syncthreads();
     const uint64_t i0 = s_i0, i1 = s_i1;
@@ -601,23 +714,17 @@ __global__ __launch_bounds__(kBlock) void k_merge(Ctrl* ctrl, Bufs<K> b) {
     }
     __syncthreads();
   }
-  if (finish_launch(b.lb + kLbMerge, 0, &s_flag) && threadIdx.x == 0) {
-    ctrl->F = total;
-    ctrl->D = nb;
-    ctrl->full_side = fs ^ 1u;
-    ctrl->delta_side = ds ^ 1u;
-  }
 }
 
 // ---------------------------------------------------------------------------
-// Edge index: E is sorted once and never modified (Section IV-A), so the edges of
-// each (inst, src) row are contiguous.  U lists the distinct rows, R their starts.
+// Edge index: E is sorted once and never modified (Section IV-A), so the edges of each
+// (inst, src) row are contiguous.  U lists the distinct rows, R their starts.
 // ---------------------------------------------------------------------------
 template <typename K, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_edge_index(Ctrl* ctrl, Bufs<K> b, int w) {
   constexpr uint32_t T = kBlock * ITEMS;
   __shared__ TileScanShared sh;
-  __shared__ uint32_t s_tile, s_flag;
+  __shared__ uint32_t s_claim[2];
   if (ctrl->error | ctrl->overflow) return;
   const uint64_t n = ctrl->m_unique;
   const K* __restrict__ E = b.E;
@@ -633,39 +740,44 @@ __global__ __launch_bounds__(kBlock) void k_edge_index(Ctrl* ctrl, Bufs<K> b, in
   LbState* st = b.lb + kLbIndex;
   const uint32_t epoch = launch_epoch(st);
   for (;;) {
-    const uint32_t tile = claim_tile(st, &s_tile);
-    if (tile >= ntiles) break;
-    const uint64_t base = (uint64_t)tile * T + (uint64_t)threadIdx.x * ITEMS;
-    uint32_t heads = 0, cnt = 0;
+    const TileClaim cl = claim_tile(st, ntiles, s_claim);
+    if (!cl.ok) {
+      if (cl.last && threadIdx.x == 0) release_launch(st, epoch);
+      break;
+    }
+    {
+      const uint32_t tile = cl.tile;
+      const uint64_t base = (uint64_t)tile * T + (uint64_t)threadIdx.x * ITEMS;
+      uint32_t heads = 0, cnt = 0;
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      const uint64_t i = base + k;
-      if (i < n) {
-        const K e = E[i];
-        b.Edst[i] = (uint32_t)(e & mask);
-        if (i == 0 || (e >> w) != (E[i - 1] >> w)) {
-          heads |= 1u << k;
-          ++cnt;
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint64_t i = base + k;
+        if (i < n) {
+          const K e = E[i];
+          b.Edst[i] = (uint32_t)(e & mask);
+          if (i == 0 || (e >> w) != (E[i - 1] >> w)) {
+            heads |= 1u << k;
+            ++cnt;
+          }
         }
       }
-    }
-    uint64_t grand, tex;
-    uint64_t g = tile_scan(cnt, tile, epoch, b.status[kLbIndex], &ctrl->error, &sh, grand, tex);
+      uint64_t grand, tex;
+      uint64_t g = tile_scan(cnt, tile, epoch, b.status[kLbIndex], &ctrl->error, &sh, grand, tex);
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      if ((heads >> k) & 1u) {
-        const uint64_t i = base + k;
-        b.U[g] = (uint32_t)(E[i] >> w);
-        b.R[g] = (uint32_t)i;
-        ++g;
+      for (int k = 0; k < ITEMS; ++k) {
+        if ((heads >> k) & 1u) {
+          const uint64_t i = base + k;
+          b.U[g] = (uint32_t)(E[i] >> w);
+          b.R[g] = (uint32_t)i;
+          ++g;
+        }
+      }
+      if (tile == ntiles - 1 && threadIdx.x == 0) {
+        ctrl->nu = grand;
+        b.R[grand] = (uint32_t)n;
       }
     }
-    if (tile == ntiles - 1 && threadIdx.x == 0) {
-      ctrl->nu = grand;
-      b.R[grand] = (uint32_t)n;
-    }
   }
-  finish_launch(st, epoch, &s_flag);
 }
 
 // SG with WG_SG_IRREFLEXIVE: drop (x, x) from the final relation (Full -> other side).
@@ -674,7 +786,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_offdiag(Ctrl* ctrl, Bufs<K> b
   constexpr uint32_t T = kBlock * ITEMS;
   __shared__ TileScanShared sh;
   __shared__ K s_out[T];
-  __shared__ uint32_t s_tile, s_flag;
+  __shared__ uint32_t s_claim[2];
   if (ctrl->error) return;
   const uint64_t n = ctrl->F;
   const uint32_t fs = ctrl->full_side;
@@ -686,39 +798,47 @@ __global__ __launch_bounds__(kBlock) void k_filter_offdiag(Ctrl* ctrl, Bufs<K> b
   LbState* st = b.lb + kLbFilter;
   const uint32_t epoch = launch_epoch(st);
   for (;;) {
-    const uint32_t tile = claim_tile(st, &s_tile);
-    if (tile >= ntiles) break;
-    const uint64_t base = (uint64_t)tile * T + (uint64_t)threadIdx.x * ITEMS;
-    uint32_t keep = 0, cnt = 0;
-    K v[ITEMS];
+    const TileClaim cl = claim_tile(st, ntiles, s_claim);
+    if (!cl.ok) {
+      if (cl.last && threadIdx.x == 0) {
+        __threadfence();
+        ctrl->F = __hip_atomic_load(&ctrl->total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ctrl->full_side = fs ^ 1u;
+        release_launch(st, epoch);
+      }
+      break;
+    }
+    {
+      const uint32_t tile = cl.tile;
+      const uint64_t base = (uint64_t)tile * T + (uint64_t)threadIdx.x * ITEMS;
+      uint32_t keep = 0, cnt = 0;
+      K v[ITEMS];
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      const uint64_t i = base + k;
-      v[k] = 0;
-      if (i < n) {
-        v[k] = in[i];
-        if (((v[k] >> w) & mask) != (v[k] & mask)) {
-          keep |= 1u << k;
-          ++cnt;
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint64_t i = base + k;
+        v[k] = 0;
+        if (i < n) {
+          v[k] = in[i];
+          if (((v[k] >> w) & mask) != (v[k] & mask)) {
+            keep |= 1u << k;
+            ++cnt;
+          }
         }
       }
-    }
-    uint64_t grand, tex;
-    const uint64_t g = tile_scan(cnt, tile, epoch, b.status[kLbFilter], &ctrl->error, &sh, grand, tex);
-    uint32_t lpos = (uint32_t)(g - tex);
+      uint64_t grand, tex;
+      const uint64_t g = tile_scan(cnt, tile, epoch, b.status[kLbFilter], &ctrl->error, &sh, grand, tex);
+      uint32_t lpos = (uint32_t)(g - tex);
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k)
-      if ((keep >> k) & 1u) s_out[lpos++] = v[k];
-    __syncthreads();
-    const uint32_t tcount = (uint32_t)(grand - tex);
-    for (uint32_t j = threadIdx.x; j < tcount; j += kBlock) out[tex + j] = s_out[j];
-    if (tile == ntiles - 1 && threadIdx.x == 0) {
-      ctrl->F = grand;
-      ctrl->full_side = fs ^ 1u;
+      for (int k = 0; k < ITEMS; ++k)
+        if ((keep >> k) & 1u) s_out[lpos++] = v[k];
+      __syncthreads();
+      const uint32_t tcount = (uint32_t)(grand - tex);
+      for (uint32_t j = threadIdx.x; j < tcount; j += kBlock) out[tex + j] = s_out[j];
+      if (tile == ntiles - 1 && threadIdx.x == 0)
+        __hip_atomic_store(&ctrl->total, grand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __syncthreads();
     }
-    __syncthreads();
   }
-  finish_launch(st, epoch, &s_flag);
 }
 
 template <typename K>
@@ -760,9 +880,10 @@ void launch_max_id(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint32_t* src
 }
 
 template <typename K>
-void launch_pack(hipStream_t s, const Grid& g, const uint32_t* src, const uint32_t* dst,
-                 uint64_t m, int w, K* keys) {
-  hipLaunchKernelGGL(k_pack<K>, dim3(stream_blocks(g, m)), dim3(kBlock), 0, s, src, dst, m, w, keys);
+void launch_pack(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint32_t* src, const uint32_t* dst,
+                 uint64_t m, int w, K* keys, int passes, const Bufs<K>& b) {
+  hipLaunchKernelGGL(k_pack<K>, dim3(g.persistent), dim3(kBlock), 0, s, ctrl, src, dst, m, w, keys,
+                     passes, b);
 }
 
 template <typename K>
@@ -776,19 +897,14 @@ void launch_join_count(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const
 }
 
 template <typename K>
-void launch_join_emit(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w) {
+void launch_join_emit(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w,
+                      int passes) {
   if (kind == kJoinTC)
-    hipLaunchKernelGGL((k_join_emit<K, kJoinTC, kEmitItems>), dim3(g.stream), dim3(kBlock), 0, s, ctrl, b, w);
+    hipLaunchKernelGGL((k_join_emit<K, kJoinTC, kEmitItems>), dim3(g.stream), dim3(kBlock), 0, s, ctrl, b, w, passes);
   else if (kind == kJoinSG)
-    hipLaunchKernelGGL((k_join_emit<K, kJoinSG, kEmitItems>), dim3(g.stream), dim3(kBlock), 0, s, ctrl, b, w);
+    hipLaunchKernelGGL((k_join_emit<K, kJoinSG, kEmitItems>), dim3(g.stream), dim3(kBlock), 0, s, ctrl, b, w, passes);
   else
-    hipLaunchKernelGGL((k_join_emit<K, kJoinSGBase, kEmitItems>), dim3(g.stream), dim3(kBlock), 0, s, ctrl, b, w);
-}
-
-template <typename K>
-void launch_radix_hist(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint64_t* n_ptr,
-                       const K* keys, int passes, const Bufs<K>& b) {
-  hipLaunchKernelGGL(k_radix_hist<K>, dim3(g.persistent), dim3(kBlock), 0, s, ctrl, n_ptr, keys, passes, b);
+    hipLaunchKernelGGL((k_join_emit<K, kJoinSGBase, kEmitItems>), dim3(g.stream), dim3(kBlock), 0, s, ctrl, b, w, passes);
 }
 
 template <typename K>
@@ -832,12 +948,10 @@ void launch_resume(hipStream_t s, Ctrl* ctrl, uint64_t cand_cap, uint64_t full_c
 }
 
 #define WG_INSTANTIATE(K)                                                                          \
-  template void launch_pack<K>(hipStream_t, const Grid&, const uint32_t*, const uint32_t*,       \
-                               uint64_t, int, K*);                                                \
+  template void launch_pack<K>(hipStream_t, const Grid&, Ctrl*, const uint32_t*, const uint32_t*, \
+                               uint64_t, int, K*, int, const Bufs<K>&);                            \
   template void launch_join_count<K>(hipStream_t, const Grid&, int, Ctrl*, const Bufs<K>&, int);   \
-  template void launch_join_emit<K>(hipStream_t, const Grid&, int, Ctrl*, const Bufs<K>&, int);    \
-  template void launch_radix_hist<K>(hipStream_t, const Grid&, Ctrl*, const uint64_t*, const K*,   \
-                                     int, const Bufs<K>&);                                         \
+  template void launch_join_emit<K>(hipStream_t, const Grid&, int, Ctrl*, const Bufs<K>&, int, int); \
   template void launch_radix_pass<K>(hipStream_t, const Grid&, Ctrl*, const uint64_t*, const K*,   \
                                      K*, int, const Bufs<K>&);                                     \
   template void launch_dedup_diff<K>(hipStream_t, const Grid&, int, Ctrl*, const uint64_t*,        \

@@ -43,7 +43,7 @@ class WgOptions(ctypes.Structure):
         ("batch_k", c_uint32),
         ("loop_mode", c_uint32),
         ("radix_field_bits", c_uint32),
-        ("reserved", c_uint32),
+        ("timing_stages", c_uint32),
         ("max_iterations", c_uint64),
         ("mem_budget_bytes", c_uint64),
         ("force_overflow_at_iter", c_uint64),
@@ -176,7 +176,7 @@ def wg_last_error(engine) -> str:
 
 def make_options(flags: int = 0, batch_k: int = 0, loop_mode: int = WG_LOOP_AUTO,
                  radix_field_bits: int = 0, max_iterations: int = 0, mem_budget_bytes: int = 0,
-                 force_overflow_at_iter: int = 0) -> WgOptions:
+                 force_overflow_at_iter: int = 0, timing_stages: int = 0) -> WgOptions:
     o = WgOptions()
     o.struct_size = ctypes.sizeof(WgOptions)
     o.flags = flags
@@ -186,6 +186,7 @@ def make_options(flags: int = 0, batch_k: int = 0, loop_mode: int = WG_LOOP_AUTO
     o.max_iterations = max_iterations
     o.mem_budget_bytes = mem_budget_bytes
     o.force_overflow_at_iter = force_overflow_at_iter
+    o.timing_stages = timing_stages
     return o
 
 
