@@ -44,7 +44,7 @@ struct Ctrl {
   uint32_t delta_side;   // which delta buffer holds Delta^{i-1}
   uint32_t maxid;        // largest vertex id of the input
   uint32_t force_overflow_at;  // test hook: report a candidate overflow at this iteration
-  uint32_t sort_seq;     // sorts completed; its parity selects the histogram slot
+  uint32_t pad0;
   uint64_t D0;           // |Delta^0|, the seed size
   uint64_t total;        // hand-over of a launch-wide total to the launch's last claimer
 };

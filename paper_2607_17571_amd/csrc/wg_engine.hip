@@ -45,7 +45,8 @@ struct wg_engine {
   Ctrl* h_down = nullptr;  // pinned readback, 2 slots
   hipEvent_t ev_batch[2] = {nullptr, nullptr};
   LbState* d_lb = nullptr;
-  uint32_t* d_ghist = nullptr;
+  uint32_t* d_rcnt = nullptr;
+  uint32_t* d_rtot = nullptr;
   DevBuf status[kLbCount];
   DevBuf cand[2], full[2], delta[2], E, U, R, Edst, rowa, rowb, off, hist;
   size_t allocated = 0;
@@ -193,10 +194,6 @@ void size_buffers(wg_engine* e, bool keep, const Ctrl* c) {
   }
 }
 
-void clear_histograms(wg_engine* e) {
-  hip_check(e, hipMemsetAsync(e->d_ghist, 0, sizeof(uint32_t) * kHistWords, e->stream), "memset");
-}
-
 void refresh_epochs(wg_engine* e) {
   sync_stream(e);
   for (int s = 0; s < kLbCount; ++s)
@@ -223,7 +220,8 @@ Bufs<K> make_bufs(wg_engine* e) {
   b.hist = (uint64_t*)e->hist.p;
   b.lb = e->d_lb;
   for (int s = 0; s < kLbCount; ++s) b.status[s] = (uint64_t*)e->status[s].p;
-  b.ghist = e->d_ghist;
+  b.rcnt = e->d_rcnt;
+  b.rtot = e->d_rtot;
   return b;
 }
 
@@ -270,7 +268,6 @@ void collect_timing(wg_engine* e, wg_stats* st) {
 // ----- pipeline pieces
 template <typename K>
 void enqueue_sort(wg_engine* e, const Bufs<K>& b, const uint64_t* n_ptr, int passes) {
-  // the digit histograms come from the kernel that produced the keys (pack or emit);
   // one event pair brackets all passes, so stage_ms / launches is the mean pass time
   begin(e, WG_STAGE_RADIX_PASS);
   for (int p = 0; p < passes; ++p)
@@ -285,7 +282,7 @@ void enqueue_iteration(wg_engine* e, const Bufs<K>& b, int kind, int w, int pass
   launch_join_count<K>(e->stream, e->grid, kind, e->d_ctrl, b, w);
   end(e, WG_STAGE_JOIN_COUNT);
   begin(e, WG_STAGE_JOIN_EMIT);
-  launch_join_emit<K>(e->stream, e->grid, kind, e->d_ctrl, b, w, passes);
+  launch_join_emit<K>(e->stream, e->grid, kind, e->d_ctrl, b, w);
   end(e, WG_STAGE_JOIN_EMIT);
   enqueue_sort<K>(e, b, &e->d_ctrl->C, passes);
   begin(e, WG_STAGE_DEDUP_DIFF);
@@ -327,8 +324,6 @@ void grow_and_resume(wg_engine* e, const Ctrl& c, bool hooked) {
   e->full_cap = full;
   e->dsz_cap = dsz;
   size_buffers(e, true, &c);
-  // the abandoned attempt may have accumulated digit counts for the sort it never finished
-  clear_histograms(e);
   launch_resume(e->stream, e->d_ctrl, e->cand_cap, e->full_cap, e->dsz_cap, clear_hook ? 1u : 0u);
 }
 
@@ -345,11 +340,11 @@ void bytes_model(wg_stats* st, int query, uint32_t kb, int passes, uint64_t m,
                  const std::vector<uint64_t>& N, const std::vector<uint64_t>& C, uint64_t base_cand) {
   // prepare: max scan + pack + sort + dedup of m edges + index
   add_bytes(st, WG_STAGE_PREPARE, 8.0 * m + (8.0 + kb) * m + (kb + 12.0) * m);
-  add_bytes(st, WG_STAGE_RADIX_PASS, 2.0 * kb * m * passes);
+  add_bytes(st, WG_STAGE_RADIX_PASS, 3.0 * kb * m * passes);
   add_bytes(st, WG_STAGE_DEDUP_DIFF, (double)kb * m + (double)kb * N[0] * (query == WG_QUERY_TC ? 3 : 0));
   if (query == WG_QUERY_SG) {
     add_bytes(st, WG_STAGE_JOIN_EMIT, (double)(kb + 8) * base_cand);
-    add_bytes(st, WG_STAGE_RADIX_PASS, 2.0 * kb * base_cand * passes);
+    add_bytes(st, WG_STAGE_RADIX_PASS, 3.0 * kb * base_cand * passes);
     add_bytes(st, WG_STAGE_DEDUP_DIFF, (double)kb * base_cand + 2.0 * kb * N[0]);
   }
   uint64_t F = N[0];
@@ -359,7 +354,7 @@ void bytes_model(wg_stats* st, int query, uint32_t kb, int passes, uint64_t m,
     const double D = (double)N[i - 1], c = (double)C[i], n = (double)N[i];
     add_bytes(st, WG_STAGE_JOIN_COUNT, D * (kb + row_bytes));
     add_bytes(st, WG_STAGE_JOIN_EMIT, D * (kb + row_bytes) + c * (edst + kb));
-    add_bytes(st, WG_STAGE_RADIX_PASS, 2.0 * c * kb * passes);
+    add_bytes(st, WG_STAGE_RADIX_PASS, 3.0 * c * kb * passes);
     add_bytes(st, WG_STAGE_DEDUP_DIFF, (c + n) * kb);
     if (N[i] > 0) add_bytes(st, WG_STAGE_MERGE, 2.0 * ((double)F + n) * kb);
     F += N[i];
@@ -391,12 +386,11 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   c0.max_iter = (uint32_t)std::min<uint64_t>(o.max_iterations, 0xFFFFFFFFu);
   c0.force_overflow_at = (uint32_t)std::min<uint64_t>(o.force_overflow_at_iter, 0xFFFFFFFFu);
   hip_check(e, hipMemcpyAsync(e->d_ctrl, e->h_up, sizeof(Ctrl), hipMemcpyHostToDevice, e->stream), "upload");
-  clear_histograms(e);
 
   // ---- prepare: sort + dedup E, edge index, seed (Section IV-A: E sorted once)
   Bufs<K> b = make_bufs<K>(e);
   begin(e, WG_STAGE_PREPARE);
-  launch_pack<K>(e->stream, e->grid, e->d_ctrl, src, dst, m, w, b.cand[0], passes, b);
+  launch_pack<K>(e->stream, e->grid, src, dst, m, w, b.cand[0]);
   end(e, WG_STAGE_PREPARE);
   enqueue_sort<K>(e, b, &e->d_ctrl->m_in, passes);
   const int mode = query == WG_QUERY_TC ? (kModeEdges | kModeSeed) : kModeEdges;
@@ -417,7 +411,7 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
       launch_join_count<K>(e->stream, e->grid, kJoinSGBase, e->d_ctrl, b, w);
       end(e, WG_STAGE_JOIN_COUNT);
       begin(e, WG_STAGE_JOIN_EMIT);
-      launch_join_emit<K>(e->stream, e->grid, kJoinSGBase, e->d_ctrl, b, w, passes);
+      launch_join_emit<K>(e->stream, e->grid, kJoinSGBase, e->d_ctrl, b, w);
       end(e, WG_STAGE_JOIN_EMIT);
       enqueue_sort<K>(e, b, &e->d_ctrl->C, passes);
       begin(e, WG_STAGE_DEDUP_DIFF);
@@ -634,13 +628,14 @@ wg_status wg_engine_create(int device, wg_engine** out) {
     const int cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     e->grid.persistent = cu * 4;
     e->grid.stream = cu * 8;
+    e->grid.sort = std::min(cu * 4, kSortBlocksMax);
     hip_check(e, hipMalloc((void**)&e->d_ctrl, sizeof(Ctrl)), "hipMalloc");
     hip_check(e, hipHostMalloc((void**)&e->h_up, sizeof(Ctrl)), "hipHostMalloc");
     hip_check(e, hipHostMalloc((void**)&e->h_down, 2 * sizeof(Ctrl)), "hipHostMalloc");
     hip_check(e, hipMalloc((void**)&e->d_lb, sizeof(LbState) * kLbCount), "hipMalloc");
-    hip_check(e, hipMalloc((void**)&e->d_ghist, sizeof(uint32_t) * kHistWords), "hipMalloc");
+    hip_check(e, hipMalloc((void**)&e->d_rcnt, sizeof(uint32_t) * kRadix * kSortBlocksMax), "hipMalloc");
+    hip_check(e, hipMalloc((void**)&e->d_rtot, sizeof(uint32_t) * kRadix), "hipMalloc");
     hip_check(e, hipMemset(e->d_lb, 0, sizeof(LbState) * kLbCount), "hipMemset");
-    hip_check(e, hipMemset(e->d_ghist, 0, sizeof(uint32_t) * kHistWords), "hipMemset");
     hip_check(e, hipMemset(e->d_ctrl, 0, sizeof(Ctrl)), "hipMemset");
     for (int s = 0; s < 2; ++s)
       hip_check(e, hipEventCreateWithFlags(&e->ev_batch[s], hipEventDisableTiming), "hipEventCreate");
@@ -677,7 +672,8 @@ void wg_engine_destroy(wg_engine* e) {
   for (int s = 0; s < kLbCount; ++s) release(e->status[s]);
   if (e->d_ctrl) (void)hipFree(e->d_ctrl);
   if (e->d_lb) (void)hipFree(e->d_lb);
-  if (e->d_ghist) (void)hipFree(e->d_ghist);
+  if (e->d_rcnt) (void)hipFree(e->d_rcnt);
+  if (e->d_rtot) (void)hipFree(e->d_rtot);
   if (e->h_up) (void)hipHostFree(e->h_up);
   if (e->h_down) (void)hipHostFree(e->h_down);
   for (int s = 0; s < 2; ++s)

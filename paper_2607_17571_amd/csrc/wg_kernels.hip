@@ -19,45 +19,6 @@ namespace wg {
 
 constexpr uint32_t kNoRow = 0xFFFFFFFFu;
 
-__device__ __forceinline__ uint32_t hist_base(uint32_t slot, uint32_t copy, int pass) {
-  return ((slot * kHistCopies + copy) * kMaxPasses + (uint32_t)pass) * kRadix;
-}
-
-// ---------------------------------------------------------------------------
-// Digit histograms of every radix pass (Section V-C), accumulated by the kernel that
-// produces the keys so the sort needs no extra read of them.  Lanes of a wave holding the
-// same digit add once (ballot peers), which keeps skewed digits from serialising on one
-// LDS address.  Blocks flush into one of 8 global copies to spread the atomics; the pass
-// kernels add the copies up.  The slot is the parity of the sort sequence; a producer
-// clears the other slot, which the previous sort used and the next sort will use.
-// ---------------------------------------------------------------------------
-template <typename K>
-__device__ __forceinline__ void hist_add(uint32_t* s_h, K key, bool valid, int passes) {
-  const uint64_t active = __ballot(valid);
-  const uint64_t lt = lanemask_lt();
-  for (int p = 0; p < passes; ++p) {
-    const uint32_t d = (uint32_t)(key >> (p * kRadixBits)) & (kRadix - 1);
-    const uint64_t peers = digit_peers(d, active);
-    if (valid && (peers & lt) == 0) atomicAdd(&s_h[p * kRadix + d], (uint32_t)__popcll(peers));
-  }
-}
-
-__device__ __forceinline__ void hist_begin(uint32_t* s_h, int passes, uint32_t* ghist, uint32_t slot) {
-  for (int j = threadIdx.x; j < passes * kRadix; j += kBlock) s_h[j] = 0;
-  uint32_t* other = ghist + (slot ^ 1u) * kHistSlotWords;
-  for (uint32_t j = blockIdx.x * kBlock + threadIdx.x; j < (uint32_t)kHistSlotWords;
-       j += gridDim.x * kBlock)
-    other[j] = 0;
-}
-
-__device__ __forceinline__ void hist_flush(const uint32_t* s_h, int passes, uint32_t* ghist,
-                                           uint32_t slot) {
-  __syncthreads();
-  const uint32_t copy = blockIdx.x & (kHistCopies - 1);
-  for (int j = threadIdx.x; j < passes * kRadix; j += kBlock)
-    if (s_h[j]) atomicAdd(&ghist[hist_base(slot, copy, j / kRadix) + (j % kRadix)], s_h[j]);
-}
-
 // ---------------------------------------------------------------------------
 // Prepare: largest id, packing.
 // ---------------------------------------------------------------------------
@@ -74,27 +35,12 @@ __global__ __launch_bounds__(kBlock) void k_max_id(Ctrl* ctrl, const uint32_t* _
 }
 
 template <typename K>
-__global__ __launch_bounds__(kBlock) void k_pack(Ctrl* ctrl, const uint32_t* __restrict__ src,
+__global__ __launch_bounds__(kBlock) void k_pack(const uint32_t* __restrict__ src,
                                                  const uint32_t* __restrict__ dst, uint64_t m,
-                                                 int w, K* __restrict__ keys, int passes,
-                                                 Bufs<K> b) {
-  __shared__ uint32_t s_h[kMaxPasses * kRadix];
-  const uint32_t slot = ctrl->sort_seq & 1u;
-  hist_begin(s_h, passes, b.ghist, slot);
-  __syncthreads();
-  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-  const uint64_t rounds = (m + stride - 1) / stride;
-  for (uint64_t r = 0; r < rounds; ++r) {
-    const uint64_t i = r * stride + (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool valid = i < m;
-    K key = 0;
-    if (valid) {
-      key = ((K)src[i] << w) | (K)dst[i];
-      keys[i] = key;
-    }
-    hist_add<K>(s_h, key, valid, passes);
-  }
-  hist_flush(s_h, passes, b.ghist, slot);
+                                                 int w, K* __restrict__ keys) {
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < m;
+       i += (uint64_t)gridDim.x * kBlock)
+    keys[i] = ((K)src[i] << w) | (K)dst[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -209,19 +155,16 @@ __global__ __launch_bounds__(kBlock) void k_join_count(Ctrl* ctrl, Bufs<K> b, in
 // Join, emit phase.  Output positions are dealt out in tiles; each position finds the
 // delta tuple that owns it by binary search over the scanned offsets (a load-balanced
 // expansion, so a hub tuple with thousands of matches is spread over many threads
-// instead of serialising one).  Writes are coalesced.  The radix histograms of the
-// emitted keys are accumulated on the way.
+// instead of serialising one).  Writes are coalesced.
 // ---------------------------------------------------------------------------
 template <typename K, int Q, int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int w, int passes) {
+__global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int w) {
   constexpr uint32_t T = kBlock * ITEMS;
   __shared__ uint32_t s_off[T];
-  __shared__ uint32_t s_h[kMaxPasses * kRadix];
   __shared__ uint64_t s_i0, s_i1;
   if (halted(ctrl)) return;
   const uint64_t C = ctrl->C;
   const uint64_t n = (Q == kJoinSGBase) ? ctrl->nu : ctrl->D;
-  const uint32_t slot = ctrl->sort_seq & 1u;
   const K* __restrict__ delta = b.delta[ctrl->delta_side];
   const uint32_t* __restrict__ off = b.off;
   const uint32_t* __restrict__ R = b.R;
@@ -229,7 +172,6 @@ __global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int
   K* __restrict__ cand = b.cand[0];
   const uint64_t ntiles = (C + T - 1) / T;
   const int wid = threadIdx.x / kWave;
-  hist_begin(s_h, passes, b.ghist, slot);
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const uint64_t p0 = tile * T;
     const uint64_t p1 = min(p0 + T, C);
@@ -289,159 +231,169 @@ __global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int
         }
         cand[p] = key;
       }
-      hist_add<K>(s_h, key, valid, passes);
     }
     __syncthreads();
   }
-  hist_flush(s_h, passes, b.ghist, slot);
 }
 
 // ---------------------------------------------------------------------------
-// One stable LSD scatter pass (Section V-C).  A tile is loaded wave-striped (wave w owns
-// a contiguous run of ITEMS*64 keys), ranked within each wave with ballot-based peer
-// masks, ranked across waves and tiles by per-digit prefix sums with decoupled lookback,
-// sorted by digit in LDS and written out so consecutive lanes write consecutive addresses.
+// LSD radix sort (Section V-C): 8 bits per pass, dst field first, every pass stable.
+//
+// A pass is three launches with no waiting between blocks: count (block b counts the
+// digits of a static contiguous range of tiles), scan (one block per digit turns the
+// per-block counts into per-block offsets) and scatter (block b re-reads its range tile by
+// tile, ranks each tile stably in LDS and writes every key to its final position).
+// Chained single-pass scans (decoupled lookback) pay a cross-XCD round trip per
+// dependency on this chip; this form pays one extra read of the keys instead, and each
+// block writes long per-digit runs of consecutive positions.
 // ---------------------------------------------------------------------------
+
+// Static tile range of this block: tiles [b*tpb, (b+1)*tpb) of T keys.
+__device__ __forceinline__ void block_range(uint64_t n, uint32_t T, uint64_t& lo, uint64_t& hi) {
+  const uint64_t tiles = (n + T - 1) / T;
+  const uint64_t tpb = (tiles + gridDim.x - 1) / gridDim.x;
+  lo = min(n, (uint64_t)blockIdx.x * tpb * T);
+  hi = min(n, lo + tpb * T);
+}
+
 template <typename K, int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_radix_pass(Ctrl* ctrl, const uint64_t* n_ptr,
-                                                       const K* __restrict__ in,
-                                                       K* __restrict__ out, int pass, Bufs<K> b) {
+__global__ __launch_bounds__(kBlock) void k_radix_count(Ctrl* ctrl, const uint64_t* n_ptr,
+                                                        const K* __restrict__ in, int pass,
+                                                        uint32_t* __restrict__ cnt) {
+  constexpr uint32_t T = kBlock * ITEMS;
+  __shared__ uint32_t s_cnt[kRadix];
+  if (halted(ctrl)) return;
+  const uint64_t n = *n_ptr;
+  uint64_t lo, hi;
+  block_range(n, T, lo, hi);
+  s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int shift = pass * kRadixBits;
+  const uint64_t lt = lanemask_lt();
+  for (uint64_t base = lo; base < hi; base += T) {
+    K key[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint64_t i = base + (uint64_t)k * kBlock + threadIdx.x;
+      key[k] = i < hi ? in[i] : K(0);
+    }
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const bool valid = base + (uint64_t)k * kBlock + threadIdx.x < hi;
+      const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
+      const uint64_t peers = digit_peers(d, __ballot(valid));
+      if (valid && (peers & lt) == 0) atomicAdd(&s_cnt[d], (uint32_t)__popcll(peers));
+    }
+  }
+  __syncthreads();
+  cnt[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x] = s_cnt[threadIdx.x];
+}
+
+// One block per digit: per-block counts of the digit -> exclusive per-block offsets (in
+// place); tot[d] = the digit's total.
+__global__ __launch_bounds__(kBlock) void k_radix_scan(Ctrl* ctrl, uint32_t* __restrict__ cnt,
+                                                       uint32_t* __restrict__ tot, int G) {
+  __shared__ uint32_t s_wave[kWavesPerBlock];
+  if (halted(ctrl)) return;
+  uint32_t* row = cnt + (uint64_t)blockIdx.x * G;
+  uint32_t carry = 0;
+  for (int base = 0; base < G; base += kBlock) {
+    const int i = base + threadIdx.x;
+    const uint32_t v = i < G ? row[i] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_excl_scan<uint32_t>(v, s_wave, total);
+    if (i < G) row[i] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) tot[blockIdx.x] = carry;
+}
+
+template <typename K, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(Ctrl* ctrl, const uint64_t* n_ptr,
+                                                          const K* __restrict__ in,
+                                                          K* __restrict__ out, int pass,
+                                                          const uint32_t* __restrict__ off,
+                                                          const uint32_t* __restrict__ tot) {
   constexpr uint32_t T = kBlock * ITEMS;
   __shared__ K s_keys[T];
   __shared__ uint32_t s_cnt[kWavesPerBlock][kRadix];
   __shared__ uint32_t s_loc[kRadix];
-  __shared__ uint64_t s_glob[kRadix];
-  __shared__ uint32_t s_base[kRadix];
+  __shared__ uint64_t s_run[kRadix];
   __shared__ uint32_t s_wave[kWavesPerBlock];
-  __shared__ uint32_t s_claim[2];
   if (halted(ctrl)) return;
   const uint64_t n = *n_ptr;
-  const uint64_t ntiles = (n + T - 1) / T;
-  if (ntiles == 0) return;
+  uint64_t lo, hi;
+  block_range(n, T, lo, hi);
+  if (lo >= hi) return;
   const int shift = pass * kRadixBits;
-  uint64_t* status = b.status[kLbPass];
-  LbState* st = b.lb + kLbPass;
-  uint32_t* err = &ctrl->error;
-  const uint32_t epoch = launch_epoch(st);
   const int tid = threadIdx.x;
   const int wid = tid / kWave;
   const int lane = lane_id();
   const uint64_t lt = lanemask_lt();
   {
-    // global start of every digit bucket: exclusive scan of the summed histogram copies
-    const uint32_t slot = ctrl->sort_seq & 1u;
-    uint32_t tot = 0;
-#pragma unroll
-    for (int c = 0; c < kHistCopies; ++c) tot += b.ghist[hist_base(slot, c, pass) + tid];
+    // first position of each digit for this block: digit base + earlier blocks' keys
+    const uint32_t t = tot[tid];
     uint32_t all;
-    s_base[tid] = block_excl_scan<uint32_t>(tot, s_wave, all);
+    const uint32_t base = block_excl_scan<uint32_t>(t, s_wave, all);
+    s_run[tid] = (uint64_t)base + off[(uint64_t)tid * gridDim.x + blockIdx.x];
   }
-  for (;;) {
-    const TileClaim cl = claim_tile(st, ntiles, s_claim);
-    if (!cl.ok) {
-      if (cl.last && threadIdx.x == 0) release_launch(st, epoch);
-      break;
+  for (uint64_t tbase = lo; tbase < hi; tbase += T) {
+    for (int j = tid; j < kWavesPerBlock * kRadix; j += kBlock) (&s_cnt[0][0])[j] = 0;
+    __syncthreads();
+    // wave-striped: wave `wid` owns a contiguous run of 64*ITEMS keys
+    const uint64_t wbase = tbase + (uint64_t)wid * (ITEMS * kWave);
+    K key[ITEMS];
+    uint32_t rank[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint64_t idx = wbase + (uint64_t)k * kWave + lane;
+      key[k] = idx < hi ? in[idx] : K(0);
     }
-    {
-      const uint32_t tile = cl.tile;
-      for (int j = tid; j < kWavesPerBlock * kRadix; j += kBlock) (&s_cnt[0][0])[j] = 0;
-      __syncthreads();
-      const uint64_t tbase = (uint64_t)tile * T;
-      const uint64_t wbase = tbase + (uint64_t)wid * (ITEMS * kWave);
-      K key[ITEMS];
-      uint32_t rank[ITEMS];
 #pragma unroll
-      for (int k = 0; k < ITEMS; ++k) {
-        const uint64_t idx = wbase + (uint64_t)k * kWave + lane;
-        key[k] = idx < n ? in[idx] : K(0);
-      }
+    for (int k = 0; k < ITEMS; ++k) {
+      const bool valid = wbase + (uint64_t)k * kWave + lane < hi;
+      const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
+      const uint64_t peers = digit_peers(d, __ballot(valid));
+      const uint32_t below = __popcll(peers & lt);
+      uint32_t before = 0;
+      if (valid) before = s_cnt[wid][d];
+      if (valid && below == 0) s_cnt[wid][d] = before + __popcll(peers);
+      rank[k] = before + below;
+    }
+    __syncthreads();
+    // thread `tid` owns digit `tid`: per-wave exclusive offsets and the tile total
+    uint32_t tile_cnt = 0;
 #pragma unroll
-      for (int k = 0; k < ITEMS; ++k) {
-        const uint64_t idx = wbase + (uint64_t)k * kWave + lane;
-        const bool valid = idx < n;
+    for (int w2 = 0; w2 < kWavesPerBlock; ++w2) {
+      const uint32_t c = s_cnt[w2][tid];
+      s_cnt[w2][tid] = tile_cnt;
+      tile_cnt += c;
+    }
+    uint32_t total;
+    s_loc[tid] = block_excl_scan<uint32_t>(tile_cnt, s_wave, total);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      if (wbase + (uint64_t)k * kWave + lane < hi) {
         const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
-        const uint64_t peers = digit_peers(d, __ballot(valid));
-        const uint32_t below = __popcll(peers & lt);
-        uint32_t before = 0;
-        if (valid) before = s_cnt[wid][d];
-        if (valid && below == 0) s_cnt[wid][d] = before + __popcll(peers);
-        rank[k] = before + below;
+        const uint32_t pos = s_loc[d] + s_cnt[wid][d] + rank[k];
+        if (pos < T) s_keys[pos] = key[k];
       }
-      __syncthreads();
-      // Thread `tid` owns digit `tid`: per-wave exclusive offsets, tile total, lookback.
-      uint32_t tot = 0;
-#pragma unroll
-      for (int w2 = 0; w2 < kWavesPerBlock; ++w2) {
-        const uint32_t c = s_cnt[w2][tid];
-        s_cnt[w2][tid] = tot;
-        tot += c;
-      }
-      {
-        uint64_t* sw = status + (uint64_t)tile * kRadix + tid;
-        uint64_t ex = 0;
-        if (tile == 0) {
-          status_store(sw, status_word(kFlagIncl, epoch, tot));
-        } else {
-          status_store(sw, status_word(kFlagAgg, epoch, tot));
-          // look back over up to 8 predecessor tiles per round, their loads in flight together
-          constexpr int kAhead = 8;
-          int64_t t = (int64_t)tile - 1;
-          bool found = false;
-          while (!found && t >= 0) {
-            uint64_t sv[kAhead];
-#pragma unroll
-            for (int j = 0; j < kAhead; ++j)
-              sv[j] = (t - j >= 0) ? status_load(status + (uint64_t)(t - j) * kRadix + tid) : kFlagIncl;
-#pragma unroll
-            for (int j = 0; j < kAhead; ++j) {
-              if (found) break;
-              uint64_t s = sv[j];
-              uint32_t spins = 0;
-              while (t - j >= 0 && !((s >> 62) != 0 && ((uint32_t)(s >> 40) & kEpochMask) == epoch)) {
-                if (++spins > kSpinLimit) {
-                  atomicOr(err, 1u);
-                  s = kFlagIncl;
-                  break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-                s = status_load(status + (uint64_t)(t - j) * kRadix + tid);
-              }
-              ex += s & kValMask;
-              if ((s >> 62) == 2) found = true;
-            }
-            t -= kAhead;
-          }
-          status_store(sw, status_word(kFlagIncl, epoch, ex + tot));
-        }
-        s_glob[tid] = (uint64_t)s_base[tid] + ex;
-      }
-      uint32_t total;
-      const uint32_t loc = block_excl_scan<uint32_t>(tot, s_wave, total);
-      s_loc[tid] = loc;
-      __syncthreads();
-#pragma unroll
-      for (int k = 0; k < ITEMS; ++k) {
-        const uint64_t idx = wbase + (uint64_t)k * kWave + lane;
-        if (idx < n) {
-          const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
-          const uint32_t pos = s_loc[d] + s_cnt[wid][d] + rank[k];
-          if (pos < T) s_keys[pos] = key[k];
-        }
-      }
-      __syncthreads();
-      const uint32_t tile_n = (uint32_t)min<uint64_t>(T, n - tbase);
-#pragma unroll
-      for (int k = 0; k < ITEMS; ++k) {
-        const uint32_t j = (uint32_t)k * kBlock + tid;
-        if (j < tile_n) {
-          const K kk = s_keys[j];
-          const uint32_t d = (uint32_t)(kk >> shift) & (kRadix - 1);
-          const uint64_t pos = s_glob[d] + (j - s_loc[d]);
-          if (pos < n) out[pos] = kk;
-        }
-      }
-      __syncthreads();
     }
+    __syncthreads();
+    const uint32_t tile_n = (uint32_t)min<uint64_t>(T, hi - tbase);
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint32_t j = (uint32_t)k * kBlock + tid;
+      if (j < tile_n) {
+        const K kk = s_keys[j];
+        const uint32_t d = (uint32_t)(kk >> shift) & (kRadix - 1);
+        const uint64_t pos = s_run[d] + (j - s_loc[d]);
+        if (pos < n) out[pos] = kk;
+      }
+    }
+    __syncthreads();
+    s_run[tid] += tile_cnt;
   }
 }
 
@@ -457,7 +409,6 @@ __global__ __launch_bounds__(kBlock) void k_radix_pass(Ctrl* ctrl, const uint64_
 // the control block and the next iteration starts from the new delta.
 // ---------------------------------------------------------------------------
 __device__ void dedup_publish(Ctrl* c, int mode, uint64_t cnt, uint64_t* hist) {
-  c->sort_seq = c->sort_seq + 1;
   if (mode & kModeIter) {
     const uint64_t F = c->F;
     const uint32_t it = c->iter;
@@ -880,10 +831,9 @@ void launch_max_id(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint32_t* src
 }
 
 template <typename K>
-void launch_pack(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint32_t* src, const uint32_t* dst,
-                 uint64_t m, int w, K* keys, int passes, const Bufs<K>& b) {
-  hipLaunchKernelGGL(k_pack<K>, dim3(g.persistent), dim3(kBlock), 0, s, ctrl, src, dst, m, w, keys,
-                     passes, b);
+void launch_pack(hipStream_t s, const Grid& g, const uint32_t* src, const uint32_t* dst,
+                 uint64_t m, int w, K* keys) {
+  hipLaunchKernelGGL(k_pack<K>, dim3(stream_blocks(g, m)), dim3(kBlock), 0, s, src, dst, m, w, keys);
 }
 
 template <typename K>
@@ -897,21 +847,24 @@ void launch_join_count(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const
 }
 
 template <typename K>
-void launch_join_emit(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w,
-                      int passes) {
+void launch_join_emit(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w) {
   if (kind == kJoinTC)
-    hipLaunchKernelGGL((k_join_emit<K, kJoinTC, kEmitItems>), dim3(g.stream), dim3(kBlock), 0, s, ctrl, b, w, passes);
+    hipLaunchKernelGGL((k_join_emit<K, kJoinTC, kEmitItems>), dim3(g.stream), dim3(kBlock), 0, s, ctrl, b, w);
   else if (kind == kJoinSG)
-    hipLaunchKernelGGL((k_join_emit<K, kJoinSG, kEmitItems>), dim3(g.stream), dim3(kBlock), 0, s, ctrl, b, w, passes);
+    hipLaunchKernelGGL((k_join_emit<K, kJoinSG, kEmitItems>), dim3(g.stream), dim3(kBlock), 0, s, ctrl, b, w);
   else
-    hipLaunchKernelGGL((k_join_emit<K, kJoinSGBase, kEmitItems>), dim3(g.stream), dim3(kBlock), 0, s, ctrl, b, w, passes);
+    hipLaunchKernelGGL((k_join_emit<K, kJoinSGBase, kEmitItems>), dim3(g.stream), dim3(kBlock), 0, s, ctrl, b, w);
 }
 
 template <typename K>
 void launch_radix_pass(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint64_t* n_ptr,
                        const K* in, K* out, int pass, const Bufs<K>& b) {
-  hipLaunchKernelGGL((k_radix_pass<K, pass_items<K>()>), dim3(g.persistent), dim3(kBlock), 0, s,
-                     ctrl, n_ptr, in, out, pass, b);
+  constexpr int ITEMS = pass_items<K>();
+  hipLaunchKernelGGL((k_radix_count<K, ITEMS>), dim3(g.sort), dim3(kBlock), 0, s, ctrl, n_ptr, in,
+                     pass, b.rcnt);
+  hipLaunchKernelGGL(k_radix_scan, dim3(kRadix), dim3(kBlock), 0, s, ctrl, b.rcnt, b.rtot, g.sort);
+  hipLaunchKernelGGL((k_radix_scatter<K, ITEMS>), dim3(g.sort), dim3(kBlock), 0, s, ctrl, n_ptr, in,
+                     out, pass, b.rcnt, b.rtot);
 }
 
 template <typename K>
@@ -948,10 +901,10 @@ void launch_resume(hipStream_t s, Ctrl* ctrl, uint64_t cand_cap, uint64_t full_c
 }
 
 #define WG_INSTANTIATE(K)                                                                          \
-  template void launch_pack<K>(hipStream_t, const Grid&, Ctrl*, const uint32_t*, const uint32_t*, \
-                               uint64_t, int, K*, int, const Bufs<K>&);                            \
+  template void launch_pack<K>(hipStream_t, const Grid&, const uint32_t*, const uint32_t*,       \
+                               uint64_t, int, K*);                                                \
   template void launch_join_count<K>(hipStream_t, const Grid&, int, Ctrl*, const Bufs<K>&, int);   \
-  template void launch_join_emit<K>(hipStream_t, const Grid&, int, Ctrl*, const Bufs<K>&, int, int); \
+  template void launch_join_emit<K>(hipStream_t, const Grid&, int, Ctrl*, const Bufs<K>&, int);    \
   template void launch_radix_pass<K>(hipStream_t, const Grid&, Ctrl*, const uint64_t*, const K*,   \
                                      K*, int, const Bufs<K>&);                                     \
   template void launch_dedup_diff<K>(hipStream_t, const Grid&, int, Ctrl*, const uint64_t*,        \

@@ -44,15 +44,13 @@ constexpr uint32_t kIndexTile = kBlock * kIndexItems;
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kMaxPasses = 8;
-// Global digit histograms: 2 slots (parity of the sort sequence) x 8 copies (producer
-// blocks spread their atomics over them) x passes x digits.
-constexpr int kHistCopies = 8;
-constexpr int kHistSlotWords = kHistCopies * kMaxPasses * kRadix;
-constexpr int kHistWords = 2 * kHistSlotWords;
+// Blocks of the radix count / scatter kernels (one static key range each).
+constexpr int kSortBlocksMax = 4096;
 
 struct Grid {
   int persistent;  // blocks of the lookback kernels
   int stream;      // blocks of grid-stride kernels
+  int sort;        // blocks of the radix count / scatter kernels (<= kSortBlocksMax)
 };
 
 // Per-iteration device arrays of one solve.
@@ -71,25 +69,24 @@ struct Bufs {
   uint64_t* hist;  // per iteration: [2*i] = |Delta^i|, [2*i+1] = candidates of iteration i
   LbState* lb;     // kLbCount entries
   uint64_t* status[kLbCount];
-  uint32_t* ghist; // kHistWords
+  uint32_t* rcnt;  // radix per-block digit counts / offsets, kRadix x sort blocks
+  uint32_t* rtot;  // radix digit totals, kRadix
 };
 
 void launch_max_id(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint32_t* src,
                    const uint32_t* dst, uint64_t m);
 
-// Packs keys and accumulates the radix histograms of all `passes` (then digit offsets).
 template <typename K>
-void launch_pack(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint32_t* src, const uint32_t* dst,
-                 uint64_t m, int w, K* keys, int passes, const Bufs<K>& b);
+void launch_pack(hipStream_t s, const Grid& g, const uint32_t* src, const uint32_t* dst,
+                 uint64_t m, int w, K* keys);
 
 template <typename K>
 void launch_join_count(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w);
 
-// Emits candidates and accumulates the radix histograms of all `passes`.
 template <typename K>
-void launch_join_emit(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w,
-                      int passes);
+void launch_join_emit(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w);
 
+// One stable 8-bit LSD pass: count, scan and scatter launches.
 template <typename K>
 void launch_radix_pass(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint64_t* n_ptr,
                        const K* in, K* out, int pass, const Bufs<K>& b);
