@@ -18,147 +18,66 @@ constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 
 // ---------------------------------------------------------------------------
-// Control block: every size that decides a launch lives here, in device memory.
-// Kernels read it at entry; the host reads it only at batch boundaries.
+// Control block and per-iteration records.
+//
+// Every size that decides a launch lives in device memory.  The host passes each kernel
+// of iteration j the number j; the kernel reads what iteration j needs from record j-1
+// (written by an earlier launch) and the launch that finishes iteration j writes record
+// j.  No field is ever written while other blocks of the same launch may still read it,
+// so no launch needs a grid-wide barrier, a blocks-done counter or a lookback chain --
+// cross-block handshakes cost microsecond round trips across the XCDs of this chip.
 // ---------------------------------------------------------------------------
+struct IterRec {
+  uint64_t N;  // |Delta^j| (record 0: the seed)
+  uint64_t C;  // join candidates of iteration j (record 0: base-rule candidates for SG)
+  uint64_t F;  // |Full| after iteration j
+};
+
 struct Ctrl {
-  uint64_t D;            // |Delta^{i-1}|, input of the next join
-  uint64_t F;            // |Full|
-  uint64_t C;            // join candidates of the running iteration (saturating)
-  uint64_t N;            // |Delta^i| produced by the running iteration
-  uint64_t m_in;         // input edge count (prepare)
+  uint64_t m_in;         // input edge count
   uint64_t m_unique;     // |E| after sort + dedup
   uint64_t nu;           // distinct (inst, src) rows of the edge index
-  uint64_t total_cand;   // candidates summed over completed iterations
-  uint64_t cand_cap;     // capacity of each candidate buffer (keys)
+  uint64_t cand_cap;     // capacity of each candidate and delta buffer (keys)
   uint64_t full_cap;     // capacity of each Full buffer (keys)
-  uint64_t delta_cap;    // capacity of each delta buffer (keys)
-  uint64_t dsz_cap;      // capacity of the per-iteration delta-size array
-  uint32_t iter;         // completed iterations
+  uint64_t filtered;     // size after the SG diagonal filter
+  uint32_t iter;         // highest iteration whose record is complete
   uint32_t max_iter;     // 0: unlimited
   uint32_t done;         // the last delta was empty: fixpoint reached
-  uint32_t overflow;     // bit 0 candidates, bit 1 Full, bit 2 delta, bit 3 size array
-  uint32_t error;        // bit 0: a bounded device wait expired
+  uint32_t overflow;     // bit 0 candidates, bit 1 Full, bit 2 delta
   uint32_t limit_hit;    // max_iter reached with a non-empty delta
-  uint32_t full_side;    // which Full buffer holds the current relation
-  uint32_t delta_side;   // which delta buffer holds Delta^{i-1}
   uint32_t maxid;        // largest vertex id of the input
   uint32_t force_overflow_at;  // test hook: report a candidate overflow at this iteration
-  uint32_t pad0;
-  uint64_t D0;           // |Delta^0|, the seed size
-  uint64_t total;        // hand-over of a launch-wide total to the launch's last claimer
+  uint32_t pad;
 };
 
 // A halted loop turns every later kernel of the batch into a no-op.
 __device__ __forceinline__ bool halted(const Ctrl* c) {
-  return (c->done | c->overflow | c->error | c->limit_hit) != 0;
+  return (c->done | c->overflow | c->limit_hit) != 0;
 }
-
-// ---------------------------------------------------------------------------
-// Decoupled lookback state (single-pass scans, Section IV-B).
-//
-// A status word is  [63:62] flag | [61:40] epoch | [39:0] value.  flag 1 = tile
-// aggregate, 2 = inclusive prefix.  Words from earlier launches carry another epoch and
-// read as "not ready", so the status array never needs clearing between launches.  The
-// block that makes a launch's last tile claim resets the counter and advances the epoch.
-// ---------------------------------------------------------------------------
-constexpr int kClaimLanes = 8;
-struct LbState {
-  uint32_t lane_ctr[kClaimLanes][64];  // one claim counter per 256-byte line
-  uint32_t lanes_done;
-  uint32_t epoch;
-  uint32_t pad[62];
-};
 
 constexpr uint64_t kValMask = (1ull << 40) - 1;
-constexpr uint32_t kEpochMask = (1u << 22) - 1;
-constexpr uint64_t kFlagAgg = 1ull << 62;
-constexpr uint64_t kFlagIncl = 2ull << 62;
-constexpr uint32_t kSpinLimit = 1u << 24;
-
-__device__ __forceinline__ uint32_t launch_epoch(const LbState* st) {
-  const uint32_t cur = __hip_atomic_load(const_cast<uint32_t*>(&st->epoch), __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
-  const uint32_t e = (cur & kEpochMask) + 1;
-  return e > kEpochMask ? 1u : e;
-}
 
 __device__ __forceinline__ uint64_t sat_add(uint64_t a, uint64_t b) {
   uint64_t s = a + b;
   return s > kValMask ? kValMask : s;
 }
 
-__device__ __forceinline__ uint64_t status_word(uint64_t flag, uint32_t epoch, uint64_t v) {
-  return flag | ((uint64_t)epoch << 40) | (v > kValMask ? kValMask : v);
+// Static tile range of this block: tiles [b*tpb, (b+1)*tpb) of T items each.  Producer
+// and consumer launches of one scan use the same n, T and grid, hence the same ranges.
+__device__ __forceinline__ void block_range(uint64_t n, uint32_t T, uint64_t& lo, uint64_t& hi) {
+  const uint64_t tiles = (n + T - 1) / T;
+  const uint64_t tpb = (tiles + gridDim.x - 1) / gridDim.x;
+  lo = (uint64_t)blockIdx.x * tpb * T;
+  if (lo > n) lo = n;
+  hi = lo + tpb * T;
+  if (hi > n) hi = n;
 }
 
-__device__ __forceinline__ void status_store(uint64_t* p, uint64_t w) {
-  __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ uint64_t status_load(const uint64_t* p) {
-  return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Dynamic tile claims.  A tile only ever waits on tiles claimed before it in its own
-// claim order, by blocks that are already running, so lookback cannot deadlock.  Claims
-// go through 8 independent counters ("lanes", one per 256-byte line): block b draws from
-// lane b % 8, whose k-th claim is tile 8k + lane.  Same-address atomics serialise at a
-// few tens of ns each across the XCDs, so spreading them over 8 addresses keeps claims
-// off the critical path.  The smallest unfinished tile is always either held by a running
-// block or the next tile of its lane, which a block of that lane (all of whose earlier
-// tiles are finished) claims next: progress is guaranteed.
-//
-// Every block ends with exactly one failing claim.  The last failing claim on a lane
-// resets that lane; the last lane to finish (a second counter) marks the block that
-// knows every block of the launch is done: it advances the epoch and may publish
-// launch-wide results.
-struct TileClaim {
-  uint32_t tile;   // valid when `ok`
-  bool ok;         // a tile was claimed
-  bool last;       // this block closed the launch
-};
-
-__device__ __forceinline__ uint32_t lane_tiles(uint64_t ntiles, uint32_t lane) {
-  return ntiles > lane ? (uint32_t)((ntiles - lane + kClaimLanes - 1) / kClaimLanes) : 0u;
-}
-
-__device__ __forceinline__ uint32_t lane_blocks(uint32_t lane) {
-  return (gridDim.x - lane + kClaimLanes - 1) / kClaimLanes;
-}
-
-__device__ __forceinline__ TileClaim claim_tile(LbState* st, uint64_t ntiles, uint32_t* s_buf) {
-  const uint32_t lane = blockIdx.x & (kClaimLanes - 1);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const uint32_t k = atomicAdd(&st->lane_ctr[lane][0], 1u);
-    uint32_t last = 0;
-    const uint32_t tiles = lane_tiles(ntiles, lane);
-    if (k >= tiles && k == tiles + lane_blocks(lane) - 1) {
-      // final claim on this lane: reset it, then count finished lanes
-      __hip_atomic_store(&st->lane_ctr[lane][0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const uint32_t lanes = gridDim.x < (uint32_t)kClaimLanes ? gridDim.x : (uint32_t)kClaimLanes;
-      last = (atomicAdd(&st->lanes_done, 1u) == lanes - 1) ? 1u : 0u;
-    }
-    s_buf[0] = k;
-    s_buf[1] = last;
-  }
-  __syncthreads();
-  const uint32_t k = s_buf[0];
-  TileClaim r;
-  r.ok = (uint64_t)k * kClaimLanes + lane < ntiles;
-  r.tile = k * kClaimLanes + lane;
-  r.last = s_buf[1] != 0;
-  return r;
-}
-
-// Thread 0 of the closing block: reset the lane-done counter and publish the epoch.
-__device__ __forceinline__ void release_launch(LbState* st, uint32_t epoch) {
-  __threadfence();
-  __hip_atomic_store(&st->lanes_done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(&st->epoch, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __threadfence();
+// Items per block range for a grid of `G` blocks (what block_range gives every block but
+// possibly the last).
+__device__ __forceinline__ uint64_t range_len(uint64_t n, uint32_t T, uint32_t G) {
+  const uint64_t tiles = (n + T - 1) / T;
+  return ((tiles + G - 1) / G) * T;
 }
 
 // ---------------------------------------------------------------------------
@@ -208,83 +127,29 @@ __device__ __forceinline__ T block_excl_scan(T v, T* s_wave, T& total) {
   return before + incl - v;
 }
 
-// Wave-parallel lookback: the calling wave (all 64 lanes) sums the values of tiles
-// [0, tile) using the status words of up to 64 predecessors per step.  Stops at the
-// nearest inclusive prefix.  Sets *err on an expired wait.
-__device__ __forceinline__ uint64_t wave_lookback(const uint64_t* status, uint32_t tile,
-                                                  uint32_t epoch, uint32_t* err) {
-  const int lane = lane_id();
-  uint64_t excl = 0;
-  int64_t top = (int64_t)tile - 1;
-  while (top >= 0) {
-    const int64_t idx = top - lane;
-    uint64_t val = 0;
-    bool incl = true;
-    if (idx >= 0) {
-      uint32_t spins = 0;
-      for (;;) {
-        uint64_t s = status_load(status + idx);
-        uint64_t flag = s >> 62;
-        uint32_t ep = (uint32_t)(s >> 40) & kEpochMask;
-        if (flag != 0 && ep == epoch) {
-          incl = (flag == 2);
-          val = s & kValMask;
-          break;
-        }
-        if (++spins > kSpinLimit) {
-          atomicOr(err, 1u);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-    }
-    const uint64_t incl_mask = __ballot(incl);
-    if (incl_mask) {
-      const int first = __ffsll((unsigned long long)incl_mask) - 1;
-      excl = sat_add(excl, wave_sum(lane <= first ? val : 0ull));
-      break;
-    }
-    excl = sat_add(excl, wave_sum(val));
-    top -= kWave;
+// Exclusive prefix sums of the per-block totals vals[0..G) of a producer launch, into
+// LDS s_pre[0..G); returns the grand total in every thread.  G <= 4 * kBlock.
+__device__ __forceinline__ uint64_t block_prefix(const uint64_t* __restrict__ vals, int G,
+                                                 uint64_t* s_pre, uint64_t* s_wave) {
+  constexpr int PER = 4;
+  uint64_t v[PER];
+  uint64_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int i = (int)threadIdx.x * PER + k;
+    v[k] = i < G ? vals[i] : 0ull;
+    sum = sat_add(sum, v[k]);
   }
-  return excl;
-}
-
-// Tile-level exclusive offsets for a single-pass scan: every thread contributes `v`;
-// returns the global exclusive prefix of this thread, `grand` gets the inclusive total
-// through this tile and `tile_excl` the total of all earlier tiles.  Uses lookback.
-struct TileScanShared {
-  uint64_t wave[kWavesPerBlock];
-  uint64_t excl;
-};
-
-__device__ __forceinline__ uint64_t tile_scan(uint64_t v, uint32_t tile, uint32_t epoch,
-                                              uint64_t* status, uint32_t* err,
-                                              TileScanShared* sh, uint64_t& grand,
-                                              uint64_t& tile_excl) {
   uint64_t total;
-  uint64_t local = block_excl_scan<uint64_t>(v, sh->wave, total);
-  if (threadIdx.x < kWave) {
-    if (tile == 0) {
-      if (threadIdx.x == 0) {
-        status_store(status, status_word(kFlagIncl, epoch, total));
-        sh->excl = 0;
-      }
-    } else {
-      if (threadIdx.x == 0) status_store(status + tile, status_word(kFlagAgg, epoch, total));
-      uint64_t ex = wave_lookback(status, tile, epoch, err);
-      if (threadIdx.x == 0) {
-        status_store(status + tile, status_word(kFlagIncl, epoch, sat_add(ex, total)));
-        sh->excl = ex;
-      }
-    }
+  uint64_t ex = block_excl_scan<uint64_t>(sum, s_wave, total);
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int i = (int)threadIdx.x * PER + k;
+    if (i < G) s_pre[i] = ex;
+    ex = sat_add(ex, v[k]);
   }
   __syncthreads();
-  uint64_t ex = sh->excl;
-  __syncthreads();
-  grand = sat_add(ex, total);
-  tile_excl = ex;
-  return ex + local;
+  return total;
 }
 
 // ---------------------------------------------------------------------------
@@ -378,6 +243,24 @@ __device__ __forceinline__ void multi_upper_bound(const T* __restrict__ a, uint6
   }
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) out[k] += (a[out[k]] <= v[k]) ? 1 : 0;
+}
+
+// multi_upper_bound over a virtual sorted array given by an accessor at(i).
+template <int ITEMS, typename At, typename T>
+__device__ __forceinline__ void multi_upper_bound_at(At at, uint64_t n, const T (&v)[ITEMS],
+                                                     uint64_t (&out)[ITEMS]) {
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) out[k] = 0;
+  if (n == 0) return;
+  uint64_t len = n;
+  while (len > 1) {
+    const uint64_t half = len >> 1;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) out[k] = (at(out[k] + half - 1) <= v[k]) ? out[k] + half : out[k];
+    len -= half;
+  }
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) out[k] += (at(out[k]) <= v[k]) ? 1 : 0;
 }
 
 // Peers of this lane: lanes of the wave whose 8-bit digit equals this lane's (and that

@@ -2,10 +2,11 @@
 // device-resident loop and the C ABI declared in include/wg.h.
 //
 // Engine rule (Section V): the host decides when the fixpoint terminates, the device
-// decides every stage size.  The host enqueues K iterations at a time; each kernel
-// reads its sizes from the device control block.  The host reads the control block
-// back once per batch, after the next batch has already been enqueued (double-buffered
-// submission, Section V-B), and adapts K by the paper's halving rule.
+// decides every stage size.  The host enqueues K iterations at a time, passing each
+// kernel its iteration number j; every size comes from the device-side per-iteration
+// records.  The host reads the control block back once per batch while a short
+// speculative batch keeps the device busy (double-buffered submission, Section V-B), and
+// adapts K by the paper's halving rule.
 
 #include <algorithm>
 #include <chrono>
@@ -26,9 +27,16 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
-constexpr uint64_t kMaxKeys = 0xFFFFFFF0ull;        // offsets are 32-bit
-constexpr uint64_t kEpochRefresh = 3'500'000ull;    // well below the 22-bit epoch range
+// What the host reads back at a batch boundary.
+struct Readback {
+  Ctrl c;
+  IterRec first;  // record before the batch's first iteration
+  IterRec last;   // record of the batch's last iteration
+};
+
+constexpr uint64_t kMaxKeys = 0xFFFFFFF0ull;  // slab offsets are 32-bit
 constexpr uint32_t kMaxEvents = 1u << 16;
+constexpr uint32_t kSpec = 4;                 // speculative iterations behind each batch
 
 double now_ms() {
   return std::chrono::duration<double, std::milli>(
@@ -41,22 +49,21 @@ struct wg_engine {
   int device = 0;
   Grid grid{};
   Ctrl* d_ctrl = nullptr;
-  Ctrl* h_up = nullptr;    // pinned upload staging
-  Ctrl* h_down = nullptr;  // pinned readback, 2 slots
+  Ctrl* h_up = nullptr;        // pinned upload staging
+  Readback* h_rb = nullptr;    // pinned readback, 2 slots
   hipEvent_t ev_batch[2] = {nullptr, nullptr};
-  LbState* d_lb = nullptr;
+  uint64_t* d_jtot = nullptr;
+  uint64_t* d_bcnt = nullptr;
   uint32_t* d_rcnt = nullptr;
   uint32_t* d_rtot = nullptr;
-  DevBuf status[kLbCount];
-  DevBuf cand[2], full[2], delta[2], E, U, R, Edst, rowa, rowb, off, hist;
+  DevBuf cand[2], full[2], delta[2], E, U, R, Edst, rowa, rowb, off, rec;
   size_t allocated = 0;
   uint64_t budget = 0;
-  uint64_t lb_launches = 0;
   uint64_t generation = 0;
   std::string err;
   // per-solve
   uint32_t key_bytes = 4;
-  uint64_t cand_cap = 0, full_cap = 0, edge_cap = 0, row_cap = 0, dsz_cap = 0;
+  uint64_t cand_cap = 0, full_cap = 0, edge_cap = 0, row_cap = 0, rec_cap = 0;
   uint64_t syncs = 0;
   // stage timing
   bool timing = false;
@@ -131,48 +138,35 @@ void ensure(wg_engine* e, DevBuf& b, size_t bytes) {
   alloc_buf(e, b, bytes);
 }
 
-// Grow keeping the first `live` bytes (stream-ordered copy).
-void grow_keep(wg_engine* e, DevBuf& b, size_t bytes, size_t live) {
-  if (b.bytes >= bytes && b.p) return;
-  DevBuf nb;
-  alloc_buf(e, nb, bytes);
-  if (live && b.p) hip_check(e, hipMemcpyAsync(nb.p, b.p, live, hipMemcpyDeviceToDevice, e->stream), "copy");
-  hip_check(e, hipStreamSynchronize(e->stream), "sync");
-  ++e->syncs;
-  free_buf(e, b);
-  b = nb;
-}
-
 void sync_stream(wg_engine* e) {
   hip_check(e, hipStreamSynchronize(e->stream), "hipStreamSynchronize");
   ++e->syncs;
 }
 
-uint64_t status_entries(int slot, uint64_t cand_cap, uint64_t full_cap, uint64_t edge_cap,
-                        uint64_t row_cap, uint32_t key_bytes) {
-  const uint32_t ptile = key_bytes == 4 ? pass_tile<uint32_t>() : pass_tile<uint64_t>();
-  switch (slot) {
-    case kLbJoin: return row_cap / kJoinTile + 2;
-    case kLbPass: return (std::max(cand_cap, edge_cap) / ptile + 2) * kRadix;
-    case kLbDedup: return std::max(cand_cap, edge_cap) / kDedupTile + 2;
-    case kLbIndex: return edge_cap / kIndexTile + 2;
-    case kLbFilter: return full_cap / kIndexTile + 2;
-    default: return 0;
-  }
+// Grow keeping the first `live` bytes (waits for the stream before freeing the old one).
+void grow_keep(wg_engine* e, DevBuf& b, size_t bytes, size_t live) {
+  if (b.bytes >= bytes && b.p) return;
+  DevBuf nb;
+  alloc_buf(e, nb, bytes);
+  if (live && b.p) hip_check(e, hipMemcpyAsync(nb.p, b.p, live, hipMemcpyDeviceToDevice, e->stream), "copy");
+  sync_stream(e);
+  free_buf(e, b);
+  b = nb;
 }
 
-// (Re)size every buffer for the current capacities.  `keep` preserves the live Full and
-// delta contents described by the control block (grow-and-resume).
-void size_buffers(wg_engine* e, bool keep, const Ctrl* c) {
+// (Re)size every buffer for the current capacities.  With `iter`/`last`, the Full and
+// delta contents that iteration iter + 1 reads (side iter & 1) are kept (grow-and-resume).
+void size_buffers(wg_engine* e, bool keep, uint32_t iter, const IterRec* last) {
   const uint64_t kb = e->key_bytes;
   for (int s = 0; s < 2; ++s) ensure(e, e->cand[s], e->cand_cap * kb);
   for (int s = 0; s < 2; ++s) {
-    const bool live_f = keep && c && (uint32_t)s == c->full_side;
-    const bool live_d = keep && c && (uint32_t)s == c->delta_side;
-    if (live_f) grow_keep(e, e->full[s], e->full_cap * kb, c->F * kb);
-    else ensure(e, e->full[s], e->full_cap * kb);
-    if (live_d) grow_keep(e, e->delta[s], e->cand_cap * kb, c->D * kb);
-    else ensure(e, e->delta[s], e->cand_cap * kb);
+    if (keep && (uint32_t)s == (iter & 1u)) {
+      grow_keep(e, e->full[s], e->full_cap * kb, last->F * kb);
+      grow_keep(e, e->delta[s], e->cand_cap * kb, last->N * kb);
+    } else {
+      ensure(e, e->full[s], e->full_cap * kb);
+      ensure(e, e->delta[s], e->cand_cap * kb);
+    }
   }
   ensure(e, e->E, e->edge_cap * kb);
   ensure(e, e->U, (e->edge_cap + 1) * 4);
@@ -182,24 +176,21 @@ void size_buffers(wg_engine* e, bool keep, const Ctrl* c) {
   ensure(e, e->rowa, e->row_cap * 4);
   ensure(e, e->rowb, e->row_cap * 4);
   ensure(e, e->off, e->row_cap * 4);
-  if (keep) grow_keep(e, e->hist, e->dsz_cap * 16, e->hist.bytes);
-  else ensure(e, e->hist, e->dsz_cap * 16);
-  for (int s = 0; s < kLbCount; ++s) {
-    const uint64_t need = status_entries(s, e->cand_cap, e->full_cap, e->edge_cap, e->row_cap, e->key_bytes) * 8;
-    if (need && (e->status[s].bytes < need || !e->status[s].p)) {
-      ensure(e, e->status[s], need);
-      // fresh memory must read as "not ready" for every epoch
-      hip_check(e, hipMemsetAsync(e->status[s].p, 0, e->status[s].bytes, e->stream), "memset");
-    }
-  }
 }
 
-void refresh_epochs(wg_engine* e) {
+void ensure_records(wg_engine* e, uint64_t need) {
+  if (e->rec_cap >= need) return;
+  const uint64_t cap = std::max<uint64_t>(e->rec_cap * 2, need + 1024);
+  DevBuf nb;
+  alloc_buf(e, nb, cap * sizeof(IterRec));
+  hip_check(e, hipMemsetAsync(nb.p, 0, cap * sizeof(IterRec), e->stream), "memset");
+  if (e->rec.p)
+    hip_check(e, hipMemcpyAsync(nb.p, e->rec.p, e->rec_cap * sizeof(IterRec), hipMemcpyDeviceToDevice,
+                                e->stream), "copy");
   sync_stream(e);
-  for (int s = 0; s < kLbCount; ++s)
-    if (e->status[s].p) hip_check(e, hipMemsetAsync(e->status[s].p, 0, e->status[s].bytes, e->stream), "memset");
-  hip_check(e, hipMemsetAsync(e->d_lb, 0, sizeof(LbState) * kLbCount, e->stream), "memset");
-  e->lb_launches = 0;
+  free_buf(e, e->rec);
+  e->rec = nb;
+  e->rec_cap = cap;
 }
 
 template <typename K>
@@ -217,15 +208,15 @@ Bufs<K> make_bufs(wg_engine* e) {
   b.rowa = (uint32_t*)e->rowa.p;
   b.rowb = (uint32_t*)e->rowb.p;
   b.off = (uint32_t*)e->off.p;
-  b.hist = (uint64_t*)e->hist.p;
-  b.lb = e->d_lb;
-  for (int s = 0; s < kLbCount; ++s) b.status[s] = (uint64_t*)e->status[s].p;
+  b.jtot = e->d_jtot;
+  b.bcnt = e->d_bcnt;
   b.rcnt = e->d_rcnt;
   b.rtot = e->d_rtot;
+  b.rec = (IterRec*)e->rec.p;
   return b;
 }
 
-// ----- stage timing: events bracket every launch (begin, end) when WG_STAGE_TIMING is set.
+// ----- stage timing: events bracket launches (begin, end) when WG_STAGE_TIMING is set.
 hipEvent_t next_event(wg_engine* e) {
   if (e->n_events >= e->events.size()) {
     hipEvent_t ev;
@@ -268,63 +259,77 @@ void collect_timing(wg_engine* e, wg_stats* st) {
 // ----- pipeline pieces
 template <typename K>
 void enqueue_sort(wg_engine* e, const Bufs<K>& b, const uint64_t* n_ptr, int passes) {
-  // one event pair brackets all passes, so stage_ms / launches is the mean pass time
+  // one event pair brackets all passes (each pass is a count, a scan and a scatter launch)
   begin(e, WG_STAGE_RADIX_PASS);
-  for (int p = 0; p < passes; ++p)
-    launch_radix_pass<K>(e->stream, e->grid, e->d_ctrl, n_ptr, b.cand[p & 1], b.cand[(p + 1) & 1], p, b);
+  launch_sort<K>(e->stream, e->grid, e->d_ctrl, n_ptr, passes, b);
   end(e, WG_STAGE_RADIX_PASS, passes);
-  e->lb_launches += passes;
 }
 
 template <typename K>
-void enqueue_iteration(wg_engine* e, const Bufs<K>& b, int kind, int w, int passes) {
+void enqueue_iteration(wg_engine* e, const Bufs<K>& b, int kind, int w, int passes, uint32_t j) {
   begin(e, WG_STAGE_JOIN_COUNT);
-  launch_join_count<K>(e->stream, e->grid, kind, e->d_ctrl, b, w);
+  launch_join_count<K>(e->stream, e->grid, kind, e->d_ctrl, b, w, j);
   end(e, WG_STAGE_JOIN_COUNT);
   begin(e, WG_STAGE_JOIN_EMIT);
-  launch_join_emit<K>(e->stream, e->grid, kind, e->d_ctrl, b, w);
+  launch_join_emit<K>(e->stream, e->grid, kind, e->d_ctrl, b, w, j);
   end(e, WG_STAGE_JOIN_EMIT);
-  enqueue_sort<K>(e, b, &e->d_ctrl->C, passes);
+  enqueue_sort<K>(e, b, &b.rec[j].C, passes);
   begin(e, WG_STAGE_DEDUP_DIFF);
-  launch_dedup_diff<K>(e->stream, e->grid, kModeIter, e->d_ctrl, &e->d_ctrl->C, b.cand[passes & 1], b);
+  launch_compact<K>(e->stream, e->grid, kModeIter, e->d_ctrl, &b.rec[j].C, b.cand[passes & 1],
+                    b.cand[(passes & 1) ^ 1], b, w, j, 0);
   end(e, WG_STAGE_DEDUP_DIFF);
   begin(e, WG_STAGE_MERGE);
-  launch_merge<K>(e->stream, e->grid, e->d_ctrl, b);
+  launch_merge<K>(e->stream, e->grid, e->d_ctrl, b, j);
   end(e, WG_STAGE_MERGE);
-  e->lb_launches += 3;
 }
 
-void read_ctrl(wg_engine* e, int slot) {
-  hip_check(e, hipMemcpyAsync(&e->h_down[slot], e->d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, e->stream),
+// Enqueue the readback of the control block and of records `first` and `last`.
+void read_back(wg_engine* e, int slot, uint32_t first, uint32_t last) {
+  Readback* rb = &e->h_rb[slot];
+  hip_check(e, hipMemcpyAsync(&rb->c, e->d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, e->stream), "readback");
+  const IterRec* rec = (const IterRec*)e->rec.p;
+  hip_check(e, hipMemcpyAsync(&rb->first, rec + first, sizeof(IterRec), hipMemcpyDeviceToHost, e->stream),
+            "readback");
+  hip_check(e, hipMemcpyAsync(&rb->last, rec + last, sizeof(IterRec), hipMemcpyDeviceToHost, e->stream),
             "readback");
   hip_check(e, hipEventRecord(e->ev_batch[slot], e->stream), "hipEventRecord");
 }
 
-Ctrl wait_ctrl(wg_engine* e, int slot) {
+Readback wait_back(wg_engine* e, int slot) {
   hip_check(e, hipEventSynchronize(e->ev_batch[slot]), "hipEventSynchronize");
   ++e->syncs;
-  return e->h_down[slot];
+  return e->h_rb[slot];
 }
 
-// Grow the buffers after an overflow and clear the flag; the loop then resumes from the
-// last completed iteration, whose Full and delta are intact.
+// Synchronous read of one record (used only with the stream drained).
+IterRec read_record(wg_engine* e, uint32_t j) {
+  IterRec r{};
+  hip_check(e, hipMemcpyAsync(&e->h_rb[0].last, (const IterRec*)e->rec.p + j, sizeof(IterRec),
+                              hipMemcpyDeviceToHost, e->stream), "record");
+  sync_stream(e);
+  r = e->h_rb[0].last;
+  return r;
+}
+
+// Grow the buffers after an overflow and clear the flag; the loop then resumes at
+// iteration c.iter + 1, whose inputs (record c.iter, its Full and delta) are intact.
 void grow_and_resume(wg_engine* e, const Ctrl& c, bool hooked) {
-  uint64_t cand = e->cand_cap, full = e->full_cap, dsz = e->dsz_cap;
+  const IterRec last = read_record(e, c.iter);
+  const IterRec next = read_record(e, c.iter + 1);
+  uint64_t cand = e->cand_cap, full = e->full_cap;
   bool clear_hook = false;
   if (c.overflow & 1u) {
-    if (hooked && c.C <= e->cand_cap) clear_hook = true;  // forced by the test hook
-    else cand = std::max(cand * 2, c.C + c.C / 4);
+    if (hooked && next.C <= e->cand_cap) clear_hook = true;  // forced by the test hook
+    else cand = std::max(cand * 2, next.C + next.C / 4);
   }
-  if (c.overflow & 4u) cand = std::max(cand * 2, c.N + c.N / 4);
-  if (c.overflow & 2u) full = std::max(full * 2, (c.F + c.N) + (c.F + c.N) / 4);
-  if (c.overflow & 8u) dsz = dsz * 2;
+  if (c.overflow & 4u) cand = std::max(cand * 2, next.N + next.N / 4);
+  if (c.overflow & 2u) full = std::max(full * 2, (last.F + next.N) + (last.F + next.N) / 4);
   if (cand > kMaxKeys || full > kMaxKeys)
     fail(e, WG_ERR_CAPACITY, "relation exceeds 2^32 keys per buffer");
   e->cand_cap = cand;
   e->full_cap = full;
-  e->dsz_cap = dsz;
-  size_buffers(e, true, &c);
-  launch_resume(e->stream, e->d_ctrl, e->cand_cap, e->full_cap, e->dsz_cap, clear_hook ? 1u : 0u);
+  size_buffers(e, true, c.iter, &last);
+  launch_resume(e->stream, e->d_ctrl, e->cand_cap, e->full_cap, clear_hook ? 1u : 0u);
 }
 
 int field_bits(uint32_t maxid) {
@@ -337,27 +342,27 @@ void add_bytes(wg_stats* st, int k, double b) { st->stage_bytes[k] += (uint64_t)
 
 // Algorithmic HBM bytes per kernel kind (what each stage must stream at minimum).
 void bytes_model(wg_stats* st, int query, uint32_t kb, int passes, uint64_t m,
-                 const std::vector<uint64_t>& N, const std::vector<uint64_t>& C, uint64_t base_cand) {
-  // prepare: max scan + pack + sort + dedup of m edges + index
-  add_bytes(st, WG_STAGE_PREPARE, 8.0 * m + (8.0 + kb) * m + (kb + 12.0) * m);
+                 const std::vector<IterRec>& rec, uint64_t mu) {
+  // prepare: max scan (8m), pack (8m read + kb*m), sort + dedup of m keys, index
+  add_bytes(st, WG_STAGE_PREPARE, 8.0 * m + (8.0 + kb) * m + (kb + 12.0) * mu);
   add_bytes(st, WG_STAGE_RADIX_PASS, 3.0 * kb * m * passes);
-  add_bytes(st, WG_STAGE_DEDUP_DIFF, (double)kb * m + (double)kb * N[0] * (query == WG_QUERY_TC ? 3 : 0));
+  add_bytes(st, WG_STAGE_DEDUP_DIFF, (double)kb * m + 3.0 * kb * mu);
   if (query == WG_QUERY_SG) {
-    add_bytes(st, WG_STAGE_JOIN_EMIT, (double)(kb + 8) * base_cand);
-    add_bytes(st, WG_STAGE_RADIX_PASS, 3.0 * kb * base_cand * passes);
-    add_bytes(st, WG_STAGE_DEDUP_DIFF, (double)kb * base_cand + 2.0 * kb * N[0]);
+    const double c = (double)rec[0].C, n = (double)rec[0].N;
+    add_bytes(st, WG_STAGE_JOIN_EMIT, (kb + 8.0) * c);
+    add_bytes(st, WG_STAGE_RADIX_PASS, 3.0 * kb * c * passes);
+    add_bytes(st, WG_STAGE_DEDUP_DIFF, (c + 4.0 * n) * kb);
   }
-  uint64_t F = N[0];
   const double row_bytes = query == WG_QUERY_TC ? 8.0 : 12.0;
   const double edst = query == WG_QUERY_TC ? 4.0 : 8.0;
-  for (size_t i = 1; i < N.size(); ++i) {
-    const double D = (double)N[i - 1], c = (double)C[i], n = (double)N[i];
+  for (size_t i = 1; i < rec.size(); ++i) {
+    const double D = (double)rec[i - 1].N, c = (double)rec[i].C, n = (double)rec[i].N;
+    const double F = (double)rec[i - 1].F;
     add_bytes(st, WG_STAGE_JOIN_COUNT, D * (kb + row_bytes));
     add_bytes(st, WG_STAGE_JOIN_EMIT, D * (kb + row_bytes) + c * (edst + kb));
     add_bytes(st, WG_STAGE_RADIX_PASS, 3.0 * c * kb * passes);
-    add_bytes(st, WG_STAGE_DEDUP_DIFF, (c + n) * kb);
-    if (N[i] > 0) add_bytes(st, WG_STAGE_MERGE, 2.0 * ((double)F + n) * kb);
-    F += N[i];
+    add_bytes(st, WG_STAGE_DEDUP_DIFF, (c + 3.0 * n) * kb);
+    if (rec[i].N > 0) add_bytes(st, WG_STAGE_MERGE, 2.0 * (F + n) * kb);
   }
 }
 
@@ -368,21 +373,17 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   const int passes = (key_bits + kRadixBits - 1) / kRadixBits;
   e->key_bytes = sizeof(K);
   e->edge_cap = std::max<uint64_t>(e->edge_cap, m);
-  e->cand_cap = std::max<uint64_t>({e->cand_cap, 2 * m, 1u << 20});
-  e->full_cap = std::max<uint64_t>({e->full_cap, 2 * m, 1u << 20});
-  e->cand_cap = std::min(e->cand_cap, kMaxKeys);
-  e->full_cap = std::min(e->full_cap, kMaxKeys);
-  e->dsz_cap = std::max<uint64_t>(e->dsz_cap, 4096);
-  size_buffers(e, false, nullptr);
-  if (e->lb_launches > kEpochRefresh) refresh_epochs(e);
+  e->cand_cap = std::min(std::max<uint64_t>({e->cand_cap, 2 * m, 1u << 20}), kMaxKeys);
+  e->full_cap = std::min(std::max<uint64_t>({e->full_cap, 2 * m, 1u << 20}), kMaxKeys);
+  size_buffers(e, false, 0, nullptr);
+  ensure_records(e, 1024);
+  hip_check(e, hipMemsetAsync(e->rec.p, 0, e->rec_cap * sizeof(IterRec), e->stream), "memset");
 
   Ctrl& c0 = *e->h_up;
   std::memset(&c0, 0, sizeof(Ctrl));
   c0.m_in = m;
   c0.cand_cap = e->cand_cap;
-  c0.delta_cap = e->cand_cap;
   c0.full_cap = e->full_cap;
-  c0.dsz_cap = e->dsz_cap;
   c0.max_iter = (uint32_t)std::min<uint64_t>(o.max_iterations, 0xFFFFFFFFu);
   c0.force_overflow_at = (uint32_t)std::min<uint64_t>(o.force_overflow_at_iter, 0xFFFFFFFFu);
   hip_check(e, hipMemcpyAsync(e->d_ctrl, e->h_up, sizeof(Ctrl), hipMemcpyHostToDevice, e->stream), "upload");
@@ -395,37 +396,42 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   enqueue_sort<K>(e, b, &e->d_ctrl->m_in, passes);
   const int mode = query == WG_QUERY_TC ? (kModeEdges | kModeSeed) : kModeEdges;
   begin(e, WG_STAGE_DEDUP_DIFF);
-  launch_dedup_diff<K>(e->stream, e->grid, mode, e->d_ctrl, &e->d_ctrl->m_in, b.cand[passes & 1], b);
+  launch_compact<K>(e->stream, e->grid, mode, e->d_ctrl, &e->d_ctrl->m_in, b.cand[passes & 1],
+                    b.cand[(passes & 1) ^ 1], b, w, 0, 0);
   end(e, WG_STAGE_DEDUP_DIFF);
   begin(e, WG_STAGE_PREPARE);
   launch_edge_index<K>(e->stream, e->grid, e->d_ctrl, b, w);
   end(e, WG_STAGE_PREPARE);
-  e->lb_launches += 2;
 
-  uint64_t base_cand = 0;
   if (query == WG_QUERY_SG) {
     // base rule: Delta^0 = Full = {(x, y) : E(p, x), E(p, y), x != y}, sorted + deduplicated
     for (;;) {
       b = make_bufs<K>(e);
       begin(e, WG_STAGE_JOIN_COUNT);
-      launch_join_count<K>(e->stream, e->grid, kJoinSGBase, e->d_ctrl, b, w);
+      launch_join_count<K>(e->stream, e->grid, kJoinSGBase, e->d_ctrl, b, w, 0);
       end(e, WG_STAGE_JOIN_COUNT);
       begin(e, WG_STAGE_JOIN_EMIT);
-      launch_join_emit<K>(e->stream, e->grid, kJoinSGBase, e->d_ctrl, b, w);
+      launch_join_emit<K>(e->stream, e->grid, kJoinSGBase, e->d_ctrl, b, w, 0);
       end(e, WG_STAGE_JOIN_EMIT);
-      enqueue_sort<K>(e, b, &e->d_ctrl->C, passes);
+      enqueue_sort<K>(e, b, &b.rec[0].C, passes);
       begin(e, WG_STAGE_DEDUP_DIFF);
-      launch_dedup_diff<K>(e->stream, e->grid, kModeSeed, e->d_ctrl, &e->d_ctrl->C, b.cand[passes & 1], b);
+      launch_compact<K>(e->stream, e->grid, kModeSeed, e->d_ctrl, &b.rec[0].C, b.cand[passes & 1],
+                        b.cand[(passes & 1) ^ 1], b, w, 0, 0);
       end(e, WG_STAGE_DEDUP_DIFF);
-      e->lb_launches += 2;
-      read_ctrl(e, 0);
-      const Ctrl c = wait_ctrl(e, 0);
-      if (c.error) fail(e, WG_ERR_DEVICE, "device wait expired in the base stage");
-      if (!c.overflow) {
-        base_cand = c.C;
-        break;
+      read_back(e, 0, 0, 0);
+      const Readback r = wait_back(e, 0);
+      if (!r.c.overflow) break;
+      if (r.c.overflow & 1u) e->cand_cap = std::max(e->cand_cap * 2, r.last.C + r.last.C / 4);
+      if (r.c.overflow & 2u) {
+        const uint64_t need = r.last.N > 0 ? r.last.N : r.last.C;
+        e->full_cap = std::max(e->full_cap * 2, need + need / 4);
+        e->cand_cap = std::max(e->cand_cap, need + need / 4);
       }
-      grow_and_resume(e, c, false);
+      if (e->cand_cap > kMaxKeys || e->full_cap > kMaxKeys)
+        fail(e, WG_ERR_CAPACITY, "relation exceeds 2^32 keys per buffer");
+      sync_stream(e);
+      size_buffers(e, false, 0, nullptr);
+      launch_resume(e->stream, e->d_ctrl, e->cand_cap, e->full_cap, 0);
       if (st) st->resumes++;
     }
   }
@@ -436,84 +442,87 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   const bool adaptive = (o.batch_k == 0 && query == WG_QUERY_TC);
   if (o.loop_mode == WG_LOOP_HOST) K_batch = 1;
   const bool hooked = o.force_overflow_at_iter != 0;
-  Ctrl c{};
+  uint32_t next_j = 1;
+  uint32_t batch_first = 1;
+  Readback r{};
   int slot = 0;
-  uint64_t prev_D = 0;
-  bool have_prev = false;
   auto enqueue_iters = [&](uint32_t k) {
+    ensure_records(e, (uint64_t)next_j + k + 2);
     b = make_bufs<K>(e);
-    for (uint32_t i = 0; i < k; ++i) enqueue_iteration<K>(e, b, kind, w, passes);
+    for (uint32_t i = 0; i < k; ++i) enqueue_iteration<K>(e, b, kind, w, passes, next_j++);
   };
   auto enqueue_batch = [&](uint32_t k, int sl) {
     enqueue_iters(k);
-    read_ctrl(e, sl);
+    read_back(e, sl, batch_first - 1, next_j - 1);
+    batch_first = next_j;
   };
-  const uint64_t per_iter_launches = 3 + (uint64_t)passes;
-  constexpr uint32_t kSpec = 4;
   enqueue_batch(K_batch, slot);
   for (;;) {
     // While the host waits on this batch, the device runs a short speculative batch
     // behind it (Section V-B overlaps the next batch with the host check); after the
     // fixpoint its launches are no-ops, so it is kept short.
-    const uint32_t spec = std::min(K_batch, kSpec);
-    const bool speculate = e->lb_launches + per_iter_launches * (K_batch + spec) < kEpochRefresh;
-    if (speculate) enqueue_iters(spec);
-    c = wait_ctrl(e, slot);
-    if (c.error | c.overflow | c.done | c.limit_hit) sync_stream(e);
-    if (c.error) fail(e, WG_ERR_DEVICE, "device wait expired (lookback spin limit)");
-    if (c.overflow) {
-      grow_and_resume(e, c, hooked);
+    enqueue_iters(std::min(K_batch, kSpec));
+    r = wait_back(e, slot);
+    if (r.c.overflow | r.c.done | r.c.limit_hit) sync_stream(e);
+    if (r.c.overflow) {
+      grow_and_resume(e, r.c, hooked);
       if (st) st->resumes++;
-      if (e->lb_launches > kEpochRefresh) refresh_epochs(e);
+      next_j = r.c.iter + 1;
+      batch_first = next_j;
       enqueue_batch(K_batch, slot);
       continue;
     }
-    if (c.done || c.limit_hit) break;
-    if (adaptive) {
-      // Section V-B: halve K when the batch's last/first delta-size ratio is below 0.1
-      const uint64_t first = have_prev ? prev_D : c.D0;
-      if (first > 0 && (double)c.D / (double)first < 0.1) K_batch = std::max(1u, K_batch / 2);
-    }
-    prev_D = c.D;
-    have_prev = true;
-    if (!speculate) refresh_epochs(e);
+    if (r.c.done || r.c.limit_hit) break;
+    // Section V-B: halve K when the batch's last/first delta-size ratio is below 0.1
+    if (adaptive && r.first.N > 0 && (double)r.last.N / (double)r.first.N < 0.1)
+      K_batch = std::max(1u, K_batch / 2);
     slot ^= 1;
     enqueue_batch(K_batch, slot);
   }
-  if (c.limit_hit && !c.done) fail(e, WG_ERR_ITER_LIMIT, "max_iterations reached before the fixpoint");
+  if (r.c.limit_hit && !r.c.done) fail(e, WG_ERR_ITER_LIMIT, "max_iterations reached before the fixpoint");
 
+  // result: Full after the last iteration.  The last merge (iteration iter - 1) wrote side
+  // (iter - 1) & 1; with no merge at all the seed is on side 0.
+  const uint32_t iters = r.c.iter;
+  const IterRec fin = read_record(e, iters);
+  uint32_t side = iters >= 1 ? ((iters - 1) & 1u) : 0u;
+  uint64_t F = fin.F;
   b = make_bufs<K>(e);
-  if (query == WG_QUERY_SG && (o.flags & WG_SG_IRREFLEXIVE)) {
+  if (query == WG_QUERY_SG && (o.flags & WG_SG_IRREFLEXIVE) && F > 0) {
+    if (e->cand_cap < F) {
+      e->cand_cap = F;
+      for (int s = 0; s < 2; ++s) ensure(e, e->cand[s], e->cand_cap * e->key_bytes);
+      b = make_bufs<K>(e);
+    }
     begin(e, WG_STAGE_PREPARE);
-    launch_filter_offdiag<K>(e->stream, e->grid, e->d_ctrl, b, w);
+    launch_compact<K>(e->stream, e->grid, kModeFilter, e->d_ctrl, &b.rec[iters].F, b.full[side],
+                      b.cand[0], b, w, 0, side);
     end(e, WG_STAGE_PREPARE);
-    e->lb_launches += 1;
-    read_ctrl(e, 0);
-    c = wait_ctrl(e, 0);
-    if (c.error) fail(e, WG_ERR_DEVICE, "device wait expired in the diagonal filter");
+    read_back(e, 0, 0, 0);
+    F = wait_back(e, 0).c.filtered;
+    side ^= 1u;
   }
-  e->res_keys = b.full[c.full_side];
-  e->res_n = c.F;
+  e->res_keys = b.full[side];
+  e->res_n = F;
   e->res_w = w;
 
   if (st) {
-    st->iterations = c.iter;
-    st->result_tuples = c.F;
-    st->base_tuples = c.D0;
-    st->join_candidates = c.total_cand;
+    st->iterations = iters;
+    st->result_tuples = F;
     st->field_bits = (uint32_t)w;
     st->key_bytes = (uint32_t)sizeof(K);
-    std::vector<uint64_t> h(2 * ((size_t)c.iter + 1));
-    hip_check(e, hipMemcpy(h.data(), e->hist.p, h.size() * 8, hipMemcpyDeviceToHost), "hist readback");
-    ++e->syncs;
-    std::vector<uint64_t> N(c.iter + 1), C(c.iter + 1);
-    for (size_t i = 0; i <= c.iter; ++i) {
-      N[i] = h[2 * i];
-      C[i] = h[2 * i + 1];
-    }
+    std::vector<IterRec> recs((size_t)iters + 1);
+    hip_check(e, hipMemcpyAsync(recs.data(), e->rec.p, recs.size() * sizeof(IterRec),
+                                hipMemcpyDeviceToHost, e->stream), "records");
+    sync_stream(e);
+    st->base_tuples = recs[0].N;
+    uint64_t cand_total = 0;
+    for (size_t i = 1; i < recs.size(); ++i) cand_total += recs[i].C;
+    st->join_candidates = cand_total;
     if (st->delta_sizes)
-      for (uint64_t i = 0; i < std::min<uint64_t>(st->delta_sizes_cap, N.size()); ++i) st->delta_sizes[i] = N[i];
-    bytes_model(st, query, sizeof(K), passes, m, N, C, base_cand);
+      for (uint64_t i = 0; i < std::min<uint64_t>(st->delta_sizes_cap, recs.size()); ++i)
+        st->delta_sizes[i] = recs[i].N;
+    bytes_model(st, query, sizeof(K), passes, m, recs, r.c.m_unique);
     collect_timing(e, st);
   }
   return WG_OK;
@@ -580,9 +589,10 @@ wg_status solve(wg_engine* e, int query, const uint32_t* d_src, const uint32_t* 
       std::memset(e->h_up, 0, sizeof(Ctrl));
       hip_check(e, hipMemcpyAsync(e->d_ctrl, e->h_up, sizeof(Ctrl), hipMemcpyHostToDevice, e->stream), "upload");
       launch_max_id(e->stream, e->grid, e->d_ctrl, d_src, d_dst, m);
-      read_ctrl(e, 0);
-      const Ctrl c = wait_ctrl(e, 0);
-      int w = field_bits(c.maxid);
+      hip_check(e, hipMemcpyAsync(&e->h_rb[0].c, e->d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, e->stream),
+                "readback");
+      sync_stream(e);
+      int w = field_bits(e->h_rb[0].c.maxid);
       if (o.radix_field_bits) {
         if ((int)o.radix_field_bits < w) {
           e->err = "radix_field_bits does not cover the largest vertex id";
@@ -602,10 +612,7 @@ wg_status solve(wg_engine* e, int query, const uint32_t* d_src, const uint32_t* 
     }
     return WG_OK;
   } catch (const Fail& f) {
-    if (f.st != WG_ERR_DEVICE) {
-      (void)hipStreamSynchronize(e->stream);
-      // capacity errors leave device-side flags set; the next solve re-uploads the block
-    }
+    (void)hipStreamSynchronize(e->stream);
     return f.st;
   }
 }
@@ -626,16 +633,15 @@ wg_status wg_engine_create(int device, wg_engine** out) {
     hipDeviceProp_t prop;
     hip_check(e, hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
     const int cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-    e->grid.persistent = cu * 4;
     e->grid.stream = cu * 8;
-    e->grid.sort = std::min(cu * 4, kSortBlocksMax);
+    e->grid.scan = std::min(cu * 4, kScanBlocksMax);
     hip_check(e, hipMalloc((void**)&e->d_ctrl, sizeof(Ctrl)), "hipMalloc");
     hip_check(e, hipHostMalloc((void**)&e->h_up, sizeof(Ctrl)), "hipHostMalloc");
-    hip_check(e, hipHostMalloc((void**)&e->h_down, 2 * sizeof(Ctrl)), "hipHostMalloc");
-    hip_check(e, hipMalloc((void**)&e->d_lb, sizeof(LbState) * kLbCount), "hipMalloc");
-    hip_check(e, hipMalloc((void**)&e->d_rcnt, sizeof(uint32_t) * kRadix * kSortBlocksMax), "hipMalloc");
+    hip_check(e, hipHostMalloc((void**)&e->h_rb, 2 * sizeof(Readback)), "hipHostMalloc");
+    hip_check(e, hipMalloc((void**)&e->d_jtot, sizeof(uint64_t) * kScanBlocksMax), "hipMalloc");
+    hip_check(e, hipMalloc((void**)&e->d_bcnt, sizeof(uint64_t) * kScanBlocksMax), "hipMalloc");
+    hip_check(e, hipMalloc((void**)&e->d_rcnt, sizeof(uint32_t) * kRadix * kScanBlocksMax), "hipMalloc");
     hip_check(e, hipMalloc((void**)&e->d_rtot, sizeof(uint32_t) * kRadix), "hipMalloc");
-    hip_check(e, hipMemset(e->d_lb, 0, sizeof(LbState) * kLbCount), "hipMemset");
     hip_check(e, hipMemset(e->d_ctrl, 0, sizeof(Ctrl)), "hipMemset");
     for (int s = 0; s < 2; ++s)
       hip_check(e, hipEventCreateWithFlags(&e->ev_batch[s], hipEventDisableTiming), "hipEventCreate");
@@ -668,14 +674,14 @@ void wg_engine_destroy(wg_engine* e) {
   release(e->rowa);
   release(e->rowb);
   release(e->off);
-  release(e->hist);
-  for (int s = 0; s < kLbCount; ++s) release(e->status[s]);
+  release(e->rec);
   if (e->d_ctrl) (void)hipFree(e->d_ctrl);
-  if (e->d_lb) (void)hipFree(e->d_lb);
+  if (e->d_jtot) (void)hipFree(e->d_jtot);
+  if (e->d_bcnt) (void)hipFree(e->d_bcnt);
   if (e->d_rcnt) (void)hipFree(e->d_rcnt);
   if (e->d_rtot) (void)hipFree(e->d_rtot);
   if (e->h_up) (void)hipHostFree(e->h_up);
-  if (e->h_down) (void)hipHostFree(e->h_down);
+  if (e->h_rb) (void)hipHostFree(e->h_rb);
   for (int s = 0; s < 2; ++s)
     if (e->ev_batch[s]) (void)hipEventDestroy(e->ev_batch[s]);
   for (hipEvent_t ev : e->events) (void)hipEventDestroy(ev);

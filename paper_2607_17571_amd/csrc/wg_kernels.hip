@@ -1,17 +1,22 @@
 // HIP kernels of one semi-naive iteration for gfx950 (CDNA4, wave64).
 //
-//   join count + scan   Section IV-A, two-phase binary-search join (count phase)
-//   join emit           Section IV-A (emit phase) and Section VI (SG cross product)
-//   radix pass          Section V-C, LSD radix sort, 8 bits per pass, dst field first
-//   dedup_diff          Section IV-B, fused dedup + set difference, ordered compaction
+//   join count, emit    Section IV-A, two-phase binary-search join; Section VI (SG)
+//   radix count/scan/   Section V-C, LSD radix sort, 8 bits per pass, dst field first
+//     scatter
+//   compact local/      Section IV-B, fused dedup + set difference, ordered compaction
+//     gather
 //   merge               Section IV-C, disjoint merge-path merge
 //
-// Every kernel reads the sizes it works on from the device control block, so a whole
-// batch of iterations is enqueued without the host knowing any intermediate size
-// (Section V-B).  Kernels that start after the loop halted return at once.
+// Every kernel reads the sizes it works on from device memory (the control block and
+// the per-iteration records), so whole batches of iterations are enqueued without the
+// host knowing any intermediate size (Section V-B).  Kernels that start after the loop
+// halted return at once.
 //
-// Launch shapes: persistent grids (a few blocks per CU).  Lookback kernels claim tiles
-// dynamically over 8 claim lanes; streaming kernels (emit, merge) use a static grid stride.
+// Scans across blocks are two launches, never a chain inside one launch: a producer in
+// which block b handles a static contiguous range and writes its total, and a consumer
+// in which every block adds up the totals of the blocks before it.  On this chip a
+// cross-block handshake (same-address atomics, lookback polling across the XCDs' L2s)
+// costs a microsecond-scale round trip, which a chained scan pays once per tile.
 
 #include "wg_launch.h"
 
@@ -44,132 +49,136 @@ __global__ __launch_bounds__(kBlock) void k_pack(const uint32_t* __restrict__ sr
 }
 
 // ---------------------------------------------------------------------------
-// Join, count phase (Section IV-A).  One thread per delta tuple finds the range of its
-// join key in the edge index by binary search and counts the candidates it will emit;
-// a single-pass scan turns the counts into output offsets, so every tuple owns one
-// contiguous output slab and the emit phase needs no atomics.  The row ids found here
-// are kept for the emit phase instead of searching twice.  Tuples are laid out
-// wave-striped (coalesced loads) and all searches of a thread run interleaved.
+// Join, count phase (Section IV-A).  Each delta tuple finds the range of its join key in
+// the edge index by binary search and counts the candidates it will emit.  Block b owns
+// a static range of tuples and writes, per tuple, the offset of its slab relative to the
+// range and, per block, the range's total; the emit phase adds the totals of earlier
+// blocks, so every tuple owns one contiguous output slab and no atomics are needed.  The
+// row ids found here are kept for the emit phase instead of searching twice.  Tuples are
+// laid out wave-striped (coalesced loads) and a thread's searches run interleaved.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ bool row_found(const uint32_t* __restrict__ U, uint64_t nu, uint64_t j,
+                                          uint32_t v) {
+  return j < nu && U[j] == v;
+}
+
 template <typename K, int Q, int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_join_count(Ctrl* ctrl, Bufs<K> b, int w) {
+__global__ __launch_bounds__(kBlock) void k_join_count(Ctrl* ctrl, Bufs<K> b, int w, uint32_t j) {
   constexpr uint32_t T = kBlock * ITEMS;
-  __shared__ TileScanShared sh;
-  __shared__ uint32_t s_claim[2];
+  __shared__ uint64_t s_wave[kWavesPerBlock];
   if (halted(ctrl)) return;
-  const uint64_t n = (Q == kJoinSGBase) ? ctrl->nu : ctrl->D;
+  const uint64_t n = (Q == kJoinSGBase) ? ctrl->nu : b.rec[j - 1].N;
   const uint64_t nu = ctrl->nu;
-  const K* __restrict__ delta = b.delta[ctrl->delta_side];
+  const K* __restrict__ delta = b.delta[(j - 1) & 1u];
   const uint32_t* __restrict__ U = b.U;
   const uint32_t* __restrict__ R = b.R;
-  const uint64_t ntiles = (n + T - 1) / T;
-  if (ntiles == 0) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->C = 0;
-    return;
-  }
-  LbState* st = b.lb + kLbJoin;
-  const uint32_t epoch = launch_epoch(st);
+  uint64_t lo, hi;
+  block_range(n, T, lo, hi);
   const int wid = threadIdx.x / kWave;
   const int lane = lane_id();
-  for (;;) {
-    const TileClaim cl = claim_tile(st, ntiles, s_claim);
-    if (!cl.ok) {
-      if (cl.last && threadIdx.x == 0) release_launch(st, epoch);
-      break;
-    }
-    {
-      const uint32_t tile = cl.tile;
-      // wave `wid` owns a contiguous run of 64*ITEMS tuples
-      const uint64_t wbase = (uint64_t)tile * T + (uint64_t)wid * (kWave * ITEMS);
-      uint64_t cnt[ITEMS];
-      if (Q == kJoinSGBase) {
-#pragma unroll
-        for (int k = 0; k < ITEMS; ++k) {
-          const uint64_t i = wbase + (uint64_t)k * kWave + lane;
-          uint64_t len = 0;
-          if (i < n) len = R[i + 1] - R[i];
-          cnt[k] = len ? len * (len - 1) : 0;
-        }
-      } else {
-        uint32_t vb[ITEMS], va[ITEMS];
-#pragma unroll
-        for (int k = 0; k < ITEMS; ++k) {
-          const uint64_t i = wbase + (uint64_t)k * kWave + lane;
-          const K key = i < n ? delta[i] : K(0);
-          vb[k] = tc_join_row<K>(key, w);
-          va[k] = head_row<K>(key, w);
-        }
-        uint64_t jb[ITEMS];
-        multi_lower_bound<uint32_t, ITEMS>(U, nu, vb, jb);
-        uint64_t ja[ITEMS];
-        if (Q == kJoinSG) multi_lower_bound<uint32_t, ITEMS>(U, nu, va, ja);
-#pragma unroll
-        for (int k = 0; k < ITEMS; ++k) {
-          const uint64_t i = wbase + (uint64_t)k * kWave + lane;
-          uint64_t c = 0;
-          if (i < n) {
-            const uint32_t rb = (jb[k] < nu && U[jb[k]] == vb[k]) ? (uint32_t)jb[k] : kNoRow;
-            b.rowb[i] = rb;
-            if (Q == kJoinTC) {
-              c = (rb == kNoRow) ? 0 : (uint64_t)(R[rb + 1] - R[rb]);
-            } else {
-              const uint32_t ra = (ja[k] < nu && U[ja[k]] == va[k]) ? (uint32_t)ja[k] : kNoRow;
-              b.rowa[i] = ra;
-              c = (ra == kNoRow || rb == kNoRow)
-                      ? 0
-                      : (uint64_t)(R[ra + 1] - R[ra]) * (uint64_t)(R[rb + 1] - R[rb]);
-            }
-          }
-          cnt[k] = c;
-        }
-      }
-      // exclusive offsets in (k, lane) order inside the wave, then across waves and tiles
-      uint64_t ex[ITEMS];
-      uint64_t run = 0;
-#pragma unroll
-      for (int k = 0; k < ITEMS; ++k) {
-        const uint64_t incl = wave_incl_scan<uint64_t>(cnt[k]);
-        ex[k] = run + incl - cnt[k];
-        run = sat_add(run, __shfl(incl, kWave - 1, kWave));
-      }
-      uint64_t grand, tex;
-      const uint64_t g = tile_scan(lane == 0 ? run : 0ull, tile, epoch, b.status[kLbJoin],
-                                   &ctrl->error, &sh, grand, tex);
-      const uint64_t wave_base = __shfl(g, 0, kWave);
+  uint64_t running = 0;
+  for (uint64_t tbase = lo; tbase < hi; tbase += T) {
+    const uint64_t wbase = tbase + (uint64_t)wid * (kWave * ITEMS);
+    uint64_t cnt[ITEMS];
+    if (Q == kJoinSGBase) {
 #pragma unroll
       for (int k = 0; k < ITEMS; ++k) {
         const uint64_t i = wbase + (uint64_t)k * kWave + lane;
-        if (i < n) b.off[i] = (uint32_t)sat_add(wave_base, ex[k]);
+        uint64_t len = 0;
+        if (i < hi) len = R[i + 1] - R[i];
+        cnt[k] = len ? len * (len - 1) : 0;
       }
-      if (tile == ntiles - 1 && threadIdx.x == 0) {
-        ctrl->C = grand;
-        const uint32_t hook = ctrl->force_overflow_at;
-        const bool forced = Q != kJoinSGBase && hook != 0 && hook == ctrl->iter + 1;
-        if (grand > ctrl->cand_cap || forced) atomicOr(&ctrl->overflow, 1u);
+    } else {
+      uint32_t vb[ITEMS], va[ITEMS];
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint64_t i = wbase + (uint64_t)k * kWave + lane;
+        const K key = i < hi ? delta[i] : K(0);
+        vb[k] = tc_join_row<K>(key, w);
+        va[k] = head_row<K>(key, w);
+      }
+      uint64_t jb[ITEMS];
+      multi_lower_bound<uint32_t, ITEMS>(U, nu, vb, jb);
+      uint64_t ja[ITEMS];
+      if (Q == kJoinSG) multi_lower_bound<uint32_t, ITEMS>(U, nu, va, ja);
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint64_t i = wbase + (uint64_t)k * kWave + lane;
+        uint64_t c = 0;
+        if (i < hi) {
+          const uint32_t rb = row_found(U, nu, jb[k], vb[k]) ? (uint32_t)jb[k] : kNoRow;
+          b.rowb[i] = rb;
+          if (Q == kJoinTC) {
+            c = (rb == kNoRow) ? 0 : (uint64_t)(R[rb + 1] - R[rb]);
+          } else {
+            const uint32_t ra = row_found(U, nu, ja[k], va[k]) ? (uint32_t)ja[k] : kNoRow;
+            b.rowa[i] = ra;
+            c = (ra == kNoRow || rb == kNoRow)
+                    ? 0
+                    : (uint64_t)(R[ra + 1] - R[ra]) * (uint64_t)(R[rb + 1] - R[rb]);
+          }
+        }
+        cnt[k] = c;
       }
     }
+    // exclusive offsets in (k, lane) order inside the wave, then across the waves
+    uint64_t ex[ITEMS];
+    uint64_t run = 0;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint64_t incl = wave_incl_scan<uint64_t>(cnt[k]);
+      ex[k] = run + incl - cnt[k];
+      run = sat_add(run, __shfl(incl, kWave - 1, kWave));
+    }
+    uint64_t tile_total;
+    const uint64_t g = block_excl_scan<uint64_t>(lane == 0 ? run : 0ull, s_wave, tile_total);
+    const uint64_t wave_base = sat_add(running, __shfl(g, 0, kWave));
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint64_t i = wbase + (uint64_t)k * kWave + lane;
+      if (i < hi) b.off[i] = (uint32_t)sat_add(wave_base, ex[k]);
+    }
+    running = sat_add(running, tile_total);
   }
+  if (threadIdx.x == 0) b.jtot[blockIdx.x] = running;
 }
 
 // ---------------------------------------------------------------------------
-// Join, emit phase.  Output positions are dealt out in tiles; each position finds the
-// delta tuple that owns it by binary search over the scanned offsets (a load-balanced
-// expansion, so a hub tuple with thousands of matches is spread over many threads
-// instead of serialising one).  Writes are coalesced.
+// Join, emit phase.  Every block first adds up the per-block totals of the count phase
+// (the candidate total C, and the slab base of every count block).  Output positions are
+// dealt out in tiles; each position finds the delta tuple that owns it by binary search
+// over the slab offsets (a load-balanced expansion, so a hub tuple with thousands of
+// matches is spread over many threads instead of serialising one).  Writes are coalesced.
 // ---------------------------------------------------------------------------
 template <typename K, int Q, int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int w) {
+__global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int w, uint32_t j,
+                                                      int gc) {
   constexpr uint32_t T = kBlock * ITEMS;
+  __shared__ uint64_t s_pre[kScanBlocksMax];
+  __shared__ uint64_t s_wave[kWavesPerBlock];
   __shared__ uint32_t s_off[T];
   __shared__ uint64_t s_i0, s_i1;
   if (halted(ctrl)) return;
-  const uint64_t C = ctrl->C;
-  const uint64_t n = (Q == kJoinSGBase) ? ctrl->nu : ctrl->D;
-  const K* __restrict__ delta = b.delta[ctrl->delta_side];
+  const uint64_t n = (Q == kJoinSGBase) ? ctrl->nu : b.rec[j - 1].N;
+  const uint64_t C = block_prefix(b.jtot, gc, s_pre, s_wave);
+  const uint32_t hook = ctrl->force_overflow_at;
+  const bool forced = Q != kJoinSGBase && hook != 0 && hook == j;
+  if (C > ctrl->cand_cap || forced) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      b.rec[j].C = C;
+      atomicOr(&ctrl->overflow, 1u);
+    }
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) b.rec[j].C = C;
+  const K* __restrict__ delta = b.delta[(j - 1) & 1u];
   const uint32_t* __restrict__ off = b.off;
   const uint32_t* __restrict__ R = b.R;
   const uint32_t* __restrict__ Edst = b.Edst;
   K* __restrict__ cand = b.cand[0];
+  const uint64_t Pc = range_len(n, kJoinTile, (uint32_t)gc);
+  // first candidate of tuple i
+  auto at = [&](uint64_t i) -> uint64_t { return s_pre[i / Pc] + off[i]; };
   const uint64_t ntiles = (C + T - 1) / T;
   const int wid = threadIdx.x / kWave;
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -177,10 +186,10 @@ __global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int
     const uint64_t p1 = min(p0 + T, C);
     // owners of the first and last position of the tile (two waves search concurrently)
     if (wid == 0) {
-      const uint64_t i0 = wave_upper_bound(off, n, (uint32_t)p0) - 1;
+      const uint64_t i0 = wave_partition(0, n, [&](uint64_t i) { return at(i) <= p0; }) - 1;
       if (lane_id() == 0) s_i0 = i0;
     } else if (wid == 1) {
-      const uint64_t i1 = wave_upper_bound(off, n, (uint32_t)(p1 - 1)) - 1;
+      const uint64_t i1 = wave_partition(0, n, [&](uint64_t i) { return at(i) <= p1 - 1; }) - 1;
       if (lane_id() == 0) s_i1 = i1;
     }
     __syncthreads();
@@ -188,7 +197,7 @@ __global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int
     const uint64_t span = s_i1 - i0 + 1;
     const bool in_lds = span <= T;
     if (in_lds) {
-      for (uint32_t j = threadIdx.x; j < span; j += kBlock) s_off[j] = off[i0 + j];
+      for (uint32_t jj = threadIdx.x; jj < span; jj += kBlock) s_off[jj] = (uint32_t)at(i0 + jj);
     }
     __syncthreads();
     uint32_t pos[ITEMS];
@@ -198,17 +207,19 @@ __global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int
       pos[k] = (uint32_t)min(p, p1 - 1);
     }
     uint64_t li[ITEMS];
-    if (in_lds) multi_upper_bound<uint32_t, ITEMS>(s_off, span, pos, li);
-    else multi_upper_bound<uint32_t, ITEMS>(off + i0, span, pos, li);
+    if (in_lds) {
+      multi_upper_bound<uint32_t, ITEMS>(s_off, span, pos, li);
+    } else {
+      multi_upper_bound_at<ITEMS>([&](uint64_t x) { return (uint32_t)at(i0 + x); }, span, pos, li);
+    }
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
       const uint64_t p = p0 + (uint64_t)k * kBlock + threadIdx.x;
-      const bool valid = p < p1;
-      K key = 0;
-      if (valid) {
+      if (p < p1) {
         const uint64_t i = i0 + li[k] - 1;
-        const uint32_t start = in_lds ? s_off[li[k] - 1] : off[i];
+        const uint32_t start = in_lds ? s_off[li[k] - 1] : (uint32_t)at(i);
         const uint32_t r = (uint32_t)p - start;
+        K key;
         if (Q == kJoinTC) {
           const K dk = delta[i];
           key = ((dk >> w) << w) | (K)Edst[R[b.rowb[i]] + r];
@@ -239,23 +250,12 @@ __global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int
 // ---------------------------------------------------------------------------
 // LSD radix sort (Section V-C): 8 bits per pass, dst field first, every pass stable.
 //
-// A pass is three launches with no waiting between blocks: count (block b counts the
-// digits of a static contiguous range of tiles), scan (one block per digit turns the
-// per-block counts into per-block offsets) and scatter (block b re-reads its range tile by
-// tile, ranks each tile stably in LDS and writes every key to its final position).
-// Chained single-pass scans (decoupled lookback) pay a cross-XCD round trip per
-// dependency on this chip; this form pays one extra read of the keys instead, and each
-// block writes long per-digit runs of consecutive positions.
+// A pass is three launches: count (block b counts the digits of a static contiguous
+// range of tiles), scan (one block per digit turns the per-block counts into per-block
+// offsets) and scatter (block b re-reads its range tile by tile, ranks each tile stably
+// in LDS and writes every key to its final position).  Each block writes long per-digit
+// runs of consecutive positions.
 // ---------------------------------------------------------------------------
-
-// Static tile range of this block: tiles [b*tpb, (b+1)*tpb) of T keys.
-__device__ __forceinline__ void block_range(uint64_t n, uint32_t T, uint64_t& lo, uint64_t& hi) {
-  const uint64_t tiles = (n + T - 1) / T;
-  const uint64_t tpb = (tiles + gridDim.x - 1) / gridDim.x;
-  lo = min(n, (uint64_t)blockIdx.x * tpb * T);
-  hi = min(n, lo + tpb * T);
-}
-
 template <typename K, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_radix_count(Ctrl* ctrl, const uint64_t* n_ptr,
                                                         const K* __restrict__ in, int pass,
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(Ctrl* ctrl, const uint
     s_run[tid] = (uint64_t)base + off[(uint64_t)tid * gridDim.x + blockIdx.x];
   }
   for (uint64_t tbase = lo; tbase < hi; tbase += T) {
-    for (int j = tid; j < kWavesPerBlock * kRadix; j += kBlock) (&s_cnt[0][0])[j] = 0;
+    for (int jj = tid; jj < kWavesPerBlock * kRadix; jj += kBlock) (&s_cnt[0][0])[jj] = 0;
     __syncthreads();
     // wave-striped: wave `wid` owns a contiguous run of 64*ITEMS keys
     const uint64_t wbase = tbase + (uint64_t)wid * (ITEMS * kWave);
@@ -384,11 +384,11 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(Ctrl* ctrl, const uint
     const uint32_t tile_n = (uint32_t)min<uint64_t>(T, hi - tbase);
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
-      const uint32_t j = (uint32_t)k * kBlock + tid;
-      if (j < tile_n) {
-        const K kk = s_keys[j];
+      const uint32_t jj = (uint32_t)k * kBlock + tid;
+      if (jj < tile_n) {
+        const K kk = s_keys[jj];
         const uint32_t d = (uint32_t)(kk >> shift) & (kRadix - 1);
-        const uint64_t pos = s_run[d] + (j - s_loc[d]);
+        const uint64_t pos = s_run[d] + (jj - s_loc[d]);
         if (pos < n) out[pos] = kk;
       }
     }
@@ -398,192 +398,198 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(Ctrl* ctrl, const uint
 }
 
 // ---------------------------------------------------------------------------
-// Fused dedup + set difference (Section IV-B).  A candidate survives when it is the first
-// of its run of equal keys and is absent from Full.  Each tile finds the window of Full
-// that can hold its keys with two wave-parallel searches, stages it in LDS when it is
-// small, classifies its candidates, and compacts survivors in input order with a
-// single-pass scan, so the output stays sorted.
+// Compaction: fused dedup + set difference (Section IV-B), also used for seeding the
+// relations (dedup only) and for the SG diagonal filter.
 //
-// The launch's last claimer publishes the iteration: |Delta^i|, the new Full size and the
-// flipped ping-pong sides (Section V-C), so the merge that follows reads its shape from
-// the control block and the next iteration starts from the new delta.
+// compact_local: block b owns a static range of the sorted input.  A key survives dedup
+// when it is the first of its run of equal keys (the key before the range is read from
+// memory) and, in iteration mode, is absent from Full.  For each tile the window of Full
+// that can hold its keys is found by two wave-parallel searches inside the block's own
+// Full range; small windows are staged in LDS and searched there.  Survivors are
+// compacted, in input order, to the start of the block's range in a scratch buffer.
+//
+// compact_gather: every block adds up the survivor counts of the blocks before it and
+// copies its survivors to their final positions; the output stays sorted.  Block 0 then
+// records the iteration (|Delta^j|, |Full| after it, the fixpoint and limit flags).
 // ---------------------------------------------------------------------------
-__device__ void dedup_publish(Ctrl* c, int mode, uint64_t cnt, uint64_t* hist) {
-  if (mode & kModeIter) {
-    const uint64_t F = c->F;
-    const uint32_t it = c->iter;
-    c->N = cnt;
-    if (F + cnt > c->full_cap) { atomicOr(&c->overflow, 2u); return; }
-    if (cnt > c->delta_cap) { atomicOr(&c->overflow, 4u); return; }
-    if ((uint64_t)it + 2 > c->dsz_cap) { atomicOr(&c->overflow, 8u); return; }
-    hist[2 * (uint64_t)(it + 1)] = cnt;
-    hist[2 * (uint64_t)(it + 1) + 1] = c->C;
-    c->total_cand += c->C;
-    c->iter = it + 1;
-    if (cnt == 0) {
-      c->done = 1;
-      return;
-    }
-    // Delta^i lives in the other delta buffer; Full' goes to the other Full buffer
-    c->F = F + cnt;
-    c->D = cnt;
-    c->full_side ^= 1u;
-    c->delta_side ^= 1u;
-    if (c->max_iter != 0 && it + 1 >= c->max_iter) c->limit_hit = 1;
-    return;
-  }
-  if (mode & kModeEdges) c->m_unique = cnt;
-  if (mode & kModeSeed) {
-    c->N = cnt;
-    if (cnt > c->full_cap || cnt > c->delta_cap) { atomicOr(&c->overflow, 2u); return; }
-    c->F = cnt;
-    c->D = cnt;
-    c->D0 = cnt;
-    c->iter = 0;
-    c->total_cand = 0;
-    c->full_side = 0;
-    c->delta_side = 0;
-    hist[0] = cnt;
-    hist[1] = (mode & kModeEdges) ? 0 : c->C;
-    if (cnt == 0) c->done = 1;
-  }
-}
-
 template <typename K, int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_dedup_diff(Ctrl* ctrl, int mode, const uint64_t* n_ptr,
-                                                       const K* __restrict__ cand, Bufs<K> b) {
+__global__ __launch_bounds__(kBlock) void k_compact_local(Ctrl* ctrl, int mode, const uint64_t* n_ptr,
+                                                          const K* __restrict__ in,
+                                                          K* __restrict__ tmp, Bufs<K> b, int w,
+                                                          uint32_t j) {
   constexpr uint32_t T = kBlock * ITEMS;
   __shared__ K s_c[T + 1];
   __shared__ K s_f[T];
-  __shared__ TileScanShared sh;
-  __shared__ uint64_t s_flo, s_fhi;
-  __shared__ uint32_t s_claim[2];
-  if (halted(ctrl)) return;
+  __shared__ uint64_t s_wave[kWavesPerBlock];
+  __shared__ uint64_t s_lo, s_hi;
+  const bool filt = (mode & kModeFilter) != 0;
+  if (!filt && halted(ctrl)) return;
   const uint64_t n = *n_ptr;
-  const bool diff = (mode & kModeIter) != 0;
-  const K* __restrict__ full = diff ? b.full[ctrl->full_side] : nullptr;
-  const uint64_t F = diff ? ctrl->F : 0;
-  K* out1;
-  uint64_t cap1;
-  K* out2 = nullptr;
-  K* out3 = nullptr;
-  uint64_t cap2 = 0, cap3 = 0;
-  if (diff) {
-    out1 = b.delta[ctrl->delta_side ^ 1u];
-    cap1 = ctrl->delta_cap;
-  } else if (mode & kModeEdges) {
-    out1 = b.E;
-    cap1 = ctrl->m_in;
-    if (mode & kModeSeed) {
-      out2 = b.full[0];
-      cap2 = ctrl->full_cap;
-      out3 = b.delta[0];
-      cap3 = ctrl->delta_cap;
-    }
-  } else {
-    out1 = b.full[0];
-    cap1 = ctrl->full_cap;
-    out2 = b.delta[0];
-    cap2 = ctrl->delta_cap;
-  }
-  const uint64_t ntiles = (n + T - 1) / T;
-  if (ntiles == 0) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) dedup_publish(ctrl, mode, 0, b.hist);
+  uint64_t lo, hi;
+  block_range(n, T, lo, hi);
+  if (lo >= hi) {
+    if (threadIdx.x == 0) b.bcnt[blockIdx.x] = 0;
     return;
   }
-  LbState* st = b.lb + kLbDedup;
-  const uint32_t epoch = launch_epoch(st);
+  const bool diff = (mode & kModeIter) != 0;
+  const K* __restrict__ full = diff ? b.full[(j - 1) & 1u] : nullptr;
+  const uint64_t F = diff ? b.rec[j - 1].F : 0;
+  const K mask = field_mask<K>(w);
   const int wid = threadIdx.x / kWave;
-  for (;;) {
-    const TileClaim cl = claim_tile(st, ntiles, s_claim);
-    if (!cl.ok) {
-      if (cl.last && threadIdx.x == 0) {
-        __threadfence();
-        const uint64_t total = __hip_atomic_load(&ctrl->total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        dedup_publish(ctrl, mode, total, b.hist);
-        release_launch(st, epoch);
-      }
-      break;
+  // the part of Full that can hold any key of this block
+  uint64_t bflo = 0, bfhi = 0;
+  if (diff) {
+    if (wid == 0) {
+      const uint64_t v = wave_lower_bound(full, F, in[lo]);
+      if (lane_id() == 0) s_lo = v;
+    } else if (wid == 1) {
+      const uint64_t v = wave_upper_bound(full, F, in[hi - 1]);
+      if (lane_id() == 0) s_hi = v;
     }
-    {
-      const uint32_t tile = cl.tile;
-      const uint64_t tbase = (uint64_t)tile * T;
-      const uint32_t tn = (uint32_t)min<uint64_t>(T, n - tbase);
-      for (uint32_t j = threadIdx.x; j < tn; j += kBlock) s_c[j + 1] = cand[tbase + j];
-      if (threadIdx.x == 0 && tile > 0) s_c[0] = cand[tbase - 1];
-      if (diff) {
-        // window of Full that can hold this tile's keys (two waves search concurrently)
-        if (wid == 0) {
-          const uint64_t flo = wave_lower_bound(full, F, cand[tbase]);
-          if (lane_id() == 0) s_flo = flo;
-        } else if (wid == 1) {
-          const uint64_t fhi = wave_upper_bound(full, F, cand[tbase + tn - 1]);
-          if (lane_id() == 0) s_fhi = fhi;
-        }
+    __syncthreads();
+    bflo = s_lo;
+    bfhi = s_hi > bflo ? s_hi : bflo;
+    __syncthreads();
+  }
+  uint64_t running = 0;
+  for (uint64_t tbase = lo; tbase < hi; tbase += T) {
+    const uint32_t tn = (uint32_t)min<uint64_t>(T, hi - tbase);
+    for (uint32_t jj = threadIdx.x; jj < tn; jj += kBlock) s_c[jj + 1] = in[tbase + jj];
+    if (threadIdx.x == 0 && tbase > 0) s_c[0] = in[tbase - 1];
+    if (diff) {
+      // window of Full that can hold this tile's keys (two waves search concurrently)
+      if (wid == 0) {
+        const uint64_t v = bflo + wave_lower_bound(full + bflo, bfhi - bflo, in[tbase]);
+        if (lane_id() == 0) s_lo = v;
+      } else if (wid == 1) {
+        const uint64_t v = bflo + wave_upper_bound(full + bflo, bfhi - bflo, in[tbase + tn - 1]);
+        if (lane_id() == 0) s_hi = v;
+      }
+    }
+    __syncthreads();
+    uint64_t flo = 0, fspan = 0;
+    bool win = false;
+    if (diff) {
+      flo = s_lo;
+      fspan = s_hi > flo ? s_hi - flo : 0;
+      win = fspan <= T;
+      if (win) {
+        for (uint32_t jj = threadIdx.x; jj < fspan; jj += kBlock) s_f[jj] = full[flo + jj];
       }
       __syncthreads();
-      uint64_t flo = 0, fspan = 0;
-      bool win = false;
-      if (diff) {
-        flo = s_flo;
-        fspan = s_fhi > flo ? s_fhi - flo : 0;
-        win = fspan <= T;
-        if (win) {
-          for (uint32_t j = threadIdx.x; j < fspan; j += kBlock) s_f[j] = full[flo + j];
-        }
-        __syncthreads();
+    }
+    const uint32_t j0 = threadIdx.x * ITEMS;
+    K cv[ITEMS];
+    bool keep[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint32_t jj = j0 + k;
+      cv[k] = (jj < tn) ? s_c[jj + 1] : K(0);
+      if (filt) keep[k] = jj < tn && ((cv[k] >> w) & mask) != (cv[k] & mask);
+      else keep[k] = jj < tn && ((tbase + jj == 0) || (cv[k] != s_c[jj]));
+    }
+    if (fspan > 0) {
+      uint64_t pos[ITEMS];
+      if (win) {
+        multi_lower_bound<K, ITEMS>(s_f, fspan, cv, pos);
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k)
+          if (pos[k] < fspan && s_f[pos[k]] == cv[k]) keep[k] = false;
+      } else {
+        multi_lower_bound<K, ITEMS>(full + flo, fspan, cv, pos);
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k)
+          if (pos[k] < fspan && full[flo + pos[k]] == cv[k]) keep[k] = false;
       }
-      uint32_t keep_mask = 0, cnt = 0;
-      const uint32_t j0 = threadIdx.x * ITEMS;
-      K cv[ITEMS];
-      bool dup[ITEMS];
+    }
+    uint64_t cnt = 0;
 #pragma unroll
-      for (int k = 0; k < ITEMS; ++k) {
-        const uint32_t j = j0 + k;
-        cv[k] = (j < tn) ? s_c[j + 1] : K(0);
-        dup[k] = (j >= tn) || !((tbase + j == 0) || (cv[k] != s_c[j]));
+    for (int k = 0; k < ITEMS; ++k) cnt += keep[k] ? 1u : 0u;
+    uint64_t tile_total;
+    const uint64_t ex = block_excl_scan<uint64_t>(cnt, s_wave, tile_total);
+    // (the scan ends with a barrier, so s_f is free for the survivors)
+    uint32_t lpos = (uint32_t)ex;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k)
+      if (keep[k]) s_f[lpos++] = cv[k];
+    __syncthreads();
+    for (uint32_t jj = threadIdx.x; jj < (uint32_t)tile_total; jj += kBlock)
+      tmp[lo + running + jj] = s_f[jj];
+    running += tile_total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) b.bcnt[blockIdx.x] = running;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_compact_gather(Ctrl* ctrl, int mode, const uint64_t* n_ptr,
+                                                           const K* __restrict__ tmp, Bufs<K> b,
+                                                           uint32_t j, uint32_t side) {
+  constexpr uint32_t T = kDedupTile;
+  __shared__ uint64_t s_pre[kScanBlocksMax];
+  __shared__ uint64_t s_wave[kWavesPerBlock];
+  const bool filt = (mode & kModeFilter) != 0;
+  if (!filt && halted(ctrl)) return;
+  const uint64_t n = *n_ptr;
+  const uint64_t N = block_prefix(b.bcnt, gridDim.x, s_pre, s_wave);
+  uint64_t lo, hi;
+  block_range(n, T, lo, hi);
+  K* out1 = nullptr;
+  K* out2 = nullptr;
+  K* out3 = nullptr;
+  uint32_t ovf = 0;
+  uint64_t F = 0;
+  if (mode & kModeIter) {
+    F = b.rec[j - 1].F;
+    out1 = b.delta[j & 1u];
+    if (F + N > ctrl->full_cap) ovf |= 2u;
+    if (N > ctrl->cand_cap) ovf |= 4u;
+  } else if (mode & kModeEdges) {
+    out1 = b.E;
+    if (mode & kModeSeed) {
+      out2 = b.full[0];
+      out3 = b.delta[0];
+      if (N > ctrl->full_cap || N > ctrl->cand_cap) ovf |= 2u;
+    }
+  } else if (mode & kModeSeed) {
+    out1 = b.full[0];
+    out2 = b.delta[0];
+    if (N > ctrl->full_cap || N > ctrl->cand_cap) ovf |= 2u;
+  } else {
+    out1 = b.full[side ^ 1u];
+  }
+  if (ovf) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (mode & kModeIter) b.rec[j].N = N;
+      atomicOr(&ctrl->overflow, ovf);
+    }
+    return;
+  }
+  const uint64_t cnt = b.bcnt[blockIdx.x];
+  const uint64_t pre = s_pre[blockIdx.x];
+  for (uint64_t t = threadIdx.x; t < cnt; t += kBlock) {
+    const K v = tmp[lo + t];
+    out1[pre + t] = v;
+    if (out2) out2[pre + t] = v;
+    if (out3) out3[pre + t] = v;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (mode & kModeIter) {
+      b.rec[j].N = N;
+      b.rec[j].F = F + N;
+      ctrl->iter = j;
+      if (N == 0) ctrl->done = 1;
+      else if (ctrl->max_iter != 0 && j >= ctrl->max_iter) ctrl->limit_hit = 1;
+    } else if (mode & (kModeEdges | kModeSeed)) {
+      if (mode & kModeEdges) ctrl->m_unique = N;
+      if (mode & kModeSeed) {
+        b.rec[0].N = N;
+        b.rec[0].F = N;
+        ctrl->iter = 0;
+        if (N == 0) ctrl->done = 1;
       }
-      bool member[ITEMS];
-#pragma unroll
-      for (int k = 0; k < ITEMS; ++k) member[k] = false;
-      if (fspan > 0) {
-        uint64_t pos[ITEMS];
-        if (win) {
-          multi_lower_bound<K, ITEMS>(s_f, fspan, cv, pos);
-#pragma unroll
-          for (int k = 0; k < ITEMS; ++k) member[k] = pos[k] < fspan && s_f[pos[k]] == cv[k];
-        } else {
-          multi_lower_bound<K, ITEMS>(full + flo, fspan, cv, pos);
-#pragma unroll
-          for (int k = 0; k < ITEMS; ++k) member[k] = pos[k] < fspan && full[flo + pos[k]] == cv[k];
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < ITEMS; ++k) {
-        if (!dup[k] && !member[k]) {
-          keep_mask |= 1u << k;
-          ++cnt;
-        }
-      }
-      uint64_t grand, tex;
-      const uint64_t g = tile_scan(cnt, tile, epoch, b.status[kLbDedup], &ctrl->error, &sh, grand, tex);
-      // tile_scan ends with a barrier, so s_f is free to reuse for the survivors.
-      uint32_t lpos = (uint32_t)(g - tex);
-#pragma unroll
-      for (int k = 0; k < ITEMS; ++k)
-        if ((keep_mask >> k) & 1u) s_f[lpos++] = cv[k];
-      __syncthreads();
-      const uint32_t tcount = (uint32_t)(grand - tex);
-      for (uint32_t j = threadIdx.x; j < tcount; j += kBlock) {
-        const uint64_t p = tex + j;
-        const K v = s_f[j];
-        if (p < cap1) out1[p] = v;
-        if (out2 && p < cap2) out2[p] = v;
-        if (out3 && p < cap3) out3[p] = v;
-      }
-      if (tile == ntiles - 1 && threadIdx.x == 0)
-        __hip_atomic_store(&ctrl->total, grand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __syncthreads();
+    } else {
+      ctrl->filtered = N;
     }
   }
 }
@@ -592,8 +598,8 @@ __global__ __launch_bounds__(kBlock) void k_dedup_diff(Ctrl* ctrl, int mode, con
 // Disjoint merge (Section IV-C).  Full and the new delta are disjoint by construction, so
 // Full' has exactly |Full| + |Delta| keys and each tile's slice of both inputs is fixed by
 // a merge-path diagonal search: no atomics, no cleanup pass.  Tiles that take keys from
-// one input only are straight copies.  The sizes and sides were published by dedup_diff:
-// Full' goes to full[full_side], the old Full is the other buffer.
+// one input only are straight copies.  Iteration j merges Full[(j-1)&1] and delta[j&1]
+// into Full[j&1] (ping-pong, Section V-C).
 // ---------------------------------------------------------------------------
 // Number of A keys among the first `diag` keys of merge(A, B), found by the whole wave.
 template <typename K>
@@ -605,19 +611,18 @@ __device__ __forceinline__ uint64_t wave_merge_path(const K* A, uint64_t na, con
 }
 
 template <typename K, int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_merge(Ctrl* ctrl, Bufs<K> b) {
+__global__ __launch_bounds__(kBlock) void k_merge(Ctrl* ctrl, Bufs<K> b, uint32_t j) {
   constexpr uint32_t T = kBlock * ITEMS;
   __shared__ K s_in[T];
   __shared__ K s_out[T];
   __shared__ uint64_t s_i0, s_i1;
   if (halted(ctrl)) return;
-  const uint64_t total = ctrl->F;
-  const uint64_t nb = ctrl->N;
-  const uint64_t na = total - nb;
-  const uint32_t fs = ctrl->full_side, ds = ctrl->delta_side;
-  const K* __restrict__ A = b.full[fs ^ 1u];
-  const K* __restrict__ B = b.delta[ds];
-  K* __restrict__ O = b.full[fs];
+  const uint64_t nb = b.rec[j].N;
+  const uint64_t na = b.rec[j - 1].F;
+  const uint64_t total = na + nb;
+  const K* __restrict__ A = b.full[(j - 1) & 1u];
+  const K* __restrict__ B = b.delta[j & 1u];
+  K* __restrict__ O = b.full[j & 1u];
   const uint64_t ntiles = (total + T - 1) / T;
   const int wid = threadIdx.x / kWave;
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -669,126 +674,61 @@ __global__ __launch_bounds__(kBlock) void k_merge(Ctrl* ctrl, Bufs<K> b) {
 
 // ---------------------------------------------------------------------------
 // Edge index: E is sorted once and never modified (Section IV-A), so the edges of each
-// (inst, src) row are contiguous.  U lists the distinct rows, R their starts.
+// (inst, src) row are contiguous.  U lists the distinct rows, R their starts.  Two
+// launches: per-block row-head counts, then every block writes its heads.
 // ---------------------------------------------------------------------------
 template <typename K, int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_edge_index(Ctrl* ctrl, Bufs<K> b, int w) {
+__global__ __launch_bounds__(kBlock) void k_index_count(Ctrl* ctrl, Bufs<K> b, int w) {
   constexpr uint32_t T = kBlock * ITEMS;
-  __shared__ TileScanShared sh;
-  __shared__ uint32_t s_claim[2];
-  if (ctrl->error | ctrl->overflow) return;
+  __shared__ uint64_t s_wave[kWavesPerBlock];
+  if (halted(ctrl)) return;
   const uint64_t n = ctrl->m_unique;
   const K* __restrict__ E = b.E;
   const K mask = field_mask<K>(w);
-  const uint64_t ntiles = (n + T - 1) / T;
-  if (ntiles == 0) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      ctrl->nu = 0;
-      b.R[0] = 0;
-    }
-    return;
+  uint64_t lo, hi;
+  block_range(n, T, lo, hi);
+  uint64_t cnt = 0;
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+    const K e = E[i];
+    b.Edst[i] = (uint32_t)(e & mask);
+    if (i == 0 || (e >> w) != (E[i - 1] >> w)) ++cnt;
   }
-  LbState* st = b.lb + kLbIndex;
-  const uint32_t epoch = launch_epoch(st);
-  for (;;) {
-    const TileClaim cl = claim_tile(st, ntiles, s_claim);
-    if (!cl.ok) {
-      if (cl.last && threadIdx.x == 0) release_launch(st, epoch);
-      break;
-    }
-    {
-      const uint32_t tile = cl.tile;
-      const uint64_t base = (uint64_t)tile * T + (uint64_t)threadIdx.x * ITEMS;
-      uint32_t heads = 0, cnt = 0;
-#pragma unroll
-      for (int k = 0; k < ITEMS; ++k) {
-        const uint64_t i = base + k;
-        if (i < n) {
-          const K e = E[i];
-          b.Edst[i] = (uint32_t)(e & mask);
-          if (i == 0 || (e >> w) != (E[i - 1] >> w)) {
-            heads |= 1u << k;
-            ++cnt;
-          }
-        }
-      }
-      uint64_t grand, tex;
-      uint64_t g = tile_scan(cnt, tile, epoch, b.status[kLbIndex], &ctrl->error, &sh, grand, tex);
-#pragma unroll
-      for (int k = 0; k < ITEMS; ++k) {
-        if ((heads >> k) & 1u) {
-          const uint64_t i = base + k;
-          b.U[g] = (uint32_t)(E[i] >> w);
-          b.R[g] = (uint32_t)i;
-          ++g;
-        }
-      }
-      if (tile == ntiles - 1 && threadIdx.x == 0) {
-        ctrl->nu = grand;
-        b.R[grand] = (uint32_t)n;
-      }
-    }
-  }
+  uint64_t total;
+  block_excl_scan<uint64_t>(cnt, s_wave, total);
+  if (threadIdx.x == 0) b.bcnt[blockIdx.x] = total;
 }
 
-// SG with WG_SG_IRREFLEXIVE: drop (x, x) from the final relation (Full -> other side).
 template <typename K, int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_filter_offdiag(Ctrl* ctrl, Bufs<K> b, int w) {
+__global__ __launch_bounds__(kBlock) void k_index_write(Ctrl* ctrl, Bufs<K> b, int w) {
   constexpr uint32_t T = kBlock * ITEMS;
-  __shared__ TileScanShared sh;
-  __shared__ K s_out[T];
-  __shared__ uint32_t s_claim[2];
-  if (ctrl->error) return;
-  const uint64_t n = ctrl->F;
-  const uint32_t fs = ctrl->full_side;
-  const K* __restrict__ in = b.full[fs];
-  K* __restrict__ out = b.full[fs ^ 1u];
-  const K mask = field_mask<K>(w);
-  const uint64_t ntiles = (n + T - 1) / T;
-  if (ntiles == 0) return;
-  LbState* st = b.lb + kLbFilter;
-  const uint32_t epoch = launch_epoch(st);
-  for (;;) {
-    const TileClaim cl = claim_tile(st, ntiles, s_claim);
-    if (!cl.ok) {
-      if (cl.last && threadIdx.x == 0) {
-        __threadfence();
-        ctrl->F = __hip_atomic_load(&ctrl->total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ctrl->full_side = fs ^ 1u;
-        release_launch(st, epoch);
-      }
-      break;
+  __shared__ uint64_t s_pre[kScanBlocksMax];
+  __shared__ uint64_t s_wave[kWavesPerBlock];
+  if (halted(ctrl)) return;
+  const uint64_t n = ctrl->m_unique;
+  const K* __restrict__ E = b.E;
+  const uint64_t nu = block_prefix(b.bcnt, gridDim.x, s_pre, s_wave);
+  uint64_t lo, hi;
+  block_range(n, T, lo, hi);
+  uint64_t run = s_pre[blockIdx.x];
+  for (uint64_t base = lo; base < hi; base += kBlock) {
+    const uint64_t i = base + threadIdx.x;
+    bool head = false;
+    K e = 0;
+    if (i < hi) {
+      e = E[i];
+      head = (i == 0 || (e >> w) != (E[i - 1] >> w));
     }
-    {
-      const uint32_t tile = cl.tile;
-      const uint64_t base = (uint64_t)tile * T + (uint64_t)threadIdx.x * ITEMS;
-      uint32_t keep = 0, cnt = 0;
-      K v[ITEMS];
-#pragma unroll
-      for (int k = 0; k < ITEMS; ++k) {
-        const uint64_t i = base + k;
-        v[k] = 0;
-        if (i < n) {
-          v[k] = in[i];
-          if (((v[k] >> w) & mask) != (v[k] & mask)) {
-            keep |= 1u << k;
-            ++cnt;
-          }
-        }
-      }
-      uint64_t grand, tex;
-      const uint64_t g = tile_scan(cnt, tile, epoch, b.status[kLbFilter], &ctrl->error, &sh, grand, tex);
-      uint32_t lpos = (uint32_t)(g - tex);
-#pragma unroll
-      for (int k = 0; k < ITEMS; ++k)
-        if ((keep >> k) & 1u) s_out[lpos++] = v[k];
-      __syncthreads();
-      const uint32_t tcount = (uint32_t)(grand - tex);
-      for (uint32_t j = threadIdx.x; j < tcount; j += kBlock) out[tex + j] = s_out[j];
-      if (tile == ntiles - 1 && threadIdx.x == 0)
-        __hip_atomic_store(&ctrl->total, grand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __syncthreads();
+    uint64_t total;
+    const uint64_t ex = block_excl_scan<uint64_t>(head ? 1ull : 0ull, s_wave, total);
+    if (head) {
+      b.U[run + ex] = (uint32_t)(e >> w);
+      b.R[run + ex] = (uint32_t)i;
     }
+    run += total;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctrl->nu = nu;
+    b.R[nu] = (uint32_t)n;
   }
 }
 
@@ -805,13 +745,10 @@ __global__ __launch_bounds__(kBlock) void k_unpack(const K* __restrict__ keys, u
   }
 }
 
-__global__ void k_resume(Ctrl* ctrl, uint64_t cand_cap, uint64_t full_cap, uint64_t dsz_cap,
-                         uint32_t clear_hook) {
+__global__ void k_resume(Ctrl* ctrl, uint64_t cand_cap, uint64_t full_cap, uint32_t clear_hook) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     ctrl->cand_cap = cand_cap;
-    ctrl->delta_cap = cand_cap;
     ctrl->full_cap = full_cap;
-    ctrl->dsz_cap = dsz_cap;
     ctrl->overflow = 0;
     if (clear_hook) ctrl->force_overflow_at = 0;
   }
@@ -837,56 +774,60 @@ void launch_pack(hipStream_t s, const Grid& g, const uint32_t* src, const uint32
 }
 
 template <typename K>
-void launch_join_count(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w) {
+void launch_join_count(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w,
+                       uint32_t j) {
   if (kind == kJoinTC)
-    hipLaunchKernelGGL((k_join_count<K, kJoinTC, kJoinItems>), dim3(g.persistent), dim3(kBlock), 0, s, ctrl, b, w);
+    hipLaunchKernelGGL((k_join_count<K, kJoinTC, kJoinItems>), dim3(g.scan), dim3(kBlock), 0, s, ctrl, b, w, j);
   else if (kind == kJoinSG)
-    hipLaunchKernelGGL((k_join_count<K, kJoinSG, kJoinItems>), dim3(g.persistent), dim3(kBlock), 0, s, ctrl, b, w);
+    hipLaunchKernelGGL((k_join_count<K, kJoinSG, kJoinItems>), dim3(g.scan), dim3(kBlock), 0, s, ctrl, b, w, j);
   else
-    hipLaunchKernelGGL((k_join_count<K, kJoinSGBase, kJoinItems>), dim3(g.persistent), dim3(kBlock), 0, s, ctrl, b, w);
+    hipLaunchKernelGGL((k_join_count<K, kJoinSGBase, kJoinItems>), dim3(g.scan), dim3(kBlock), 0, s, ctrl, b, w, j);
 }
 
 template <typename K>
-void launch_join_emit(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w) {
+void launch_join_emit(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w,
+                      uint32_t j) {
   if (kind == kJoinTC)
-    hipLaunchKernelGGL((k_join_emit<K, kJoinTC, kEmitItems>), dim3(g.stream), dim3(kBlock), 0, s, ctrl, b, w);
+    hipLaunchKernelGGL((k_join_emit<K, kJoinTC, kEmitItems>), dim3(g.stream), dim3(kBlock), 0, s, ctrl, b, w, j, g.scan);
   else if (kind == kJoinSG)
-    hipLaunchKernelGGL((k_join_emit<K, kJoinSG, kEmitItems>), dim3(g.stream), dim3(kBlock), 0, s, ctrl, b, w);
+    hipLaunchKernelGGL((k_join_emit<K, kJoinSG, kEmitItems>), dim3(g.stream), dim3(kBlock), 0, s, ctrl, b, w, j, g.scan);
   else
-    hipLaunchKernelGGL((k_join_emit<K, kJoinSGBase, kEmitItems>), dim3(g.stream), dim3(kBlock), 0, s, ctrl, b, w);
+    hipLaunchKernelGGL((k_join_emit<K, kJoinSGBase, kEmitItems>), dim3(g.stream), dim3(kBlock), 0, s, ctrl, b, w, j, g.scan);
 }
 
 template <typename K>
-void launch_radix_pass(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint64_t* n_ptr,
-                       const K* in, K* out, int pass, const Bufs<K>& b) {
+void launch_sort(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint64_t* n_ptr, int passes,
+                 const Bufs<K>& b) {
   constexpr int ITEMS = pass_items<K>();
-  hipLaunchKernelGGL((k_radix_count<K, ITEMS>), dim3(g.sort), dim3(kBlock), 0, s, ctrl, n_ptr, in,
-                     pass, b.rcnt);
-  hipLaunchKernelGGL(k_radix_scan, dim3(kRadix), dim3(kBlock), 0, s, ctrl, b.rcnt, b.rtot, g.sort);
-  hipLaunchKernelGGL((k_radix_scatter<K, ITEMS>), dim3(g.sort), dim3(kBlock), 0, s, ctrl, n_ptr, in,
-                     out, pass, b.rcnt, b.rtot);
+  for (int p = 0; p < passes; ++p) {
+    const K* in = b.cand[p & 1];
+    K* out = b.cand[(p + 1) & 1];
+    hipLaunchKernelGGL((k_radix_count<K, ITEMS>), dim3(g.scan), dim3(kBlock), 0, s, ctrl, n_ptr, in,
+                       p, b.rcnt);
+    hipLaunchKernelGGL(k_radix_scan, dim3(kRadix), dim3(kBlock), 0, s, ctrl, b.rcnt, b.rtot, g.scan);
+    hipLaunchKernelGGL((k_radix_scatter<K, ITEMS>), dim3(g.scan), dim3(kBlock), 0, s, ctrl, n_ptr,
+                       in, out, p, b.rcnt, b.rtot);
+  }
 }
 
 template <typename K>
-void launch_dedup_diff(hipStream_t s, const Grid& g, int mode, Ctrl* ctrl, const uint64_t* n_ptr,
-                       const K* cand, const Bufs<K>& b) {
-  hipLaunchKernelGGL((k_dedup_diff<K, kDedupItems>), dim3(g.persistent), dim3(kBlock), 0, s, ctrl,
-                     mode, n_ptr, cand, b);
+void launch_compact(hipStream_t s, const Grid& g, int mode, Ctrl* ctrl, const uint64_t* n_ptr,
+                    const K* in, K* tmp, const Bufs<K>& b, int w, uint32_t j, uint32_t side) {
+  hipLaunchKernelGGL((k_compact_local<K, kDedupItems>), dim3(g.scan), dim3(kBlock), 0, s, ctrl, mode,
+                     n_ptr, in, tmp, b, w, j);
+  hipLaunchKernelGGL(k_compact_gather<K>, dim3(g.scan), dim3(kBlock), 0, s, ctrl, mode, n_ptr, tmp, b,
+                     j, side);
 }
 
 template <typename K>
-void launch_merge(hipStream_t s, const Grid& g, Ctrl* ctrl, const Bufs<K>& b) {
-  hipLaunchKernelGGL((k_merge<K, kMergeItems>), dim3(g.stream), dim3(kBlock), 0, s, ctrl, b);
+void launch_merge(hipStream_t s, const Grid& g, Ctrl* ctrl, const Bufs<K>& b, uint32_t j) {
+  hipLaunchKernelGGL((k_merge<K, kMergeItems>), dim3(g.stream), dim3(kBlock), 0, s, ctrl, b, j);
 }
 
 template <typename K>
 void launch_edge_index(hipStream_t s, const Grid& g, Ctrl* ctrl, const Bufs<K>& b, int w) {
-  hipLaunchKernelGGL((k_edge_index<K, kIndexItems>), dim3(g.persistent), dim3(kBlock), 0, s, ctrl, b, w);
-}
-
-template <typename K>
-void launch_filter_offdiag(hipStream_t s, const Grid& g, Ctrl* ctrl, const Bufs<K>& b, int w) {
-  hipLaunchKernelGGL((k_filter_offdiag<K, kIndexItems>), dim3(g.persistent), dim3(kBlock), 0, s, ctrl, b, w);
+  hipLaunchKernelGGL((k_index_count<K, kIndexItems>), dim3(g.scan), dim3(kBlock), 0, s, ctrl, b, w);
+  hipLaunchKernelGGL((k_index_write<K, kIndexItems>), dim3(g.scan), dim3(kBlock), 0, s, ctrl, b, w);
 }
 
 template <typename K>
@@ -895,24 +836,24 @@ void launch_unpack(hipStream_t s, const Grid& g, const K* keys, uint64_t n, int 
   hipLaunchKernelGGL(k_unpack<K>, dim3(stream_blocks(g, n)), dim3(kBlock), 0, s, keys, n, w, src, dst);
 }
 
-void launch_resume(hipStream_t s, Ctrl* ctrl, uint64_t cand_cap, uint64_t full_cap,
-                   uint64_t dsz_cap, uint32_t clear_hook) {
-  hipLaunchKernelGGL(k_resume, dim3(1), dim3(64), 0, s, ctrl, cand_cap, full_cap, dsz_cap, clear_hook);
+void launch_resume(hipStream_t s, Ctrl* ctrl, uint64_t cand_cap, uint64_t full_cap, uint32_t clear_hook) {
+  hipLaunchKernelGGL(k_resume, dim3(1), dim3(64), 0, s, ctrl, cand_cap, full_cap, clear_hook);
 }
 
 #define WG_INSTANTIATE(K)                                                                          \
   template void launch_pack<K>(hipStream_t, const Grid&, const uint32_t*, const uint32_t*,       \
                                uint64_t, int, K*);                                                \
-  template void launch_join_count<K>(hipStream_t, const Grid&, int, Ctrl*, const Bufs<K>&, int);   \
-  template void launch_join_emit<K>(hipStream_t, const Grid&, int, Ctrl*, const Bufs<K>&, int);    \
-  template void launch_radix_pass<K>(hipStream_t, const Grid&, Ctrl*, const uint64_t*, const K*,   \
-                                     K*, int, const Bufs<K>&);                                     \
-  template void launch_dedup_diff<K>(hipStream_t, const Grid&, int, Ctrl*, const uint64_t*,        \
-                                     const K*, const Bufs<K>&);                                    \
-  template void launch_merge<K>(hipStream_t, const Grid&, Ctrl*, const Bufs<K>&);                  \
-  template void launch_edge_index<K>(hipStream_t, const Grid&, Ctrl*, const Bufs<K>&, int);        \
-  template void launch_filter_offdiag<K>(hipStream_t, const Grid&, Ctrl*, const Bufs<K>&, int);    \
-  template void launch_unpack<K>(hipStream_t, const Grid&, const K*, uint64_t, int, uint32_t*,     \
+  template void launch_join_count<K>(hipStream_t, const Grid&, int, Ctrl*, const Bufs<K>&, int,   \
+                                     uint32_t);                                                    \
+  template void launch_join_emit<K>(hipStream_t, const Grid&, int, Ctrl*, const Bufs<K>&, int,    \
+                                    uint32_t);                                                     \
+  template void launch_sort<K>(hipStream_t, const Grid&, Ctrl*, const uint64_t*, int,             \
+                               const Bufs<K>&);                                                    \
+  template void launch_compact<K>(hipStream_t, const Grid&, int, Ctrl*, const uint64_t*, const K*, \
+                                  K*, const Bufs<K>&, int, uint32_t, uint32_t);                    \
+  template void launch_merge<K>(hipStream_t, const Grid&, Ctrl*, const Bufs<K>&, uint32_t);       \
+  template void launch_edge_index<K>(hipStream_t, const Grid&, Ctrl*, const Bufs<K>&, int);       \
+  template void launch_unpack<K>(hipStream_t, const Grid&, const K*, uint64_t, int, uint32_t*,    \
                                  uint32_t*);
 
 WG_INSTANTIATE(uint32_t)
