@@ -1,17 +1,21 @@
-"""Benchmark: derived tuples/s of the TC fixpoint on one MI355X.
+"""Benchmark: derived tuples/s of TC / SG fixpoints on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
 
-A step is one whole solve through the C ABI (wg_tc / wg_sg): prepare (sort, dedup and
-index E), every semi-naive iteration (join, sort, fused dedup + difference, merge,
-empty-delta test) and the result unpacked into torch-allocated split arrays.  Inputs
-are resident in HBM before the timed region.  The value is |fixpoint| per second of
-solve time.
+A step is one whole solve through the C ABI (wg_tc / wg_sg, or wg_tc_batch /
+wg_sg_batch for batched workloads): prepare (sort, dedup and index E), every
+semi-naive iteration (join, sort, fused dedup + difference, merge, empty-delta test)
+and the result unpacked into torch-allocated split arrays.  Inputs are resident in HBM
+before the timed region.  The value is |fixpoint| per second of solve time.
 
 Default workload: TC on an R-MAT graph of scale 15 (32,768 vertices), m = 29,491,
 (a,b,c,d) = (0.57,0.19,0.19,0.05), seed 2.  R-MAT scale 22 with 3.8M edges has a
 closure of ~3.9e11 tuples, which no single GPU can hold; scale 15 keeps the same skew
 and degree with a closure of 4.99e7 tuples.
+
+Batched workloads (tc_batch_er_4096: 4,096 ER instances in one solve) first run the
+autotuner on the batch (outside the timed region), then also time the plain path: the
+same instances solved one at a time with wg_tc.
 
 The JSON line also carries the roofline of the dominant kernel (algorithmic bytes /
 HIP-event time of its launches in the timed region, against 8 TB/s HBM) and the CPU
@@ -35,9 +39,14 @@ WORKLOAD_TEXT = {
     "tc_rmat_s15": "TC, R-MAT scale 15 (n=32,768, m=29,491, a,b,c,d=0.57,0.19,0.19,0.05, seed 2); "
                    "stands in for R-MAT scale 22 whose ~3.9e11-tuple closure exceeds one GPU",
     "tc_rmat_s16": "TC, R-MAT scale 16 (n=65,536, m=58,982, a,b,c,d=0.57,0.19,0.19,0.05, seed 2)",
+    "tc_rmat_s15_ids24": "TC, R-MAT scale 15 with ids scattered into [0, 2^22) (24-bit radix field)",
     "tc_er_2000": "TC, directed ER n=2,000 m=1,900 seed 1",
     "sg_er_500k": "SG, directed ER n=500,000 m=450,000 seed 3",
     "tc_grid_100": "TC, 100x100 grid DAG (198 iterations)",
+    "tc_batch_er_4096": "batched TC, 4,096 ER instances, n log-uniform in [256, 65,536], mean "
+                        "out-degree uniform in [0.5, 0.95], seed 4, one solve",
+    "tc_batch_er_256": "batched TC, 256 ER instances (same recipe), seed 6",
+    "sg_batch_er_256": "batched SG, 256 ER instances, n log-uniform in [64, 4,096], seed 7",
 }
 
 
@@ -49,14 +58,35 @@ def parse():
     p.add_argument("--workload", default="tc_rmat_s15")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-timing", action="store_true", help="time steps without per-kernel events")
+    p.add_argument("--digit-bits", type=int, default=0, help="radix digit bits (0: engine's choice)")
+    p.add_argument("--tile-items", type=int, default=0, help="sort tile keys per thread (0: engine's)")
+    p.add_argument("--no-autotune", action="store_true", help="batched workloads: skip the autotuner")
+    p.add_argument("--no-plain", action="store_true", help="batched workloads: skip the one-by-one path")
     return p.parse_args()
 
 
+def is_batch(name: str) -> bool:
+    return "_batch_" in name
+
+
 def cpu_baseline(name: str):
-    """The oracle as it stands, timed on the host on one whole solve of the workload."""
+    """The oracle as it stands, timed on the host: one whole solve, or for a batch the
+    instances in order until about 15 s of work."""
     import oracle
     from paper_2607_17571_amd import inputs
 
+    if is_batch(name):
+        query, b = inputs.batch_workload(name)
+        fn = oracle.tc if query == "tc" else oracle.sg
+        t0 = time.perf_counter()
+        tuples = done = 0
+        while done < b.num and time.perf_counter() - t0 < 15.0:
+            tuples += fn(*b.instance(done)).src.size
+            done += 1
+        dt = time.perf_counter() - t0
+        return {"value": tuples / dt, "unit": "tuples/s", "cores": 1, "kind": "oracle",
+                "sample": f"instances 0..{done - 1} of {name} ({tuples} tuples) solved one by one "
+                          f"in {dt:.2f} s, single-threaded numpy"}, None
     w = inputs.workload(name)
     t0 = time.perf_counter()
     r = oracle.tc(w.src, w.dst) if w.query == "tc" else oracle.sg(w.src, w.dst)
@@ -72,6 +102,7 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    import numpy as np
     import torch
 
     from paper_2607_17571_amd import inputs, wg
@@ -79,22 +110,45 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(2)
-    w = inputs.workload(args.workload)
-    src = torch.from_numpy(w.src).cuda()
-    dst = torch.from_numpy(w.dst).cuda()
     eng = wg.Engine(0)
-    solve = eng.tc if w.query == "tc" else eng.sg
+    extra = {}
+    if is_batch(args.workload):
+        query, b = inputs.batch_workload(args.workload)
+        src = torch.from_numpy(b.src).cuda()
+        dst = torch.from_numpy(b.dst).cuda()
+        offs = torch.from_numpy(b.offsets.astype(np.int64)).cuda()
+        edges = int(b.src.size)
+        if not args.no_autotune and not (args.digit_bits or args.tile_items):
+            rep = eng.autotune(query, src, dst, offs)
+            extra["autotune"] = {"best": rep["best"], "best_ms": round(rep["best_ms"], 3),
+                                 "default_ms": round(rep["before_ms"], 3),
+                                 "trials": len(rep["trials"])}
 
+        def solve(opts):
+            _, _, _, st = eng.solve_batch(query, src, dst, offs, opts)
+            return st
+    else:
+        w = inputs.workload(args.workload)
+        query = w.query
+        src = torch.from_numpy(w.src).cuda()
+        dst = torch.from_numpy(w.dst).cuda()
+        edges = int(w.src.size)
+
+        def solve(opts):
+            _, _, st = eng.solve(query, src, dst, opts)
+            return st
+
+    sort_opts = dict(radix_digit_bits=args.digit_bits, tile_items=args.tile_items)
     for _ in range(args.warmup):
-        solve(src, dst, None)
+        solve(wg.make_options(**sort_opts))
     torch.cuda.synchronize()
     # Untimed probe with events on every kernel kind: per-stage breakdown and the dominant
     # kernel.  The timed region below records events around that kernel kind only.
-    _, _, probe = solve(src, dst, wg.make_options(flags=wg.WG_STAGE_TIMING))
+    probe = solve(wg.make_options(flags=wg.WG_STAGE_TIMING, **sort_opts))
     dom = max(wg.STAGES, key=lambda k: probe["stage_ms"][k])
     probe_ms = {k: round(v, 3) for k, v in probe["stage_ms"].items()}
     flags = 0 if args.no_timing else wg.WG_STAGE_TIMING
-    opts = wg.make_options(flags=flags, timing_stages=1 << wg.STAGES.index(dom))
+    opts = wg.make_options(flags=flags, timing_stages=1 << wg.STAGES.index(dom), **sort_opts)
     torch.cuda.synchronize()
     stage_ms = {k: 0.0 for k in wg.STAGES}
     stage_bytes = {k: 0 for k in wg.STAGES}
@@ -103,7 +157,7 @@ def main():
     st = None
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        s, d, st = solve(src, dst, opts)
+        st = solve(opts)
         tuples += st["result_tuples"]
         for k in wg.STAGES:
             stage_ms[k] += st["stage_ms"][k]
@@ -125,6 +179,22 @@ def main():
                     "bytes_per_step": stage_bytes[dom] // args.steps,
                     "launches_per_step": stage_launches[dom] // args.steps}
 
+    if is_batch(args.workload) and not args.no_plain:
+        # the plain single-instance path over the same inputs: one wg_tc / wg_sg per instance
+        plain_tuples = 0
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for i in range(b.num):
+            lo, hi = int(b.offsets[i]), int(b.offsets[i + 1])
+            if hi > lo:
+                _, _, sti = eng.solve(query, src[lo:hi], dst[lo:hi], None)
+                plain_tuples += sti["result_tuples"]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        extra["single_instance_path"] = {"value": round(plain_tuples / dt, 1), "unit": "tuples/s",
+                                         "ms": round(1e3 * dt, 3), "solves": int(b.num)}
+        extra["batched_speedup"] = round(value / (plain_tuples / dt), 2)
+
     out = {
         "metric": "derived tuples/sec per TC/SG fixpoint",
         "value": round(value, 1),
@@ -139,17 +209,19 @@ def main():
         "dtype": "u32" if st["key_bytes"] == 4 else "u64",
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT.get(args.workload, args.workload), "name": args.workload,
-                   "query": w.query, "edges": int(w.src.size), "fixpoint_tuples": st["result_tuples"],
+                   "query": query, "edges": edges, "fixpoint_tuples": st["result_tuples"],
                    "iterations": st["iterations"], "join_candidates": st["join_candidates"],
-                   "radix_field_bits": st["field_bits"], "host_syncs_per_step": st["host_syncs"]},
+                   "radix_field_bits": st["field_bits"], "radix_digit_bits": st["digit_bits"],
+                   "sort_passes": st["sort_passes"], "host_syncs_per_step": st["host_syncs"]},
         "stage_ms_probe": probe_ms,
         "roofline": roofline,
         "cpu_baseline": None,
     }
+    out.update(extra)
     eng.close()
     if not args.no_cpu_baseline:
         cb, ref = cpu_baseline(args.workload)
-        if ref.src.size != st["result_tuples"] or ref.iterations != st["iterations"]:
+        if ref is not None and (ref.src.size != st["result_tuples"] or ref.iterations != st["iterations"]):
             out["cpu_baseline_mismatch"] = True
         out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)

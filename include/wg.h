@@ -78,6 +78,11 @@ typedef struct {
   uint64_t mem_budget_bytes; /* 0 = no limit beyond the device allocator */
   uint64_t force_overflow_at_iter; /* test hook: report a capacity overflow once at this
                                       iteration (1-based) to exercise grow-and-resume */
+  uint32_t radix_digit_bits; /* 0 = the engine's choice (default 8, or autotuned); else
+                                8..11 bits per LSD pass: ceil(2w / bits) passes */
+  uint32_t tile_items;       /* 0 = the engine's choice; 8 = small sort tile; 12 or 16 =
+                                large tile (16 keys per thread for 32-bit keys, 12 for
+                                64-bit keys) */
 } wg_options;
 
 /* Kernel kinds reported in wg_stats.stage_ms / stage_launches / stage_bytes. */
@@ -86,7 +91,7 @@ enum {
   WG_STAGE_JOIN_EMIT = 1,  /* candidate emission into scanned slabs (Section IV-A) */
   WG_STAGE_RADIX_HIST = 2, /* digit histograms (Section V-C); computed inside the kernel
                               that produces the keys, so this kind has no launches */
-  WG_STAGE_RADIX_PASS = 3, /* one stable 8-bit LSD scatter pass (Section V-C) */
+  WG_STAGE_RADIX_PASS = 3, /* one stable LSD pass: count, scan, scatter (Section V-C) */
   WG_STAGE_DEDUP_DIFF = 4, /* fused dedup + set difference (Section IV-B) */
   WG_STAGE_MERGE = 5,      /* disjoint merge-path merge (Section IV-C) */
   WG_STAGE_PREPARE = 6,    /* max-id scan, packing, edge index, result unpack */
@@ -108,13 +113,16 @@ typedef struct {
   uint64_t stage_bytes[WG_NUM_STAGES];   /* algorithmic HBM bytes of each kernel kind */
   uint64_t* delta_sizes;    /* optional caller HOST buffer: |Delta^0| .. |Delta^iterations| */
   uint64_t delta_sizes_cap; /* its capacity in entries (filled up to the capacity) */
+  uint32_t digit_bits;      /* radix digit bits per LSD pass used */
+  uint32_t sort_passes;     /* LSD passes per sort: ceil(key bits / digit_bits) */
 } wg_stats;
 
-typedef struct wg_engine wg_engine; /* per device: buffers, control block, lookback state */
+typedef struct wg_engine wg_engine; /* per device: buffers, control block, sort tuning table */
 typedef struct wg_result wg_result; /* a device-resident fixpoint owned by the caller */
 
-/* Create an engine on HIP device `device`.  Allocates the control block and
- * lookback state; relation buffers grow on demand and are reused across calls. */
+/* Create an engine on HIP device `device`.  Allocates the control block and the sort's
+ * count arrays; relation buffers grow on demand and are reused across calls.  An engine
+ * serves one host thread at a time. */
 wg_status wg_engine_create(int device, wg_engine** out);
 
 /* Free every device allocation of the engine.  Results of the engine become invalid. */
@@ -129,6 +137,34 @@ wg_status wg_tc(wg_engine* engine, const uint32_t* d_src, const uint32_t* d_dst,
 wg_status wg_sg(wg_engine* engine, const uint32_t* d_src, const uint32_t* d_dst, uint64_t m,
                 const wg_options* options, void* stream, wg_result** out, wg_stats* stats);
 
+/* Batched fixpoints: `num_instances` independent instances laid out back to back.
+ * Instance i owns edges d_offsets[i] .. d_offsets[i+1] of (d_src, d_dst); its vertex ids
+ * are local to it.  d_offsets (device, num_instances + 1 entries) starts at 0, does not
+ * decrease and ends at m, else WG_ERR_INVALID_ARG.  The instances run as one fixpoint
+ * over their disjoint union: every key carries the instance in its top bits
+ * (instance | src | dst), so one launch sequence serves all of them and the loop ends
+ * when every instance has reached its fixpoint (iterations = the largest instance's).
+ * The instance bits plus the id field must fit 32 bits (e.g. 4096 instances of up to
+ * 65,536 vertices).  The result holds every instance's fixpoint, sorted by (instance,
+ * src, dst), with local ids; wg_result_offsets gives the instance boundaries.  This
+ * packing of many graphs into one solve is an addition to the paper's method, which
+ * evaluates one query at a time. */
+wg_status wg_tc_batch(wg_engine* engine, uint32_t num_instances, const uint64_t* d_offsets,
+                      const uint32_t* d_src, const uint32_t* d_dst, uint64_t m,
+                      const wg_options* options, void* stream, wg_result** out, wg_stats* stats);
+wg_status wg_sg_batch(wg_engine* engine, uint32_t num_instances, const uint64_t* d_offsets,
+                      const uint32_t* d_src, const uint32_t* d_dst, uint64_t m,
+                      const wg_options* options, void* stream, wg_result** out, wg_stats* stats);
+
+/* Instances of the result (1 for wg_tc / wg_sg). */
+uint32_t wg_result_instances(const wg_result* result);
+
+/* Instance boundaries of the result: offsets_out[i] = first tuple of instance i,
+ * offsets_out[instances] = wg_result_size.  offsets_out is a device or a host pointer
+ * (then the call waits) with capacity >= instances + 1 entries. */
+wg_status wg_result_offsets(const wg_result* result, uint64_t* offsets_out, uint64_t capacity,
+                            void* stream);
+
 /* Number of tuples in the result (for a batch: over all instances). */
 uint64_t wg_result_size(const wg_result* result);
 
@@ -141,6 +177,42 @@ wg_status wg_result_copy(const wg_result* result, uint32_t* src_out, uint32_t* d
 
 /* Release a result handle (the storage belongs to the engine until its next solve). */
 void wg_result_free(wg_result* result);
+
+/* ----- Sort configuration and the autotuner (radix digit width and tile size).
+ * The engine keeps one configuration per key type (32-bit keys when 2w + instance bits
+ * <= 32, else 64-bit).  Defaults: 8-bit digits (Section V-C), large tile, 4 blocks per
+ * compute unit.  Results never depend on the configuration, only time does. */
+typedef struct {
+  uint32_t digit_bits; /* 8..11 bits per LSD pass */
+  uint32_t tile_items; /* keys per thread: 8 (small tile), 16 (32-bit keys) or 12 (64-bit) */
+  uint32_t blocks;     /* blocks of each count and scatter launch, 1..2048 */
+  uint32_t reserved;
+} wg_sort_config;
+
+#define WG_TUNE_MAX_TRIALS 64
+typedef struct {
+  uint32_t trials;        /* configurations timed (besides the one in use before) */
+  uint32_t key_bytes;     /* key type the installed configuration applies to */
+  wg_sort_config best;    /* the configuration installed */
+  double best_ms;         /* its solve time: minimum over the timed repetitions */
+  double before_ms;       /* the same for the configuration in use before the call */
+  wg_sort_config tried[WG_TUNE_MAX_TRIALS];
+  double tried_ms[WG_TUNE_MAX_TRIALS];
+} wg_tune_report;
+
+wg_status wg_get_sort_config(const wg_engine* engine, uint32_t key_bytes, wg_sort_config* out);
+wg_status wg_set_sort_config(wg_engine* engine, uint32_t key_bytes, const wg_sort_config* config);
+
+/* Autotuner: solve the given query (num_instances = 0 with d_offsets = NULL: a single
+ * instance, else a batch as in wg_tc_batch) once per candidate configuration -- digit
+ * bits 8..11 x small or large tile x 2, 4 or 8 blocks per compute unit -- `repeats` timed
+ * times each after one warm-up (0 = 2), and install the fastest for the solve's key
+ * type, keeping the current one unless another is faster.  options' digit and tile
+ * fields are ignored.  report (nullable, host) receives every timing. */
+wg_status wg_autotune(wg_engine* engine, int query, uint32_t num_instances, const uint64_t* d_offsets,
+                      const uint32_t* d_src, const uint32_t* d_dst, uint64_t m,
+                      const wg_options* options, uint32_t repeats, void* stream,
+                      wg_tune_report* report);
 
 /* Static text for a status code. */
 const char* wg_status_string(wg_status status);

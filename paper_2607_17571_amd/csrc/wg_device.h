@@ -47,7 +47,7 @@ struct Ctrl {
   uint32_t limit_hit;    // max_iter reached with a non-empty delta
   uint32_t maxid;        // largest vertex id of the input
   uint32_t force_overflow_at;  // test hook: report a candidate overflow at this iteration
-  uint32_t pad;
+  uint32_t bad_input;          // batched input offsets are malformed
 };
 
 // A halted loop turns every later kernel of the batch into a no-op.
@@ -71,6 +71,15 @@ __device__ __forceinline__ void block_range(uint64_t n, uint32_t T, uint64_t& lo
   if (lo > n) lo = n;
   hi = lo + tpb * T;
   if (hi > n) hi = n;
+}
+
+// Blocks of a G-block launch whose static range is non-empty: exactly blocks
+// [0, active_blocks) own keys.
+__device__ __forceinline__ uint32_t active_blocks(uint64_t n, uint32_t T, uint32_t G) {
+  const uint64_t tiles = (n + T - 1) / T;
+  if (tiles == 0) return 0;
+  const uint64_t tpb = (tiles + G - 1) / G;
+  return (uint32_t)((tiles + tpb - 1) / tpb);
 }
 
 // Items per block range for a grid of `G` blocks (what block_range gives every block but
@@ -261,19 +270,6 @@ __device__ __forceinline__ void multi_upper_bound_at(At at, uint64_t n, const T 
   }
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) out[k] += (at(out[k]) <= v[k]) ? 1 : 0;
-}
-
-// Peers of this lane: lanes of the wave whose 8-bit digit equals this lane's (and that
-// are in `active`).  Eight ballots, one per bit.
-__device__ __forceinline__ uint64_t digit_peers(uint32_t d, uint64_t active) {
-  uint64_t peers = active;
-#pragma unroll
-  for (int bit = 0; bit < 8; ++bit) {
-    const bool set = (d >> bit) & 1u;
-    const uint64_t m = __ballot(set);
-    peers &= set ? m : ~m;
-  }
-  return peers;
 }
 
 // Key field helpers.  `w` < bit width of K always holds (w = 32 only with 64-bit keys).

@@ -63,6 +63,12 @@ struct wg_engine {
   std::string err;
   // per-solve
   uint32_t key_bytes = 4;
+  int key_bits = 32;
+  uint32_t num_inst = 0;                 // batched solve: instances (0: single instance)
+  const uint64_t* d_offsets = nullptr;   // batched solve: edge offsets of the instances
+  const SortCfg* trial = nullptr;        // autotuner: configuration under test
+  SortCfg sort{};            // sort configuration of the current solve
+  SortCfg tune[2];           // per key type (32-bit, 64-bit): defaults or autotuned
   uint64_t cand_cap = 0, full_cap = 0, edge_cap = 0, row_cap = 0, rec_cap = 0;
   uint64_t syncs = 0;
   // stage timing
@@ -86,6 +92,7 @@ struct wg_result {
   int w;
   uint32_t key_bytes;
   const void* keys;
+  uint32_t num_inst;  // instances (1 for a single solve)
 };
 
 namespace {
@@ -258,11 +265,11 @@ void collect_timing(wg_engine* e, wg_stats* st) {
 
 // ----- pipeline pieces
 template <typename K>
-void enqueue_sort(wg_engine* e, const Bufs<K>& b, const uint64_t* n_ptr, int passes) {
+void enqueue_sort(wg_engine* e, const Bufs<K>& b, const uint64_t* n_ptr) {
   // one event pair brackets all passes (each pass is a count, a scan and a scatter launch)
   begin(e, WG_STAGE_RADIX_PASS);
-  launch_sort<K>(e->stream, e->grid, e->d_ctrl, n_ptr, passes, b);
-  end(e, WG_STAGE_RADIX_PASS, passes);
+  launch_sort<K>(e->stream, e->d_ctrl, n_ptr, e->key_bits, e->sort, b);
+  end(e, WG_STAGE_RADIX_PASS, sort_passes(e->key_bits, e->sort.rb));
 }
 
 template <typename K>
@@ -273,7 +280,7 @@ void enqueue_iteration(wg_engine* e, const Bufs<K>& b, int kind, int w, int pass
   begin(e, WG_STAGE_JOIN_EMIT);
   launch_join_emit<K>(e->stream, e->grid, kind, e->d_ctrl, b, w, j);
   end(e, WG_STAGE_JOIN_EMIT);
-  enqueue_sort<K>(e, b, &b.rec[j].C, passes);
+  enqueue_sort<K>(e, b, &b.rec[j].C);
   begin(e, WG_STAGE_DEDUP_DIFF);
   launch_compact<K>(e->stream, e->grid, kModeIter, e->d_ctrl, &b.rec[j].C, b.cand[passes & 1],
                     b.cand[(passes & 1) ^ 1], b, w, j, 0);
@@ -368,9 +375,12 @@ void bytes_model(wg_stats* st, int query, uint32_t kb, int passes, uint64_t m,
 
 template <typename K>
 wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst, uint64_t m,
-              const wg_options& o, int w, wg_stats* st) {
-  const int key_bits = 2 * w;
-  const int passes = (key_bits + kRadixBits - 1) / kRadixBits;
+              const wg_options& o, int w, int ib, wg_stats* st) {
+  e->key_bits = ib + 2 * w;
+  e->sort = e->trial ? *e->trial : e->tune[sizeof(K) == 8];
+  if (o.radix_digit_bits) e->sort.rb = (int)o.radix_digit_bits;
+  if (o.tile_items) e->sort.items = (int)o.tile_items;
+  const int passes = sort_passes(e->key_bits, e->sort.rb);
   e->key_bytes = sizeof(K);
   e->edge_cap = std::max<uint64_t>(e->edge_cap, m);
   e->cand_cap = std::min(std::max<uint64_t>({e->cand_cap, 2 * m, 1u << 20}), kMaxKeys);
@@ -391,9 +401,12 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   // ---- prepare: sort + dedup E, edge index, seed (Section IV-A: E sorted once)
   Bufs<K> b = make_bufs<K>(e);
   begin(e, WG_STAGE_PREPARE);
-  launch_pack<K>(e->stream, e->grid, src, dst, m, w, b.cand[0]);
+  if (e->num_inst)
+    launch_pack_batch<K>(e->stream, e->grid, src, dst, m, w, e->d_offsets, e->num_inst, b.cand[0]);
+  else
+    launch_pack<K>(e->stream, e->grid, src, dst, m, w, b.cand[0]);
   end(e, WG_STAGE_PREPARE);
-  enqueue_sort<K>(e, b, &e->d_ctrl->m_in, passes);
+  enqueue_sort<K>(e, b, &e->d_ctrl->m_in);
   const int mode = query == WG_QUERY_TC ? (kModeEdges | kModeSeed) : kModeEdges;
   begin(e, WG_STAGE_DEDUP_DIFF);
   launch_compact<K>(e->stream, e->grid, mode, e->d_ctrl, &e->d_ctrl->m_in, b.cand[passes & 1],
@@ -413,7 +426,7 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
       begin(e, WG_STAGE_JOIN_EMIT);
       launch_join_emit<K>(e->stream, e->grid, kJoinSGBase, e->d_ctrl, b, w, 0);
       end(e, WG_STAGE_JOIN_EMIT);
-      enqueue_sort<K>(e, b, &b.rec[0].C, passes);
+      enqueue_sort<K>(e, b, &b.rec[0].C);
       begin(e, WG_STAGE_DEDUP_DIFF);
       launch_compact<K>(e->stream, e->grid, kModeSeed, e->d_ctrl, &b.rec[0].C, b.cand[passes & 1],
                         b.cand[(passes & 1) ^ 1], b, w, 0, 0);
@@ -511,6 +524,8 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
     st->result_tuples = F;
     st->field_bits = (uint32_t)w;
     st->key_bytes = (uint32_t)sizeof(K);
+    st->digit_bits = (uint32_t)e->sort.rb;
+    st->sort_passes = (uint32_t)passes;
     std::vector<IterRec> recs((size_t)iters + 1);
     hip_check(e, hipMemcpyAsync(recs.data(), e->rec.p, recs.size() * sizeof(IterRec),
                                 hipMemcpyDeviceToHost, e->stream), "records");
@@ -528,7 +543,24 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   return WG_OK;
 }
 
-wg_status solve(wg_engine* e, int query, const uint32_t* d_src, const uint32_t* d_dst, uint64_t m,
+bool is_device_pointer(const void* p) {
+  hipPointerAttribute_t a{};
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice;
+}
+
+int ceil_log2(uint64_t v) {
+  int b = 0;
+  while ((1ull << b) < v) ++b;
+  return b;
+}
+
+// num == 0: a single instance; else a batch of `num` instances with edge offsets.
+wg_status solve(wg_engine* e, int query, uint32_t num, const uint64_t* d_offsets,
+                const uint32_t* d_src, const uint32_t* d_dst, uint64_t m,
                 const wg_options* opt_in, void* stream, wg_result** out, wg_stats* st) {
   if (!e) return WG_ERR_INVALID_ARG;
   const double t0 = now_ms();
@@ -551,6 +583,14 @@ wg_status solve(wg_engine* e, int query, const uint32_t* d_src, const uint32_t* 
     e->err = "NULL edge array with m > 0";
     return WG_ERR_INVALID_ARG;
   }
+  if (num > 0 && !d_offsets) {
+    e->err = "NULL offsets for a batch";
+    return WG_ERR_INVALID_ARG;
+  }
+  if (num > (1u << 24)) {
+    e->err = "more than 2^24 instances";
+    return WG_ERR_INVALID_ARG;
+  }
   if (m >= kMaxKeys / 2) {
     e->err = "too many edges";
     return WG_ERR_INVALID_ARG;
@@ -558,6 +598,15 @@ wg_status solve(wg_engine* e, int query, const uint32_t* d_src, const uint32_t* 
   if (o.radix_field_bits != 0 && o.radix_field_bits != 16 && o.radix_field_bits != 24 &&
       o.radix_field_bits != 32) {
     e->err = "radix_field_bits must be 0, 16, 24 or 32";
+    return WG_ERR_INVALID_ARG;
+  }
+  if (o.radix_digit_bits != 0 &&
+      (o.radix_digit_bits < (uint32_t)kRadixBitsMin || o.radix_digit_bits > (uint32_t)kRadixBitsMax)) {
+    e->err = "radix_digit_bits must be 0 or 8..11";
+    return WG_ERR_INVALID_ARG;
+  }
+  if (o.tile_items != 0 && o.tile_items != 8 && o.tile_items != 12 && o.tile_items != 16) {
+    e->err = "tile_items must be 0, 8, 12 or 16";
     return WG_ERR_INVALID_ARG;
   }
   if (o.loop_mode > WG_LOOP_HOST || (o.flags & ~(WG_SG_IRREFLEXIVE | WG_STAGE_TIMING))) {
@@ -582,6 +631,9 @@ wg_status solve(wg_engine* e, int query, const uint32_t* d_src, const uint32_t* 
     e->timing = (o.flags & WG_STAGE_TIMING) != 0;
     e->timing_mask = o.timing_stages ? o.timing_stages : 0xFFFFFFFFu;
     e->n_events = 0;
+    e->num_inst = num;
+    e->d_offsets = d_offsets;
+    const int ib = num > 1 ? ceil_log2(num) : 0;
     if (m == 0) {
       if (st && st->delta_sizes && st->delta_sizes_cap) st->delta_sizes[0] = 0;
     } else {
@@ -589,9 +641,14 @@ wg_status solve(wg_engine* e, int query, const uint32_t* d_src, const uint32_t* 
       std::memset(e->h_up, 0, sizeof(Ctrl));
       hip_check(e, hipMemcpyAsync(e->d_ctrl, e->h_up, sizeof(Ctrl), hipMemcpyHostToDevice, e->stream), "upload");
       launch_max_id(e->stream, e->grid, e->d_ctrl, d_src, d_dst, m);
+      if (num) launch_check_offsets(e->stream, e->grid, e->d_ctrl, d_offsets, num, m);
       hip_check(e, hipMemcpyAsync(&e->h_rb[0].c, e->d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, e->stream),
                 "readback");
       sync_stream(e);
+      if (e->h_rb[0].c.bad_input) {
+        e->err = "batch offsets must start at 0, not decrease and end at m";
+        return WG_ERR_INVALID_ARG;
+      }
       int w = field_bits(e->h_rb[0].c.maxid);
       if (o.radix_field_bits) {
         if ((int)o.radix_field_bits < w) {
@@ -600,11 +657,16 @@ wg_status solve(wg_engine* e, int query, const uint32_t* d_src, const uint32_t* 
         }
         w = (int)o.radix_field_bits;
       }
-      wg_status r = (2 * w <= 32) ? run<uint32_t>(e, query, d_src, d_dst, m, o, w, st)
-                                  : run<uint64_t>(e, query, d_src, d_dst, m, o, w, st);
+      if (ib + w > 32) {
+        e->err = "batch too wide: instance bits plus the id field exceed 32 bits";
+        return WG_ERR_INVALID_ARG;
+      }
+      wg_status r = (ib + 2 * w <= 32) ? run<uint32_t>(e, query, d_src, d_dst, m, o, w, ib, st)
+                                       : run<uint64_t>(e, query, d_src, d_dst, m, o, w, ib, st);
       if (r != WG_OK) return r;
     }
-    wg_result* res = new wg_result{e, e->generation, e->res_n, e->res_w, e->key_bytes, e->res_keys};
+    wg_result* res = new wg_result{e, e->generation, e->res_n, e->res_w, e->key_bytes, e->res_keys,
+                                   num ? num : 1u};
     *out = res;
     if (st) {
       st->host_syncs = e->syncs;
@@ -635,13 +697,18 @@ wg_status wg_engine_create(int device, wg_engine** out) {
     const int cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     e->grid.stream = cu * 8;
     e->grid.scan = std::min(cu * 4, kScanBlocksMax);
+    for (SortCfg& t : e->tune) {
+      t.rb = 8;
+      t.items = 16;
+      t.blocks = std::min(cu * 4, kRadixBlocksMax);
+    }
     hip_check(e, hipMalloc((void**)&e->d_ctrl, sizeof(Ctrl)), "hipMalloc");
     hip_check(e, hipHostMalloc((void**)&e->h_up, sizeof(Ctrl)), "hipHostMalloc");
     hip_check(e, hipHostMalloc((void**)&e->h_rb, 2 * sizeof(Readback)), "hipHostMalloc");
     hip_check(e, hipMalloc((void**)&e->d_jtot, sizeof(uint64_t) * kScanBlocksMax), "hipMalloc");
     hip_check(e, hipMalloc((void**)&e->d_bcnt, sizeof(uint64_t) * kScanBlocksMax), "hipMalloc");
-    hip_check(e, hipMalloc((void**)&e->d_rcnt, sizeof(uint32_t) * kRadix * kScanBlocksMax), "hipMalloc");
-    hip_check(e, hipMalloc((void**)&e->d_rtot, sizeof(uint32_t) * kRadix), "hipMalloc");
+    hip_check(e, hipMalloc((void**)&e->d_rcnt, sizeof(uint32_t) * kRadixMax * kRadixBlocksMax), "hipMalloc");
+    hip_check(e, hipMalloc((void**)&e->d_rtot, sizeof(uint32_t) * kRadixMax), "hipMalloc");
     hip_check(e, hipMemset(e->d_ctrl, 0, sizeof(Ctrl)), "hipMemset");
     for (int s = 0; s < 2; ++s)
       hip_check(e, hipEventCreateWithFlags(&e->ev_batch[s], hipEventDisableTiming), "hipEventCreate");
@@ -690,12 +757,194 @@ void wg_engine_destroy(wg_engine* e) {
 
 wg_status wg_tc(wg_engine* e, const uint32_t* d_src, const uint32_t* d_dst, uint64_t m,
                 const wg_options* o, void* stream, wg_result** out, wg_stats* st) {
-  return solve(e, WG_QUERY_TC, d_src, d_dst, m, o, stream, out, st);
+  return solve(e, WG_QUERY_TC, 0, nullptr, d_src, d_dst, m, o, stream, out, st);
 }
 
 wg_status wg_sg(wg_engine* e, const uint32_t* d_src, const uint32_t* d_dst, uint64_t m,
                 const wg_options* o, void* stream, wg_result** out, wg_stats* st) {
-  return solve(e, WG_QUERY_SG, d_src, d_dst, m, o, stream, out, st);
+  return solve(e, WG_QUERY_SG, 0, nullptr, d_src, d_dst, m, o, stream, out, st);
+}
+
+wg_status wg_tc_batch(wg_engine* e, uint32_t num_instances, const uint64_t* d_offsets,
+                      const uint32_t* d_src, const uint32_t* d_dst, uint64_t m, const wg_options* o,
+                      void* stream, wg_result** out, wg_stats* st) {
+  if (e && num_instances == 0) {
+    e->err = "a batch needs at least one instance";
+    return WG_ERR_INVALID_ARG;
+  }
+  return solve(e, WG_QUERY_TC, num_instances, d_offsets, d_src, d_dst, m, o, stream, out, st);
+}
+
+wg_status wg_sg_batch(wg_engine* e, uint32_t num_instances, const uint64_t* d_offsets,
+                      const uint32_t* d_src, const uint32_t* d_dst, uint64_t m, const wg_options* o,
+                      void* stream, wg_result** out, wg_stats* st) {
+  if (e && num_instances == 0) {
+    e->err = "a batch needs at least one instance";
+    return WG_ERR_INVALID_ARG;
+  }
+  return solve(e, WG_QUERY_SG, num_instances, d_offsets, d_src, d_dst, m, o, stream, out, st);
+}
+
+uint32_t wg_result_instances(const wg_result* r) { return r ? r->num_inst : 0; }
+
+wg_status wg_get_sort_config(const wg_engine* e, uint32_t key_bytes, wg_sort_config* out) {
+  if (!e || !out || (key_bytes != 4 && key_bytes != 8)) return WG_ERR_INVALID_ARG;
+  const SortCfg& c = e->tune[key_bytes == 8];
+  out->digit_bits = (uint32_t)c.rb;
+  out->tile_items = (uint32_t)(c.items == 8 ? 8 : (key_bytes == 4 ? 16 : 12));
+  out->blocks = (uint32_t)c.blocks;
+  out->reserved = 0;
+  return WG_OK;
+}
+
+wg_status wg_set_sort_config(wg_engine* e, uint32_t key_bytes, const wg_sort_config* cfg) {
+  if (!e) return WG_ERR_INVALID_ARG;
+  if (!cfg || (key_bytes != 4 && key_bytes != 8) || cfg->digit_bits < (uint32_t)kRadixBitsMin ||
+      cfg->digit_bits > (uint32_t)kRadixBitsMax ||
+      (cfg->tile_items != 8 && cfg->tile_items != 12 && cfg->tile_items != 16) || cfg->blocks == 0 ||
+      cfg->blocks > (uint32_t)kRadixBlocksMax) {
+    e->err = "sort config: key_bytes 4 or 8, digit_bits 8..11, tile_items 8/12/16, blocks 1..2048";
+    return WG_ERR_INVALID_ARG;
+  }
+  SortCfg& c = e->tune[key_bytes == 8];
+  c.rb = (int)cfg->digit_bits;
+  c.items = (int)cfg->tile_items;
+  c.blocks = (int)cfg->blocks;
+  return WG_OK;
+}
+
+wg_status wg_autotune(wg_engine* e, int query, uint32_t num_instances, const uint64_t* d_offsets,
+                      const uint32_t* d_src, const uint32_t* d_dst, uint64_t m, const wg_options* opt_in,
+                      uint32_t repeats, void* stream, wg_tune_report* rep) {
+  if (!e) return WG_ERR_INVALID_ARG;
+  if (query != WG_QUERY_TC && query != WG_QUERY_SG) {
+    e->err = "query must be WG_QUERY_TC or WG_QUERY_SG";
+    return WG_ERR_INVALID_ARG;
+  }
+  wg_options o{};
+  o.struct_size = sizeof(wg_options);
+  if (opt_in) {
+    if (opt_in->struct_size < 8 || opt_in->struct_size > sizeof(wg_options)) {
+      e->err = "wg_options.struct_size is not a known size";
+      return WG_ERR_INVALID_ARG;
+    }
+    std::memcpy(&o, opt_in, opt_in->struct_size);
+  }
+  o.radix_digit_bits = 0;  // the trial configuration decides
+  o.tile_items = 0;
+  o.flags &= ~WG_STAGE_TIMING;
+  if (repeats == 0) repeats = 2;
+  // one untimed solve: allocations, the key type
+  wg_stats st{};
+  wg_result* res = nullptr;
+  wg_status r = solve(e, query, num_instances, d_offsets, d_src, d_dst, m, &o, stream, &res, &st);
+  wg_result_free(res);
+  if (r != WG_OK) return r;
+  const uint32_t kb = st.key_bytes ? st.key_bytes : 4;
+  const SortCfg before = e->tune[kb == 8];
+  int cu = 256;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, e->device) == hipSuccess && prop.multiProcessorCount > 0)
+    cu = prop.multiProcessorCount;
+  std::vector<SortCfg> cands;
+  for (int rb = kRadixBitsMin; rb <= kRadixBitsMax; ++rb)
+    for (int items : {8, 16})
+      for (int mult : {2, 4, 8}) {
+        SortCfg c;
+        c.rb = rb;
+        c.items = items;
+        c.blocks = std::min(cu * mult, kRadixBlocksMax);
+        cands.push_back(c);
+      }
+  auto time_cfg = [&](const SortCfg& c, double& best) -> wg_status {
+    best = 1e300;
+    e->trial = &c;
+    for (uint32_t i = 0; i <= repeats; ++i) {
+      wg_stats s2{};
+      wg_result* rr = nullptr;
+      const wg_status q = solve(e, query, num_instances, d_offsets, d_src, d_dst, m, &o, stream, &rr, &s2);
+      wg_result_free(rr);
+      if (q != WG_OK) {
+        e->trial = nullptr;
+        return q;
+      }
+      if (i > 0) best = std::min(best, s2.solve_ms);  // the first run of a configuration warms it
+    }
+    e->trial = nullptr;
+    return WG_OK;
+  };
+  double before_ms = 0;
+  r = time_cfg(before, before_ms);
+  if (r != WG_OK) return r;
+  SortCfg best_cfg = before;
+  double best_ms = before_ms;
+  if (rep) {
+    std::memset(rep, 0, sizeof(*rep));
+    rep->key_bytes = kb;
+    rep->before_ms = before_ms;
+  }
+  for (const SortCfg& c : cands) {
+    double ms = 0;
+    r = time_cfg(c, ms);
+    if (r != WG_OK) return r;
+    if (rep && rep->trials < WG_TUNE_MAX_TRIALS) {
+      wg_sort_config& t = rep->tried[rep->trials];
+      t.digit_bits = (uint32_t)c.rb;
+      t.tile_items = (uint32_t)(c.items == 8 ? 8 : (kb == 4 ? 16 : 12));
+      t.blocks = (uint32_t)c.blocks;
+      rep->tried_ms[rep->trials] = ms;
+      rep->trials++;
+    }
+    if (ms < best_ms) {
+      best_ms = ms;
+      best_cfg = c;
+    }
+  }
+  e->tune[kb == 8] = best_cfg;
+  if (rep) {
+    rep->best.digit_bits = (uint32_t)best_cfg.rb;
+    rep->best.tile_items = (uint32_t)(best_cfg.items == 8 ? 8 : (kb == 4 ? 16 : 12));
+    rep->best.blocks = (uint32_t)best_cfg.blocks;
+    rep->best_ms = best_ms;
+  }
+  return WG_OK;
+}
+
+wg_status wg_result_offsets(const wg_result* r, uint64_t* offsets_out, uint64_t capacity, void* stream) {
+  if (!r || !r->engine) return WG_ERR_INVALID_ARG;
+  wg_engine* e = r->engine;
+  if (r->generation != e->generation) {
+    e->err = "result is stale: the engine ran another solve";
+    return WG_ERR_STALE;
+  }
+  if (!offsets_out || capacity < (uint64_t)r->num_inst + 1) {
+    e->err = "offsets array missing or shorter than instances + 1";
+    return WG_ERR_INVALID_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    hip_check(e, hipSetDevice(e->device), "hipSetDevice");
+    const bool host = !is_device_pointer(offsets_out);
+    uint64_t* dst = offsets_out;
+    if (host) hip_check(e, hipMalloc((void**)&dst, ((uint64_t)r->num_inst + 1) * 8), "hipMalloc");
+    if (r->key_bytes == 4)
+      launch_offsets<uint32_t>(s, e->grid, (const uint32_t*)r->keys, r->n, 2 * r->w, r->num_inst, dst);
+    else
+      launch_offsets<uint64_t>(s, e->grid, (const uint64_t*)r->keys, r->n, 2 * r->w, r->num_inst, dst);
+    if (host) {
+      hipError_t e1 = hipMemcpyAsync(offsets_out, dst, ((uint64_t)r->num_inst + 1) * 8,
+                                     hipMemcpyDeviceToHost, s);
+      hipError_t e2 = hipStreamSynchronize(s);
+      (void)hipFree(dst);
+      hip_check(e, e1, "copy");
+      hip_check(e, e2, "sync");
+    } else {
+      hip_check(e, hipGetLastError(), "offsets launch");
+    }
+    return WG_OK;
+  } catch (const Fail& f) {
+    return f.st;
+  }
 }
 
 uint64_t wg_result_size(const wg_result* r) { return r ? r->n : 0; }
@@ -716,14 +965,7 @@ wg_status wg_result_copy(const wg_result* r, uint32_t* src_out, uint32_t* dst_ou
   hipStream_t s = (hipStream_t)stream;
   try {
     hip_check(e, hipSetDevice(e->device), "hipSetDevice");
-    hipPointerAttribute_t a{};
-    bool host = false;
-    if (hipPointerGetAttributes(&a, src_out) != hipSuccess) {
-      (void)hipGetLastError();
-      host = true;
-    } else {
-      host = a.type != hipMemoryTypeDevice;
-    }
+    const bool host = !is_device_pointer(src_out);
     Grid g = e->grid;
     if (!host) {
       if (r->key_bytes == 4)

@@ -39,6 +39,32 @@ __global__ __launch_bounds__(kBlock) void k_max_id(Ctrl* ctrl, const uint32_t* _
   if (lane_id() == 0 && mx) atomicMax(&ctrl->maxid, mx);
 }
 
+// Batched input: instance i owns edges [offsets[i], offsets[i+1]).  Malformed offsets
+// (not starting at 0, decreasing, or not ending at m) set ctrl->bad_input.
+__global__ __launch_bounds__(kBlock) void k_check_offsets(Ctrl* ctrl, const uint64_t* __restrict__ offsets,
+                                                          uint32_t num, uint64_t m) {
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < num;
+       i += (uint64_t)gridDim.x * kBlock) {
+    const bool bad = offsets[i] > offsets[i + 1] || (i == 0 && offsets[0] != 0) ||
+                     (i + 1 == num && offsets[num] != m);
+    if (bad) ctrl->bad_input = 1;
+  }
+}
+
+// key = inst << 2w | src << w | dst, with inst the instance owning edge i: the number of
+// instance ends offsets[1..num] at or below i.
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_pack_batch(const uint32_t* __restrict__ src,
+                                                       const uint32_t* __restrict__ dst, uint64_t m,
+                                                       int w, const uint64_t* __restrict__ offsets,
+                                                       uint32_t num, K* __restrict__ keys) {
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < m;
+       i += (uint64_t)gridDim.x * kBlock) {
+    const K inst = (K)upper_bound<uint64_t>(offsets + 1, num, i);
+    keys[i] = (((inst << w) | (K)src[i]) << w) | (K)dst[i];
+  }
+}
+
 template <typename K>
 __global__ __launch_bounds__(kBlock) void k_pack(const uint32_t* __restrict__ src,
                                                  const uint32_t* __restrict__ dst, uint64_t m,
@@ -248,136 +274,232 @@ __global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int
 }
 
 // ---------------------------------------------------------------------------
-// LSD radix sort (Section V-C): 8 bits per pass, dst field first, every pass stable.
+// LSD radix sort (Section V-C): RB bits per pass, dst field first, every pass stable.
 //
 // A pass is three launches: count (block b counts the digits of a static contiguous
 // range of tiles), scan (one block per digit turns the per-block counts into per-block
 // offsets) and scatter (block b re-reads its range tile by tile, ranks each tile stably
-// in LDS and writes every key to its final position).  Each block writes long per-digit
-// runs of consecutive positions.
+// in LDS and writes every key to its final position).  Each block writes per-digit runs
+// of consecutive positions.  RB is 8 in the paper; wider digits (up to 11 bits) trade
+// shorter runs for fewer passes and are picked by the autotuner per key width.
+//
+// Both range kernels keep the next tile's loads in flight while they work on the current
+// one.  A wave whose keys share one digit (common in the passes over the src field,
+// whose input is nearly grouped) takes one LDS update instead of RB ballots.
 // ---------------------------------------------------------------------------
+template <int RB>
+struct RadixShape {
+  static constexpr int R = 1 << RB;
+  // digits owned by each thread for per-digit work: thread t owns [t*DPT, t*DPT+DPT)
+  static constexpr int DPT = R >= kBlock ? R / kBlock : 1;
+  static constexpr int OWNERS = R >= kBlock ? kBlock : R;
+};
+
 template <typename K, int ITEMS>
+__device__ __forceinline__ void load_tile_striped(const K* __restrict__ in, uint64_t base,
+                                                  uint64_t hi, K (&key)[ITEMS]) {
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    const uint64_t i = base + (uint64_t)k * kBlock + threadIdx.x;
+    key[k] = i < hi ? in[i] : K(0);
+  }
+}
+
+// Wave-striped layout of the scatter: wave `wid` owns a contiguous run of 64*ITEMS keys.
+template <typename K, int ITEMS>
+__device__ __forceinline__ void load_tile_wave(const K* __restrict__ in, uint64_t wbase,
+                                               uint64_t hi, K (&key)[ITEMS]) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    const uint64_t i = wbase + (uint64_t)k * kWave + lane;
+    key[k] = i < hi ? in[i] : K(0);
+  }
+}
+
+template <typename K, int RB, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_radix_count(Ctrl* ctrl, const uint64_t* n_ptr,
-                                                        const K* __restrict__ in, int pass,
+                                                        const K* __restrict__ in, int shift,
                                                         uint32_t* __restrict__ cnt) {
+  using S = RadixShape<RB>;
   constexpr uint32_t T = kBlock * ITEMS;
-  __shared__ uint32_t s_cnt[kRadix];
+  __shared__ uint32_t s_cnt[S::R];
   if (halted(ctrl)) return;
   const uint64_t n = *n_ptr;
   uint64_t lo, hi;
   block_range(n, T, lo, hi);
-  s_cnt[threadIdx.x] = 0;
+  if (lo >= hi) return;  // past the active blocks: the scan reads none of their counts
+  for (int d = threadIdx.x; d < S::R; d += kBlock) s_cnt[d] = 0;
   __syncthreads();
-  const int shift = pass * kRadixBits;
   const uint64_t lt = lanemask_lt();
+  K cur[ITEMS];
+  load_tile_striped<K, ITEMS>(in, lo, hi, cur);
   for (uint64_t base = lo; base < hi; base += T) {
-    K key[ITEMS];
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      const uint64_t i = base + (uint64_t)k * kBlock + threadIdx.x;
-      key[k] = i < hi ? in[i] : K(0);
-    }
+    K nxt[ITEMS];
+    if (base + T < hi) load_tile_striped<K, ITEMS>(in, base + T, hi, nxt);
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
       const bool valid = base + (uint64_t)k * kBlock + threadIdx.x < hi;
-      const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
-      const uint64_t peers = digit_peers(d, __ballot(valid));
-      if (valid && (peers & lt) == 0) atomicAdd(&s_cnt[d], (uint32_t)__popcll(peers));
+      const uint32_t d = (uint32_t)(cur[k] >> shift) & (S::R - 1);
+      const uint64_t active = __ballot(valid);
+      const uint32_t first = __builtin_amdgcn_readfirstlane(d);
+      if (__ballot(valid && d == first) == active) {
+        if (valid && (active & lt) == 0) atomicAdd(&s_cnt[first], (uint32_t)__popcll(active));
+      } else if (valid) {
+        atomicAdd(&s_cnt[d], 1u);
+      }
     }
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) cur[k] = nxt[k];
   }
   __syncthreads();
-  cnt[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x] = s_cnt[threadIdx.x];
+  for (int d = threadIdx.x; d < S::R; d += kBlock) cnt[(uint64_t)d * gridDim.x + blockIdx.x] = s_cnt[d];
 }
 
 // One block per digit: per-block counts of the digit -> exclusive per-block offsets (in
-// place); tot[d] = the digit's total.
-__global__ __launch_bounds__(kBlock) void k_radix_scan(Ctrl* ctrl, uint32_t* __restrict__ cnt,
+// place); tot[d] = the digit's total.  Only the blocks that own keys wrote counts.
+__global__ __launch_bounds__(kBlock) void k_radix_scan(Ctrl* ctrl, const uint64_t* n_ptr, uint32_t T,
+                                                       uint32_t* __restrict__ cnt,
                                                        uint32_t* __restrict__ tot, int G) {
   __shared__ uint32_t s_wave[kWavesPerBlock];
   if (halted(ctrl)) return;
+  const int GA = (int)active_blocks(*n_ptr, T, (uint32_t)G);
   uint32_t* row = cnt + (uint64_t)blockIdx.x * G;
   uint32_t carry = 0;
-  for (int base = 0; base < G; base += kBlock) {
+  for (int base = 0; base < GA; base += kBlock) {
     const int i = base + threadIdx.x;
-    const uint32_t v = i < G ? row[i] : 0u;
+    const uint32_t v = i < GA ? row[i] : 0u;
     uint32_t total;
     const uint32_t ex = block_excl_scan<uint32_t>(v, s_wave, total);
-    if (i < G) row[i] = carry + ex;
+    if (i < GA) row[i] = carry + ex;
     carry += total;
   }
   if (threadIdx.x == 0) tot[blockIdx.x] = carry;
 }
 
-template <typename K, int ITEMS>
+// Lanes of the wave (within `active`) whose RB-bit digit equals this lane's: one ballot
+// per bit.
+template <int RB>
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, uint64_t active) {
+  uint64_t peers = active;
+#pragma unroll
+  for (int bit = 0; bit < RB; ++bit) {
+    const bool set = (d >> bit) & 1u;
+    const uint64_t m = __ballot(set);
+    peers &= set ? m : ~m;
+  }
+  return peers;
+}
+
+template <typename K, int RB, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(Ctrl* ctrl, const uint64_t* n_ptr,
                                                           const K* __restrict__ in,
-                                                          K* __restrict__ out, int pass,
+                                                          K* __restrict__ out, int shift,
                                                           const uint32_t* __restrict__ off,
                                                           const uint32_t* __restrict__ tot) {
+  using S = RadixShape<RB>;
+  constexpr int DPT = S::DPT;
   constexpr uint32_t T = kBlock * ITEMS;
+  static_assert(T <= 65535, "tile offsets are kept in 16 bits");
   __shared__ K s_keys[T];
-  __shared__ uint32_t s_cnt[kWavesPerBlock][kRadix];
-  __shared__ uint32_t s_loc[kRadix];
-  __shared__ uint64_t s_run[kRadix];
+  __shared__ uint16_t s_cnt[kWavesPerBlock][S::R];  // per-wave digit counts, then offsets
+  __shared__ uint16_t s_loc[S::R];                  // first tile position of each digit
+  __shared__ uint32_t s_run[S::R];                  // next output position of each digit
   __shared__ uint32_t s_wave[kWavesPerBlock];
   if (halted(ctrl)) return;
   const uint64_t n = *n_ptr;
   uint64_t lo, hi;
   block_range(n, T, lo, hi);
   if (lo >= hi) return;
-  const int shift = pass * kRadixBits;
   const int tid = threadIdx.x;
   const int wid = tid / kWave;
   const int lane = lane_id();
   const uint64_t lt = lanemask_lt();
+  const bool owner = tid < S::OWNERS;
   {
     // first position of each digit for this block: digit base + earlier blocks' keys
-    const uint32_t t = tot[tid];
+    uint32_t t[DPT];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) {
+      t[i] = owner ? tot[tid * DPT + i] : 0u;
+      sum += t[i];
+    }
     uint32_t all;
-    const uint32_t base = block_excl_scan<uint32_t>(t, s_wave, all);
-    s_run[tid] = (uint64_t)base + off[(uint64_t)tid * gridDim.x + blockIdx.x];
+    uint32_t base = block_excl_scan<uint32_t>(sum, s_wave, all);
+    if (owner) {
+#pragma unroll
+      for (int i = 0; i < DPT; ++i) {
+        const int d = tid * DPT + i;
+        s_run[d] = base + off[(uint64_t)d * gridDim.x + blockIdx.x];
+        base += t[i];
+      }
+    }
   }
+  K cur[ITEMS];
+  load_tile_wave<K, ITEMS>(in, lo + (uint64_t)wid * (ITEMS * kWave), hi, cur);
   for (uint64_t tbase = lo; tbase < hi; tbase += T) {
-    for (int jj = tid; jj < kWavesPerBlock * kRadix; jj += kBlock) (&s_cnt[0][0])[jj] = 0;
+    K nxt[ITEMS];
+    if (tbase + T < hi) load_tile_wave<K, ITEMS>(in, tbase + T + (uint64_t)wid * (ITEMS * kWave), hi, nxt);
+    for (int jj = tid; jj < kWavesPerBlock * S::R; jj += kBlock) (&s_cnt[0][0])[jj] = 0;
     __syncthreads();
-    // wave-striped: wave `wid` owns a contiguous run of 64*ITEMS keys
     const uint64_t wbase = tbase + (uint64_t)wid * (ITEMS * kWave);
-    K key[ITEMS];
     uint32_t rank[ITEMS];
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
-      const uint64_t idx = wbase + (uint64_t)k * kWave + lane;
-      key[k] = idx < hi ? in[idx] : K(0);
-    }
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
       const bool valid = wbase + (uint64_t)k * kWave + lane < hi;
-      const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
-      const uint64_t peers = digit_peers(d, __ballot(valid));
-      const uint32_t below = __popcll(peers & lt);
-      uint32_t before = 0;
-      if (valid) before = s_cnt[wid][d];
-      if (valid && below == 0) s_cnt[wid][d] = before + __popcll(peers);
-      rank[k] = before + below;
+      const uint32_t d = (uint32_t)(cur[k] >> shift) & (S::R - 1);
+      const uint64_t active = __ballot(valid);
+      const uint32_t first = __builtin_amdgcn_readfirstlane(d);
+      if (__ballot(valid && d == first) == active) {
+        // every active lane holds digit `first`
+        const uint32_t before = s_cnt[wid][first];
+        rank[k] = before + (uint32_t)__popcll(active & lt);
+        if (valid && (active & lt) == 0) s_cnt[wid][first] = (uint16_t)(before + __popcll(active));
+      } else {
+        const uint64_t peers = digit_peers<RB>(d, active);
+        const uint32_t below = __popcll(peers & lt);
+        uint32_t before = 0;
+        if (valid) before = s_cnt[wid][d];
+        if (valid && below == 0) s_cnt[wid][d] = (uint16_t)(before + __popcll(peers));
+        rank[k] = before + below;
+      }
     }
     __syncthreads();
-    // thread `tid` owns digit `tid`: per-wave exclusive offsets and the tile total
-    uint32_t tile_cnt = 0;
+    // owned digits: per-wave exclusive offsets, tile totals, tile-local digit starts
+    uint32_t tile_cnt[DPT];
+    uint32_t own_sum = 0;
 #pragma unroll
-    for (int w2 = 0; w2 < kWavesPerBlock; ++w2) {
-      const uint32_t c = s_cnt[w2][tid];
-      s_cnt[w2][tid] = tile_cnt;
-      tile_cnt += c;
+    for (int i = 0; i < DPT; ++i) {
+      const int d = tid * DPT + i;
+      uint32_t c_run = 0;
+      if (owner) {
+#pragma unroll
+        for (int w2 = 0; w2 < kWavesPerBlock; ++w2) {
+          const uint32_t c = s_cnt[w2][d];
+          s_cnt[w2][d] = (uint16_t)c_run;
+          c_run += c;
+        }
+      }
+      tile_cnt[i] = c_run;
+      own_sum += c_run;
     }
     uint32_t total;
-    s_loc[tid] = block_excl_scan<uint32_t>(tile_cnt, s_wave, total);
+    uint32_t start = block_excl_scan<uint32_t>(own_sum, s_wave, total);
+    if (owner) {
+#pragma unroll
+      for (int i = 0; i < DPT; ++i) {
+        s_loc[tid * DPT + i] = (uint16_t)start;
+        start += tile_cnt[i];
+      }
+    }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
       if (wbase + (uint64_t)k * kWave + lane < hi) {
-        const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
-        const uint32_t pos = s_loc[d] + s_cnt[wid][d] + rank[k];
-        if (pos < T) s_keys[pos] = key[k];
+        const uint32_t d = (uint32_t)(cur[k] >> shift) & (S::R - 1);
+        const uint32_t pos = (uint32_t)s_loc[d] + s_cnt[wid][d] + rank[k];
+        if (pos < T) s_keys[pos] = cur[k];
       }
     }
     __syncthreads();
@@ -387,13 +509,18 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(Ctrl* ctrl, const uint
       const uint32_t jj = (uint32_t)k * kBlock + tid;
       if (jj < tile_n) {
         const K kk = s_keys[jj];
-        const uint32_t d = (uint32_t)(kk >> shift) & (kRadix - 1);
-        const uint64_t pos = s_run[d] + (jj - s_loc[d]);
+        const uint32_t d = (uint32_t)(kk >> shift) & (S::R - 1);
+        const uint64_t pos = (uint64_t)s_run[d] + (jj - s_loc[d]);
         if (pos < n) out[pos] = kk;
       }
     }
     __syncthreads();
-    s_run[tid] += tile_cnt;
+    if (owner) {
+#pragma unroll
+      for (int i = 0; i < DPT; ++i) s_run[tid * DPT + i] += tile_cnt[i];
+    }
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) cur[k] = nxt[k];
   }
 }
 
@@ -745,6 +872,15 @@ __global__ __launch_bounds__(kBlock) void k_unpack(const K* __restrict__ keys, u
   }
 }
 
+// Per-instance result offsets: out[i] = first key of instance i, out[num] = n.
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_offsets(const K* __restrict__ keys, uint64_t n, int shift,
+                                                    uint32_t num, uint64_t* __restrict__ out) {
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i <= num;
+       i += (uint64_t)gridDim.x * kBlock)
+    out[i] = (i == num) ? n : lower_bound<K>(keys, n, (K)i << shift);
+}
+
 __global__ void k_resume(Ctrl* ctrl, uint64_t cand_cap, uint64_t full_cap, uint32_t clear_hook) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     ctrl->cand_cap = cand_cap;
@@ -765,6 +901,26 @@ static inline int stream_blocks(const Grid& g, uint64_t n) {
 void launch_max_id(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint32_t* src,
                    const uint32_t* dst, uint64_t m) {
   hipLaunchKernelGGL(k_max_id, dim3(stream_blocks(g, m)), dim3(kBlock), 0, s, ctrl, src, dst, m);
+}
+
+void launch_check_offsets(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint64_t* offsets,
+                          uint32_t num, uint64_t m) {
+  hipLaunchKernelGGL(k_check_offsets, dim3(stream_blocks(g, num)), dim3(kBlock), 0, s, ctrl, offsets,
+                     num, m);
+}
+
+template <typename K>
+void launch_pack_batch(hipStream_t s, const Grid& g, const uint32_t* src, const uint32_t* dst,
+                       uint64_t m, int w, const uint64_t* offsets, uint32_t num, K* keys) {
+  hipLaunchKernelGGL(k_pack_batch<K>, dim3(stream_blocks(g, m)), dim3(kBlock), 0, s, src, dst, m, w,
+                     offsets, num, keys);
+}
+
+template <typename K>
+void launch_offsets(hipStream_t s, const Grid& g, const K* keys, uint64_t n, int shift, uint32_t num,
+                    uint64_t* out) {
+  hipLaunchKernelGGL(k_offsets<K>, dim3(stream_blocks(g, (uint64_t)num + 1)), dim3(kBlock), 0, s, keys,
+                     n, shift, num, out);
 }
 
 template <typename K>
@@ -795,18 +951,42 @@ void launch_join_emit(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const 
     hipLaunchKernelGGL((k_join_emit<K, kJoinSGBase, kEmitItems>), dim3(g.stream), dim3(kBlock), 0, s, ctrl, b, w, j, g.scan);
 }
 
-template <typename K>
-void launch_sort(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint64_t* n_ptr, int passes,
-                 const Bufs<K>& b) {
-  constexpr int ITEMS = pass_items<K>();
+template <typename K, int RB, int ITEMS>
+void sort_impl(hipStream_t s, Ctrl* ctrl, const uint64_t* n_ptr, int key_bits, int G,
+               const Bufs<K>& b) {
+  constexpr uint32_t T = kBlock * ITEMS;
+  const int passes = sort_passes(key_bits, RB);
   for (int p = 0; p < passes; ++p) {
     const K* in = b.cand[p & 1];
     K* out = b.cand[(p + 1) & 1];
-    hipLaunchKernelGGL((k_radix_count<K, ITEMS>), dim3(g.scan), dim3(kBlock), 0, s, ctrl, n_ptr, in,
-                       p, b.rcnt);
-    hipLaunchKernelGGL(k_radix_scan, dim3(kRadix), dim3(kBlock), 0, s, ctrl, b.rcnt, b.rtot, g.scan);
-    hipLaunchKernelGGL((k_radix_scatter<K, ITEMS>), dim3(g.scan), dim3(kBlock), 0, s, ctrl, n_ptr,
-                       in, out, p, b.rcnt, b.rtot);
+    hipLaunchKernelGGL((k_radix_count<K, RB, ITEMS>), dim3(G), dim3(kBlock), 0, s, ctrl, n_ptr, in,
+                       p * RB, b.rcnt);
+    hipLaunchKernelGGL(k_radix_scan, dim3(1 << RB), dim3(kBlock), 0, s, ctrl, n_ptr, T, b.rcnt, b.rtot, G);
+    hipLaunchKernelGGL((k_radix_scatter<K, RB, ITEMS>), dim3(G), dim3(kBlock), 0, s, ctrl, n_ptr, in,
+                       out, p * RB, b.rcnt, b.rtot);
+  }
+}
+
+template <typename K>
+void launch_sort(hipStream_t s, Ctrl* ctrl, const uint64_t* n_ptr, int key_bits, const SortCfg& c,
+                 const Bufs<K>& b) {
+  constexpr int SMALL = 8;
+  constexpr int LARGE = sizeof(K) == 4 ? 16 : 12;
+  const bool large = c.items != SMALL;
+  const int G = c.blocks;
+  switch (c.rb) {
+#define WG_SORT_CASE(RB)                                                        \
+    case RB:                                                                    \
+      if (large) sort_impl<K, RB, LARGE>(s, ctrl, n_ptr, key_bits, G, b);       \
+      else sort_impl<K, RB, SMALL>(s, ctrl, n_ptr, key_bits, G, b);            \
+      break;
+    WG_SORT_CASE(8)
+    WG_SORT_CASE(9)
+    WG_SORT_CASE(10)
+    WG_SORT_CASE(11)
+#undef WG_SORT_CASE
+    default:
+      break;
   }
 }
 
@@ -843,11 +1023,15 @@ void launch_resume(hipStream_t s, Ctrl* ctrl, uint64_t cand_cap, uint64_t full_c
 #define WG_INSTANTIATE(K)                                                                          \
   template void launch_pack<K>(hipStream_t, const Grid&, const uint32_t*, const uint32_t*,       \
                                uint64_t, int, K*);                                                \
+  template void launch_pack_batch<K>(hipStream_t, const Grid&, const uint32_t*, const uint32_t*, \
+                                     uint64_t, int, const uint64_t*, uint32_t, K*);               \
+  template void launch_offsets<K>(hipStream_t, const Grid&, const K*, uint64_t, int, uint32_t,   \
+                                  uint64_t*);                                                      \
   template void launch_join_count<K>(hipStream_t, const Grid&, int, Ctrl*, const Bufs<K>&, int,   \
                                      uint32_t);                                                    \
   template void launch_join_emit<K>(hipStream_t, const Grid&, int, Ctrl*, const Bufs<K>&, int,    \
                                     uint32_t);                                                     \
-  template void launch_sort<K>(hipStream_t, const Grid&, Ctrl*, const uint64_t*, int,             \
+  template void launch_sort<K>(hipStream_t, Ctrl*, const uint64_t*, int, const SortCfg&,         \
                                const Bufs<K>&);                                                    \
   template void launch_compact<K>(hipStream_t, const Grid&, int, Ctrl*, const uint64_t*, const K*, \
                                   K*, const Bufs<K>&, int, uint32_t, uint32_t);                    \

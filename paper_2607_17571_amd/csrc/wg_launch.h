@@ -25,13 +25,24 @@ constexpr int kEmitItems = 8;
 constexpr int kDedupItems = 8;
 constexpr int kMergeItems = 8;
 constexpr int kIndexItems = 8;
-template <typename K> constexpr int pass_items() { return sizeof(K) == 4 ? 16 : 12; }
 constexpr uint32_t kJoinTile = kBlock * kJoinItems;
 constexpr uint32_t kDedupTile = kBlock * kDedupItems;
 constexpr uint32_t kIndexTile = kBlock * kIndexItems;
-constexpr int kRadixBits = 8;
-constexpr int kRadix = 1 << kRadixBits;
-constexpr int kMaxPasses = 8;
+// Radix digit widths the sort is built for, and its grid limit (the per-block digit
+// counts of one pass take (1 << digit bits) x blocks entries).
+constexpr int kRadixBitsMin = 8;
+constexpr int kRadixBitsMax = 11;
+constexpr int kRadixMax = 1 << kRadixBitsMax;
+constexpr int kRadixBlocksMax = 2048;
+inline int sort_passes(int key_bits, int rb) { return (key_bits + rb - 1) / rb; }
+
+// One configuration of the sort: digit bits, keys per thread and tile (8, or the large
+// tile: 16 for 32-bit keys, 12 for 64-bit keys), blocks per pass.
+struct SortCfg {
+  int rb = 8;
+  int items = 0;  // 8 = small tile; anything else = the large tile
+  int blocks = 1024;
+};
 // Blocks of the static-range kernels (join count, radix count/scatter, compaction, index).
 // Consumers keep the per-block totals of a launch in LDS, so this is bounded.
 constexpr int kScanBlocksMax = 1024;
@@ -56,8 +67,8 @@ struct Bufs {
   uint32_t* off;   // per delta tuple: first candidate, relative to its block's range
   uint64_t* jtot;  // per join-count block: candidates of its range
   uint64_t* bcnt;  // per compaction block: survivors of its range
-  uint32_t* rcnt;  // radix: per-block digit counts, then offsets (kRadix x scan blocks)
-  uint32_t* rtot;  // radix: digit totals (kRadix)
+  uint32_t* rcnt;  // radix: per-block digit counts, then offsets (digits x blocks)
+  uint32_t* rtot;  // radix: digit totals
   IterRec* rec;    // per-iteration sizes
 };
 
@@ -68,6 +79,17 @@ template <typename K>
 void launch_pack(hipStream_t s, const Grid& g, const uint32_t* src, const uint32_t* dst,
                  uint64_t m, int w, K* keys);
 
+// Batches: validate the instance offsets (sets ctrl->bad_input), pack with the instance
+// in the top key bits, and find each instance's first key in the sorted result.
+void launch_check_offsets(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint64_t* offsets,
+                          uint32_t num, uint64_t m);
+template <typename K>
+void launch_pack_batch(hipStream_t s, const Grid& g, const uint32_t* src, const uint32_t* dst,
+                       uint64_t m, int w, const uint64_t* offsets, uint32_t num, K* keys);
+template <typename K>
+void launch_offsets(hipStream_t s, const Grid& g, const K* keys, uint64_t n, int shift, uint32_t num,
+                    uint64_t* out);
+
 // Join of iteration j (kind kJoinSGBase: the base rule, j = 0): count, then emit.
 template <typename K>
 void launch_join_count(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w,
@@ -76,9 +98,10 @@ template <typename K>
 void launch_join_emit(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w,
                       uint32_t j);
 
-// LSD sort of *n_ptr keys starting in cand[0]; `passes` 8-bit passes; ends in cand[passes&1].
+// LSD sort of the low `key_bits` bits of *n_ptr keys starting in cand[0]:
+// sort_passes(key_bits, c.rb) passes; the result ends in cand[passes & 1].
 template <typename K>
-void launch_sort(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint64_t* n_ptr, int passes,
+void launch_sort(hipStream_t s, Ctrl* ctrl, const uint64_t* n_ptr, int key_bits, const SortCfg& c,
                  const Bufs<K>& b);
 
 // Compaction (dedup + set difference, seeding, or the diagonal filter): local + gather.

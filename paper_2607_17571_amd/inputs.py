@@ -250,3 +250,20 @@ def er_batch(num: int, seed: int, n_lo: int = 256, n_hi: int = 65536,
     offsets[1:] = np.cumsum(m).astype(np.uint64)
     return Batch(np.concatenate(srcs) if srcs else np.empty(0, U32),
                  np.concatenate(dsts) if dsts else np.empty(0, U32), offsets, n)
+
+
+def batch_workload(name: str) -> tuple[str, Batch]:
+    """Named batched workloads: (query, batch).
+
+    tc_batch_er_4096   4,096 ER instances, n log-uniform in [256, 65,536], mean
+                       out-degree uniform in [0.5, 0.95], seed 4
+    tc_batch_er_256    the same recipe with 256 instances, seed 6 (a smaller batch)
+    sg_batch_er_256    SG over 256 instances, n in [64, 4,096], seed 7
+    """
+    if name == "tc_batch_er_4096":
+        return "tc", er_batch(4096, seed=4)
+    if name == "tc_batch_er_256":
+        return "tc", er_batch(256, seed=6)
+    if name == "sg_batch_er_256":
+        return "sg", er_batch(256, seed=7, n_lo=64, n_hi=4096)
+    raise KeyError(name)

@@ -28,6 +28,9 @@ WG_ERR_STALE = 6
 WG_SG_IRREFLEXIVE = 0x1
 WG_STAGE_TIMING = 0x2
 
+WG_QUERY_TC = 0
+WG_QUERY_SG = 1
+
 WG_LOOP_AUTO = 0
 WG_LOOP_BATCHED = 1
 WG_LOOP_HOST = 2
@@ -47,6 +50,8 @@ class WgOptions(ctypes.Structure):
         ("max_iterations", c_uint64),
         ("mem_budget_bytes", c_uint64),
         ("force_overflow_at_iter", c_uint64),
+        ("radix_digit_bits", c_uint32),
+        ("tile_items", c_uint32),
     ]
 
 
@@ -66,7 +71,39 @@ class WgStats(ctypes.Structure):
         ("stage_bytes", c_uint64 * WG_NUM_STAGES),
         ("delta_sizes", POINTER(c_uint64)),
         ("delta_sizes_cap", c_uint64),
+        ("digit_bits", c_uint32),
+        ("sort_passes", c_uint32),
     ]
+
+
+class WgSortConfig(ctypes.Structure):
+    _fields_ = [("digit_bits", c_uint32), ("tile_items", c_uint32), ("blocks", c_uint32),
+                ("reserved", c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {"digit_bits": int(self.digit_bits), "tile_items": int(self.tile_items),
+                "blocks": int(self.blocks)}
+
+
+WG_TUNE_MAX_TRIALS = 64
+
+
+class WgTuneReport(ctypes.Structure):
+    _fields_ = [
+        ("trials", c_uint32),
+        ("key_bytes", c_uint32),
+        ("best", WgSortConfig),
+        ("best_ms", c_double),
+        ("before_ms", c_double),
+        ("tried", WgSortConfig * WG_TUNE_MAX_TRIALS),
+        ("tried_ms", c_double * WG_TUNE_MAX_TRIALS),
+    ]
+
+    def as_dict(self) -> dict:
+        return {"key_bytes": int(self.key_bytes), "best": self.best.as_dict(),
+                "best_ms": float(self.best_ms), "before_ms": float(self.before_ms),
+                "trials": [dict(self.tried[i].as_dict(), ms=float(self.tried_ms[i]))
+                           for i in range(int(self.trials))]}
 
 
 class WgError(RuntimeError):
@@ -85,6 +122,16 @@ SIGNATURES = [
                       POINTER(c_void_p), POINTER(WgStats)]),
     ("wg_sg", c_int, [c_void_p, c_void_p, c_void_p, c_uint64, POINTER(WgOptions), c_void_p,
                       POINTER(c_void_p), POINTER(WgStats)]),
+    ("wg_tc_batch", c_int, [c_void_p, c_uint32, c_void_p, c_void_p, c_void_p, c_uint64,
+                            POINTER(WgOptions), c_void_p, POINTER(c_void_p), POINTER(WgStats)]),
+    ("wg_sg_batch", c_int, [c_void_p, c_uint32, c_void_p, c_void_p, c_void_p, c_uint64,
+                            POINTER(WgOptions), c_void_p, POINTER(c_void_p), POINTER(WgStats)]),
+    ("wg_result_instances", c_uint32, [c_void_p]),
+    ("wg_result_offsets", c_int, [c_void_p, c_void_p, c_uint64, c_void_p]),
+    ("wg_get_sort_config", c_int, [c_void_p, c_uint32, POINTER(WgSortConfig)]),
+    ("wg_set_sort_config", c_int, [c_void_p, c_uint32, POINTER(WgSortConfig)]),
+    ("wg_autotune", c_int, [c_void_p, c_int, c_uint32, c_void_p, c_void_p, c_void_p, c_uint64,
+                            POINTER(WgOptions), c_uint32, c_void_p, POINTER(WgTuneReport)]),
     ("wg_result_size", c_uint64, [c_void_p]),
     ("wg_result_copy", c_int, [c_void_p, c_void_p, c_void_p, c_uint64, c_void_p]),
     ("wg_result_free", None, [c_void_p]),
@@ -150,6 +197,54 @@ def wg_sg(engine, d_src: int, d_dst: int, m: int, options: WgOptions | None, str
     return st, res
 
 
+def _batch(fn, engine, num: int, d_offsets: int, d_src: int, d_dst: int, m: int,
+           options: WgOptions | None, stream: int, stats: WgStats | None):
+    res = c_void_p()
+    st = fn(engine, num, c_void_p(d_offsets), c_void_p(d_src), c_void_p(d_dst), m,
+            byref(options) if options is not None else None, c_void_p(stream), byref(res),
+            byref(stats) if stats is not None else None)
+    return st, res
+
+
+def wg_tc_batch(engine, num: int, d_offsets: int, d_src: int, d_dst: int, m: int,
+                options: WgOptions | None, stream: int, stats: WgStats | None = None):
+    """Returns (status, result handle)."""
+    return _batch(lib().wg_tc_batch, engine, num, d_offsets, d_src, d_dst, m, options, stream, stats)
+
+
+def wg_sg_batch(engine, num: int, d_offsets: int, d_src: int, d_dst: int, m: int,
+                options: WgOptions | None, stream: int, stats: WgStats | None = None):
+    return _batch(lib().wg_sg_batch, engine, num, d_offsets, d_src, d_dst, m, options, stream, stats)
+
+
+def wg_result_instances(result) -> int:
+    return int(lib().wg_result_instances(result))
+
+
+def wg_result_offsets(result, offsets_out: int, capacity: int, stream: int) -> int:
+    return lib().wg_result_offsets(result, c_void_p(offsets_out), capacity, c_void_p(stream))
+
+
+def wg_get_sort_config(engine, key_bytes: int):
+    cfg = WgSortConfig()
+    st = lib().wg_get_sort_config(engine, key_bytes, byref(cfg))
+    return st, cfg
+
+
+def wg_set_sort_config(engine, key_bytes: int, cfg: WgSortConfig) -> int:
+    return lib().wg_set_sort_config(engine, key_bytes, byref(cfg))
+
+
+def wg_autotune(engine, query: int, num: int, d_offsets: int, d_src: int, d_dst: int, m: int,
+                options: WgOptions | None, repeats: int, stream: int):
+    """Returns (status, WgTuneReport)."""
+    rep = WgTuneReport()
+    st = lib().wg_autotune(engine, query, num, c_void_p(d_offsets), c_void_p(d_src), c_void_p(d_dst),
+                           m, byref(options) if options is not None else None, repeats,
+                           c_void_p(stream), byref(rep))
+    return st, rep
+
+
 def wg_result_size(result) -> int:
     return int(lib().wg_result_size(result))
 
@@ -176,7 +271,8 @@ def wg_last_error(engine) -> str:
 
 def make_options(flags: int = 0, batch_k: int = 0, loop_mode: int = WG_LOOP_AUTO,
                  radix_field_bits: int = 0, max_iterations: int = 0, mem_budget_bytes: int = 0,
-                 force_overflow_at_iter: int = 0, timing_stages: int = 0) -> WgOptions:
+                 force_overflow_at_iter: int = 0, timing_stages: int = 0,
+                 radix_digit_bits: int = 0, tile_items: int = 0) -> WgOptions:
     o = WgOptions()
     o.struct_size = ctypes.sizeof(WgOptions)
     o.flags = flags
@@ -187,6 +283,8 @@ def make_options(flags: int = 0, batch_k: int = 0, loop_mode: int = WG_LOOP_AUTO
     o.mem_budget_bytes = mem_budget_bytes
     o.force_overflow_at_iter = force_overflow_at_iter
     o.timing_stages = timing_stages
+    o.radix_digit_bits = radix_digit_bits
+    o.tile_items = tile_items
     return o
 
 
@@ -196,6 +294,7 @@ def stats_dict(s: WgStats, deltas=None) -> dict:
         "base_tuples": int(s.base_tuples), "join_candidates": int(s.join_candidates),
         "host_syncs": int(s.host_syncs), "resumes": int(s.resumes),
         "field_bits": int(s.field_bits), "key_bytes": int(s.key_bytes),
+        "digit_bits": int(s.digit_bits), "sort_passes": int(s.sort_passes),
         "solve_ms": float(s.solve_ms),
         "stage_ms": {k: float(s.stage_ms[i]) for i, k in enumerate(STAGES)},
         "stage_launches": {k: int(s.stage_launches[i]) for i, k in enumerate(STAGES)},
@@ -233,14 +332,7 @@ class Engine:
         """Run wg_tc / wg_sg on torch uint32/int32 CUDA tensors; returns (src, dst, stats)."""
         import torch
 
-        if src.device.type != "cuda" or dst.device.type != "cuda":
-            raise ValueError("edge tensors must live on the GPU")
-        if src.shape != dst.shape or src.dim() != 1:
-            raise ValueError("src and dst must be 1-D tensors of equal length")
-        if src.dtype not in (torch.uint32, torch.int32) or dst.dtype != src.dtype:
-            raise ValueError("edge tensors must be uint32 (or int32 bit patterns)")
-        src = src.contiguous()
-        dst = dst.contiguous()
+        src, dst, _ = self._check_edges(src, dst)
         stream = torch.cuda.current_stream(src.device).cuda_stream
         stats = WgStats()
         deltas = (c_uint64 * max_deltas)()
@@ -250,19 +342,95 @@ class Engine:
         st, res = fn(self.handle, src.data_ptr(), dst.data_ptr(), src.numel(), options, stream, stats)
         if st != WG_OK:
             raise WgError(st, wg_last_error(self.handle))
+        out_s, out_d, _ = self._take(res, src.device, stream, want_result, False)
+        return out_s, out_d, stats_dict(stats, deltas)
+
+    def _take(self, res, device, stream, want_result, want_offsets):
+        """Copy a result handle into torch tensors (split arrays, optional offsets) and free it."""
+        import torch
+
         try:
             n = wg_result_size(res)
-            out_s = out_d = None
+            out_s = out_d = offs = None
             if want_result:
-                out_s = torch.empty(n, dtype=torch.uint32, device=src.device)
-                out_d = torch.empty(n, dtype=torch.uint32, device=src.device)
+                out_s = torch.empty(n, dtype=torch.uint32, device=device)
+                out_d = torch.empty(n, dtype=torch.uint32, device=device)
                 if n:
                     st = wg_result_copy(res, out_s.data_ptr(), out_d.data_ptr(), n, stream)
                     if st != WG_OK:
                         raise WgError(st, wg_last_error(self.handle))
+            if want_offsets:
+                k = wg_result_instances(res)
+                offs = torch.empty(k + 1, dtype=torch.int64, device=device)
+                st = wg_result_offsets(res, offs.data_ptr(), k + 1, stream)
+                if st != WG_OK:
+                    raise WgError(st, wg_last_error(self.handle))
         finally:
             wg_result_free(res)
-        return out_s, out_d, stats_dict(stats, deltas)
+        return out_s, out_d, offs
+
+    @staticmethod
+    def _check_edges(src, dst, offsets=None):
+        import torch
+
+        if src.device.type != "cuda" or dst.device.type != "cuda":
+            raise ValueError("edge tensors must live on the GPU")
+        if src.shape != dst.shape or src.dim() != 1:
+            raise ValueError("src and dst must be 1-D tensors of equal length")
+        if src.dtype not in (torch.uint32, torch.int32) or dst.dtype != src.dtype:
+            raise ValueError("edge tensors must be uint32 (or int32 bit patterns)")
+        if offsets is not None:
+            if offsets.device.type != "cuda" or offsets.dim() != 1 or offsets.numel() < 2:
+                raise ValueError("offsets must be a 1-D GPU tensor of instances + 1 entries")
+            if offsets.dtype not in (torch.int64, torch.uint64):
+                raise ValueError("offsets must be int64 (or uint64)")
+        return src.contiguous(), dst.contiguous(), None if offsets is None else offsets.contiguous()
+
+    def solve_batch(self, query: str, src, dst, offsets, options: WgOptions | None = None,
+                    want_result: bool = True, max_deltas: int = 1 << 16):
+        """wg_tc_batch / wg_sg_batch; returns (src, dst, result offsets, stats)."""
+        import torch
+
+        src, dst, offsets = self._check_edges(src, dst, offsets)
+        stream = torch.cuda.current_stream(src.device).cuda_stream
+        stats = WgStats()
+        deltas = (c_uint64 * max_deltas)()
+        stats.delta_sizes = deltas
+        stats.delta_sizes_cap = max_deltas
+        fn = wg_tc_batch if query == "tc" else wg_sg_batch
+        st, res = fn(self.handle, offsets.numel() - 1, offsets.data_ptr(), src.data_ptr(), dst.data_ptr(),
+                     src.numel(), options, stream, stats)
+        if st != WG_OK:
+            raise WgError(st, wg_last_error(self.handle))
+        out_s, out_d, offs = self._take(res, src.device, stream, want_result, True)
+        return out_s, out_d, offs, stats_dict(stats, deltas)
+
+    def autotune(self, query: str, src, dst, offsets=None, options: WgOptions | None = None,
+                 repeats: int = 2) -> dict:
+        """wg_autotune on a single instance (offsets None) or a batch; returns the report."""
+        import torch
+
+        src, dst, offsets = self._check_edges(src, dst, offsets)
+        stream = torch.cuda.current_stream(src.device).cuda_stream
+        num = 0 if offsets is None else offsets.numel() - 1
+        st, rep = wg_autotune(self.handle, WG_QUERY_TC if query == "tc" else WG_QUERY_SG, num,
+                              0 if offsets is None else offsets.data_ptr(), src.data_ptr(),
+                              dst.data_ptr(), src.numel(), options, repeats, stream)
+        if st != WG_OK:
+            raise WgError(st, wg_last_error(self.handle))
+        return rep.as_dict()
+
+    def sort_config(self, key_bytes: int) -> dict:
+        st, cfg = wg_get_sort_config(self.handle, key_bytes)
+        if st != WG_OK:
+            raise WgError(st, wg_last_error(self.handle))
+        return cfg.as_dict()
+
+    def set_sort_config(self, key_bytes: int, digit_bits: int, tile_items: int, blocks: int) -> None:
+        cfg = WgSortConfig(digit_bits, tile_items, blocks, 0)
+        st = wg_set_sort_config(self.handle, key_bytes, cfg)
+        if st != WG_OK:
+            raise WgError(st, wg_last_error(self.handle))
 
     def tc(self, src, dst, options=None, **kw):
         return self.solve("tc", src, dst, options, **kw)

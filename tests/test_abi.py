@@ -28,7 +28,9 @@ def declared_functions():
 def test_header_declares_the_entry_points():
     names = declared_functions()
     for required in ["wg_engine_create", "wg_engine_destroy", "wg_tc", "wg_sg", "wg_result_size",
-                     "wg_result_copy", "wg_result_free", "wg_status_string", "wg_last_error"]:
+                     "wg_result_copy", "wg_result_free", "wg_status_string", "wg_last_error",
+                     "wg_tc_batch", "wg_sg_batch", "wg_result_offsets", "wg_result_instances",
+                     "wg_autotune", "wg_get_sort_config", "wg_set_sort_config"]:
         assert required in names
 
 
@@ -54,7 +56,45 @@ def test_status_strings_without_gpu():
     assert "invalid" in wg.wg_status_string(wg.WG_ERR_INVALID_ARG)
 
 
-def test_options_struct_matches_header_layout():
+LAYOUT_PROBE = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "wg.h"
+#define F(T, f) printf(#T "." #f " %zu\n", offsetof(T, f))
+#define S(T) printf(#T " %zu\n", sizeof(T))
+int main(void) {
+  S(wg_options); F(wg_options, max_iterations); F(wg_options, radix_digit_bits);
+  F(wg_options, tile_items);
+  S(wg_stats); F(wg_stats, solve_ms); F(wg_stats, stage_bytes); F(wg_stats, delta_sizes);
+  F(wg_stats, digit_bits); F(wg_stats, sort_passes);
+  S(wg_sort_config); S(wg_tune_report); F(wg_tune_report, best); F(wg_tune_report, best_ms);
+  F(wg_tune_report, tried); F(wg_tune_report, tried_ms);
+  return 0;
+}
+"""
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Sizes and offsets of every ABI struct, from gcc on the header, equal the binding's."""
+    import shutil
+    import subprocess
+
     from paper_2607_17571_amd import wg
-    assert ctypes.sizeof(wg.WgOptions) == 48
-    assert wg.WgStats.delta_sizes.offset == 8 * 6 + 8 + 8 + 3 * 8 * wg.WG_NUM_STAGES
+    gcc = shutil.which("gcc") or shutil.which("cc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    c = tmp_path / "probe.c"
+    c.write_text(LAYOUT_PROBE)
+    exe = tmp_path / "probe"
+    subprocess.run([gcc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)],
+                   check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                         check=True).stdout.splitlines())
+    types = {"wg_options": wg.WgOptions, "wg_stats": wg.WgStats, "wg_sort_config": wg.WgSortConfig,
+             "wg_tune_report": wg.WgTuneReport}
+    for key, val in got.items():
+        if "." in key:
+            t, f = key.split(".")
+            assert getattr(types[t], f).offset == int(val), key
+        else:
+            assert ctypes.sizeof(types[key]) == int(val), key

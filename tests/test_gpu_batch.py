@@ -1,0 +1,150 @@
+"""Batched fixpoints (wg_tc_batch / wg_sg_batch) against the oracle, instance by instance.
+
+Every instance of a batch must equal the oracle's fixpoint of that instance alone, and
+the result offsets must delimit the instances.  Full-size batches compare against the
+oracle-written summaries in tests/golden/fixpoints.json and check sampled instances
+against the oracle live.
+"""
+
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2607_17571_amd import inputs
+from paper_2607_17571_amd import wg
+from tests.gpu_util import run as run_single
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "fixpoints.json")))
+
+
+def run_batch(engine, query, src, dst, offsets, options=None):
+    import sys
+
+    import torch
+    print(f"[gpu] {query} batch of {len(offsets) - 1}, m={len(src)}", flush=True, file=sys.stderr)
+    s, d, offs, st = engine.solve_batch(
+        query, torch.from_numpy(np.ascontiguousarray(src, dtype=np.uint32)).cuda(),
+        torch.from_numpy(np.ascontiguousarray(dst, dtype=np.uint32)).cuda(),
+        torch.from_numpy(np.ascontiguousarray(offsets, dtype=np.int64)).cuda(), options)
+    return s.cpu().numpy(), d.cpu().numpy(), offs.cpu().numpy(), st
+
+
+def check_instances(s, d, offs, refs, idx):
+    assert offs[0] == 0 and offs[-1] == s.size
+    assert np.all(np.diff(offs) >= 0)
+    for i in idx:
+        lo, hi = int(offs[i]), int(offs[i + 1])
+        np.testing.assert_array_equal(s[lo:hi], refs[i].src, err_msg=f"instance {i} src")
+        np.testing.assert_array_equal(d[lo:hi], refs[i].dst, err_msg=f"instance {i} dst")
+
+
+def layout(instances):
+    """Instances [(src, dst), ...] back to back -> (src, dst, offsets)."""
+    offsets = np.zeros(len(instances) + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum([len(s) for s, _ in instances])
+    src = np.concatenate([np.asarray(s, np.uint32) for s, _ in instances]) if instances else np.empty(0, np.uint32)
+    dst = np.concatenate([np.asarray(d, np.uint32) for _, d in instances]) if instances else np.empty(0, np.uint32)
+    return src, dst, offsets
+
+
+def test_small_tc_batch(engine):
+    b = inputs.er_batch(48, seed=11, n_lo=8, n_hi=600)
+    refs = oracle.tc_batch(b.src, b.dst, b.offsets)
+    s, d, offs, st = run_batch(engine, "tc", b.src, b.dst, b.offsets)
+    check_instances(s, d, offs, refs, range(b.num))
+    assert st["iterations"] == max(r.iterations for r in refs)
+    assert st["result_tuples"] == sum(r.src.size for r in refs)
+
+
+def test_small_sg_batch(engine):
+    b = inputs.er_batch(32, seed=12, n_lo=8, n_hi=300, deg_lo=0.9, deg_hi=1.6)
+    for irreflexive in (False, True):
+        refs = oracle.sg_batch(b.src, b.dst, b.offsets, irreflexive)
+        opts = wg.make_options(flags=wg.WG_SG_IRREFLEXIVE if irreflexive else 0)
+        s, d, offs, st = run_batch(engine, "sg", b.src, b.dst, b.offsets, opts)
+        check_instances(s, d, offs, refs, range(b.num))
+
+
+def test_batch_with_empty_and_tiny_instances(engine):
+    inst = [(np.empty(0, np.uint32), np.empty(0, np.uint32)), ([0], [1]), inputs.chain(5),
+            inputs.cycle(3), (np.empty(0, np.uint32), np.empty(0, np.uint32)), ([7, 7], [7, 3]),
+            inputs.out_star(9), (np.empty(0, np.uint32), np.empty(0, np.uint32))]
+    src, dst, offsets = layout(inst)
+    for query in ("tc", "sg"):
+        refs = [(oracle.tc if query == "tc" else oracle.sg)(np.asarray(s, np.uint32), np.asarray(d, np.uint32))
+                for s, d in inst]
+        s, d, offs, st = run_batch(engine, query, src, dst, offsets)
+        assert offs.size == len(inst) + 1
+        check_instances(s, d, offs, refs, range(len(inst)))
+
+
+def test_batch_of_one_equals_single_solve(engine):
+    src, dst = inputs.rmat(10, 900, *inputs.RMAT_ABCD, seed=13)
+    s1, d1, st1 = run_single(engine, "tc", src, dst)
+    s, d, offs, st = run_batch(engine, "tc", src, dst, np.array([0, len(src)]))
+    np.testing.assert_array_equal(s, s1)
+    np.testing.assert_array_equal(d, d1)
+    assert list(offs) == [0, s1.size]
+    assert st["delta_sizes"] == st1["delta_sizes"]
+
+
+@pytest.mark.parametrize("opts", [dict(radix_digit_bits=11), dict(radix_digit_bits=9, tile_items=8),
+                                  dict(force_overflow_at_iter=2), dict(batch_k=1)])
+def test_batch_independent_of_options(engine, opts):
+    b = inputs.er_batch(40, seed=14, n_lo=16, n_hi=2000)
+    refs = oracle.tc_batch(b.src, b.dst, b.offsets)
+    s, d, offs, st = run_batch(engine, "tc", b.src, b.dst, b.offsets, wg.make_options(**opts))
+    check_instances(s, d, offs, refs, range(b.num))
+
+
+def test_batch_rejects_bad_offsets(engine):
+    src, dst, offsets = layout([inputs.chain(4), inputs.chain(3)])  # m = 5
+    assert list(offsets) == [0, 3, 5]
+    # decreasing, not ending at m, not starting at 0
+    for bad in (np.array([0, 3, 2, 5]), np.array([0, 3, 4]), np.array([1, 3, 5])):
+        with pytest.raises(wg.WgError) as ei:
+            run_batch(engine, "tc", src, dst, bad)
+        assert ei.value.status == wg.WG_ERR_INVALID_ARG
+    # 2^17 + 1 instances (18 instance bits) with 16-bit ids need 34 bits: too wide
+    num = (1 << 17) + 1
+    offsets = np.zeros(num + 1, dtype=np.int64)
+    offsets[num] = 1
+    with pytest.raises(wg.WgError) as ei:
+        run_batch(engine, "tc", np.array([0], np.uint32), np.array([65535], np.uint32), offsets)
+    assert ei.value.status == wg.WG_ERR_INVALID_ARG
+
+
+def _golden_batch(engine, name, sample):
+    if name not in GOLDEN:
+        pytest.fail(f"no golden record for {name}; run tests/golden/make_golden.py {name}")
+    g = GOLDEN[name]
+    query, b = inputs.batch_workload(name)
+    s, d, offs, st = run_batch(engine, query, b.src, b.dst, b.offsets)
+    assert s.size == g["size"]
+    assert st["iterations"] == g["iterations"]
+    assert hashlib.sha256(offs.astype("<i8").tobytes()).hexdigest() == g["offsets_sha256"]
+    assert hashlib.sha256(s.astype("<u4").tobytes() + d.astype("<u4").tobytes()).hexdigest() == g["sha256"]
+    # sampled instances against the oracle, computed here one by one
+    fn = oracle.tc if query == "tc" else oracle.sg
+    idx = sorted(set(sample) | {int(np.argmax(b.n))})
+    refs = {i: fn(*b.instance(i)) for i in idx}
+    check_instances(s, d, offs, refs, idx)
+
+
+def test_batch_256_against_golden(engine):
+    _golden_batch(engine, "tc_batch_er_256", [0, 1, 100, 255])
+
+
+def test_sg_batch_256_against_golden(engine):
+    _golden_batch(engine, "sg_batch_er_256", [0, 17, 200, 255])
+
+
+def test_batch_4096_against_golden(engine):
+    """The full batched workload, in the configuration the benchmark times."""
+    _golden_batch(engine, "tc_batch_er_4096", [0, 1, 2047, 4095])

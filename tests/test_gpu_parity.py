@@ -164,6 +164,31 @@ def test_result_independent_of_loop_policy(engine, opts):
     assert_same(s, d, st, ref)
 
 
+SORT_CFGS = [(rb, items) for rb in (8, 9, 10, 11) for items in (8, 16)]
+
+
+@pytest.mark.parametrize("rb,items", SORT_CFGS)
+def test_sort_configurations_tc(engine, rb, items):
+    """Every digit width and tile of the LSD sort gives the same fixpoint (32-bit keys)."""
+    src, dst = inputs.rmat(11, 1800, *inputs.RMAT_ABCD, seed=9)
+    ref = oracle.tc(src, dst)
+    s, d, st = run(engine, "tc", src, dst, wg.make_options(radix_digit_bits=rb, tile_items=items))
+    assert_same(s, d, st, ref)
+    assert st["digit_bits"] == rb and st["sort_passes"] == -(-32 // rb)
+
+
+@pytest.mark.parametrize("rb,items", [(8, 12), (9, 8), (10, 12), (11, 12), (11, 8)])
+def test_sort_configurations_wide_keys(engine, rb, items):
+    """64-bit keys (ids scattered over 2^22, w = 24): TC and SG, every digit width."""
+    src, dst = inputs.scatter_ids(*inputs.rmat(10, 900, *inputs.RMAT_ABCD, seed=4), 22, seed=5)
+    opts = wg.make_options(radix_digit_bits=rb, tile_items=items)
+    s, d, st = run(engine, "tc", src, dst, opts)
+    assert_same(s, d, st, oracle.tc(src, dst))
+    assert st["key_bytes"] == 8 and st["sort_passes"] == -(-48 // rb)
+    s, d, st = run(engine, "sg", src, dst, opts)
+    assert_same(s, d, st, oracle.sg(src, dst))
+
+
 @pytest.mark.parametrize("at", [1, 3, 6])
 def test_forced_overflow_resumes_identically(engine, at):
     src, dst = inputs.rmat(11, 1800, *inputs.RMAT_ABCD, seed=9)
@@ -211,6 +236,10 @@ def test_invalid_arguments(engine):
     src, dst = inputs.scatter_ids(*inputs.chain(5), 30, seed=1)
     with pytest.raises(wg.WgError):
         run(engine, "tc", src, dst, wg.make_options(radix_field_bits=16))
+    for bad in (dict(radix_digit_bits=7), dict(radix_digit_bits=12), dict(tile_items=5)):
+        with pytest.raises(wg.WgError) as ei:
+            run(engine, "tc", a, b, wg.make_options(**bad))
+        assert ei.value.status == wg.WG_ERR_INVALID_ARG
 
 
 def test_stale_result_is_rejected(engine):
@@ -256,11 +285,22 @@ def test_result_copy_to_host_memory(engine):
 @pytest.mark.parametrize("name", ["tc_er_2000", "tc_rmat_s15", "tc_rmat_s15_ids24", "sg_er_500k",
                                   "tc_grid_100"])
 def test_full_size_against_golden(engine, name):
+    _check_golden(engine, name, None)
+
+
+@pytest.mark.parametrize("name,rb,items", [("tc_rmat_s15", 11, 16), ("tc_rmat_s15", 9, 8),
+                                           ("tc_rmat_s15_ids24", 11, 12), ("sg_er_500k", 10, 8)])
+def test_full_size_sort_configurations(engine, name, rb, items):
+    """Sort configurations at full size, where every block sorts many tiles."""
+    _check_golden(engine, name, wg.make_options(radix_digit_bits=rb, tile_items=items))
+
+
+def _check_golden(engine, name, opts):
     if name not in GOLDEN:
         pytest.fail(f"no golden record for {name}; run tests/golden/make_golden.py")
     g = GOLDEN[name]
     w = inputs.workload(name)
-    s, d, st = run(engine, w.query, w.src, w.dst)
+    s, d, st = run(engine, w.query, w.src, w.dst, opts)
     assert s.size == g["size"]
     assert st["iterations"] == g["iterations"]
     assert st["delta_sizes"] == g["delta_sizes"]
