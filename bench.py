@@ -47,6 +47,9 @@ WORKLOAD_TEXT = {
                         "out-degree uniform in [0.5, 0.95], seed 4, one solve",
     "tc_batch_er_256": "batched TC, 256 ER instances (same recipe), seed 6",
     "sg_batch_er_256": "batched SG, 256 ER instances, n log-uniform in [64, 4,096], seed 7",
+    "served_mix": "served TC/SG mix: Poisson arrivals at 0.7x the single-stream capacity, 70% TC / "
+                  "30% SG, 50/50 ER / R-MAT(0.57,0.19,0.19,0.05), n log-uniform in [1k, 1M] (R-MAT "
+                  "capped at scale 15), mean out-degree uniform in [0.5, 0.95], seed 5",
 }
 
 
@@ -62,6 +65,9 @@ def parse():
     p.add_argument("--tile-items", type=int, default=0, help="sort tile keys per thread (0: engine's)")
     p.add_argument("--no-autotune", action="store_true", help="batched workloads: skip the autotuner")
     p.add_argument("--no-plain", action="store_true", help="batched workloads: skip the one-by-one path")
+    p.add_argument("--requests", type=int, default=120, help="served_mix: number of requests")
+    p.add_argument("--slots", type=int, default=4, help="served_mix: concurrent solves")
+    p.add_argument("--load", type=float, default=0.7, help="served_mix: offered load / capacity")
     return p.parse_args()
 
 
@@ -96,6 +102,139 @@ def cpu_baseline(name: str):
                       f"in {dt:.2f} s, single-threaded numpy"}, r
 
 
+def percentile(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else 0.0
+
+
+def served_cpu_baseline(reqs):
+    import oracle
+
+    t0 = time.perf_counter()
+    tuples = done = 0
+    while done < len(reqs) and time.perf_counter() - t0 < 15.0:
+        r = reqs[done]
+        tuples += (oracle.tc(r.src, r.dst) if r.query == "tc" else oracle.sg(r.src, r.dst)).src.size
+        done += 1
+    dt = time.perf_counter() - t0
+    return {"value": tuples / dt, "unit": "tuples/s", "cores": 1, "kind": "oracle",
+            "sample": f"requests 0..{done - 1} of the served mix ({tuples} tuples) solved one by "
+                      f"one in {dt:.2f} s, single-threaded numpy"}
+
+
+def run_served(args):
+    """Continuous batching under Poisson arrivals vs the plain one-at-a-time path."""
+    import numpy as np
+    import torch
+
+    from paper_2607_17571_amd import inputs, wg
+
+    def progress(msg):
+        print(f"[served] {msg}", file=sys.stderr, flush=True)
+
+    reqs = inputs.served_requests(args.requests, seed=5)
+    dev = [(torch.from_numpy(r.src).cuda(), torch.from_numpy(r.dst).cuda()) for r in reqs]
+    torch.cuda.synchronize()
+    progress(f"{len(reqs)} requests staged on the device")
+    # plain path: each request alone through wg_tc / wg_sg, one after another
+    eng = wg.Engine(0)
+    for (s, d), r in list(zip(dev, reqs))[:4]:
+        eng.solve(r.query, s, d, None)
+    service, plain_tuples = [], 0
+    for (s, d), r in zip(dev, reqs):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, _, st = eng.solve(r.query, s, d, None)
+        torch.cuda.synchronize()
+        service.append(time.perf_counter() - t)
+        plain_tuples += st["result_tuples"]
+        if len(service) % 20 == 0:
+            progress(f"plain path: {len(service)} solved, {sum(service):.2f} s of service")
+    eng.close()
+    capacity = len(reqs) / sum(service)
+    progress(f"plain path done: capacity {capacity:.1f} req/s")
+    srv = wg.Server(0, slots=args.slots)
+    for (s, d), r in list(zip(dev, reqs))[:2 * args.slots]:
+        srv.submit(r.query, s, d).wait(want_result=False)
+    progress("server warm")
+
+    def at_load(load):
+        rate = load * capacity
+        rng = np.random.default_rng(5)
+        gaps = rng.exponential(1.0 / rate, size=len(reqs))
+        arrivals = np.cumsum(gaps) - gaps[0]
+        # the plain path as one FIFO server under the same arrivals
+        fin, plain_lat = 0.0, []
+        for a, sv in zip(arrivals, service):
+            fin = max(fin, a) + sv
+            plain_lat.append(fin - a)
+        # served: submit at the arrival times; results stay on the device until waited
+        jobs = []
+        t0 = time.perf_counter()
+        for (s, d), r, a in zip(dev, reqs, arrivals):
+            delay = t0 + a - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            jobs.append(srv.submit(r.query, s, d))
+        lat, tuples, first, last = [], 0, None, None
+        for j in jobs:
+            _, _, st, info = j.wait(want_result=False)
+            lat.append((info["end_ms"] - info["submit_ms"]) / 1e3)
+            tuples += st["result_tuples"]
+            first = info["submit_ms"] if first is None else min(first, info["submit_ms"])
+            last = info["end_ms"] if last is None else max(last, info["end_ms"])
+            j.close()
+        span = (last - first) / 1e3
+        res = {"load": load, "offered_req_per_s": round(rate, 2),
+               "served": {"p50_ms": round(1e3 * percentile(lat, 50), 3),
+                          "p99_ms": round(1e3 * percentile(lat, 99), 3),
+                          "tuples_per_s": round(tuples / span, 1), "span_ms": round(1e3 * span, 3)},
+               "single_instance_path": {"p50_ms": round(1e3 * percentile(plain_lat, 50), 3),
+                                        "p99_ms": round(1e3 * percentile(plain_lat, 99), 3),
+                                        "tuples_per_s": round(plain_tuples / fin, 1),
+                                        "span_ms": round(1e3 * fin, 3)}}
+        progress(f"load {load}: {res}")
+        return res, tuples, span
+
+    sweep = []
+    for load in sorted(set([args.load, 1.0, 1.5])):
+        res, tuples_l, span_l = at_load(load)
+        sweep.append(res)
+        if load == args.load:
+            head, tuples, span = res, tuples_l, span_l
+    stats = srv.stats()
+    srv.close()
+    rate = head["offered_req_per_s"]
+    out = {
+        "metric": "derived tuples/sec per TC/SG fixpoint; p50/p99 served latency",
+        "value": round(tuples / span, 1),
+        "unit": "tuples/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 2 * args.slots,
+        "ms_per_step": round(1e3 * span, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32/u64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT["served_mix"], "name": "served_mix",
+                   "requests": len(reqs), "slots": args.slots, "edges": int(sum(len(r.src) for r in reqs)),
+                   "tc_requests": sum(r.query == "tc" for r in reqs),
+                   "offered_rate_per_s": round(rate, 2), "load": args.load},
+        "served": dict(head["served"], max_running=stats["max_running"], requeued=stats["requeued"],
+                       failed=stats["failed"]),
+        "single_instance_path": dict(head["single_instance_path"],
+                                     capacity_req_per_s=round(capacity, 2),
+                                     service_ms_p50=round(1e3 * percentile(service, 50), 3),
+                                     service_ms_max=round(1e3 * max(service), 3)),
+        "load_sweep": sweep,
+        "roofline": None,
+        "cpu_baseline": None if args.no_cpu_baseline else served_cpu_baseline(reqs),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -110,6 +249,9 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(2)
+    if args.workload == "served_mix":
+        run_served(args)
+        return
     eng = wg.Engine(0)
     extra = {}
     if is_batch(args.workload):

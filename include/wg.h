@@ -50,7 +50,8 @@ typedef enum {
   WG_ERR_CAPACITY = 3,      /* the fixpoint needs more device memory than mem_budget_bytes */
   WG_ERR_DEVICE = 4,        /* a HIP call failed or a device wait expired; destroy the engine */
   WG_ERR_ITER_LIMIT = 5,    /* max_iterations reached before the fixpoint */
-  WG_ERR_STALE = 6          /* the result belongs to an earlier solve of this engine */
+  WG_ERR_STALE = 6,         /* the result belongs to an earlier solve of this engine */
+  WG_ERR_CANCELLED = 7      /* a served request was cancelled */
 } wg_status;
 
 typedef enum { WG_QUERY_TC = 0, WG_QUERY_SG = 1 } wg_query;
@@ -175,7 +176,9 @@ uint64_t wg_result_size(const wg_result* result);
 wg_status wg_result_copy(const wg_result* result, uint32_t* src_out, uint32_t* dst_out,
                          uint64_t capacity, void* stream);
 
-/* Release a result handle (the storage belongs to the engine until its next solve). */
+/* Release a result handle.  An engine's result lives in the engine's buffers until its
+ * next solve; a served result owns a device copy, freed in order on the null stream
+ * (after copies enqueued on blocking streams). */
 void wg_result_free(wg_result* result);
 
 /* ----- Sort configuration and the autotuner (radix digit width and tile size).
@@ -213,6 +216,75 @@ wg_status wg_autotune(wg_engine* engine, int query, uint32_t num_instances, cons
                       const uint32_t* d_src, const uint32_t* d_dst, uint64_t m,
                       const wg_options* options, uint32_t repeats, void* stream,
                       wg_tune_report* report);
+
+/* ----- Serving: a request server with continuous batching (an addition to the paper's
+ * method, which evaluates one query at a time).
+ *
+ * The server owns `slots` engines, each with a worker thread and its own HIP stream, so
+ * the solves of different slots overlap on the device.  Requests queue up and are
+ * admitted to a free slot as soon as the device-memory budget allows: each reserves an
+ * estimate of its peak memory (bytes per edge, learned per query kind from finished
+ * solves).  The reservations of running solves, the buffers idle engines keep, resident
+ * results and queued inputs stay within mem_budget_bytes.  A solve that outgrows its
+ * reservation asks for more and waits while others hold the memory; when every running
+ * solve is waiting, the youngest gives up and is queued again with a larger reservation
+ * (the whole budget if need be: it then runs alone).  A request larger than the whole
+ * budget fails with WG_ERR_CAPACITY.  Results stay on the device until freed.  Each
+ * result is the same bytes as wg_tc / wg_sg on the same input alone.  Functions of one
+ * server may be called from any host threads. */
+typedef struct wg_server wg_server;
+typedef struct wg_job wg_job;
+
+typedef struct {
+  uint32_t slots;            /* concurrent solves, 1..16; 0 = 4 */
+  uint32_t reserved;
+  uint64_t mem_budget_bytes; /* device memory of all slots, results and inputs; 0 = 80% of free */
+} wg_server_config;
+
+typedef struct {
+  uint64_t submitted, completed, failed, cancelled, requeued;
+  uint32_t slots;
+  uint32_t max_running;   /* most solves that ran at once */
+  uint32_t queued;        /* requests waiting now */
+  uint32_t reserved;
+  uint64_t budget_bytes;
+  uint64_t held_bytes;    /* resident results and queued inputs now */
+  double busy_ms;         /* summed wall time of all solves */
+} wg_server_stats;
+
+typedef struct {
+  wg_status status;       /* final status once phase == 2 */
+  uint32_t phase;         /* 0 queued, 1 running, 2 done */
+  uint32_t query;         /* WG_QUERY_* */
+  uint32_t requeues;      /* times the request was queued again with a larger reservation */
+  uint64_t reservation_bytes;
+  uint64_t peak_bytes;    /* engine memory high-water mark of the solve */
+  double submit_ms, start_ms, end_ms; /* server clock (ms since wg_server_create) */
+} wg_job_info;
+
+wg_status wg_server_create(int device, const wg_server_config* config /* nullable */,
+                           wg_server** out);
+/* Cancels queued requests, lets running solves stop at their next host check, joins the
+ * workers.  Results already handed out stay valid until freed. */
+void wg_server_destroy(wg_server* server);
+
+/* Queue a TC or SG solve of m edges.  src / dst are device or host pointers; they are
+ * copied (on a stream of the server) before the call returns, so device inputs must be
+ * complete when it is made.  options as for wg_tc (mem_budget_bytes is set by the
+ * server). */
+wg_status wg_submit(wg_server* server, int query, const uint32_t* src, const uint32_t* dst,
+                    uint64_t m, const wg_options* options, wg_job** out);
+wg_status wg_poll(wg_job* job, int* done);
+/* Block until the request is done; returns its status.  On WG_OK *out (nullable) receives
+ * the result, which the caller frees with wg_result_free (once per job). */
+wg_status wg_wait(wg_job* job, wg_result** out, wg_stats* stats);
+/* A queued request ends at once with WG_ERR_CANCELLED; a running one at its next host
+ * check. */
+wg_status wg_cancel(wg_job* job);
+wg_status wg_job_get_info(const wg_job* job, wg_job_info* info);
+/* Release the handle (cancels the request if it has not finished). */
+void wg_job_free(wg_job* job);
+wg_status wg_server_get_stats(const wg_server* server, wg_server_stats* out);
 
 /* Static text for a status code. */
 const char* wg_status_string(wg_status status);

@@ -10,12 +10,14 @@
 
 #include <algorithm>
 #include <chrono>
+#include <functional>
 #include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
 
 #include "../../include/wg.h"
+#include "wg_internal.h"
 #include "wg_launch.h"
 
 using namespace wg;
@@ -58,7 +60,10 @@ struct wg_engine {
   uint32_t* d_rtot = nullptr;
   DevBuf cand[2], full[2], delta[2], E, U, R, Edst, rowa, rowb, off, rec;
   size_t allocated = 0;
+  size_t peak = 0;
   uint64_t budget = 0;
+  GrowHook grow_hook;  // request server: asked for more budget before a solve fails
+  const std::atomic<bool>* cancel = nullptr;  // request server: stop at the next host check
   uint64_t generation = 0;
   std::string err;
   // per-solve
@@ -86,13 +91,19 @@ struct wg_engine {
 };
 
 struct wg_result {
-  wg_engine* engine;
+  wg_engine* engine;  // engine whose buffers hold the keys (nullptr: `owned` holds them)
   uint64_t generation;
   uint64_t n;
   int w;
   uint32_t key_bytes;
   const void* keys;
   uint32_t num_inst;  // instances (1 for a single solve)
+  // results detached from their engine (request server)
+  void* owned = nullptr;
+  uint64_t owned_bytes = 0;
+  int device = 0;
+  Grid grid{};
+  std::function<void(uint64_t)> release;
 };
 
 namespace {
@@ -125,8 +136,11 @@ void free_buf(wg_engine* e, DevBuf& b) {
 void alloc_buf(wg_engine* e, DevBuf& b, size_t bytes) {
   bytes = (bytes + 255) & ~size_t(255);
   if (bytes == 0) bytes = 256;
-  if (e->budget && e->allocated + bytes > e->budget)
-    fail(e, WG_ERR_CAPACITY, "device memory budget exceeded");
+  if (e->budget && e->allocated + bytes > e->budget) {
+    const uint64_t granted = e->grow_hook ? e->grow_hook(e->allocated + bytes) : 0;
+    if (granted < e->allocated + bytes) fail(e, WG_ERR_CAPACITY, "device memory budget exceeded");
+    e->budget = granted;
+  }
   void* p = nullptr;
   hipError_t r = hipMalloc(&p, bytes);
   if (r != hipSuccess) {
@@ -136,6 +150,7 @@ void alloc_buf(wg_engine* e, DevBuf& b, size_t bytes) {
   b.p = p;
   b.bytes = bytes;
   e->allocated += bytes;
+  e->peak = std::max(e->peak, e->allocated);
 }
 
 // Ensure capacity without keeping contents.
@@ -477,6 +492,10 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
     enqueue_iters(std::min(K_batch, kSpec));
     r = wait_back(e, slot);
     if (r.c.overflow | r.c.done | r.c.limit_hit) sync_stream(e);
+    if (e->cancel && e->cancel->load()) {
+      sync_stream(e);
+      fail(e, WG_ERR_CANCELLED, "cancelled");
+    }
     if (r.c.overflow) {
       grow_and_resume(e, r.c, hooked);
       if (st) st->resumes++;
@@ -628,6 +647,7 @@ wg_status solve(wg_engine* e, int query, uint32_t num, const uint64_t* d_offsets
     e->res_n = 0;
     e->syncs = 0;
     e->budget = o.mem_budget_bytes;
+    e->peak = e->allocated;
     e->timing = (o.flags & WG_STAGE_TIMING) != 0;
     e->timing_mask = o.timing_stages ? o.timing_stages : 0xFFFFFFFFu;
     e->n_events = 0;
@@ -679,7 +699,95 @@ wg_status solve(wg_engine* e, int query, uint32_t num, const uint64_t* d_offsets
   }
 }
 
+// ----- result handles: engine-backed (valid until the engine's next solve) or owned
+wg_status check_result(const wg_result* r) {
+  if (!r) return WG_ERR_INVALID_ARG;
+  if (r->owned || r->n == 0) return WG_OK;
+  if (!r->engine) return WG_ERR_INVALID_ARG;
+  if (r->generation != r->engine->generation) {
+    r->engine->err = "result is stale: the engine ran another solve";
+    return WG_ERR_STALE;
+  }
+  return WG_OK;
+}
+
+void note(const wg_result* r, const char* msg) {
+  if (r->engine) r->engine->err = msg;
+}
+
+wg_status device_error(const wg_result* r, const char* what) {
+  const hipError_t err = hipGetLastError();
+  if (r->engine) r->engine->err = std::string(what) + ": " + hipGetErrorString(err);
+  return WG_ERR_DEVICE;
+}
+
+int result_device(const wg_result* r) { return r->engine ? r->engine->device : r->device; }
+Grid result_grid(const wg_result* r) { return r->engine ? r->engine->grid : r->grid; }
+
 }  // namespace
+
+namespace wg {
+
+wg_status engine_solve(wg_engine* e, int query, uint32_t num, const uint64_t* d_offsets,
+                       const uint32_t* src, const uint32_t* dst, uint64_t m, const wg_options* o,
+                       void* stream, wg_result** out, wg_stats* st) {
+  return solve(e, query, num, d_offsets, src, dst, m, o, stream, out, st);
+}
+
+uint64_t engine_allocated(const wg_engine* e) { return e->allocated; }
+uint64_t engine_peak(const wg_engine* e) { return e->peak; }
+void engine_set_grow_hook(wg_engine* e, GrowHook hook) { e->grow_hook = std::move(hook); }
+void engine_set_cancel(wg_engine* e, const std::atomic<bool>* flag) { e->cancel = flag; }
+
+void engine_trim(wg_engine* e) {
+  try {
+    hip_check(e, hipSetDevice(e->device), "hipSetDevice");
+    if (e->stream) hip_check(e, hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+    for (int s = 0; s < 2; ++s) {
+      free_buf(e, e->cand[s]);
+      free_buf(e, e->full[s]);
+      free_buf(e, e->delta[s]);
+    }
+    for (DevBuf* b : {&e->E, &e->U, &e->R, &e->Edst, &e->rowa, &e->rowb, &e->off, &e->rec}) free_buf(e, *b);
+  } catch (const Fail&) {
+  }
+  e->cand_cap = e->full_cap = e->edge_cap = e->row_cap = e->rec_cap = 0;
+  e->generation++;
+  e->res_keys = nullptr;
+  e->res_n = 0;
+}
+
+wg_status result_detach(const wg_result* r, hipStream_t s, std::function<void(uint64_t)> release,
+                        wg_result** out, uint64_t* bytes) {
+  const wg_status v = check_result(r);
+  if (v != WG_OK) return v;
+  wg_result* c = new wg_result(*r);
+  c->engine = nullptr;
+  c->device = result_device(r);
+  c->grid = result_grid(r);
+  c->owned_bytes = std::max<uint64_t>(r->n * r->key_bytes, 256);
+  if (hipSetDevice(c->device) != hipSuccess || hipMallocAsync(&c->owned, c->owned_bytes, s) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return WG_ERR_OUT_OF_MEMORY;
+  }
+  hipError_t err = hipSuccess;
+  if (r->n) err = hipMemcpyAsync(c->owned, r->keys, r->n * r->key_bytes, hipMemcpyDeviceToDevice, s);
+  if (err == hipSuccess) err = hipStreamSynchronize(s);
+  if (err != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFreeAsync(c->owned, s);
+    delete c;
+    return WG_ERR_DEVICE;
+  }
+  c->keys = c->owned;
+  c->release = std::move(release);
+  if (bytes) *bytes = c->owned_bytes;
+  *out = c;
+  return WG_OK;
+}
+
+}  // namespace wg
 
 extern "C" {
 
@@ -911,90 +1019,81 @@ wg_status wg_autotune(wg_engine* e, int query, uint32_t num_instances, const uin
 }
 
 wg_status wg_result_offsets(const wg_result* r, uint64_t* offsets_out, uint64_t capacity, void* stream) {
-  if (!r || !r->engine) return WG_ERR_INVALID_ARG;
-  wg_engine* e = r->engine;
-  if (r->generation != e->generation) {
-    e->err = "result is stale: the engine ran another solve";
-    return WG_ERR_STALE;
-  }
+  const wg_status v = check_result(r);
+  if (v != WG_OK) return v;
   if (!offsets_out || capacity < (uint64_t)r->num_inst + 1) {
-    e->err = "offsets array missing or shorter than instances + 1";
+    note(r, "offsets array missing or shorter than instances + 1");
     return WG_ERR_INVALID_ARG;
   }
   hipStream_t s = (hipStream_t)stream;
-  try {
-    hip_check(e, hipSetDevice(e->device), "hipSetDevice");
-    const bool host = !is_device_pointer(offsets_out);
-    uint64_t* dst = offsets_out;
-    if (host) hip_check(e, hipMalloc((void**)&dst, ((uint64_t)r->num_inst + 1) * 8), "hipMalloc");
-    if (r->key_bytes == 4)
-      launch_offsets<uint32_t>(s, e->grid, (const uint32_t*)r->keys, r->n, 2 * r->w, r->num_inst, dst);
-    else
-      launch_offsets<uint64_t>(s, e->grid, (const uint64_t*)r->keys, r->n, 2 * r->w, r->num_inst, dst);
-    if (host) {
-      hipError_t e1 = hipMemcpyAsync(offsets_out, dst, ((uint64_t)r->num_inst + 1) * 8,
-                                     hipMemcpyDeviceToHost, s);
-      hipError_t e2 = hipStreamSynchronize(s);
-      (void)hipFree(dst);
-      hip_check(e, e1, "copy");
-      hip_check(e, e2, "sync");
-    } else {
-      hip_check(e, hipGetLastError(), "offsets launch");
-    }
-    return WG_OK;
-  } catch (const Fail& f) {
-    return f.st;
+  const uint64_t bytes = ((uint64_t)r->num_inst + 1) * 8;
+  if (hipSetDevice(result_device(r)) != hipSuccess) return device_error(r, "hipSetDevice");
+  const bool host = !is_device_pointer(offsets_out);
+  uint64_t* dst = offsets_out;
+  if (host && hipMalloc((void**)&dst, bytes) != hipSuccess) return device_error(r, "hipMalloc");
+  const Grid g = result_grid(r);
+  if (r->key_bytes == 4)
+    launch_offsets<uint32_t>(s, g, (const uint32_t*)r->keys, r->n, 2 * r->w, r->num_inst, dst);
+  else
+    launch_offsets<uint64_t>(s, g, (const uint64_t*)r->keys, r->n, 2 * r->w, r->num_inst, dst);
+  hipError_t err = hipGetLastError();
+  if (host) {
+    if (err == hipSuccess) err = hipMemcpyAsync(offsets_out, dst, bytes, hipMemcpyDeviceToHost, s);
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    (void)hipFree(dst);
   }
+  return err == hipSuccess ? WG_OK : device_error(r, "result offsets");
 }
 
 uint64_t wg_result_size(const wg_result* r) { return r ? r->n : 0; }
 
 wg_status wg_result_copy(const wg_result* r, uint32_t* src_out, uint32_t* dst_out, uint64_t capacity,
                          void* stream) {
-  if (!r || !r->engine) return WG_ERR_INVALID_ARG;
-  wg_engine* e = r->engine;
-  if (r->generation != e->generation) {
-    e->err = "result is stale: the engine ran another solve";
-    return WG_ERR_STALE;
-  }
+  const wg_status v = check_result(r);
+  if (v != WG_OK) return v;
   if (r->n == 0) return WG_OK;
   if (!src_out || !dst_out || capacity < r->n) {
-    e->err = "output arrays missing or too small";
+    note(r, "output arrays missing or too small");
     return WG_ERR_INVALID_ARG;
   }
   hipStream_t s = (hipStream_t)stream;
-  try {
-    hip_check(e, hipSetDevice(e->device), "hipSetDevice");
-    const bool host = !is_device_pointer(src_out);
-    Grid g = e->grid;
-    if (!host) {
-      if (r->key_bytes == 4)
-        launch_unpack<uint32_t>(s, g, (const uint32_t*)r->keys, r->n, r->w, src_out, dst_out);
-      else
-        launch_unpack<uint64_t>(s, g, (const uint64_t*)r->keys, r->n, r->w, src_out, dst_out);
-      hip_check(e, hipGetLastError(), "unpack launch");
-      return WG_OK;
-    }
-    uint32_t* tmp = nullptr;
-    hip_check(e, hipMalloc((void**)&tmp, r->n * 8), "hipMalloc");
-    if (r->key_bytes == 4)
-      launch_unpack<uint32_t>(s, g, (const uint32_t*)r->keys, r->n, r->w, tmp, tmp + r->n);
-    else
-      launch_unpack<uint64_t>(s, g, (const uint64_t*)r->keys, r->n, r->w, tmp, tmp + r->n);
-    hipError_t e1 = hipMemcpyAsync(src_out, tmp, r->n * 4, hipMemcpyDeviceToHost, s);
-    hipError_t e2 = hipMemcpyAsync(dst_out, tmp + r->n, r->n * 4, hipMemcpyDeviceToHost, s);
-    hipError_t e3 = hipStreamSynchronize(s);
-    (void)hipFree(tmp);
-    hip_check(e, e1, "copy");
-    hip_check(e, e2, "copy");
-    hip_check(e, e3, "sync");
-    return WG_OK;
-  } catch (const Fail& f) {
-    return f.st;
+  if (hipSetDevice(result_device(r)) != hipSuccess) return device_error(r, "hipSetDevice");
+  const bool host = !is_device_pointer(src_out);
+  const Grid g = result_grid(r);
+  uint32_t* ds = src_out;
+  uint32_t* dd = dst_out;
+  uint32_t* tmp = nullptr;
+  if (host) {
+    if (hipMalloc((void**)&tmp, r->n * 8) != hipSuccess) return device_error(r, "hipMalloc");
+    ds = tmp;
+    dd = tmp + r->n;
   }
+  if (r->key_bytes == 4)
+    launch_unpack<uint32_t>(s, g, (const uint32_t*)r->keys, r->n, r->w, ds, dd);
+  else
+    launch_unpack<uint64_t>(s, g, (const uint64_t*)r->keys, r->n, r->w, ds, dd);
+  hipError_t err = hipGetLastError();
+  if (host) {
+    if (err == hipSuccess) err = hipMemcpyAsync(src_out, tmp, r->n * 4, hipMemcpyDeviceToHost, s);
+    if (err == hipSuccess) err = hipMemcpyAsync(dst_out, tmp + r->n, r->n * 4, hipMemcpyDeviceToHost, s);
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    (void)hipFree(tmp);
+  }
+  return err == hipSuccess ? WG_OK : device_error(r, "result copy");
 }
 
-void wg_result_free(wg_result* r) { delete r; }
+void wg_result_free(wg_result* r) {
+  if (!r) return;
+  if (r->owned) {
+    // stream-ordered on the null stream: after the copies callers enqueued on blocking
+    // streams, without waiting for the whole device
+    (void)hipSetDevice(r->device);
+    (void)hipFreeAsync(r->owned, nullptr);
+    if (r->release) r->release(r->owned_bytes);
+  }
+  delete r;
+}
+
 
 const char* wg_status_string(wg_status s) {
   switch (s) {
@@ -1005,6 +1104,7 @@ const char* wg_status_string(wg_status s) {
     case WG_ERR_DEVICE: return "device error";
     case WG_ERR_ITER_LIMIT: return "iteration limit reached";
     case WG_ERR_STALE: return "stale result";
+    case WG_ERR_CANCELLED: return "cancelled";
   }
   return "unknown status";
 }

@@ -267,3 +267,37 @@ def batch_workload(name: str) -> tuple[str, Batch]:
     if name == "sg_batch_er_256":
         return "sg", er_batch(256, seed=7, n_lo=64, n_hi=4096)
     raise KeyError(name)
+
+
+@dataclass(frozen=True)
+class Request:
+    """One served request: a TC or SG query on a seeded graph."""
+    query: str
+    kind: str  # "er" or "rmat"
+    n: int
+    src: np.ndarray
+    dst: np.ndarray
+
+
+def served_requests(num: int, seed: int, n_lo: int = 1000, n_hi: int = 1_000_000,
+                    rmat_max_scale: int = 15, tc_share: float = 0.7) -> list:
+    """The served mix: 70% TC / 30% SG, half ER and half R-MAT (0.57, 0.19, 0.19, 0.05),
+    n log-uniform in [n_lo, n_hi], mean out-degree uniform in [0.5, 0.95].  R-MAT graphs
+    take scale round(log2 n) capped at rmat_max_scale (larger R-MAT closures do not fit
+    one device) and at least 4; m = round(degree * 2^scale)."""
+    rng = _rng(0x5352, seed, num)
+    out = []
+    for i in range(num):
+        query = "tc" if rng.random() < tc_share else "sg"
+        kind = "er" if rng.random() < 0.5 else "rmat"
+        n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        deg = float(rng.uniform(0.5, 0.95))
+        sub = seed * 1_000_003 + i
+        if kind == "er":
+            s, d = erdos_renyi(n, max(1, int(round(deg * n))), seed=sub)
+        else:
+            scale = min(rmat_max_scale, max(4, int(round(math.log2(n)))))
+            n = 1 << scale
+            s, d = rmat(scale, max(1, int(round(deg * n))), *RMAT_ABCD, seed=sub)
+        out.append(Request(query, kind, n, s, d))
+    return out

@@ -24,6 +24,7 @@ WG_ERR_CAPACITY = 3
 WG_ERR_DEVICE = 4
 WG_ERR_ITER_LIMIT = 5
 WG_ERR_STALE = 6
+WG_ERR_CANCELLED = 7
 
 WG_SG_IRREFLEXIVE = 0x1
 WG_STAGE_TIMING = 0x2
@@ -106,6 +107,31 @@ class WgTuneReport(ctypes.Structure):
                            for i in range(int(self.trials))]}
 
 
+class WgServerConfig(ctypes.Structure):
+    _fields_ = [("slots", c_uint32), ("reserved", c_uint32), ("mem_budget_bytes", c_uint64)]
+
+
+class WgServerStats(ctypes.Structure):
+    _fields_ = [("submitted", c_uint64), ("completed", c_uint64), ("failed", c_uint64),
+                ("cancelled", c_uint64), ("requeued", c_uint64), ("slots", c_uint32),
+                ("max_running", c_uint32), ("queued", c_uint32), ("reserved", c_uint32),
+                ("budget_bytes", c_uint64), ("held_bytes", c_uint64), ("busy_ms", c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: (float(getattr(self, k)) if k == "busy_ms" else int(getattr(self, k)))
+                for k, _ in self._fields_ if k != "reserved"}
+
+
+class WgJobInfo(ctypes.Structure):
+    _fields_ = [("status", c_int), ("phase", c_uint32), ("query", c_uint32), ("requeues", c_uint32),
+                ("reservation_bytes", c_uint64), ("peak_bytes", c_uint64), ("submit_ms", c_double),
+                ("start_ms", c_double), ("end_ms", c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: (float(getattr(self, k)) if k.endswith("_ms") else int(getattr(self, k)))
+                for k, _ in self._fields_}
+
+
 class WgError(RuntimeError):
     def __init__(self, status: int, detail: str):
         super().__init__(f"{_status_name(status)}: {detail}")
@@ -132,6 +158,16 @@ SIGNATURES = [
     ("wg_set_sort_config", c_int, [c_void_p, c_uint32, POINTER(WgSortConfig)]),
     ("wg_autotune", c_int, [c_void_p, c_int, c_uint32, c_void_p, c_void_p, c_void_p, c_uint64,
                             POINTER(WgOptions), c_uint32, c_void_p, POINTER(WgTuneReport)]),
+    ("wg_server_create", c_int, [c_int, POINTER(WgServerConfig), POINTER(c_void_p)]),
+    ("wg_server_destroy", None, [c_void_p]),
+    ("wg_submit", c_int, [c_void_p, c_int, c_void_p, c_void_p, c_uint64, POINTER(WgOptions),
+                          POINTER(c_void_p)]),
+    ("wg_poll", c_int, [c_void_p, POINTER(c_int)]),
+    ("wg_wait", c_int, [c_void_p, POINTER(c_void_p), POINTER(WgStats)]),
+    ("wg_cancel", c_int, [c_void_p]),
+    ("wg_job_get_info", c_int, [c_void_p, POINTER(WgJobInfo)]),
+    ("wg_job_free", None, [c_void_p]),
+    ("wg_server_get_stats", c_int, [c_void_p, POINTER(WgServerStats)]),
     ("wg_result_size", c_uint64, [c_void_p]),
     ("wg_result_copy", c_int, [c_void_p, c_void_p, c_void_p, c_uint64, c_void_p]),
     ("wg_result_free", None, [c_void_p]),
@@ -243,6 +279,59 @@ def wg_autotune(engine, query: int, num: int, d_offsets: int, d_src: int, d_dst:
                            m, byref(options) if options is not None else None, repeats,
                            c_void_p(stream), byref(rep))
     return st, rep
+
+
+def wg_server_create(device: int = 0, slots: int = 0, mem_budget_bytes: int = 0) -> c_void_p:
+    srv = c_void_p()
+    st = lib().wg_server_create(device, byref(WgServerConfig(slots, 0, mem_budget_bytes)), byref(srv))
+    if st != WG_OK:
+        raise WgError(st, f"wg_server_create(device={device})")
+    return srv
+
+
+def wg_server_destroy(server) -> None:
+    lib().wg_server_destroy(server)
+
+
+def wg_submit(server, query: int, src: int, dst: int, m: int, options: WgOptions | None):
+    """Returns (status, job handle); src / dst are device or host addresses."""
+    job = c_void_p()
+    st = lib().wg_submit(server, query, c_void_p(src), c_void_p(dst), m,
+                         byref(options) if options is not None else None, byref(job))
+    return st, job
+
+
+def wg_poll(job) -> tuple[int, bool]:
+    done = c_int(0)
+    st = lib().wg_poll(job, byref(done))
+    return st, bool(done.value)
+
+
+def wg_wait(job, stats: WgStats | None = None):
+    """Returns (status, result handle or None)."""
+    res = c_void_p()
+    st = lib().wg_wait(job, byref(res), byref(stats) if stats is not None else None)
+    return st, res
+
+
+def wg_cancel(job) -> int:
+    return lib().wg_cancel(job)
+
+
+def wg_job_get_info(job) -> WgJobInfo:
+    info = WgJobInfo()
+    lib().wg_job_get_info(job, byref(info))
+    return info
+
+
+def wg_job_free(job) -> None:
+    lib().wg_job_free(job)
+
+
+def wg_server_get_stats(server) -> WgServerStats:
+    out = WgServerStats()
+    lib().wg_server_get_stats(server, byref(out))
+    return out
 
 
 def wg_result_size(result) -> int:
@@ -437,3 +526,109 @@ class Engine:
 
     def sg(self, src, dst, options=None, **kw):
         return self.solve("sg", src, dst, options, **kw)
+
+
+class Job:
+    """A request submitted to a Server."""
+
+    def __init__(self, server: "Server", handle):
+        self.server = server
+        self.handle = handle
+
+    def done(self) -> bool:
+        return wg_poll(self.handle)[1]
+
+    def cancel(self) -> None:
+        wg_cancel(self.handle)
+
+    def info(self) -> dict:
+        return wg_job_get_info(self.handle).as_dict()
+
+    def wait(self, want_result: bool = True, max_deltas: int = 1 << 16):
+        """Block until done; returns (src, dst, stats, info).  Raises WgError on failure."""
+        import torch
+
+        stats = WgStats()
+        deltas = (c_uint64 * max_deltas)()
+        stats.delta_sizes = deltas
+        stats.delta_sizes_cap = max_deltas
+        st, res = wg_wait(self.handle, stats)
+        info = self.info()
+        if st != WG_OK:
+            raise WgError(st, "served request failed")
+        device = torch.device("cuda", self.server.device)
+        stream = torch.cuda.current_stream(device).cuda_stream
+        try:
+            n = wg_result_size(res)
+            out_s = out_d = None
+            if want_result:
+                out_s = torch.empty(n, dtype=torch.uint32, device=device)
+                out_d = torch.empty(n, dtype=torch.uint32, device=device)
+                if n:
+                    st = wg_result_copy(res, out_s.data_ptr(), out_d.data_ptr(), n, stream)
+                    if st != WG_OK:
+                        raise WgError(st, "result copy")
+        finally:
+            wg_result_free(res)
+        return out_s, out_d, stats_dict(stats, deltas), info
+
+    def close(self) -> None:
+        if self.handle is not None:
+            wg_job_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+
+class Server:
+    """Continuous-batching request server (wg_server_*) on one device."""
+
+    def __init__(self, device: int = 0, slots: int = 0, mem_budget_bytes: int = 0):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("the request server needs a ROCm GPU")
+        self.device = device
+        self.handle = wg_server_create(device, slots, mem_budget_bytes)
+
+    def submit(self, query: str, src, dst, options: WgOptions | None = None) -> Job:
+        """src / dst: torch tensors (GPU or CPU) or numpy arrays of uint32 ids."""
+        import numpy as np
+
+        keep = []
+        ptrs = []
+        for a in (src, dst):
+            if isinstance(a, np.ndarray):
+                a = np.ascontiguousarray(a, dtype=np.uint32)
+                keep.append(a)
+                ptrs.append(a.ctypes.data)
+            else:
+                a = a.contiguous()
+                keep.append(a)
+                ptrs.append(a.data_ptr())
+        m = len(keep[0])
+        if len(keep[1]) != m:
+            raise ValueError("src and dst differ in length")
+        q = WG_QUERY_TC if query == "tc" else WG_QUERY_SG
+        st, job = wg_submit(self.handle, q, ptrs[0], ptrs[1], m, options)
+        if st != WG_OK:
+            raise WgError(st, "wg_submit")
+        return Job(self, job)
+
+    def stats(self) -> dict:
+        return wg_server_get_stats(self.handle).as_dict()
+
+    def close(self) -> None:
+        if self.handle is not None:
+            wg_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass

@@ -30,7 +30,9 @@ def test_header_declares_the_entry_points():
     for required in ["wg_engine_create", "wg_engine_destroy", "wg_tc", "wg_sg", "wg_result_size",
                      "wg_result_copy", "wg_result_free", "wg_status_string", "wg_last_error",
                      "wg_tc_batch", "wg_sg_batch", "wg_result_offsets", "wg_result_instances",
-                     "wg_autotune", "wg_get_sort_config", "wg_set_sort_config"]:
+                     "wg_autotune", "wg_get_sort_config", "wg_set_sort_config",
+                     "wg_server_create", "wg_server_destroy", "wg_submit", "wg_poll", "wg_wait",
+                     "wg_cancel", "wg_job_get_info", "wg_job_free", "wg_server_get_stats"]:
         assert required in names
 
 
@@ -69,6 +71,10 @@ int main(void) {
   F(wg_stats, digit_bits); F(wg_stats, sort_passes);
   S(wg_sort_config); S(wg_tune_report); F(wg_tune_report, best); F(wg_tune_report, best_ms);
   F(wg_tune_report, tried); F(wg_tune_report, tried_ms);
+  S(wg_server_config); F(wg_server_config, mem_budget_bytes);
+  S(wg_server_stats); F(wg_server_stats, slots); F(wg_server_stats, budget_bytes);
+  F(wg_server_stats, busy_ms);
+  S(wg_job_info); F(wg_job_info, reservation_bytes); F(wg_job_info, submit_ms); F(wg_job_info, end_ms);
   return 0;
 }
 """
@@ -91,7 +97,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
                                                          check=True).stdout.splitlines())
     types = {"wg_options": wg.WgOptions, "wg_stats": wg.WgStats, "wg_sort_config": wg.WgSortConfig,
-             "wg_tune_report": wg.WgTuneReport}
+             "wg_tune_report": wg.WgTuneReport, "wg_server_config": wg.WgServerConfig,
+             "wg_server_stats": wg.WgServerStats, "wg_job_info": wg.WgJobInfo}
     for key, val in got.items():
         if "." in key:
             t, f = key.split(".")

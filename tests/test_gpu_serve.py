@@ -1,0 +1,125 @@
+"""Request server (wg_server_*): continuous batching keeps every result exact.
+
+Each served result must be byte-identical to the same request solved alone through
+wg_tc / wg_sg, and to the oracle.  Admission under a tight memory budget, requeueing,
+rejection of an oversize request, cancellation and host-pointer inputs are covered.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2607_17571_amd import inputs
+from paper_2607_17571_amd import wg
+from tests.gpu_util import run as run_single
+from tests.gpu_util import to_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def served(server, reqs, host=False):
+    jobs = []
+    for r in reqs:
+        if host:
+            jobs.append(server.submit(r.query, r.src, r.dst))
+        else:
+            jobs.append(server.submit(r.query, to_gpu(r.src), to_gpu(r.dst)))
+    out = []
+    for j in jobs:
+        s, d, st, info = j.wait()
+        out.append((s.cpu().numpy(), d.cpu().numpy(), st, info))
+        j.close()
+    return out
+
+
+def test_alone_equals_in_mix(engine):
+    reqs = inputs.served_requests(24, seed=21, n_lo=100, n_hi=3000)
+    print(f"[gpu] serve mix of {len(reqs)}", flush=True, file=sys.stderr)
+    srv = wg.Server(0, slots=4, mem_budget_bytes=8 << 30)
+    try:
+        mix = served(srv, reqs)
+        stats = srv.stats()
+    finally:
+        srv.close()
+    for r, (s, d, st, info) in zip(reqs, mix):
+        a_s, a_d, a_st = run_single(engine, r.query, r.src, r.dst)
+        np.testing.assert_array_equal(s, a_s)
+        np.testing.assert_array_equal(d, a_d)
+        assert st["iterations"] == a_st["iterations"]
+        assert st["delta_sizes"] == a_st["delta_sizes"]
+        ref = oracle.tc(r.src, r.dst) if r.query == "tc" else oracle.sg(r.src, r.dst)
+        np.testing.assert_array_equal(s, ref.src)
+        np.testing.assert_array_equal(d, ref.dst)
+        assert info["phase"] == 2 and info["status"] == wg.WG_OK
+        assert info["submit_ms"] <= info["start_ms"] <= info["end_ms"]
+    assert stats["completed"] == len(reqs) and stats["failed"] == 0
+    assert stats["held_bytes"] == 0  # every result freed
+
+
+def test_tight_budget_requeues_and_rejects_oversize(engine):
+    """A 320 MB budget: medium requests must share it; one request needs far more."""
+    reqs = [inputs.Request("tc", "rmat", 1 << 12, *inputs.rmat(12, 3800, *inputs.RMAT_ABCD, seed=s))
+            for s in (31, 32, 33)]
+    reqs += [inputs.Request("sg", "rmat", 1 << 11, *inputs.rmat(11, 1900, *inputs.RMAT_ABCD, seed=34))]
+    big = inputs.workload("tc_rmat_s15")
+    print("[gpu] serve under a tight budget", flush=True, file=sys.stderr)
+    srv = wg.Server(0, slots=3, mem_budget_bytes=320 << 20)
+    try:
+        jobs = [srv.submit(r.query, to_gpu(r.src), to_gpu(r.dst)) for r in reqs]
+        jbig = srv.submit("tc", to_gpu(big.src), to_gpu(big.dst))
+        results = [j.wait() for j in jobs]
+        with pytest.raises(wg.WgError) as ei:
+            jbig.wait()
+        assert ei.value.status == wg.WG_ERR_CAPACITY
+        stats = srv.stats()
+        for j in jobs + [jbig]:
+            j.close()
+    finally:
+        srv.close()
+    for r, (s, d, st, info) in zip(reqs, results):
+        ref = oracle.tc(r.src, r.dst) if r.query == "tc" else oracle.sg(r.src, r.dst)
+        np.testing.assert_array_equal(s.cpu().numpy(), ref.src)
+        np.testing.assert_array_equal(d.cpu().numpy(), ref.dst)
+    assert stats["completed"] == len(reqs) and stats["failed"] == 1
+
+
+def test_cancel_queued_request(engine):
+    srv = wg.Server(0, slots=1, mem_budget_bytes=4 << 30)
+    try:
+        g = inputs.grid_dag(60)
+        first = srv.submit("tc", to_gpu(g[0]), to_gpu(g[1]))  # keeps the only slot busy
+        small = [srv.submit("tc", *map(to_gpu, inputs.chain(20 + k))) for k in range(4)]
+        small[2].cancel()
+        with pytest.raises(wg.WgError) as ei:
+            small[2].wait()
+        assert ei.value.status == wg.WG_ERR_CANCELLED
+        first.wait()
+        for k in (0, 1, 3):
+            s, d, st, _ = small[k].wait()
+            ref = oracle.tc(*inputs.chain(20 + k))
+            np.testing.assert_array_equal(s.cpu().numpy(), ref.src)
+        stats = srv.stats()
+        for j in [first] + small:
+            j.close()
+    finally:
+        srv.close()
+    assert stats["cancelled"] == 1
+
+
+def test_host_pointer_inputs_and_empty_request(engine):
+    reqs = inputs.served_requests(6, seed=22, n_lo=50, n_hi=500)
+    srv = wg.Server(0, slots=2, mem_budget_bytes=2 << 30)
+    try:
+        host = served(srv, reqs, host=True)
+        e = srv.submit("tc", np.empty(0, np.uint32), np.empty(0, np.uint32))
+        s, d, st, _ = e.wait()
+        assert s.numel() == 0 and st["iterations"] == 0
+        e.close()
+    finally:
+        srv.close()
+    for r, (s, d, st, info) in zip(reqs, host):
+        ref = oracle.tc(r.src, r.dst) if r.query == "tc" else oracle.sg(r.src, r.dst)
+        np.testing.assert_array_equal(s, ref.src)
+        np.testing.assert_array_equal(d, ref.dst)
