@@ -17,9 +17,12 @@ Batched workloads (tc_batch_er_4096: 4,096 ER instances in one solve) first run 
 autotuner on the batch (outside the timed region), then also time the plain path: the
 same instances solved one at a time with wg_tc.
 
-The JSON line also carries the roofline of the dominant kernel (algorithmic bytes /
-HIP-event time of its launches in the timed region, against 8 TB/s HBM) and the CPU
-oracle timed on the host (test infrastructure, used only for this baseline).
+The JSON line also carries the roofline of the dominant kernel: its algorithmic bytes
+(include/wg.h, wg_stats.stage_bytes) over the HIP-event time of its launches, taken in a
+second run of the same K solves with events around that kernel only (events cost launch
+overlap, so the throughput figure comes from the run without them), against 8 TB/s of
+HBM; and the CPU oracle timed on the host (test infrastructure, used only for this
+baseline).
 """
 
 from __future__ import annotations
@@ -35,6 +38,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# kernels behind each timed stage kind (include/wg.h, WG_STAGE_*)
+STAGE_KERNELS = {
+    "join_count": "k_join_count", "join_emit": "k_join_emit",
+    "radix_hist": "k_radix_count + k_radix_scan", "radix_pass": "k_radix_scatter",
+    "dedup_diff": "k_compact_local + k_compact_gather", "merge": "k_merge",
+    "prepare": "k_max_id, k_pack, k_index_*, k_unpack",
+}
 WORKLOAD_TEXT = {
     "tc_rmat_s15": "TC, R-MAT scale 15 (n=32,768, m=29,491, a,b,c,d=0.57,0.19,0.19,0.05, seed 2); "
                    "stands in for R-MAT scale 22 whose ~3.9e11-tuple closure exceeds one GPU",
@@ -65,6 +75,12 @@ def parse():
     p.add_argument("--tile-items", type=int, default=0, help="sort tile keys per thread (0: engine's)")
     p.add_argument("--no-autotune", action="store_true", help="batched workloads: skip the autotuner")
     p.add_argument("--no-plain", action="store_true", help="batched workloads: skip the one-by-one path")
+    p.add_argument("--no-spec", action="store_true", help="no speculative batch behind host checks")
+    p.add_argument("--dominant", default=None, help="kernel kind to take the roofline of (skips the probe)")
+    p.add_argument("--roofline-only", action="store_true",
+                   help="run only the instrumented steps (value then comes from them); for profiling")
+    p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                   help="only copy MIB MiB device to device 10 times (counter calibration) and exit")
     p.add_argument("--requests", type=int, default=120, help="served_mix: number of requests")
     p.add_argument("--slots", type=int, default=4, help="served_mix: concurrent solves")
     p.add_argument("--load", type=float, default=0.7, help="served_mix: offered load / capacity")
@@ -249,6 +265,18 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(2)
+    if args.copy_calibration:
+        # a plain device-to-device copy of known size: what FETCH_SIZE / WRITE_SIZE read for
+        # it calibrates the counters against known bytes
+        n = args.copy_calibration << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty(n, dtype=torch.uint8, device="cuda")
+        a.fill_(1)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n, "copies": 10}), flush=True)
+        return
     if args.workload == "served_mix":
         run_served(args)
         return
@@ -281,45 +309,66 @@ def main():
             return st
 
     sort_opts = dict(radix_digit_bits=args.digit_bits, tile_items=args.tile_items)
+    base_flags = wg.WG_NO_SPECULATION if args.no_spec else 0
     for _ in range(args.warmup):
-        solve(wg.make_options(**sort_opts))
+        solve(wg.make_options(flags=base_flags, **sort_opts))
     torch.cuda.synchronize()
     # Untimed probe with events on every kernel kind: per-stage breakdown and the dominant
-    # kernel.  The timed region below records events around that kernel kind only.
-    probe = solve(wg.make_options(flags=wg.WG_STAGE_TIMING, **sort_opts))
-    dom = max(wg.STAGES, key=lambda k: probe["stage_ms"][k])
-    probe_ms = {k: round(v, 3) for k, v in probe["stage_ms"].items()}
-    flags = 0 if args.no_timing else wg.WG_STAGE_TIMING
-    opts = wg.make_options(flags=flags, timing_stages=1 << wg.STAGES.index(dom), **sort_opts)
-    torch.cuda.synchronize()
-    stage_ms = {k: 0.0 for k in wg.STAGES}
-    stage_bytes = {k: 0 for k in wg.STAGES}
-    stage_launches = {k: 0 for k in wg.STAGES}
+    # kernel kind, which the instrumented run after the timed region measures alone.
+    if args.dominant:
+        if args.dominant not in wg.STAGES:
+            raise SystemExit(f"--dominant must be one of {wg.STAGES}")
+        dom, probe_ms = args.dominant, None
+    else:
+        probe = solve(wg.make_options(flags=wg.WG_STAGE_TIMING | base_flags, **sort_opts))
+        dom = max(wg.STAGES, key=lambda k: probe["stage_ms"][k])
+        probe_ms = {k: round(v, 3) for k, v in probe["stage_ms"].items()}
     tuples = 0
     st = None
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        st = solve(opts)
-        tuples += st["result_tuples"]
-        for k in wg.STAGES:
-            stage_ms[k] += st["stage_ms"][k]
-            stage_bytes[k] += st["stage_bytes"][k]
-            stage_launches[k] += st["stage_launches"][k]
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = tuples / elapsed
+    ms_per_step = value = None
+    if not args.roofline_only:
+        # timed region: K whole solves, no instrumentation
+        clean = wg.make_options(flags=base_flags, **sort_opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            st = solve(clean)
+            tuples += st["result_tuples"]
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        ms_per_step = 1e3 * elapsed / args.steps
+        value = tuples / elapsed
 
     roofline = None
     if not args.no_timing:
-        secs = stage_ms[dom] / 1e3
-        achieved = stage_bytes[dom] / secs / 1e9 if secs > 0 else 0.0
-        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": None,
-                    "avg_launch_us": round(1e3 * stage_ms[dom] / max(1, stage_launches[dom]), 2),
-                    "bytes_per_step": stage_bytes[dom] // args.steps,
-                    "launches_per_step": stage_launches[dom] // args.steps}
+        # the same K solves with HIP events stamped by the dispatches of the dominant kernel
+        # kind only (hipExtLaunchKernelGGL on the engine's stream); the stamping slows
+        # those kernels slightly, so the throughput comes from the run above
+        timed = wg.make_options(flags=wg.WG_STAGE_TIMING | base_flags,
+                                timing_stages=1 << wg.STAGES.index(dom), **sort_opts)
+        ms = nbytes = launches = inst_tuples = 0
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            sti = solve(timed)
+            ms += sti["stage_ms"][dom]
+            nbytes += sti["stage_bytes"][dom]
+            launches += sti["stage_launches"][dom]
+            inst_tuples += sti["result_tuples"]
+            st = sti if st is None else st
+        torch.cuda.synchronize()
+        inst_elapsed = time.perf_counter() - t1
+        inst_ms = 1e3 * inst_elapsed / args.steps
+        if value is None:
+            ms_per_step, value = inst_ms, inst_tuples / inst_elapsed
+        achieved = nbytes / (ms / 1e3) / 1e9 if ms > 0 else 0.0
+        roofline = {"bound": "hbm", "kernel": STAGE_KERNELS[dom], "stage": dom,
+                    "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "avg_launch_us": round(1e3 * ms / max(1, launches), 2),
+                    "bytes_per_launch": nbytes // max(1, launches),
+                    "launches_per_step": launches // args.steps,
+                    "instrumented_ms_per_step": round(inst_ms, 3)}
 
     if is_batch(args.workload) and not args.no_plain:
         # the plain single-instance path over the same inputs: one wg_tc / wg_sg per instance
@@ -359,6 +408,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": None,
     }
+    if args.roofline_only:
+        out["instrumented"] = True
     out.update(extra)
     eng.close()
     if not args.no_cpu_baseline:

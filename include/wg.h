@@ -59,6 +59,7 @@ typedef enum { WG_QUERY_TC = 0, WG_QUERY_SG = 1 } wg_query;
 /* wg_options.flags */
 #define WG_SG_IRREFLEXIVE 0x1u /* SG: drop (x,x) from the final relation */
 #define WG_STAGE_TIMING 0x2u   /* time every kernel launch with HIP events (fills stage_ms) */
+#define WG_NO_SPECULATION 0x4u /* enqueue nothing behind a batch while the host checks it */
 
 /* wg_options.loop_mode */
 #define WG_LOOP_AUTO 0u     /* the default: batched device-resident loop */
@@ -90,9 +91,9 @@ typedef struct {
 enum {
   WG_STAGE_JOIN_COUNT = 0, /* binary-search range lookup + count scan (Section IV-A) */
   WG_STAGE_JOIN_EMIT = 1,  /* candidate emission into scanned slabs (Section IV-A) */
-  WG_STAGE_RADIX_HIST = 2, /* digit histograms (Section V-C); computed inside the kernel
-                              that produces the keys, so this kind has no launches */
-  WG_STAGE_RADIX_PASS = 3, /* one stable LSD pass: count, scan, scatter (Section V-C) */
+  WG_STAGE_RADIX_HIST = 2, /* per-block digit counts and their scan, one per LSD pass
+                              (Section V-C) */
+  WG_STAGE_RADIX_PASS = 3, /* the stable scatter of one LSD pass (Section V-C) */
   WG_STAGE_DEDUP_DIFF = 4, /* fused dedup + set difference (Section IV-B) */
   WG_STAGE_MERGE = 5,      /* disjoint merge-path merge (Section IV-C) */
   WG_STAGE_PREPARE = 6,    /* max-id scan, packing, edge index, result unpack */

@@ -27,11 +27,23 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 // so no launch needs a grid-wide barrier, a blocks-done counter or a lookback chain --
 // cross-block handshakes cost microsecond round trips across the XCDs of this chip.
 // ---------------------------------------------------------------------------
+// Full is kept as two disjoint sorted runs: a large run A and a small run B of recent
+// deltas.  Iteration j merges its delta into B -- unless B (non-empty) plus the delta
+// would outgrow A / kFoldRatio: then it folds B into A and the delta becomes the new B.
+// A is rewritten only when Full has grown by about an eighth, not every iteration as a
+// single run would be.
 struct IterRec {
-  uint64_t N;  // |Delta^j| (record 0: the seed)
-  uint64_t C;  // join candidates of iteration j (record 0: base-rule candidates for SG)
-  uint64_t F;  // |Full| after iteration j
+  uint64_t N;   // |Delta^j| (record 0: the seed)
+  uint64_t C;   // join candidates of iteration j (record 0: base-rule candidates for SG)
+  uint64_t F;   // |Full| after iteration j (= |A| + |B|)
+  uint64_t FA;  // |A| after iteration j
+  uint32_t a;   // buffer side of A after iteration j
+  uint32_t b;   // buffer side of B after iteration j
+  uint32_t fold;  // iteration j folded B into A (and its delta became B)
+  uint32_t pad;
 };
+
+constexpr uint32_t kFoldRatio = 8;  // fold B into A once |B| > |A| / kFoldRatio
 
 struct Ctrl {
   uint64_t m_in;         // input edge count
@@ -186,24 +198,27 @@ __device__ __forceinline__ uint64_t upper_bound(const T* a, uint64_t n, T v) {
 
 // Wave-cooperative partition point: all 64 lanes of the calling wave search [lo, hi)
 // for the first index whose predicate is false (the predicate holds on a prefix).  Each
-// round probes 64 positions at once and narrows the range 65-fold, so a search over
-// 5e7 keys takes 5 rounds of parallel loads instead of 26 dependent ones.  The result
-// is uniform across the wave.
+// round splits the range into 64 chunks and probes the last index of each, so a search
+// over 5e7 keys takes 5 rounds of parallel loads instead of 26 dependent ones.  Indices
+// stay below 2^32 (no relation here holds more keys), so the arithmetic is 32-bit shifts.
+// The result is uniform across the wave.
 template <typename Pred>
-__device__ __forceinline__ uint64_t wave_partition(uint64_t lo, uint64_t hi, Pred pred) {
-  const int lane = (int)(threadIdx.x & (kWave - 1));
+__device__ __forceinline__ uint64_t wave_partition(uint64_t lo64, uint64_t hi64, Pred pred) {
+  const uint32_t lane = (uint32_t)(threadIdx.x & (kWave - 1));
+  uint32_t lo = (uint32_t)lo64, hi = (uint32_t)hi64;
   while (lo < hi) {
-    const uint64_t span = hi - lo;
-    if (span <= (uint64_t)kWave) {
-      const bool t = (uint64_t)lane < span && pred(lo + (uint64_t)lane);
-      return lo + (uint64_t)__popcll(__ballot(t));
+    const uint32_t span = hi - lo;
+    if (span <= (uint32_t)kWave) {
+      const bool t = lane < span && pred((uint64_t)(lo + lane));
+      return lo + (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(t));
     }
-    const uint64_t q = lo + (span * (uint64_t)(lane + 1)) / (kWave + 1);
-    const uint32_t J = (uint32_t)__popcll(__ballot(pred(q)));
-    const uint64_t q_before = lo + (span * (uint64_t)J) / (kWave + 1);
-    const uint64_t q_at = lo + (span * (uint64_t)(J + 1)) / (kWave + 1);
-    if (J > 0) lo = q_before + 1;
-    if (J < (uint32_t)kWave) hi = q_at;
+    const uint32_t chunk = (span + kWave - 1) >> 6;
+    const uint32_t q = lo + (lane + 1) * chunk - 1;  // last index of chunk `lane`
+    const bool t = q < hi && pred((uint64_t)q);
+    const uint32_t J = (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(t));  // chunks wholly before
+    const uint32_t qJ = lo + (J + 1) * chunk - 1;  // pred fails here (or qJ >= hi)
+    lo += J * chunk;
+    if (qJ < hi) hi = qJ;
   }
   return lo;
 }

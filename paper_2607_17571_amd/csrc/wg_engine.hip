@@ -58,7 +58,7 @@ struct wg_engine {
   uint64_t* d_bcnt = nullptr;
   uint32_t* d_rcnt = nullptr;
   uint32_t* d_rtot = nullptr;
-  DevBuf cand[2], full[2], delta[2], E, U, R, Edst, rowa, rowb, off, rec;
+  DevBuf cand[2], full[2], fullB[2], delta[2], E, U, R, Edst, rowa, rowb, off, rec;
   size_t allocated = 0;
   size_t peak = 0;
   uint64_t budget = 0;
@@ -80,9 +80,8 @@ struct wg_engine {
   bool timing = false;
   uint32_t timing_mask = 0;
   std::vector<hipEvent_t> events;
-  std::vector<int> event_kind;
-  std::vector<int> event_launches;
-  uint32_t n_events = 0;
+  std::vector<int> event_kind;  // stage kind of each timed launch group
+  uint32_t n_events = 0;         // timed launch groups (two events each)
   hipStream_t stream = nullptr;
   // result of the latest solve
   const void* res_keys = nullptr;
@@ -181,14 +180,16 @@ void grow_keep(wg_engine* e, DevBuf& b, size_t bytes, size_t live) {
 void size_buffers(wg_engine* e, bool keep, uint32_t iter, const IterRec* last) {
   const uint64_t kb = e->key_bytes;
   for (int s = 0; s < 2; ++s) ensure(e, e->cand[s], e->cand_cap * kb);
+  // with `keep`: iteration iter + 1 reads run A (side last->a), run B (side last->b) and
+  // the delta (side iter & 1); their contents survive the growth
   for (int s = 0; s < 2; ++s) {
-    if (keep && (uint32_t)s == (iter & 1u)) {
-      grow_keep(e, e->full[s], e->full_cap * kb, last->F * kb);
-      grow_keep(e, e->delta[s], e->cand_cap * kb, last->N * kb);
-    } else {
-      ensure(e, e->full[s], e->full_cap * kb);
-      ensure(e, e->delta[s], e->cand_cap * kb);
-    }
+    if (keep && (uint32_t)s == last->a) grow_keep(e, e->full[s], e->full_cap * kb, last->FA * kb);
+    else ensure(e, e->full[s], e->full_cap * kb);
+    if (keep && (uint32_t)s == last->b)
+      grow_keep(e, e->fullB[s], e->full_cap * kb, (last->F - last->FA) * kb);
+    else ensure(e, e->fullB[s], e->full_cap * kb);
+    if (keep && (uint32_t)s == (iter & 1u)) grow_keep(e, e->delta[s], e->cand_cap * kb, last->N * kb);
+    else ensure(e, e->delta[s], e->cand_cap * kb);
   }
   ensure(e, e->E, e->edge_cap * kb);
   ensure(e, e->U, (e->edge_cap + 1) * 4);
@@ -198,6 +199,19 @@ void size_buffers(wg_engine* e, bool keep, uint32_t iter, const IterRec* last) {
   ensure(e, e->rowa, e->row_cap * 4);
   ensure(e, e->rowb, e->row_cap * 4);
   ensure(e, e->off, e->row_cap * 4);
+}
+
+// Free every relation buffer (the engine stays usable; the next solve starts small).
+void release_relations(wg_engine* e) {
+  if (e->stream) hip_check(e, hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+  for (int s = 0; s < 2; ++s) {
+    free_buf(e, e->cand[s]);
+    free_buf(e, e->full[s]);
+    free_buf(e, e->fullB[s]);
+    free_buf(e, e->delta[s]);
+  }
+  for (DevBuf* b : {&e->E, &e->U, &e->R, &e->Edst, &e->rowa, &e->rowb, &e->off, &e->rec}) free_buf(e, *b);
+  e->cand_cap = e->full_cap = e->edge_cap = e->row_cap = e->rec_cap = 0;
 }
 
 void ensure_records(wg_engine* e, uint64_t need) {
@@ -221,6 +235,7 @@ Bufs<K> make_bufs(wg_engine* e) {
   for (int s = 0; s < 2; ++s) {
     b.cand[s] = (K*)e->cand[s].p;
     b.full[s] = (K*)e->full[s].p;
+    b.fullB[s] = (K*)e->fullB[s].p;
     b.delta[s] = (K*)e->delta[s].p;
   }
   b.E = (K*)e->E.p;
@@ -239,70 +254,57 @@ Bufs<K> make_bufs(wg_engine* e) {
 }
 
 // ----- stage timing: events bracket launches (begin, end) when WG_STAGE_TIMING is set.
-hipEvent_t next_event(wg_engine* e) {
-  if (e->n_events >= e->events.size()) {
+hipEvent_t pooled_event(wg_engine* e, uint32_t i) {
+  while (e->events.size() <= i) {
     hipEvent_t ev;
     hip_check(e, hipEventCreate(&ev), "hipEventCreate");
     e->events.push_back(ev);
-    e->event_kind.push_back(-1);
-    e->event_launches.push_back(1);
   }
-  return e->events[e->n_events];
+  return e->events[i];
 }
 
-void begin(wg_engine* e, int kind) {
-  if (!e->timing || !((e->timing_mask >> kind) & 1u) || e->n_events + 2 > kMaxEvents) return;
-  hip_check(e, hipEventRecord(next_event(e), e->stream), "hipEventRecord");
-  e->event_kind[e->n_events] = -1;
-  ++e->n_events;
-}
-
-void end(wg_engine* e, int kind, int launches = 1) {
-  if (!e->timing || e->n_events == 0 || e->event_kind[e->n_events - 1] != -1) return;
-  hip_check(e, hipEventRecord(next_event(e), e->stream), "hipEventRecord");
+// Events for one launch group of stage `kind` (empty when that kind is not timed): the
+// first kernel of the group stamps the start, the last the stop (hipExtLaunchKernelGGL).
+Ev stage(wg_engine* e, int kind) {
+  if (!e->timing || !((e->timing_mask >> kind) & 1u) || 2 * (e->n_events + 1) > kMaxEvents) return Ev();
+  Ev ev;
+  ev.start = pooled_event(e, 2 * e->n_events);
+  ev.stop = pooled_event(e, 2 * e->n_events + 1);
+  if (e->event_kind.size() <= e->n_events) e->event_kind.resize(e->n_events + 1);
   e->event_kind[e->n_events] = kind;
-  e->event_launches[e->n_events] = launches;
   ++e->n_events;
+  return ev;
 }
 
 void collect_timing(wg_engine* e, wg_stats* st) {
-  if (!e->timing || e->n_events < 2) return;
-  hip_check(e, hipEventSynchronize(e->events[e->n_events - 1]), "hipEventSynchronize");
-  for (uint32_t i = 1; i < e->n_events; ++i) {
-    const int k = e->event_kind[i];
-    if (k < 0 || e->event_kind[i - 1] != -1) continue;
+  if (!e->timing || e->n_events == 0) return;
+  hip_check(e, hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+  for (uint32_t i = 0; i < e->n_events; ++i) {
     float ms = 0.f;
-    hip_check(e, hipEventElapsedTime(&ms, e->events[i - 1], e->events[i]), "hipEventElapsedTime");
-    st->stage_ms[k] += ms;
-    st->stage_launches[k] += (uint64_t)e->event_launches[i];
+    hip_check(e, hipEventElapsedTime(&ms, e->events[2 * i], e->events[2 * i + 1]), "hipEventElapsedTime");
+    st->stage_ms[e->event_kind[i]] += ms;
+    st->stage_launches[e->event_kind[i]] += 1;
   }
 }
 
 // ----- pipeline pieces
 template <typename K>
 void enqueue_sort(wg_engine* e, const Bufs<K>& b, const uint64_t* n_ptr) {
-  // one event pair brackets all passes (each pass is a count, a scan and a scatter launch)
-  begin(e, WG_STAGE_RADIX_PASS);
-  launch_sort<K>(e->stream, e->d_ctrl, n_ptr, e->key_bits, e->sort, b);
-  end(e, WG_STAGE_RADIX_PASS, sort_passes(e->key_bits, e->sort.rb));
+  const int passes = sort_passes(e->key_bits, e->sort.rb);
+  for (int p = 0; p < passes; ++p) {
+    launch_sort_pass<K>(e->stream, e->d_ctrl, n_ptr, e->sort, b, p, false, stage(e, WG_STAGE_RADIX_HIST));
+    launch_sort_pass<K>(e->stream, e->d_ctrl, n_ptr, e->sort, b, p, true, stage(e, WG_STAGE_RADIX_PASS));
+  }
 }
 
 template <typename K>
 void enqueue_iteration(wg_engine* e, const Bufs<K>& b, int kind, int w, int passes, uint32_t j) {
-  begin(e, WG_STAGE_JOIN_COUNT);
-  launch_join_count<K>(e->stream, e->grid, kind, e->d_ctrl, b, w, j);
-  end(e, WG_STAGE_JOIN_COUNT);
-  begin(e, WG_STAGE_JOIN_EMIT);
-  launch_join_emit<K>(e->stream, e->grid, kind, e->d_ctrl, b, w, j);
-  end(e, WG_STAGE_JOIN_EMIT);
+  launch_join_count<K>(e->stream, e->grid, kind, e->d_ctrl, b, w, j, stage(e, WG_STAGE_JOIN_COUNT));
+  launch_join_emit<K>(e->stream, e->grid, kind, e->d_ctrl, b, w, j, stage(e, WG_STAGE_JOIN_EMIT));
   enqueue_sort<K>(e, b, &b.rec[j].C);
-  begin(e, WG_STAGE_DEDUP_DIFF);
   launch_compact<K>(e->stream, e->grid, kModeIter, e->d_ctrl, &b.rec[j].C, b.cand[passes & 1],
-                    b.cand[(passes & 1) ^ 1], b, w, j, 0);
-  end(e, WG_STAGE_DEDUP_DIFF);
-  begin(e, WG_STAGE_MERGE);
-  launch_merge<K>(e->stream, e->grid, e->d_ctrl, b, j);
-  end(e, WG_STAGE_MERGE);
+                    b.cand[(passes & 1) ^ 1], b, w, j, 0, stage(e, WG_STAGE_DEDUP_DIFF));
+  launch_merge<K>(e->stream, e->grid, e->d_ctrl, b, j, stage(e, WG_STAGE_MERGE));
 }
 
 // Enqueue the readback of the control block and of records `first` and `last`.
@@ -363,29 +365,48 @@ int field_bits(uint32_t maxid) {
 void add_bytes(wg_stats* st, int k, double b) { st->stage_bytes[k] += (uint64_t)b; }
 
 // Algorithmic HBM bytes per kernel kind (what each stage must stream at minimum).
+// Algorithmic bytes: what each kernel kind must move, per launch, for the sizes the
+// records hold (probes into cache-resident indexes are not counted).
+//   join count  D * (kb + 4)           read delta, write one offset per tuple
+//   join emit   D * (kb + 4) + C * (4 + kb) TC,  + C * (8 + kb) SG
+//                                      read delta and offsets, read E.dst, write candidates
+//   radix count C * kb per pass         read every key
+//   radix pass  2 * C * kb per pass     read and write every key (the scatter)
+//   dedup/diff  (C + N) * kb            read candidates, write the new delta
+//   merge       2 * (|B| + N) * kb      read run B and the delta, write B'
+//               2 * (F + N) * kb         on a fold: A and B into A', the delta into B'
+//               + 2 * F * kb             once: the final union of A and B
 void bytes_model(wg_stats* st, int query, uint32_t kb, int passes, uint64_t m,
                  const std::vector<IterRec>& rec, uint64_t mu) {
-  // prepare: max scan (8m), pack (8m read + kb*m), sort + dedup of m keys, index
+  // prepare: max scan (8m), pack (8m read + kb*m write), edge index (read E, write U/R/Edst)
   add_bytes(st, WG_STAGE_PREPARE, 8.0 * m + (8.0 + kb) * m + (kb + 12.0) * mu);
-  add_bytes(st, WG_STAGE_RADIX_PASS, 3.0 * kb * m * passes);
-  add_bytes(st, WG_STAGE_DEDUP_DIFF, (double)kb * m + 3.0 * kb * mu);
+  add_bytes(st, WG_STAGE_RADIX_HIST, 1.0 * kb * m * passes);
+  add_bytes(st, WG_STAGE_RADIX_PASS, 2.0 * kb * m * passes);
+  add_bytes(st, WG_STAGE_DEDUP_DIFF, (double)kb * (m + mu));
   if (query == WG_QUERY_SG) {
     const double c = (double)rec[0].C, n = (double)rec[0].N;
     add_bytes(st, WG_STAGE_JOIN_EMIT, (kb + 8.0) * c);
-    add_bytes(st, WG_STAGE_RADIX_PASS, 3.0 * kb * c * passes);
-    add_bytes(st, WG_STAGE_DEDUP_DIFF, (c + 4.0 * n) * kb);
+    add_bytes(st, WG_STAGE_RADIX_HIST, 1.0 * kb * c * passes);
+    add_bytes(st, WG_STAGE_RADIX_PASS, 2.0 * kb * c * passes);
+    add_bytes(st, WG_STAGE_DEDUP_DIFF, (c + n) * kb);
   }
-  const double row_bytes = query == WG_QUERY_TC ? 8.0 : 12.0;
   const double edst = query == WG_QUERY_TC ? 4.0 : 8.0;
   for (size_t i = 1; i < rec.size(); ++i) {
     const double D = (double)rec[i - 1].N, c = (double)rec[i].C, n = (double)rec[i].N;
     const double F = (double)rec[i - 1].F;
-    add_bytes(st, WG_STAGE_JOIN_COUNT, D * (kb + row_bytes));
-    add_bytes(st, WG_STAGE_JOIN_EMIT, D * (kb + row_bytes) + c * (edst + kb));
-    add_bytes(st, WG_STAGE_RADIX_PASS, 3.0 * c * kb * passes);
-    add_bytes(st, WG_STAGE_DEDUP_DIFF, (c + 3.0 * n) * kb);
-    if (rec[i].N > 0) add_bytes(st, WG_STAGE_MERGE, 2.0 * (F + n) * kb);
+    add_bytes(st, WG_STAGE_JOIN_COUNT, D * (kb + 4.0));
+    add_bytes(st, WG_STAGE_JOIN_EMIT, D * (kb + 4.0) + c * (edst + kb));
+    add_bytes(st, WG_STAGE_RADIX_HIST, 1.0 * c * kb * passes);
+    add_bytes(st, WG_STAGE_RADIX_PASS, 2.0 * c * kb * passes);
+    add_bytes(st, WG_STAGE_DEDUP_DIFF, (c + n) * kb);
+    // the merge: delta into run B, or on a fold B into A plus the delta as the new B
+    const double FA = (double)rec[i - 1].FA, FB = F - FA;
+    if (rec[i].fold) add_bytes(st, WG_STAGE_MERGE, 2.0 * (FA + FB + n) * kb);
+    else if (rec[i].N > 0) add_bytes(st, WG_STAGE_MERGE, 2.0 * (FB + n) * kb);
   }
+  // the final union of the two runs
+  const IterRec& fin = rec.back();
+  if (fin.F > fin.FA) add_bytes(st, WG_STAGE_MERGE, 2.0 * (double)fin.F * kb);
 }
 
 template <typename K>
@@ -415,37 +436,26 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
 
   // ---- prepare: sort + dedup E, edge index, seed (Section IV-A: E sorted once)
   Bufs<K> b = make_bufs<K>(e);
-  begin(e, WG_STAGE_PREPARE);
   if (e->num_inst)
-    launch_pack_batch<K>(e->stream, e->grid, src, dst, m, w, e->d_offsets, e->num_inst, b.cand[0]);
+    launch_pack_batch<K>(e->stream, e->grid, src, dst, m, w, e->d_offsets, e->num_inst, b.cand[0],
+                         stage(e, WG_STAGE_PREPARE));
   else
-    launch_pack<K>(e->stream, e->grid, src, dst, m, w, b.cand[0]);
-  end(e, WG_STAGE_PREPARE);
+    launch_pack<K>(e->stream, e->grid, src, dst, m, w, b.cand[0], stage(e, WG_STAGE_PREPARE));
   enqueue_sort<K>(e, b, &e->d_ctrl->m_in);
   const int mode = query == WG_QUERY_TC ? (kModeEdges | kModeSeed) : kModeEdges;
-  begin(e, WG_STAGE_DEDUP_DIFF);
   launch_compact<K>(e->stream, e->grid, mode, e->d_ctrl, &e->d_ctrl->m_in, b.cand[passes & 1],
-                    b.cand[(passes & 1) ^ 1], b, w, 0, 0);
-  end(e, WG_STAGE_DEDUP_DIFF);
-  begin(e, WG_STAGE_PREPARE);
-  launch_edge_index<K>(e->stream, e->grid, e->d_ctrl, b, w);
-  end(e, WG_STAGE_PREPARE);
+                    b.cand[(passes & 1) ^ 1], b, w, 0, 0, stage(e, WG_STAGE_DEDUP_DIFF));
+  launch_edge_index<K>(e->stream, e->grid, e->d_ctrl, b, w, stage(e, WG_STAGE_PREPARE));
 
   if (query == WG_QUERY_SG) {
     // base rule: Delta^0 = Full = {(x, y) : E(p, x), E(p, y), x != y}, sorted + deduplicated
     for (;;) {
       b = make_bufs<K>(e);
-      begin(e, WG_STAGE_JOIN_COUNT);
-      launch_join_count<K>(e->stream, e->grid, kJoinSGBase, e->d_ctrl, b, w, 0);
-      end(e, WG_STAGE_JOIN_COUNT);
-      begin(e, WG_STAGE_JOIN_EMIT);
-      launch_join_emit<K>(e->stream, e->grid, kJoinSGBase, e->d_ctrl, b, w, 0);
-      end(e, WG_STAGE_JOIN_EMIT);
+      launch_join_count<K>(e->stream, e->grid, kJoinSGBase, e->d_ctrl, b, w, 0, stage(e, WG_STAGE_JOIN_COUNT));
+      launch_join_emit<K>(e->stream, e->grid, kJoinSGBase, e->d_ctrl, b, w, 0, stage(e, WG_STAGE_JOIN_EMIT));
       enqueue_sort<K>(e, b, &b.rec[0].C);
-      begin(e, WG_STAGE_DEDUP_DIFF);
       launch_compact<K>(e->stream, e->grid, kModeSeed, e->d_ctrl, &b.rec[0].C, b.cand[passes & 1],
-                        b.cand[(passes & 1) ^ 1], b, w, 0, 0);
-      end(e, WG_STAGE_DEDUP_DIFF);
+                        b.cand[(passes & 1) ^ 1], b, w, 0, 0, stage(e, WG_STAGE_DEDUP_DIFF));
       read_back(e, 0, 0, 0);
       const Readback r = wait_back(e, 0);
       if (!r.c.overflow) break;
@@ -489,7 +499,7 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
     // While the host waits on this batch, the device runs a short speculative batch
     // behind it (Section V-B overlaps the next batch with the host check); after the
     // fixpoint its launches are no-ops, so it is kept short.
-    enqueue_iters(std::min(K_batch, kSpec));
+    if (!(o.flags & WG_NO_SPECULATION)) enqueue_iters(std::min(K_batch, kSpec));
     r = wait_back(e, slot);
     if (r.c.overflow | r.c.done | r.c.limit_hit) sync_stream(e);
     if (e->cancel && e->cancel->load()) {
@@ -513,23 +523,26 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   }
   if (r.c.limit_hit && !r.c.done) fail(e, WG_ERR_ITER_LIMIT, "max_iterations reached before the fixpoint");
 
-  // result: Full after the last iteration.  The last merge (iteration iter - 1) wrote side
-  // (iter - 1) & 1; with no merge at all the seed is on side 0.
+  // result: Full after the last iteration, the union of its runs A and B (one final
+  // disjoint merge into the free A buffer unless B is empty)
   const uint32_t iters = r.c.iter;
   const IterRec fin = read_record(e, iters);
-  uint32_t side = iters >= 1 ? ((iters - 1) & 1u) : 0u;
+  uint32_t side = fin.a;
   uint64_t F = fin.F;
   b = make_bufs<K>(e);
+  if (fin.F > fin.FA) {
+    launch_merge_pair<K>(e->stream, e->grid, b.full[fin.a], fin.FA, b.fullB[fin.b], fin.F - fin.FA,
+                         b.full[fin.a ^ 1u], stage(e, WG_STAGE_MERGE));
+    side = fin.a ^ 1u;
+  }
   if (query == WG_QUERY_SG && (o.flags & WG_SG_IRREFLEXIVE) && F > 0) {
     if (e->cand_cap < F) {
       e->cand_cap = F;
       for (int s = 0; s < 2; ++s) ensure(e, e->cand[s], e->cand_cap * e->key_bytes);
       b = make_bufs<K>(e);
     }
-    begin(e, WG_STAGE_PREPARE);
     launch_compact<K>(e->stream, e->grid, kModeFilter, e->d_ctrl, &b.rec[iters].F, b.full[side],
-                      b.cand[0], b, w, 0, side);
-    end(e, WG_STAGE_PREPARE);
+                      b.cand[0], b, w, 0, side, stage(e, WG_STAGE_PREPARE));
     read_back(e, 0, 0, 0);
     F = wait_back(e, 0).c.filtered;
     side ^= 1u;
@@ -628,7 +641,8 @@ wg_status solve(wg_engine* e, int query, uint32_t num, const uint64_t* d_offsets
     e->err = "tile_items must be 0, 8, 12 or 16";
     return WG_ERR_INVALID_ARG;
   }
-  if (o.loop_mode > WG_LOOP_HOST || (o.flags & ~(WG_SG_IRREFLEXIVE | WG_STAGE_TIMING))) {
+  if (o.loop_mode > WG_LOOP_HOST ||
+      (o.flags & ~(WG_SG_IRREFLEXIVE | WG_STAGE_TIMING | WG_NO_SPECULATION))) {
     e->err = "unknown loop_mode or flag";
     return WG_ERR_INVALID_ARG;
   }
@@ -647,6 +661,9 @@ wg_status solve(wg_engine* e, int query, uint32_t num, const uint64_t* d_offsets
     e->res_n = 0;
     e->syncs = 0;
     e->budget = o.mem_budget_bytes;
+    // the budget bounds everything the engine holds: buffers kept from earlier solves
+    // that already exceed it are released first
+    if (e->budget && e->allocated > e->budget) release_relations(e);
     e->peak = e->allocated;
     e->timing = (o.flags & WG_STAGE_TIMING) != 0;
     e->timing_mask = o.timing_stages ? o.timing_stages : 0xFFFFFFFFu;
@@ -742,16 +759,9 @@ void engine_set_cancel(wg_engine* e, const std::atomic<bool>* flag) { e->cancel 
 void engine_trim(wg_engine* e) {
   try {
     hip_check(e, hipSetDevice(e->device), "hipSetDevice");
-    if (e->stream) hip_check(e, hipStreamSynchronize(e->stream), "hipStreamSynchronize");
-    for (int s = 0; s < 2; ++s) {
-      free_buf(e, e->cand[s]);
-      free_buf(e, e->full[s]);
-      free_buf(e, e->delta[s]);
-    }
-    for (DevBuf* b : {&e->E, &e->U, &e->R, &e->Edst, &e->rowa, &e->rowb, &e->off, &e->rec}) free_buf(e, *b);
+    release_relations(e);
   } catch (const Fail&) {
   }
-  e->cand_cap = e->full_cap = e->edge_cap = e->row_cap = e->rec_cap = 0;
   e->generation++;
   e->res_keys = nullptr;
   e->res_n = 0;
@@ -840,6 +850,7 @@ void wg_engine_destroy(wg_engine* e) {
   for (int s = 0; s < 2; ++s) {
     release(e->cand[s]);
     release(e->full[s]);
+    release(e->fullB[s]);
     release(e->delta[s]);
   }
   release(e->E);

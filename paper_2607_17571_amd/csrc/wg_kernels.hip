@@ -18,6 +18,10 @@
 // cross-block handshake (same-address atomics, lookback polling across the XCDs' L2s)
 // costs a microsecond-scale round trip, which a chained scan pays once per tile.
 
+#include <hip/hip_ext.h>
+
+#include <type_traits>
+
 #include "wg_launch.h"
 
 namespace wg {
@@ -323,37 +327,53 @@ __global__ __launch_bounds__(kBlock) void k_radix_count(Ctrl* ctrl, const uint64
                                                         uint32_t* __restrict__ cnt) {
   using S = RadixShape<RB>;
   constexpr uint32_t T = kBlock * ITEMS;
-  __shared__ uint32_t s_cnt[S::R];
+  // Lanes add into one of COPIES histograms (lane % COPIES), laid out so that the copies
+  // of one digit sit in different LDS banks: lanes holding the same digit then collide
+  // COPIES times less often.
+  constexpr int COPIES = RB <= 8 ? 8 : (RB == 9 ? 4 : (RB == 10 ? 2 : 1));
+  constexpr int STRIDE = S::R + 1;
+  __shared__ uint32_t s_cnt[COPIES * STRIDE];
   if (halted(ctrl)) return;
   const uint64_t n = *n_ptr;
   uint64_t lo, hi;
   block_range(n, T, lo, hi);
   if (lo >= hi) return;  // past the active blocks: the scan reads none of their counts
-  for (int d = threadIdx.x; d < S::R; d += kBlock) s_cnt[d] = 0;
+  for (int d = threadIdx.x; d < COPIES * STRIDE; d += kBlock) s_cnt[d] = 0;
   __syncthreads();
   const uint64_t lt = lanemask_lt();
+  uint32_t* my = s_cnt + (lane_id() % COPIES) * STRIDE;
+  auto count_tile = [&](const K (&key)[ITEMS], uint64_t base, auto full_t) {
+    constexpr bool FULL = decltype(full_t)::value;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const bool valid = FULL || base + (uint64_t)k * kBlock + threadIdx.x < hi;
+      const uint32_t d = (uint32_t)(key[k] >> shift) & (S::R - 1);
+      const uint64_t active = FULL ? ~0ull : __builtin_amdgcn_ballot_w64(valid);
+      const uint32_t first = __builtin_amdgcn_readfirstlane(d);
+      if (__builtin_amdgcn_ballot_w64(valid && d == first) == active) {
+        if (valid && (active & lt) == 0) atomicAdd(&s_cnt[first], (uint32_t)__popcll(active));
+      } else if (valid) {
+        atomicAdd(&my[d], 1u);
+      }
+    }
+  };
   K cur[ITEMS];
   load_tile_striped<K, ITEMS>(in, lo, hi, cur);
   for (uint64_t base = lo; base < hi; base += T) {
     K nxt[ITEMS];
     if (base + T < hi) load_tile_striped<K, ITEMS>(in, base + T, hi, nxt);
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      const bool valid = base + (uint64_t)k * kBlock + threadIdx.x < hi;
-      const uint32_t d = (uint32_t)(cur[k] >> shift) & (S::R - 1);
-      const uint64_t active = __ballot(valid);
-      const uint32_t first = __builtin_amdgcn_readfirstlane(d);
-      if (__ballot(valid && d == first) == active) {
-        if (valid && (active & lt) == 0) atomicAdd(&s_cnt[first], (uint32_t)__popcll(active));
-      } else if (valid) {
-        atomicAdd(&s_cnt[d], 1u);
-      }
-    }
+    if (base + T <= hi) count_tile(cur, base, std::true_type());
+    else count_tile(cur, base, std::false_type());
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) cur[k] = nxt[k];
   }
   __syncthreads();
-  for (int d = threadIdx.x; d < S::R; d += kBlock) cnt[(uint64_t)d * gridDim.x + blockIdx.x] = s_cnt[d];
+  for (int d = threadIdx.x; d < S::R; d += kBlock) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int r = 0; r < COPIES; ++r) c += s_cnt[r * STRIDE + d];
+    cnt[(uint64_t)d * gridDim.x + blockIdx.x] = c;
+  }
 }
 
 // One block per digit: per-block counts of the digit -> exclusive per-block offsets (in
@@ -378,17 +398,20 @@ __global__ __launch_bounds__(kBlock) void k_radix_scan(Ctrl* ctrl, const uint64_
 }
 
 // Lanes of the wave (within `active`) whose RB-bit digit equals this lane's: one ballot
-// per bit.
+// per bit.  For bit b, sb is 0 or all ones (the lane's bit, sign-extended); the lanes that
+// agree with this lane on bit b are ballot(bit b) XNOR sb, per 32-lane half -- about six
+// VALU instructions per bit.
 template <int RB>
 __device__ __forceinline__ uint64_t digit_peers(uint32_t d, uint64_t active) {
-  uint64_t peers = active;
+  uint32_t lo = (uint32_t)active, hi = (uint32_t)(active >> 32);
 #pragma unroll
   for (int bit = 0; bit < RB; ++bit) {
-    const bool set = (d >> bit) & 1u;
-    const uint64_t m = __ballot(set);
-    peers &= set ? m : ~m;
+    const uint32_t sb = (uint32_t)(((int32_t)(d << (31 - bit))) >> 31);
+    const uint64_t m = __builtin_amdgcn_ballot_w64(sb != 0u);
+    lo &= ~((uint32_t)m ^ sb);
+    hi &= ~((uint32_t)(m >> 32) ^ sb);
   }
-  return peers;
+  return ((uint64_t)hi << 32) | lo;
 }
 
 template <typename K, int RB, int ITEMS>
@@ -436,22 +459,23 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(Ctrl* ctrl, const uint
       }
     }
   }
-  K cur[ITEMS];
-  load_tile_wave<K, ITEMS>(in, lo + (uint64_t)wid * (ITEMS * kWave), hi, cur);
-  for (uint64_t tbase = lo; tbase < hi; tbase += T) {
-    K nxt[ITEMS];
-    if (tbase + T < hi) load_tile_wave<K, ITEMS>(in, tbase + T + (uint64_t)wid * (ITEMS * kWave), hi, nxt);
+  // One tile: stable rank in LDS, then every key to its final position.  FULL tiles (all
+  // but possibly the last of the range) skip the per-key bounds checks.
+  auto scatter_tile = [&](const K (&cur)[ITEMS], uint64_t tbase, auto full_t) {
+    constexpr bool FULL = decltype(full_t)::value;
     for (int jj = tid; jj < kWavesPerBlock * S::R; jj += kBlock) (&s_cnt[0][0])[jj] = 0;
     __syncthreads();
-    const uint64_t wbase = tbase + (uint64_t)wid * (ITEMS * kWave);
+    // wave-striped: wave `wid` owns a contiguous run of 64*ITEMS keys
+    const uint32_t wofs = (uint32_t)wid * (ITEMS * kWave);
+    const uint32_t tile_n = FULL ? T : (uint32_t)(hi - tbase);
     uint32_t rank[ITEMS];
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
-      const bool valid = wbase + (uint64_t)k * kWave + lane < hi;
+      const bool valid = FULL || wofs + (uint32_t)k * kWave + lane < tile_n;
       const uint32_t d = (uint32_t)(cur[k] >> shift) & (S::R - 1);
-      const uint64_t active = __ballot(valid);
+      const uint64_t active = FULL ? ~0ull : __builtin_amdgcn_ballot_w64(valid);
       const uint32_t first = __builtin_amdgcn_readfirstlane(d);
-      if (__ballot(valid && d == first) == active) {
+      if (__builtin_amdgcn_ballot_w64(valid && d == first) == active) {
         // every active lane holds digit `first`
         const uint32_t before = s_cnt[wid][first];
         rank[k] = before + (uint32_t)__popcll(active & lt);
@@ -496,22 +520,21 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(Ctrl* ctrl, const uint
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
-      if (wbase + (uint64_t)k * kWave + lane < hi) {
+      if (FULL || wofs + (uint32_t)k * kWave + lane < tile_n) {
         const uint32_t d = (uint32_t)(cur[k] >> shift) & (S::R - 1);
         const uint32_t pos = (uint32_t)s_loc[d] + s_cnt[wid][d] + rank[k];
-        if (pos < T) s_keys[pos] = cur[k];
+        if (FULL || pos < T) s_keys[pos] = cur[k];
       }
     }
     __syncthreads();
-    const uint32_t tile_n = (uint32_t)min<uint64_t>(T, hi - tbase);
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
       const uint32_t jj = (uint32_t)k * kBlock + tid;
-      if (jj < tile_n) {
+      if (FULL || jj < tile_n) {
         const K kk = s_keys[jj];
         const uint32_t d = (uint32_t)(kk >> shift) & (S::R - 1);
-        const uint64_t pos = (uint64_t)s_run[d] + (jj - s_loc[d]);
-        if (pos < n) out[pos] = kk;
+        const uint32_t pos = s_run[d] + (jj - s_loc[d]);  // < n < 2^32
+        if (FULL || pos < n) out[pos] = kk;
       }
     }
     __syncthreads();
@@ -519,6 +542,14 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(Ctrl* ctrl, const uint
 #pragma unroll
       for (int i = 0; i < DPT; ++i) s_run[tid * DPT + i] += tile_cnt[i];
     }
+  };
+  K cur[ITEMS];
+  load_tile_wave<K, ITEMS>(in, lo + (uint64_t)wid * (ITEMS * kWave), hi, cur);
+  for (uint64_t tbase = lo; tbase < hi; tbase += T) {
+    K nxt[ITEMS];
+    if (tbase + T < hi) load_tile_wave<K, ITEMS>(in, tbase + T + (uint64_t)wid * (ITEMS * kWave), hi, nxt);
+    if (tbase + T <= hi) scatter_tile(cur, tbase, std::true_type());
+    else scatter_tile(cur, tbase, std::false_type());
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) cur[k] = nxt[k];
   }
@@ -539,6 +570,38 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(Ctrl* ctrl, const uint
 // copies its survivors to their final positions; the output stays sorted.  Block 0 then
 // records the iteration (|Delta^j|, |Full| after it, the fixpoint and limit flags).
 // ---------------------------------------------------------------------------
+// First index in [lo, hi) of sorted LDS array w whose key is >= v (32-bit indices).
+template <typename K>
+__device__ __forceinline__ uint32_t lds_lower_bound(const K* w, uint32_t lo, uint32_t hi, K v) {
+  uint32_t len = hi - lo;
+  while (len > 0) {
+    const uint32_t half = len >> 1;
+    if (w[lo + half] < v) {
+      lo += half + 1;
+      len -= half + 1;
+    } else {
+      len = half;
+    }
+  }
+  return lo;
+}
+
+// keep[k] = false for every item of this thread present in the sorted LDS window w[0, n).
+// The thread's items are ascending, so two searches bound the part of the window they
+// can hit, and each item is then searched in what remains of that part.
+template <typename K, int ITEMS>
+__device__ __forceinline__ void drop_present(const K* w, uint32_t n, const K (&cv)[ITEMS],
+                                             bool (&keep)[ITEMS]) {
+  uint32_t lo = lds_lower_bound<K>(w, 0, n, cv[0]);
+  const uint32_t hi = lds_lower_bound<K>(w, lo, n, cv[ITEMS - 1]) + 1;
+  const uint32_t end = hi < n ? hi : n;
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    lo = lds_lower_bound<K>(w, lo, end, cv[k]);
+    if (lo < end && w[lo] == cv[k]) keep[k] = false;
+  }
+}
+
 template <typename K, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_compact_local(Ctrl* ctrl, int mode, const uint64_t* n_ptr,
                                                           const K* __restrict__ in,
@@ -546,9 +609,9 @@ __global__ __launch_bounds__(kBlock) void k_compact_local(Ctrl* ctrl, int mode, 
                                                           uint32_t j) {
   constexpr uint32_t T = kBlock * ITEMS;
   __shared__ K s_c[T + 1];
-  __shared__ K s_f[T];
-  __shared__ uint64_t s_wave[kWavesPerBlock];
-  __shared__ uint64_t s_lo, s_hi;
+  __shared__ K s_f[2 * T];  // windows of A [0, T) and B [T, 2T); then the survivors
+  __shared__ uint32_t s_wave[kWavesPerBlock];
+  __shared__ uint64_t s_lo[2], s_hi[2];
   const bool filt = (mode & kModeFilter) != 0;
   if (!filt && halted(ctrl)) return;
   const uint64_t n = *n_ptr;
@@ -559,23 +622,41 @@ __global__ __launch_bounds__(kBlock) void k_compact_local(Ctrl* ctrl, int mode, 
     return;
   }
   const bool diff = (mode & kModeIter) != 0;
-  const K* __restrict__ full = diff ? b.full[(j - 1) & 1u] : nullptr;
-  const uint64_t F = diff ? b.rec[j - 1].F : 0;
+  // Full of iteration j-1: runs A and B, each tile's window of each staged in LDS when it
+  // fits (searched in place otherwise)
+  const K* __restrict__ runA = nullptr;
+  const K* __restrict__ runB = nullptr;
+  uint64_t FA = 0, FB = 0;
+  if (diff) {
+    const IterRec rp = b.rec[j - 1];
+    runA = b.full[rp.a];
+    runB = b.fullB[rp.b];
+    FA = rp.FA;
+    FB = rp.F - rp.FA;
+  }
   const K mask = field_mask<K>(w);
   const int wid = threadIdx.x / kWave;
-  // the part of Full that can hold any key of this block
-  uint64_t bflo = 0, bfhi = 0;
+  // the parts of A and B that can hold any key of this block (four waves search at once)
+  uint64_t alo = 0, ahi = 0, blo = 0, bhi = 0;
   if (diff) {
     if (wid == 0) {
-      const uint64_t v = wave_lower_bound(full, F, in[lo]);
-      if (lane_id() == 0) s_lo = v;
+      const uint64_t v = wave_lower_bound(runA, FA, in[lo]);
+      if (lane_id() == 0) s_lo[0] = v;
     } else if (wid == 1) {
-      const uint64_t v = wave_upper_bound(full, F, in[hi - 1]);
-      if (lane_id() == 0) s_hi = v;
+      const uint64_t v = wave_upper_bound(runA, FA, in[hi - 1]);
+      if (lane_id() == 0) s_hi[0] = v;
+    } else if (wid == 2) {
+      const uint64_t v = wave_lower_bound(runB, FB, in[lo]);
+      if (lane_id() == 0) s_lo[1] = v;
+    } else {
+      const uint64_t v = wave_upper_bound(runB, FB, in[hi - 1]);
+      if (lane_id() == 0) s_hi[1] = v;
     }
     __syncthreads();
-    bflo = s_lo;
-    bfhi = s_hi > bflo ? s_hi : bflo;
+    alo = s_lo[0];
+    ahi = s_hi[0] > alo ? s_hi[0] : alo;
+    blo = s_lo[1];
+    bhi = s_hi[1] > blo ? s_hi[1] : blo;
     __syncthreads();
   }
   uint64_t running = 0;
@@ -584,24 +665,37 @@ __global__ __launch_bounds__(kBlock) void k_compact_local(Ctrl* ctrl, int mode, 
     for (uint32_t jj = threadIdx.x; jj < tn; jj += kBlock) s_c[jj + 1] = in[tbase + jj];
     if (threadIdx.x == 0 && tbase > 0) s_c[0] = in[tbase - 1];
     if (diff) {
-      // window of Full that can hold this tile's keys (two waves search concurrently)
+      // windows of A and B that can hold this tile's keys
+      const K first = in[tbase], last = in[tbase + tn - 1];
       if (wid == 0) {
-        const uint64_t v = bflo + wave_lower_bound(full + bflo, bfhi - bflo, in[tbase]);
-        if (lane_id() == 0) s_lo = v;
+        const uint64_t v = alo + wave_lower_bound(runA + alo, ahi - alo, first);
+        if (lane_id() == 0) s_lo[0] = v;
       } else if (wid == 1) {
-        const uint64_t v = bflo + wave_upper_bound(full + bflo, bfhi - bflo, in[tbase + tn - 1]);
-        if (lane_id() == 0) s_hi = v;
+        const uint64_t v = alo + wave_upper_bound(runA + alo, ahi - alo, last);
+        if (lane_id() == 0) s_hi[0] = v;
+      } else if (wid == 2) {
+        const uint64_t v = blo + wave_lower_bound(runB + blo, bhi - blo, first);
+        if (lane_id() == 0) s_lo[1] = v;
+      } else {
+        const uint64_t v = blo + wave_upper_bound(runB + blo, bhi - blo, last);
+        if (lane_id() == 0) s_hi[1] = v;
       }
     }
     __syncthreads();
-    uint64_t flo = 0, fspan = 0;
-    bool win = false;
+    uint64_t flo = 0, fspan = 0, glo = 0, gspan = 0;
+    bool win = false, gwin = false;
     if (diff) {
-      flo = s_lo;
-      fspan = s_hi > flo ? s_hi - flo : 0;
+      flo = s_lo[0];
+      fspan = s_hi[0] > flo ? s_hi[0] - flo : 0;
+      glo = s_lo[1];
+      gspan = s_hi[1] > glo ? s_hi[1] - glo : 0;
       win = fspan <= T;
+      gwin = gspan <= T;
       if (win) {
-        for (uint32_t jj = threadIdx.x; jj < fspan; jj += kBlock) s_f[jj] = full[flo + jj];
+        for (uint32_t jj = threadIdx.x; jj < fspan; jj += kBlock) s_f[jj] = runA[flo + jj];
+      }
+      if (gwin) {
+        for (uint32_t jj = threadIdx.x; jj < gspan; jj += kBlock) s_f[T + jj] = runB[glo + jj];
       }
       __syncthreads();
     }
@@ -611,29 +705,38 @@ __global__ __launch_bounds__(kBlock) void k_compact_local(Ctrl* ctrl, int mode, 
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
       const uint32_t jj = j0 + k;
-      cv[k] = (jj < tn) ? s_c[jj + 1] : K(0);
+      // past the tile: the largest key keeps the thread's items ascending (never kept)
+      cv[k] = (jj < tn) ? s_c[jj + 1] : ~K(0);
       if (filt) keep[k] = jj < tn && ((cv[k] >> w) & mask) != (cv[k] & mask);
       else keep[k] = jj < tn && ((tbase + jj == 0) || (cv[k] != s_c[jj]));
     }
     if (fspan > 0) {
       uint64_t pos[ITEMS];
       if (win) {
-        multi_lower_bound<K, ITEMS>(s_f, fspan, cv, pos);
-#pragma unroll
-        for (int k = 0; k < ITEMS; ++k)
-          if (pos[k] < fspan && s_f[pos[k]] == cv[k]) keep[k] = false;
+        drop_present<K, ITEMS>(s_f, (uint32_t)fspan, cv, keep);
       } else {
-        multi_lower_bound<K, ITEMS>(full + flo, fspan, cv, pos);
+        multi_lower_bound<K, ITEMS>(runA + flo, fspan, cv, pos);
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k)
-          if (pos[k] < fspan && full[flo + pos[k]] == cv[k]) keep[k] = false;
+          if (pos[k] < fspan && runA[flo + pos[k]] == cv[k]) keep[k] = false;
       }
     }
-    uint64_t cnt = 0;
+    if (gspan > 0) {
+      uint64_t pos[ITEMS];
+      if (gwin) {
+        drop_present<K, ITEMS>(s_f + T, (uint32_t)gspan, cv, keep);
+      } else {
+        multi_lower_bound<K, ITEMS>(runB + glo, gspan, cv, pos);
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k)
+          if (pos[k] < gspan && runB[glo + pos[k]] == cv[k]) keep[k] = false;
+      }
+    }
+    uint32_t cnt = 0;
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) cnt += keep[k] ? 1u : 0u;
-    uint64_t tile_total;
-    const uint64_t ex = block_excl_scan<uint64_t>(cnt, s_wave, tile_total);
+    uint32_t tile_total;
+    const uint32_t ex = block_excl_scan<uint32_t>(cnt, s_wave, tile_total);
     // (the scan ends with a barrier, so s_f is free for the survivors)
     uint32_t lpos = (uint32_t)ex;
 #pragma unroll
@@ -667,7 +770,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_gather(Ctrl* ctrl, int mode,
   uint32_t ovf = 0;
   uint64_t F = 0;
   if (mode & kModeIter) {
-    F = b.rec[j - 1].F;
+    F = b.rec[j - 1].F;  // |A| + |B| of iteration j - 1
     out1 = b.delta[j & 1u];
     if (F + N > ctrl->full_cap) ovf |= 2u;
     if (N > ctrl->cand_cap) ovf |= 4u;
@@ -702,16 +805,33 @@ __global__ __launch_bounds__(kBlock) void k_compact_gather(Ctrl* ctrl, int mode,
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (mode & kModeIter) {
-      b.rec[j].N = N;
-      b.rec[j].F = F + N;
+      // where the merge of iteration j puts Full: the delta goes into B (the other B
+      // buffer), or, when B would outgrow A / kFoldRatio, B folds into A (the other A
+      // buffer) and the delta alone becomes B.  With an empty delta nothing is merged
+      // and both runs stay where they are.
+      const IterRec rp = b.rec[j - 1];
+      const uint64_t fb = rp.F - rp.FA;
+      const bool fold = N > 0 && fb > 0 && (fb + N) * kFoldRatio > rp.FA;
+      IterRec& r = b.rec[j];
+      r.N = N;
+      r.F = F + N;
+      r.FA = fold ? F : rp.FA;
+      r.a = fold ? (rp.a ^ 1u) : rp.a;
+      r.b = N > 0 ? (rp.b ^ 1u) : rp.b;
+      r.fold = fold ? 1u : 0u;
       ctrl->iter = j;
       if (N == 0) ctrl->done = 1;
       else if (ctrl->max_iter != 0 && j >= ctrl->max_iter) ctrl->limit_hit = 1;
     } else if (mode & (kModeEdges | kModeSeed)) {
       if (mode & kModeEdges) ctrl->m_unique = N;
       if (mode & kModeSeed) {
-        b.rec[0].N = N;
-        b.rec[0].F = N;
+        IterRec& r = b.rec[0];
+        r.N = N;
+        r.F = N;
+        r.FA = N;  // the seed is run A (Full[0]); run B starts empty
+        r.a = 0;
+        r.b = 0;
+        r.fold = 0;
         ctrl->iter = 0;
         if (N == 0) ctrl->done = 1;
       }
@@ -722,11 +842,12 @@ __global__ __launch_bounds__(kBlock) void k_compact_gather(Ctrl* ctrl, int mode,
 }
 
 // ---------------------------------------------------------------------------
-// Disjoint merge (Section IV-C).  Full and the new delta are disjoint by construction, so
-// Full' has exactly |Full| + |Delta| keys and each tile's slice of both inputs is fixed by
-// a merge-path diagonal search: no atomics, no cleanup pass.  Tiles that take keys from
-// one input only are straight copies.  Iteration j merges Full[(j-1)&1] and delta[j&1]
-// into Full[j&1] (ping-pong, Section V-C).
+// Disjoint merge (Section IV-C).  The inputs are disjoint by construction, so the output
+// has exactly the sum of their sizes and each tile's slice of both inputs is fixed by a
+// merge-path diagonal search: no atomics, no cleanup pass.  Tiles that take keys from one
+// input only are straight copies.  Full is two runs (see IterRec): iteration j merges its
+// delta into run B or, on a fold, B into A, each into the other buffer of a ping-pong
+// pair (Section V-C).
 // ---------------------------------------------------------------------------
 // Number of A keys among the first `diag` keys of merge(A, B), found by the whole wave.
 template <typename K>
@@ -737,33 +858,27 @@ __device__ __forceinline__ uint64_t wave_merge_path(const K* A, uint64_t na, con
   return wave_partition(lo, hi, [&](uint64_t i) { return A[i] < B[diag - 1 - i]; });
 }
 
+// Tiles of merge(A, B) -> O, taken by blocks `bid` of `nblocks` in a grid-stride loop.
 template <typename K, int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_merge(Ctrl* ctrl, Bufs<K> b, uint32_t j) {
+__device__ __forceinline__ void merge_tiles(const K* __restrict__ A, uint64_t na, const K* __restrict__ B,
+                                            uint64_t nb, K* __restrict__ O, K* s_in, K* s_out,
+                                            uint64_t* s_i, uint32_t bid, uint32_t nblocks) {
   constexpr uint32_t T = kBlock * ITEMS;
-  __shared__ K s_in[T];
-  __shared__ K s_out[T];
-  __shared__ uint64_t s_i0, s_i1;
-  if (halted(ctrl)) return;
-  const uint64_t nb = b.rec[j].N;
-  const uint64_t na = b.rec[j - 1].F;
   const uint64_t total = na + nb;
-  const K* __restrict__ A = b.full[(j - 1) & 1u];
-  const K* __restrict__ B = b.delta[j & 1u];
-  K* __restrict__ O = b.full[j & 1u];
   const uint64_t ntiles = (total + T - 1) / T;
   const int wid = threadIdx.x / kWave;
-  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (uint64_t tile = bid; tile < ntiles; tile += nblocks) {
     const uint64_t o0 = tile * T;
     const uint64_t o1 = min(o0 + T, total);
     if (wid == 0) {
       const uint64_t i0 = wave_merge_path(A, na, B, nb, o0);
-      if (lane_id() == 0) s_i0 = i0;
+      if (lane_id() == 0) s_i[0] = i0;
     } else if (wid == 1) {
       const uint64_t i1 = wave_merge_path(A, na, B, nb, o1);
-      if (lane_id() == 0) s_i1 = i1;
+      if (lane_id() == 0) s_i[1] = i1;
     }
     __syncthreads();
-    const uint64_t i0 = s_i0, i1 = s_i1;
+    const uint64_t i0 = s_i[0], i1 = s_i[1];
     const uint64_t j0 = o0 - i0, j1 = o1 - i1;
     const uint32_t ca = (uint32_t)(i1 - i0), cb = (uint32_t)(j1 - j0);
     if (cb == 0) {
@@ -797,6 +912,50 @@ __global__ __launch_bounds__(kBlock) void k_merge(Ctrl* ctrl, Bufs<K> b, uint32_
     }
     __syncthreads();
   }
+}
+
+// Iteration j: B' = merge(B, delta^j) into the other B buffer, or on a fold
+// A' = merge(A, B) into the other A buffer and B' = delta^j.  The two parts of a fold
+// write different buffers and share the grid (one launch per iteration either way).
+template <typename K, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_merge(Ctrl* ctrl, Bufs<K> b, uint32_t j) {
+  constexpr uint32_t T = kBlock * ITEMS;
+  __shared__ K s_in[T];
+  __shared__ K s_out[T];
+  __shared__ uint64_t s_i[2];
+  if (halted(ctrl)) return;
+  const IterRec rp = b.rec[j - 1];
+  const IterRec rj = b.rec[j];
+  const uint64_t fb = rp.F - rp.FA;
+  const K* __restrict__ delta = b.delta[j & 1u];
+  K* __restrict__ outB = b.fullB[rp.b ^ 1u];
+  if (!rj.fold) {
+    merge_tiles<K, ITEMS>(b.fullB[rp.b], fb, delta, rj.N, outB, s_in, s_out, s_i, blockIdx.x,
+                          gridDim.x);
+    return;
+  }
+  // blocks [0, ga) fold A and B, blocks [ga, grid) copy the delta, in proportion to size
+  const uint64_t fold_n = rp.FA + fb;
+  uint32_t ga = (uint32_t)((double)gridDim.x * (double)fold_n / (double)(fold_n + rj.N));
+  ga = max(1u, min(ga, gridDim.x - 1));
+  if (blockIdx.x < ga)
+    merge_tiles<K, ITEMS>(b.full[rp.a], rp.FA, b.fullB[rp.b], fb, b.full[rp.a ^ 1u], s_in, s_out, s_i,
+                          blockIdx.x, ga);
+  else
+    merge_tiles<K, ITEMS>(delta, rj.N, delta, 0, outB, s_in, s_out, s_i, blockIdx.x - ga,
+                          gridDim.x - ga);
+}
+
+// O = merge(A, B), sizes from the host (the final union of the two runs).
+template <typename K, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_merge_pair(const K* __restrict__ A, uint64_t na,
+                                                       const K* __restrict__ B, uint64_t nb,
+                                                       K* __restrict__ O) {
+  constexpr uint32_t T = kBlock * ITEMS;
+  __shared__ K s_in[T];
+  __shared__ K s_out[T];
+  __shared__ uint64_t s_i[2];
+  merge_tiles<K, ITEMS>(A, na, B, nb, O, s_in, s_out, s_i, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -893,6 +1052,16 @@ __global__ void k_resume(Ctrl* ctrl, uint64_t cand_cap, uint64_t full_cap, uint3
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
+// Launch with optional start / stop events stamped by the dispatch itself (timing that
+// agrees with a kernel trace; no marker packets between kernels).
+#define WG_LAUNCH(kernel, grid, start, stop, s, ...)                                            \
+  do {                                                                                           \
+    if ((start) || (stop))                                                                       \
+      hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, s, start, stop, 0, __VA_ARGS__); \
+    else                                                                                         \
+      hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, s, __VA_ARGS__);                   \
+  } while (0)
+
 static inline int stream_blocks(const Grid& g, uint64_t n) {
   const uint64_t need = (n + kBlock - 1) / kBlock;
   return (int)(need < (uint64_t)g.stream ? (need ? need : 1) : (uint64_t)g.stream);
@@ -911,9 +1080,9 @@ void launch_check_offsets(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint64
 
 template <typename K>
 void launch_pack_batch(hipStream_t s, const Grid& g, const uint32_t* src, const uint32_t* dst,
-                       uint64_t m, int w, const uint64_t* offsets, uint32_t num, K* keys) {
-  hipLaunchKernelGGL(k_pack_batch<K>, dim3(stream_blocks(g, m)), dim3(kBlock), 0, s, src, dst, m, w,
-                     offsets, num, keys);
+                       uint64_t m, int w, const uint64_t* offsets, uint32_t num, K* keys, Ev ev) {
+  WG_LAUNCH(k_pack_batch<K>, stream_blocks(g, m), ev.start, ev.stop, s, src, dst, m, w, offsets, num,
+            keys);
 }
 
 template <typename K>
@@ -925,60 +1094,61 @@ void launch_offsets(hipStream_t s, const Grid& g, const K* keys, uint64_t n, int
 
 template <typename K>
 void launch_pack(hipStream_t s, const Grid& g, const uint32_t* src, const uint32_t* dst,
-                 uint64_t m, int w, K* keys) {
-  hipLaunchKernelGGL(k_pack<K>, dim3(stream_blocks(g, m)), dim3(kBlock), 0, s, src, dst, m, w, keys);
+                 uint64_t m, int w, K* keys, Ev ev) {
+  WG_LAUNCH(k_pack<K>, stream_blocks(g, m), ev.start, ev.stop, s, src, dst, m, w, keys);
 }
 
 template <typename K>
 void launch_join_count(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w,
-                       uint32_t j) {
+                       uint32_t j, Ev ev) {
   if (kind == kJoinTC)
-    hipLaunchKernelGGL((k_join_count<K, kJoinTC, kJoinItems>), dim3(g.scan), dim3(kBlock), 0, s, ctrl, b, w, j);
+    WG_LAUNCH((k_join_count<K, kJoinTC, kJoinItems>), g.scan, ev.start, ev.stop, s, ctrl, b, w, j);
   else if (kind == kJoinSG)
-    hipLaunchKernelGGL((k_join_count<K, kJoinSG, kJoinItems>), dim3(g.scan), dim3(kBlock), 0, s, ctrl, b, w, j);
+    WG_LAUNCH((k_join_count<K, kJoinSG, kJoinItems>), g.scan, ev.start, ev.stop, s, ctrl, b, w, j);
   else
-    hipLaunchKernelGGL((k_join_count<K, kJoinSGBase, kJoinItems>), dim3(g.scan), dim3(kBlock), 0, s, ctrl, b, w, j);
+    WG_LAUNCH((k_join_count<K, kJoinSGBase, kJoinItems>), g.scan, ev.start, ev.stop, s, ctrl, b, w, j);
 }
 
 template <typename K>
 void launch_join_emit(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w,
-                      uint32_t j) {
+                      uint32_t j, Ev ev) {
   if (kind == kJoinTC)
-    hipLaunchKernelGGL((k_join_emit<K, kJoinTC, kEmitItems>), dim3(g.stream), dim3(kBlock), 0, s, ctrl, b, w, j, g.scan);
+    WG_LAUNCH((k_join_emit<K, kJoinTC, kEmitItems>), g.stream, ev.start, ev.stop, s, ctrl, b, w, j, g.scan);
   else if (kind == kJoinSG)
-    hipLaunchKernelGGL((k_join_emit<K, kJoinSG, kEmitItems>), dim3(g.stream), dim3(kBlock), 0, s, ctrl, b, w, j, g.scan);
+    WG_LAUNCH((k_join_emit<K, kJoinSG, kEmitItems>), g.stream, ev.start, ev.stop, s, ctrl, b, w, j, g.scan);
   else
-    hipLaunchKernelGGL((k_join_emit<K, kJoinSGBase, kEmitItems>), dim3(g.stream), dim3(kBlock), 0, s, ctrl, b, w, j, g.scan);
+    WG_LAUNCH((k_join_emit<K, kJoinSGBase, kEmitItems>), g.stream, ev.start, ev.stop, s, ctrl, b, w, j,
+              g.scan);
 }
 
 template <typename K, int RB, int ITEMS>
-void sort_impl(hipStream_t s, Ctrl* ctrl, const uint64_t* n_ptr, int key_bits, int G,
-               const Bufs<K>& b) {
+void sort_pass_impl(hipStream_t s, Ctrl* ctrl, const uint64_t* n_ptr, int G, const Bufs<K>& b, int p,
+                    bool scatter, Ev ev) {
   constexpr uint32_t T = kBlock * ITEMS;
-  const int passes = sort_passes(key_bits, RB);
-  for (int p = 0; p < passes; ++p) {
-    const K* in = b.cand[p & 1];
-    K* out = b.cand[(p + 1) & 1];
-    hipLaunchKernelGGL((k_radix_count<K, RB, ITEMS>), dim3(G), dim3(kBlock), 0, s, ctrl, n_ptr, in,
-                       p * RB, b.rcnt);
-    hipLaunchKernelGGL(k_radix_scan, dim3(1 << RB), dim3(kBlock), 0, s, ctrl, n_ptr, T, b.rcnt, b.rtot, G);
-    hipLaunchKernelGGL((k_radix_scatter<K, RB, ITEMS>), dim3(G), dim3(kBlock), 0, s, ctrl, n_ptr, in,
-                       out, p * RB, b.rcnt, b.rtot);
+  const K* in = b.cand[p & 1];
+  K* out = b.cand[(p + 1) & 1];
+  hipEvent_t none = nullptr;
+  if (!scatter) {
+    WG_LAUNCH((k_radix_count<K, RB, ITEMS>), G, ev.start, none, s, ctrl, n_ptr, in, p * RB, b.rcnt);
+    WG_LAUNCH(k_radix_scan, 1 << RB, none, ev.stop, s, ctrl, n_ptr, T, b.rcnt, b.rtot, G);
+  } else {
+    WG_LAUNCH((k_radix_scatter<K, RB, ITEMS>), G, ev.start, ev.stop, s, ctrl, n_ptr, in, out, p * RB,
+              b.rcnt, b.rtot);
   }
 }
 
 template <typename K>
-void launch_sort(hipStream_t s, Ctrl* ctrl, const uint64_t* n_ptr, int key_bits, const SortCfg& c,
-                 const Bufs<K>& b) {
+void launch_sort_pass(hipStream_t s, Ctrl* ctrl, const uint64_t* n_ptr, const SortCfg& c,
+                      const Bufs<K>& b, int pass, bool scatter, Ev ev) {
   constexpr int SMALL = 8;
   constexpr int LARGE = sizeof(K) == 4 ? 16 : 12;
   const bool large = c.items != SMALL;
   const int G = c.blocks;
   switch (c.rb) {
-#define WG_SORT_CASE(RB)                                                        \
-    case RB:                                                                    \
-      if (large) sort_impl<K, RB, LARGE>(s, ctrl, n_ptr, key_bits, G, b);       \
-      else sort_impl<K, RB, SMALL>(s, ctrl, n_ptr, key_bits, G, b);            \
+#define WG_SORT_CASE(RB)                                                                 \
+    case RB:                                                                             \
+      if (large) sort_pass_impl<K, RB, LARGE>(s, ctrl, n_ptr, G, b, pass, scatter, ev);  \
+      else sort_pass_impl<K, RB, SMALL>(s, ctrl, n_ptr, G, b, pass, scatter, ev);        \
       break;
     WG_SORT_CASE(8)
     WG_SORT_CASE(9)
@@ -992,22 +1162,30 @@ void launch_sort(hipStream_t s, Ctrl* ctrl, const uint64_t* n_ptr, int key_bits,
 
 template <typename K>
 void launch_compact(hipStream_t s, const Grid& g, int mode, Ctrl* ctrl, const uint64_t* n_ptr,
-                    const K* in, K* tmp, const Bufs<K>& b, int w, uint32_t j, uint32_t side) {
-  hipLaunchKernelGGL((k_compact_local<K, kDedupItems>), dim3(g.scan), dim3(kBlock), 0, s, ctrl, mode,
-                     n_ptr, in, tmp, b, w, j);
-  hipLaunchKernelGGL(k_compact_gather<K>, dim3(g.scan), dim3(kBlock), 0, s, ctrl, mode, n_ptr, tmp, b,
-                     j, side);
+                    const K* in, K* tmp, const Bufs<K>& b, int w, uint32_t j, uint32_t side, Ev ev) {
+  hipEvent_t none = nullptr;
+  WG_LAUNCH((k_compact_local<K, kDedupItems>), g.scan, ev.start, none, s, ctrl, mode, n_ptr, in, tmp, b, w,
+            j);
+  WG_LAUNCH(k_compact_gather<K>, g.scan, none, ev.stop, s, ctrl, mode, n_ptr, tmp, b, j, side);
 }
 
 template <typename K>
-void launch_merge(hipStream_t s, const Grid& g, Ctrl* ctrl, const Bufs<K>& b, uint32_t j) {
-  hipLaunchKernelGGL((k_merge<K, kMergeItems>), dim3(g.stream), dim3(kBlock), 0, s, ctrl, b, j);
+void launch_merge(hipStream_t s, const Grid& g, Ctrl* ctrl, const Bufs<K>& b, uint32_t j, Ev ev) {
+  WG_LAUNCH((k_merge<K, kMergeItems>), g.stream, ev.start, ev.stop, s, ctrl, b, j);
 }
 
 template <typename K>
-void launch_edge_index(hipStream_t s, const Grid& g, Ctrl* ctrl, const Bufs<K>& b, int w) {
-  hipLaunchKernelGGL((k_index_count<K, kIndexItems>), dim3(g.scan), dim3(kBlock), 0, s, ctrl, b, w);
-  hipLaunchKernelGGL((k_index_write<K, kIndexItems>), dim3(g.scan), dim3(kBlock), 0, s, ctrl, b, w);
+void launch_merge_pair(hipStream_t s, const Grid& g, const K* A, uint64_t na, const K* B, uint64_t nb,
+                       K* O, Ev ev) {
+  WG_LAUNCH((k_merge_pair<K, kMergeItems>), stream_blocks(g, (na + nb + 7) / 8), ev.start, ev.stop, s, A,
+            na, B, nb, O);
+}
+
+template <typename K>
+void launch_edge_index(hipStream_t s, const Grid& g, Ctrl* ctrl, const Bufs<K>& b, int w, Ev ev) {
+  hipEvent_t none = nullptr;
+  WG_LAUNCH((k_index_count<K, kIndexItems>), g.scan, ev.start, none, s, ctrl, b, w);
+  WG_LAUNCH((k_index_write<K, kIndexItems>), g.scan, none, ev.stop, s, ctrl, b, w);
 }
 
 template <typename K>
@@ -1022,21 +1200,23 @@ void launch_resume(hipStream_t s, Ctrl* ctrl, uint64_t cand_cap, uint64_t full_c
 
 #define WG_INSTANTIATE(K)                                                                          \
   template void launch_pack<K>(hipStream_t, const Grid&, const uint32_t*, const uint32_t*,       \
-                               uint64_t, int, K*);                                                \
+                               uint64_t, int, K*, Ev);                                            \
   template void launch_pack_batch<K>(hipStream_t, const Grid&, const uint32_t*, const uint32_t*, \
-                                     uint64_t, int, const uint64_t*, uint32_t, K*);               \
+                                     uint64_t, int, const uint64_t*, uint32_t, K*, Ev);           \
   template void launch_offsets<K>(hipStream_t, const Grid&, const K*, uint64_t, int, uint32_t,   \
                                   uint64_t*);                                                      \
   template void launch_join_count<K>(hipStream_t, const Grid&, int, Ctrl*, const Bufs<K>&, int,   \
-                                     uint32_t);                                                    \
+                                     uint32_t, Ev);                                                \
   template void launch_join_emit<K>(hipStream_t, const Grid&, int, Ctrl*, const Bufs<K>&, int,    \
-                                    uint32_t);                                                     \
-  template void launch_sort<K>(hipStream_t, Ctrl*, const uint64_t*, int, const SortCfg&,         \
-                               const Bufs<K>&);                                                    \
+                                    uint32_t, Ev);                                                 \
+  template void launch_sort_pass<K>(hipStream_t, Ctrl*, const uint64_t*, const SortCfg&,         \
+                                    const Bufs<K>&, int, bool, Ev);                                \
   template void launch_compact<K>(hipStream_t, const Grid&, int, Ctrl*, const uint64_t*, const K*, \
-                                  K*, const Bufs<K>&, int, uint32_t, uint32_t);                    \
-  template void launch_merge<K>(hipStream_t, const Grid&, Ctrl*, const Bufs<K>&, uint32_t);       \
-  template void launch_edge_index<K>(hipStream_t, const Grid&, Ctrl*, const Bufs<K>&, int);       \
+                                  K*, const Bufs<K>&, int, uint32_t, uint32_t, Ev);                \
+  template void launch_merge<K>(hipStream_t, const Grid&, Ctrl*, const Bufs<K>&, uint32_t, Ev);   \
+  template void launch_merge_pair<K>(hipStream_t, const Grid&, const K*, uint64_t, const K*,     \
+                                     uint64_t, K*, Ev);                                            \
+  template void launch_edge_index<K>(hipStream_t, const Grid&, Ctrl*, const Bufs<K>&, int, Ev);   \
   template void launch_unpack<K>(hipStream_t, const Grid&, const K*, uint64_t, int, uint32_t*,    \
                                  uint32_t*);
 

@@ -47,6 +47,12 @@ struct SortCfg {
 // Consumers keep the per-block totals of a launch in LDS, so this is bounded.
 constexpr int kScanBlocksMax = 1024;
 
+// Optional events stamped at the start of a stage's first kernel and the end of its last.
+struct Ev {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+};
+
 struct Grid {
   int stream;  // blocks of grid-stride kernels (emit, merge, pack, unpack)
   int scan;    // blocks of the static-range kernels (<= kScanBlocksMax)
@@ -56,7 +62,8 @@ struct Grid {
 template <typename K>
 struct Bufs {
   K* cand[2];      // join output / radix ping-pong; the free one is compaction scratch
-  K* full[2];      // Full ping-pong: iteration j reads side (j-1)&1, writes side j&1
+  K* full[2];      // large run A of Full, ping-pong (side in the records)
+  K* fullB[2];     // small run B of Full, ping-pong (side in the records)
   K* delta[2];     // delta ping-pong: iteration j reads side (j-1)&1, writes side j&1
   K* E;            // sorted, deduplicated edge keys
   uint32_t* U;     // distinct (inst, src) rows of E, ascending
@@ -77,7 +84,7 @@ void launch_max_id(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint32_t* src
 
 template <typename K>
 void launch_pack(hipStream_t s, const Grid& g, const uint32_t* src, const uint32_t* dst,
-                 uint64_t m, int w, K* keys);
+                 uint64_t m, int w, K* keys, Ev ev = Ev());
 
 // Batches: validate the instance offsets (sets ctrl->bad_input), pack with the instance
 // in the top key bits, and find each instance's first key in the sorted result.
@@ -85,7 +92,8 @@ void launch_check_offsets(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint64
                           uint32_t num, uint64_t m);
 template <typename K>
 void launch_pack_batch(hipStream_t s, const Grid& g, const uint32_t* src, const uint32_t* dst,
-                       uint64_t m, int w, const uint64_t* offsets, uint32_t num, K* keys);
+                       uint64_t m, int w, const uint64_t* offsets, uint32_t num, K* keys,
+                       Ev ev = Ev());
 template <typename K>
 void launch_offsets(hipStream_t s, const Grid& g, const K* keys, uint64_t n, int shift, uint32_t num,
                     uint64_t* out);
@@ -93,28 +101,39 @@ void launch_offsets(hipStream_t s, const Grid& g, const K* keys, uint64_t n, int
 // Join of iteration j (kind kJoinSGBase: the base rule, j = 0): count, then emit.
 template <typename K>
 void launch_join_count(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w,
-                       uint32_t j);
+                       uint32_t j, Ev ev = Ev());
 template <typename K>
 void launch_join_emit(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w,
-                      uint32_t j);
+                      uint32_t j, Ev ev = Ev());
 
-// LSD sort of the low `key_bits` bits of *n_ptr keys starting in cand[0]:
-// sort_passes(key_bits, c.rb) passes; the result ends in cand[passes & 1].
+// One LSD pass over *n_ptr keys: pass p reads cand[p & 1] and writes cand[(p + 1) & 1];
+// digit p covers bits [p * c.rb, (p + 1) * c.rb).  `scatter` false: the count and scan
+// launches; true: the scatter launch.  sort_passes(key bits, c.rb) passes sort the keys,
+// which end in cand[passes & 1].
 template <typename K>
-void launch_sort(hipStream_t s, Ctrl* ctrl, const uint64_t* n_ptr, int key_bits, const SortCfg& c,
-                 const Bufs<K>& b);
+void launch_sort_pass(hipStream_t s, Ctrl* ctrl, const uint64_t* n_ptr, const SortCfg& c,
+                      const Bufs<K>& b, int pass, bool scatter, Ev ev = Ev());
 
 // Compaction (dedup + set difference, seeding, or the diagonal filter): local + gather.
 // `in` holds *n_ptr sorted keys; `tmp` is scratch of the same capacity.
 template <typename K>
 void launch_compact(hipStream_t s, const Grid& g, int mode, Ctrl* ctrl, const uint64_t* n_ptr,
-                    const K* in, K* tmp, const Bufs<K>& b, int w, uint32_t j, uint32_t side);
+                    const K* in, K* tmp, const Bufs<K>& b, int w, uint32_t j, uint32_t side,
+                    Ev ev = Ev());
+
+// Merge of iteration j: B' = merge(B, delta), or on a fold A' = merge(A, B) and B' = delta.
+template <typename K>
+void launch_merge(hipStream_t s, const Grid& g, Ctrl* ctrl, const Bufs<K>& b, uint32_t j,
+                  Ev ev = Ev());
+
+// O = merge(A, B) of two disjoint sorted arrays with sizes known on the host.
+template <typename K>
+void launch_merge_pair(hipStream_t s, const Grid& g, const K* A, uint64_t na, const K* B, uint64_t nb,
+                       K* O, Ev ev = Ev());
 
 template <typename K>
-void launch_merge(hipStream_t s, const Grid& g, Ctrl* ctrl, const Bufs<K>& b, uint32_t j);
-
-template <typename K>
-void launch_edge_index(hipStream_t s, const Grid& g, Ctrl* ctrl, const Bufs<K>& b, int w);
+void launch_edge_index(hipStream_t s, const Grid& g, Ctrl* ctrl, const Bufs<K>& b, int w,
+                       Ev ev = Ev());
 
 template <typename K>
 void launch_unpack(hipStream_t s, const Grid& g, const K* keys, uint64_t n, int w,

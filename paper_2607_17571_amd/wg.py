@@ -28,6 +28,7 @@ WG_ERR_CANCELLED = 7
 
 WG_SG_IRREFLEXIVE = 0x1
 WG_STAGE_TIMING = 0x2
+WG_NO_SPECULATION = 0x4
 
 WG_QUERY_TC = 0
 WG_QUERY_SG = 1

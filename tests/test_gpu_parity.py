@@ -156,6 +156,7 @@ def test_sg_irreflexive(engine):
 @pytest.mark.parametrize("opts", [
     dict(batch_k=1), dict(batch_k=3), dict(batch_k=64), dict(loop_mode=wg.WG_LOOP_HOST),
     dict(radix_field_bits=32), dict(radix_field_bits=24), dict(flags=wg.WG_STAGE_TIMING),
+    dict(flags=wg.WG_NO_SPECULATION), dict(flags=wg.WG_NO_SPECULATION, batch_k=2),
 ])
 def test_result_independent_of_loop_policy(engine, opts):
     src, dst = inputs.rmat(11, 1800, *inputs.RMAT_ABCD, seed=9)
