@@ -219,6 +219,18 @@ def test_capacity_error_leaves_engine_usable(engine):
     assert_same(s, d, st, oracle.tc(a, b))
 
 
+def test_rmat_scale22_reports_capacity(engine):
+    """R-MAT scale 22 (3.8M edges) has a ~3.9e11-tuple closure: under a 12 GiB budget the
+    solve must stop with WG_ERR_CAPACITY and leave the engine usable."""
+    w = inputs.workload("tc_rmat_s22")
+    with pytest.raises(wg.WgError) as ei:
+        run(engine, "tc", w.src, w.dst, wg.make_options(mem_budget_bytes=12 << 30))
+    assert ei.value.status == wg.WG_ERR_CAPACITY
+    a, b = inputs.chain(30)
+    s, d, st = run(engine, "tc", a, b)
+    assert_same(s, d, st, oracle.tc(a, b))
+
+
 def test_iteration_limit(engine):
     a, b = inputs.chain(100)
     with pytest.raises(wg.WgError) as ei:
