@@ -54,7 +54,7 @@ typedef enum {
   WG_ERR_CANCELLED = 7      /* a served request was cancelled */
 } wg_status;
 
-typedef enum { WG_QUERY_TC = 0, WG_QUERY_SG = 1 } wg_query;
+typedef enum { WG_QUERY_TC = 0, WG_QUERY_SG = 1, WG_QUERY_TRIANGLES = 2 } wg_query;
 
 /* wg_options.flags */
 #define WG_SG_IRREFLEXIVE 0x1u /* SG: drop (x,x) from the final relation */
@@ -166,6 +166,18 @@ uint32_t wg_result_instances(const wg_result* result);
  * (then the call waits) with capacity >= instances + 1 entries. */
 wg_status wg_result_offsets(const wg_result* result, uint64_t* offsets_out, uint64_t capacity,
                             void* stream);
+
+/* Triangle counting (Section VI): the number of bindings (a, b, c) of
+ * triangle(a,b,c) <- edge(a,b), edge(b,c), edge(c,a) over the set of the m edges
+ * (d_src[i], d_dst[i]) -- a directed 3-cycle counts once per rotation, an edge (a, a)
+ * counts once as (a, a, a) -- which equals trace(A^3) of the 0/1 adjacency matrix.  One
+ * non-recursive pass of the sorted-array join: every edge (a, b) expands the row of b in
+ * E, and each two-path (a, c) is probed against E for (c, a); nothing is materialised.
+ * *count_out (host) receives the count.  More than 2^32 two-paths: WG_ERR_CAPACITY.
+ * stats.join_candidates is the number of two-paths. */
+wg_status wg_triangles(wg_engine* engine, const uint32_t* d_src, const uint32_t* d_dst, uint64_t m,
+                       const wg_options* options, void* stream, uint64_t* count_out,
+                       wg_stats* stats);
 
 /* Number of tuples in the result (for a batch: over all instances). */
 uint64_t wg_result_size(const wg_result* result);

@@ -58,6 +58,8 @@ struct wg_engine {
   uint64_t* d_bcnt = nullptr;
   uint32_t* d_rcnt = nullptr;
   uint32_t* d_rtot = nullptr;
+  uint64_t* d_hits = nullptr;  // triangle probe: hits per emit block (grid.stream entries)
+  uint64_t tri_count = 0;      // the latest triangle count
   DevBuf cand[2], full[2], fullB[2], delta[2], E, U, R, Edst, rowa, rowb, off, rec;
   size_t allocated = 0;
   size_t peak = 0;
@@ -249,6 +251,7 @@ Bufs<K> make_bufs(wg_engine* e) {
   b.bcnt = e->d_bcnt;
   b.rcnt = e->d_rcnt;
   b.rtot = e->d_rtot;
+  b.hits = e->d_hits;
   b.rec = (IterRec*)e->rec.p;
   return b;
 }
@@ -442,10 +445,43 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   else
     launch_pack<K>(e->stream, e->grid, src, dst, m, w, b.cand[0], stage(e, WG_STAGE_PREPARE));
   enqueue_sort<K>(e, b, &e->d_ctrl->m_in);
-  const int mode = query == WG_QUERY_TC ? (kModeEdges | kModeSeed) : kModeEdges;
+  const int mode = query == WG_QUERY_SG ? kModeEdges : (kModeEdges | kModeSeed);
   launch_compact<K>(e->stream, e->grid, mode, e->d_ctrl, &e->d_ctrl->m_in, b.cand[passes & 1],
                     b.cand[(passes & 1) ^ 1], b, w, 0, 0, stage(e, WG_STAGE_DEDUP_DIFF));
   launch_edge_index<K>(e->stream, e->grid, e->d_ctrl, b, w, stage(e, WG_STAGE_PREPARE));
+
+  if (query == WG_QUERY_TRIANGLES) {
+    // Section VI: one pass of the join of E with itself; the emit phase probes E for the
+    // closing edge of each two-path and counts the hits per block
+    launch_join_count<K>(e->stream, e->grid, kJoinTri, e->d_ctrl, b, w, 1, stage(e, WG_STAGE_JOIN_COUNT));
+    launch_join_emit<K>(e->stream, e->grid, kJoinTri, e->d_ctrl, b, w, 1, stage(e, WG_STAGE_JOIN_EMIT));
+    std::vector<uint64_t> hits((size_t)e->grid.stream);
+    hip_check(e, hipMemcpyAsync(hits.data(), e->d_hits, hits.size() * sizeof(uint64_t),
+                                hipMemcpyDeviceToHost, e->stream), "readback");
+    read_back(e, 0, 0, 1);
+    const Readback r = wait_back(e, 0);
+    if (r.c.overflow) fail(e, WG_ERR_CAPACITY, "more than 2^32 two-paths");
+    uint64_t total = 0;
+    for (uint64_t h : hits) total += h;
+    e->tri_count = total;
+    e->res_keys = nullptr;
+    e->res_n = 0;
+    e->res_w = w;
+    if (st) {
+      st->iterations = 1;
+      st->base_tuples = r.first.N;
+      st->join_candidates = r.last.C;
+      st->field_bits = (uint32_t)w;
+      st->key_bytes = (uint32_t)sizeof(K);
+      st->digit_bits = (uint32_t)e->sort.rb;
+      st->sort_passes = (uint32_t)passes;
+      const double D = (double)r.first.N, C = (double)r.last.C;
+      add_bytes(st, WG_STAGE_JOIN_COUNT, D * (sizeof(K) + 4.0));
+      add_bytes(st, WG_STAGE_JOIN_EMIT, D * (sizeof(K) + 4.0) + C * 4.0);
+      collect_timing(e, st);
+    }
+    return WG_OK;
+  }
 
   if (query == WG_QUERY_SG) {
     // base rule: Delta^0 = Full = {(x, y) : E(p, x), E(p, y), x != y}, sorted + deduplicated
@@ -827,6 +863,7 @@ wg_status wg_engine_create(int device, wg_engine** out) {
     hip_check(e, hipMalloc((void**)&e->d_bcnt, sizeof(uint64_t) * kScanBlocksMax), "hipMalloc");
     hip_check(e, hipMalloc((void**)&e->d_rcnt, sizeof(uint32_t) * kRadixMax * kRadixBlocksMax), "hipMalloc");
     hip_check(e, hipMalloc((void**)&e->d_rtot, sizeof(uint32_t) * kRadixMax), "hipMalloc");
+    hip_check(e, hipMalloc((void**)&e->d_hits, sizeof(uint64_t) * e->grid.stream), "hipMalloc");
     hip_check(e, hipMemset(e->d_ctrl, 0, sizeof(Ctrl)), "hipMemset");
     for (int s = 0; s < 2; ++s)
       hip_check(e, hipEventCreateWithFlags(&e->ev_batch[s], hipEventDisableTiming), "hipEventCreate");
@@ -866,6 +903,7 @@ void wg_engine_destroy(wg_engine* e) {
   if (e->d_bcnt) (void)hipFree(e->d_bcnt);
   if (e->d_rcnt) (void)hipFree(e->d_rcnt);
   if (e->d_rtot) (void)hipFree(e->d_rtot);
+  if (e->d_hits) (void)hipFree(e->d_hits);
   if (e->h_up) (void)hipHostFree(e->h_up);
   if (e->h_rb) (void)hipHostFree(e->h_rb);
   for (int s = 0; s < 2; ++s)
@@ -902,6 +940,22 @@ wg_status wg_sg_batch(wg_engine* e, uint32_t num_instances, const uint64_t* d_of
     return WG_ERR_INVALID_ARG;
   }
   return solve(e, WG_QUERY_SG, num_instances, d_offsets, d_src, d_dst, m, o, stream, out, st);
+}
+
+wg_status wg_triangles(wg_engine* e, const uint32_t* d_src, const uint32_t* d_dst, uint64_t m,
+                       const wg_options* o, void* stream, uint64_t* count_out, wg_stats* st) {
+  if (!e) return WG_ERR_INVALID_ARG;
+  if (!count_out) {
+    e->err = "count_out is NULL";
+    return WG_ERR_INVALID_ARG;
+  }
+  *count_out = 0;
+  e->tri_count = 0;
+  wg_result* res = nullptr;
+  const wg_status r = solve(e, WG_QUERY_TRIANGLES, 0, nullptr, d_src, d_dst, m, o, stream, &res, st);
+  wg_result_free(res);
+  if (r == WG_OK) *count_out = e->tri_count;
+  return r;
 }
 
 uint32_t wg_result_instances(const wg_result* r) { return r ? r->num_inst : 0; }

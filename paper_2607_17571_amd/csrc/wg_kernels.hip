@@ -192,8 +192,10 @@ __global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int
   const uint64_t n = (Q == kJoinSGBase) ? ctrl->nu : b.rec[j - 1].N;
   const uint64_t C = block_prefix(b.jtot, gc, s_pre, s_wave);
   const uint32_t hook = ctrl->force_overflow_at;
-  const bool forced = Q != kJoinSGBase && hook != 0 && hook == j;
-  if (C > ctrl->cand_cap || forced) {
+  const bool forced = Q != kJoinSGBase && Q != kJoinTri && hook != 0 && hook == j;
+  // candidates are stored (all but the probe), and positions are 32-bit
+  const bool over = Q == kJoinTri ? C > 0xFFFFFFFFull : C > ctrl->cand_cap;
+  if (over || forced) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       b.rec[j].C = C;
       atomicOr(&ctrl->overflow, 1u);
@@ -211,6 +213,7 @@ __global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int
   auto at = [&](uint64_t i) -> uint64_t { return s_pre[i / Pc] + off[i]; };
   const uint64_t ntiles = (C + T - 1) / T;
   const int wid = threadIdx.x / kWave;
+  uint64_t hits = 0;  // kJoinTri: closing edges found by this thread
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const uint64_t p0 = tile * T;
     const uint64_t p1 = min(p0 + T, C);
@@ -237,6 +240,8 @@ __global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int
       pos[k] = (uint32_t)min(p, p1 - 1);
     }
     uint64_t li[ITEMS];
+    K probe[ITEMS];
+    bool live[ITEMS];
     if (in_lds) {
       multi_upper_bound<uint32_t, ITEMS>(s_off, span, pos, li);
     } else {
@@ -245,6 +250,8 @@ __global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
       const uint64_t p = p0 + (uint64_t)k * kBlock + threadIdx.x;
+      live[k] = p < p1;
+      probe[k] = K(0);
       if (p < p1) {
         const uint64_t i = i0 + li[k] - 1;
         const uint32_t start = in_lds ? s_off[li[k] - 1] : (uint32_t)at(i);
@@ -253,6 +260,15 @@ __global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int
         if (Q == kJoinTC) {
           const K dk = delta[i];
           key = ((dk >> w) << w) | (K)Edst[R[b.rowb[i]] + r];
+        } else if (Q == kJoinTri) {
+          // two-path (a, c) of edges (a, b), (b, c); the closing edge is (c, a)
+          const K dk = delta[i];
+          const K mask = field_mask<K>(w);
+          const K a = (dk >> w) & mask;
+          const K inst = (dk >> w) >> w;
+          const K c = (K)Edst[R[b.rowb[i]] + r];
+          probe[k] = (((inst << w) | c) << w) | a;
+          key = K(0);
         } else if (Q == kJoinSG) {
           const K dk = delta[i];
           const uint32_t ja = b.rowa[i], jb = b.rowb[i];
@@ -270,10 +286,23 @@ __global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int
           const K inst = (K)(b.U[i] >> w);
           key = ((((inst << w) | (K)Edst[R[i] + qa]) << w) | (K)Edst[R[i] + qb]);
         }
-        cand[p] = key;
+        if (Q != kJoinTri) cand[p] = key;
       }
     }
+    if (Q == kJoinTri) {
+      uint64_t pos[ITEMS];
+      const uint64_t mu = ctrl->m_unique;
+      multi_lower_bound<K, ITEMS>(b.E, mu, probe, pos);
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k)
+        if (live[k] && pos[k] < mu && b.E[pos[k]] == probe[k]) ++hits;
+    }
     __syncthreads();
+  }
+  if (Q == kJoinTri) {
+    uint64_t total;
+    (void)block_excl_scan<uint64_t>(hits, s_wave, total);
+    if (threadIdx.x == 0) b.hits[blockIdx.x] = total;
   }
 }
 
@@ -1105,6 +1134,8 @@ void launch_join_count(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const
     WG_LAUNCH((k_join_count<K, kJoinTC, kJoinItems>), g.scan, ev.start, ev.stop, s, ctrl, b, w, j);
   else if (kind == kJoinSG)
     WG_LAUNCH((k_join_count<K, kJoinSG, kJoinItems>), g.scan, ev.start, ev.stop, s, ctrl, b, w, j);
+  else if (kind == kJoinTri)  // counts as the TC join
+    WG_LAUNCH((k_join_count<K, kJoinTC, kJoinItems>), g.scan, ev.start, ev.stop, s, ctrl, b, w, j);
   else
     WG_LAUNCH((k_join_count<K, kJoinSGBase, kJoinItems>), g.scan, ev.start, ev.stop, s, ctrl, b, w, j);
 }
@@ -1116,6 +1147,9 @@ void launch_join_emit(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const 
     WG_LAUNCH((k_join_emit<K, kJoinTC, kEmitItems>), g.stream, ev.start, ev.stop, s, ctrl, b, w, j, g.scan);
   else if (kind == kJoinSG)
     WG_LAUNCH((k_join_emit<K, kJoinSG, kEmitItems>), g.stream, ev.start, ev.stop, s, ctrl, b, w, j, g.scan);
+  else if (kind == kJoinTri)
+    WG_LAUNCH((k_join_emit<K, kJoinTri, kEmitItems>), g.stream, ev.start, ev.stop, s, ctrl, b, w, j,
+              g.scan);
   else
     WG_LAUNCH((k_join_emit<K, kJoinSGBase, kEmitItems>), g.stream, ev.start, ev.stop, s, ctrl, b, w, j,
               g.scan);

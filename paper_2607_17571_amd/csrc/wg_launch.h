@@ -9,7 +9,9 @@
 namespace wg {
 
 // Query kinds of the join.
-enum JoinKind : int { kJoinTC = 0, kJoinSG = 1, kJoinSGBase = 2 };
+// kJoinTri: the TC join of E with itself whose emit phase probes E for each two-path's
+// closing edge instead of writing candidates (triangle counting, Section VI).
+enum JoinKind : int { kJoinTC = 0, kJoinSG = 1, kJoinSGBase = 2, kJoinTri = 3 };
 
 // Compaction modes of dedup_local / dedup_gather.
 enum CompactMode : int {
@@ -74,6 +76,7 @@ struct Bufs {
   uint32_t* off;   // per delta tuple: first candidate, relative to its block's range
   uint64_t* jtot;  // per join-count block: candidates of its range
   uint64_t* bcnt;  // per compaction block: survivors of its range
+  uint64_t* hits;  // triangle probe: closing edges found per emit block
   uint32_t* rcnt;  // radix: per-block digit counts, then offsets (digits x blocks)
   uint32_t* rtot;  // radix: digit totals
   IterRec* rec;    // per-iteration sizes

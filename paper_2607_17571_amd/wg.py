@@ -32,6 +32,7 @@ WG_NO_SPECULATION = 0x4
 
 WG_QUERY_TC = 0
 WG_QUERY_SG = 1
+WG_QUERY_TRIANGLES = 2
 
 WG_LOOP_AUTO = 0
 WG_LOOP_BATCHED = 1
@@ -153,6 +154,8 @@ SIGNATURES = [
                             POINTER(WgOptions), c_void_p, POINTER(c_void_p), POINTER(WgStats)]),
     ("wg_sg_batch", c_int, [c_void_p, c_uint32, c_void_p, c_void_p, c_void_p, c_uint64,
                             POINTER(WgOptions), c_void_p, POINTER(c_void_p), POINTER(WgStats)]),
+    ("wg_triangles", c_int, [c_void_p, c_void_p, c_void_p, c_uint64, POINTER(WgOptions), c_void_p,
+                             POINTER(c_uint64), POINTER(WgStats)]),
     ("wg_result_instances", c_uint32, [c_void_p]),
     ("wg_result_offsets", c_int, [c_void_p, c_void_p, c_uint64, c_void_p]),
     ("wg_get_sort_config", c_int, [c_void_p, c_uint32, POINTER(WgSortConfig)]),
@@ -252,6 +255,16 @@ def wg_tc_batch(engine, num: int, d_offsets: int, d_src: int, d_dst: int, m: int
 def wg_sg_batch(engine, num: int, d_offsets: int, d_src: int, d_dst: int, m: int,
                 options: WgOptions | None, stream: int, stats: WgStats | None = None):
     return _batch(lib().wg_sg_batch, engine, num, d_offsets, d_src, d_dst, m, options, stream, stats)
+
+
+def wg_triangles(engine, d_src: int, d_dst: int, m: int, options: WgOptions | None, stream: int,
+                 stats: WgStats | None = None):
+    """Returns (status, count)."""
+    count = c_uint64(0)
+    st = lib().wg_triangles(engine, c_void_p(d_src), c_void_p(d_dst), m,
+                            byref(options) if options is not None else None, c_void_p(stream),
+                            byref(count), byref(stats) if stats is not None else None)
+    return st, int(count.value)
 
 
 def wg_result_instances(result) -> int:
@@ -509,6 +522,19 @@ class Engine:
         if st != WG_OK:
             raise WgError(st, wg_last_error(self.handle))
         return rep.as_dict()
+
+    def triangles(self, src, dst, options: WgOptions | None = None):
+        """wg_triangles on torch uint32/int32 CUDA tensors; returns (count, stats)."""
+        import torch
+
+        src, dst, _ = self._check_edges(src, dst)
+        stream = torch.cuda.current_stream(src.device).cuda_stream
+        stats = WgStats()
+        st, count = wg_triangles(self.handle, src.data_ptr(), dst.data_ptr(), src.numel(), options,
+                                 stream, stats)
+        if st != WG_OK:
+            raise WgError(st, wg_last_error(self.handle))
+        return count, stats_dict(stats)
 
     def sort_config(self, key_bytes: int) -> dict:
         st, cfg = wg_get_sort_config(self.handle, key_bytes)
