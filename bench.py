@@ -84,6 +84,10 @@ def parse():
     p.add_argument("--requests", type=int, default=120, help="served_mix: number of requests")
     p.add_argument("--slots", type=int, default=4, help="served_mix: concurrent solves")
     p.add_argument("--load", type=float, default=0.7, help="served_mix: offered load / capacity")
+    p.add_argument("--ablation", choices=["join", "triangles", "sync", "engineering"], default=None,
+                   help="time the variants of one design choice instead of the headline line")
+    p.add_argument("--ablation-workloads", default=None,
+                   help="comma-separated workload names for --ablation (default: per ablation)")
     return p.parse_args()
 
 
@@ -251,6 +255,190 @@ def run_served(args):
     print(json.dumps(out), flush=True)
 
 
+# ---------------------------------------------------------------------------
+# Ablations: the same solves with one design choice switched, each variant timed over
+# the same K steps after W warmup solves (no events in the timed solves; one extra solve
+# with events on every kernel gives the per-stage split).  One JSON line per ablation.
+# ---------------------------------------------------------------------------
+ABLATION_DEFAULTS = {
+    "join": "tc_rmat_s15,tc_rmat_s16",
+    "triangles": "tri_rmat_s14,tri_rmat_s16",
+    "sync": "tc_er_2000,sg_er_500k,tc_grid_100",
+    "engineering": "tc_rmat_s15,sg_er_500k,tc_er_2000",
+}
+TRIANGLE_GRAPHS = {  # R-MAT stand-ins for SNAP graphs with hubs of out-degree in the thousands
+    "tri_rmat_s14": (14, 8 << 14), "tri_rmat_s16": (16, 8 << 16), "tri_rmat_s17": (17, 8 << 17),
+}
+
+
+def _progress(msg):
+    print(f"[ablation] {msg}", file=sys.stderr, flush=True)
+
+
+def _time_variant(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = None
+    for _ in range(steps):
+        st = fn(False)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    probe = fn(True)
+    return ms, st, probe
+
+
+def _latencies(torch):
+    """Host round-trip latencies of the runtime: the cost the loop policies trade."""
+    reps = 2000
+    x = torch.zeros(1, dtype=torch.int32, device="cuda")
+    h = torch.empty(1, dtype=torch.int32, pin_memory=True)
+    s = torch.cuda.current_stream()
+    out = {}
+
+    def clock(name, body):
+        for _ in range(50):
+            body()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            body()
+        out[name] = round(1e6 * (time.perf_counter() - t0) / reps, 2)
+
+    clock("sync_idle_stream_us", lambda: s.synchronize())
+    ev = torch.cuda.Event()
+
+    def fence():
+        ev.record(s)
+        ev.synchronize()
+    clock("event_record_wait_us", fence)
+
+    def readback():
+        h.copy_(x, non_blocking=True)
+        s.synchronize()
+    clock("readback_4B_us", readback)
+
+    def launch_wait():
+        x.add_(1)
+        s.synchronize()
+    clock("kernel_launch_wait_us", launch_wait)
+
+    def launches():
+        x.add_(1)
+    clock("kernel_launch_enqueue_us", launches)
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(s)
+    with torch.cuda.stream(cs):
+        x.add_(1)
+        cs.synchronize()
+        with torch.cuda.graph(g, stream=cs):
+            for _ in range(32):
+                x.add_(1)
+    s.wait_stream(cs)
+    s.synchronize()
+
+    def graph_wait():
+        g.replay()
+        torch.cuda.current_stream().synchronize()
+    clock("graph_32_kernels_replay_wait_us", graph_wait)
+
+    def eager_wait():
+        for _ in range(32):
+            x.add_(1)
+        s.synchronize()
+    clock("eager_32_kernels_wait_us", eager_wait)
+    return out
+
+
+def run_ablation(args):
+    import numpy as np  # noqa: F401
+    import torch
+
+    from paper_2607_17571_amd import inputs, wg
+
+    names = (args.ablation_workloads or ABLATION_DEFAULTS[args.ablation]).split(",")
+    eng = wg.Engine(0)
+    T = wg.WG_STAGE_TIMING
+    results = {}
+    extra = {}
+    for name in names:
+        if args.ablation == "triangles":
+            scale, m = TRIANGLE_GRAPHS[name]
+            s_np, d_np = inputs.rmat(scale, m, *inputs.RMAT_ABCD, seed=scale)
+            src, dst = torch.from_numpy(s_np).cuda(), torch.from_numpy(d_np).cuda()
+            variants = {"sorted": 0, "hash": wg.WG_JOIN_HASH}
+            row = {"graph": f"R-MAT scale {scale}, m={len(s_np)}, seed {scale}",
+                   "max_out_degree": int(np.bincount(s_np).max())}
+            for vname, fl in variants.items():
+                def fn(timing, fl=fl):
+                    return eng.triangles(src, dst, wg.make_options(flags=fl | (T if timing else 0)))
+                ms, (count, st), (_, pr) = _time_variant(torch, fn, args.steps, args.warmup)
+                row[vname] = {"ms": round(ms, 3), "triangles": count,
+                              "two_paths": st["join_candidates"],
+                              "join_ms": round(pr["stage_ms"]["join_count"] + pr["stage_ms"]["join_emit"], 3),
+                              "prepare_ms": round(pr["stage_ms"]["prepare"], 3)}
+                _progress(f"{name} {vname}: {row[vname]}")
+            row["triangles_per_edge"] = round(row["sorted"]["triangles"] / max(1, len(s_np)), 2)
+            row["hash_over_sorted"] = round(row["hash"]["ms"] / row["sorted"]["ms"], 3)
+            row["agree"] = row["sorted"]["triangles"] == row["hash"]["triangles"]
+            results[name] = row
+            continue
+        w = inputs.workload(name)
+        src, dst = torch.from_numpy(w.src).cuda(), torch.from_numpy(w.dst).cuda()
+        if args.ablation == "join":
+            variants = {"sorted": {}, "hash": dict(flags=wg.WG_JOIN_HASH)}
+        elif args.ablation == "sync":
+            ns = wg.WG_NO_SPECULATION
+            variants = {
+                "per_stage_readback": dict(loop_mode=wg.WG_LOOP_STAGE),
+                "per_iteration_readback": dict(loop_mode=wg.WG_LOOP_HOST, flags=ns),
+                "batch_10": dict(loop_mode=wg.WG_LOOP_BATCHED, batch_k=10, flags=ns),
+                "batch_30": dict(loop_mode=wg.WG_LOOP_BATCHED, batch_k=30, flags=ns),
+                "adaptive": dict(flags=ns),
+                "adaptive_speculative": {},
+            }
+            if w.query == "tc":
+                for k in (2, 5, 20, 40, 50):
+                    variants[f"batch_{k}"] = dict(loop_mode=wg.WG_LOOP_BATCHED, batch_k=k, flags=ns)
+        else:
+            variants = {
+                "default": {},
+                "unfused_dedup_diff": dict(flags=wg.WG_UNFUSED_DEDUP),
+                "digits_8_adaptive_width": dict(radix_digit_bits=8),
+                "digits_8_fixed_32bit_fields": dict(radix_digit_bits=8, radix_field_bits=32),
+            }
+        row = {"query": w.query, "edges": int(w.src.size)}
+        tuples = None
+        for vname, kw in variants.items():
+            kw = dict(kw)
+            fl = kw.pop("flags", 0)
+
+            def fn(timing, fl=fl, kw=kw):
+                return eng.solve(w.query, src, dst, wg.make_options(flags=fl | (T if timing else 0), **kw),
+                                 )[2]
+            ms, st, pr = _time_variant(torch, fn, args.steps, args.warmup)
+            if tuples is None:
+                tuples = st["result_tuples"]
+            elif st["result_tuples"] != tuples:
+                raise SystemExit(f"{name} {vname}: {st['result_tuples']} tuples, expected {tuples}")
+            row[vname] = {"ms_per_step": round(ms, 3), "host_syncs": st["host_syncs"],
+                          "iterations": st["iterations"], "sort_passes": st["sort_passes"],
+                          "stage_ms": {k: round(v, 3) for k, v in pr["stage_ms"].items()}}
+            _progress(f"{name} {vname}: {ms:.3f} ms, {st['host_syncs']} host syncs")
+        row["fixpoint_tuples"] = tuples
+        results[name] = row
+    if args.ablation == "sync":
+        extra["latency"] = _latencies(torch)
+        _progress(f"latencies: {extra['latency']}")
+    eng.close()
+    out = {"ablation": args.ablation, "steps": args.steps, "warmup": args.warmup, "n_gpus": 1,
+           "data": "synthetic", "results": results}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -276,6 +464,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": n, "copies": 10}), flush=True)
+        return
+    if args.ablation:
+        run_ablation(args)
         return
     if args.workload == "served_mix":
         run_served(args)

@@ -60,15 +60,26 @@ typedef enum { WG_QUERY_TC = 0, WG_QUERY_SG = 1, WG_QUERY_TRIANGLES = 2 } wg_que
 #define WG_SG_IRREFLEXIVE 0x1u /* SG: drop (x,x) from the final relation */
 #define WG_STAGE_TIMING 0x2u   /* time every kernel launch with HIP events (fills stage_ms) */
 #define WG_NO_SPECULATION 0x4u /* enqueue nothing behind a batch while the host checks it */
+#define WG_JOIN_HASH 0x8u      /* TC and triangles: join through a linear-probing hash table of
+                                  E (thread per tuple) instead of the binary-search join of
+                                  Section IV-A -- the baseline of the paper's comparison */
+#define WG_UNFUSED_DEDUP 0x10u /* ablation of Section IV-B's fusion: deduplicate the sorted
+                                  candidates in one compaction pass, then take the set
+                                  difference with Full in a second (same result) */
 
 /* wg_options.loop_mode */
 #define WG_LOOP_AUTO 0u     /* the default: batched device-resident loop */
 #define WG_LOOP_BATCHED 1u  /* K iterations per host check (Section V-B, batched recording) */
 #define WG_LOOP_HOST 2u     /* one host check per iteration (K = 1); reference mode */
+#define WG_LOOP_STAGE 3u    /* ablation of Section V-B: K = 1 plus a blocking host read of
+                               the candidate count after the join count and of the delta
+                               size after the compaction, as a loop that sizes each stage
+                               from the host would do (three host round trips per
+                               iteration; the kernels still size themselves on the device) */
 
 typedef struct {
   uint32_t struct_size;      /* sizeof(wg_options); older sizes are accepted */
-  uint32_t flags;            /* WG_SG_IRREFLEXIVE, WG_STAGE_TIMING */
+  uint32_t flags;            /* WG_SG_IRREFLEXIVE, WG_STAGE_TIMING, ... (above) */
   uint32_t batch_k;          /* iterations per host check; 0 = 30 with halving for TC,
                                 10 fixed for SG (Section V-B, adaptive batch sizing) */
   uint32_t loop_mode;        /* WG_LOOP_* */

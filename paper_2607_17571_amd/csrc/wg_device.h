@@ -60,6 +60,8 @@ struct Ctrl {
   uint32_t maxid;        // largest vertex id of the input
   uint32_t force_overflow_at;  // test hook: report a candidate overflow at this iteration
   uint32_t bad_input;          // batched input offsets are malformed
+  uint32_t pad;
+  uint64_t dedup_n;            // unfused variant: candidates left after the dedup pass
 };
 
 // A halted loop turns every later kernel of the batch into a no-op.

@@ -52,7 +52,7 @@ struct wg_engine {
   Grid grid{};
   Ctrl* d_ctrl = nullptr;
   Ctrl* h_up = nullptr;        // pinned upload staging
-  Readback* h_rb = nullptr;    // pinned readback, 2 slots
+  Readback* h_rb = nullptr;    // pinned readback, 2 slots + 1 for stage probes
   hipEvent_t ev_batch[2] = {nullptr, nullptr};
   uint64_t* d_jtot = nullptr;
   uint64_t* d_bcnt = nullptr;
@@ -60,7 +60,10 @@ struct wg_engine {
   uint32_t* d_rtot = nullptr;
   uint64_t* d_hits = nullptr;  // triangle probe: hits per emit block (grid.stream entries)
   uint64_t tri_count = 0;      // the latest triangle count
-  DevBuf cand[2], full[2], fullB[2], delta[2], E, U, R, Edst, rowa, rowb, off, rec;
+  DevBuf cand[2], full[2], fullB[2], delta[2], E, U, R, Edst, rowa, rowb, off, rec, htab;
+  uint64_t hash_slots = 0;  // hash-join variant: table slots of the current solve (0: off)
+  bool unfused = false;     // WG_UNFUSED_DEDUP: dedup and set difference as two passes
+  bool stage_sync = false;  // WG_LOOP_STAGE: host round trips inside each iteration
   size_t allocated = 0;
   size_t peak = 0;
   uint64_t budget = 0;
@@ -212,7 +215,8 @@ void release_relations(wg_engine* e) {
     free_buf(e, e->fullB[s]);
     free_buf(e, e->delta[s]);
   }
-  for (DevBuf* b : {&e->E, &e->U, &e->R, &e->Edst, &e->rowa, &e->rowb, &e->off, &e->rec}) free_buf(e, *b);
+  for (DevBuf* b : {&e->E, &e->U, &e->R, &e->Edst, &e->rowa, &e->rowb, &e->off, &e->rec, &e->htab})
+    free_buf(e, *b);
   e->cand_cap = e->full_cap = e->edge_cap = e->row_cap = e->rec_cap = 0;
 }
 
@@ -252,6 +256,7 @@ Bufs<K> make_bufs(wg_engine* e) {
   b.rcnt = e->d_rcnt;
   b.rtot = e->d_rtot;
   b.hits = e->d_hits;
+  b.htab = (uint64_t*)e->htab.p;
   b.rec = (IterRec*)e->rec.p;
   return b;
 }
@@ -300,13 +305,36 @@ void enqueue_sort(wg_engine* e, const Bufs<K>& b, const uint64_t* n_ptr) {
   }
 }
 
+// WG_LOOP_STAGE: a blocking 8-byte read of a size the stream has just produced.
+void stage_probe(wg_engine* e, const uint64_t* d_size) {
+  hip_check(e, hipMemcpyAsync(&e->h_rb[2].c.m_in, d_size, sizeof(uint64_t), hipMemcpyDeviceToHost, e->stream),
+            "stage probe");
+  sync_stream(e);
+}
+
 template <typename K>
 void enqueue_iteration(wg_engine* e, const Bufs<K>& b, int kind, int w, int passes, uint32_t j) {
-  launch_join_count<K>(e->stream, e->grid, kind, e->d_ctrl, b, w, j, stage(e, WG_STAGE_JOIN_COUNT));
-  launch_join_emit<K>(e->stream, e->grid, kind, e->d_ctrl, b, w, j, stage(e, WG_STAGE_JOIN_EMIT));
+  if (e->hash_slots) {
+    const Ev ec = stage(e, WG_STAGE_JOIN_COUNT);
+    launch_join_hash<K>(e->stream, e->grid, kind, e->d_ctrl, b, w, j, e->hash_slots, ec,
+                        stage(e, WG_STAGE_JOIN_EMIT));
+  } else {
+    launch_join_count<K>(e->stream, e->grid, kind, e->d_ctrl, b, w, j, stage(e, WG_STAGE_JOIN_COUNT));
+    launch_join_emit<K>(e->stream, e->grid, kind, e->d_ctrl, b, w, j, stage(e, WG_STAGE_JOIN_EMIT));
+  }
+  if (e->stage_sync) stage_probe(e, &b.rec[j].C);
   enqueue_sort<K>(e, b, &b.rec[j].C);
-  launch_compact<K>(e->stream, e->grid, kModeIter, e->d_ctrl, &b.rec[j].C, b.cand[passes & 1],
-                    b.cand[(passes & 1) ^ 1], b, w, j, 0, stage(e, WG_STAGE_DEDUP_DIFF));
+  const uint32_t p = (uint32_t)passes & 1u;
+  if (e->unfused) {
+    launch_compact<K>(e->stream, e->grid, kModeDedup, e->d_ctrl, &b.rec[j].C, b.cand[p], b.cand[p ^ 1u],
+                      b, w, j, p, stage(e, WG_STAGE_DEDUP_DIFF));
+    launch_compact<K>(e->stream, e->grid, kModeIter, e->d_ctrl, &e->d_ctrl->dedup_n, b.cand[p],
+                      b.cand[p ^ 1u], b, w, j, 0, stage(e, WG_STAGE_DEDUP_DIFF));
+  } else {
+    launch_compact<K>(e->stream, e->grid, kModeIter, e->d_ctrl, &b.rec[j].C, b.cand[p], b.cand[p ^ 1u],
+                      b, w, j, 0, stage(e, WG_STAGE_DEDUP_DIFF));
+  }
+  if (e->stage_sync) stage_probe(e, &b.rec[j].N);
   launch_merge<K>(e->stream, e->grid, e->d_ctrl, b, j, stage(e, WG_STAGE_MERGE));
 }
 
@@ -449,13 +477,34 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   launch_compact<K>(e->stream, e->grid, mode, e->d_ctrl, &e->d_ctrl->m_in, b.cand[passes & 1],
                     b.cand[(passes & 1) ^ 1], b, w, 0, 0, stage(e, WG_STAGE_DEDUP_DIFF));
   launch_edge_index<K>(e->stream, e->grid, e->d_ctrl, b, w, stage(e, WG_STAGE_PREPARE));
+  e->hash_slots = 0;
+  e->unfused = (o.flags & WG_UNFUSED_DEDUP) != 0;
+  e->stage_sync = false;
+  if (o.flags & WG_JOIN_HASH) {
+    // hash-join variant: a table of E with at least twice as many slots as edges
+    uint64_t slots = 1024;
+    while (slots < 2 * m) slots <<= 1;
+    if (slots > (1ull << 32)) fail(e, WG_ERR_CAPACITY, "hash table beyond 2^32 slots");
+    ensure(e, e->htab, slots * sizeof(uint64_t));
+    e->hash_slots = slots;
+    b = make_bufs<K>(e);
+    launch_hash_build<K>(e->stream, e->grid, e->d_ctrl, b, w, slots, stage(e, WG_STAGE_PREPARE));
+  }
 
   if (query == WG_QUERY_TRIANGLES) {
     // Section VI: one pass of the join of E with itself; the emit phase probes E for the
     // closing edge of each two-path and counts the hits per block
-    launch_join_count<K>(e->stream, e->grid, kJoinTri, e->d_ctrl, b, w, 1, stage(e, WG_STAGE_JOIN_COUNT));
-    launch_join_emit<K>(e->stream, e->grid, kJoinTri, e->d_ctrl, b, w, 1, stage(e, WG_STAGE_JOIN_EMIT));
-    std::vector<uint64_t> hits((size_t)e->grid.stream);
+    if (e->hash_slots) {
+      const Ev ec = stage(e, WG_STAGE_JOIN_COUNT);
+      launch_join_hash<K>(e->stream, e->grid, kJoinTri, e->d_ctrl, b, w, 1, e->hash_slots, ec,
+                          stage(e, WG_STAGE_JOIN_EMIT));
+    } else {
+      launch_join_count<K>(e->stream, e->grid, kJoinTri, e->d_ctrl, b, w, 1, stage(e, WG_STAGE_JOIN_COUNT));
+      launch_join_emit<K>(e->stream, e->grid, kJoinTri, e->d_ctrl, b, w, 1, stage(e, WG_STAGE_JOIN_EMIT));
+    }
+    // the sorted probe writes one total per emit block (grid.stream), the hash probe one
+    // per count block (grid.scan)
+    std::vector<uint64_t> hits((size_t)(e->hash_slots ? e->grid.scan : e->grid.stream));
     hip_check(e, hipMemcpyAsync(hits.data(), e->d_hits, hits.size() * sizeof(uint64_t),
                                 hipMemcpyDeviceToHost, e->stream), "readback");
     read_back(e, 0, 0, 1);
@@ -514,7 +563,9 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   const int kind = query == WG_QUERY_TC ? kJoinTC : kJoinSG;
   uint32_t K_batch = o.batch_k ? o.batch_k : (query == WG_QUERY_TC ? 30u : 10u);
   const bool adaptive = (o.batch_k == 0 && query == WG_QUERY_TC);
-  if (o.loop_mode == WG_LOOP_HOST) K_batch = 1;
+  if (o.loop_mode == WG_LOOP_HOST || o.loop_mode == WG_LOOP_STAGE) K_batch = 1;
+  const bool speculate = !(o.flags & WG_NO_SPECULATION) && o.loop_mode != WG_LOOP_STAGE;
+  e->stage_sync = o.loop_mode == WG_LOOP_STAGE;
   const bool hooked = o.force_overflow_at_iter != 0;
   uint32_t next_j = 1;
   uint32_t batch_first = 1;
@@ -535,7 +586,7 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
     // While the host waits on this batch, the device runs a short speculative batch
     // behind it (Section V-B overlaps the next batch with the host check); after the
     // fixpoint its launches are no-ops, so it is kept short.
-    if (!(o.flags & WG_NO_SPECULATION)) enqueue_iters(std::min(K_batch, kSpec));
+    if (speculate) enqueue_iters(std::min(K_batch, kSpec));
     r = wait_back(e, slot);
     if (r.c.overflow | r.c.done | r.c.limit_hit) sync_stream(e);
     if (e->cancel && e->cancel->load()) {
@@ -677,8 +728,12 @@ wg_status solve(wg_engine* e, int query, uint32_t num, const uint64_t* d_offsets
     e->err = "tile_items must be 0, 8, 12 or 16";
     return WG_ERR_INVALID_ARG;
   }
-  if (o.loop_mode > WG_LOOP_HOST ||
-      (o.flags & ~(WG_SG_IRREFLEXIVE | WG_STAGE_TIMING | WG_NO_SPECULATION))) {
+  if ((o.flags & WG_JOIN_HASH) && query == WG_QUERY_SG) {
+    e->err = "WG_JOIN_HASH applies to TC and triangle counting";
+    return WG_ERR_INVALID_ARG;
+  }
+  if (o.loop_mode > WG_LOOP_STAGE || (o.flags & ~(WG_SG_IRREFLEXIVE | WG_STAGE_TIMING | WG_NO_SPECULATION |
+                                                   WG_JOIN_HASH | WG_UNFUSED_DEDUP))) {
     e->err = "unknown loop_mode or flag";
     return WG_ERR_INVALID_ARG;
   }
@@ -858,7 +913,7 @@ wg_status wg_engine_create(int device, wg_engine** out) {
     }
     hip_check(e, hipMalloc((void**)&e->d_ctrl, sizeof(Ctrl)), "hipMalloc");
     hip_check(e, hipHostMalloc((void**)&e->h_up, sizeof(Ctrl)), "hipHostMalloc");
-    hip_check(e, hipHostMalloc((void**)&e->h_rb, 2 * sizeof(Readback)), "hipHostMalloc");
+    hip_check(e, hipHostMalloc((void**)&e->h_rb, 3 * sizeof(Readback)), "hipHostMalloc");
     hip_check(e, hipMalloc((void**)&e->d_jtot, sizeof(uint64_t) * kScanBlocksMax), "hipMalloc");
     hip_check(e, hipMalloc((void**)&e->d_bcnt, sizeof(uint64_t) * kScanBlocksMax), "hipMalloc");
     hip_check(e, hipMalloc((void**)&e->d_rcnt, sizeof(uint32_t) * kRadixMax * kRadixBlocksMax), "hipMalloc");
@@ -898,6 +953,7 @@ void wg_engine_destroy(wg_engine* e) {
   release(e->rowb);
   release(e->off);
   release(e->rec);
+  release(e->htab);
   if (e->d_ctrl) (void)hipFree(e->d_ctrl);
   if (e->d_jtot) (void)hipFree(e->d_jtot);
   if (e->d_bcnt) (void)hipFree(e->d_bcnt);

@@ -307,6 +307,158 @@ __global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int
 }
 
 // ---------------------------------------------------------------------------
+// Hash-join variant of the join (the baseline the paper's binary-search join is
+// compared against, Sections III-A and VII): E goes into an open-addressing multimap
+// keyed by the source row, built with 64-bit CAS and linear probing; a probe for row b
+// walks b's whole cluster.  The count and emit phases are thread-per-tuple, so a hub's
+// work is serial in its degree -- the skew the sorted-array join avoids.  A slot holds
+// (row << 32 | index of the edge in E); kHashEmpty never equals a stored slot because
+// edge indices stay below 2^32 - 16.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kHashEmpty = ~0ull;
+
+__device__ __forceinline__ uint32_t hash_slot(uint32_t row, uint32_t mask) {
+  uint32_t x = row * 0x9E3779B1u;
+  x ^= x >> 15;
+  x *= 0x85EBCA77u;
+  x ^= x >> 13;
+  return x & mask;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_u64(uint64_t* __restrict__ a, uint64_t n, uint64_t v) {
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kBlock)
+    a[i] = v;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_hash_build(Ctrl* ctrl, Bufs<K> b, int w, uint32_t mask) {
+  const uint64_t mu = ctrl->m_unique;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < mu; i += (uint64_t)gridDim.x * kBlock) {
+    const uint32_t row = head_row<K>(b.E[i], w);
+    const uint64_t entry = ((uint64_t)row << 32) | (uint64_t)i;
+    uint32_t slot = hash_slot(row, mask);
+    while (atomicCAS((unsigned long long*)&b.htab[slot], (unsigned long long)kHashEmpty,
+                     (unsigned long long)entry) != (unsigned long long)kHashEmpty)
+      slot = (slot + 1) & mask;
+  }
+}
+
+// Entries of `row` in the table (walks its cluster to the first empty slot).
+__device__ __forceinline__ uint32_t hash_count(const uint64_t* __restrict__ t, uint32_t mask, uint32_t row) {
+  uint32_t c = 0;
+  for (uint32_t slot = hash_slot(row, mask);; slot = (slot + 1) & mask) {
+    const uint64_t e = t[slot];
+    if (e == kHashEmpty) return c;
+    c += (uint32_t)(e >> 32) == row ? 1u : 0u;
+  }
+}
+
+template <typename K, int Q, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_join_count_hash(Ctrl* ctrl, Bufs<K> b, int w, uint32_t j,
+                                                            uint32_t mask) {
+  constexpr uint32_t T = kBlock * ITEMS;
+  __shared__ uint64_t s_wave[kWavesPerBlock];
+  if (halted(ctrl)) return;
+  const uint64_t n = b.rec[j - 1].N;
+  const K* __restrict__ delta = b.delta[(j - 1) & 1u];
+  uint64_t lo, hi;
+  block_range(n, T, lo, hi);
+  const int wid = threadIdx.x / kWave;
+  const int lane = lane_id();
+  uint64_t running = 0;
+  for (uint64_t tbase = lo; tbase < hi; tbase += T) {
+    const uint64_t wbase = tbase + (uint64_t)wid * (kWave * ITEMS);
+    uint64_t cnt[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint64_t i = wbase + (uint64_t)k * kWave + lane;
+      cnt[k] = i < hi ? hash_count(b.htab, mask, tc_join_row<K>(delta[i], w)) : 0u;
+    }
+    uint64_t ex[ITEMS];
+    uint64_t run = 0;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint64_t incl = wave_incl_scan<uint64_t>(cnt[k]);
+      ex[k] = run + incl - cnt[k];
+      run = sat_add(run, __shfl(incl, kWave - 1, kWave));
+    }
+    uint64_t tile_total;
+    const uint64_t g = block_excl_scan<uint64_t>(lane == 0 ? run : 0ull, s_wave, tile_total);
+    const uint64_t wave_base = sat_add(running, __shfl(g, 0, kWave));
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint64_t i = wbase + (uint64_t)k * kWave + lane;
+      if (i < hi) b.off[i] = (uint32_t)sat_add(wave_base, ex[k]);
+    }
+    running = sat_add(running, tile_total);
+  }
+  if (threadIdx.x == 0) b.jtot[blockIdx.x] = running;
+}
+
+// Thread per delta tuple: walk the cluster of its join row again and write every match
+// into the tuple's slab (TC), or (kJoinTri) walk the cluster of c for each match (a, c)
+// and count the closing edges (c, a).  Same static ranges as the count.
+template <typename K, int Q, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_join_emit_hash(Ctrl* ctrl, Bufs<K> b, int w, uint32_t j,
+                                                           uint32_t mask) {
+  constexpr uint32_t T = kBlock * ITEMS;
+  __shared__ uint64_t s_pre[kScanBlocksMax];
+  __shared__ uint64_t s_wave[kWavesPerBlock];
+  if (halted(ctrl)) return;
+  const uint64_t n = b.rec[j - 1].N;
+  const uint64_t C = block_prefix(b.jtot, gridDim.x, s_pre, s_wave);
+  const bool over = Q == kJoinTri ? C > 0xFFFFFFFFull : C > ctrl->cand_cap;
+  if (over) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      b.rec[j].C = C;
+      atomicOr(&ctrl->overflow, 1u);
+    }
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) b.rec[j].C = C;
+  const K* __restrict__ delta = b.delta[(j - 1) & 1u];
+  const uint64_t* __restrict__ t = b.htab;
+  const K mask_w = field_mask<K>(w);
+  uint64_t lo, hi;
+  block_range(n, T, lo, hi);
+  const uint64_t base = s_pre[blockIdx.x];
+  uint64_t hits = 0;
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+    const K dk = delta[i];
+    const uint32_t row = tc_join_row<K>(dk, w);
+    uint64_t at = base + b.off[i];
+    for (uint32_t slot = hash_slot(row, mask);; slot = (slot + 1) & mask) {
+      const uint64_t e = t[slot];
+      if (e == kHashEmpty) break;
+      if ((uint32_t)(e >> 32) != row) continue;
+      const K c = (K)b.Edst[(uint32_t)e];
+      if (Q == kJoinTri) {
+        // closing edge (c, a): walk the cluster of row (inst, c) for destination a
+        const K a = (dk >> w) & mask_w;
+        const K inst = (dk >> w) >> w;
+        const uint32_t rc = (uint32_t)((inst << w) | c);
+        for (uint32_t s2 = hash_slot(rc, mask);; s2 = (s2 + 1) & mask) {
+          const uint64_t e2 = t[s2];
+          if (e2 == kHashEmpty) break;
+          if ((uint32_t)(e2 >> 32) == rc && (K)b.Edst[(uint32_t)e2] == a) {
+            ++hits;
+            break;
+          }
+        }
+      } else {
+        b.cand[0][at++] = ((dk >> w) << w) | c;
+      }
+    }
+  }
+  if (Q == kJoinTri) {
+    __syncthreads();
+    uint64_t total;
+    (void)block_excl_scan<uint64_t>(hits, s_wave, total);
+    if (threadIdx.x == 0) b.hits[blockIdx.x] = total;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // LSD radix sort (Section V-C): RB bits per pass, dst field first, every pass stable.
 //
 // A pass is three launches: count (block b counts the digits of a static contiguous
@@ -814,6 +966,8 @@ __global__ __launch_bounds__(kBlock) void k_compact_gather(Ctrl* ctrl, int mode,
     out1 = b.full[0];
     out2 = b.delta[0];
     if (N > ctrl->full_cap || N > ctrl->cand_cap) ovf |= 2u;
+  } else if (mode & kModeDedup) {
+    out1 = b.cand[side];  // the input buffer: the local pass has read all of it
   } else {
     out1 = b.full[side ^ 1u];
   }
@@ -864,6 +1018,8 @@ __global__ __launch_bounds__(kBlock) void k_compact_gather(Ctrl* ctrl, int mode,
         ctrl->iter = 0;
         if (N == 0) ctrl->done = 1;
       }
+    } else if (mode & kModeDedup) {
+      ctrl->dedup_n = N;
     } else {
       ctrl->filtered = N;
     }
@@ -1141,6 +1297,28 @@ void launch_join_count(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const
 }
 
 template <typename K>
+void launch_hash_build(hipStream_t s, const Grid& g, Ctrl* ctrl, const Bufs<K>& b, int w, uint64_t slots,
+                       Ev ev) {
+  hipEvent_t none = nullptr;
+  WG_LAUNCH(k_fill_u64, stream_blocks(g, slots), ev.start, none, s, b.htab, slots, kHashEmpty);
+  WG_LAUNCH(k_hash_build<K>, g.stream, none, ev.stop, s, ctrl, b, w, (uint32_t)(slots - 1));
+}
+
+template <typename K>
+void launch_join_hash(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w,
+                      uint32_t j, uint64_t slots, Ev ev_count, Ev ev_emit) {
+  const uint32_t mask = (uint32_t)(slots - 1);
+  WG_LAUNCH((k_join_count_hash<K, kJoinTC, kJoinItems>), g.scan, ev_count.start, ev_count.stop, s, ctrl, b, w,
+            j, mask);
+  if (kind == kJoinTri)
+    WG_LAUNCH((k_join_emit_hash<K, kJoinTri, kJoinItems>), g.scan, ev_emit.start, ev_emit.stop, s, ctrl, b, w,
+              j, mask);
+  else
+    WG_LAUNCH((k_join_emit_hash<K, kJoinTC, kJoinItems>), g.scan, ev_emit.start, ev_emit.stop, s, ctrl, b, w,
+              j, mask);
+}
+
+template <typename K>
 void launch_join_emit(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w,
                       uint32_t j, Ev ev) {
   if (kind == kJoinTC)
@@ -1248,6 +1426,9 @@ void launch_resume(hipStream_t s, Ctrl* ctrl, uint64_t cand_cap, uint64_t full_c
   template void launch_compact<K>(hipStream_t, const Grid&, int, Ctrl*, const uint64_t*, const K*, \
                                   K*, const Bufs<K>&, int, uint32_t, uint32_t, Ev);                \
   template void launch_merge<K>(hipStream_t, const Grid&, Ctrl*, const Bufs<K>&, uint32_t, Ev);   \
+  template void launch_hash_build<K>(hipStream_t, const Grid&, Ctrl*, const Bufs<K>&, int, uint64_t, Ev); \
+  template void launch_join_hash<K>(hipStream_t, const Grid&, int, Ctrl*, const Bufs<K>&, int, uint32_t, \
+                                    uint64_t, Ev, Ev);                                             \
   template void launch_merge_pair<K>(hipStream_t, const Grid&, const K*, uint64_t, const K*,     \
                                      uint64_t, K*, Ev);                                            \
   template void launch_edge_index<K>(hipStream_t, const Grid&, Ctrl*, const Bufs<K>&, int, Ev);   \

@@ -19,6 +19,9 @@ enum CompactMode : int {
   kModeSeed = 2,    // sorted candidates -> Full[0] and delta[0] (dedup only), record 0
   kModeIter = 4,    // sorted candidates minus Full[(j-1)&1] -> delta[j&1], record j
   kModeFilter = 8,  // Full[side] without (x, x) -> Full[side^1], count -> filtered
+  // unfused variant: sorted candidates in cand[side] -> deduplicated in place, count ->
+  // dedup_n; a kModeIter pass over them then takes the set difference alone
+  kModeDedup = 16,
 };
 
 // Tile sizes (items per tile) of the static-range kernels.
@@ -77,6 +80,7 @@ struct Bufs {
   uint64_t* jtot;  // per join-count block: candidates of its range
   uint64_t* bcnt;  // per compaction block: survivors of its range
   uint64_t* hits;  // triangle probe: closing edges found per emit block
+  uint64_t* htab;  // hash-join variant: open-addressing table of E (power-of-two slots)
   uint32_t* rcnt;  // radix: per-block digit counts, then offsets (digits x blocks)
   uint32_t* rtot;  // radix: digit totals
   IterRec* rec;    // per-iteration sizes
@@ -108,6 +112,15 @@ void launch_join_count(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const
 template <typename K>
 void launch_join_emit(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w,
                       uint32_t j, Ev ev = Ev());
+
+// Hash-join variant (TC and triangle joins): build the table of E (`slots` a power of
+// two), then the count and emit phases of iteration j through it.
+template <typename K>
+void launch_hash_build(hipStream_t s, const Grid& g, Ctrl* ctrl, const Bufs<K>& b, int w, uint64_t slots,
+                       Ev ev = Ev());
+template <typename K>
+void launch_join_hash(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w,
+                      uint32_t j, uint64_t slots, Ev ev_count = Ev(), Ev ev_emit = Ev());
 
 // One LSD pass over *n_ptr keys: pass p reads cand[p & 1] and writes cand[(p + 1) & 1];
 // digit p covers bits [p * c.rb, (p + 1) * c.rb).  `scatter` false: the count and scan

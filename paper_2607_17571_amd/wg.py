@@ -29,6 +29,8 @@ WG_ERR_CANCELLED = 7
 WG_SG_IRREFLEXIVE = 0x1
 WG_STAGE_TIMING = 0x2
 WG_NO_SPECULATION = 0x4
+WG_JOIN_HASH = 0x8
+WG_UNFUSED_DEDUP = 0x10
 
 WG_QUERY_TC = 0
 WG_QUERY_SG = 1
@@ -37,6 +39,7 @@ WG_QUERY_TRIANGLES = 2
 WG_LOOP_AUTO = 0
 WG_LOOP_BATCHED = 1
 WG_LOOP_HOST = 2
+WG_LOOP_STAGE = 3
 
 STAGES = ["join_count", "join_emit", "radix_hist", "radix_pass", "dedup_diff", "merge", "prepare"]
 WG_NUM_STAGES = len(STAGES)

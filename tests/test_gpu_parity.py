@@ -157,12 +157,39 @@ def test_sg_irreflexive(engine):
     dict(batch_k=1), dict(batch_k=3), dict(batch_k=64), dict(loop_mode=wg.WG_LOOP_HOST),
     dict(radix_field_bits=32), dict(radix_field_bits=24), dict(flags=wg.WG_STAGE_TIMING),
     dict(flags=wg.WG_NO_SPECULATION), dict(flags=wg.WG_NO_SPECULATION, batch_k=2),
+    dict(loop_mode=wg.WG_LOOP_STAGE), dict(flags=wg.WG_UNFUSED_DEDUP),
+    dict(flags=wg.WG_UNFUSED_DEDUP, force_overflow_at_iter=2),
+    dict(flags=wg.WG_UNFUSED_DEDUP | wg.WG_JOIN_HASH, loop_mode=wg.WG_LOOP_STAGE),
 ])
 def test_result_independent_of_loop_policy(engine, opts):
     src, dst = inputs.rmat(11, 1800, *inputs.RMAT_ABCD, seed=9)
     ref = oracle.tc(src, dst)
     s, d, st = run(engine, "tc", src, dst, wg.make_options(**opts))
     assert_same(s, d, st, ref)
+
+
+def test_stage_readbacks_counted(engine):
+    """The per-stage policy makes three host round trips per iteration, the batched one few."""
+    src, dst = inputs.rmat(11, 1800, *inputs.RMAT_ABCD, seed=9)
+    _, _, st_stage = run(engine, "tc", src, dst, wg.make_options(loop_mode=wg.WG_LOOP_STAGE))
+    _, _, st_host = run(engine, "tc", src, dst, wg.make_options(loop_mode=wg.WG_LOOP_HOST,
+                                                                flags=wg.WG_NO_SPECULATION))
+    _, _, st_auto = run(engine, "tc", src, dst, None)
+    it = st_stage["iterations"]
+    assert st_stage["host_syncs"] >= 3 * it
+    assert st_host["host_syncs"] >= it and st_host["host_syncs"] < st_stage["host_syncs"]
+    assert st_auto["host_syncs"] < st_host["host_syncs"]
+
+
+@pytest.mark.parametrize("name", ["sg_er_500k", "tc_rmat_s15"])
+def test_unfused_variant_full_size(engine, name):
+    _check_golden(engine, name, wg.make_options(flags=wg.WG_UNFUSED_DEDUP))
+
+
+def test_unfused_variant_sg(engine):
+    src, dst = inputs.erdos_renyi(3000, 2800, seed=11)
+    s, d, st = run(engine, "sg", src, dst, wg.make_options(flags=wg.WG_UNFUSED_DEDUP))
+    assert_same(s, d, st, oracle.sg(src, dst))
 
 
 SORT_CFGS = [(rb, items) for rb in (8, 9, 10, 11) for items in (8, 16)]
@@ -188,6 +215,29 @@ def test_sort_configurations_wide_keys(engine, rb, items):
     assert st["key_bytes"] == 8 and st["sort_passes"] == -(-48 // rb)
     s, d, st = run(engine, "sg", src, dst, opts)
     assert_same(s, d, st, oracle.sg(src, dst))
+
+
+@pytest.mark.parametrize("make", [
+    lambda: inputs.rmat(11, 1800, *inputs.RMAT_ABCD, seed=9), lambda: inputs.chain(300),
+    lambda: inputs.cycle(40), lambda: inputs.out_star(500),
+    lambda: inputs.scatter_ids(*inputs.rmat(10, 900, *inputs.RMAT_ABCD, seed=4), 30, seed=5),
+])
+def test_hash_join_variant_tc(engine, make):
+    """The hash-join baseline gives the same fixpoint (emission order differs before the sort)."""
+    src, dst = make()
+    s, d, st = run(engine, "tc", src, dst, wg.make_options(flags=wg.WG_JOIN_HASH))
+    assert_same(s, d, st, oracle.tc(src, dst))
+
+
+def test_hash_join_variant_full_size(engine):
+    _check_golden(engine, "tc_rmat_s15", wg.make_options(flags=wg.WG_JOIN_HASH))
+
+
+def test_hash_join_rejected_for_sg(engine):
+    a, b = inputs.chain(6)
+    with pytest.raises(wg.WgError) as ei:
+        run(engine, "sg", a, b, wg.make_options(flags=wg.WG_JOIN_HASH))
+    assert ei.value.status == wg.WG_ERR_INVALID_ARG
 
 
 @pytest.mark.parametrize("at", [1, 3, 6])

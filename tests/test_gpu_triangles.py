@@ -68,3 +68,11 @@ def test_empty_and_repeat(engine):
     src, dst = inputs.cycle(3)
     assert gpu_triangles(engine, src, dst)[0] == 3
     assert gpu_triangles(engine, src, dst)[0] == 3
+
+
+@pytest.mark.parametrize("scale,m", [(10, 4000), (13, 40000)])
+def test_hash_join_variant(engine, scale, m):
+    src, dst = inputs.rmat(scale, m, *inputs.RMAT_ABCD, seed=scale)
+    count, st = gpu_triangles(engine, src, dst, wg.make_options(flags=wg.WG_JOIN_HASH))
+    ref, two = oracle.triangles(src, dst)
+    assert count == ref and st["join_candidates"] == two
