@@ -396,12 +396,16 @@ def run_ablation(args):
                 "per_iteration_readback": dict(loop_mode=wg.WG_LOOP_HOST, flags=ns),
                 "batch_10": dict(loop_mode=wg.WG_LOOP_BATCHED, batch_k=10, flags=ns),
                 "batch_30": dict(loop_mode=wg.WG_LOOP_BATCHED, batch_k=30, flags=ns),
-                "adaptive": dict(flags=ns),
-                "adaptive_speculative": {},
+                "paper_adaptive": dict(loop_mode=wg.WG_LOOP_BATCHED, flags=ns),
+                "paper_adaptive_speculative": dict(loop_mode=wg.WG_LOOP_BATCHED),
+                "default": {},
+                "default_graph_replay": dict(flags=wg.WG_ITER_GRAPH),
             }
             if w.query == "tc":
                 for k in (2, 5, 20, 40, 50):
                     variants[f"batch_{k}"] = dict(loop_mode=wg.WG_LOOP_BATCHED, batch_k=k, flags=ns)
+            for k in (1, 2, 4, 8, 16):
+                variants[f"batch_{k}_speculative"] = dict(loop_mode=wg.WG_LOOP_BATCHED, batch_k=k)
         else:
             variants = {
                 "default": {},

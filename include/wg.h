@@ -66,10 +66,21 @@ typedef enum { WG_QUERY_TC = 0, WG_QUERY_SG = 1, WG_QUERY_TRIANGLES = 2 } wg_que
 #define WG_UNFUSED_DEDUP 0x10u /* ablation of Section IV-B's fusion: deduplicate the sorted
                                   candidates in one compaction pass, then take the set
                                   difference with Full in a second (same result) */
+#define WG_SPARSE_INDEX 0x20u /* index the edge rows by bisection over the distinct rows even
+                                 where the row ids span a range small enough for the dense
+                                 index (one array entry per row id) the engine would use */
+#define WG_ITER_GRAPH 0x40u   /* record one iteration's launches once as a HIP graph and replay
+                                 it, instead of launching every kernel from the host (the
+                                 default; on MI355X both take the same time, since a loop
+                                 kernel's own latency, not its launch, bounds small iterations) */
 
 /* wg_options.loop_mode */
-#define WG_LOOP_AUTO 0u     /* the default: batched device-resident loop */
-#define WG_LOOP_BATCHED 1u  /* K iterations per host check (Section V-B, batched recording) */
+#define WG_LOOP_AUTO 0u     /* the default: device-resident loop checked by the host every 2
+                               iterations (batch_k overrides), with a speculative batch
+                               enqueued behind every check */
+#define WG_LOOP_BATCHED 1u  /* K iterations per host check (Section V-B, batched recording);
+                               batch_k = 0 takes the paper's policy: K = 30 halving for
+                               TC, 10 for SG */
 #define WG_LOOP_HOST 2u     /* one host check per iteration (K = 1); reference mode */
 #define WG_LOOP_STAGE 3u    /* ablation of Section V-B: K = 1 plus a blocking host read of
                                the candidate count after the join count and of the delta
@@ -80,8 +91,9 @@ typedef enum { WG_QUERY_TC = 0, WG_QUERY_SG = 1, WG_QUERY_TRIANGLES = 2 } wg_que
 typedef struct {
   uint32_t struct_size;      /* sizeof(wg_options); older sizes are accepted */
   uint32_t flags;            /* WG_SG_IRREFLEXIVE, WG_STAGE_TIMING, ... (above) */
-  uint32_t batch_k;          /* iterations per host check; 0 = 30 with halving for TC,
-                                10 fixed for SG (Section V-B, adaptive batch sizing) */
+  uint32_t batch_k;          /* iterations per host check; 0 = the loop mode's default
+                                (WG_LOOP_BATCHED: 30 with halving for TC, 10 for SG, as in
+                                Section V-B's adaptive batch sizing) */
   uint32_t loop_mode;        /* WG_LOOP_* */
   uint32_t radix_field_bits; /* 0 = from the largest id: 16, 24 or 32 (Section V-C);
                                 else 16, 24 or 32, which must cover the largest id */

@@ -60,9 +60,28 @@ struct Ctrl {
   uint32_t maxid;        // largest vertex id of the input
   uint32_t force_overflow_at;  // test hook: report a candidate overflow at this iteration
   uint32_t bad_input;          // batched input offsets are malformed
-  uint32_t pad;
+  uint32_t cur;                // iteration in flight (set by its first kernel)
   uint64_t dedup_n;            // unfused variant: candidates left after the dedup pass
+  uint64_t cand_n;             // join candidates of the iteration in flight
 };
+
+// Kernels of the loop take their iteration from the device, so that one iteration's
+// launches are the same for every iteration (and can be recorded once as a graph): the
+// join count, first kernel of an iteration, works on the one after the last completed
+// and publishes it; the later kernels read it.  An explicit j (the seed, the base rule,
+// the triangle join) is used as given.
+constexpr uint32_t kIterDevice = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t iter_begin(Ctrl* c, uint32_t j) {
+  if (j != kIterDevice) return j;
+  const uint32_t cur = c->iter + 1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) c->cur = cur;  // read only by later launches
+  return cur;
+}
+
+__device__ __forceinline__ uint32_t iter_cur(const Ctrl* c, uint32_t j) {
+  return j != kIterDevice ? j : c->cur;
+}
 
 // A halted loop turns every later kernel of the batch into a no-op.
 __device__ __forceinline__ bool halted(const Ctrl* c) {
@@ -132,6 +151,29 @@ __device__ __forceinline__ T wave_sum(T v) {
 
 // Exclusive scan over the block; `total` receives the block sum.  `s_wave` needs
 // kWavesPerBlock entries.  Contains two barriers.
+// Largest v of the threads before this one in the block (0 for thread 0).
+__device__ __forceinline__ uint32_t block_excl_max(uint32_t v, uint32_t* s_wave) {
+  const int lane = lane_id();
+  uint32_t incl = v;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint32_t t = __shfl_up(incl, d, kWave);
+    if (lane >= d) incl = incl > t ? incl : t;
+  }
+  uint32_t ex = __shfl_up(incl, 1, kWave);
+  if (lane == 0) ex = 0;
+  const int wid = threadIdx.x / kWave;
+  if (lane == kWave - 1) s_wave[wid] = incl;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kWavesPerBlock; ++i) {
+    const uint32_t x = s_wave[i];
+    if (i < wid && x > ex) ex = x;
+  }
+  __syncthreads();
+  return ex;
+}
+
 template <typename T>
 __device__ __forceinline__ T block_excl_scan(T v, T* s_wave, T& total) {
   T incl = wave_incl_scan(v);

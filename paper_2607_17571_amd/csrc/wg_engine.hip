@@ -38,7 +38,9 @@ struct Readback {
 
 constexpr uint64_t kMaxKeys = 0xFFFFFFF0ull;  // slab offsets are 32-bit
 constexpr uint32_t kMaxEvents = 1u << 16;
-constexpr uint32_t kSpec = 4;                 // speculative iterations behind each batch
+constexpr uint32_t kSpec = 4;                 // speculative iterations behind each batch (<= K)
+constexpr uint32_t kAutoK = 2;                // iterations per host check of the default loop
+constexpr uint64_t kDenseRowsMax = 1ull << 26;  // largest dense edge index (256 MB)
 
 double now_ms() {
   return std::chrono::duration<double, std::milli>(
@@ -62,6 +64,11 @@ struct wg_engine {
   uint64_t tri_count = 0;      // the latest triangle count
   DevBuf cand[2], full[2], fullB[2], delta[2], E, U, R, Edst, rowa, rowb, off, rec, htab;
   uint64_t hash_slots = 0;  // hash-join variant: table slots of the current solve (0: off)
+  uint64_t dense_rows = 0;  // rows of the dense edge index of the current solve (0: U + search)
+  hipStream_t capture_stream = nullptr;  // private stream the iteration graph is recorded on
+  hipGraphExec_t graph_exec = nullptr;   // the recorded iteration (see iteration_graph)
+  std::vector<uint8_t> graph_key;        // the kernel arguments it was recorded with
+  uint64_t graph_builds = 0;
   bool unfused = false;     // WG_UNFUSED_DEDUP: dedup and set difference as two passes
   bool stage_sync = false;  // WG_LOOP_STAGE: host round trips inside each iteration
   size_t allocated = 0;
@@ -238,6 +245,7 @@ void ensure_records(wg_engine* e, uint64_t need) {
 template <typename K>
 Bufs<K> make_bufs(wg_engine* e) {
   Bufs<K> b;
+  std::memset(&b, 0, sizeof(b));  // padding too: the bytes key the recorded iteration graph
   for (int s = 0; s < 2; ++s) {
     b.cand[s] = (K*)e->cand[s].p;
     b.full[s] = (K*)e->full[s].p;
@@ -258,6 +266,7 @@ Bufs<K> make_bufs(wg_engine* e) {
   b.hits = e->d_hits;
   b.htab = (uint64_t*)e->htab.p;
   b.rec = (IterRec*)e->rec.p;
+  b.dense = (uint32_t)e->dense_rows;
   return b;
 }
 
@@ -312,30 +321,89 @@ void stage_probe(wg_engine* e, const uint64_t* d_size) {
   sync_stream(e);
 }
 
+// One semi-naive iteration.  The kernels take the iteration number from the device
+// (kIterDevice), so this launch sequence is the same for every iteration; `j` is the
+// host's count, used only by the per-stage probes.
 template <typename K>
 void enqueue_iteration(wg_engine* e, const Bufs<K>& b, int kind, int w, int passes, uint32_t j) {
+  const uint32_t jd = kIterDevice;
+  const uint64_t* C = &e->d_ctrl->cand_n;
   if (e->hash_slots) {
     const Ev ec = stage(e, WG_STAGE_JOIN_COUNT);
-    launch_join_hash<K>(e->stream, e->grid, kind, e->d_ctrl, b, w, j, e->hash_slots, ec,
+    launch_join_hash<K>(e->stream, e->grid, kind, e->d_ctrl, b, w, jd, e->hash_slots, ec,
                         stage(e, WG_STAGE_JOIN_EMIT));
   } else {
-    launch_join_count<K>(e->stream, e->grid, kind, e->d_ctrl, b, w, j, stage(e, WG_STAGE_JOIN_COUNT));
-    launch_join_emit<K>(e->stream, e->grid, kind, e->d_ctrl, b, w, j, stage(e, WG_STAGE_JOIN_EMIT));
+    launch_join_count<K>(e->stream, e->grid, kind, e->d_ctrl, b, w, jd, stage(e, WG_STAGE_JOIN_COUNT));
+    launch_join_emit<K>(e->stream, e->grid, kind, e->d_ctrl, b, w, jd, stage(e, WG_STAGE_JOIN_EMIT));
   }
   if (e->stage_sync) stage_probe(e, &b.rec[j].C);
-  enqueue_sort<K>(e, b, &b.rec[j].C);
+  enqueue_sort<K>(e, b, C);
   const uint32_t p = (uint32_t)passes & 1u;
   if (e->unfused) {
-    launch_compact<K>(e->stream, e->grid, kModeDedup, e->d_ctrl, &b.rec[j].C, b.cand[p], b.cand[p ^ 1u],
-                      b, w, j, p, stage(e, WG_STAGE_DEDUP_DIFF));
+    launch_compact<K>(e->stream, e->grid, kModeDedup, e->d_ctrl, C, b.cand[p], b.cand[p ^ 1u], b, w, jd, p,
+                      stage(e, WG_STAGE_DEDUP_DIFF));
     launch_compact<K>(e->stream, e->grid, kModeIter, e->d_ctrl, &e->d_ctrl->dedup_n, b.cand[p],
-                      b.cand[p ^ 1u], b, w, j, 0, stage(e, WG_STAGE_DEDUP_DIFF));
+                      b.cand[p ^ 1u], b, w, jd, 0, stage(e, WG_STAGE_DEDUP_DIFF));
   } else {
-    launch_compact<K>(e->stream, e->grid, kModeIter, e->d_ctrl, &b.rec[j].C, b.cand[p], b.cand[p ^ 1u],
-                      b, w, j, 0, stage(e, WG_STAGE_DEDUP_DIFF));
+    launch_compact<K>(e->stream, e->grid, kModeIter, e->d_ctrl, C, b.cand[p], b.cand[p ^ 1u], b, w, jd, 0,
+                      stage(e, WG_STAGE_DEDUP_DIFF));
   }
   if (e->stage_sync) stage_probe(e, &b.rec[j].N);
-  launch_merge<K>(e->stream, e->grid, e->d_ctrl, b, j, stage(e, WG_STAGE_MERGE));
+  launch_merge<K>(e->stream, e->grid, e->d_ctrl, b, jd, stage(e, WG_STAGE_MERGE));
+}
+
+// The launches of one iteration recorded once as a graph and replayed (Section V-B
+// records a batch of iterations into one submission).  Recorded on a private stream and
+// kept until a kernel argument changes (buffers regrown, another key type or layout).
+struct IterGraphKey {
+  uint8_t bufs[sizeof(Bufs<uint64_t>)];
+  int kind, w, passes, key_bytes;
+  SortCfg sort;
+  Grid grid;
+  uint64_t hash_slots;
+  int unfused;
+};
+
+template <typename K>
+hipGraphExec_t iteration_graph(wg_engine* e, const Bufs<K>& b, int kind, int w, int passes) {
+  IterGraphKey key;
+  std::memset(&key, 0, sizeof(key));
+  std::memcpy(key.bufs, &b, sizeof(b));
+  key.kind = kind;
+  key.w = w;
+  key.passes = passes;
+  key.key_bytes = (int)sizeof(K);
+  key.sort = e->sort;
+  key.grid = e->grid;
+  key.hash_slots = e->hash_slots;
+  key.unfused = e->unfused ? 1 : 0;
+  if (e->graph_exec && e->graph_key.size() == sizeof(key) &&
+      std::memcmp(e->graph_key.data(), &key, sizeof(key)) == 0)
+    return e->graph_exec;
+  if (e->graph_exec) {
+    hip_check(e, hipGraphExecDestroy(e->graph_exec), "hipGraphExecDestroy");
+    e->graph_exec = nullptr;
+  }
+  if (!e->capture_stream)
+    hip_check(e, hipStreamCreateWithFlags(&e->capture_stream, hipStreamNonBlocking), "hipStreamCreate");
+  hipStream_t user = e->stream;
+  e->stream = e->capture_stream;
+  hipGraph_t g = nullptr;
+  hipError_t r = hipStreamBeginCapture(e->capture_stream, hipStreamCaptureModeThreadLocal);
+  if (r == hipSuccess) {
+    enqueue_iteration<K>(e, b, kind, w, passes, 0);
+    r = hipStreamEndCapture(e->capture_stream, &g);
+  }
+  e->stream = user;
+  hip_check(e, r, "graph capture");
+  hipGraphExec_t x = nullptr;
+  r = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  hip_check(e, r, "hipGraphInstantiate");
+  e->graph_exec = x;
+  e->graph_key.assign((const uint8_t*)&key, (const uint8_t*)&key + sizeof(key));
+  ++e->graph_builds;
+  return x;
 }
 
 // Enqueue the readback of the control block and of records `first` and `last`.
@@ -453,6 +521,7 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   e->cand_cap = std::min(std::max<uint64_t>({e->cand_cap, 2 * m, 1u << 20}), kMaxKeys);
   e->full_cap = std::min(std::max<uint64_t>({e->full_cap, 2 * m, 1u << 20}), kMaxKeys);
   size_buffers(e, false, 0, nullptr);
+  if (e->dense_rows) ensure(e, e->R, (e->dense_rows + 1) * 4);
   ensure_records(e, 1024);
   hip_check(e, hipMemsetAsync(e->rec.p, 0, e->rec_cap * sizeof(IterRec), e->stream), "memset");
 
@@ -561,8 +630,14 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
 
   // ---- the semi-naive loop, K iterations per host check
   const int kind = query == WG_QUERY_TC ? kJoinTC : kJoinSG;
-  uint32_t K_batch = o.batch_k ? o.batch_k : (query == WG_QUERY_TC ? 30u : 10u);
-  const bool adaptive = (o.batch_k == 0 && query == WG_QUERY_TC);
+  // Section V-B sizes batches for a host round trip of milliseconds: K = 30 halving for
+  // TC, 10 for SG (WG_LOOP_BATCHED with batch_k = 0).  Here a round trip costs about
+  // 12 us and the speculative batch hides it, while every iteration enqueued past the
+  // fixpoint still costs its no-op launches (about 30 us), so the default checks every
+  // kAutoK iterations.
+  const bool paper_policy = o.loop_mode == WG_LOOP_BATCHED && o.batch_k == 0;
+  uint32_t K_batch = o.batch_k ? o.batch_k : (paper_policy ? (query == WG_QUERY_TC ? 30u : 10u) : kAutoK);
+  const bool adaptive = paper_policy && query == WG_QUERY_TC;
   if (o.loop_mode == WG_LOOP_HOST || o.loop_mode == WG_LOOP_STAGE) K_batch = 1;
   const bool speculate = !(o.flags & WG_NO_SPECULATION) && o.loop_mode != WG_LOOP_STAGE;
   e->stage_sync = o.loop_mode == WG_LOOP_STAGE;
@@ -571,9 +646,20 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   uint32_t batch_first = 1;
   Readback r{};
   int slot = 0;
+  // WG_ITER_GRAPH replays the recorded iteration; the event-timed and per-stage-probed
+  // loops always launch one by one
+  const bool graphs = !e->timing && !e->stage_sync && (o.flags & WG_ITER_GRAPH);
   auto enqueue_iters = [&](uint32_t k) {
     ensure_records(e, (uint64_t)next_j + k + 2);
     b = make_bufs<K>(e);
+    if (graphs && k > 0) {
+      hipGraphExec_t x = iteration_graph<K>(e, b, kind, w, passes);
+      for (uint32_t i = 0; i < k; ++i) {
+        hip_check(e, hipGraphLaunch(x, e->stream), "hipGraphLaunch");
+        ++next_j;
+      }
+      return;
+    }
     for (uint32_t i = 0; i < k; ++i) enqueue_iteration<K>(e, b, kind, w, passes, next_j++);
   };
   auto enqueue_batch = [&](uint32_t k, int sl) {
@@ -732,8 +818,9 @@ wg_status solve(wg_engine* e, int query, uint32_t num, const uint64_t* d_offsets
     e->err = "WG_JOIN_HASH applies to TC and triangle counting";
     return WG_ERR_INVALID_ARG;
   }
-  if (o.loop_mode > WG_LOOP_STAGE || (o.flags & ~(WG_SG_IRREFLEXIVE | WG_STAGE_TIMING | WG_NO_SPECULATION |
-                                                   WG_JOIN_HASH | WG_UNFUSED_DEDUP))) {
+  if (o.loop_mode > WG_LOOP_STAGE ||
+      (o.flags & ~(WG_SG_IRREFLEXIVE | WG_STAGE_TIMING | WG_NO_SPECULATION | WG_JOIN_HASH | WG_UNFUSED_DEDUP |
+                   WG_SPARSE_INDEX | WG_ITER_GRAPH))) {
     e->err = "unknown loop_mode or flag";
     return WG_ERR_INVALID_ARG;
   }
@@ -789,6 +876,13 @@ wg_status solve(wg_engine* e, int query, uint32_t num, const uint64_t* d_offsets
         e->err = "batch too wide: instance bits plus the id field exceed 32 bits";
         return WG_ERR_INVALID_ARG;
       }
+      // Row ids are (instance << w) | src.  When they span a range not much larger than the
+      // graph, the edge index is a dense array over that range (two loads per lookup);
+      // otherwise a sorted array of the distinct rows searched by bisection.
+      const uint64_t space = (num > 1 ? ((uint64_t)(num - 1) << w) : 0) + e->h_rb[0].c.maxid + 1;
+      e->dense_rows = (!(o.flags & WG_SPARSE_INDEX) && space <= kDenseRowsMax && space <= 16 * m + (1u << 20))
+                          ? space
+                          : 0;
       wg_status r = (ib + 2 * w <= 32) ? run<uint32_t>(e, query, d_src, d_dst, m, o, w, ib, st)
                                        : run<uint64_t>(e, query, d_src, d_dst, m, o, w, ib, st);
       if (r != WG_OK) return r;
@@ -965,6 +1059,8 @@ void wg_engine_destroy(wg_engine* e) {
   for (int s = 0; s < 2; ++s)
     if (e->ev_batch[s]) (void)hipEventDestroy(e->ev_batch[s]);
   for (hipEvent_t ev : e->events) (void)hipEventDestroy(ev);
+  if (e->graph_exec) (void)hipGraphExecDestroy(e->graph_exec);
+  if (e->capture_stream) (void)hipStreamDestroy(e->capture_stream);
   delete e;
 }
 

@@ -80,7 +80,9 @@ __global__ __launch_bounds__(kBlock) void k_pack(const uint32_t* __restrict__ sr
 
 // ---------------------------------------------------------------------------
 // Join, count phase (Section IV-A).  Each delta tuple finds the range of its join key in
-// the edge index by binary search and counts the candidates it will emit.  Block b owns
+// the edge index and counts the candidates it will emit: by binary search over the
+// distinct rows U, or, when the row ids span a small enough range, by two loads from a
+// dense index whose entry v is the first edge of row v.  Block b owns
 // a static range of tuples and writes, per tuple, the offset of its slab relative to the
 // range and, per block, the range's total; the emit phase adds the totals of earlier
 // blocks, so every tuple owns one contiguous output slab and no atomics are needed.  The
@@ -97,8 +99,10 @@ __global__ __launch_bounds__(kBlock) void k_join_count(Ctrl* ctrl, Bufs<K> b, in
   constexpr uint32_t T = kBlock * ITEMS;
   __shared__ uint64_t s_wave[kWavesPerBlock];
   if (halted(ctrl)) return;
+  j = iter_begin(ctrl, j);
   const uint64_t n = (Q == kJoinSGBase) ? ctrl->nu : b.rec[j - 1].N;
   const uint64_t nu = ctrl->nu;
+  const bool dense = b.dense != 0;
   const K* __restrict__ delta = b.delta[(j - 1) & 1u];
   const uint32_t* __restrict__ U = b.U;
   const uint32_t* __restrict__ R = b.R;
@@ -127,22 +131,25 @@ __global__ __launch_bounds__(kBlock) void k_join_count(Ctrl* ctrl, Bufs<K> b, in
         vb[k] = tc_join_row<K>(key, w);
         va[k] = head_row<K>(key, w);
       }
-      uint64_t jb[ITEMS];
-      multi_lower_bound<uint32_t, ITEMS>(U, nu, vb, jb);
-      uint64_t ja[ITEMS];
-      if (Q == kJoinSG) multi_lower_bound<uint32_t, ITEMS>(U, nu, va, ja);
+      uint64_t jb[ITEMS], ja[ITEMS];
+      if (!dense) {
+        multi_lower_bound<uint32_t, ITEMS>(U, nu, vb, jb);
+        if (Q == kJoinSG) multi_lower_bound<uint32_t, ITEMS>(U, nu, va, ja);
+      }
 #pragma unroll
       for (int k = 0; k < ITEMS; ++k) {
         const uint64_t i = wbase + (uint64_t)k * kWave + lane;
         uint64_t c = 0;
         if (i < hi) {
-          const uint32_t rb = row_found(U, nu, jb[k], vb[k]) ? (uint32_t)jb[k] : kNoRow;
-          b.rowb[i] = rb;
+          // dense index: the row id is the vertex id itself (every id below b.dense)
+          const uint32_t rb = dense ? vb[k] : (row_found(U, nu, jb[k], vb[k]) ? (uint32_t)jb[k] : kNoRow);
+          if (!dense) b.rowb[i] = rb;
           if (Q == kJoinTC) {
             c = (rb == kNoRow) ? 0 : (uint64_t)(R[rb + 1] - R[rb]);
           } else {
-            const uint32_t ra = row_found(U, nu, ja[k], va[k]) ? (uint32_t)ja[k] : kNoRow;
-            b.rowa[i] = ra;
+            const uint32_t ra =
+                dense ? va[k] : (row_found(U, nu, ja[k], va[k]) ? (uint32_t)ja[k] : kNoRow);
+            if (!dense) b.rowa[i] = ra;
             c = (ra == kNoRow || rb == kNoRow)
                     ? 0
                     : (uint64_t)(R[ra + 1] - R[ra]) * (uint64_t)(R[rb + 1] - R[rb]);
@@ -176,19 +183,29 @@ __global__ __launch_bounds__(kBlock) void k_join_count(Ctrl* ctrl, Bufs<K> b, in
 // ---------------------------------------------------------------------------
 // Join, emit phase.  Every block first adds up the per-block totals of the count phase
 // (the candidate total C, and the slab base of every count block).  Output positions are
-// dealt out in tiles; each position finds the delta tuple that owns it by binary search
-// over the slab offsets (a load-balanced expansion, so a hub tuple with thousands of
-// matches is spread over many threads instead of serialising one).  Writes are coalesced.
+// dealt out in tiles of T; the tuples whose slabs meet a tile are found by two searches
+// over the slab offsets, and, when there are at most T of them, each is looked up once
+// into LDS (slab start, key bits it passes on, first edge of its join row).  Every
+// position then finds its tuple by a max-scan over the slab starts marked in the tile (a
+// load-balanced expansion: a hub tuple with thousands of matches is spread over many
+// threads instead of serialising one), and reads one edge.  Writes are coalesced.
 // ---------------------------------------------------------------------------
 template <typename K, int Q, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int w, uint32_t j,
                                                       int gc) {
   constexpr uint32_t T = kBlock * ITEMS;
+  constexpr bool kSG = Q == kJoinSG || Q == kJoinSGBase;
   __shared__ uint64_t s_pre[kScanBlocksMax];
   __shared__ uint64_t s_wave[kWavesPerBlock];
-  __shared__ uint32_t s_off[T];
+  __shared__ uint32_t s_own[T];             // per position of the tile: its tuple (from i0)
+  __shared__ uint32_t s_start[T];           // per staged tuple: first position
+  __shared__ uint32_t s_base[T];            // per staged tuple: first edge of the join row
+  __shared__ uint32_t s_aux[kSG ? T : 1];   // SG: first edge of the head row
+  __shared__ uint32_t s_len[kSG ? T : 1];   // SG: divisor of the pair index
+  __shared__ K s_head[T];                   // per staged tuple: key bits passed on
   __shared__ uint64_t s_i0, s_i1;
   if (halted(ctrl)) return;
+  j = iter_cur(ctrl, j);
   const uint64_t n = (Q == kJoinSGBase) ? ctrl->nu : b.rec[j - 1].N;
   const uint64_t C = block_prefix(b.jtot, gc, s_pre, s_wave);
   const uint32_t hook = ctrl->force_overflow_at;
@@ -202,15 +219,56 @@ __global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int
     }
     return;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) b.rec[j].C = C;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    b.rec[j].C = C;
+    ctrl->cand_n = C;
+  }
+  const bool dense = b.dense != 0;
   const K* __restrict__ delta = b.delta[(j - 1) & 1u];
   const uint32_t* __restrict__ off = b.off;
   const uint32_t* __restrict__ R = b.R;
   const uint32_t* __restrict__ Edst = b.Edst;
+  const K mask = field_mask<K>(w);
   K* __restrict__ cand = b.cand[0];
   const uint64_t Pc = range_len(n, kJoinTile, (uint32_t)gc);
   // first candidate of tuple i
   auto at = [&](uint64_t i) -> uint64_t { return s_pre[i / Pc] + off[i]; };
+  // join rows of tuple i: rb (the row its candidates come from), ra (SG: the head row)
+  auto row_b = [&](uint64_t i, K dk) -> uint32_t { return dense ? tc_join_row<K>(dk, w) : b.rowb[i]; };
+  auto row_a = [&](uint64_t i, K dk) -> uint32_t { return dense ? head_row<K>(dk, w) : b.rowa[i]; };
+  // whether the closing edge (c, a) of a two-path is in E (kJoinTri)
+  auto closes = [&](K dk, K c) -> bool {
+    const K a = (dk >> w) & mask;
+    const K inst = (dk >> w) >> w;
+    if (dense) {
+      const uint32_t rc = (uint32_t)((inst << w) | c);
+      uint32_t lo = R[rc];
+      uint32_t len = R[rc + 1] - lo;
+      while (len > 0) {
+        const uint32_t half = len >> 1;
+        if ((K)Edst[lo + half] < a) {
+          lo += half + 1;
+          len -= half + 1;
+        } else {
+          len = half;
+        }
+      }
+      return len == 0 && lo < R[rc + 1] && (K)Edst[lo] == a;
+    }
+    const K probe = (((inst << w) | c) << w) | a;
+    const uint64_t mu = ctrl->m_unique;
+    uint64_t lo = 0, len = mu;
+    while (len > 0) {
+      const uint64_t half = len >> 1;
+      if (b.E[lo + half] < probe) {
+        lo += half + 1;
+        len -= half + 1;
+      } else {
+        len = half;
+      }
+    }
+    return lo < mu && b.E[lo] == probe;
+  };
   const uint64_t ntiles = (C + T - 1) / T;
   const int wid = threadIdx.x / kWave;
   uint64_t hits = 0;  // kJoinTri: closing edges found by this thread
@@ -228,74 +286,124 @@ __global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int
     __syncthreads();
     const uint64_t i0 = s_i0;
     const uint64_t span = s_i1 - i0 + 1;
-    const bool in_lds = span <= T;
-    if (in_lds) {
-      for (uint32_t jj = threadIdx.x; jj < span; jj += kBlock) s_off[jj] = (uint32_t)at(i0 + jj);
-    }
-    __syncthreads();
-    uint32_t pos[ITEMS];
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      const uint64_t p = p0 + (uint64_t)k * kBlock + threadIdx.x;
-      pos[k] = (uint32_t)min(p, p1 - 1);
-    }
-    uint64_t li[ITEMS];
-    K probe[ITEMS];
-    bool live[ITEMS];
-    if (in_lds) {
-      multi_upper_bound<uint32_t, ITEMS>(s_off, span, pos, li);
-    } else {
-      multi_upper_bound_at<ITEMS>([&](uint64_t x) { return (uint32_t)at(i0 + x); }, span, pos, li);
-    }
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      const uint64_t p = p0 + (uint64_t)k * kBlock + threadIdx.x;
-      live[k] = p < p1;
-      probe[k] = K(0);
-      if (p < p1) {
-        const uint64_t i = i0 + li[k] - 1;
-        const uint32_t start = in_lds ? s_off[li[k] - 1] : (uint32_t)at(i);
-        const uint32_t r = (uint32_t)p - start;
-        K key;
-        if (Q == kJoinTC) {
-          const K dk = delta[i];
-          key = ((dk >> w) << w) | (K)Edst[R[b.rowb[i]] + r];
-        } else if (Q == kJoinTri) {
-          // two-path (a, c) of edges (a, b), (b, c); the closing edge is (c, a)
-          const K dk = delta[i];
-          const K mask = field_mask<K>(w);
-          const K a = (dk >> w) & mask;
-          const K inst = (dk >> w) >> w;
-          const K c = (K)Edst[R[b.rowb[i]] + r];
-          probe[k] = (((inst << w) | c) << w) | a;
-          key = K(0);
-        } else if (Q == kJoinSG) {
-          const K dk = delta[i];
-          const uint32_t ja = b.rowa[i], jb = b.rowb[i];
-          const uint32_t lb = R[jb + 1] - R[jb];
-          const uint32_t qa = r / lb;
-          const uint32_t rb = r - qa * lb;
-          const K inst = (dk >> w) >> w;
-          key = ((((inst << w) | (K)Edst[R[ja] + qa]) << w) | (K)Edst[R[jb] + rb]);
+    if (span <= T) {
+      // stage the tuples; the owners of i0 and i1 have candidates, and so do all the
+      // tuples whose slab starts are marked (zero-length slabs share the next start)
+      for (uint32_t x = threadIdx.x; x < T; x += kBlock) s_own[x] = 0;
+      for (uint32_t t = threadIdx.x; t < span; t += kBlock) {
+        const uint64_t i = i0 + t;
+        const uint32_t st = (uint32_t)at(i);
+        s_start[t] = st;
+        if (Q == kJoinSGBase) {
+          s_base[t] = R[i];
+          s_len[t] = R[i + 1] - R[i] - 1;
+          const K inst = dense ? (K)(i >> w) : (K)(b.U[i] >> w);
+          s_head[t] = (inst << w) << w;
         } else {
-          // base rule: ordered pairs (x, y) of distinct children of row i
-          const uint32_t len1 = R[i + 1] - R[i] - 1;
-          const uint32_t qa = r / len1;
-          uint32_t qb = r - qa * len1;
-          qb += (qb >= qa) ? 1u : 0u;
-          const K inst = (K)(b.U[i] >> w);
-          key = ((((inst << w) | (K)Edst[R[i] + qa]) << w) | (K)Edst[R[i] + qb]);
+          const K dk = delta[i];
+          const uint32_t rb = row_b(i, dk);
+          if (Q == kJoinTC) {
+            s_head[t] = (dk >> w) << w;
+            s_base[t] = rb == kNoRow ? 0u : R[rb];
+          } else if (Q == kJoinTri) {
+            s_head[t] = dk;
+            s_base[t] = rb == kNoRow ? 0u : R[rb];
+          } else {
+            const uint32_t ra = row_a(i, dk);
+            s_head[t] = ((dk >> w) >> w) << w << w;
+            const bool live = ra != kNoRow && rb != kNoRow;
+            s_aux[t] = live ? R[ra] : 0u;
+            s_base[t] = live ? R[rb] : 0u;
+            s_len[t] = live ? R[rb + 1] - R[rb] : 1u;
+          }
         }
-        if (Q != kJoinTri) cand[p] = key;
       }
-    }
-    if (Q == kJoinTri) {
-      uint64_t pos[ITEMS];
-      const uint64_t mu = ctrl->m_unique;
-      multi_lower_bound<K, ITEMS>(b.E, mu, probe, pos);
+      __syncthreads();
+      for (uint32_t t = 1 + threadIdx.x; t < span; t += kBlock) {
+        const uint32_t st = s_start[t];
+        if (t + 1 == span || s_start[t + 1] != st) s_own[st - (uint32_t)p0] = t;
+      }
+      __syncthreads();
+      // running max over the marks: position x belongs to the last tuple starting at or before it
+      uint32_t own[ITEMS];
+      uint32_t mx = 0;
 #pragma unroll
-      for (int k = 0; k < ITEMS; ++k)
-        if (live[k] && pos[k] < mu && b.E[pos[k]] == probe[k]) ++hits;
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t v = s_own[threadIdx.x * ITEMS + k];
+        mx = v > mx ? v : mx;
+        own[k] = mx;
+      }
+      const uint32_t before = block_excl_max(mx, (uint32_t*)s_wave);
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) s_own[threadIdx.x * ITEMS + k] = own[k] > before ? own[k] : before;
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint64_t p = p0 + (uint64_t)k * kBlock + threadIdx.x;
+        if (p < p1) {
+          const uint32_t x = (uint32_t)(p - p0);
+          const uint32_t t = s_own[x];
+          const uint32_t r = (uint32_t)p - s_start[t];
+          if (Q == kJoinTC) {
+            cand[p] = s_head[t] | (K)Edst[s_base[t] + r];
+          } else if (Q == kJoinTri) {
+            if (closes(s_head[t], (K)Edst[s_base[t] + r])) ++hits;
+          } else if (Q == kJoinSG) {
+            const uint32_t lb = s_len[t];
+            const uint32_t qa = r / lb;
+            const uint32_t rb = r - qa * lb;
+            cand[p] = s_head[t] | ((K)Edst[s_aux[t] + qa] << w) | (K)Edst[s_base[t] + rb];
+          } else {
+            // base rule: ordered pairs (x, y) of distinct children of the row
+            const uint32_t len1 = s_len[t];
+            const uint32_t qa = r / len1;
+            uint32_t qb = r - qa * len1;
+            qb += (qb >= qa) ? 1u : 0u;
+            cand[p] = s_head[t] | ((K)Edst[s_base[t] + qa] << w) | (K)Edst[s_base[t] + qb];
+          }
+        }
+      }
+    } else {
+      // more tuples than positions (runs of empty slabs): search each position's tuple
+      uint32_t pos[ITEMS];
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint64_t p = p0 + (uint64_t)k * kBlock + threadIdx.x;
+        pos[k] = (uint32_t)min(p, p1 - 1);
+      }
+      uint64_t li[ITEMS];
+      multi_upper_bound_at<ITEMS>([&](uint64_t x) { return (uint32_t)at(i0 + x); }, span, pos, li);
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint64_t p = p0 + (uint64_t)k * kBlock + threadIdx.x;
+        if (p < p1) {
+          const uint64_t i = i0 + li[k] - 1;
+          const uint32_t r = (uint32_t)p - (uint32_t)at(i);
+          if (Q == kJoinSGBase) {
+            const uint32_t len1 = R[i + 1] - R[i] - 1;
+            const uint32_t qa = r / len1;
+            uint32_t qb = r - qa * len1;
+            qb += (qb >= qa) ? 1u : 0u;
+            const K inst = dense ? (K)(i >> w) : (K)(b.U[i] >> w);
+            cand[p] = ((((inst << w) | (K)Edst[R[i] + qa]) << w) | (K)Edst[R[i] + qb]);
+          } else {
+            const K dk = delta[i];
+            const uint32_t rb = row_b(i, dk);
+            if (Q == kJoinTC) {
+              cand[p] = ((dk >> w) << w) | (K)Edst[R[rb] + r];
+            } else if (Q == kJoinTri) {
+              if (closes(dk, (K)Edst[R[rb] + r])) ++hits;
+            } else {
+              const uint32_t ra = row_a(i, dk);
+              const uint32_t lb = R[rb + 1] - R[rb];
+              const uint32_t qa = r / lb;
+              const uint32_t qb = r - qa * lb;
+              const K inst = (dk >> w) >> w;
+              cand[p] = ((((inst << w) | (K)Edst[R[ra] + qa]) << w) | (K)Edst[R[rb] + qb]);
+            }
+          }
+        }
+      }
     }
     __syncthreads();
   }
@@ -359,6 +467,7 @@ __global__ __launch_bounds__(kBlock) void k_join_count_hash(Ctrl* ctrl, Bufs<K> 
   constexpr uint32_t T = kBlock * ITEMS;
   __shared__ uint64_t s_wave[kWavesPerBlock];
   if (halted(ctrl)) return;
+  j = iter_begin(ctrl, j);
   const uint64_t n = b.rec[j - 1].N;
   const K* __restrict__ delta = b.delta[(j - 1) & 1u];
   uint64_t lo, hi;
@@ -405,6 +514,7 @@ __global__ __launch_bounds__(kBlock) void k_join_emit_hash(Ctrl* ctrl, Bufs<K> b
   __shared__ uint64_t s_pre[kScanBlocksMax];
   __shared__ uint64_t s_wave[kWavesPerBlock];
   if (halted(ctrl)) return;
+  j = iter_cur(ctrl, j);
   const uint64_t n = b.rec[j - 1].N;
   const uint64_t C = block_prefix(b.jtot, gridDim.x, s_pre, s_wave);
   const bool over = Q == kJoinTri ? C > 0xFFFFFFFFull : C > ctrl->cand_cap;
@@ -415,7 +525,10 @@ __global__ __launch_bounds__(kBlock) void k_join_emit_hash(Ctrl* ctrl, Bufs<K> b
     }
     return;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) b.rec[j].C = C;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    b.rec[j].C = C;
+    ctrl->cand_n = C;
+  }
   const K* __restrict__ delta = b.delta[(j - 1) & 1u];
   const uint64_t* __restrict__ t = b.htab;
   const K mask_w = field_mask<K>(w);
@@ -795,6 +908,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_local(Ctrl* ctrl, int mode, 
   __shared__ uint64_t s_lo[2], s_hi[2];
   const bool filt = (mode & kModeFilter) != 0;
   if (!filt && halted(ctrl)) return;
+  j = iter_cur(ctrl, j);
   const uint64_t n = *n_ptr;
   uint64_t lo, hi;
   block_range(n, T, lo, hi);
@@ -941,6 +1055,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_gather(Ctrl* ctrl, int mode,
   __shared__ uint64_t s_wave[kWavesPerBlock];
   const bool filt = (mode & kModeFilter) != 0;
   if (!filt && halted(ctrl)) return;
+  j = iter_cur(ctrl, j);
   const uint64_t n = *n_ptr;
   const uint64_t N = block_prefix(b.bcnt, gridDim.x, s_pre, s_wave);
   uint64_t lo, hi;
@@ -1109,6 +1224,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(Ctrl* ctrl, Bufs<K> b, uint32_
   __shared__ K s_out[T];
   __shared__ uint64_t s_i[2];
   if (halted(ctrl)) return;
+  j = iter_cur(ctrl, j);
   const IterRec rp = b.rec[j - 1];
   const IterRec rj = b.rec[j];
   const uint64_t fb = rp.F - rp.FA;
@@ -1148,6 +1264,33 @@ __global__ __launch_bounds__(kBlock) void k_merge_pair(const K* __restrict__ A, 
 // (inst, src) row are contiguous.  U lists the distinct rows, R their starts.  Two
 // launches: per-block row-head counts, then every block writes its heads.
 // ---------------------------------------------------------------------------
+// Dense edge index: Edst, and R[v] = first edge of row v for every row id v <= b.dense
+// (R[b.dense] = |E|), by a binary search of E per row id.
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_index_dense(Ctrl* ctrl, Bufs<K> b, int w) {
+  if (halted(ctrl)) return;
+  const uint64_t n = ctrl->m_unique;
+  const K* __restrict__ E = b.E;
+  const K mask = field_mask<K>(w);
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  const uint64_t first = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  for (uint64_t i = first; i < n; i += stride) b.Edst[i] = (uint32_t)(E[i] & mask);
+  for (uint64_t v = first; v <= b.dense; v += stride) {
+    uint64_t lo = 0, len = n;
+    while (len > 0) {
+      const uint64_t half = len >> 1;
+      if ((uint64_t)(E[lo + half] >> w) < v) {
+        lo += half + 1;
+        len -= half + 1;
+      } else {
+        len = half;
+      }
+    }
+    b.R[v] = (uint32_t)lo;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->nu = b.dense;
+}
+
 template <typename K, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_index_count(Ctrl* ctrl, Bufs<K> b, int w) {
   constexpr uint32_t T = kBlock * ITEMS;
@@ -1395,6 +1538,10 @@ void launch_merge_pair(hipStream_t s, const Grid& g, const K* A, uint64_t na, co
 
 template <typename K>
 void launch_edge_index(hipStream_t s, const Grid& g, Ctrl* ctrl, const Bufs<K>& b, int w, Ev ev) {
+  if (b.dense) {
+    WG_LAUNCH(k_index_dense<K>, g.stream, ev.start, ev.stop, s, ctrl, b, w);
+    return;
+  }
   hipEvent_t none = nullptr;
   WG_LAUNCH((k_index_count<K, kIndexItems>), g.scan, ev.start, none, s, ctrl, b, w);
   WG_LAUNCH((k_index_write<K, kIndexItems>), g.scan, none, ev.stop, s, ctrl, b, w);

@@ -84,6 +84,8 @@ struct Bufs {
   uint32_t* rcnt;  // radix: per-block digit counts, then offsets (digits x blocks)
   uint32_t* rtot;  // radix: digit totals
   IterRec* rec;    // per-iteration sizes
+  uint32_t dense;  // > 0: R is a dense index over the row ids [0, dense) (R[v] = first edge
+                   // of row v, R[dense] = |E|) and U is unused; 0: rows are U's entries
 };
 
 void launch_max_id(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint32_t* src,
@@ -147,6 +149,7 @@ template <typename K>
 void launch_merge_pair(hipStream_t s, const Grid& g, const K* A, uint64_t na, const K* B, uint64_t nb,
                        K* O, Ev ev = Ev());
 
+// Edge index of the sorted, deduplicated E: Edst, and the rows (dense index when b.dense).
 template <typename K>
 void launch_edge_index(hipStream_t s, const Grid& g, Ctrl* ctrl, const Bufs<K>& b, int w,
                        Ev ev = Ev());

@@ -158,6 +158,8 @@ def test_sg_irreflexive(engine):
     dict(radix_field_bits=32), dict(radix_field_bits=24), dict(flags=wg.WG_STAGE_TIMING),
     dict(flags=wg.WG_NO_SPECULATION), dict(flags=wg.WG_NO_SPECULATION, batch_k=2),
     dict(loop_mode=wg.WG_LOOP_STAGE), dict(flags=wg.WG_UNFUSED_DEDUP),
+    dict(loop_mode=wg.WG_LOOP_BATCHED), dict(loop_mode=wg.WG_LOOP_BATCHED, flags=wg.WG_NO_SPECULATION),
+    dict(flags=wg.WG_ITER_GRAPH), dict(flags=wg.WG_ITER_GRAPH | wg.WG_NO_SPECULATION, batch_k=5),
     dict(flags=wg.WG_UNFUSED_DEDUP, force_overflow_at_iter=2),
     dict(flags=wg.WG_UNFUSED_DEDUP | wg.WG_JOIN_HASH, loop_mode=wg.WG_LOOP_STAGE),
 ])
@@ -166,6 +168,22 @@ def test_result_independent_of_loop_policy(engine, opts):
     ref = oracle.tc(src, dst)
     s, d, st = run(engine, "tc", src, dst, wg.make_options(**opts))
     assert_same(s, d, st, ref)
+
+
+def test_graph_replays_match_eager_launches(engine):
+    """Iterations replayed from the recorded graph, with eager solves (and other buffer
+    layouts) in between, give the eager result every time."""
+    cases = [("tc", inputs.rmat(11, 1800, *inputs.RMAT_ABCD, seed=9)),
+             ("sg", inputs.erdos_renyi(2000, 1900, seed=2)),
+             ("tc", inputs.grid_dag(12))]
+    for _ in range(2):
+        for query, (src, dst) in cases:
+            ref = run(engine, query, src, dst, None)
+            for _ in range(3):
+                s, d, st = run(engine, query, src, dst, wg.make_options(flags=wg.WG_ITER_GRAPH))
+                np.testing.assert_array_equal(s, ref[0])
+                np.testing.assert_array_equal(d, ref[1])
+                assert st["delta_sizes"] == ref[2]["delta_sizes"]
 
 
 def test_stage_readbacks_counted(engine):
@@ -184,6 +202,24 @@ def test_stage_readbacks_counted(engine):
 @pytest.mark.parametrize("name", ["sg_er_500k", "tc_rmat_s15"])
 def test_unfused_variant_full_size(engine, name):
     _check_golden(engine, name, wg.make_options(flags=wg.WG_UNFUSED_DEDUP))
+
+
+@pytest.mark.parametrize("query,make", [
+    ("tc", lambda: inputs.rmat(11, 1800, *inputs.RMAT_ABCD, seed=9)),
+    ("tc", lambda: inputs.grid_dag(12)),
+    ("sg", lambda: inputs.erdos_renyi(2000, 1900, seed=2)),
+    ("sg", lambda: inputs.rmat(10, 900, *inputs.RMAT_ABCD, seed=3)),
+])
+def test_sparse_index_variant(engine, query, make):
+    """The bisection index over distinct rows, forced where the dense index would be used."""
+    src, dst = make()
+    ref = oracle.tc(src, dst) if query == "tc" else oracle.sg(src, dst)
+    s, d, st = run(engine, query, src, dst, wg.make_options(flags=wg.WG_SPARSE_INDEX))
+    assert_same(s, d, st, ref)
+
+
+def test_sparse_index_full_size(engine):
+    _check_golden(engine, "sg_er_500k", wg.make_options(flags=wg.WG_SPARSE_INDEX))
 
 
 def test_unfused_variant_sg(engine):

@@ -76,3 +76,11 @@ def test_hash_join_variant(engine, scale, m):
     count, st = gpu_triangles(engine, src, dst, wg.make_options(flags=wg.WG_JOIN_HASH))
     ref, two = oracle.triangles(src, dst)
     assert count == ref and st["join_candidates"] == two
+
+
+@pytest.mark.parametrize("scale,m", [(10, 4000), (12, 20000)])
+def test_sparse_index_variant(engine, scale, m):
+    src, dst = inputs.rmat(scale, m, *inputs.RMAT_ABCD, seed=scale + 1)
+    count, st = gpu_triangles(engine, src, dst, wg.make_options(flags=wg.WG_SPARSE_INDEX))
+    ref, two = oracle.triangles(src, dst)
+    assert count == ref and st["join_candidates"] == two
