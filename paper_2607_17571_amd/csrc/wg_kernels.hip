@@ -857,42 +857,85 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(Ctrl* ctrl, const uint
 // when it is the first of its run of equal keys (the key before the range is read from
 // memory) and, in iteration mode, is absent from Full.  For each tile the window of Full
 // that can hold its keys is found by two wave-parallel searches inside the block's own
-// Full range; small windows are staged in LDS and searched there.  Survivors are
+// Full range; a window of at most a tile is staged in LDS and searched there, a larger
+// one through every st-th key staged in LDS, then in place.  Survivors are
 // compacted, in input order, to the start of the block's range in a scratch buffer.
 //
 // compact_gather: every block adds up the survivor counts of the blocks before it and
 // copies its survivors to their final positions; the output stays sorted.  Block 0 then
 // records the iteration (|Delta^j|, |Full| after it, the fixpoint and limit flags).
 // ---------------------------------------------------------------------------
-// First index in [lo, hi) of sorted LDS array w whose key is >= v (32-bit indices).
-template <typename K>
-__device__ __forceinline__ uint32_t lds_lower_bound(const K* w, uint32_t lo, uint32_t hi, K v) {
-  uint32_t len = hi - lo;
-  while (len > 0) {
-    const uint32_t half = len >> 1;
-    if (w[lo + half] < v) {
-      lo += half + 1;
-      len -= half + 1;
-    } else {
-      len = half;
-    }
-  }
-  return lo;
-}
-
-// keep[k] = false for every item of this thread present in the sorted LDS window w[0, n).
-// The thread's items are ascending, so two searches bound the part of the window they
-// can hit, and each item is then searched in what remains of that part.
+// keep[k] = false for every item of this thread present in the sorted LDS window w[0, n)
+// (n >= 1).  The thread's items are ascending: two bisections (in lockstep) bound the
+// part of the window they can hit, then every item bisects that part independently, all
+// items in lockstep, so the LDS reads of one step overlap instead of forming a chain.
 template <typename K, int ITEMS>
 __device__ __forceinline__ void drop_present(const K* w, uint32_t n, const K (&cv)[ITEMS],
                                              bool (&keep)[ITEMS]) {
-  uint32_t lo = lds_lower_bound<K>(w, 0, n, cv[0]);
-  const uint32_t hi = lds_lower_bound<K>(w, lo, n, cv[ITEMS - 1]) + 1;
-  const uint32_t end = hi < n ? hi : n;
+  uint32_t lo = 0, hi = 0;
+  for (uint32_t len = n; len > 1;) {
+    const uint32_t half = len >> 1;
+    lo = (w[lo + half - 1] < cv[0]) ? lo + half : lo;
+    hi = (w[hi + half - 1] <= cv[ITEMS - 1]) ? hi + half : hi;
+    len -= half;
+  }
+  lo += (w[lo] < cv[0]) ? 1u : 0u;
+  hi += (w[hi] <= cv[ITEMS - 1]) ? 1u : 0u;
+  if (hi <= lo) return;
+  uint32_t p[ITEMS];
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) p[k] = lo;
+  for (uint32_t len = hi - lo; len > 1;) {
+    const uint32_t half = len >> 1;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) p[k] = (w[p[k] + half - 1] < cv[k]) ? p[k] + half : p[k];
+    len -= half;
+  }
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
-    lo = lds_lower_bound<K>(w, lo, end, cv[k]);
-    if (lo < end && w[lo] == cv[k]) keep[k] = false;
+    const uint32_t q = p[k] + ((w[p[k]] < cv[k]) ? 1u : 0u);
+    if (q < hi && w[q] == cv[k]) keep[k] = false;
+  }
+}
+
+// The same for a window g[0, gn) too large for LDS: `s` holds every st-th key of it
+// (s[i] = g[i * st], ns entries).  Each item finds its stretch of st keys among the
+// samples (LDS), then bisects that stretch in place; all items in lockstep.
+template <typename K, int ITEMS>
+__device__ __forceinline__ void drop_present_sampled(const K* s, uint32_t ns, const K* __restrict__ g,
+                                                     uint32_t gn, uint32_t st, const K (&cv)[ITEMS],
+                                                     bool (&keep)[ITEMS]) {
+  uint32_t u[ITEMS];
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) u[k] = 0;
+  for (uint32_t len = ns; len > 1;) {
+    const uint32_t half = len >> 1;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) u[k] = (s[u[k] + half - 1] <= cv[k]) ? u[k] + half : u[k];
+    len -= half;
+  }
+  uint32_t p[ITEMS], end[ITEMS];
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    u[k] += (s[u[k]] <= cv[k]) ? 1u : 0u;  // samples <= the item
+    p[k] = u[k] ? (u[k] - 1) * st : 0u;
+    end[k] = u[k] ? min(p[k] + st, gn) : 1u;
+  }
+  // reads past a stretch's end are clamped to its last key (as if +infinity: when that
+  // key is below the item the item is absent either way)
+  for (uint32_t len = st; len > 1;) {
+    const uint32_t half = len >> 1;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint32_t at = min(p[k] + half - 1, end[k] - 1);
+      p[k] = (g[at] < cv[k]) ? p[k] + half : p[k];
+    }
+    len -= half;
+  }
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    const uint32_t q = p[k] + ((g[min(p[k], end[k] - 1)] < cv[k]) ? 1u : 0u);
+    if (u[k] && q < end[k] && g[q] == cv[k]) keep[k] = false;
   }
 }
 
@@ -979,6 +1022,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_local(Ctrl* ctrl, int mode, 
     __syncthreads();
     uint64_t flo = 0, fspan = 0, glo = 0, gspan = 0;
     bool win = false, gwin = false;
+    uint32_t fst = 1, gst = 1;
     if (diff) {
       flo = s_lo[0];
       fspan = s_hi[0] > flo ? s_hi[0] - flo : 0;
@@ -986,12 +1030,13 @@ __global__ __launch_bounds__(kBlock) void k_compact_local(Ctrl* ctrl, int mode, 
       gspan = s_hi[1] > glo ? s_hi[1] - glo : 0;
       win = fspan <= T;
       gwin = gspan <= T;
-      if (win) {
-        for (uint32_t jj = threadIdx.x; jj < fspan; jj += kBlock) s_f[jj] = runA[flo + jj];
-      }
-      if (gwin) {
-        for (uint32_t jj = threadIdx.x; jj < gspan; jj += kBlock) s_f[T + jj] = runB[glo + jj];
-      }
+      // a window that fits is staged whole, a larger one as every st-th key
+      fst = win ? 1u : (uint32_t)((fspan + T - 1) / T);
+      gst = gwin ? 1u : (uint32_t)((gspan + T - 1) / T);
+      const uint32_t fns = (uint32_t)((fspan + fst - 1) / fst);
+      const uint32_t gns = (uint32_t)((gspan + gst - 1) / gst);
+      for (uint32_t jj = threadIdx.x; jj < fns; jj += kBlock) s_f[jj] = runA[flo + (uint64_t)jj * fst];
+      for (uint32_t jj = threadIdx.x; jj < gns; jj += kBlock) s_f[T + jj] = runB[glo + (uint64_t)jj * gst];
       __syncthreads();
     }
     const uint32_t j0 = threadIdx.x * ITEMS;
@@ -1006,25 +1051,19 @@ __global__ __launch_bounds__(kBlock) void k_compact_local(Ctrl* ctrl, int mode, 
       else keep[k] = jj < tn && ((tbase + jj == 0) || (cv[k] != s_c[jj]));
     }
     if (fspan > 0) {
-      uint64_t pos[ITEMS];
       if (win) {
         drop_present<K, ITEMS>(s_f, (uint32_t)fspan, cv, keep);
       } else {
-        multi_lower_bound<K, ITEMS>(runA + flo, fspan, cv, pos);
-#pragma unroll
-        for (int k = 0; k < ITEMS; ++k)
-          if (pos[k] < fspan && runA[flo + pos[k]] == cv[k]) keep[k] = false;
+        drop_present_sampled<K, ITEMS>(s_f, (uint32_t)((fspan + fst - 1) / fst), runA + flo, (uint32_t)fspan,
+                                       fst, cv, keep);
       }
     }
     if (gspan > 0) {
-      uint64_t pos[ITEMS];
       if (gwin) {
         drop_present<K, ITEMS>(s_f + T, (uint32_t)gspan, cv, keep);
       } else {
-        multi_lower_bound<K, ITEMS>(runB + glo, gspan, cv, pos);
-#pragma unroll
-        for (int k = 0; k < ITEMS; ++k)
-          if (pos[k] < gspan && runB[glo + pos[k]] == cv[k]) keep[k] = false;
+        drop_present_sampled<K, ITEMS>(s_f + T, (uint32_t)((gspan + gst - 1) / gst), runB + glo,
+                                       (uint32_t)gspan, gst, cv, keep);
       }
     }
     uint32_t cnt = 0;
