@@ -55,7 +55,13 @@ struct wg_engine {
   Ctrl* d_ctrl = nullptr;
   Ctrl* h_up = nullptr;        // pinned upload staging
   Readback* h_rb = nullptr;    // pinned readback, 2 slots + 1 for stage probes
+  IterRec* h_rec = nullptr;    // pinned mirror of the records, filled by the batch readbacks
+  uint64_t h_rec_cap = 0;
+  uint32_t rb_first[2] = {0, 0}, rb_last[2] = {0, 0};  // records each readback slot covers
   hipEvent_t ev_batch[2] = {nullptr, nullptr};
+  hipEvent_t ev_done = nullptr;  // after the last launch of the latest solve (which may still
+                                 // be draining its speculative batch)
+  bool done_pending = false;
   uint64_t* d_jtot = nullptr;
   uint64_t* d_bcnt = nullptr;
   uint32_t* d_rcnt = nullptr;
@@ -96,8 +102,10 @@ struct wg_engine {
   uint32_t n_events = 0;         // timed launch groups (two events each)
   hipStream_t stream = nullptr;
   // result of the latest solve
-  const void* res_keys = nullptr;
+  const void* res_keys = nullptr;   // the result: res_n keys, the union of two sorted runs
   uint64_t res_n = 0;
+  const void* res_keys2 = nullptr;  // second run: the last res_n2 of the res_n keys
+  uint64_t res_n2 = 0;
   int res_w = 16;
 };
 
@@ -109,6 +117,9 @@ struct wg_result {
   uint32_t key_bytes;
   const void* keys;
   uint32_t num_inst;  // instances (1 for a single solve)
+  // the keys are the union of two disjoint sorted runs: keys[0, n - n2) and keys2[0, n2)
+  const void* keys2 = nullptr;
+  uint64_t n2 = 0;
   // results detached from their engine (request server)
   void* owned = nullptr;
   uint64_t owned_bytes = 0;
@@ -240,6 +251,17 @@ void ensure_records(wg_engine* e, uint64_t need) {
   free_buf(e, e->rec);
   e->rec = nb;
   e->rec_cap = cap;
+  if (e->h_rec_cap < cap) {  // the stream is drained: no readback is writing the old mirror
+    IterRec* h = nullptr;
+    hip_check(e, hipHostMalloc((void**)&h, cap * sizeof(IterRec)), "hipHostMalloc");
+    std::memset(h, 0, cap * sizeof(IterRec));
+    if (e->h_rec) {
+      std::memcpy(h, e->h_rec, e->h_rec_cap * sizeof(IterRec));
+      (void)hipHostFree(e->h_rec);
+    }
+    e->h_rec = h;
+    e->h_rec_cap = cap;
+  }
 }
 
 template <typename K>
@@ -406,22 +428,26 @@ hipGraphExec_t iteration_graph(wg_engine* e, const Bufs<K>& b, int kind, int w, 
   return x;
 }
 
-// Enqueue the readback of the control block and of records `first` and `last`.
+// Enqueue the readback of the control block and of records first..last (into the host
+// mirror at the same indices).
 void read_back(wg_engine* e, int slot, uint32_t first, uint32_t last) {
   Readback* rb = &e->h_rb[slot];
   hip_check(e, hipMemcpyAsync(&rb->c, e->d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, e->stream), "readback");
   const IterRec* rec = (const IterRec*)e->rec.p;
-  hip_check(e, hipMemcpyAsync(&rb->first, rec + first, sizeof(IterRec), hipMemcpyDeviceToHost, e->stream),
-            "readback");
-  hip_check(e, hipMemcpyAsync(&rb->last, rec + last, sizeof(IterRec), hipMemcpyDeviceToHost, e->stream),
-            "readback");
+  hip_check(e, hipMemcpyAsync(e->h_rec + first, rec + first, (size_t)(last - first + 1) * sizeof(IterRec),
+                              hipMemcpyDeviceToHost, e->stream), "readback");
   hip_check(e, hipEventRecord(e->ev_batch[slot], e->stream), "hipEventRecord");
+  e->rb_first[slot] = first;
+  e->rb_last[slot] = last;
 }
 
 Readback wait_back(wg_engine* e, int slot) {
   hip_check(e, hipEventSynchronize(e->ev_batch[slot]), "hipEventSynchronize");
   ++e->syncs;
-  return e->h_rb[slot];
+  Readback r = e->h_rb[slot];
+  r.first = e->h_rec[e->rb_first[slot]];
+  r.last = e->h_rec[e->rb_last[slot]];
+  return r;
 }
 
 // Synchronous read of one record (used only with the stream drained).
@@ -474,9 +500,11 @@ void add_bytes(wg_stats* st, int k, double b) { st->stage_bytes[k] += (uint64_t)
 //   dedup/diff  (C + N) * kb            read candidates, write the new delta
 //   merge       2 * (|B| + N) * kb      read run B and the delta, write B'
 //               2 * (F + N) * kb         on a fold: A and B into A', the delta into B'
-//               + 2 * F * kb             once: the final union of A and B
+//               + 2 * F * kb             once, before the SG diagonal filter: the union of
+//                                        A and B (otherwise the result stays two runs,
+//                                        merged by wg_result_copy)
 void bytes_model(wg_stats* st, int query, uint32_t kb, int passes, uint64_t m,
-                 const std::vector<IterRec>& rec, uint64_t mu) {
+                 const std::vector<IterRec>& rec, uint64_t mu, bool final_union) {
   // prepare: max scan (8m), pack (8m read + kb*m write), edge index (read E, write U/R/Edst)
   add_bytes(st, WG_STAGE_PREPARE, 8.0 * m + (8.0 + kb) * m + (kb + 12.0) * mu);
   add_bytes(st, WG_STAGE_RADIX_HIST, 1.0 * kb * m * passes);
@@ -503,9 +531,8 @@ void bytes_model(wg_stats* st, int query, uint32_t kb, int passes, uint64_t m,
     if (rec[i].fold) add_bytes(st, WG_STAGE_MERGE, 2.0 * (FA + FB + n) * kb);
     else if (rec[i].N > 0) add_bytes(st, WG_STAGE_MERGE, 2.0 * (FB + n) * kb);
   }
-  // the final union of the two runs
   const IterRec& fin = rec.back();
-  if (fin.F > fin.FA) add_bytes(st, WG_STAGE_MERGE, 2.0 * (double)fin.F * kb);
+  if (final_union && fin.F > fin.FA) add_bytes(st, WG_STAGE_MERGE, 2.0 * (double)fin.F * kb);
 }
 
 template <typename K>
@@ -582,8 +609,8 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
     uint64_t total = 0;
     for (uint64_t h : hits) total += h;
     e->tri_count = total;
-    e->res_keys = nullptr;
-    e->res_n = 0;
+    e->res_keys = e->res_keys2 = nullptr;
+    e->res_n = e->res_n2 = 0;
     e->res_w = w;
     if (st) {
       st->iterations = 1;
@@ -674,7 +701,9 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
     // fixpoint its launches are no-ops, so it is kept short.
     if (speculate) enqueue_iters(std::min(K_batch, kSpec));
     r = wait_back(e, slot);
-    if (r.c.overflow | r.c.done | r.c.limit_hit) sync_stream(e);
+    // (at the fixpoint the speculative batch still drains behind the final launches;
+    // everything after this is stream-ordered and reads the host mirror of the records)
+    if (r.c.overflow | r.c.limit_hit) sync_stream(e);
     if (e->cancel && e->cancel->load()) {
       sync_stream(e);
       fail(e, WG_ERR_CANCELLED, "cancelled");
@@ -699,16 +728,23 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   // result: Full after the last iteration, the union of its runs A and B (one final
   // disjoint merge into the free A buffer unless B is empty)
   const uint32_t iters = r.c.iter;
-  const IterRec fin = read_record(e, iters);
+  const IterRec fin = e->h_rec[iters];  // covered by the last readback
   uint32_t side = fin.a;
   uint64_t F = fin.F;
   b = make_bufs<K>(e);
-  if (fin.F > fin.FA) {
+  const bool filter = query == WG_QUERY_SG && (o.flags & WG_SG_IRREFLEXIVE) && F > 0;
+  e->res_keys2 = nullptr;
+  e->res_n2 = 0;
+  if (fin.F > fin.FA && !filter) {
+    // the result stays two runs; reading it merges them (wg_result_copy)
+    e->res_keys2 = b.fullB[fin.b];
+    e->res_n2 = fin.F - fin.FA;
+  } else if (fin.F > fin.FA) {
     launch_merge_pair<K>(e->stream, e->grid, b.full[fin.a], fin.FA, b.fullB[fin.b], fin.F - fin.FA,
                          b.full[fin.a ^ 1u], stage(e, WG_STAGE_MERGE));
     side = fin.a ^ 1u;
   }
-  if (query == WG_QUERY_SG && (o.flags & WG_SG_IRREFLEXIVE) && F > 0) {
+  if (filter) {
     if (e->cand_cap < F) {
       e->cand_cap = F;
       for (int s = 0; s < 2; ++s) ensure(e, e->cand[s], e->cand_cap * e->key_bytes);
@@ -731,10 +767,8 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
     st->key_bytes = (uint32_t)sizeof(K);
     st->digit_bits = (uint32_t)e->sort.rb;
     st->sort_passes = (uint32_t)passes;
-    std::vector<IterRec> recs((size_t)iters + 1);
-    hip_check(e, hipMemcpyAsync(recs.data(), e->rec.p, recs.size() * sizeof(IterRec),
-                                hipMemcpyDeviceToHost, e->stream), "records");
-    sync_stream(e);
+    // every record up to the fixpoint came back with some batch readback
+    const std::vector<IterRec> recs(e->h_rec, e->h_rec + iters + 1);
     st->base_tuples = recs[0].N;
     uint64_t cand_total = 0;
     for (size_t i = 1; i < recs.size(); ++i) cand_total += recs[i].C;
@@ -742,7 +776,7 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
     if (st->delta_sizes)
       for (uint64_t i = 0; i < std::min<uint64_t>(st->delta_sizes_cap, recs.size()); ++i)
         st->delta_sizes[i] = recs[i].N;
-    bytes_model(st, query, sizeof(K), passes, m, recs, r.c.m_unique);
+    bytes_model(st, query, sizeof(K), passes, m, recs, r.c.m_unique, filter);
     collect_timing(e, st);
   }
   return WG_OK;
@@ -834,9 +868,15 @@ wg_status solve(wg_engine* e, int query, uint32_t num, const uint64_t* d_offsets
   try {
     hip_check(e, hipSetDevice(e->device), "hipSetDevice");
     e->stream = (hipStream_t)stream;
+    // the previous solve may have returned with launches still queued on its stream:
+    // this one's stream waits for them (a no-op on the same stream)
+    if (e->done_pending) {
+      hip_check(e, hipStreamWaitEvent(e->stream, e->ev_done, 0), "hipStreamWaitEvent");
+      e->done_pending = false;
+    }
     e->generation++;
-    e->res_keys = nullptr;
-    e->res_n = 0;
+    e->res_keys = e->res_keys2 = nullptr;
+    e->res_n = e->res_n2 = 0;
     e->syncs = 0;
     e->budget = o.mem_budget_bytes;
     // the budget bounds everything the engine holds: buffers kept from earlier solves
@@ -886,9 +926,13 @@ wg_status solve(wg_engine* e, int query, uint32_t num, const uint64_t* d_offsets
       wg_status r = (ib + 2 * w <= 32) ? run<uint32_t>(e, query, d_src, d_dst, m, o, w, ib, st)
                                        : run<uint64_t>(e, query, d_src, d_dst, m, o, w, ib, st);
       if (r != WG_OK) return r;
+      hip_check(e, hipEventRecord(e->ev_done, e->stream), "hipEventRecord");
+      e->done_pending = true;
     }
     wg_result* res = new wg_result{e, e->generation, e->res_n, e->res_w, e->key_bytes, e->res_keys,
                                    num ? num : 1u};
+    res->keys2 = e->res_keys2;
+    res->n2 = e->res_n2;
     *out = res;
     if (st) {
       st->host_syncs = e->syncs;
@@ -924,6 +968,21 @@ wg_status device_error(const wg_result* r, const char* what) {
 }
 
 int result_device(const wg_result* r) { return r->engine ? r->engine->device : r->device; }
+
+// Reads of an engine-backed result on stream s: they wait for the solve's launches (which
+// may still be queued on the solve's stream), and the engine's next solve, on any stream,
+// waits for them before reusing the buffers.
+hipError_t wait_engine(const wg_result* r, hipStream_t s) {
+  if (!r->engine || !r->engine->done_pending) return hipSuccess;
+  return hipStreamWaitEvent(s, r->engine->ev_done, 0);
+}
+
+hipError_t mark_engine_use(const wg_result* r, hipStream_t s) {
+  if (!r->engine) return hipSuccess;
+  const hipError_t err = hipEventRecord(r->engine->ev_done, s);
+  if (err == hipSuccess) r->engine->done_pending = true;
+  return err;
+}
 Grid result_grid(const wg_result* r) { return r->engine ? r->engine->grid : r->grid; }
 
 }  // namespace
@@ -948,8 +1007,8 @@ void engine_trim(wg_engine* e) {
   } catch (const Fail&) {
   }
   e->generation++;
-  e->res_keys = nullptr;
-  e->res_n = 0;
+  e->res_keys = e->res_keys2 = nullptr;
+  e->res_n = e->res_n2 = 0;
 }
 
 wg_status result_detach(const wg_result* r, hipStream_t s, std::function<void(uint64_t)> release,
@@ -966,8 +1025,13 @@ wg_status result_detach(const wg_result* r, hipStream_t s, std::function<void(ui
     delete c;
     return WG_ERR_OUT_OF_MEMORY;
   }
-  hipError_t err = hipSuccess;
-  if (r->n) err = hipMemcpyAsync(c->owned, r->keys, r->n * r->key_bytes, hipMemcpyDeviceToDevice, s);
+  // both runs, back to back
+  const uint64_t na = r->n - r->n2;
+  hipError_t err = wait_engine(r, s);
+  if (na) err = hipMemcpyAsync(c->owned, r->keys, na * r->key_bytes, hipMemcpyDeviceToDevice, s);
+  if (err == hipSuccess && r->n2)
+    err = hipMemcpyAsync((uint8_t*)c->owned + na * r->key_bytes, r->keys2, r->n2 * r->key_bytes,
+                         hipMemcpyDeviceToDevice, s);
   if (err == hipSuccess) err = hipStreamSynchronize(s);
   if (err != hipSuccess) {
     (void)hipGetLastError();
@@ -976,6 +1040,7 @@ wg_status result_detach(const wg_result* r, hipStream_t s, std::function<void(ui
     return WG_ERR_DEVICE;
   }
   c->keys = c->owned;
+  c->keys2 = r->n2 ? (const uint8_t*)c->owned + na * r->key_bytes : nullptr;
   c->release = std::move(release);
   if (bytes) *bytes = c->owned_bytes;
   *out = c;
@@ -1016,6 +1081,7 @@ wg_status wg_engine_create(int device, wg_engine** out) {
     hip_check(e, hipMemset(e->d_ctrl, 0, sizeof(Ctrl)), "hipMemset");
     for (int s = 0; s < 2; ++s)
       hip_check(e, hipEventCreateWithFlags(&e->ev_batch[s], hipEventDisableTiming), "hipEventCreate");
+    hip_check(e, hipEventCreateWithFlags(&e->ev_done, hipEventDisableTiming), "hipEventCreate");
     hip_check(e, hipDeviceSynchronize(), "hipDeviceSynchronize");
   } catch (const Fail&) {
     wg_engine_destroy(e);
@@ -1056,8 +1122,10 @@ void wg_engine_destroy(wg_engine* e) {
   if (e->d_hits) (void)hipFree(e->d_hits);
   if (e->h_up) (void)hipHostFree(e->h_up);
   if (e->h_rb) (void)hipHostFree(e->h_rb);
+  if (e->h_rec) (void)hipHostFree(e->h_rec);
   for (int s = 0; s < 2; ++s)
     if (e->ev_batch[s]) (void)hipEventDestroy(e->ev_batch[s]);
+  if (e->ev_done) (void)hipEventDestroy(e->ev_done);
   for (hipEvent_t ev : e->events) (void)hipEventDestroy(ev);
   if (e->graph_exec) (void)hipGraphExecDestroy(e->graph_exec);
   if (e->capture_stream) (void)hipStreamDestroy(e->capture_stream);
@@ -1249,11 +1317,15 @@ wg_status wg_result_offsets(const wg_result* r, uint64_t* offsets_out, uint64_t 
   uint64_t* dst = offsets_out;
   if (host && hipMalloc((void**)&dst, bytes) != hipSuccess) return device_error(r, "hipMalloc");
   const Grid g = result_grid(r);
+  if (wait_engine(r, s) != hipSuccess) return device_error(r, "hipStreamWaitEvent");
   if (r->key_bytes == 4)
-    launch_offsets<uint32_t>(s, g, (const uint32_t*)r->keys, r->n, 2 * r->w, r->num_inst, dst);
+    launch_offsets<uint32_t>(s, g, (const uint32_t*)r->keys, r->n - r->n2, (const uint32_t*)r->keys2, r->n2,
+                             2 * r->w, r->num_inst, dst);
   else
-    launch_offsets<uint64_t>(s, g, (const uint64_t*)r->keys, r->n, 2 * r->w, r->num_inst, dst);
+    launch_offsets<uint64_t>(s, g, (const uint64_t*)r->keys, r->n - r->n2, (const uint64_t*)r->keys2, r->n2,
+                             2 * r->w, r->num_inst, dst);
   hipError_t err = hipGetLastError();
+  if (err == hipSuccess) err = mark_engine_use(r, s);
   if (host) {
     if (err == hipSuccess) err = hipMemcpyAsync(offsets_out, dst, bytes, hipMemcpyDeviceToHost, s);
     if (err == hipSuccess) err = hipStreamSynchronize(s);
@@ -1285,11 +1357,15 @@ wg_status wg_result_copy(const wg_result* r, uint32_t* src_out, uint32_t* dst_ou
     ds = tmp;
     dd = tmp + r->n;
   }
+  if (wait_engine(r, s) != hipSuccess) return device_error(r, "hipStreamWaitEvent");
   if (r->key_bytes == 4)
-    launch_unpack<uint32_t>(s, g, (const uint32_t*)r->keys, r->n, r->w, ds, dd);
+    launch_unpack<uint32_t>(s, g, (const uint32_t*)r->keys, r->n - r->n2, (const uint32_t*)r->keys2, r->n2,
+                            r->w, ds, dd);
   else
-    launch_unpack<uint64_t>(s, g, (const uint64_t*)r->keys, r->n, r->w, ds, dd);
+    launch_unpack<uint64_t>(s, g, (const uint64_t*)r->keys, r->n - r->n2, (const uint64_t*)r->keys2, r->n2,
+                            r->w, ds, dd);
   hipError_t err = hipGetLastError();
+  if (err == hipSuccess) err = mark_engine_use(r, s);
   if (host) {
     if (err == hipSuccess) err = hipMemcpyAsync(src_out, tmp, r->n * 4, hipMemcpyDeviceToHost, s);
     if (err == hipSuccess) err = hipMemcpyAsync(dst_out, tmp + r->n, r->n * 4, hipMemcpyDeviceToHost, s);

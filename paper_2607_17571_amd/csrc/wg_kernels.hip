@@ -1197,11 +1197,12 @@ __device__ __forceinline__ uint64_t wave_merge_path(const K* A, uint64_t na, con
   return wave_partition(lo, hi, [&](uint64_t i) { return A[i] < B[diag - 1 - i]; });
 }
 
-// Tiles of merge(A, B) -> O, taken by blocks `bid` of `nblocks` in a grid-stride loop.
-template <typename K, int ITEMS>
-__device__ __forceinline__ void merge_tiles(const K* __restrict__ A, uint64_t na, const K* __restrict__ B,
-                                            uint64_t nb, K* __restrict__ O, K* s_in, K* s_out,
-                                            uint64_t* s_i, uint32_t bid, uint32_t nblocks) {
+// Tiles of merge(A, B), taken by blocks `bid` of `nblocks` in a grid-stride loop; output
+// position p gets key v through put(p, v) (a store into O, or the split unpack).
+template <typename K, int ITEMS, typename Put>
+__device__ __forceinline__ void merge_tiles_to(const K* __restrict__ A, uint64_t na, const K* __restrict__ B,
+                                               uint64_t nb, Put put, K* s_in, K* s_out, uint64_t* s_i,
+                                               uint32_t bid, uint32_t nblocks) {
   constexpr uint32_t T = kBlock * ITEMS;
   const uint64_t total = na + nb;
   const uint64_t ntiles = (total + T - 1) / T;
@@ -1221,9 +1222,9 @@ __device__ __forceinline__ void merge_tiles(const K* __restrict__ A, uint64_t na
     const uint64_t j0 = o0 - i0, j1 = o1 - i1;
     const uint32_t ca = (uint32_t)(i1 - i0), cb = (uint32_t)(j1 - j0);
     if (cb == 0) {
-      for (uint32_t t = threadIdx.x; t < ca; t += kBlock) O[o0 + t] = A[i0 + t];
+      for (uint32_t t = threadIdx.x; t < ca; t += kBlock) put(o0 + t, A[i0 + t]);
     } else if (ca == 0) {
-      for (uint32_t t = threadIdx.x; t < cb; t += kBlock) O[o0 + t] = B[j0 + t];
+      for (uint32_t t = threadIdx.x; t < cb; t += kBlock) put(o0 + t, B[j0 + t]);
     } else {
       const uint32_t cn = ca + cb;
       for (uint32_t t = threadIdx.x; t < cn; t += kBlock)
@@ -1247,10 +1248,18 @@ __device__ __forceinline__ void merge_tiles(const K* __restrict__ A, uint64_t na
         }
       }
       __syncthreads();
-      for (uint32_t t = threadIdx.x; t < cn; t += kBlock) O[o0 + t] = s_out[t];
+      for (uint32_t t = threadIdx.x; t < cn; t += kBlock) put(o0 + t, s_out[t]);
     }
     __syncthreads();
   }
+}
+
+template <typename K, int ITEMS>
+__device__ __forceinline__ void merge_tiles(const K* __restrict__ A, uint64_t na, const K* __restrict__ B,
+                                            uint64_t nb, K* __restrict__ O, K* s_in, K* s_out,
+                                            uint64_t* s_i, uint32_t bid, uint32_t nblocks) {
+  merge_tiles_to<K, ITEMS>(A, na, B, nb, [O](uint64_t p, K v) { O[p] = v; }, s_in, s_out, s_i, bid,
+                           nblocks);
 }
 
 // Iteration j: B' = merge(B, delta^j) into the other B buffer, or on a fold
@@ -1398,6 +1407,27 @@ __global__ __launch_bounds__(kBlock) void k_unpack(const K* __restrict__ keys, u
   }
 }
 
+// The result held as two disjoint sorted runs (Full's A and B): merge them while
+// splitting the keys into src and dst arrays.
+template <typename K, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_unpack_merge(const K* __restrict__ A, uint64_t na,
+                                                         const K* __restrict__ B, uint64_t nb, int w,
+                                                         uint32_t* __restrict__ src,
+                                                         uint32_t* __restrict__ dst) {
+  constexpr uint32_t T = kBlock * ITEMS;
+  __shared__ K s_in[T];
+  __shared__ K s_out[T];
+  __shared__ uint64_t s_i[2];
+  const K mask = field_mask<K>(w);
+  merge_tiles_to<K, ITEMS>(
+      A, na, B, nb,
+      [=](uint64_t p, K v) {
+        src[p] = (uint32_t)((v >> w) & mask);
+        dst[p] = (uint32_t)(v & mask);
+      },
+      s_in, s_out, s_i, blockIdx.x, gridDim.x);
+}
+
 // Per-instance result offsets: out[i] = first key of instance i, out[num] = n.
 template <typename K>
 __global__ __launch_bounds__(kBlock) void k_offsets(const K* __restrict__ keys, uint64_t n, int shift,
@@ -1405,6 +1435,18 @@ __global__ __launch_bounds__(kBlock) void k_offsets(const K* __restrict__ keys, 
   for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i <= num;
        i += (uint64_t)gridDim.x * kBlock)
     out[i] = (i == num) ? n : lower_bound<K>(keys, n, (K)i << shift);
+}
+
+// The same over two disjoint runs: a key's position in their union is the number of keys
+// below it in both.
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_offsets2(const K* __restrict__ A, uint64_t na,
+                                                     const K* __restrict__ B, uint64_t nb, int shift,
+                                                     uint32_t num, uint64_t* __restrict__ out) {
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i <= num;
+       i += (uint64_t)gridDim.x * kBlock)
+    out[i] = (i == num) ? na + nb
+                        : lower_bound<K>(A, na, (K)i << shift) + lower_bound<K>(B, nb, (K)i << shift);
 }
 
 __global__ void k_resume(Ctrl* ctrl, uint64_t cand_cap, uint64_t full_cap, uint32_t clear_hook) {
@@ -1453,10 +1495,14 @@ void launch_pack_batch(hipStream_t s, const Grid& g, const uint32_t* src, const 
 }
 
 template <typename K>
-void launch_offsets(hipStream_t s, const Grid& g, const K* keys, uint64_t n, int shift, uint32_t num,
-                    uint64_t* out) {
-  hipLaunchKernelGGL(k_offsets<K>, dim3(stream_blocks(g, (uint64_t)num + 1)), dim3(kBlock), 0, s, keys,
-                     n, shift, num, out);
+void launch_offsets(hipStream_t s, const Grid& g, const K* keys, uint64_t n, const K* keys2, uint64_t n2,
+                    int shift, uint32_t num, uint64_t* out) {
+  if (n2 == 0)
+    hipLaunchKernelGGL(k_offsets<K>, dim3(stream_blocks(g, (uint64_t)num + 1)), dim3(kBlock), 0, s, keys, n,
+                       shift, num, out);
+  else
+    hipLaunchKernelGGL(k_offsets2<K>, dim3(stream_blocks(g, (uint64_t)num + 1)), dim3(kBlock), 0, s, keys,
+                       n, keys2, n2, shift, num, out);
 }
 
 template <typename K>
@@ -1587,9 +1633,14 @@ void launch_edge_index(hipStream_t s, const Grid& g, Ctrl* ctrl, const Bufs<K>& 
 }
 
 template <typename K>
-void launch_unpack(hipStream_t s, const Grid& g, const K* keys, uint64_t n, int w, uint32_t* src,
-                   uint32_t* dst) {
-  hipLaunchKernelGGL(k_unpack<K>, dim3(stream_blocks(g, n)), dim3(kBlock), 0, s, keys, n, w, src, dst);
+void launch_unpack(hipStream_t s, const Grid& g, const K* keys, uint64_t n, const K* keys2, uint64_t n2, int w,
+                   uint32_t* src, uint32_t* dst) {
+  if (n2 == 0) {
+    hipLaunchKernelGGL(k_unpack<K>, dim3(stream_blocks(g, n)), dim3(kBlock), 0, s, keys, n, w, src, dst);
+    return;
+  }
+  hipLaunchKernelGGL((k_unpack_merge<K, kMergeItems>), dim3(stream_blocks(g, (n + n2 + 7) / 8)), dim3(kBlock), 0,
+                     s, keys, n, keys2, n2, w, src, dst);
 }
 
 void launch_resume(hipStream_t s, Ctrl* ctrl, uint64_t cand_cap, uint64_t full_cap, uint32_t clear_hook) {
@@ -1601,8 +1652,8 @@ void launch_resume(hipStream_t s, Ctrl* ctrl, uint64_t cand_cap, uint64_t full_c
                                uint64_t, int, K*, Ev);                                            \
   template void launch_pack_batch<K>(hipStream_t, const Grid&, const uint32_t*, const uint32_t*, \
                                      uint64_t, int, const uint64_t*, uint32_t, K*, Ev);           \
-  template void launch_offsets<K>(hipStream_t, const Grid&, const K*, uint64_t, int, uint32_t,   \
-                                  uint64_t*);                                                      \
+  template void launch_offsets<K>(hipStream_t, const Grid&, const K*, uint64_t, const K*, uint64_t, int, \
+                                  uint32_t, uint64_t*);                                            \
   template void launch_join_count<K>(hipStream_t, const Grid&, int, Ctrl*, const Bufs<K>&, int,   \
                                      uint32_t, Ev);                                                \
   template void launch_join_emit<K>(hipStream_t, const Grid&, int, Ctrl*, const Bufs<K>&, int,    \
@@ -1618,8 +1669,8 @@ void launch_resume(hipStream_t s, Ctrl* ctrl, uint64_t cand_cap, uint64_t full_c
   template void launch_merge_pair<K>(hipStream_t, const Grid&, const K*, uint64_t, const K*,     \
                                      uint64_t, K*, Ev);                                            \
   template void launch_edge_index<K>(hipStream_t, const Grid&, Ctrl*, const Bufs<K>&, int, Ev);   \
-  template void launch_unpack<K>(hipStream_t, const Grid&, const K*, uint64_t, int, uint32_t*,    \
-                                 uint32_t*);
+  template void launch_unpack<K>(hipStream_t, const Grid&, const K*, uint64_t, const K*, uint64_t, int, \
+                                 uint32_t*, uint32_t*);
 
 WG_INSTANTIATE(uint32_t)
 WG_INSTANTIATE(uint64_t)

@@ -103,9 +103,10 @@ template <typename K>
 void launch_pack_batch(hipStream_t s, const Grid& g, const uint32_t* src, const uint32_t* dst,
                        uint64_t m, int w, const uint64_t* offsets, uint32_t num, K* keys,
                        Ev ev = Ev());
+// (of the union of the sorted runs keys[0, n) and keys2[0, n2); n2 may be 0)
 template <typename K>
-void launch_offsets(hipStream_t s, const Grid& g, const K* keys, uint64_t n, int shift, uint32_t num,
-                    uint64_t* out);
+void launch_offsets(hipStream_t s, const Grid& g, const K* keys, uint64_t n, const K* keys2, uint64_t n2,
+                    int shift, uint32_t num, uint64_t* out);
 
 // Join of iteration j (kind kJoinSGBase: the base rule, j = 0): count, then emit.
 template <typename K>
@@ -154,8 +155,10 @@ template <typename K>
 void launch_edge_index(hipStream_t s, const Grid& g, Ctrl* ctrl, const Bufs<K>& b, int w,
                        Ev ev = Ev());
 
+// Split keys into src / dst arrays; with n2 > 0 the keys are the union of two disjoint
+// sorted runs, merged on the way.
 template <typename K>
-void launch_unpack(hipStream_t s, const Grid& g, const K* keys, uint64_t n, int w,
+void launch_unpack(hipStream_t s, const Grid& g, const K* keys, uint64_t n, const K* keys2, uint64_t n2, int w,
                    uint32_t* src, uint32_t* dst);
 
 void launch_resume(hipStream_t s, Ctrl* ctrl, uint64_t cand_cap, uint64_t full_cap,

@@ -186,6 +186,27 @@ def test_graph_replays_match_eager_launches(engine):
                 assert st["delta_sizes"] == ref[2]["delta_sizes"]
 
 
+def test_back_to_back_solves_on_two_streams(engine):
+    """A solve returns with launches still queued; a solve on another stream, and reads of
+    the first result from another stream, are ordered after them."""
+    import torch
+    from tests.gpu_util import to_gpu
+
+    cases = [inputs.rmat(11, 1800, *inputs.RMAT_ABCD, seed=9), inputs.grid_dag(12),
+             inputs.rmat(12, 3600, *inputs.RMAT_ABCD, seed=5)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    dev = [(to_gpu(a), to_gpu(b)) for a, b in cases]
+    torch.cuda.synchronize()
+    outs = []
+    for i, (a, b) in enumerate(dev):
+        with torch.cuda.stream(streams[i % 2]):
+            s, d, st = engine.solve("tc", a, b, None)
+            outs.append((s, d, st))
+    torch.cuda.synchronize()
+    for (a, b), (s, d, st) in zip(cases, outs):
+        assert_same(s.cpu().numpy(), d.cpu().numpy(), st, oracle.tc(a, b))
+
+
 def test_stage_readbacks_counted(engine):
     """The per-stage policy makes three host round trips per iteration, the batched one few."""
     src, dst = inputs.rmat(11, 1800, *inputs.RMAT_ABCD, seed=9)
