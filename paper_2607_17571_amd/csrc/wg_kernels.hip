@@ -195,9 +195,10 @@ __global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int
                                                       int gc) {
   constexpr uint32_t T = kBlock * ITEMS;
   constexpr bool kSG = Q == kJoinSG || Q == kJoinSGBase;
+  static_assert(T <= 65536, "tuple indices within a tile are kept in 16 bits");
   __shared__ uint64_t s_pre[kScanBlocksMax];
   __shared__ uint64_t s_wave[kWavesPerBlock];
-  __shared__ uint32_t s_own[T];             // per position of the tile: its tuple (from i0)
+  __shared__ uint16_t s_own[T];             // per position of the tile: its tuple (from i0, < T)
   __shared__ uint32_t s_start[T];           // per staged tuple: first position
   __shared__ uint32_t s_base[T];            // per staged tuple: first edge of the join row
   __shared__ uint32_t s_aux[kSG ? T : 1];   // SG: first edge of the head row
@@ -321,7 +322,7 @@ __global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int
       __syncthreads();
       for (uint32_t t = 1 + threadIdx.x; t < span; t += kBlock) {
         const uint32_t st = s_start[t];
-        if (t + 1 == span || s_start[t + 1] != st) s_own[st - (uint32_t)p0] = t;
+        if (t + 1 == span || s_start[t + 1] != st) s_own[st - (uint32_t)p0] = (uint16_t)t;
       }
       __syncthreads();
       // running max over the marks: position x belongs to the last tuple starting at or before it
@@ -335,7 +336,8 @@ __global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int
       }
       const uint32_t before = block_excl_max(mx, (uint32_t*)s_wave);
 #pragma unroll
-      for (int k = 0; k < ITEMS; ++k) s_own[threadIdx.x * ITEMS + k] = own[k] > before ? own[k] : before;
+      for (int k = 0; k < ITEMS; ++k)
+        s_own[threadIdx.x * ITEMS + k] = (uint16_t)(own[k] > before ? own[k] : before);
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < ITEMS; ++k) {
