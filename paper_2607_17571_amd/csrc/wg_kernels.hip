@@ -1199,8 +1199,11 @@ __device__ __forceinline__ uint64_t wave_merge_path(const K* A, uint64_t na, con
   return wave_partition(lo, hi, [&](uint64_t i) { return A[i] < B[diag - 1 - i]; });
 }
 
-// Tiles of merge(A, B), taken by blocks `bid` of `nblocks` in a grid-stride loop; output
-// position p gets key v through put(p, v) (a store into O, or the split unpack).
+// Tiles of merge(A, B): block `bid` of `nblocks` takes a contiguous range of tiles; output
+// position p gets key v through put(p, v) (a store into O, or the split unpack).  Only the
+// first tile of a range searches the whole merge path; every later split is searched
+// within the one tile's worth of A past the previous split, which keeps the searches'
+// scattered reads to a small fraction of the data moved.
 template <typename K, int ITEMS, typename Put>
 __device__ __forceinline__ void merge_tiles_to(const K* __restrict__ A, uint64_t na, const K* __restrict__ B,
                                                uint64_t nb, Put put, K* s_in, K* s_out, uint64_t* s_i,
@@ -1208,19 +1211,29 @@ __device__ __forceinline__ void merge_tiles_to(const K* __restrict__ A, uint64_t
   constexpr uint32_t T = kBlock * ITEMS;
   const uint64_t total = na + nb;
   const uint64_t ntiles = (total + T - 1) / T;
+  const uint64_t tpb = (ntiles + nblocks - 1) / nblocks;
+  const uint64_t t_begin = (uint64_t)bid * tpb;
+  const uint64_t t_end = min(t_begin + tpb, ntiles);
+  if (t_begin >= t_end) return;
   const int wid = threadIdx.x / kWave;
-  for (uint64_t tile = bid; tile < ntiles; tile += nblocks) {
+  if (wid == 0) {
+    const uint64_t i = wave_merge_path(A, na, B, nb, t_begin * T);
+    if (lane_id() == 0) s_i[0] = i;
+  }
+  __syncthreads();
+  uint64_t i0 = s_i[0];
+  for (uint64_t tile = t_begin; tile < t_end; ++tile) {
     const uint64_t o0 = tile * T;
     const uint64_t o1 = min(o0 + T, total);
     if (wid == 0) {
-      const uint64_t i0 = wave_merge_path(A, na, B, nb, o0);
-      if (lane_id() == 0) s_i[0] = i0;
-    } else if (wid == 1) {
-      const uint64_t i1 = wave_merge_path(A, na, B, nb, o1);
+      // A keys among the first o1 outputs: at least i0, at most i0 + (o1 - o0)
+      const uint64_t lo = max(i0, o1 > nb ? o1 - nb : 0);
+      const uint64_t hi = min(i0 + (o1 - o0), na);
+      const uint64_t i1 = wave_partition(lo, hi, [&](uint64_t i) { return A[i] < B[o1 - 1 - i]; });
       if (lane_id() == 0) s_i[1] = i1;
     }
     __syncthreads();
-    const uint64_t i0 = s_i[0], i1 = s_i[1];
+    const uint64_t i1 = s_i[1];
     const uint64_t j0 = o0 - i0, j1 = o1 - i1;
     const uint32_t ca = (uint32_t)(i1 - i0), cb = (uint32_t)(j1 - j0);
     if (cb == 0) {
@@ -1253,6 +1266,7 @@ __device__ __forceinline__ void merge_tiles_to(const K* __restrict__ A, uint64_t
       for (uint32_t t = threadIdx.x; t < cn; t += kBlock) put(o0 + t, s_out[t]);
     }
     __syncthreads();
+    i0 = i1;
   }
 }
 
