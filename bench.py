@@ -513,11 +513,12 @@ def main():
     if args.dominant:
         if args.dominant not in wg.STAGES:
             raise SystemExit(f"--dominant must be one of {wg.STAGES}")
-        dom, probe_ms = args.dominant, None
+        dom, probe_ms, probe_gb = args.dominant, None, None
     else:
         probe = solve(wg.make_options(flags=wg.WG_STAGE_TIMING | base_flags, **sort_opts))
         dom = max(wg.STAGES, key=lambda k: probe["stage_ms"][k])
         probe_ms = {k: round(v, 3) for k, v in probe["stage_ms"].items()}
+        probe_gb = {k: round(v / 1e9, 4) for k, v in probe["stage_bytes"].items()}
     tuples = 0
     st = None
     ms_per_step = value = None
@@ -600,6 +601,7 @@ def main():
                    "radix_field_bits": st["field_bits"], "radix_digit_bits": st["digit_bits"],
                    "sort_passes": st["sort_passes"], "host_syncs_per_step": st["host_syncs"]},
         "stage_ms_probe": probe_ms,
+        "stage_algorithmic_gb": probe_gb,
         "roofline": roofline,
         "cpu_baseline": None,
     }

@@ -1000,24 +1000,21 @@ __global__ __launch_bounds__(kBlock) void k_compact_local(Ctrl* ctrl, int mode, 
     __syncthreads();
   }
   uint64_t running = 0;
+  // each tile's windows start where the previous tile's ended (tiles are consecutive keys):
+  // only the ends are searched, from the current starts
+  uint64_t a_at = alo, b_at = blo;
   for (uint64_t tbase = lo; tbase < hi; tbase += T) {
     const uint32_t tn = (uint32_t)min<uint64_t>(T, hi - tbase);
     for (uint32_t jj = threadIdx.x; jj < tn; jj += kBlock) s_c[jj + 1] = in[tbase + jj];
     if (threadIdx.x == 0 && tbase > 0) s_c[0] = in[tbase - 1];
     if (diff) {
-      // windows of A and B that can hold this tile's keys
-      const K first = in[tbase], last = in[tbase + tn - 1];
+      // ends of the windows of A and B that can hold this tile's keys
+      const K last = in[tbase + tn - 1];
       if (wid == 0) {
-        const uint64_t v = alo + wave_lower_bound(runA + alo, ahi - alo, first);
-        if (lane_id() == 0) s_lo[0] = v;
-      } else if (wid == 1) {
-        const uint64_t v = alo + wave_upper_bound(runA + alo, ahi - alo, last);
+        const uint64_t v = a_at + wave_upper_bound(runA + a_at, ahi - a_at, last);
         if (lane_id() == 0) s_hi[0] = v;
-      } else if (wid == 2) {
-        const uint64_t v = blo + wave_lower_bound(runB + blo, bhi - blo, first);
-        if (lane_id() == 0) s_lo[1] = v;
-      } else {
-        const uint64_t v = blo + wave_upper_bound(runB + blo, bhi - blo, last);
+      } else if (wid == 1) {
+        const uint64_t v = b_at + wave_upper_bound(runB + b_at, bhi - b_at, last);
         if (lane_id() == 0) s_hi[1] = v;
       }
     }
@@ -1026,10 +1023,18 @@ __global__ __launch_bounds__(kBlock) void k_compact_local(Ctrl* ctrl, int mode, 
     bool win = false, gwin = false;
     uint32_t fst = 1, gst = 1;
     if (diff) {
-      flo = s_lo[0];
-      fspan = s_hi[0] > flo ? s_hi[0] - flo : 0;
-      glo = s_lo[1];
-      gspan = s_hi[1] > glo ? s_hi[1] - glo : 0;
+      const uint64_t a_end = s_hi[0], b_end = s_hi[1];
+      flo = a_at;
+      fspan = a_end - a_at;
+      glo = b_at;
+      gspan = b_end - b_at;
+      // the next tile's first key may equal this tile's last, and so the last key of a
+      // window: then the next window starts one earlier
+      if (tbase + tn < hi) {
+        const K next = in[tbase + tn];
+        a_at = (a_end > a_at && runA[a_end - 1] == next) ? a_end - 1 : a_end;
+        b_at = (b_end > b_at && runB[b_end - 1] == next) ? b_end - 1 : b_end;
+      }
       win = fspan <= T;
       gwin = gspan <= T;
       // a window that fits is staged whole, a larger one as every st-th key
