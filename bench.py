@@ -63,6 +63,33 @@ WORKLOAD_TEXT = {
 }
 
 
+def kernel_source_digest() -> str:
+    """sha256 of the kernel source: a stored HBM-traffic figure applies only to the kernels
+    it was measured on."""
+    import hashlib
+
+    with open(os.path.join(ROOT, "paper_2607_17571_amd", "csrc", "wg_kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str):
+    """Calibrated HBM bytes per launch of `kernel` on `workload` from the rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs stored under profiles/ (null when none matches the current kernels)."""
+    prof = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(prof):
+        return None
+    digest = kernel_source_digest()
+    for name in sorted(os.listdir(prof)):
+        if not name.endswith("_traffic.json"):
+            continue
+        with open(os.path.join(prof, name)) as f:
+            rec = json.load(f)
+        if (rec.get("kernel") == kernel and rec.get("workload") == workload
+                and rec.get("kernel_source_sha256") == digest):
+            return rec
+    return None
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -558,9 +585,11 @@ def main():
         if value is None:
             ms_per_step, value = inst_ms, inst_tuples / inst_elapsed
         achieved = nbytes / (ms / 1e3) / 1e9 if ms > 0 else 0.0
+        tr = measured_traffic(STAGE_KERNELS[dom], args.workload)
         roofline = {"bound": "hbm", "kernel": STAGE_KERNELS[dom], "stage": dom,
                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": tr["traffic_bytes_per_launch"] if tr else None,
                     "avg_launch_us": round(1e3 * ms / max(1, launches), 2),
                     "bytes_per_launch": nbytes // max(1, launches),
                     "launches_per_step": launches // args.steps,
