@@ -49,7 +49,7 @@ WORKLOAD_TEXT = {
     "tc_rmat_s15": "TC, R-MAT scale 15 (n=32,768, m=29,491, a,b,c,d=0.57,0.19,0.19,0.05, seed 2); "
                    "stands in for R-MAT scale 22 whose ~3.9e11-tuple closure exceeds one GPU",
     "tc_rmat_s16": "TC, R-MAT scale 16 (n=65,536, m=58,982, a,b,c,d=0.57,0.19,0.19,0.05, seed 2)",
-    "tc_rmat_s15_ids24": "TC, R-MAT scale 15 with ids scattered into [0, 2^22) (24-bit radix field)",
+    "tc_rmat_s15_ids24": "TC, R-MAT scale 15 with ids scattered into [0, 2^22) (22-bit radix fields, 64-bit keys)",
     "tc_er_2000": "TC, directed ER n=2,000 m=1,900 seed 1",
     "sg_er_500k": "SG, directed ER n=500,000 m=450,000 seed 3",
     "tc_grid_100": "TC, 100x100 grid DAG (198 iterations)",
@@ -100,6 +100,7 @@ def parse():
     p.add_argument("--no-timing", action="store_true", help="time steps without per-kernel events")
     p.add_argument("--digit-bits", type=int, default=0, help="radix digit bits (0: engine's choice)")
     p.add_argument("--tile-items", type=int, default=0, help="sort tile keys per thread (0: engine's)")
+    p.add_argument("--field-bits", type=int, default=0, help="radix field width per id (0: engine's)")
     p.add_argument("--no-autotune", action="store_true", help="batched workloads: skip the autotuner")
     p.add_argument("--no-plain", action="store_true", help="batched workloads: skip the one-by-one path")
     p.add_argument("--no-spec", action="store_true", help="no speculative batch behind host checks")
@@ -434,10 +435,14 @@ def run_ablation(args):
             for k in (1, 2, 4, 8, 16):
                 variants[f"batch_{k}_speculative"] = dict(loop_mode=wg.WG_LOOP_BATCHED, batch_k=k)
         else:
+            # the paper's adaptive width rounds the largest id's bit length up to 16, 24 or 32
+            mx = int(max(w.src.max(), w.dst.max())) if w.src.size else 0
+            paper_w = 16 if mx < (1 << 16) else (24 if mx < (1 << 24) else 32)
             variants = {
                 "default": {},
                 "unfused_dedup_diff": dict(flags=wg.WG_UNFUSED_DEDUP),
-                "digits_8_adaptive_width": dict(radix_digit_bits=8),
+                "digits_8_exact_width": dict(radix_digit_bits=8),
+                "digits_8_width_16_24_32": dict(radix_digit_bits=8, radix_field_bits=paper_w),
                 "digits_8_fixed_32bit_fields": dict(radix_digit_bits=8, radix_field_bits=32),
             }
         row = {"query": w.query, "edges": int(w.src.size)}
@@ -530,7 +535,8 @@ def main():
             _, _, st = eng.solve(query, src, dst, opts)
             return st
 
-    sort_opts = dict(radix_digit_bits=args.digit_bits, tile_items=args.tile_items)
+    sort_opts = dict(radix_digit_bits=args.digit_bits, tile_items=args.tile_items,
+                     radix_field_bits=args.field_bits)
     base_flags = wg.WG_NO_SPECULATION if args.no_spec else 0
     for _ in range(args.warmup):
         solve(wg.make_options(flags=base_flags, **sort_opts))

@@ -95,8 +95,9 @@ typedef struct {
                                 (WG_LOOP_BATCHED: 30 with halving for TC, 10 for SG, as in
                                 Section V-B's adaptive batch sizing) */
   uint32_t loop_mode;        /* WG_LOOP_* */
-  uint32_t radix_field_bits; /* 0 = from the largest id: 16, 24 or 32 (Section V-C);
-                                else 16, 24 or 32, which must cover the largest id */
+  uint32_t radix_field_bits; /* 0 = the bit length of the largest id (Section V-C adapts
+                                the width; it rounds to 16, 24 or 32); else 1..32 bits,
+                                which must cover the largest id */
   uint32_t timing_stages;    /* with WG_STAGE_TIMING: bitmask of WG_STAGE_* kinds to time
                                 (0 = all); events cost launch overlap, so time few kinds */
   uint64_t max_iterations;   /* 0 = unlimited */
@@ -130,7 +131,7 @@ typedef struct {
   uint64_t join_candidates; /* candidates summed over iterations, with multiplicity */
   uint64_t host_syncs;      /* host waits on the device during the call */
   uint64_t resumes;         /* grow-and-resume cycles after a capacity overflow */
-  uint32_t field_bits;      /* radix field width used (16, 24, 32) */
+  uint32_t field_bits;      /* radix field width used (bits per id) */
   uint32_t key_bytes;       /* bytes per packed key (4 or 8) */
   double solve_ms;          /* host wall clock of the call */
   double stage_ms[WG_NUM_STAGES];        /* with WG_STAGE_TIMING: summed kernel time */

@@ -481,10 +481,15 @@ void grow_and_resume(wg_engine* e, const Ctrl& c, bool hooked) {
   launch_resume(e->stream, e->d_ctrl, e->cand_cap, e->full_cap, clear_hook ? 1u : 0u);
 }
 
+// Radix field width: the bit length of the largest id.  Section V-C rounds it up to 16, 24
+// or 32, a whole number of its 8-bit digits; the exact width drops bits that are zero in
+// every key, which saves a pass whenever the key width crosses a digit boundary (SG on
+// ER n = 500,000: 38-bit instead of 48-bit keys, 5 passes instead of 6) and keeps more
+// batched keys within 32 bits.
 int field_bits(uint32_t maxid) {
-  if (maxid < (1u << 16)) return 16;
-  if (maxid < (1u << 24)) return 24;
-  return 32;
+  int w = 1;
+  while (w < 32 && (maxid >> w) != 0) ++w;
+  return w;
 }
 
 void add_bytes(wg_stats* st, int k, double b) { st->stage_bytes[k] += (uint64_t)b; }
@@ -834,9 +839,8 @@ wg_status solve(wg_engine* e, int query, uint32_t num, const uint64_t* d_offsets
     e->err = "too many edges";
     return WG_ERR_INVALID_ARG;
   }
-  if (o.radix_field_bits != 0 && o.radix_field_bits != 16 && o.radix_field_bits != 24 &&
-      o.radix_field_bits != 32) {
-    e->err = "radix_field_bits must be 0, 16, 24 or 32";
+  if (o.radix_field_bits > 32) {
+    e->err = "radix_field_bits must be 0..32";
     return WG_ERR_INVALID_ARG;
   }
   if (o.radix_digit_bits != 0 &&
@@ -906,7 +910,8 @@ wg_status solve(wg_engine* e, int query, uint32_t num, const uint64_t* d_offsets
       }
       int w = field_bits(e->h_rb[0].c.maxid);
       if (o.radix_field_bits) {
-        if ((int)o.radix_field_bits < w) {
+        const uint32_t maxid = e->h_rb[0].c.maxid;
+        if (o.radix_field_bits < 32 && (maxid >> o.radix_field_bits) != 0) {
           e->err = "radix_field_bits does not cover the largest vertex id";
           return WG_ERR_INVALID_ARG;
         }

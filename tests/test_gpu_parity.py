@@ -67,15 +67,31 @@ def test_tc_rmat_small(engine, scale, m):
     assert_same(s, d, st, oracle.tc(src, dst))
 
 
-@pytest.mark.parametrize("bits", [22, 30, 32])
+@pytest.mark.parametrize("bits", [17, 22, 30, 32])
 def test_tc_wide_ids(engine, bits):
-    """24- and 32-bit radix fields (64-bit keys), ids up to 2^32 - 1."""
+    """Radix fields as wide as the largest id (64-bit keys), ids up to 2^32 - 1."""
     src, dst = inputs.rmat(10, 1000, *inputs.RMAT_ABCD, seed=7)
     src, dst = inputs.scatter_ids(src, dst, bits, seed=bits)
     s, d, st = run(engine, "tc", src, dst)
     ref = oracle.tc(src, dst)
     assert_same(s, d, st, ref)
-    assert st["field_bits"] == (24 if bits <= 24 else 32)
+    assert st["field_bits"] == int(max(src.max(), dst.max())).bit_length()
+
+
+@pytest.mark.parametrize("field", [5, 11, 15, 16, 24, 32])
+def test_tc_explicit_field_widths(engine, field):
+    """Every field width that covers the ids gives the same fixpoint (key widths 10..64)."""
+    src, dst = inputs.rmat(5, 120, *inputs.RMAT_ABCD, seed=3)
+    s, d, st = run(engine, "tc", src, dst, wg.make_options(radix_field_bits=field))
+    assert_same(s, d, st, oracle.tc(src, dst))
+    assert st["field_bits"] == field
+
+
+@pytest.mark.parametrize("field", [19, 24])
+def test_sg_explicit_field_widths(engine, field):
+    src, dst = inputs.erdos_renyi(400_000, 30_000, seed=13)
+    s, d, st = run(engine, "sg", src, dst, wg.make_options(radix_field_bits=field))
+    assert_same(s, d, st, oracle.sg(src, dst))
 
 
 def test_tc_extreme_ids_and_self_loops(engine):
@@ -259,17 +275,20 @@ def test_sort_configurations_tc(engine, rb, items):
     ref = oracle.tc(src, dst)
     s, d, st = run(engine, "tc", src, dst, wg.make_options(radix_digit_bits=rb, tile_items=items))
     assert_same(s, d, st, ref)
-    assert st["digit_bits"] == rb and st["sort_passes"] == -(-32 // rb)
+    key_bits = 2 * int(max(src.max(), dst.max())).bit_length()
+    assert st["digit_bits"] == rb and st["sort_passes"] == -(-key_bits // rb)
 
 
 @pytest.mark.parametrize("rb,items", [(8, 12), (9, 8), (10, 12), (11, 12), (11, 8)])
 def test_sort_configurations_wide_keys(engine, rb, items):
-    """64-bit keys (ids scattered over 2^22, w = 24): TC and SG, every digit width."""
+    """64-bit keys (ids scattered over 2^22, w = 22): TC and SG, every digit width."""
     src, dst = inputs.scatter_ids(*inputs.rmat(10, 900, *inputs.RMAT_ABCD, seed=4), 22, seed=5)
     opts = wg.make_options(radix_digit_bits=rb, tile_items=items)
     s, d, st = run(engine, "tc", src, dst, opts)
     assert_same(s, d, st, oracle.tc(src, dst))
-    assert st["key_bytes"] == 8 and st["sort_passes"] == -(-48 // rb)
+    key_bits = 2 * st["field_bits"]
+    assert st["field_bits"] == int(max(src.max(), dst.max())).bit_length()
+    assert st["key_bytes"] == 8 and st["sort_passes"] == -(-key_bits // rb)
     s, d, st = run(engine, "sg", src, dst, opts)
     assert_same(s, d, st, oracle.sg(src, dst))
 
@@ -348,14 +367,15 @@ def test_iteration_limit(engine):
 def test_invalid_arguments(engine):
     st, res = wg.wg_tc(engine.handle, 0, 0, 5, None, 0)
     assert st == wg.WG_ERR_INVALID_ARG and not res.value
-    opts = wg.make_options(radix_field_bits=20)
+    opts = wg.make_options(radix_field_bits=33)
     a, b = inputs.chain(5)
     with pytest.raises(wg.WgError) as ei:
         run(engine, "tc", a, b, opts)
     assert ei.value.status == wg.WG_ERR_INVALID_ARG
     src, dst = inputs.scatter_ids(*inputs.chain(5), 30, seed=1)
+    need = int(max(src.max(), dst.max())).bit_length()
     with pytest.raises(wg.WgError):
-        run(engine, "tc", src, dst, wg.make_options(radix_field_bits=16))
+        run(engine, "tc", src, dst, wg.make_options(radix_field_bits=need - 1))
     for bad in (dict(radix_digit_bits=7), dict(radix_digit_bits=12), dict(tile_items=5)):
         with pytest.raises(wg.WgError) as ei:
             run(engine, "tc", a, b, wg.make_options(**bad))
