@@ -1070,11 +1070,14 @@ wg_status wg_engine_create(int device, wg_engine** out) {
     const int cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     e->grid.stream = cu * 8;
     e->grid.scan = std::min(cu * 4, kScanBlocksMax);
+    // defaults: 8-bit digits; the large tile for 32-bit keys, the small one for 64-bit keys
+    // (measured best without tuning on R-MAT and SG workloads); wg_autotune refines them
     for (SortCfg& t : e->tune) {
       t.rb = 8;
       t.items = 16;
       t.blocks = std::min(cu * 4, kRadixBlocksMax);
     }
+    e->tune[1].items = 8;
     hip_check(e, hipMalloc((void**)&e->d_ctrl, sizeof(Ctrl)), "hipMalloc");
     hip_check(e, hipHostMalloc((void**)&e->h_up, sizeof(Ctrl)), "hipHostMalloc");
     hip_check(e, hipHostMalloc((void**)&e->h_rb, 3 * sizeof(Readback)), "hipHostMalloc");
