@@ -574,6 +574,50 @@ __global__ __launch_bounds__(kBlock) void k_join_emit_hash(Ctrl* ctrl, Bufs<K> b
 }
 
 // ---------------------------------------------------------------------------
+// A sort whose input fits one block's LDS (the tail of a fixpoint, small graphs) is done
+// by one block in a single launch -- a bitonic network over the keys padded to a power of
+// two -- instead of count / scan / scatter launches per pass; the passes then find
+// small_sorted set and exit.  Output in the buffer the LSD passes would have ended in.
+// The host launches it only where the input may fit (the flag is cleared by the
+// compaction that follows every sort, and on resume).
+// ---------------------------------------------------------------------------
+constexpr int kSmallSortThreads = 1024;
+
+template <typename K>
+__global__ __launch_bounds__(kSmallSortThreads) void k_small_sort(Ctrl* ctrl, const uint64_t* n_ptr,
+                                                                  const K* __restrict__ in, K* out) {
+  constexpr uint32_t CAP = kSmallSortBytes / sizeof(K);
+  __shared__ K s[CAP];
+  if (halted(ctrl)) return;
+  const uint64_t n = *n_ptr;
+  if (n > CAP) {
+    if (threadIdx.x == 0) ctrl->small_sorted = 0;
+    return;
+  }
+  uint32_t P = 1;
+  while (P < n) P <<= 1;
+  for (uint32_t i = threadIdx.x; i < P; i += kSmallSortThreads) s[i] = i < n ? in[i] : ~K(0);
+  __syncthreads();
+  for (uint32_t k = 2; k <= P; k <<= 1) {
+    for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+      for (uint32_t i = threadIdx.x; i < P; i += kSmallSortThreads) {
+        const uint32_t l = i ^ jj;
+        if (l > i) {
+          const K a = s[i], c = s[l];
+          if ((a > c) == ((i & k) == 0)) {
+            s[i] = c;
+            s[l] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (uint32_t i = threadIdx.x; i < n; i += kSmallSortThreads) out[i] = s[i];
+  if (threadIdx.x == 0) ctrl->small_sorted = 1;
+}
+
+// ---------------------------------------------------------------------------
 // LSD radix sort (Section V-C): RB bits per pass, dst field first, every pass stable.
 //
 // A pass is three launches: count (block b counts the digits of a static contiguous
@@ -629,7 +673,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_count(Ctrl* ctrl, const uint64
   constexpr int COPIES = RB <= 8 ? 8 : (RB == 9 ? 4 : (RB == 10 ? 2 : 1));
   constexpr int STRIDE = S::R + 1;
   __shared__ uint32_t s_cnt[COPIES * STRIDE];
-  if (halted(ctrl)) return;
+  if (halted(ctrl) || ctrl->small_sorted) return;
   const uint64_t n = *n_ptr;
   uint64_t lo, hi;
   block_range(n, T, lo, hi);
@@ -678,7 +722,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scan(Ctrl* ctrl, const uint64_
                                                        uint32_t* __restrict__ cnt,
                                                        uint32_t* __restrict__ tot, int G) {
   __shared__ uint32_t s_wave[kWavesPerBlock];
-  if (halted(ctrl)) return;
+  if (halted(ctrl) || ctrl->small_sorted) return;
   const int GA = (int)active_blocks(*n_ptr, T, (uint32_t)G);
   uint32_t* row = cnt + (uint64_t)blockIdx.x * G;
   uint32_t carry = 0;
@@ -725,7 +769,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(Ctrl* ctrl, const uint
   __shared__ uint16_t s_loc[S::R];                  // first tile position of each digit
   __shared__ uint32_t s_run[S::R];                  // next output position of each digit
   __shared__ uint32_t s_wave[kWavesPerBlock];
-  if (halted(ctrl)) return;
+  if (halted(ctrl) || ctrl->small_sorted) return;
   const uint64_t n = *n_ptr;
   uint64_t lo, hi;
   block_range(n, T, lo, hi);
@@ -1102,6 +1146,9 @@ __global__ __launch_bounds__(kBlock) void k_compact_gather(Ctrl* ctrl, int mode,
   const bool filt = (mode & kModeFilter) != 0;
   if (!filt && halted(ctrl)) return;
   j = iter_cur(ctrl, j);
+  // the sort before this compaction is over: a later sort that skips the one-block path
+  // must not find its flag (nothing else in this launch reads it)
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->small_sorted = 0;
   const uint64_t n = *n_ptr;
   const uint64_t N = block_prefix(b.bcnt, gridDim.x, s_pre, s_wave);
   uint64_t lo, hi;
@@ -1475,6 +1522,7 @@ __global__ void k_resume(Ctrl* ctrl, uint64_t cand_cap, uint64_t full_cap, uint3
     ctrl->cand_cap = cand_cap;
     ctrl->full_cap = full_cap;
     ctrl->overflow = 0;
+    ctrl->small_sorted = 0;
     if (clear_hook) ctrl->force_overflow_at = 0;
   }
 }
@@ -1599,6 +1647,18 @@ void sort_pass_impl(hipStream_t s, Ctrl* ctrl, const uint64_t* n_ptr, int G, con
 }
 
 template <typename K>
+void launch_small_sort(hipStream_t s, Ctrl* ctrl, const uint64_t* n_ptr, const Bufs<K>& b, int passes, Ev ev) {
+  hipEvent_t none = nullptr;
+  (void)none;
+  if (ev.start || ev.stop)
+    hipExtLaunchKernelGGL(k_small_sort<K>, dim3(1), dim3(kSmallSortThreads), 0, s, ev.start, ev.stop, 0, ctrl,
+                          n_ptr, (const K*)b.cand[0], b.cand[passes & 1]);
+  else
+    hipLaunchKernelGGL(k_small_sort<K>, dim3(1), dim3(kSmallSortThreads), 0, s, ctrl, n_ptr,
+                       (const K*)b.cand[0], b.cand[passes & 1]);
+}
+
+template <typename K>
 void launch_sort_pass(hipStream_t s, Ctrl* ctrl, const uint64_t* n_ptr, const SortCfg& c,
                       const Bufs<K>& b, int pass, bool scatter, Ev ev) {
   constexpr int SMALL = 8;
@@ -1679,6 +1739,7 @@ void launch_resume(hipStream_t s, Ctrl* ctrl, uint64_t cand_cap, uint64_t full_c
                                      uint32_t, Ev);                                                \
   template void launch_join_emit<K>(hipStream_t, const Grid&, int, Ctrl*, const Bufs<K>&, int,    \
                                     uint32_t, Ev);                                                 \
+  template void launch_small_sort<K>(hipStream_t, Ctrl*, const uint64_t*, const Bufs<K>&, int, Ev); \
   template void launch_sort_pass<K>(hipStream_t, Ctrl*, const uint64_t*, const SortCfg&,         \
                                     const Bufs<K>&, int, bool, Ev);                                \
   template void launch_compact<K>(hipStream_t, const Grid&, int, Ctrl*, const uint64_t*, const K*, \

@@ -29,6 +29,7 @@ constexpr int kJoinItems = 8;
 constexpr int kEmitItems = 8;
 constexpr int kDedupItems = 8;
 constexpr int kMergeItems = 8;
+constexpr uint32_t kSmallSortBytes = 32768;  // LDS of the one-block sort (8,192 / 4,096 keys)
 constexpr int kIndexItems = 8;
 constexpr uint32_t kJoinTile = kBlock * kJoinItems;
 constexpr uint32_t kDedupTile = kBlock * kDedupItems;
@@ -124,6 +125,12 @@ void launch_hash_build(hipStream_t s, const Grid& g, Ctrl* ctrl, const Bufs<K>& 
 template <typename K>
 void launch_join_hash(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w,
                       uint32_t j, uint64_t slots, Ev ev_count = Ev(), Ev ev_emit = Ev());
+
+// Sort *n_ptr keys of cand[0] into cand[passes & 1] in one block when they fit its LDS
+// (sets ctrl->small_sorted, which turns the LSD passes of this sort into no-ops).
+template <typename K>
+void launch_small_sort(hipStream_t s, Ctrl* ctrl, const uint64_t* n_ptr, const Bufs<K>& b, int passes,
+                       Ev ev = Ev());
 
 // One LSD pass over *n_ptr keys: pass p reads cand[p & 1] and writes cand[(p + 1) & 1];
 // digit p covers bits [p * c.rb, (p + 1) * c.rb).  `scatter` false: the count and scan

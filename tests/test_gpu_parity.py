@@ -47,6 +47,17 @@ def test_tc_shapes(engine, shape):
     assert_same(s, d, st, oracle.tc(src, dst))
 
 
+def test_small_to_large_iterations(engine):
+    """Iterations that fit the one-block sort, then outgrow it mid-batch, then shrink."""
+    c_src, c_dst = inputs.chain(60)
+    d_src, d_dst = inputs.complete_dag(400)
+    src = np.concatenate([c_src, d_src + 59]).astype(np.uint32)  # the chain ends in the DAG
+    dst = np.concatenate([c_dst, d_dst + 59]).astype(np.uint32)
+    for opts in (None, wg.make_options(batch_k=8), wg.make_options(flags=wg.WG_NO_SPECULATION, batch_k=1)):
+        s, d, st = run(engine, "tc", src, dst, opts)
+        assert_same(s, d, st, oracle.tc(src, dst))
+
+
 def test_tc_er_2000_config(engine):
     w = inputs.workload("tc_er_2000")
     s, d, st = run(engine, "tc", w.src, w.dst)
