@@ -553,12 +553,16 @@ def main():
     if args.dominant:
         if args.dominant not in wg.STAGES:
             raise SystemExit(f"--dominant must be one of {wg.STAGES}")
-        dom, probe_ms, probe_gb = args.dominant, None, None
+        dom, probe_ms, probe_gb, probe_frac = args.dominant, None, None, None
     else:
         probe = solve(wg.make_options(flags=wg.WG_STAGE_TIMING | base_flags, **sort_opts))
         dom = max(wg.STAGES, key=lambda k: probe["stage_ms"][k])
         probe_ms = {k: round(v, 3) for k, v in probe["stage_ms"].items()}
         probe_gb = {k: round(v / 1e9, 4) for k, v in probe["stage_bytes"].items()}
+        # every kernel kind against the HBM peak (algorithmic bytes / event time, one solve
+        # with events on every launch, so slightly pessimistic for the small kinds)
+        probe_frac = {k: round(probe["stage_bytes"][k] / (probe["stage_ms"][k] * 1e6) / HBM_PEAK_GBS, 4)
+                      for k in probe["stage_ms"] if probe["stage_ms"][k] > 0}
     tuples = 0
     st = None
     ms_per_step = value = None
@@ -644,6 +648,7 @@ def main():
                    "sort_passes": st["sort_passes"], "host_syncs_per_step": st["host_syncs"]},
         "stage_ms_probe": probe_ms,
         "stage_algorithmic_gb": probe_gb,
+        "stage_hbm_frac": probe_frac,
         "roofline": roofline,
         "cpu_baseline": None,
     }
