@@ -739,17 +739,21 @@ __global__ __launch_bounds__(kBlock) void k_radix_scan(Ctrl* ctrl, const uint64_
 
 // Lanes of the wave (within `active`) whose RB-bit digit equals this lane's: one ballot
 // per bit.  For bit b, sb is 0 or all ones (the lane's bit, sign-extended); the lanes that
-// agree with this lane on bit b are ballot(bit b) XNOR sb, per 32-lane half -- about six
-// VALU instructions per bit.
+// agree with this lane on bit b are ballot(bit b) XNOR sb, per 32-lane half.  The ballot
+// compares sb itself (so the bit is extracted once) and each half's update
+// acc & ~(ballot ^ sb) is one three-input bit operation: four VALU instructions per bit.
+// The operation's table is indexed by (first, second, third) operand bits, first most
+// significant, so evaluating the function on the patterns 0xF0, 0xCC, 0xAA yields it.
+constexpr uint32_t kAndXnor = (0xF0u & ~(0xCCu ^ 0xAAu)) & 0xFFu;  // acc & ~(m ^ sb)
 template <int RB>
 __device__ __forceinline__ uint64_t digit_peers(uint32_t d, uint64_t active) {
   uint32_t lo = (uint32_t)active, hi = (uint32_t)(active >> 32);
 #pragma unroll
   for (int bit = 0; bit < RB; ++bit) {
-    const uint32_t sb = (uint32_t)(((int32_t)(d << (31 - bit))) >> 31);
-    const uint64_t m = __builtin_amdgcn_ballot_w64(sb != 0u);
-    lo &= ~((uint32_t)m ^ sb);
-    hi &= ~((uint32_t)(m >> 32) ^ sb);
+    const uint32_t sb = (uint32_t)__builtin_amdgcn_sbfe((int)d, bit, 1);
+    const uint64_t m = __builtin_amdgcn_uicmp(sb, 0u, 33 /* ICMP_NE */);
+    lo = __builtin_amdgcn_bitop3_b32(lo, (uint32_t)m, sb, kAndXnor);
+    hi = __builtin_amdgcn_bitop3_b32(hi, (uint32_t)(m >> 32), sb, kAndXnor);
   }
   return ((uint64_t)hi << 32) | lo;
 }
