@@ -982,11 +982,26 @@ __device__ __forceinline__ void drop_present_sampled(const K* s, uint32_t ns, co
     }
     len -= half;
   }
+  // the item is at p or p + 1 if present: both keys are loaded at once
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
-    const uint32_t q = p[k] + ((g[min(p[k], end[k] - 1)] < cv[k]) ? 1u : 0u);
-    if (u[k] && q < end[k] && g[q] == cv[k]) keep[k] = false;
+    const K x0 = g[min(p[k], end[k] - 1)];
+    const K x1 = g[min(p[k] + 1, end[k] - 1)];
+    const bool past = x0 < cv[k];
+    const uint32_t q = p[k] + (past ? 1u : 0u);
+    if (u[k] && q < end[k] && (past ? x1 : x0) == cv[k]) keep[k] = false;
   }
+}
+
+// Items per block range of the compaction.  At least a tile per block: whole tiles.  A
+// smaller input is spread over the grid in ranges of kCompactGrain-multiples, so that each
+// block's windows of Full are shorter (fewer dependent searches per block, more blocks in
+// flight); the local and gather launches use the same grid, hence the same ranges.
+__device__ __forceinline__ uint32_t compact_span(uint64_t n, uint32_t T, uint32_t G) {
+  const uint64_t per = (n + G - 1) / G;
+  if (per >= T) return T;
+  const uint32_t g = (uint32_t)((per + kCompactGrain - 1) / kCompactGrain) * kCompactGrain;
+  return g < kCompactGrain ? kCompactGrain : g;
 }
 
 template <typename K, int ITEMS>
@@ -1004,11 +1019,22 @@ __global__ __launch_bounds__(kBlock) void k_compact_local(Ctrl* ctrl, int mode, 
   j = iter_cur(ctrl, j);
   const uint64_t n = *n_ptr;
   uint64_t lo, hi;
-  block_range(n, T, lo, hi);
+  block_range(n, compact_span(n, T, gridDim.x), lo, hi);
   if (lo >= hi) {
     if (threadIdx.x == 0) b.bcnt[blockIdx.x] = 0;
     return;
   }
+  // the first tile's keys are loaded now, so their latency overlaps the searches below
+  K first[ITEMS];
+  {
+    const uint32_t tn0 = (uint32_t)min<uint64_t>(T, hi - lo);
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint32_t jj = (uint32_t)k * kBlock + threadIdx.x;
+      first[k] = jj < tn0 ? in[lo + jj] : K(0);
+    }
+  }
+  const K before_lo = (threadIdx.x == 0 && lo > 0) ? in[lo - 1] : K(0);
   const bool diff = (mode & kModeIter) != 0;
   // Full of iteration j-1: runs A and B, each tile's window of each staged in LDS when it
   // fits (searched in place otherwise)
@@ -1053,12 +1079,27 @@ __global__ __launch_bounds__(kBlock) void k_compact_local(Ctrl* ctrl, int mode, 
   uint64_t a_at = alo, b_at = blo;
   for (uint64_t tbase = lo; tbase < hi; tbase += T) {
     const uint32_t tn = (uint32_t)min<uint64_t>(T, hi - tbase);
-    for (uint32_t jj = threadIdx.x; jj < tn; jj += kBlock) s_c[jj + 1] = in[tbase + jj];
-    if (threadIdx.x == 0 && tbase > 0) s_c[0] = in[tbase - 1];
+    if (tbase == lo) {
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t jj = (uint32_t)k * kBlock + threadIdx.x;
+        if (jj < tn) s_c[jj + 1] = first[k];
+      }
+      if (threadIdx.x == 0 && tbase > 0) s_c[0] = before_lo;
+    } else {
+      for (uint32_t jj = threadIdx.x; jj < tn; jj += kBlock) s_c[jj + 1] = in[tbase + jj];
+      if (threadIdx.x == 0) s_c[0] = in[tbase - 1];
+    }
     if (diff) {
-      // ends of the windows of A and B that can hold this tile's keys
+      // ends of the windows of A and B that can hold this tile's keys (the last tile's
+      // are the ends of the block's parts, found above)
       const K last = in[tbase + tn - 1];
-      if (wid == 0) {
+      if (tbase + tn >= hi) {
+        if (threadIdx.x == 0) {
+          s_hi[0] = ahi;
+          s_hi[1] = bhi;
+        }
+      } else if (wid == 0) {
         const uint64_t v = a_at + wave_upper_bound(runA + a_at, ahi - a_at, last);
         if (lane_id() == 0) s_hi[0] = v;
       } else if (wid == 1) {
@@ -1156,7 +1197,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_gather(Ctrl* ctrl, int mode,
   const uint64_t n = *n_ptr;
   const uint64_t N = block_prefix(b.bcnt, gridDim.x, s_pre, s_wave);
   uint64_t lo, hi;
-  block_range(n, T, lo, hi);
+  block_range(n, compact_span(n, T, gridDim.x), lo, hi);
   K* out1 = nullptr;
   K* out2 = nullptr;
   K* out3 = nullptr;

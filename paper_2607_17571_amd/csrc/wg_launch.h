@@ -28,6 +28,7 @@ enum CompactMode : int {
 constexpr int kJoinItems = 8;
 constexpr int kEmitItems = 8;
 constexpr int kDedupItems = 8;
+constexpr uint32_t kCompactGrain = 64;  // smallest block range of a spread compaction
 constexpr int kMergeItems = 8;
 constexpr uint32_t kSmallSortBytes = 32768;  // LDS of the one-block sort (8,192 / 4,096 keys)
 constexpr int kIndexItems = 8;
