@@ -71,7 +71,10 @@ struct wg_engine {
   DevBuf cand[2], full[2], fullB[2], delta[2], E, U, R, Edst, rowa, rowb, off, rec, htab;
   uint64_t hash_slots = 0;  // hash-join variant: table slots of the current solve (0: off)
   uint64_t dense_rows = 0;  // rows of the dense edge index of the current solve (0: U + search)
-  bool small_hint = true;   // the next iterations' candidates may fit the one-block sort
+  // how the loop's iterations sort their candidates: 0 the LSD passes; 1 the one-block
+  // sort, then the passes (no-ops when it fit); 2 the one-block sort alone (a miss halts
+  // the loop and the iteration is re-run with mode 1)
+  int small_mode = 1;
   hipStream_t capture_stream = nullptr;  // private stream the iteration graph is recorded on
   hipGraphExec_t graph_exec = nullptr;   // the recorded iteration (see iteration_graph)
   std::vector<uint8_t> graph_key;        // the kernel arguments it was recorded with
@@ -328,12 +331,15 @@ void collect_timing(wg_engine* e, wg_stats* st) {
 }
 
 // ----- pipeline pieces
-// `small`: the input may fit one block (then the one-block sort runs first and, if it did
-// fit, the passes below exit at once).
+// `small` 1: the input may fit one block (then the one-block sort runs first and, if it
+// did fit, the passes below exit at once); 2: it is expected to fit and the passes are not
+// enqueued (a miss sets overflow bit 3); 0: the passes alone.
 template <typename K>
-void enqueue_sort(wg_engine* e, const Bufs<K>& b, const uint64_t* n_ptr, bool small = true) {
+void enqueue_sort(wg_engine* e, const Bufs<K>& b, const uint64_t* n_ptr, int small = 1) {
   const int passes = sort_passes(e->key_bits, e->sort.rb);
-  if (small) launch_small_sort<K>(e->stream, e->d_ctrl, n_ptr, b, passes, stage(e, WG_STAGE_RADIX_HIST));
+  if (small)
+    launch_small_sort<K>(e->stream, e->d_ctrl, n_ptr, b, passes, small == 2, stage(e, WG_STAGE_RADIX_HIST));
+  if (small == 2) return;
   for (int p = 0; p < passes; ++p) {
     launch_sort_pass<K>(e->stream, e->d_ctrl, n_ptr, e->sort, b, p, false, stage(e, WG_STAGE_RADIX_HIST));
     launch_sort_pass<K>(e->stream, e->d_ctrl, n_ptr, e->sort, b, p, true, stage(e, WG_STAGE_RADIX_PASS));
@@ -363,7 +369,7 @@ void enqueue_iteration(wg_engine* e, const Bufs<K>& b, int kind, int w, int pass
     launch_join_emit<K>(e->stream, e->grid, kind, e->d_ctrl, b, w, jd, stage(e, WG_STAGE_JOIN_EMIT));
   }
   if (e->stage_sync) stage_probe(e, &b.rec[j].C);
-  enqueue_sort<K>(e, b, C, e->small_hint);
+  enqueue_sort<K>(e, b, C, e->small_mode);
   const uint32_t p = (uint32_t)passes & 1u;
   if (e->unfused) {
     launch_compact<K>(e->stream, e->grid, kModeDedup, e->d_ctrl, C, b.cand[p], b.cand[p ^ 1u], b, w, jd, p,
@@ -387,7 +393,7 @@ struct IterGraphKey {
   SortCfg sort;
   Grid grid;
   uint64_t hash_slots;
-  int unfused, small_hint;
+  int unfused, small_mode;
 };
 
 template <typename K>
@@ -403,7 +409,7 @@ hipGraphExec_t iteration_graph(wg_engine* e, const Bufs<K>& b, int kind, int w, 
   key.grid = e->grid;
   key.hash_slots = e->hash_slots;
   key.unfused = e->unfused ? 1 : 0;
-  key.small_hint = e->small_hint ? 1 : 0;
+  key.small_mode = e->small_mode;
   if (e->graph_exec && e->graph_key.size() == sizeof(key) &&
       std::memcmp(e->graph_key.data(), &key, sizeof(key)) == 0)
     return e->graph_exec;
@@ -578,7 +584,8 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
                          stage(e, WG_STAGE_PREPARE));
   else
     launch_pack<K>(e->stream, e->grid, src, dst, m, w, b.cand[0], stage(e, WG_STAGE_PREPARE));
-  enqueue_sort<K>(e, b, &e->d_ctrl->m_in, m * sizeof(K) <= kSmallSortBytes);
+  // (the m packed keys are all sorted: when they fit one block its sort runs alone)
+  enqueue_sort<K>(e, b, &e->d_ctrl->m_in, m * sizeof(K) <= kSmallSortBytes ? 2 : 0);
   const int mode = query == WG_QUERY_SG ? kModeEdges : (kModeEdges | kModeSeed);
   launch_compact<K>(e->stream, e->grid, mode, e->d_ctrl, &e->d_ctrl->m_in, b.cand[passes & 1],
                     b.cand[(passes & 1) ^ 1], b, w, 0, 0, stage(e, WG_STAGE_DEDUP_DIFF));
@@ -704,10 +711,22 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
     read_back(e, sl, batch_first - 1, next_j - 1);
     batch_first = next_j;
   };
-  // the one-block sort is enqueued while the last checked iteration's candidates were
-  // within 4x of what it holds (the first batch has no size yet)
-  e->small_hint = true;
-  const uint64_t small_keys = 4 * (kSmallSortBytes / sizeof(K));
+  // The one-block sort is enqueued while the last checked iteration's candidates were
+  // within 4x of what it holds (the first batch has no size yet).  Once they are at most
+  // half of it and no longer growing it is enqueued alone, without the LSD passes behind
+  // it (a dozen no-op launches per iteration of the fixpoint's tail): the loop's next
+  // iterations run up to a batch and a speculative batch ahead of that check, and a miss
+  // halts the loop, which re-runs the iteration with the passes and keeps them for the
+  // rest of the solve.  Batches of many iterations (the paper's policy) never go alone.
+  const uint64_t small_keys = kSmallSortBytes / sizeof(K);
+  bool small_missed = false;
+  auto pick_small_mode = [&](uint32_t it) {
+    const uint64_t C = e->h_rec[it].C;
+    const bool shrinking = it >= 2 && C <= e->h_rec[it - 1].C;
+    if (!small_missed && K_batch <= kAutoK && shrinking && 2 * C <= small_keys) e->small_mode = 2;
+    else e->small_mode = C <= 4 * small_keys ? 1 : 0;
+  };
+  e->small_mode = 1;
   enqueue_batch(K_batch, slot);
   for (;;) {
     // While the host waits on this batch, the device runs a short speculative batch
@@ -715,7 +734,7 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
     // fixpoint its launches are no-ops, so it is kept short.
     if (speculate) enqueue_iters(std::min(K_batch, kSpec));
     r = wait_back(e, slot);
-    e->small_hint = e->h_rec[r.c.iter].C <= small_keys;
+    pick_small_mode(r.c.iter);
     // (at the fixpoint the speculative batch still drains behind the final launches;
     // everything after this is stream-ordered and reads the host mirror of the records)
     if (r.c.overflow | r.c.limit_hit) sync_stream(e);
@@ -724,6 +743,10 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
       fail(e, WG_ERR_CANCELLED, "cancelled");
     }
     if (r.c.overflow) {
+      if (r.c.overflow & 8u) {
+        small_missed = true;
+        e->small_mode = 1;
+      }
       grow_and_resume(e, r.c, hooked);
       if (st) st->resumes++;
       next_j = r.c.iter + 1;

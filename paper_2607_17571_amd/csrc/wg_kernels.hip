@@ -585,13 +585,19 @@ constexpr int kSmallSortThreads = 1024;
 
 template <typename K>
 __global__ __launch_bounds__(kSmallSortThreads) void k_small_sort(Ctrl* ctrl, const uint64_t* n_ptr,
-                                                                  const K* __restrict__ in, K* out) {
+                                                                  const K* __restrict__ in, K* out,
+                                                                  uint32_t alone) {
   constexpr uint32_t CAP = kSmallSortBytes / sizeof(K);
   __shared__ K s[CAP];
   if (halted(ctrl)) return;
   const uint64_t n = *n_ptr;
   if (n > CAP) {
-    if (threadIdx.x == 0) ctrl->small_sorted = 0;
+    if (threadIdx.x == 0) {
+      // no LSD passes follow a sort enqueued alone: halt the loop (the host re-runs the
+      // iteration with them)
+      if (alone) atomicOr(&ctrl->overflow, 8u);
+      else ctrl->small_sorted = 0;
+    }
     return;
   }
   uint32_t P = 1;
@@ -1692,15 +1698,15 @@ void sort_pass_impl(hipStream_t s, Ctrl* ctrl, const uint64_t* n_ptr, int G, con
 }
 
 template <typename K>
-void launch_small_sort(hipStream_t s, Ctrl* ctrl, const uint64_t* n_ptr, const Bufs<K>& b, int passes, Ev ev) {
-  hipEvent_t none = nullptr;
-  (void)none;
+void launch_small_sort(hipStream_t s, Ctrl* ctrl, const uint64_t* n_ptr, const Bufs<K>& b, int passes,
+                       bool alone, Ev ev) {
+  const uint32_t a = alone ? 1u : 0u;
   if (ev.start || ev.stop)
     hipExtLaunchKernelGGL(k_small_sort<K>, dim3(1), dim3(kSmallSortThreads), 0, s, ev.start, ev.stop, 0, ctrl,
-                          n_ptr, (const K*)b.cand[0], b.cand[passes & 1]);
+                          n_ptr, (const K*)b.cand[0], b.cand[passes & 1], a);
   else
     hipLaunchKernelGGL(k_small_sort<K>, dim3(1), dim3(kSmallSortThreads), 0, s, ctrl, n_ptr,
-                       (const K*)b.cand[0], b.cand[passes & 1]);
+                       (const K*)b.cand[0], b.cand[passes & 1], a);
 }
 
 template <typename K>
@@ -1784,7 +1790,7 @@ void launch_resume(hipStream_t s, Ctrl* ctrl, uint64_t cand_cap, uint64_t full_c
                                      uint32_t, Ev);                                                \
   template void launch_join_emit<K>(hipStream_t, const Grid&, int, Ctrl*, const Bufs<K>&, int,    \
                                     uint32_t, Ev);                                                 \
-  template void launch_small_sort<K>(hipStream_t, Ctrl*, const uint64_t*, const Bufs<K>&, int, Ev); \
+  template void launch_small_sort<K>(hipStream_t, Ctrl*, const uint64_t*, const Bufs<K>&, int, bool, Ev); \
   template void launch_sort_pass<K>(hipStream_t, Ctrl*, const uint64_t*, const SortCfg&,         \
                                     const Bufs<K>&, int, bool, Ev);                                \
   template void launch_compact<K>(hipStream_t, const Grid&, int, Ctrl*, const uint64_t*, const K*, \

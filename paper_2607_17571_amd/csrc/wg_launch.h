@@ -129,9 +129,10 @@ void launch_join_hash(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const 
 
 // Sort *n_ptr keys of cand[0] into cand[passes & 1] in one block when they fit its LDS
 // (sets ctrl->small_sorted, which turns the LSD passes of this sort into no-ops).
+// `alone`: no LSD passes follow; more keys than fit set overflow bit 3 (halting the loop).
 template <typename K>
 void launch_small_sort(hipStream_t s, Ctrl* ctrl, const uint64_t* n_ptr, const Bufs<K>& b, int passes,
-                       Ev ev = Ev());
+                       bool alone, Ev ev = Ev());
 
 // One LSD pass over *n_ptr keys: pass p reads cand[p & 1] and writes cand[(p + 1) & 1];
 // digit p covers bits [p * c.rb, (p + 1) * c.rb).  `scatter` false: the count and scan

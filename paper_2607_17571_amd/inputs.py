@@ -161,6 +161,40 @@ def diamond():
     return np.array([0, 0, 1, 2], dtype=U32), np.array([1, 2, 3, 3], dtype=U32)
 
 
+def layers_and_intree(K: int, W: int, H: int, F: int, D: int):
+    """Two components whose per-iteration join sizes first shrink, then jump.
+
+    (1) K + 1 layers of W vertices, every vertex of layer k pointing to every vertex of
+    layer k + 1 (ids 0 .. (K+1)W-1); (2) an F-ary in-tree of depth H whose edges point
+    towards its root r, and r pointing to D fresh leaves.  Under transitive closure the
+    layered part's joins shrink each iteration and end after K of them, while the paths
+    reaching r multiply by F per iteration, each joining with r's D out-edges.
+    """
+    src, dst = [], []
+    for k in range(K):
+        for a in range(W):
+            for b in range(W):
+                src.append(k * W + a)
+                dst.append((k + 1) * W + b)
+    root = (K + 1) * W
+    nxt = root + 1
+    level = [root]
+    for _ in range(H):
+        new = []
+        for p in level:
+            for _ in range(F):
+                src.append(nxt)
+                dst.append(p)
+                new.append(nxt)
+                nxt += 1
+        level = new
+    for _ in range(D):
+        src.append(root)
+        dst.append(nxt)
+        nxt += 1
+    return np.array(src, dtype=U32), np.array(dst, dtype=U32)
+
+
 # ---------------------------------------------------------------------------
 # Workload recipes (the shapes the benchmarks and parity tests run).
 # ---------------------------------------------------------------------------

@@ -335,6 +335,23 @@ def test_forced_overflow_resumes_identically(engine, at):
     assert st["resumes"] >= 1
 
 
+def test_one_block_sort_miss_reruns_iteration(engine):
+    """Join sizes 13144, 7656, 3200, 8704, 30720 (32-bit keys; the one-block sort holds
+    8192): with a check after every iteration, iteration 4 is sorted by the one-block sort
+    alone (3200 <= 4096 and shrinking), finds 8704 keys, halts the loop and is re-run with
+    the LSD passes.  Every loop policy gives the closure."""
+    src, dst = inputs.layers_and_intree(3, 18, 5, 4, 30)
+    ref = oracle.tc(src, dst)
+    s, d, st = run(engine, "tc", src, dst,
+                   wg.make_options(loop_mode=wg.WG_LOOP_HOST, flags=wg.WG_NO_SPECULATION))
+    assert_same(s, d, st, ref)
+    assert st["resumes"] == 1
+    for opts in (None, wg.make_options(loop_mode=wg.WG_LOOP_HOST), wg.make_options(flags=wg.WG_ITER_GRAPH),
+                 wg.make_options(loop_mode=wg.WG_LOOP_STAGE), wg.make_options(flags=wg.WG_UNFUSED_DEDUP)):
+        s, d, st = run(engine, "tc", src, dst, opts)
+        assert_same(s, d, st, ref)
+
+
 def test_growth_from_small_buffers(engine):
     """A fresh engine starts with small buffers; a large closure must grow and resume."""
     eng = wg.Engine(0)
