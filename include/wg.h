@@ -114,9 +114,10 @@ typedef struct {
 /* Kernel kinds reported in wg_stats.stage_ms / stage_launches / stage_bytes. */
 enum {
   WG_STAGE_JOIN_COUNT = 0, /* binary-search range lookup + count scan (Section IV-A) */
-  WG_STAGE_JOIN_EMIT = 1,  /* candidate emission into scanned slabs (Section IV-A) */
+  WG_STAGE_JOIN_EMIT = 1,  /* candidate emission into scanned slabs (Section IV-A); also
+                              the one-block join + sort of a small iteration */
   WG_STAGE_RADIX_HIST = 2, /* per-block digit counts and their scan, one per LSD pass
-                              (Section V-C) */
+                              (Section V-C); also the one-block sort of a small input */
   WG_STAGE_RADIX_PASS = 3, /* the stable scatter of one LSD pass (Section V-C) */
   WG_STAGE_DEDUP_DIFF = 4, /* fused dedup + set difference (Section IV-B) */
   WG_STAGE_MERGE = 5,      /* disjoint merge-path merge (Section IV-C) */

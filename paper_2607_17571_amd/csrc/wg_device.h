@@ -177,7 +177,9 @@ __device__ __forceinline__ uint32_t block_excl_max(uint32_t v, uint32_t* s_wave)
   return ex;
 }
 
-template <typename T>
+// (WAVES: waves of the block, kWavesPerBlock unless the kernel runs wider blocks;
+// s_wave holds WAVES entries)
+template <typename T, int WAVES = kWavesPerBlock>
 __device__ __forceinline__ T block_excl_scan(T v, T* s_wave, T& total) {
   T incl = wave_incl_scan(v);
   const int wid = threadIdx.x / kWave;
@@ -185,7 +187,7 @@ __device__ __forceinline__ T block_excl_scan(T v, T* s_wave, T& total) {
   __syncthreads();
   T before = 0, tot = 0;
 #pragma unroll
-  for (int i = 0; i < kWavesPerBlock; ++i) {
+  for (int i = 0; i < WAVES; ++i) {
     T x = s_wave[i];
     before += (i < wid) ? x : T(0);
     tot += x;

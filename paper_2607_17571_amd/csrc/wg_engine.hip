@@ -71,9 +71,10 @@ struct wg_engine {
   DevBuf cand[2], full[2], fullB[2], delta[2], E, U, R, Edst, rowa, rowb, off, rec, htab;
   uint64_t hash_slots = 0;  // hash-join variant: table slots of the current solve (0: off)
   uint64_t dense_rows = 0;  // rows of the dense edge index of the current solve (0: U + search)
-  // how the loop's iterations sort their candidates: 0 the LSD passes; 1 the one-block
-  // sort, then the passes (no-ops when it fit); 2 the one-block sort alone (a miss halts
-  // the loop and the iteration is re-run with mode 1)
+  // how the loop's iterations join and sort: 0 the LSD passes; 1 the one-block sort,
+  // then the passes (no-ops when it fit); 2 the one-block sort alone; 3 the join and the
+  // sort in one block (in 2 and 3 a miss halts the loop and the iteration is re-run with
+  // mode 1)
   int small_mode = 1;
   hipStream_t capture_stream = nullptr;  // private stream the iteration graph is recorded on
   hipGraphExec_t graph_exec = nullptr;   // the recorded iteration (see iteration_graph)
@@ -360,7 +361,10 @@ template <typename K>
 void enqueue_iteration(wg_engine* e, const Bufs<K>& b, int kind, int w, int passes, uint32_t j) {
   const uint32_t jd = kIterDevice;
   const uint64_t* C = &e->d_ctrl->cand_n;
-  if (e->hash_slots) {
+  const bool one_block = e->small_mode == 3 && !e->hash_slots && !e->stage_sync;
+  if (one_block) {
+    launch_small_join<K>(e->stream, kind, e->d_ctrl, b, w, jd, passes, stage(e, WG_STAGE_JOIN_EMIT));
+  } else if (e->hash_slots) {
     const Ev ec = stage(e, WG_STAGE_JOIN_COUNT);
     launch_join_hash<K>(e->stream, e->grid, kind, e->d_ctrl, b, w, jd, e->hash_slots, ec,
                         stage(e, WG_STAGE_JOIN_EMIT));
@@ -369,7 +373,7 @@ void enqueue_iteration(wg_engine* e, const Bufs<K>& b, int kind, int w, int pass
     launch_join_emit<K>(e->stream, e->grid, kind, e->d_ctrl, b, w, jd, stage(e, WG_STAGE_JOIN_EMIT));
   }
   if (e->stage_sync) stage_probe(e, &b.rec[j].C);
-  enqueue_sort<K>(e, b, C, e->small_mode);
+  if (!one_block) enqueue_sort<K>(e, b, C, std::min(e->small_mode, 2));
   const uint32_t p = (uint32_t)passes & 1u;
   if (e->unfused) {
     launch_compact<K>(e->stream, e->grid, kModeDedup, e->d_ctrl, C, b.cand[p], b.cand[p ^ 1u], b, w, jd, p,
@@ -713,18 +717,25 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   };
   // The one-block sort is enqueued while the last checked iteration's candidates were
   // within 4x of what it holds (the first batch has no size yet).  Once they are at most
-  // half of it and no longer growing it is enqueued alone, without the LSD passes behind
-  // it (a dozen no-op launches per iteration of the fixpoint's tail): the loop's next
-  // iterations run up to a batch and a speculative batch ahead of that check, and a miss
-  // halts the loop, which re-runs the iteration with the passes and keeps them for the
-  // rest of the solve.  Batches of many iterations (the paper's policy) never go alone.
+  // a quarter of it, or half of it and not growing, it is enqueued alone, without the LSD
+  // passes behind it (a dozen no-op launches per iteration of the fixpoint's tail): the
+  // loop's next iterations run up to a batch and a speculative batch ahead of that check,
+  // and a miss halts the loop, which re-runs the iteration with the passes and keeps them
+  // for the rest of the solve.  Batches of many iterations (the paper's policy) never go
+  // alone.
   const uint64_t small_keys = kSmallSortBytes / sizeof(K);
   bool small_missed = false;
+  // within a quarter of a limit, or half of it and not growing
+  auto calm = [&](uint64_t now, uint64_t before, uint64_t limit) {
+    return 4 * now <= limit || (2 * now <= limit && now <= before);
+  };
   auto pick_small_mode = [&](uint32_t it) {
-    const uint64_t C = e->h_rec[it].C;
-    const bool shrinking = it >= 2 && C <= e->h_rec[it - 1].C;
-    if (!small_missed && K_batch <= kAutoK && shrinking && 2 * C <= small_keys) e->small_mode = 2;
-    else e->small_mode = C <= 4 * small_keys ? 1 : 0;
+    const IterRec& x = e->h_rec[it];
+    const IterRec& y = e->h_rec[it > 0 ? it - 1 : 0];
+    if (!small_missed && K_batch <= kAutoK && it >= 2 && calm(x.C, y.C, small_keys))
+      e->small_mode = calm(x.N, y.N, kSmallJoinTuples) ? 3 : 2;
+    else
+      e->small_mode = x.C <= 4 * small_keys ? 1 : 0;
   };
   e->small_mode = 1;
   enqueue_batch(K_batch, slot);

@@ -580,8 +580,97 @@ __global__ __launch_bounds__(kBlock) void k_join_emit_hash(Ctrl* ctrl, Bufs<K> b
 // small_sorted set and exit.  Output in the buffer the LSD passes would have ended in.
 // The host launches it only where the input may fit (the flag is cleared by the
 // compaction that follows every sort, and on resume).
+//
+// The network runs in registers: thread t holds the keys at positions r * 1024 + t.  A
+// compare-exchange between positions jj apart is then inside one thread (jj >= 1024), inside
+// one wave (jj < 64: a lane shuffle, no barrier), or through LDS (one store, barrier, load).
 // ---------------------------------------------------------------------------
 constexpr int kSmallSortThreads = 1024;
+static_assert(kSmallJoinTuples == kSmallSortThreads, "the one-block join takes one tuple per thread");
+
+template <typename K>
+__device__ __forceinline__ K shfl_xor_key(K v, int lane_mask) {
+  if constexpr (sizeof(K) == 4) {
+    return (K)(uint32_t)__shfl_xor((int)v, lane_mask, kWave);
+  } else {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, lane_mask, kWave);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), lane_mask, kWave);
+    return ((K)hi << 32) | (K)lo;
+  }
+}
+
+// Key at position i after its compare-exchange with position i ^ jj (partner key c) in
+// the merge of bitonic runs of length k: the lower position keeps the smaller key in an
+// ascending run ((i & k) == 0) and the larger one in a descending run.
+template <typename K>
+__device__ __forceinline__ K bitonic_keep(K a, K c, uint32_t i, uint32_t jj, uint32_t k) {
+  const bool take_min = ((i & jj) == 0) == ((i & k) == 0);
+  return take_min ? (c < a ? c : a) : (c < a ? a : c);
+}
+
+// Sorts s[0, n) (LDS, n <= CAP) ascending with all kSmallSortThreads threads of the block
+// and writes the result to out[0, n) (global).  s is clobbered.
+template <typename K>
+__device__ __forceinline__ void block_bitonic_sort(K* s, uint32_t n, K* __restrict__ out) {
+  constexpr uint32_t TH = kSmallSortThreads;
+  constexpr uint32_t CAP = kSmallSortBytes / sizeof(K);
+  constexpr int EMAX = (int)(CAP / TH);  // keys per thread at most
+  const uint32_t t = threadIdx.x;
+  uint32_t P = 1;
+  while (P < n) P <<= 1;
+  const int E = P > TH ? (int)(P / TH) : 1;
+  K v[EMAX];
+#pragma unroll
+  for (int r = 0; r < EMAX; ++r) {
+    const uint32_t i = (uint32_t)r * TH + t;
+    v[r] = (r < E && i < n) ? s[i] : ~K(0);  // padding sorts last
+  }
+  for (uint32_t k = 2; k <= P; k <<= 1) {
+    for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+      if (jj >= TH) {
+        // both keys in this thread: slots r and r ^ (jj / TH) (static indices)
+#pragma unroll
+        for (int rj = 1; rj < EMAX; rj <<= 1) {
+          if ((uint32_t)rj * TH != jj) continue;
+#pragma unroll
+          for (int r = 0; r < EMAX; ++r) {
+            if ((r & rj) != 0 || r >= E) continue;
+            const uint32_t i = (uint32_t)r * TH + t;
+            const K a = v[r], c = v[r | rj];
+            const bool asc = (i & k) == 0;
+            const K lo = c < a ? c : a, hi = c < a ? a : c;
+            v[r] = asc ? lo : hi;
+            v[r | rj] = asc ? hi : lo;
+          }
+        }
+      } else if (jj >= (uint32_t)kWave) {
+        __syncthreads();  // the previous exchange's loads are done
+#pragma unroll
+        for (int r = 0; r < EMAX; ++r)
+          if (r < E) s[(uint32_t)r * TH + t] = v[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < EMAX; ++r) {
+          if (r >= E) continue;
+          const uint32_t i = (uint32_t)r * TH + t;
+          if (i < P) v[r] = bitonic_keep(v[r], s[i ^ jj], i, jj, k);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < EMAX; ++r) {
+          if (r >= E) continue;
+          const uint32_t i = (uint32_t)r * TH + t;
+          v[r] = bitonic_keep(v[r], shfl_xor_key(v[r], (int)jj), i, jj, k);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < EMAX; ++r) {
+    const uint32_t i = (uint32_t)r * TH + t;
+    if (r < E && i < n) out[i] = v[r];
+  }
+}
 
 template <typename K>
 __global__ __launch_bounds__(kSmallSortThreads) void k_small_sort(Ctrl* ctrl, const uint64_t* n_ptr,
@@ -600,27 +689,151 @@ __global__ __launch_bounds__(kSmallSortThreads) void k_small_sort(Ctrl* ctrl, co
     }
     return;
   }
-  uint32_t P = 1;
-  while (P < n) P <<= 1;
-  for (uint32_t i = threadIdx.x; i < P; i += kSmallSortThreads) s[i] = i < n ? in[i] : ~K(0);
+  for (uint32_t i = threadIdx.x; i < (uint32_t)n; i += kSmallSortThreads) s[i] = in[i];
   __syncthreads();
-  for (uint32_t k = 2; k <= P; k <<= 1) {
-    for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
-      for (uint32_t i = threadIdx.x; i < P; i += kSmallSortThreads) {
-        const uint32_t l = i ^ jj;
-        if (l > i) {
-          const K a = s[i], c = s[l];
-          if ((a > c) == ((i & k) == 0)) {
-            s[i] = c;
-            s[l] = a;
-          }
-        }
+  block_bitonic_sort<K>(s, (uint32_t)n, out);
+  if (threadIdx.x == 0) ctrl->small_sorted = 1;
+}
+
+// ---------------------------------------------------------------------------
+// One iteration's join and sort in a single block, for the fixpoint's tail (a delta of at
+// most kSmallSortThreads tuples whose candidates fit the one-block sort): each thread
+// counts one delta tuple's candidates as the count phase does, a block scan lays out the
+// slabs, every candidate position finds its tuple by bisection over the slab starts in LDS
+// and reads one edge (two for SG), and the candidates are sorted in LDS.  It replaces the
+// count, emit and sort launches of such an iteration.  A larger delta or candidate set
+// sets overflow bit 3 (halting the loop; the host re-runs the iteration with the
+// multi-block launches); the capacity check and the overflow test hook act as in the
+// emit phase.
+// ---------------------------------------------------------------------------
+template <typename K, int Q>
+__global__ __launch_bounds__(kSmallSortThreads) void k_small_join(Ctrl* ctrl, Bufs<K> b, int w, uint32_t j,
+                                                                  K* __restrict__ out) {
+  constexpr uint32_t TH = kSmallSortThreads;
+  constexpr uint32_t CAP = kSmallSortBytes / sizeof(K);
+  constexpr int EMAX = (int)(CAP / TH);
+  constexpr bool kSG = Q == kJoinSG;
+  static_assert(Q == kJoinTC || Q == kJoinSG, "recursive joins only");
+  __shared__ K s_keys[CAP];
+  __shared__ uint32_t s_off[TH];   // per tuple: first candidate
+  __shared__ uint32_t s_base[TH];  // per tuple: first edge of the join row
+  __shared__ K s_head[TH];         // per tuple: key bits passed on (SG: the instance)
+  __shared__ uint32_t s_aux[kSG ? TH : 1];  // SG: first edge of the head row
+  __shared__ uint32_t s_len[kSG ? TH : 1];  // SG: length of the join row
+  __shared__ uint64_t s_wave[TH / kWave];
+  if (halted(ctrl)) return;
+  j = iter_begin(ctrl, j);
+  const uint64_t n = b.rec[j - 1].N;
+  const uint32_t t = threadIdx.x;
+  if (n > TH) {
+    if (t == 0) atomicOr(&ctrl->overflow, 8u);
+    return;
+  }
+  const bool dense = b.dense != 0;
+  const uint32_t* __restrict__ R = b.R;
+  const uint32_t* __restrict__ Edst = b.Edst;
+  uint64_t c = 0;
+  if (t < n) {
+    const K key = b.delta[(j - 1) & 1u][t];
+    uint32_t rb = tc_join_row<K>(key, w);
+    uint32_t ra = head_row<K>(key, w);
+    if (!dense) {
+      const uint64_t nu = ctrl->nu;
+      const uint64_t jb = lower_bound<uint32_t>(b.U, nu, rb);
+      rb = (jb < nu && b.U[jb] == rb) ? (uint32_t)jb : kNoRow;
+      if (kSG) {
+        const uint64_t ja = lower_bound<uint32_t>(b.U, nu, ra);
+        ra = (ja < nu && b.U[ja] == ra) ? (uint32_t)ja : kNoRow;
       }
-      __syncthreads();
+    }
+    if (rb != kNoRow && (!kSG || ra != kNoRow)) {
+      const uint32_t base = R[rb];
+      const uint32_t lb = R[rb + 1] - base;
+      s_base[t] = base;
+      if (kSG) {
+        const uint32_t aux = R[ra];
+        c = (uint64_t)(R[ra + 1] - aux) * lb;
+        s_aux[t] = aux;
+        s_len[t] = lb;
+        s_head[t] = (key >> w) >> w;
+      } else {
+        c = lb;
+        s_head[t] = (key >> w) << w;
+      }
     }
   }
-  for (uint32_t i = threadIdx.x; i < n; i += kSmallSortThreads) out[i] = s[i];
-  if (threadIdx.x == 0) ctrl->small_sorted = 1;
+  uint64_t C;
+  const uint64_t ex = block_excl_scan<uint64_t, TH / kWave>(c, s_wave, C);
+  if (t < n) s_off[t] = (uint32_t)min<uint64_t>(ex, 0xFFFFFFFFull);
+  const uint32_t hook = ctrl->force_overflow_at;
+  if (C > ctrl->cand_cap || (hook != 0 && hook == j)) {
+    if (t == 0) {
+      b.rec[j].C = C;
+      atomicOr(&ctrl->overflow, 1u);
+    }
+    return;
+  }
+  if (C > CAP) {
+    if (t == 0) {
+      b.rec[j].C = C;
+      atomicOr(&ctrl->overflow, 8u);
+    }
+    return;
+  }
+  if (t == 0) {
+    b.rec[j].C = C;
+    ctrl->cand_n = C;
+  }
+  __syncthreads();
+  // positions r * TH + t: their tuples (the last slab start at or before the position;
+  // tuples without candidates share the next start, so the last one holding it has
+  // candidates), then every edge load at once
+  const uint32_t nn = (uint32_t)n;
+  uint32_t e0[EMAX], e1[EMAX], tu[EMAX];
+#pragma unroll
+  for (int r = 0; r < EMAX; ++r) {
+    const uint32_t p = (uint32_t)r * TH + t;
+    tu[r] = 0;
+    if (p < C) {
+      uint32_t lo = 0, len = nn;
+      while (len > 0) {
+        const uint32_t half = len >> 1;
+        if (s_off[lo + half] <= p) {
+          lo += half + 1;
+          len -= half + 1;
+        } else {
+          len = half;
+        }
+      }
+      tu[r] = lo - 1;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < EMAX; ++r) {
+    const uint32_t p = (uint32_t)r * TH + t;
+    if (p < C) {
+      const uint32_t u = tu[r];
+      const uint32_t q = p - s_off[u];
+      if (kSG) {
+        const uint32_t lb = s_len[u];
+        const uint32_t qa = q / lb;
+        e0[r] = Edst[s_aux[u] + qa];
+        e1[r] = Edst[s_base[u] + (q - qa * lb)];
+      } else {
+        e1[r] = Edst[s_base[u] + q];
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < EMAX; ++r) {
+    const uint32_t p = (uint32_t)r * TH + t;
+    if (p < C) {
+      const K h = s_head[tu[r]];
+      s_keys[p] = kSG ? ((((h << w) | (K)e0[r]) << w) | (K)e1[r]) : (h | (K)e1[r]);
+    }
+  }
+  __syncthreads();
+  block_bitonic_sort<K>(s_keys, (uint32_t)C, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -1000,14 +1213,14 @@ __device__ __forceinline__ void drop_present_sampled(const K* s, uint32_t ns, co
 }
 
 // Items per block range of the compaction.  At least a tile per block: whole tiles.  A
-// smaller input is spread over the grid in ranges of kCompactGrain-multiples, so that each
-// block's windows of Full are shorter (fewer dependent searches per block, more blocks in
-// flight); the local and gather launches use the same grid, hence the same ranges.
+// smaller input is spread evenly over the grid (down to one key per block), so that each
+// block's windows of Full are about 1/G of it: staged whole in LDS where a tile's window
+// of a large input needs dependent searches in place.  The local and gather launches use
+// the same grid, hence the same ranges.
 __device__ __forceinline__ uint32_t compact_span(uint64_t n, uint32_t T, uint32_t G) {
   const uint64_t per = (n + G - 1) / G;
   if (per >= T) return T;
-  const uint32_t g = (uint32_t)((per + kCompactGrain - 1) / kCompactGrain) * kCompactGrain;
-  return g < kCompactGrain ? kCompactGrain : g;
+  return per > 1 ? (uint32_t)per : 1u;
 }
 
 template <typename K, int ITEMS>
@@ -1710,6 +1923,24 @@ void launch_small_sort(hipStream_t s, Ctrl* ctrl, const uint64_t* n_ptr, const B
 }
 
 template <typename K>
+void launch_small_join(hipStream_t s, int kind, Ctrl* ctrl, const Bufs<K>& b, int w, uint32_t j, int passes,
+                       Ev ev) {
+  K* out = b.cand[passes & 1];
+  const dim3 G(1), B(kSmallSortThreads);
+  if (kind == kJoinTC) {
+    if (ev.start || ev.stop)
+      hipExtLaunchKernelGGL((k_small_join<K, kJoinTC>), G, B, 0, s, ev.start, ev.stop, 0, ctrl, b, w, j, out);
+    else
+      hipLaunchKernelGGL((k_small_join<K, kJoinTC>), G, B, 0, s, ctrl, b, w, j, out);
+  } else {
+    if (ev.start || ev.stop)
+      hipExtLaunchKernelGGL((k_small_join<K, kJoinSG>), G, B, 0, s, ev.start, ev.stop, 0, ctrl, b, w, j, out);
+    else
+      hipLaunchKernelGGL((k_small_join<K, kJoinSG>), G, B, 0, s, ctrl, b, w, j, out);
+  }
+}
+
+template <typename K>
 void launch_sort_pass(hipStream_t s, Ctrl* ctrl, const uint64_t* n_ptr, const SortCfg& c,
                       const Bufs<K>& b, int pass, bool scatter, Ev ev) {
   constexpr int SMALL = 8;
@@ -1791,6 +2022,7 @@ void launch_resume(hipStream_t s, Ctrl* ctrl, uint64_t cand_cap, uint64_t full_c
   template void launch_join_emit<K>(hipStream_t, const Grid&, int, Ctrl*, const Bufs<K>&, int,    \
                                     uint32_t, Ev);                                                 \
   template void launch_small_sort<K>(hipStream_t, Ctrl*, const uint64_t*, const Bufs<K>&, int, bool, Ev); \
+  template void launch_small_join<K>(hipStream_t, int, Ctrl*, const Bufs<K>&, int, uint32_t, int, Ev); \
   template void launch_sort_pass<K>(hipStream_t, Ctrl*, const uint64_t*, const SortCfg&,         \
                                     const Bufs<K>&, int, bool, Ev);                                \
   template void launch_compact<K>(hipStream_t, const Grid&, int, Ctrl*, const uint64_t*, const K*, \

@@ -28,9 +28,9 @@ enum CompactMode : int {
 constexpr int kJoinItems = 8;
 constexpr int kEmitItems = 8;
 constexpr int kDedupItems = 8;
-constexpr uint32_t kCompactGrain = 64;  // smallest block range of a spread compaction
 constexpr int kMergeItems = 8;
 constexpr uint32_t kSmallSortBytes = 32768;  // LDS of the one-block sort (8,192 / 4,096 keys)
+constexpr uint32_t kSmallJoinTuples = 1024;   // delta tuples of the one-block join (one per thread)
 constexpr int kIndexItems = 8;
 constexpr uint32_t kJoinTile = kBlock * kJoinItems;
 constexpr uint32_t kDedupTile = kBlock * kDedupItems;
@@ -133,6 +133,13 @@ void launch_join_hash(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const 
 template <typename K>
 void launch_small_sort(hipStream_t s, Ctrl* ctrl, const uint64_t* n_ptr, const Bufs<K>& b, int passes,
                        bool alone, Ev ev = Ev());
+
+// Join (kind kJoinTC or kJoinSG) and sort of iteration j in one block, into cand[passes & 1]
+// (the fixpoint's tail: a delta beyond one tuple per thread, or candidates beyond the
+// one-block sort, set overflow bit 3).
+template <typename K>
+void launch_small_join(hipStream_t s, int kind, Ctrl* ctrl, const Bufs<K>& b, int w, uint32_t j, int passes,
+                       Ev ev = Ev());
 
 // One LSD pass over *n_ptr keys: pass p reads cand[p & 1] and writes cand[(p + 1) & 1];
 // digit p covers bits [p * c.rb, (p + 1) * c.rb).  `scatter` false: the count and scan
