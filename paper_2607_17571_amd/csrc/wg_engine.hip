@@ -40,6 +40,7 @@ constexpr uint64_t kMaxKeys = 0xFFFFFFF0ull;  // slab offsets are 32-bit
 constexpr uint32_t kMaxEvents = 1u << 16;
 constexpr uint32_t kSpec = 4;                 // speculative iterations behind each batch (<= K)
 constexpr uint32_t kAutoK = 2;                // iterations per host check of the default loop
+constexpr uint64_t kNarrowBelow = 1ull << 21;  // candidates below which the narrow tiles win
 constexpr uint64_t kDenseRowsMax = 1ull << 26;  // largest dense edge index (256 MB)
 
 double now_ms() {
@@ -76,6 +77,9 @@ struct wg_engine {
   // sort in one block (in 2 and 3 a miss halts the loop and the iteration is re-run with
   // mode 1)
   int small_mode = 1;
+  // the loop's emit and compaction use the narrow tiles (the iterations ahead are expected
+  // to have fewer than kNarrowBelow candidates)
+  bool narrow = false;
   hipStream_t capture_stream = nullptr;  // private stream the iteration graph is recorded on
   hipGraphExec_t graph_exec = nullptr;   // the recorded iteration (see iteration_graph)
   std::vector<uint8_t> graph_key;        // the kernel arguments it was recorded with
@@ -370,19 +374,20 @@ void enqueue_iteration(wg_engine* e, const Bufs<K>& b, int kind, int w, int pass
                         stage(e, WG_STAGE_JOIN_EMIT));
   } else {
     launch_join_count<K>(e->stream, e->grid, kind, e->d_ctrl, b, w, jd, stage(e, WG_STAGE_JOIN_COUNT));
-    launch_join_emit<K>(e->stream, e->grid, kind, e->d_ctrl, b, w, jd, stage(e, WG_STAGE_JOIN_EMIT));
+    launch_join_emit<K>(e->stream, e->grid, kind, e->d_ctrl, b, w, jd, stage(e, WG_STAGE_JOIN_EMIT),
+                        e->narrow);
   }
   if (e->stage_sync) stage_probe(e, &b.rec[j].C);
   if (!one_block) enqueue_sort<K>(e, b, C, std::min(e->small_mode, 2));
   const uint32_t p = (uint32_t)passes & 1u;
   if (e->unfused) {
     launch_compact<K>(e->stream, e->grid, kModeDedup, e->d_ctrl, C, b.cand[p], b.cand[p ^ 1u], b, w, jd, p,
-                      stage(e, WG_STAGE_DEDUP_DIFF));
+                      stage(e, WG_STAGE_DEDUP_DIFF), e->narrow);
     launch_compact<K>(e->stream, e->grid, kModeIter, e->d_ctrl, &e->d_ctrl->dedup_n, b.cand[p],
-                      b.cand[p ^ 1u], b, w, jd, 0, stage(e, WG_STAGE_DEDUP_DIFF));
+                      b.cand[p ^ 1u], b, w, jd, 0, stage(e, WG_STAGE_DEDUP_DIFF), e->narrow);
   } else {
     launch_compact<K>(e->stream, e->grid, kModeIter, e->d_ctrl, C, b.cand[p], b.cand[p ^ 1u], b, w, jd, 0,
-                      stage(e, WG_STAGE_DEDUP_DIFF));
+                      stage(e, WG_STAGE_DEDUP_DIFF), e->narrow);
   }
   if (e->stage_sync) stage_probe(e, &b.rec[j].N);
   launch_merge<K>(e->stream, e->grid, e->d_ctrl, b, jd, stage(e, WG_STAGE_MERGE));
@@ -397,7 +402,7 @@ struct IterGraphKey {
   SortCfg sort;
   Grid grid;
   uint64_t hash_slots;
-  int unfused, small_mode;
+  int unfused, small_mode, narrow;
 };
 
 template <typename K>
@@ -414,6 +419,7 @@ hipGraphExec_t iteration_graph(wg_engine* e, const Bufs<K>& b, int kind, int w, 
   key.hash_slots = e->hash_slots;
   key.unfused = e->unfused ? 1 : 0;
   key.small_mode = e->small_mode;
+  key.narrow = e->narrow ? 1 : 0;
   if (e->graph_exec && e->graph_key.size() == sizeof(key) &&
       std::memcmp(e->graph_key.data(), &key, sizeof(key)) == 0)
     return e->graph_exec;
@@ -732,12 +738,18 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   auto pick_small_mode = [&](uint32_t it) {
     const IterRec& x = e->h_rec[it];
     const IterRec& y = e->h_rec[it > 0 ? it - 1 : 0];
+    // narrow tiles while the candidates, grown at the last checked rate for the iterations
+    // already enqueued ahead (up to a batch and a speculative batch), stay below the bound
+    double g = it >= 2 && y.C > 0 ? (double)x.C / (double)y.C : 4.0;
+    g = std::max(g, 1.0);
+    e->narrow = (double)x.C * g * g * g * g < (double)kNarrowBelow;
     if (!small_missed && K_batch <= kAutoK && it >= 2 && calm(x.C, y.C, small_keys))
       e->small_mode = calm(x.N, y.N, kSmallJoinTuples) ? 3 : 2;
     else
       e->small_mode = x.C <= 4 * small_keys ? 1 : 0;
   };
   e->small_mode = 1;
+  e->narrow = false;  // (no size yet: the first iterations can already be large)
   enqueue_batch(K_batch, slot);
   for (;;) {
     // While the host waits on this batch, the device runs a short speculative batch

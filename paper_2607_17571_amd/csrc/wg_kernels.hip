@@ -1400,11 +1400,11 @@ __global__ __launch_bounds__(kBlock) void k_compact_local(Ctrl* ctrl, int mode, 
   if (threadIdx.x == 0) b.bcnt[blockIdx.x] = running;
 }
 
-template <typename K>
+template <typename K, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_compact_gather(Ctrl* ctrl, int mode, const uint64_t* n_ptr,
                                                            const K* __restrict__ tmp, Bufs<K> b,
                                                            uint32_t j, uint32_t side) {
-  constexpr uint32_t T = kDedupTile;
+  constexpr uint32_t T = kBlock * ITEMS;  // the tile of the local pass it follows
   __shared__ uint64_t s_pre[kScanBlocksMax];
   __shared__ uint64_t s_wave[kWavesPerBlock];
   const bool filt = (mode & kModeFilter) != 0;
@@ -1879,19 +1879,26 @@ void launch_join_hash(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const 
               j, mask);
 }
 
+template <typename K, int ITEMS>
+void join_emit_impl(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w, uint32_t j,
+                    Ev ev) {
+  if (kind == kJoinTC)
+    WG_LAUNCH((k_join_emit<K, kJoinTC, ITEMS>), g.stream, ev.start, ev.stop, s, ctrl, b, w, j, g.scan);
+  else if (kind == kJoinSG)
+    WG_LAUNCH((k_join_emit<K, kJoinSG, ITEMS>), g.stream, ev.start, ev.stop, s, ctrl, b, w, j, g.scan);
+  else if (kind == kJoinTri)
+    WG_LAUNCH((k_join_emit<K, kJoinTri, ITEMS>), g.stream, ev.start, ev.stop, s, ctrl, b, w, j, g.scan);
+  else
+    WG_LAUNCH((k_join_emit<K, kJoinSGBase, ITEMS>), g.stream, ev.start, ev.stop, s, ctrl, b, w, j, g.scan);
+}
+
 template <typename K>
 void launch_join_emit(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w,
-                      uint32_t j, Ev ev) {
-  if (kind == kJoinTC)
-    WG_LAUNCH((k_join_emit<K, kJoinTC, kEmitItems>), g.stream, ev.start, ev.stop, s, ctrl, b, w, j, g.scan);
-  else if (kind == kJoinSG)
-    WG_LAUNCH((k_join_emit<K, kJoinSG, kEmitItems>), g.stream, ev.start, ev.stop, s, ctrl, b, w, j, g.scan);
-  else if (kind == kJoinTri)
-    WG_LAUNCH((k_join_emit<K, kJoinTri, kEmitItems>), g.stream, ev.start, ev.stop, s, ctrl, b, w, j,
-              g.scan);
+                      uint32_t j, Ev ev, bool narrow) {
+  if (narrow && kind != kJoinTri && kind != kJoinSGBase)
+    join_emit_impl<K, kEmitItemsNarrow>(s, g, kind, ctrl, b, w, j, ev);
   else
-    WG_LAUNCH((k_join_emit<K, kJoinSGBase, kEmitItems>), g.stream, ev.start, ev.stop, s, ctrl, b, w, j,
-              g.scan);
+    join_emit_impl<K, kEmitItems>(s, g, kind, ctrl, b, w, j, ev);
 }
 
 template <typename K, int RB, int ITEMS>
@@ -1965,11 +1972,19 @@ void launch_sort_pass(hipStream_t s, Ctrl* ctrl, const uint64_t* n_ptr, const So
 
 template <typename K>
 void launch_compact(hipStream_t s, const Grid& g, int mode, Ctrl* ctrl, const uint64_t* n_ptr,
-                    const K* in, K* tmp, const Bufs<K>& b, int w, uint32_t j, uint32_t side, Ev ev) {
+                    const K* in, K* tmp, const Bufs<K>& b, int w, uint32_t j, uint32_t side, Ev ev, bool narrow) {
   hipEvent_t none = nullptr;
-  WG_LAUNCH((k_compact_local<K, kDedupItems>), g.scan, ev.start, none, s, ctrl, mode, n_ptr, in, tmp, b, w,
-            j);
-  WG_LAUNCH(k_compact_gather<K>, g.scan, none, ev.stop, s, ctrl, mode, n_ptr, tmp, b, j, side);
+  if (narrow) {
+    WG_LAUNCH((k_compact_local<K, kDedupItemsNarrow>), g.scan, ev.start, none, s, ctrl, mode, n_ptr, in, tmp,
+              b, w, j);
+    WG_LAUNCH((k_compact_gather<K, kDedupItemsNarrow>), g.scan, none, ev.stop, s, ctrl, mode, n_ptr, tmp, b,
+              j, side);
+  } else {
+    WG_LAUNCH((k_compact_local<K, kDedupItems>), g.scan, ev.start, none, s, ctrl, mode, n_ptr, in, tmp, b, w,
+              j);
+    WG_LAUNCH((k_compact_gather<K, kDedupItems>), g.scan, none, ev.stop, s, ctrl, mode, n_ptr, tmp, b, j,
+              side);
+  }
 }
 
 template <typename K>
@@ -2020,13 +2035,13 @@ void launch_resume(hipStream_t s, Ctrl* ctrl, uint64_t cand_cap, uint64_t full_c
   template void launch_join_count<K>(hipStream_t, const Grid&, int, Ctrl*, const Bufs<K>&, int,   \
                                      uint32_t, Ev);                                                \
   template void launch_join_emit<K>(hipStream_t, const Grid&, int, Ctrl*, const Bufs<K>&, int,    \
-                                    uint32_t, Ev);                                                 \
+                                    uint32_t, Ev, bool);                                           \
   template void launch_small_sort<K>(hipStream_t, Ctrl*, const uint64_t*, const Bufs<K>&, int, bool, Ev); \
   template void launch_small_join<K>(hipStream_t, int, Ctrl*, const Bufs<K>&, int, uint32_t, int, Ev); \
   template void launch_sort_pass<K>(hipStream_t, Ctrl*, const uint64_t*, const SortCfg&,         \
                                     const Bufs<K>&, int, bool, Ev);                                \
   template void launch_compact<K>(hipStream_t, const Grid&, int, Ctrl*, const uint64_t*, const K*, \
-                                  K*, const Bufs<K>&, int, uint32_t, uint32_t, Ev);                \
+                                  K*, const Bufs<K>&, int, uint32_t, uint32_t, Ev, bool);          \
   template void launch_merge<K>(hipStream_t, const Grid&, Ctrl*, const Bufs<K>&, uint32_t, Ev);   \
   template void launch_hash_build<K>(hipStream_t, const Grid&, Ctrl*, const Bufs<K>&, int, uint64_t, Ev); \
   template void launch_join_hash<K>(hipStream_t, const Grid&, int, Ctrl*, const Bufs<K>&, int, uint32_t, \

@@ -28,12 +28,16 @@ enum CompactMode : int {
 constexpr int kJoinItems = 8;
 constexpr int kEmitItems = 8;
 constexpr int kDedupItems = 8;
+// Narrow tiles of the emit and the compaction (half the keys per tile, half the LDS): for
+// iterations of up to a few million candidates, where more blocks in flight and shorter
+// per-tile chains win over fewer tiles.
+constexpr int kEmitItemsNarrow = 4;
+constexpr int kDedupItemsNarrow = 4;
 constexpr int kMergeItems = 8;
 constexpr uint32_t kSmallSortBytes = 32768;  // LDS of the one-block sort (8,192 / 4,096 keys)
 constexpr uint32_t kSmallJoinTuples = 1024;   // delta tuples of the one-block join (one per thread)
 constexpr int kIndexItems = 8;
 constexpr uint32_t kJoinTile = kBlock * kJoinItems;
-constexpr uint32_t kDedupTile = kBlock * kDedupItems;
 constexpr uint32_t kIndexTile = kBlock * kIndexItems;
 // Radix digit widths the sort is built for, and its grid limit (the per-block digit
 // counts of one pass take (1 << digit bits) x blocks entries).
@@ -116,7 +120,7 @@ void launch_join_count(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const
                        uint32_t j, Ev ev = Ev());
 template <typename K>
 void launch_join_emit(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w,
-                      uint32_t j, Ev ev = Ev());
+                      uint32_t j, Ev ev = Ev(), bool narrow = false);
 
 // Hash-join variant (TC and triangle joins): build the table of E (`slots` a power of
 // two), then the count and emit phases of iteration j through it.
@@ -154,7 +158,7 @@ void launch_sort_pass(hipStream_t s, Ctrl* ctrl, const uint64_t* n_ptr, const So
 template <typename K>
 void launch_compact(hipStream_t s, const Grid& g, int mode, Ctrl* ctrl, const uint64_t* n_ptr,
                     const K* in, K* tmp, const Bufs<K>& b, int w, uint32_t j, uint32_t side,
-                    Ev ev = Ev());
+                    Ev ev = Ev(), bool narrow = false);
 
 // Merge of iteration j: B' = merge(B, delta), or on a fold A' = merge(A, B) and B' = delta.
 template <typename K>
