@@ -73,6 +73,10 @@ typedef enum { WG_QUERY_TC = 0, WG_QUERY_SG = 1, WG_QUERY_TRIANGLES = 2 } wg_que
                                  it, instead of launching every kernel from the host (the
                                  default; on MI355X both take the same time, since a loop
                                  kernel's own latency, not its launch, bounds small iterations) */
+#define WG_LSD_SORT 0x80u     /* TC: sort every iteration's candidates with the LSD passes of
+                                 Section V-C, never with the segmented sort (which sorts only
+                                 each source row's run, the join having emitted the candidates
+                                 grouped by row) */
 
 /* wg_options.loop_mode */
 #define WG_LOOP_AUTO 0u     /* the default: device-resident loop checked by the host every 2

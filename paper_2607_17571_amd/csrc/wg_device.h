@@ -56,7 +56,8 @@ struct Ctrl {
   uint32_t max_iter;     // 0: unlimited
   uint32_t done;         // the last delta was empty: fixpoint reached
   uint32_t overflow;     // bit 0 candidates, bit 1 Full, bit 2 delta, bit 3 a one-block
-                         // sort enqueued alone found more keys than it holds
+                         // sort enqueued alone found more keys than it holds, bit 4 a
+                         // row of the segmented sort is longer than one block holds
   uint32_t limit_hit;    // max_iter reached with a non-empty delta
   uint32_t maxid;        // largest vertex id of the input
   uint32_t force_overflow_at;  // test hook: report a candidate overflow at this iteration

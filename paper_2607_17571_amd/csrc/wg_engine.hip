@@ -41,6 +41,7 @@ constexpr uint32_t kMaxEvents = 1u << 16;
 constexpr uint32_t kSpec = 4;                 // speculative iterations behind each batch (<= K)
 constexpr uint32_t kAutoK = 2;                // iterations per host check of the default loop
 constexpr uint64_t kNarrowBelow = 1ull << 21;  // candidates below which the narrow tiles win
+constexpr uint64_t kSegBelow = 1ull << 22;     // ... and the segmented sort beats the LSD passes
 constexpr uint64_t kDenseRowsMax = 1ull << 26;  // largest dense edge index (256 MB)
 
 double now_ms() {
@@ -77,6 +78,9 @@ struct wg_engine {
   // sort in one block (in 2 and 3 a miss halts the loop and the iteration is re-run with
   // mode 1)
   int small_mode = 1;
+  // TC: the loop sorts each row's run of the grouped candidates (segmented sort) instead
+  // of the LSD passes
+  bool seg_sort = false;
   // the loop's emit and compaction use the narrow tiles (the iterations ahead are expected
   // to have fewer than kNarrowBelow candidates)
   bool narrow = false;
@@ -378,7 +382,11 @@ void enqueue_iteration(wg_engine* e, const Bufs<K>& b, int kind, int w, int pass
                         e->narrow);
   }
   if (e->stage_sync) stage_probe(e, &b.rec[j].C);
-  if (!one_block) enqueue_sort<K>(e, b, C, std::min(e->small_mode, 2));
+  const bool seg = e->seg_sort && kind == kJoinTC && !e->hash_slots && e->small_mode != 2;
+  if (!one_block) {
+    if (seg) launch_seg_sort<K>(e->stream, e->grid, e->d_ctrl, C, b, w, passes, stage(e, WG_STAGE_RADIX_PASS));
+    else enqueue_sort<K>(e, b, C, std::min(e->small_mode, 2));
+  }
   const uint32_t p = (uint32_t)passes & 1u;
   if (e->unfused) {
     launch_compact<K>(e->stream, e->grid, kModeDedup, e->d_ctrl, C, b.cand[p], b.cand[p ^ 1u], b, w, jd, p,
@@ -402,7 +410,7 @@ struct IterGraphKey {
   SortCfg sort;
   Grid grid;
   uint64_t hash_slots;
-  int unfused, small_mode, narrow;
+  int unfused, small_mode, narrow, seg_sort;
 };
 
 template <typename K>
@@ -420,6 +428,7 @@ hipGraphExec_t iteration_graph(wg_engine* e, const Bufs<K>& b, int kind, int w, 
   key.unfused = e->unfused ? 1 : 0;
   key.small_mode = e->small_mode;
   key.narrow = e->narrow ? 1 : 0;
+  key.seg_sort = e->seg_sort ? 1 : 0;
   if (e->graph_exec && e->graph_key.size() == sizeof(key) &&
       std::memcmp(e->graph_key.data(), &key, sizeof(key)) == 0)
     return e->graph_exec;
@@ -732,6 +741,7 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   const uint64_t small_keys = kSmallSortBytes / sizeof(K);
   bool small_missed = false;
   // within a quarter of a limit, or half of it and not growing
+  bool seg_allowed = query == WG_QUERY_TC && !(o.flags & WG_LSD_SORT);
   auto calm = [&](uint64_t now, uint64_t before, uint64_t limit) {
     return 4 * now <= limit || (2 * now <= limit && now <= before);
   };
@@ -742,7 +752,9 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
     // already enqueued ahead (up to a batch and a speculative batch), stay below the bound
     double g = it >= 2 && y.C > 0 ? (double)x.C / (double)y.C : 4.0;
     g = std::max(g, 1.0);
-    e->narrow = (double)x.C * g * g * g * g < (double)kNarrowBelow;
+    const double ahead = (double)x.C * g * g * g * g;
+    e->narrow = ahead < (double)kNarrowBelow;
+    e->seg_sort = seg_allowed && ahead < (double)kSegBelow;
     if (!small_missed && K_batch <= kAutoK && it >= 2 && calm(x.C, y.C, small_keys))
       e->small_mode = calm(x.N, y.N, kSmallJoinTuples) ? 3 : 2;
     else
@@ -750,6 +762,11 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   };
   e->small_mode = 1;
   e->narrow = false;  // (no size yet: the first iterations can already be large)
+  // TC: the segmented sort while the iterations ahead are expected below kSegBelow
+  // candidates (larger ones sort faster through the LSD passes), until a row's run
+  // outgrows one block (then the LSD passes for the rest of the solve); the first batch,
+  // sizes unknown, takes the LSD passes
+  e->seg_sort = false;
   enqueue_batch(K_batch, slot);
   for (;;) {
     // While the host waits on this batch, the device runs a short speculative batch
@@ -770,6 +787,7 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
         small_missed = true;
         e->small_mode = 1;
       }
+      if (r.c.overflow & 16u) seg_allowed = e->seg_sort = false;
       grow_and_resume(e, r.c, hooked);
       if (st) st->resumes++;
       next_j = r.c.iter + 1;
@@ -914,7 +932,7 @@ wg_status solve(wg_engine* e, int query, uint32_t num, const uint64_t* d_offsets
   }
   if (o.loop_mode > WG_LOOP_STAGE ||
       (o.flags & ~(WG_SG_IRREFLEXIVE | WG_STAGE_TIMING | WG_NO_SPECULATION | WG_JOIN_HASH | WG_UNFUSED_DEDUP |
-                   WG_SPARSE_INDEX | WG_ITER_GRAPH))) {
+                   WG_SPARSE_INDEX | WG_ITER_GRAPH | WG_LSD_SORT))) {
     e->err = "unknown loop_mode or flag";
     return WG_ERR_INVALID_ARG;
   }

@@ -837,6 +837,72 @@ __global__ __launch_bounds__(kSmallSortThreads) void k_small_join(Ctrl* ctrl, Bu
 }
 
 // ---------------------------------------------------------------------------
+// Segmented sort for the TC join.  The emit writes each delta tuple's slab in delta
+// order and delta is sorted, so the candidates already come grouped by row (key >> w:
+// instance and src) in ascending order; only each row's run needs sorting (by dst).  Block
+// b takes tiles of kSegTile positions and owns the runs that start in its tile: it finds
+// the first run start in the tile, the end of the run holding the tile's last position
+// (the first later position with a larger row, by a wave-parallel search), loads that
+// range into LDS, sorts it with the bitonic network above and writes it to `out`.  Runs
+// partition the array, so every key is written exactly once, and sorting permutes keys
+// only inside a run, so rows at every position stay put: in place (out == in) the
+// neighbours' searches still read correct rows.  A range beyond one block's LDS sets
+// overflow bit 4 (halting the loop; the host re-runs the iteration with the LSD passes).
+// ---------------------------------------------------------------------------
+constexpr uint32_t kSegTile = 2048;
+
+template <typename K>
+__global__ __launch_bounds__(kSmallSortThreads) void k_seg_sort(Ctrl* ctrl, const uint64_t* n_ptr,
+                                                                const K* in, K* out, int w) {
+  constexpr uint32_t TH = kSmallSortThreads;
+  constexpr uint32_t CAP = kSmallSortBytes / sizeof(K);
+  static_assert(CAP >= 2 * kSegTile, "a tile and a run reaching past it fit the LDS");
+  __shared__ K s[CAP];
+  __shared__ uint32_t s_first;
+  __shared__ uint64_t s_end;
+  if (halted(ctrl)) return;
+  const uint64_t n = *n_ptr;
+  const uint64_t ntiles = (n + kSegTile - 1) / kSegTile;
+  const uint32_t t = threadIdx.x;
+  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const uint64_t p0 = tile * kSegTile;
+    const uint64_t p1 = min<uint64_t>(p0 + kSegTile, n);
+    if (t == 0) s_first = kSegTile;
+    __syncthreads();
+    // run starts in the tile: positions whose row differs from the previous position's
+    for (uint32_t q = t; q < (uint32_t)(p1 - p0); q += TH) {
+      const uint64_t p = p0 + q;
+      if (p == 0 || (in[p] >> w) != (in[p - 1] >> w)) atomicMin(&s_first, q);
+    }
+    __syncthreads();
+    const uint32_t f = s_first;
+    if (f < kSegTile && t < (uint32_t)kWave) {
+      // end of the run holding p1 - 1: the first position with a larger row, searched up
+      // to what one block holds
+      const uint64_t s0 = p0 + f;
+      const K last_row = in[p1 - 1] >> w;
+      const uint64_t lim = min<uint64_t>(n, s0 + CAP);
+      const uint64_t e = wave_partition(p1, lim, [&](uint64_t i) { return (in[i] >> w) <= last_row; });
+      if (t == 0) s_end = (e == lim && lim < n && (in[lim] >> w) == last_row) ? ~0ull : e;
+    }
+    __syncthreads();
+    if (f == kSegTile) continue;  // no run starts here (uniform; s_first is rewritten after
+                                  // the barrier that opens the next tile)
+    const uint64_t s0 = p0 + f;
+    const uint64_t e = s_end;
+    if (e == ~0ull) {
+      if (t == 0) atomicOr(&ctrl->overflow, 16u);
+      return;
+    }
+    const uint32_t len = (uint32_t)(e - s0);
+    for (uint32_t q = t; q < len; q += TH) s[q] = in[s0 + q];
+    __syncthreads();
+    block_bitonic_sort<K>(s, len, out + s0);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // LSD radix sort (Section V-C): RB bits per pass, dst field first, every pass stable.
 //
 // A pass is three launches: count (block b counts the digits of a static contiguous
@@ -1804,6 +1870,16 @@ __global__ void k_resume(Ctrl* ctrl, uint64_t cand_cap, uint64_t full_cap, uint3
       hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, s, __VA_ARGS__);                   \
   } while (0)
 
+// The same for the one-block kernels of kSmallSortThreads threads.
+#define WG_LAUNCH_WIDE(kernel, grid, start, stop, s, ...)                                        \
+  do {                                                                                           \
+    if ((start) || (stop))                                                                       \
+      hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(kSmallSortThreads), 0, s, start, stop, 0,    \
+                            __VA_ARGS__);                                                        \
+    else                                                                                         \
+      hipLaunchKernelGGL(kernel, dim3(grid), dim3(kSmallSortThreads), 0, s, __VA_ARGS__);        \
+  } while (0)
+
 static inline int stream_blocks(const Grid& g, uint64_t n) {
   const uint64_t need = (n + kBlock - 1) / kBlock;
   return (int)(need < (uint64_t)g.stream ? (need ? need : 1) : (uint64_t)g.stream);
@@ -1915,6 +1991,14 @@ void sort_pass_impl(hipStream_t s, Ctrl* ctrl, const uint64_t* n_ptr, int G, con
     WG_LAUNCH((k_radix_scatter<K, RB, ITEMS>), G, ev.start, ev.stop, s, ctrl, n_ptr, in, out, p * RB,
               b.rcnt, b.rtot);
   }
+}
+
+template <typename K>
+void launch_seg_sort(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint64_t* n_ptr, const Bufs<K>& b, int w,
+                     int passes, Ev ev) {
+  const int G = std::max(1, g.scan / 2);
+  WG_LAUNCH_WIDE((k_seg_sort<K>), G, ev.start, ev.stop, s, ctrl, n_ptr, (const K*)b.cand[0], b.cand[passes & 1],
+                 w);
 }
 
 template <typename K>
@@ -2038,6 +2122,7 @@ void launch_resume(hipStream_t s, Ctrl* ctrl, uint64_t cand_cap, uint64_t full_c
                                     uint32_t, Ev, bool);                                           \
   template void launch_small_sort<K>(hipStream_t, Ctrl*, const uint64_t*, const Bufs<K>&, int, bool, Ev); \
   template void launch_small_join<K>(hipStream_t, int, Ctrl*, const Bufs<K>&, int, uint32_t, int, Ev); \
+  template void launch_seg_sort<K>(hipStream_t, const Grid&, Ctrl*, const uint64_t*, const Bufs<K>&, int, int, Ev); \
   template void launch_sort_pass<K>(hipStream_t, Ctrl*, const uint64_t*, const SortCfg&,         \
                                     const Bufs<K>&, int, bool, Ev);                                \
   template void launch_compact<K>(hipStream_t, const Grid&, int, Ctrl*, const uint64_t*, const K*, \

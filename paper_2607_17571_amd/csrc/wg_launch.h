@@ -145,6 +145,13 @@ template <typename K>
 void launch_small_join(hipStream_t s, int kind, Ctrl* ctrl, const Bufs<K>& b, int w, uint32_t j, int passes,
                        Ev ev = Ev());
 
+// Segmented sort of the TC join's *n_ptr candidates (grouped by row, each row's run
+// unsorted) from cand[0] into cand[passes & 1]: each run sorted in LDS by one block; a run
+// longer than a block holds sets overflow bit 4.
+template <typename K>
+void launch_seg_sort(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint64_t* n_ptr, const Bufs<K>& b, int w,
+                     int passes, Ev ev = Ev());
+
 // One LSD pass over *n_ptr keys: pass p reads cand[p & 1] and writes cand[(p + 1) & 1];
 // digit p covers bits [p * c.rb, (p + 1) * c.rb).  `scatter` false: the count and scan
 // launches; true: the scatter launch.  sort_passes(key bits, c.rb) passes sort the keys,

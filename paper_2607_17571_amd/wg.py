@@ -33,6 +33,7 @@ WG_JOIN_HASH = 0x8
 WG_UNFUSED_DEDUP = 0x10
 WG_SPARSE_INDEX = 0x20
 WG_ITER_GRAPH = 0x40
+WG_LSD_SORT = 0x80
 
 WG_QUERY_TC = 0
 WG_QUERY_SG = 1

@@ -352,6 +352,42 @@ def test_one_block_sort_miss_reruns_iteration(engine):
         assert_same(s, d, st, ref)
 
 
+@pytest.mark.parametrize("graph", ["er", "grid", "rmat", "chain", "wide_ids"])
+def test_segmented_sort_matches_lsd(engine, graph):
+    """TC sorts each row's run of the grouped join output (segmented sort) unless
+    WG_LSD_SORT asks for the LSD passes; both give the closure."""
+    if graph == "er":
+        src, dst = inputs.erdos_renyi(3000, 4500, seed=21)
+    elif graph == "grid":
+        src, dst = inputs.grid_dag(30)
+    elif graph == "rmat":
+        src, dst = inputs.rmat(11, 1800, *inputs.RMAT_ABCD, seed=9)
+    elif graph == "chain":
+        src, dst = inputs.chain(700)
+    else:
+        src, dst = inputs.scatter_ids(*inputs.erdos_renyi(2000, 3000, seed=22), 22, seed=23)
+    ref = oracle.tc(src, dst)
+    for flags in (0, wg.WG_LSD_SORT, wg.WG_NO_SPECULATION, wg.WG_ITER_GRAPH):
+        s, d, st = run(engine, "tc", src, dst, wg.make_options(flags=flags))
+        assert_same(s, d, st, ref)
+
+
+def test_segmented_sort_long_run_reruns_iteration(engine):
+    """Binary tree of depth 14: in iteration j the root's row holds the 2^(j+1) nodes at
+    depth j + 1, so iteration 13 brings a run of 16,384 candidates, more than one block of
+    the segmented sort holds (8,192 32-bit keys): that iteration halts and is re-run with
+    the LSD passes (the earlier ones, past the first batch, use the segmented sort)."""
+    src, dst = inputs.binary_tree(14)
+    ref = oracle.tc(src, dst)
+    for opts in (None, wg.make_options(loop_mode=wg.WG_LOOP_HOST, flags=wg.WG_NO_SPECULATION)):
+        s, d, st = run(engine, "tc", src, dst, opts)
+        assert_same(s, d, st, ref)
+        assert st["resumes"] >= 1
+    s, d, st = run(engine, "tc", src, dst, wg.make_options(flags=wg.WG_LSD_SORT))
+    assert_same(s, d, st, ref)
+    assert st["resumes"] == 0
+
+
 def test_growth_from_small_buffers(engine):
     """A fresh engine starts with small buffers; a large closure must grow and resume."""
     eng = wg.Engine(0)
