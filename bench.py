@@ -293,7 +293,7 @@ ABLATION_DEFAULTS = {
     "join": "tc_rmat_s15,tc_rmat_s16",
     "triangles": "tri_rmat_s14,tri_rmat_s16",
     "sync": "tc_er_2000,sg_er_500k,tc_grid_100",
-    "engineering": "tc_rmat_s15,sg_er_500k,tc_er_2000",
+    "engineering": "tc_rmat_s15,sg_er_500k,tc_er_2000,tc_grid_100",
 }
 TRIANGLE_GRAPHS = {  # R-MAT stand-ins for SNAP graphs with hubs of out-degree in the thousands
     "tri_rmat_s14": (14, 8 << 14), "tri_rmat_s16": (16, 8 << 16), "tri_rmat_s17": (17, 8 << 17),
@@ -442,6 +442,7 @@ def run_ablation(args):
             variants = {
                 "default": {},
                 "unfused_dedup_diff": dict(flags=wg.WG_UNFUSED_DEDUP),
+                "lsd_sort_only": dict(flags=wg.WG_LSD_SORT),
                 "digits_8_exact_width": dict(radix_digit_bits=8),
                 "digits_8_width_16_24_32": dict(radix_digit_bits=8, radix_field_bits=paper_w),
                 "digits_8_fixed_32bit_fields": dict(radix_digit_bits=8, radix_field_bits=32),
