@@ -44,7 +44,7 @@ STAGE_KERNELS = {
     "join_count": "k_join_count", "join_emit": "k_join_emit",
     "radix_hist": "k_radix_count + k_radix_scan", "radix_pass": "k_radix_scatter",
     "dedup_diff": "k_compact_local + k_compact_gather", "merge": "k_merge",
-    "prepare": "k_max_id, k_pack, k_index_*, k_unpack",
+    "prepare": "k_max_id, k_pack, k_index_*, k_unpack", "seg_sort": "k_seg_sort",
 }
 WORKLOAD_TEXT = {
     "tc_rmat_s15": "TC, R-MAT scale 15 (n=32,768, m=29,491, a,b,c,d=0.57,0.19,0.19,0.05, seed 2); "
@@ -73,9 +73,10 @@ def kernel_source_digest() -> str:
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic(kernel: str, workload: str):
+def measured_traffic(kernel: str, workload: str, digit_bits: int, tile_items: int):
     """Calibrated HBM bytes per launch of `kernel` on `workload` from the rocprofv3 FETCH_SIZE /
-    WRITE_SIZE runs stored under profiles/ (null when none matches the current kernels)."""
+    WRITE_SIZE runs stored under profiles/ (null when none matches the current kernels and
+    sort configuration)."""
     prof = os.path.join(ROOT, "profiles")
     if not os.path.isdir(prof):
         return None
@@ -86,7 +87,8 @@ def measured_traffic(kernel: str, workload: str):
         with open(os.path.join(prof, name)) as f:
             rec = json.load(f)
         if (rec.get("kernel") == kernel and rec.get("workload") == workload
-                and rec.get("kernel_source_sha256") == digest):
+                and rec.get("kernel_source_sha256") == digest
+                and rec.get("digit_bits") == digit_bits and rec.get("tile_items") == tile_items):
             return rec
     return None
 
@@ -603,7 +605,9 @@ def main():
         if value is None:
             ms_per_step, value = inst_ms, inst_tuples / inst_elapsed
         achieved = nbytes / (ms / 1e3) / 1e9 if ms > 0 else 0.0
-        tr = measured_traffic(STAGE_KERNELS[dom], args.workload)
+        tile = args.tile_items or (extra["autotune"]["best"]["tile_items"] if "autotune" in extra
+                                   else eng.sort_config(st["key_bytes"])["tile_items"])
+        tr = measured_traffic(STAGE_KERNELS[dom], args.workload, st["digit_bits"], tile)
         roofline = {"bound": "hbm", "kernel": STAGE_KERNELS[dom], "stage": dom,
                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),

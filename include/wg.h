@@ -126,7 +126,8 @@ enum {
   WG_STAGE_DEDUP_DIFF = 4, /* fused dedup + set difference (Section IV-B) */
   WG_STAGE_MERGE = 5,      /* disjoint merge-path merge (Section IV-C) */
   WG_STAGE_PREPARE = 6,    /* max-id scan, packing, edge index, result unpack */
-  WG_NUM_STAGES = 7
+  WG_STAGE_SEG_SORT = 7,   /* TC: the segmented sort of a join's row-grouped candidates */
+  WG_NUM_STAGES = 8
 };
 
 typedef struct {

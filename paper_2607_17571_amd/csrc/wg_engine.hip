@@ -42,6 +42,7 @@ constexpr uint32_t kSpec = 4;                 // speculative iterations behind e
 constexpr uint32_t kAutoK = 2;                // iterations per host check of the default loop
 constexpr uint64_t kNarrowBelow = 1ull << 21;  // candidates below which the narrow tiles win
 constexpr uint64_t kSegBelow = 1ull << 22;     // ... and the segmented sort beats the LSD passes
+enum : uint8_t { kSortLsd = 0, kSortSmall = 1, kSortOneBlock = 2, kSortSegmented = 3 };
 constexpr uint64_t kDenseRowsMax = 1ull << 26;  // largest dense edge index (256 MB)
 
 double now_ms() {
@@ -81,6 +82,10 @@ struct wg_engine {
   // TC: the loop sorts each row's run of the grouped candidates (segmented sort) instead
   // of the LSD passes
   bool seg_sort = false;
+  // how each iteration of the solve sorted its candidates (the method of its last
+  // enqueue): kSortLsd, kSortSmall (one-block sort alone), kSortOneBlock (join and sort in
+  // one block), kSortSegmented
+  std::vector<uint8_t> iter_sort;
   // the loop's emit and compaction use the narrow tiles (the iterations ahead are expected
   // to have fewer than kNarrowBelow candidates)
   bool narrow = false;
@@ -362,6 +367,14 @@ void stage_probe(wg_engine* e, const uint64_t* d_size) {
   sync_stream(e);
 }
 
+// How the next enqueued iteration sorts its candidates (see iter_sort).
+uint8_t sort_method(const wg_engine* e, int kind) {
+  if (e->small_mode == 3 && !e->hash_slots && !e->stage_sync) return kSortOneBlock;
+  if (e->small_mode == 2) return kSortSmall;
+  if (e->seg_sort && kind == kJoinTC && !e->hash_slots) return kSortSegmented;
+  return kSortLsd;
+}
+
 // One semi-naive iteration.  The kernels take the iteration number from the device
 // (kIterDevice), so this launch sequence is the same for every iteration; `j` is the
 // host's count, used only by the per-stage probes.
@@ -369,7 +382,8 @@ template <typename K>
 void enqueue_iteration(wg_engine* e, const Bufs<K>& b, int kind, int w, int passes, uint32_t j) {
   const uint32_t jd = kIterDevice;
   const uint64_t* C = &e->d_ctrl->cand_n;
-  const bool one_block = e->small_mode == 3 && !e->hash_slots && !e->stage_sync;
+  const uint8_t method = sort_method(e, kind);
+  const bool one_block = method == kSortOneBlock;
   if (one_block) {
     launch_small_join<K>(e->stream, kind, e->d_ctrl, b, w, jd, passes, stage(e, WG_STAGE_JOIN_EMIT));
   } else if (e->hash_slots) {
@@ -382,11 +396,10 @@ void enqueue_iteration(wg_engine* e, const Bufs<K>& b, int kind, int w, int pass
                         e->narrow);
   }
   if (e->stage_sync) stage_probe(e, &b.rec[j].C);
-  const bool seg = e->seg_sort && kind == kJoinTC && !e->hash_slots && e->small_mode != 2;
-  if (!one_block) {
-    if (seg) launch_seg_sort<K>(e->stream, e->grid, e->d_ctrl, C, b, w, passes, stage(e, WG_STAGE_RADIX_PASS));
-    else enqueue_sort<K>(e, b, C, std::min(e->small_mode, 2));
-  }
+  if (method == kSortSegmented)
+    launch_seg_sort<K>(e->stream, e->grid, e->d_ctrl, C, b, w, passes, stage(e, WG_STAGE_SEG_SORT));
+  else if (!one_block)
+    enqueue_sort<K>(e, b, C, std::min(e->small_mode, 2));
   const uint32_t p = (uint32_t)passes & 1u;
   if (e->unfused) {
     launch_compact<K>(e->stream, e->grid, kModeDedup, e->d_ctrl, C, b.cand[p], b.cand[p ^ 1u], b, w, jd, p,
@@ -539,7 +552,8 @@ void add_bytes(wg_stats* st, int k, double b) { st->stage_bytes[k] += (uint64_t)
 //                                        A and B (otherwise the result stays two runs,
 //                                        merged by wg_result_copy)
 void bytes_model(wg_stats* st, int query, uint32_t kb, int passes, uint64_t m,
-                 const std::vector<IterRec>& rec, uint64_t mu, bool final_union) {
+                 const std::vector<IterRec>& rec, const std::vector<uint8_t>& how, uint64_t mu,
+                 bool final_union) {
   // prepare: max scan (8m), pack (8m read + kb*m write), edge index (read E, write U/R/Edst)
   add_bytes(st, WG_STAGE_PREPARE, 8.0 * m + (8.0 + kb) * m + (kb + 12.0) * mu);
   add_bytes(st, WG_STAGE_RADIX_HIST, 1.0 * kb * m * passes);
@@ -556,10 +570,22 @@ void bytes_model(wg_stats* st, int query, uint32_t kb, int passes, uint64_t m,
   for (size_t i = 1; i < rec.size(); ++i) {
     const double D = (double)rec[i - 1].N, c = (double)rec[i].C, n = (double)rec[i].N;
     const double F = (double)rec[i - 1].F;
-    add_bytes(st, WG_STAGE_JOIN_COUNT, D * (kb + 4.0));
-    add_bytes(st, WG_STAGE_JOIN_EMIT, D * (kb + 4.0) + c * (edst + kb));
-    add_bytes(st, WG_STAGE_RADIX_HIST, 1.0 * c * kb * passes);
-    add_bytes(st, WG_STAGE_RADIX_PASS, 2.0 * c * kb * passes);
+    const uint8_t sorted_by = i < how.size() ? how[i] : kSortLsd;
+    if (sorted_by == kSortOneBlock) {
+      // one kernel (timed as the emit): read delta and E.dst, write the sorted candidates
+      add_bytes(st, WG_STAGE_JOIN_EMIT, D * kb + c * (edst + kb));
+    } else {
+      add_bytes(st, WG_STAGE_JOIN_COUNT, D * (kb + 4.0));
+      add_bytes(st, WG_STAGE_JOIN_EMIT, D * (kb + 4.0) + c * (edst + kb));
+      if (sorted_by == kSortSegmented) {
+        add_bytes(st, WG_STAGE_SEG_SORT, 2.0 * c * kb);
+      } else if (sorted_by == kSortSmall) {
+        add_bytes(st, WG_STAGE_RADIX_HIST, 2.0 * c * kb);
+      } else {
+        add_bytes(st, WG_STAGE_RADIX_HIST, 1.0 * c * kb * passes);
+        add_bytes(st, WG_STAGE_RADIX_PASS, 2.0 * c * kb * passes);
+      }
+    }
     add_bytes(st, WG_STAGE_DEDUP_DIFF, (c + n) * kb);
     // the merge: delta into run B, or on a fold B into A plus the delta as the new B
     const double FA = (double)rec[i - 1].FA, FB = F - FA;
@@ -715,6 +741,8 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   auto enqueue_iters = [&](uint32_t k) {
     ensure_records(e, (uint64_t)next_j + k + 2);
     b = make_bufs<K>(e);
+    if (e->iter_sort.size() < (size_t)next_j + k + 1) e->iter_sort.resize((size_t)next_j + k + 1 + 64);
+    for (uint32_t i = 0; i < k; ++i) e->iter_sort[next_j + i] = sort_method(e, kind);
     if (graphs && k > 0) {
       hipGraphExec_t x = iteration_graph<K>(e, b, kind, w, passes);
       for (uint32_t i = 0; i < k; ++i) {
@@ -855,7 +883,7 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
     if (st->delta_sizes)
       for (uint64_t i = 0; i < std::min<uint64_t>(st->delta_sizes_cap, recs.size()); ++i)
         st->delta_sizes[i] = recs[i].N;
-    bytes_model(st, query, sizeof(K), passes, m, recs, r.c.m_unique, filter);
+    bytes_model(st, query, sizeof(K), passes, m, recs, e->iter_sort, r.c.m_unique, filter);
     collect_timing(e, st);
   }
   return WG_OK;

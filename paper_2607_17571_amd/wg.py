@@ -44,7 +44,8 @@ WG_LOOP_BATCHED = 1
 WG_LOOP_HOST = 2
 WG_LOOP_STAGE = 3
 
-STAGES = ["join_count", "join_emit", "radix_hist", "radix_pass", "dedup_diff", "merge", "prepare"]
+STAGES = ["join_count", "join_emit", "radix_hist", "radix_pass", "dedup_diff", "merge", "prepare",
+          "seg_sort"]
 WG_NUM_STAGES = len(STAGES)
 
 
