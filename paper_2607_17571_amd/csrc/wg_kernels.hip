@@ -849,7 +849,9 @@ __global__ __launch_bounds__(kSmallSortThreads) void k_small_join(Ctrl* ctrl, Bu
 // neighbours' searches still read correct rows.  A range beyond one block's LDS sets
 // overflow bit 4 (halting the loop; the host re-runs the iteration with the LSD passes).
 // ---------------------------------------------------------------------------
-constexpr uint32_t kSegTile = 2048;
+// (a tile a little under 2,048 keeps most ranges -- tile plus the tail of its last run --
+// within a 2,048-key network: 2 keys per thread)
+constexpr uint32_t kSegTile = 1792;
 
 template <typename K>
 __global__ __launch_bounds__(kSmallSortThreads) void k_seg_sort(Ctrl* ctrl, const uint64_t* n_ptr,
