@@ -115,6 +115,10 @@ def parse():
     p.add_argument("--requests", type=int, default=120, help="served_mix: number of requests")
     p.add_argument("--slots", type=int, default=4, help="served_mix: concurrent solves")
     p.add_argument("--load", type=float, default=0.7, help="served_mix: offered load / capacity")
+    p.add_argument("--kernel-sweep", action="store_true",
+                   help="sort and merge kernels alone on 2^20..2^28 synthetic keys")
+    p.add_argument("--sweep-min-log2", type=int, default=20)
+    p.add_argument("--sweep-max-log2", type=int, default=28)
     p.add_argument("--ablation", choices=["join", "triangles", "sync", "engineering"], default=None,
                    help="time the variants of one design choice instead of the headline line")
     p.add_argument("--ablation-workloads", default=None,
@@ -171,6 +175,56 @@ def served_cpu_baseline(reqs):
     return {"value": tuples / dt, "unit": "tuples/s", "cores": 1, "kind": "oracle",
             "sample": f"requests 0..{done - 1} of the served mix ({tuples} tuples) solved one by "
                       f"one in {dt:.2f} s, single-threaded numpy"}
+
+
+def run_kernel_sweep(args):
+    """Single stages on synthetic keys of 2^20..2^28 elements (uniform random 30-bit keys in
+    32-bit words, 48-bit keys in 64-bit words): the LSD sort's count (+ scan) and scatter
+    kinds, and the merge of two sorted halves, each as algorithmic bytes over its kernel
+    time (HIP events on the launches), best of 3 runs."""
+    import torch
+
+    from paper_2607_17571_amd import wg
+
+    eng = wg.Engine(0)
+    timing = wg.make_options(flags=wg.WG_STAGE_TIMING)
+    rows = []
+    for kb, bits in ((4, 30), (8, 48)):
+        dt = torch.int32 if kb == 4 else torch.int64
+        for lg in range(args.sweep_min_log2, args.sweep_max_log2 + 1):
+            n = 1 << lg
+            g = torch.Generator(device="cuda").manual_seed(lg * 10 + kb)
+            src = torch.randint(0, 1 << bits, (n,), generator=g, device="cuda", dtype=torch.int64).to(dt)
+            keys = torch.empty_like(src)
+            tmp = torch.empty_like(src)
+            best = {}
+            for _ in range(3):
+                keys.copy_(src)
+                st = eng.sort_keys(keys, tmp, bits, timing)
+                for k in ("radix_hist", "radix_pass"):
+                    gbs = st["stage_bytes"][k] / (st["stage_ms"][k] * 1e6)
+                    best[k] = max(best.get(k, 0.0), gbs)
+            passes = st["sort_passes"]
+            a, _ = torch.sort(src[: n // 2])
+            b, _ = torch.sort(src[n // 2:])
+            out = torch.empty_like(src)
+            mg = 0.0
+            for _ in range(3):
+                st = eng.merge_keys(a, b, out, timing)
+                mg = max(mg, st["stage_bytes"]["merge"] / (st["stage_ms"]["merge"] * 1e6))
+            row = {"key_bytes": kb, "key_bits": bits, "n": n, "passes": passes,
+                   "count_gbs": round(best["radix_hist"], 1),
+                   "count_frac": round(best["radix_hist"] / HBM_PEAK_GBS, 4),
+                   "scatter_gbs": round(best["radix_pass"], 1),
+                   "scatter_frac": round(best["radix_pass"] / HBM_PEAK_GBS, 4),
+                   "merge_gbs": round(mg, 1), "merge_frac": round(mg / HBM_PEAK_GBS, 4)}
+            rows.append(row)
+            _progress(f"sweep {kb * 8}-bit n=2^{lg}: count {row['count_frac']}, scatter "
+                      f"{row['scatter_frac']}, merge {row['merge_frac']} of 8 TB/s")
+            del src, keys, tmp, a, b, out
+    cfg = {"4": eng.sort_config(4), "8": eng.sort_config(8)}
+    eng.close()
+    print(json.dumps({"kernel_sweep": rows, "peak_gbs": HBM_PEAK_GBS, "sort_config": cfg}), flush=True)
 
 
 def run_served(args):
@@ -303,7 +357,7 @@ TRIANGLE_GRAPHS = {  # R-MAT stand-ins for SNAP graphs with hubs of out-degree i
 
 
 def _progress(msg):
-    print(f"[ablation] {msg}", file=sys.stderr, flush=True)
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def _time_variant(torch, fn, steps, warmup):
@@ -504,6 +558,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": n, "copies": 10}), flush=True)
+        return
+    if args.kernel_sweep:
+        run_kernel_sweep(args)
         return
     if args.ablation:
         run_ablation(args)

@@ -209,6 +209,32 @@ wg_status wg_triangles(wg_engine* engine, const uint32_t* d_src, const uint32_t*
                        const wg_options* options, void* stream, uint64_t* count_out,
                        wg_stats* stats);
 
+/* Kernel-level entry points: single stages of the hot path on caller arrays, for
+ * measuring them apart from a fixpoint (sizes and key widths of the caller's choosing).
+ *
+ * wg_sort_keys (Section V-C): sorts the n keys of d_keys (device; key_bytes 4 or 8 per
+ * key, every key below 2^key_bits) ascending, in place, with the LSD passes -- count,
+ * scan and scatter launches per pass of the engine's sort configuration for that key
+ * width (wg_get_sort_config), ceil(key_bits / digit bits) passes.  d_tmp (device, n keys,
+ * caller-owned) is the ping-pong buffer; with an odd pass count the result is copied back
+ * into d_keys.  Neither the one-block sort nor the segmented sort is used.
+ *
+ * wg_merge_keys (Section IV-C): d_out[0, na + nb) = the merge of the ascending runs
+ * d_a[0, na) and d_b[0, nb) (device, key_bytes per key; d_out caller-owned and disjoint
+ * from both; on equal keys A's come first).
+ *
+ * Both run on `stream` (NULL: the default stream) and return after enqueueing.  options
+ * (nullable): only WG_STAGE_TIMING is read; with it, stats (nullable) receives the summed
+ * kernel times, launches and algorithmic bytes per kernel kind (radix count, radix
+ * scatter; merge), after a synchronisation.  The engine's current result stays valid.
+ * WG_ERR_INVALID_ARG: a null array with n > 0, key_bytes not 4 or 8, key_bits outside
+ * 1..8*key_bytes, more than 2^32 - 16 keys. */
+wg_status wg_sort_keys(wg_engine* engine, void* d_keys, void* d_tmp, uint64_t n, uint32_t key_bytes,
+                       uint32_t key_bits, const wg_options* options, void* stream, wg_stats* stats);
+wg_status wg_merge_keys(wg_engine* engine, const void* d_a, uint64_t na, const void* d_b, uint64_t nb,
+                        void* d_out, uint32_t key_bytes, const wg_options* options, void* stream,
+                        wg_stats* stats);
+
 /* Number of tuples in the result (for a batch: over all instances). */
 uint64_t wg_result_size(const wg_result* result);
 

@@ -1156,6 +1156,73 @@ wg_status result_detach(const wg_result* r, hipStream_t s, std::function<void(ui
 
 }  // namespace wg
 
+// Helpers of the kernel-level entry points (single stages on caller arrays).
+namespace {
+
+// Shared prologue: options, stats, device and stream; the previous solve's queued work
+// ordered before this call.
+wg_status kernel_call_begin(wg_engine* e, const wg_options* opt_in, void* stream, wg_stats* st,
+                            uint32_t key_bytes) {
+  e->err.clear();
+  wg_options o{};
+  o.struct_size = sizeof(wg_options);
+  if (opt_in) {
+    if (opt_in->struct_size < 8 || opt_in->struct_size > sizeof(wg_options)) {
+      e->err = "wg_options.struct_size is not a known size";
+      return WG_ERR_INVALID_ARG;
+    }
+    std::memcpy(&o, opt_in, opt_in->struct_size);
+  }
+  if (key_bytes != 4 && key_bytes != 8) {
+    e->err = "key_bytes must be 4 or 8";
+    return WG_ERR_INVALID_ARG;
+  }
+  if (st) {
+    uint64_t* ds = st->delta_sizes;
+    uint64_t dc = st->delta_sizes_cap;
+    std::memset(st, 0, sizeof(*st));
+    st->delta_sizes = ds;
+    st->delta_sizes_cap = dc;
+    st->key_bytes = key_bytes;
+  }
+  e->timing = (o.flags & WG_STAGE_TIMING) != 0;
+  e->timing_mask = 0xFFFFFFFFu;
+  e->n_events = 0;
+  return WG_OK;
+}
+
+template <typename K>
+void sort_keys_impl(wg_engine* e, K* keys, K* tmp, uint64_t n, uint32_t key_bits, wg_stats* st) {
+  const SortCfg c = e->tune[sizeof(K) == 8];
+  const int passes = sort_passes((int)key_bits, c.rb);
+  // the passes read their size from the control block and stop on none of its flags
+  Ctrl& c0 = *e->h_up;
+  std::memset(&c0, 0, sizeof(Ctrl));
+  c0.m_in = n;
+  hip_check(e, hipMemcpyAsync(e->d_ctrl, e->h_up, sizeof(Ctrl), hipMemcpyHostToDevice, e->stream), "upload");
+  Bufs<K> b;
+  std::memset(&b, 0, sizeof(b));
+  b.cand[0] = keys;
+  b.cand[1] = tmp;
+  b.rcnt = e->d_rcnt;
+  b.rtot = e->d_rtot;
+  const uint64_t* n_ptr = &e->d_ctrl->m_in;
+  for (int p = 0; p < passes; ++p) {
+    launch_sort_pass<K>(e->stream, e->d_ctrl, n_ptr, c, b, p, false, stage(e, WG_STAGE_RADIX_HIST));
+    launch_sort_pass<K>(e->stream, e->d_ctrl, n_ptr, c, b, p, true, stage(e, WG_STAGE_RADIX_PASS));
+  }
+  if (passes & 1)
+    hip_check(e, hipMemcpyAsync(keys, tmp, n * sizeof(K), hipMemcpyDeviceToDevice, e->stream), "copy");
+  if (st) {
+    st->digit_bits = (uint32_t)c.rb;
+    st->sort_passes = (uint32_t)passes;
+    add_bytes(st, WG_STAGE_RADIX_HIST, (double)n * sizeof(K) * passes);
+    add_bytes(st, WG_STAGE_RADIX_PASS, 2.0 * (double)n * sizeof(K) * passes);
+  }
+}
+
+}  // namespace
+
 extern "C" {
 
 wg_status wg_engine_create(int device, wg_engine** out) {
@@ -1286,6 +1353,84 @@ wg_status wg_triangles(wg_engine* e, const uint32_t* d_src, const uint32_t* d_ds
   wg_result_free(res);
   if (r == WG_OK) *count_out = e->tri_count;
   return r;
+}
+
+// ----- kernel-level entry points (single stages on caller arrays)
+
+wg_status wg_sort_keys(wg_engine* e, void* d_keys, void* d_tmp, uint64_t n, uint32_t key_bytes,
+                       uint32_t key_bits, const wg_options* o, void* stream, wg_stats* st) {
+  if (!e) return WG_ERR_INVALID_ARG;
+  const wg_status v = kernel_call_begin(e, o, stream, st, key_bytes);
+  if (v != WG_OK) return v;
+  if (n > 0 && (!d_keys || !d_tmp)) {
+    e->err = "NULL key array with n > 0";
+    return WG_ERR_INVALID_ARG;
+  }
+  if (key_bits == 0 || key_bits > 8 * key_bytes) {
+    e->err = "key_bits must be 1..8*key_bytes";
+    return WG_ERR_INVALID_ARG;
+  }
+  if (n > kMaxKeys) {
+    e->err = "more than 2^32 - 16 keys";
+    return WG_ERR_INVALID_ARG;
+  }
+  try {
+    hip_check(e, hipSetDevice(e->device), "hipSetDevice");
+    e->stream = (hipStream_t)stream;
+    if (e->done_pending) hip_check(e, hipStreamWaitEvent(e->stream, e->ev_done, 0), "hipStreamWaitEvent");
+    if (n > 1) {
+      if (key_bytes == 4) sort_keys_impl<uint32_t>(e, (uint32_t*)d_keys, (uint32_t*)d_tmp, n, key_bits, st);
+      else sort_keys_impl<uint64_t>(e, (uint64_t*)d_keys, (uint64_t*)d_tmp, n, key_bits, st);
+    }
+    hip_check(e, hipEventRecord(e->ev_done, e->stream), "hipEventRecord");
+    e->done_pending = true;
+    if (st) collect_timing(e, st);
+    e->timing = false;
+    return WG_OK;
+  } catch (const Fail& f) {
+    (void)hipStreamSynchronize(e->stream);
+    e->timing = false;
+    return f.st;
+  }
+}
+
+wg_status wg_merge_keys(wg_engine* e, const void* d_a, uint64_t na, const void* d_b, uint64_t nb, void* d_out,
+                        uint32_t key_bytes, const wg_options* o, void* stream, wg_stats* st) {
+  if (!e) return WG_ERR_INVALID_ARG;
+  const wg_status v = kernel_call_begin(e, o, stream, st, key_bytes);
+  if (v != WG_OK) return v;
+  if ((na > 0 && !d_a) || (nb > 0 && !d_b) || (na + nb > 0 && !d_out)) {
+    e->err = "NULL key array with a non-empty run";
+    return WG_ERR_INVALID_ARG;
+  }
+  if (na > kMaxKeys || nb > kMaxKeys || na + nb > kMaxKeys) {
+    e->err = "more than 2^32 - 16 keys";
+    return WG_ERR_INVALID_ARG;
+  }
+  try {
+    hip_check(e, hipSetDevice(e->device), "hipSetDevice");
+    e->stream = (hipStream_t)stream;
+    if (e->done_pending) hip_check(e, hipStreamWaitEvent(e->stream, e->ev_done, 0), "hipStreamWaitEvent");
+    if (na + nb > 0) {
+      const Ev ev = stage(e, WG_STAGE_MERGE);
+      if (key_bytes == 4)
+        launch_merge_pair<uint32_t>(e->stream, e->grid, (const uint32_t*)d_a, na, (const uint32_t*)d_b, nb,
+                                    (uint32_t*)d_out, ev);
+      else
+        launch_merge_pair<uint64_t>(e->stream, e->grid, (const uint64_t*)d_a, na, (const uint64_t*)d_b, nb,
+                                    (uint64_t*)d_out, ev);
+      if (st) add_bytes(st, WG_STAGE_MERGE, 2.0 * (double)(na + nb) * key_bytes);
+    }
+    hip_check(e, hipEventRecord(e->ev_done, e->stream), "hipEventRecord");
+    e->done_pending = true;
+    if (st) collect_timing(e, st);
+    e->timing = false;
+    return WG_OK;
+  } catch (const Fail& f) {
+    (void)hipStreamSynchronize(e->stream);
+    e->timing = false;
+    return f.st;
+  }
 }
 
 uint32_t wg_result_instances(const wg_result* r) { return r ? r->num_inst : 0; }

@@ -163,6 +163,10 @@ SIGNATURES = [
                             POINTER(WgOptions), c_void_p, POINTER(c_void_p), POINTER(WgStats)]),
     ("wg_triangles", c_int, [c_void_p, c_void_p, c_void_p, c_uint64, POINTER(WgOptions), c_void_p,
                              POINTER(c_uint64), POINTER(WgStats)]),
+    ("wg_sort_keys", c_int, [c_void_p, c_void_p, c_void_p, c_uint64, c_uint32, c_uint32, POINTER(WgOptions),
+                             c_void_p, POINTER(WgStats)]),
+    ("wg_merge_keys", c_int, [c_void_p, c_void_p, c_uint64, c_void_p, c_uint64, c_void_p, c_uint32,
+                              POINTER(WgOptions), c_void_p, POINTER(WgStats)]),
     ("wg_result_instances", c_uint32, [c_void_p]),
     ("wg_result_offsets", c_int, [c_void_p, c_void_p, c_uint64, c_void_p]),
     ("wg_get_sort_config", c_int, [c_void_p, c_uint32, POINTER(WgSortConfig)]),
@@ -262,6 +266,20 @@ def wg_tc_batch(engine, num: int, d_offsets: int, d_src: int, d_dst: int, m: int
 def wg_sg_batch(engine, num: int, d_offsets: int, d_src: int, d_dst: int, m: int,
                 options: WgOptions | None, stream: int, stats: WgStats | None = None):
     return _batch(lib().wg_sg_batch, engine, num, d_offsets, d_src, d_dst, m, options, stream, stats)
+
+
+def wg_sort_keys(engine, d_keys: int, d_tmp: int, n: int, key_bytes: int, key_bits: int,
+                 options: WgOptions | None, stream: int, stats: WgStats | None = None) -> int:
+    return lib().wg_sort_keys(engine, c_void_p(d_keys), c_void_p(d_tmp), n, key_bytes, key_bits,
+                              byref(options) if options is not None else None, c_void_p(stream),
+                              byref(stats) if stats is not None else None)
+
+
+def wg_merge_keys(engine, d_a: int, na: int, d_b: int, nb: int, d_out: int, key_bytes: int,
+                  options: WgOptions | None, stream: int, stats: WgStats | None = None) -> int:
+    return lib().wg_merge_keys(engine, c_void_p(d_a), na, c_void_p(d_b), nb, c_void_p(d_out), key_bytes,
+                               byref(options) if options is not None else None, c_void_p(stream),
+                               byref(stats) if stats is not None else None)
 
 
 def wg_triangles(engine, d_src: int, d_dst: int, m: int, options: WgOptions | None, stream: int,
@@ -542,6 +560,49 @@ class Engine:
         if st != WG_OK:
             raise WgError(st, wg_last_error(self.handle))
         return count, stats_dict(stats)
+
+    @staticmethod
+    def _check_keys(t, name: str):
+        import torch
+
+        if not t.is_cuda or t.dtype not in (torch.int32, torch.uint32, torch.int64, torch.uint64):
+            raise ValueError(f"{name} must be a CUDA tensor of 32- or 64-bit integers")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return t.element_size()
+
+    def sort_keys(self, keys, tmp, key_bits: int, options: WgOptions | None = None):
+        """wg_sort_keys: sorts `keys` (CUDA, 32- or 64-bit, read as unsigned) in place with the
+        LSD passes; `tmp` is scratch of the same size and type.  Returns the stats."""
+        import torch
+
+        kb = self._check_keys(keys, "keys")
+        if self._check_keys(tmp, "tmp") != kb or tmp.numel() < keys.numel():
+            raise ValueError("tmp must match keys in type and hold as many keys")
+        stream = torch.cuda.current_stream(keys.device).cuda_stream
+        stats = WgStats()
+        st = wg_sort_keys(self.handle, keys.data_ptr(), tmp.data_ptr(), keys.numel(), kb, key_bits,
+                          options, stream, stats)
+        if st != WG_OK:
+            raise WgError(st, wg_last_error(self.handle))
+        return stats_dict(stats)
+
+    def merge_keys(self, a, b, out, options: WgOptions | None = None):
+        """wg_merge_keys: out = merge of the ascending runs a and b (CUDA, same integer type)."""
+        import torch
+
+        kb = self._check_keys(a, "a")
+        if self._check_keys(b, "b") != kb or self._check_keys(out, "out") != kb:
+            raise ValueError("a, b and out must have the same key width")
+        if out.numel() < a.numel() + b.numel():
+            raise ValueError("out must hold a.numel() + b.numel() keys")
+        stream = torch.cuda.current_stream(a.device).cuda_stream
+        stats = WgStats()
+        st = wg_merge_keys(self.handle, a.data_ptr(), a.numel(), b.data_ptr(), b.numel(), out.data_ptr(), kb,
+                           options, stream, stats)
+        if st != WG_OK:
+            raise WgError(st, wg_last_error(self.handle))
+        return stats_dict(stats)
 
     def sort_config(self, key_bytes: int) -> dict:
         st, cfg = wg_get_sort_config(self.handle, key_bytes)

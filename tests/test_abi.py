@@ -31,6 +31,7 @@ def test_header_declares_the_entry_points():
                      "wg_result_copy", "wg_result_free", "wg_status_string", "wg_last_error",
                      "wg_tc_batch", "wg_sg_batch", "wg_result_offsets", "wg_result_instances",
                      "wg_autotune", "wg_get_sort_config", "wg_set_sort_config", "wg_triangles",
+                     "wg_sort_keys", "wg_merge_keys",
                      "wg_server_create", "wg_server_destroy", "wg_submit", "wg_poll", "wg_wait",
                      "wg_cancel", "wg_job_get_info", "wg_job_free", "wg_server_get_stats"]:
         assert required in names
