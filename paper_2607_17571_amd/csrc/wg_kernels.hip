@@ -1585,9 +1585,12 @@ __device__ __forceinline__ uint64_t wave_merge_path(const K* A, uint64_t na, con
 
 // Tiles of merge(A, B): block `bid` of `nblocks` takes a contiguous range of tiles; output
 // position p gets key v through put(p, v) (a store into O, or the split unpack).  Only the
-// first tile of a range searches the whole merge path; every later split is searched
-// within the one tile's worth of A past the previous split, which keeps the searches'
-// scattered reads to a small fraction of the data moved.
+// range's first split is searched over the whole merge path; every later split is
+// searched within one tile's worth of A past the previous split, which keeps the
+// searches' scattered reads to a small fraction of the data moved.  The loop runs one
+// tile ahead: while a tile merges in LDS, wave 0 searches the next tile's end split, and
+// the next tile's keys are loaded into registers while this tile's output is written, so
+// a tile costs one exposed round of loads instead of three.  s_i: 4 words.
 template <typename K, int ITEMS, typename Put>
 __device__ __forceinline__ void merge_tiles_to(const K* __restrict__ A, uint64_t na, const K* __restrict__ B,
                                                uint64_t nb, Put put, K* s_in, K* s_out, uint64_t* s_i,
@@ -1600,34 +1603,57 @@ __device__ __forceinline__ void merge_tiles_to(const K* __restrict__ A, uint64_t
   const uint64_t t_end = min(t_begin + tpb, ntiles);
   if (t_begin >= t_end) return;
   const int wid = threadIdx.x / kWave;
+  // the first tile's two splits, searched at once by two waves
   if (wid == 0) {
     const uint64_t i = wave_merge_path(A, na, B, nb, t_begin * T);
     if (lane_id() == 0) s_i[0] = i;
+  } else if (wid == 1) {
+    const uint64_t i = wave_merge_path(A, na, B, nb, min((t_begin + 1) * T, total));
+    if (lane_id() == 0) s_i[1] = i;
   }
   __syncthreads();
-  uint64_t i0 = s_i[0];
+  uint64_t i0 = s_i[0], i1 = s_i[1];
+  // keys of output positions [o0, o1): A[a0, a1) then B from o0 - a0, thread-strided
+  K reg[ITEMS];
+  auto fetch = [&](uint64_t o0, uint64_t o1, uint64_t a0, uint64_t a1) {
+    const uint32_t ca = (uint32_t)(a1 - a0), cn = (uint32_t)(o1 - o0);
+    const uint64_t b0 = o0 - a0;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint32_t t = (uint32_t)k * kBlock + threadIdx.x;
+      reg[k] = t < cn ? (t < ca ? A[a0 + t] : B[b0 + (t - ca)]) : K(0);
+    }
+  };
+  fetch(t_begin * T, min((t_begin + 1) * T, total), i0, i1);
   for (uint64_t tile = t_begin; tile < t_end; ++tile) {
     const uint64_t o0 = tile * T;
     const uint64_t o1 = min(o0 + T, total);
-    if (wid == 0) {
-      // A keys among the first o1 outputs: at least i0, at most i0 + (o1 - o0)
-      const uint64_t lo = max(i0, o1 > nb ? o1 - nb : 0);
-      const uint64_t hi = min(i0 + (o1 - o0), na);
-      const uint64_t i1 = wave_partition(lo, hi, [&](uint64_t i) { return A[i] < B[o1 - 1 - i]; });
-      if (lane_id() == 0) s_i[1] = i1;
+    const bool more = tile + 1 < t_end;
+    uint64_t* const next = s_i + 2 + ((tile - t_begin) & 1);  // alternates: no reader overlap
+    if (more && wid == 0) {
+      // the next tile's end split: A keys among the first n1 outputs lie in
+      // [max(i1, n1 - nb), min(i1 + (n1 - o1), na)]
+      const uint64_t n1 = min(o1 + T, total);
+      const uint64_t lo = max(i1, n1 > nb ? n1 - nb : 0);
+      const uint64_t hi = min(i1 + (n1 - o1), na);
+      const uint64_t i2 = wave_partition(lo, hi, [&](uint64_t i) { return A[i] < B[n1 - 1 - i]; });
+      if (lane_id() == 0) *next = i2;
     }
-    __syncthreads();
-    const uint64_t i1 = s_i[1];
-    const uint64_t j0 = o0 - i0, j1 = o1 - i1;
-    const uint32_t ca = (uint32_t)(i1 - i0), cb = (uint32_t)(j1 - j0);
-    if (cb == 0) {
-      for (uint32_t t = threadIdx.x; t < ca; t += kBlock) put(o0 + t, A[i0 + t]);
-    } else if (ca == 0) {
-      for (uint32_t t = threadIdx.x; t < cb; t += kBlock) put(o0 + t, B[j0 + t]);
+    const uint32_t ca = (uint32_t)(i1 - i0), cn = (uint32_t)(o1 - o0), cb = cn - ca;
+    if (ca == 0 || cb == 0) {
+      // keys of one input only: already in order
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t t = (uint32_t)k * kBlock + threadIdx.x;
+        if (t < cn) put(o0 + t, reg[k]);
+      }
+      __syncthreads();
     } else {
-      const uint32_t cn = ca + cb;
-      for (uint32_t t = threadIdx.x; t < cn; t += kBlock)
-        s_in[t] = t < ca ? A[i0 + t] : B[j0 + (t - ca)];
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t t = (uint32_t)k * kBlock + threadIdx.x;
+        if (t < cn) s_in[t] = reg[k];
+      }
       __syncthreads();
       const uint32_t dg = threadIdx.x * ITEMS;
       if (dg < cn) {
@@ -1647,10 +1673,19 @@ __device__ __forceinline__ void merge_tiles_to(const K* __restrict__ A, uint64_t
         }
       }
       __syncthreads();
-      for (uint32_t t = threadIdx.x; t < cn; t += kBlock) put(o0 + t, s_out[t]);
     }
-    __syncthreads();
+    // next tile's keys in flight while this one's output goes out
+    uint64_t i2 = 0;
+    if (more) {
+      i2 = *next;
+      fetch(o1, min(o1 + T, total), i1, i2);
+    }
+    if (ca != 0 && cb != 0) {
+      for (uint32_t t = threadIdx.x; t < cn; t += kBlock) put(o0 + t, s_out[t]);
+      __syncthreads();  // s_out is rewritten by the next tile
+    }
     i0 = i1;
+    i1 = i2;
   }
 }
 
@@ -1670,7 +1705,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(Ctrl* ctrl, Bufs<K> b, uint32_
   constexpr uint32_t T = kBlock * ITEMS;
   __shared__ K s_in[T];
   __shared__ K s_out[T];
-  __shared__ uint64_t s_i[2];
+  __shared__ uint64_t s_i[4];
   if (halted(ctrl)) return;
   j = iter_cur(ctrl, j);
   const IterRec rp = b.rec[j - 1];
@@ -1703,7 +1738,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_pair(const K* __restrict__ A, 
   constexpr uint32_t T = kBlock * ITEMS;
   __shared__ K s_in[T];
   __shared__ K s_out[T];
-  __shared__ uint64_t s_i[2];
+  __shared__ uint64_t s_i[4];
   merge_tiles<K, ITEMS>(A, na, B, nb, O, s_in, s_out, s_i, blockIdx.x, gridDim.x);
 }
 
@@ -1817,7 +1852,7 @@ __global__ __launch_bounds__(kBlock) void k_unpack_merge(const K* __restrict__ A
   constexpr uint32_t T = kBlock * ITEMS;
   __shared__ K s_in[T];
   __shared__ K s_out[T];
-  __shared__ uint64_t s_i[2];
+  __shared__ uint64_t s_i[4];
   const K mask = field_mask<K>(w);
   merge_tiles_to<K, ITEMS>(
       A, na, B, nb,
