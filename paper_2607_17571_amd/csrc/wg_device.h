@@ -66,7 +66,8 @@ struct Ctrl {
   uint64_t dedup_n;            // unfused variant: candidates left after the dedup pass
   uint64_t cand_n;             // join candidates of the iteration in flight
   uint32_t small_sorted;       // the sort in flight fit one block and is done: the radix
-  uint32_t pad2;               // passes of that sort are no-ops
+                               // passes of that sort are no-ops
+  uint32_t seg_long;           // rows the segmented sort in flight left to its long-row pass
 };
 
 // Kernels of the loop take their iteration from the device, so that one iteration's

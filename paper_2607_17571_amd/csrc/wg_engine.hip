@@ -82,6 +82,7 @@ struct wg_engine {
   // TC: the loop sorts each row's run of the grouped candidates (segmented sort) instead
   // of the LSD passes
   bool seg_sort = false;
+  bool seg_long = false;  // the segmented sort hands long rows to its LDS radix pass
   // how each iteration of the solve sorted its candidates (the method of its last
   // enqueue): kSortLsd, kSortSmall (one-block sort alone), kSortOneBlock (join and sort in
   // one block), kSortSegmented
@@ -397,7 +398,7 @@ void enqueue_iteration(wg_engine* e, const Bufs<K>& b, int kind, int w, int pass
   }
   if (e->stage_sync) stage_probe(e, &b.rec[j].C);
   if (method == kSortSegmented)
-    launch_seg_sort<K>(e->stream, e->grid, e->d_ctrl, C, b, w, passes, stage(e, WG_STAGE_SEG_SORT));
+    launch_seg_sort<K>(e->stream, e->grid, e->d_ctrl, C, b, w, passes, e->seg_long, stage(e, WG_STAGE_SEG_SORT));
   else if (!one_block)
     enqueue_sort<K>(e, b, C, std::min(e->small_mode, 2));
   const uint32_t p = (uint32_t)passes & 1u;
@@ -423,7 +424,7 @@ struct IterGraphKey {
   SortCfg sort;
   Grid grid;
   uint64_t hash_slots;
-  int unfused, small_mode, narrow, seg_sort;
+  int unfused, small_mode, narrow, seg_sort, seg_long;
 };
 
 template <typename K>
@@ -442,6 +443,7 @@ hipGraphExec_t iteration_graph(wg_engine* e, const Bufs<K>& b, int kind, int w, 
   key.small_mode = e->small_mode;
   key.narrow = e->narrow ? 1 : 0;
   key.seg_sort = e->seg_sort ? 1 : 0;
+  key.seg_long = e->seg_long ? 1 : 0;
   if (e->graph_exec && e->graph_key.size() == sizeof(key) &&
       std::memcmp(e->graph_key.data(), &key, sizeof(key)) == 0)
     return e->graph_exec;
@@ -770,6 +772,7 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   bool small_missed = false;
   // within a quarter of a limit, or half of it and not growing
   bool seg_allowed = query == WG_QUERY_TC && !(o.flags & WG_LSD_SORT);
+  bool long_forced = false;  // a row outgrew the bitonic network: long-row pass from now on
   auto calm = [&](uint64_t now, uint64_t before, uint64_t limit) {
     return 4 * now <= limit || (2 * now <= limit && now <= before);
   };
@@ -783,6 +786,7 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
     const double ahead = (double)x.C * g * g * g * g;
     e->narrow = ahead < (double)kNarrowBelow;
     e->seg_sort = seg_allowed && ahead < (double)kSegBelow;
+    e->seg_long = e->seg_sort && long_forced;
     if (!small_missed && K_batch <= kAutoK && it >= 2 && calm(x.C, y.C, small_keys))
       e->small_mode = calm(x.N, y.N, kSmallJoinTuples) ? 3 : 2;
     else
@@ -791,10 +795,11 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   e->small_mode = 1;
   e->narrow = false;  // (no size yet: the first iterations can already be large)
   // TC: the segmented sort while the iterations ahead are expected below kSegBelow
-  // candidates (larger ones sort faster through the LSD passes), until a row's run
-  // outgrows one block (then the LSD passes for the rest of the solve); the first batch,
-  // sizes unknown, takes the LSD passes
-  e->seg_sort = false;
+  // candidates (larger ones sort faster through the LSD passes); once a row outgrows the
+  // bitonic network, with the long-row pass, and once a row outgrows that pass too, the
+  // LSD passes for the rest of the solve; the first batch, sizes unknown, takes the LSD
+  // passes
+  e->seg_sort = e->seg_long = false;
   enqueue_batch(K_batch, slot);
   for (;;) {
     // While the host waits on this batch, the device runs a short speculative batch
@@ -815,7 +820,16 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
         small_missed = true;
         e->small_mode = 1;
       }
-      if (r.c.overflow & 16u) seg_allowed = e->seg_sort = false;
+      if (r.c.overflow & 16u) {
+        // the first long row turns the long-row pass on for the rest of the solve; a row
+        // beyond even that pass (or a second overflow) leaves the LSD passes
+        if (!long_forced) {
+          long_forced = true;
+          e->seg_long = e->seg_sort;
+        } else {
+          seg_allowed = e->seg_sort = e->seg_long = false;
+        }
+      }
       grow_and_resume(e, r.c, hooked);
       if (st) st->resumes++;
       next_j = r.c.iter + 1;

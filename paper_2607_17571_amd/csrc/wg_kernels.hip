@@ -836,31 +836,65 @@ __global__ __launch_bounds__(kSmallSortThreads) void k_small_join(Ctrl* ctrl, Bu
   block_bitonic_sort<K>(s_keys, (uint32_t)C, out);
 }
 
+// Lanes of the wave (within `active`) whose RB-bit digit equals this lane's: one ballot
+// per bit.  For bit b, sb is 0 or all ones (the lane's bit, sign-extended); the lanes that
+// agree with this lane on bit b are ballot(bit b) XNOR sb, per 32-lane half.  The ballot
+// compares sb itself (so the bit is extracted once) and each half's update
+// acc & ~(ballot ^ sb) is one three-input bit operation: four VALU instructions per bit.
+// The operation's table is indexed by (first, second, third) operand bits, first most
+// significant, so evaluating the function on the patterns 0xF0, 0xCC, 0xAA yields it.
+constexpr uint32_t kAndXnor = (0xF0u & ~(0xCCu ^ 0xAAu)) & 0xFFu;  // acc & ~(m ^ sb)
+template <int RB>
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, uint64_t active) {
+  uint32_t lo = (uint32_t)active, hi = (uint32_t)(active >> 32);
+#pragma unroll
+  for (int bit = 0; bit < RB; ++bit) {
+    const uint32_t sb = (uint32_t)__builtin_amdgcn_sbfe((int)d, bit, 1);
+    const uint64_t m = __builtin_amdgcn_uicmp(sb, 0u, 33 /* ICMP_NE */);
+    lo = __builtin_amdgcn_bitop3_b32(lo, (uint32_t)m, sb, kAndXnor);
+    hi = __builtin_amdgcn_bitop3_b32(hi, (uint32_t)(m >> 32), sb, kAndXnor);
+  }
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // ---------------------------------------------------------------------------
 // Segmented sort for the TC join.  The emit writes each delta tuple's slab in delta
 // order and delta is sorted, so the candidates already come grouped by row (key >> w:
 // instance and src) in ascending order; only each row's run needs sorting (by dst).  Block
 // b takes tiles of kSegTile positions and owns the runs that start in its tile: it finds
-// the first run start in the tile, the end of the run holding the tile's last position
-// (the first later position with a larger row, by a wave-parallel search), loads that
-// range into LDS, sorts it with the bitonic network above and writes it to `out`.  Runs
-// partition the array, so every key is written exactly once, and sorting permutes keys
-// only inside a run, so rows at every position stay put: in place (out == in) the
-// neighbours' searches still read correct rows.  A range beyond one block's LDS sets
-// overflow bit 4 (halting the loop; the host re-runs the iteration with the LSD passes).
+// the first and last run starts in the tile, the end of the run holding the tile's last
+// position (the first later position with a larger row, by a wave-parallel search), loads
+// that range into LDS, sorts it with the bitonic network above and writes it to `out`.
+// Runs partition the array, so every key is written exactly once, and sorting permutes
+// keys only inside a run, so rows at every position stay put: in place (out == in) the
+// neighbours' searches still read correct rows.
+//
+// With `long_ok`, a range longer than kSegBitonicMax leaves its last run (the only one
+// that can reach past the tile) to k_seg_long: the block sorts the runs before it and
+// queues the last one's start and length (three words per row in `queue`, counted in
+// ctrl->seg_long).  A run longer than k_seg_long holds, or without `long_ok` a range
+// longer than the bitonic network holds, sets overflow bit 4 (halting the loop; the host
+// re-runs the iteration with the LSD passes).
 // ---------------------------------------------------------------------------
 // (a tile a little under 2,048 keeps most ranges -- tile plus the tail of its last run --
 // within a 2,048-key network: 2 keys per thread)
 constexpr uint32_t kSegTile = 1792;
+constexpr uint32_t kSegBitonicMax = 2 * kSegTile;  // longest range sorted by the network
+                                                   // when long rows go to k_seg_long
+constexpr uint32_t kSegLongBytes = 131072;         // LDS of k_seg_long's row (32K / 16K keys)
 
 template <typename K>
 __global__ __launch_bounds__(kSmallSortThreads) void k_seg_sort(Ctrl* ctrl, const uint64_t* n_ptr,
-                                                                const K* in, K* out, int w) {
+                                                                const K* in, K* out, int w,
+                                                                uint32_t* __restrict__ queue,
+                                                                int long_ok) {
   constexpr uint32_t TH = kSmallSortThreads;
   constexpr uint32_t CAP = kSmallSortBytes / sizeof(K);
+  constexpr uint32_t LCAP = kSegLongBytes / sizeof(K);
   static_assert(CAP >= 2 * kSegTile, "a tile and a run reaching past it fit the LDS");
+  static_assert(kSegBitonicMax <= CAP, "");
   __shared__ K s[CAP];
-  __shared__ uint32_t s_first;
+  __shared__ uint32_t s_first, s_last;
   __shared__ uint64_t s_end;
   if (halted(ctrl)) return;
   const uint64_t n = *n_ptr;
@@ -869,21 +903,27 @@ __global__ __launch_bounds__(kSmallSortThreads) void k_seg_sort(Ctrl* ctrl, cons
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const uint64_t p0 = tile * kSegTile;
     const uint64_t p1 = min<uint64_t>(p0 + kSegTile, n);
-    if (t == 0) s_first = kSegTile;
+    if (t == 0) {
+      s_first = kSegTile;
+      s_last = 0;
+    }
     __syncthreads();
     // run starts in the tile: positions whose row differs from the previous position's
     for (uint32_t q = t; q < (uint32_t)(p1 - p0); q += TH) {
       const uint64_t p = p0 + q;
-      if (p == 0 || (in[p] >> w) != (in[p - 1] >> w)) atomicMin(&s_first, q);
+      if (p == 0 || (in[p] >> w) != (in[p - 1] >> w)) {
+        atomicMin(&s_first, q);
+        atomicMax(&s_last, q);
+      }
     }
     __syncthreads();
     const uint32_t f = s_first;
     if (f < kSegTile && t < (uint32_t)kWave) {
       // end of the run holding p1 - 1: the first position with a larger row, searched up
-      // to what one block holds
+      // to what one block holds (the network for the whole range; k_seg_long for the run)
       const uint64_t s0 = p0 + f;
       const K last_row = in[p1 - 1] >> w;
-      const uint64_t lim = min<uint64_t>(n, s0 + CAP);
+      const uint64_t lim = min<uint64_t>(n, long_ok ? p0 + s_last + LCAP : s0 + CAP);
       const uint64_t e = wave_partition(p1, lim, [&](uint64_t i) { return (in[i] >> w) <= last_row; });
       if (t == 0) s_end = (e == lim && lim < n && (in[lim] >> w) == last_row) ? ~0ull : e;
     }
@@ -891,15 +931,130 @@ __global__ __launch_bounds__(kSmallSortThreads) void k_seg_sort(Ctrl* ctrl, cons
     if (f == kSegTile) continue;  // no run starts here (uniform; s_first is rewritten after
                                   // the barrier that opens the next tile)
     const uint64_t s0 = p0 + f;
-    const uint64_t e = s_end;
+    uint64_t e = s_end;
     if (e == ~0ull) {
       if (t == 0) atomicOr(&ctrl->overflow, 16u);
       return;
+    }
+    if (long_ok && e - s0 > kSegBitonicMax) {
+      // the last run goes to k_seg_long; the runs before it lie inside the tile
+      const uint64_t sl = p0 + s_last;
+      if (t == 0) {
+        const uint32_t q = atomicAdd(&ctrl->seg_long, 1u);
+        queue[3 * (uint64_t)q] = (uint32_t)sl;
+        queue[3 * (uint64_t)q + 1] = (uint32_t)(sl >> 32);
+        queue[3 * (uint64_t)q + 2] = (uint32_t)(e - sl);
+      }
+      e = sl;
     }
     const uint32_t len = (uint32_t)(e - s0);
     for (uint32_t q = t; q < len; q += TH) s[q] = in[s0 + q];
     __syncthreads();
     block_bitonic_sort<K>(s, len, out + s0);
+    __syncthreads();
+  }
+}
+
+// Long rows of the segmented sort: one block per queued row (start, length), the row's
+// keys held in LDS and sorted by their dst field (the low w bits; every key of a row has
+// the same higher bits) with stable 8-bit LSD passes in LDS, then written to `out` once.
+// Each pass ranks as the LSD scatter does: wave `wid` owns a contiguous segment of the
+// row, ranks its keys stably by ballots over the digit bits, the per-wave digit counts
+// are scanned digit-major into positions, and every key is stored at its position in
+// the same LDS array, whose previous contents every wave read into registers before the
+// ranking.  A 32-bit-key row of up to 32K keys thus moves through HBM once instead of
+// through four global passes and their counts.
+template <typename K>
+__global__ __launch_bounds__(kSmallSortThreads) void k_seg_long(Ctrl* ctrl, const K* in, K* out, int w,
+                                                                const uint32_t* __restrict__ queue) {
+  constexpr uint32_t TH = kSmallSortThreads;
+  constexpr int NW = (int)TH / kWave;
+  constexpr uint32_t LCAP = kSegLongBytes / sizeof(K);
+  constexpr int ITEMS = (int)(LCAP / TH);
+  constexpr int RB = 8;
+  constexpr int R = 1 << RB;
+  static_assert(R <= (int)TH, "one thread per digit");
+  __shared__ K s_k[LCAP];
+  __shared__ uint32_t s_cnt[NW][R];
+  __shared__ uint32_t s_wave[NW];
+  if (halted(ctrl)) return;
+  const uint32_t rows = ctrl->seg_long;
+  const int passes = w > RB ? (w + RB - 1) / RB : 1;
+  const int tid = threadIdx.x;
+  const int wid = tid / kWave;
+  const int lane = lane_id();
+  const uint64_t lt = lanemask_lt();
+  for (uint32_t r = blockIdx.x; r < rows; r += gridDim.x) {
+    const uint64_t s0 = (uint64_t)queue[3 * (uint64_t)r] | ((uint64_t)queue[3 * (uint64_t)r + 1] << 32);
+    const uint32_t L = queue[3 * (uint64_t)r + 2];
+    // wave segments of `seg` keys (a multiple of 64), `kk` per lane
+    const uint32_t kk = (L + NW * kWave - 1) / (NW * kWave);
+    const uint32_t seg = kk * kWave;
+    const uint32_t wofs = (uint32_t)wid * seg;
+    K key[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint32_t q = wofs + (uint32_t)k * kWave + lane;
+      key[k] = ((uint32_t)k < kk && q < L) ? in[s0 + q] : K(0);
+    }
+    for (int p = 0; p < passes; ++p) {
+      const int shift = p * RB;
+      for (int jj = tid; jj < NW * R; jj += TH) (&s_cnt[0][0])[jj] = 0;
+      __syncthreads();
+      // ranks within the wave's segment (< 2^16), two to a register
+      uint32_t rank2[(ITEMS + 1) / 2];
+#pragma unroll
+      for (int k = 0; k < (ITEMS + 1) / 2; ++k) rank2[k] = 0;
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        if ((uint32_t)k < kk) {  // uniform
+          const bool valid = wofs + (uint32_t)k * kWave + lane < L;
+          const uint32_t d = (uint32_t)(key[k] >> shift) & (R - 1);
+          const uint64_t active = __builtin_amdgcn_ballot_w64(valid);
+          const uint64_t peers = digit_peers<RB>(d, active);
+          const uint32_t below = __popcll(peers & lt);
+          uint32_t before = 0;
+          if (valid) before = s_cnt[wid][d];
+          if (valid && below == 0) s_cnt[wid][d] = before + (uint32_t)__popcll(peers);
+          rank2[k / 2] |= (before + below) << (16 * (k & 1));
+        }
+      }
+      __syncthreads();
+      // digit-major positions: digit base, then the earlier waves' keys of that digit
+      uint32_t run = 0;
+      if (tid < R) {
+#pragma unroll
+        for (int v = 0; v < NW; ++v) {
+          const uint32_t c = s_cnt[v][tid];
+          s_cnt[v][tid] = run;
+          run += c;
+        }
+      }
+      uint32_t all;
+      const uint32_t base = block_excl_scan<uint32_t, NW>(tid < R ? run : 0u, s_wave, all);
+      if (tid < R) {
+#pragma unroll
+        for (int v = 0; v < NW; ++v) s_cnt[v][tid] += base;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        if ((uint32_t)k < kk && wofs + (uint32_t)k * kWave + lane < L) {
+          const uint32_t d = (uint32_t)(key[k] >> shift) & (R - 1);
+          s_k[s_cnt[wid][d] + ((rank2[k / 2] >> (16 * (k & 1))) & 0xFFFFu)] = key[k];
+        }
+      }
+      __syncthreads();
+      if (p + 1 < passes) {
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+          const uint32_t q = wofs + (uint32_t)k * kWave + lane;
+          if ((uint32_t)k < kk && q < L) key[k] = s_k[q];
+        }
+        // (the next pass's first barrier orders these reads before its stores)
+      }
+    }
+    for (uint32_t q = tid; q < L; q += TH) out[s0 + q] = s_k[q];
     __syncthreads();
   }
 }
@@ -1022,27 +1177,6 @@ __global__ __launch_bounds__(kBlock) void k_radix_scan(Ctrl* ctrl, const uint64_
     carry += total;
   }
   if (threadIdx.x == 0) tot[blockIdx.x] = carry;
-}
-
-// Lanes of the wave (within `active`) whose RB-bit digit equals this lane's: one ballot
-// per bit.  For bit b, sb is 0 or all ones (the lane's bit, sign-extended); the lanes that
-// agree with this lane on bit b are ballot(bit b) XNOR sb, per 32-lane half.  The ballot
-// compares sb itself (so the bit is extracted once) and each half's update
-// acc & ~(ballot ^ sb) is one three-input bit operation: four VALU instructions per bit.
-// The operation's table is indexed by (first, second, third) operand bits, first most
-// significant, so evaluating the function on the patterns 0xF0, 0xCC, 0xAA yields it.
-constexpr uint32_t kAndXnor = (0xF0u & ~(0xCCu ^ 0xAAu)) & 0xFFu;  // acc & ~(m ^ sb)
-template <int RB>
-__device__ __forceinline__ uint64_t digit_peers(uint32_t d, uint64_t active) {
-  uint32_t lo = (uint32_t)active, hi = (uint32_t)(active >> 32);
-#pragma unroll
-  for (int bit = 0; bit < RB; ++bit) {
-    const uint32_t sb = (uint32_t)__builtin_amdgcn_sbfe((int)d, bit, 1);
-    const uint64_t m = __builtin_amdgcn_uicmp(sb, 0u, 33 /* ICMP_NE */);
-    lo = __builtin_amdgcn_bitop3_b32(lo, (uint32_t)m, sb, kAndXnor);
-    hi = __builtin_amdgcn_bitop3_b32(hi, (uint32_t)(m >> 32), sb, kAndXnor);
-  }
-  return ((uint64_t)hi << 32) | lo;
 }
 
 template <typename K, int RB, int ITEMS>
@@ -1480,7 +1614,11 @@ __global__ __launch_bounds__(kBlock) void k_compact_gather(Ctrl* ctrl, int mode,
   j = iter_cur(ctrl, j);
   // the sort before this compaction is over: a later sort that skips the one-block path
   // must not find its flag (nothing else in this launch reads it)
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->small_sorted = 0;
+  // (and the long-row queue of a segmented sort is consumed)
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctrl->small_sorted = 0;
+    ctrl->seg_long = 0;
+  }
   const uint64_t n = *n_ptr;
   const uint64_t N = block_prefix(b.bcnt, gridDim.x, s_pre, s_wave);
   uint64_t lo, hi;
@@ -1890,6 +2028,7 @@ __global__ void k_resume(Ctrl* ctrl, uint64_t cand_cap, uint64_t full_cap, uint3
     ctrl->full_cap = full_cap;
     ctrl->overflow = 0;
     ctrl->small_sorted = 0;
+    ctrl->seg_long = 0;
     if (clear_hook) ctrl->force_overflow_at = 0;
   }
 }
@@ -2032,10 +2171,17 @@ void sort_pass_impl(hipStream_t s, Ctrl* ctrl, const uint64_t* n_ptr, int G, con
 
 template <typename K>
 void launch_seg_sort(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint64_t* n_ptr, const Bufs<K>& b, int w,
-                     int passes, Ev ev) {
+                     int passes, bool long_rows, Ev ev) {
   const int G = std::max(1, g.scan / 2);
-  WG_LAUNCH_WIDE((k_seg_sort<K>), G, ev.start, ev.stop, s, ctrl, n_ptr, (const K*)b.cand[0], b.cand[passes & 1],
-                 w);
+  K* out = b.cand[passes & 1];
+  const hipEvent_t none = nullptr;
+  // the long-row queue lives in b.off, free between the emit that fills it per delta tuple
+  // and the next iteration's join count (at most n / kSegBitonicMax rows of three words)
+  WG_LAUNCH_WIDE((k_seg_sort<K>), G, ev.start, long_rows ? none : ev.stop, s, ctrl, n_ptr, (const K*)b.cand[0],
+                 out, w, b.off, long_rows ? 1 : 0);
+  if (long_rows)
+    WG_LAUNCH_WIDE((k_seg_long<K>), g.scan, none, ev.stop, s, ctrl, (const K*)b.cand[0], out, w,
+                   (const uint32_t*)b.off);
 }
 
 template <typename K>
@@ -2159,7 +2305,8 @@ void launch_resume(hipStream_t s, Ctrl* ctrl, uint64_t cand_cap, uint64_t full_c
                                     uint32_t, Ev, bool);                                           \
   template void launch_small_sort<K>(hipStream_t, Ctrl*, const uint64_t*, const Bufs<K>&, int, bool, Ev); \
   template void launch_small_join<K>(hipStream_t, int, Ctrl*, const Bufs<K>&, int, uint32_t, int, Ev); \
-  template void launch_seg_sort<K>(hipStream_t, const Grid&, Ctrl*, const uint64_t*, const Bufs<K>&, int, int, Ev); \
+  template void launch_seg_sort<K>(hipStream_t, const Grid&, Ctrl*, const uint64_t*, const Bufs<K>&, int, int, bool, \
+                                   Ev);                                                            \
   template void launch_sort_pass<K>(hipStream_t, Ctrl*, const uint64_t*, const SortCfg&,         \
                                     const Bufs<K>&, int, bool, Ev);                                \
   template void launch_compact<K>(hipStream_t, const Grid&, int, Ctrl*, const uint64_t*, const K*, \

@@ -146,11 +146,13 @@ void launch_small_join(hipStream_t s, int kind, Ctrl* ctrl, const Bufs<K>& b, in
                        Ev ev = Ev());
 
 // Segmented sort of the TC join's *n_ptr candidates (grouped by row, each row's run
-// unsorted) from cand[0] into cand[passes & 1]: each run sorted in LDS by one block; a run
-// longer than a block holds sets overflow bit 4.
+// unsorted) from cand[0] into cand[passes & 1]: each run sorted in LDS by one block.
+// `long_rows`: runs beyond the bitonic network go to a second launch that radix-sorts
+// each in LDS (up to 128 KB of keys; b.off holds the queue).  A run longer than a block
+// holds sets overflow bit 4.
 template <typename K>
 void launch_seg_sort(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint64_t* n_ptr, const Bufs<K>& b, int w,
-                     int passes, Ev ev = Ev());
+                     int passes, bool long_rows, Ev ev = Ev());
 
 // One LSD pass over *n_ptr keys: pass p reads cand[p & 1] and writes cand[(p + 1) & 1];
 // digit p covers bits [p * c.rb, (p + 1) * c.rb).  `scatter` false: the count and scan

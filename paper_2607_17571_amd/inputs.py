@@ -156,6 +156,17 @@ def binary_tree(depth: int):
     return ((child - U32(1)) // U32(2)).astype(U32), child
 
 
+def broom(K: int, M: int, T: int):
+    """A chain 0 -> 1 -> ... -> K, then K -> every one of M middle vertices and every
+    middle vertex -> every one of T targets (ids K+1 .. K+M, then K+M+1 .. K+M+T)."""
+    chain_s = np.arange(0, K, dtype=U32)
+    mids = np.arange(K + 1, K + 1 + M, dtype=U32)
+    tgts = np.arange(K + 1 + M, K + 1 + M + T, dtype=U32)
+    src = np.concatenate([chain_s, np.full(M, K, dtype=U32), np.repeat(mids, T)])
+    dst = np.concatenate([chain_s + U32(1), mids, np.tile(tgts, M)])
+    return src.astype(U32), dst.astype(U32)
+
+
 def diamond():
     """p -> a, p -> b, a -> x, b -> x with p=0, a=1, b=2, x=3."""
     return np.array([0, 0, 1, 2], dtype=U32), np.array([1, 2, 3, 3], dtype=U32)

@@ -352,7 +352,7 @@ def test_one_block_sort_miss_reruns_iteration(engine):
         assert_same(s, d, st, ref)
 
 
-@pytest.mark.parametrize("graph", ["er", "grid", "rmat", "chain", "wide_ids"])
+@pytest.mark.parametrize("graph", ["er", "grid", "rmat", "rmat13", "chain", "wide_ids"])
 def test_segmented_sort_matches_lsd(engine, graph):
     """TC sorts each row's run of the grouped join output (segmented sort) unless
     WG_LSD_SORT asks for the LSD passes; both give the closure."""
@@ -362,6 +362,9 @@ def test_segmented_sort_matches_lsd(engine, graph):
         src, dst = inputs.grid_dag(30)
     elif graph == "rmat":
         src, dst = inputs.rmat(11, 1800, *inputs.RMAT_ABCD, seed=9)
+    elif graph == "rmat13":
+        # iterations of 1-4M candidates, rows of thousands: the long-row pass
+        src, dst = inputs.rmat(13, 7400, *inputs.RMAT_ABCD, seed=9)
     elif graph == "chain":
         src, dst = inputs.chain(700)
     else:
@@ -374,15 +377,40 @@ def test_segmented_sort_matches_lsd(engine, graph):
 
 def test_segmented_sort_long_run_reruns_iteration(engine):
     """Binary tree of depth 14: in iteration j the root's row holds the 2^(j+1) nodes at
-    depth j + 1, so iteration 13 brings a run of 16,384 candidates, more than one block of
-    the segmented sort holds (8,192 32-bit keys): that iteration halts and is re-run with
-    the LSD passes (the earlier ones, past the first batch, use the segmented sort)."""
+    depth j + 1, so iteration 13 brings a run of 16,384 candidates, more than the bitonic
+    network of the segmented sort holds (8,192 32-bit keys): that iteration halts and is
+    re-run with the long-row pass (the earlier ones, past the first batch, use the
+    segmented sort)."""
     src, dst = inputs.binary_tree(14)
     ref = oracle.tc(src, dst)
     for opts in (None, wg.make_options(loop_mode=wg.WG_LOOP_HOST, flags=wg.WG_NO_SPECULATION)):
         s, d, st = run(engine, "tc", src, dst, opts)
         assert_same(s, d, st, ref)
         assert st["resumes"] >= 1
+    s, d, st = run(engine, "tc", src, dst, wg.make_options(flags=wg.WG_LSD_SORT))
+    assert_same(s, d, st, ref)
+    assert st["resumes"] == 0
+
+
+@pytest.mark.parametrize("wide", [False, True])
+def test_segmented_sort_long_rows(engine, wide):
+    """A chain into a complete bipartite end (100 x 200): each iteration's row of one
+    chain vertex holds 20,000 candidates over 200 distinct targets, beyond the bitonic
+    network of the segmented sort.  With 32-bit keys the first such row past the first
+    batch halts its iteration once and turns the long-row pass on, which sorts every later
+    one: exactly one re-run.  With 64-bit keys (ids scattered over 22 bits) the rows also
+    exceed what that pass holds (16,384 keys), so a second re-run leaves the LSD passes.
+    The LSD passes alone need none."""
+    src, dst = inputs.broom(14, 100, 200)
+    if wide:
+        src, dst = inputs.scatter_ids(src, dst, 22, seed=31)
+    ref = oracle.tc(src, dst)
+    run(engine, "tc", src, dst)  # grows the buffers: the re-runs below are the sort's own
+    for opts in (None, wg.make_options(flags=wg.WG_ITER_GRAPH)):
+        s, d, st = run(engine, "tc", src, dst, opts)
+        assert_same(s, d, st, ref)
+        assert st["key_bytes"] == (8 if wide else 4)
+        assert st["resumes"] == (2 if wide else 1)
     s, d, st = run(engine, "tc", src, dst, wg.make_options(flags=wg.WG_LSD_SORT))
     assert_same(s, d, st, ref)
     assert st["resumes"] == 0

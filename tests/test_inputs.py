@@ -82,3 +82,13 @@ def test_er_batch_layout():
         assert 256 <= b.n[i] <= 65536
         assert 0.5 * b.n[i] - 1 <= s.size <= 0.95 * b.n[i] + 1
         assert s.max(initial=0) < b.n[i] and d.max(initial=0) < b.n[i]
+
+
+def test_broom_shape():
+    s, d = inputs.broom(3, 4, 5)
+    assert s.dtype == np.uint32 and d.dtype == np.uint32
+    e = set(zip(s.tolist(), d.tolist()))
+    assert len(e) == len(s) == 3 + 4 + 4 * 5
+    assert {(0, 1), (1, 2), (2, 3)} <= e
+    assert all((3, m) in e for m in range(4, 8))
+    assert all((m, t) in e for m in range(4, 8) for t in range(8, 13))
