@@ -43,7 +43,7 @@ constexpr uint32_t kAutoK = 2;                // iterations per host check of th
 constexpr uint64_t kNarrowBelow = 1ull << 21;  // candidates below which the narrow tiles win
 constexpr uint64_t kSegBelow = 1ull << 22;     // ... and the segmented sort beats the LSD passes
 enum : uint8_t { kSortLsd = 0, kSortSmall = 1, kSortOneBlock = 2, kSortSegmented = 3 };
-constexpr uint64_t kDenseRowsMax = 1ull << 26;  // largest dense edge index (256 MB)
+constexpr uint64_t kDenseRowsMax = 1ull << 28;  // largest dense edge index (1 GB)
 
 double now_ms() {
   return std::chrono::duration<double, std::milli>(

@@ -1886,28 +1886,50 @@ __global__ __launch_bounds__(kBlock) void k_merge_pair(const K* __restrict__ A, 
 // launches: per-block row-head counts, then every block writes its heads.
 // ---------------------------------------------------------------------------
 // Dense edge index: Edst, and R[v] = first edge of row v for every row id v <= b.dense
-// (R[b.dense] = |E|), by a binary search of E per row id.
+// (R[b.dense] = |E|), each edge filling the rows between its predecessor's row and its own.
 template <typename K>
 __global__ __launch_bounds__(kBlock) void k_index_dense(Ctrl* ctrl, Bufs<K> b, int w) {
+  // R[v] is the first edge whose row is >= v.  Edge i (and the end, i = n) owns the rows
+  // after its predecessor's row up to its own, (row(E[i-1]), row(E[i])], and writes i
+  // there; these intervals tile [0, dense], so every entry is written once and the work
+  // is O(n + dense).  Gaps longer than kGapSerial rows (empty id ranges, e.g. the ids an
+  // instance of a batch does not use) are filled by the whole block.
+  constexpr uint64_t kGapSerial = 32;
+  __shared__ uint32_t s_n;
+  __shared__ uint64_t s_from[kBlock], s_to[kBlock];
+  __shared__ uint32_t s_val[kBlock];
   if (halted(ctrl)) return;
   const uint64_t n = ctrl->m_unique;
   const K* __restrict__ E = b.E;
   const K mask = field_mask<K>(w);
-  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-  const uint64_t first = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  for (uint64_t i = first; i < n; i += stride) b.Edst[i] = (uint32_t)(E[i] & mask);
-  for (uint64_t v = first; v <= b.dense; v += stride) {
-    uint64_t lo = 0, len = n;
-    while (len > 0) {
-      const uint64_t half = len >> 1;
-      if ((uint64_t)(E[lo + half] >> w) < v) {
-        lo += half + 1;
-        len -= half + 1;
-      } else {
-        len = half;
+  const uint64_t dense = b.dense;
+  for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base <= n; base += (uint64_t)gridDim.x * kBlock) {
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    const uint64_t i = base + threadIdx.x;
+    if (i <= n) {
+      if (i < n) b.Edst[i] = (uint32_t)(E[i] & mask);
+      const uint64_t to = i < n ? (uint64_t)(E[i] >> w) : dense;
+      const uint64_t from = i > 0 ? (uint64_t)(E[i - 1] >> w) + 1 : 0;
+      if (from <= to) {
+        if (to - from < kGapSerial) {
+          for (uint64_t v = from; v <= to; ++v) b.R[v] = (uint32_t)i;
+        } else {
+          const uint32_t q = atomicAdd(&s_n, 1u);
+          s_from[q] = from;
+          s_to[q] = to;
+          s_val[q] = (uint32_t)i;
+        }
       }
     }
-    b.R[v] = (uint32_t)lo;
+    __syncthreads();
+    const uint32_t ng = s_n;
+    for (uint32_t g = 0; g < ng; ++g) {
+      const uint64_t to = s_to[g];
+      const uint32_t val = s_val[g];
+      for (uint64_t v = s_from[g] + threadIdx.x; v <= to; v += kBlock) b.R[v] = val;
+    }
+    __syncthreads();
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->nu = b.dense;
 }

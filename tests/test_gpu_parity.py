@@ -266,6 +266,18 @@ def test_sparse_index_variant(engine, query, make):
     assert_same(s, d, st, ref)
 
 
+@pytest.mark.parametrize("query", ["tc", "sg"])
+def test_dense_index_over_sparse_ids(engine, query):
+    """Ids scattered over 2^20 (about one in 500 used) still take the dense index (the
+    id range is within 16 x |E| + 2^20): its build fills runs of hundreds of empty rows
+    block-wide.  Same closure as the bisection index and the oracle."""
+    src, dst = inputs.scatter_ids(*inputs.erdos_renyi(2000, 3000, seed=41), 20, seed=42)
+    ref = oracle.tc(src, dst) if query == "tc" else oracle.sg(src, dst)
+    for flags in (0, wg.WG_SPARSE_INDEX):
+        s, d, st = run(engine, query, src, dst, wg.make_options(flags=flags))
+        assert_same(s, d, st, ref)
+
+
 def test_sparse_index_full_size(engine):
     _check_golden(engine, "sg_er_500k", wg.make_options(flags=wg.WG_SPARSE_INDEX))
 
