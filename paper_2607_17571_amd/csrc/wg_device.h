@@ -274,6 +274,27 @@ __device__ __forceinline__ uint64_t wave_partition(uint64_t lo64, uint64_t hi64,
   return lo;
 }
 
+// The same with FAN probes per round until the span fits one 64-lane round: more rounds,
+// but each touches FAN scattered lines instead of 64 (for searches whose latency is
+// hidden behind other work and whose probed lines would otherwise cost HBM traffic).
+template <int FAN, typename Pred>
+__device__ __forceinline__ uint64_t wave_partition_fan(uint64_t lo64, uint64_t hi64, Pred pred) {
+  static_assert(FAN >= 2 && FAN < kWave, "");
+  const uint32_t lane = (uint32_t)(threadIdx.x & (kWave - 1));
+  uint32_t lo = (uint32_t)lo64, hi = (uint32_t)hi64;
+  while (hi - lo > (uint32_t)kWave) {
+    const uint32_t span = hi - lo;
+    const uint32_t chunk = (span + FAN - 1) / FAN;
+    const uint32_t q = lo + (lane + 1) * chunk - 1;  // last index of chunk `lane`
+    const bool t = lane < (uint32_t)FAN && q < hi && pred((uint64_t)q);
+    const uint32_t J = (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(t));
+    const uint32_t qJ = lo + (J + 1) * chunk - 1;
+    lo += J * chunk;
+    if (qJ < hi) hi = qJ;
+  }
+  return wave_partition(lo, hi, pred);
+}
+
 template <typename T>
 __device__ __forceinline__ uint64_t wave_lower_bound(const T* a, uint64_t n, T v) {
   return wave_partition(0, n, [&](uint64_t i) { return a[i] < v; });

@@ -1774,7 +1774,12 @@ __device__ __forceinline__ void merge_tiles_to(const K* __restrict__ A, uint64_t
       const uint64_t n1 = min(o1 + T, total);
       const uint64_t lo = max(i1, n1 > nb ? n1 - nb : 0);
       const uint64_t hi = min(i1 + (n1 - o1), na);
-      const uint64_t i2 = wave_partition(lo, hi, [&](uint64_t i) { return A[i] < B[n1 - 1 - i]; });
+      // (32-bit keys: an 8-probe first round halves the lines the search touches; its
+      // extra round is hidden behind the merge.  64-bit keys measured no gain from it.)
+      const auto pred = [&](uint64_t i) { return A[i] < B[n1 - 1 - i]; };
+      uint64_t i2;
+      if constexpr (sizeof(K) == 4) i2 = wave_partition_fan<8>(lo, hi, pred);
+      else i2 = wave_partition(lo, hi, pred);
       if (lane_id() == 0) *next = i2;
     }
     const uint32_t ca = (uint32_t)(i1 - i0), cn = (uint32_t)(o1 - o0), cb = cn - ca;
