@@ -152,12 +152,41 @@ typedef struct {
 typedef struct wg_engine wg_engine; /* per device: buffers, control block, sort tuning table */
 typedef struct wg_result wg_result; /* a device-resident fixpoint owned by the caller */
 
+/* Device memory for an engine's buffers (the boundary's allocator hook; Section V-C keeps
+ * every relation and its ping-pong partner resident in device memory, and this hook lets a
+ * caller -- e.g. a framework's caching allocator -- supply that memory).
+ *
+ *  alloc(bytes, stream, user): return `bytes` of device memory of the engine's device,
+ *      usable by work enqueued on `stream` (a hipStream_t; NULL is the null stream) from
+ *      this point on, or NULL when none is available (the call in progress then fails with
+ *      WG_ERR_OUT_OF_MEMORY and leaves the engine usable).
+ *  free(ptr, bytes, stream, user): the engine's last use of `ptr` is enqueued on `stream`
+ *      before this call (or has finished); the memory must not be handed to work that is
+ *      not ordered after that point on `stream`.  `bytes` is what alloc was asked for.
+ *
+ * Both are called on the thread that called into the engine, during wg_engine_create_ex,
+ * the solve calls (buffers grow on demand) and wg_engine_destroy; never concurrently for
+ * one engine.  Neither may call into the engine. */
+typedef struct {
+  void* (*alloc)(uint64_t bytes, void* stream, void* user);
+  void (*free)(void* ptr, uint64_t bytes, void* stream, void* user);
+  void* user;
+} wg_allocator;
+
 /* Create an engine on HIP device `device`.  Allocates the control block and the sort's
  * count arrays; relation buffers grow on demand and are reused across calls.  An engine
- * serves one host thread at a time. */
+ * serves one host thread at a time.  `allocator` (nullable; copied) supplies every device
+ * allocation of the engine; NULL takes the device's stream-ordered pool (hipMallocAsync /
+ * hipFreeAsync on the stream of the call), so growing or releasing a buffer never waits for
+ * other streams.  WG_ERR_INVALID_ARG: a non-null allocator without both functions, or no
+ * such device; WG_ERR_OUT_OF_MEMORY: the allocator failed. */
+wg_status wg_engine_create_ex(int device, const wg_allocator* allocator, wg_engine** out);
+
+/* wg_engine_create_ex(device, NULL, out). */
 wg_status wg_engine_create(int device, wg_engine** out);
 
-/* Free every device allocation of the engine.  Results of the engine become invalid. */
+/* Free every device allocation of the engine (through its allocator, after waiting for the
+ * device).  Results of the engine become invalid. */
 void wg_engine_destroy(wg_engine* engine);
 
 /* Transitive closure of the m edges (d_src[i], d_dst[i]) (Section II; semi-naive loop,

@@ -44,6 +44,11 @@ constexpr uint64_t kNarrowBelow = 1ull << 21;  // candidates below which the nar
 constexpr uint64_t kSegBelow = 1ull << 22;     // ... and the segmented sort beats the LSD passes
 enum : uint8_t { kSortLsd = 0, kSortSmall = 1, kSortOneBlock = 2, kSortSegmented = 3 };
 constexpr uint64_t kDenseRowsMax = 1ull << 28;  // largest dense edge index (1 GB)
+// fixed arrays of an engine: control block, join and compaction block totals, radix counts
+// and totals (the triangle hits depend on the grid)
+constexpr size_t kFixedBytes[5] = {sizeof(Ctrl), sizeof(uint64_t) * kScanBlocksMax,
+                                   sizeof(uint64_t) * kScanBlocksMax,
+                                   sizeof(uint32_t) * kRadixMax * kRadixBlocksMax, sizeof(uint32_t) * kRadixMax};
 
 double now_ms() {
   return std::chrono::duration<double, std::milli>(
@@ -55,8 +60,11 @@ double now_ms() {
 struct wg_engine {
   int device = 0;
   Grid grid{};
+  // device memory of every engine buffer: the caller's allocator, or (has_alloc false)
+  // stream-ordered hipMallocAsync / hipFreeAsync
+  wg_allocator alloc{};
+  bool has_alloc = false;
   Ctrl* d_ctrl = nullptr;
-  Ctrl* h_up = nullptr;        // pinned upload staging
   Readback* h_rb = nullptr;    // pinned readback, 2 slots + 1 for stage probes
   IterRec* h_rec = nullptr;    // pinned mirror of the records, filled by the batch readbacks
   uint64_t h_rec_cap = 0;
@@ -142,6 +150,9 @@ struct wg_result {
   // results detached from their engine (request server)
   void* owned = nullptr;
   uint64_t owned_bytes = 0;
+  // reads of an owned result enqueued on callers' streams (copies, offsets): the free waits
+  // for every one of them
+  mutable std::vector<hipEvent_t> uses;
   int device = 0;
   Grid grid{};
   std::function<void(uint64_t)> release;
@@ -165,9 +176,29 @@ void fail(wg_engine* e, wg_status st, const std::string& msg) {
   throw Fail{st};
 }
 
+// Device memory of the engine, in stream order on `s`: the caller's allocator when one was
+// given at creation, else the device's stream-ordered pool (hipMallocAsync), so that a
+// buffer grown or freed mid-solve waits for nothing but its own stream (a plain hipFree
+// would wait for the whole device).
+void* dev_alloc(wg_engine* e, size_t bytes, hipStream_t s) {
+  if (e->has_alloc) return e->alloc.alloc(bytes, s, e->alloc.user);
+  void* p = nullptr;
+  if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void dev_free(wg_engine* e, void* p, size_t bytes, hipStream_t s) {
+  if (!p) return;
+  if (e->has_alloc) e->alloc.free(p, bytes, s, e->alloc.user);
+  else (void)hipFreeAsync(p, s);
+}
+
 void free_buf(wg_engine* e, DevBuf& b) {
   if (b.p) {
-    hip_check(e, hipFree(b.p), "hipFree");
+    dev_free(e, b.p, b.bytes, e->stream);
     e->allocated -= b.bytes;
   }
   b.p = nullptr;
@@ -182,12 +213,8 @@ void alloc_buf(wg_engine* e, DevBuf& b, size_t bytes) {
     if (granted < e->allocated + bytes) fail(e, WG_ERR_CAPACITY, "device memory budget exceeded");
     e->budget = granted;
   }
-  void* p = nullptr;
-  hipError_t r = hipMalloc(&p, bytes);
-  if (r != hipSuccess) {
-    (void)hipGetLastError();
-    fail(e, WG_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(r));
-  }
+  void* p = dev_alloc(e, bytes, e->stream);
+  if (!p) fail(e, WG_ERR_OUT_OF_MEMORY, "device allocation of " + std::to_string(bytes) + " bytes failed");
   b.p = p;
   b.bytes = bytes;
   e->allocated += bytes;
@@ -206,13 +233,12 @@ void sync_stream(wg_engine* e) {
   ++e->syncs;
 }
 
-// Grow keeping the first `live` bytes (waits for the stream before freeing the old one).
+// Grow keeping the first `live` bytes (the old buffer is freed in stream order after the copy).
 void grow_keep(wg_engine* e, DevBuf& b, size_t bytes, size_t live) {
   if (b.bytes >= bytes && b.p) return;
   DevBuf nb;
   alloc_buf(e, nb, bytes);
   if (live && b.p) hip_check(e, hipMemcpyAsync(nb.p, b.p, live, hipMemcpyDeviceToDevice, e->stream), "copy");
-  sync_stream(e);
   free_buf(e, b);
   b = nb;
 }
@@ -615,14 +641,14 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   ensure_records(e, 1024);
   hip_check(e, hipMemsetAsync(e->rec.p, 0, e->rec_cap * sizeof(IterRec), e->stream), "memset");
 
-  Ctrl& c0 = *e->h_up;
+  Ctrl c0;
   std::memset(&c0, 0, sizeof(Ctrl));
   c0.m_in = m;
   c0.cand_cap = e->cand_cap;
   c0.full_cap = e->full_cap;
   c0.max_iter = (uint32_t)std::min<uint64_t>(o.max_iterations, 0xFFFFFFFFu);
   c0.force_overflow_at = (uint32_t)std::min<uint64_t>(o.force_overflow_at_iter, 0xFFFFFFFFu);
-  hip_check(e, hipMemcpyAsync(e->d_ctrl, e->h_up, sizeof(Ctrl), hipMemcpyHostToDevice, e->stream), "upload");
+  launch_ctrl_set(e->stream, e->d_ctrl, c0);
 
   // ---- prepare: sort + dedup E, edge index, seed (Section IV-A: E sorted once)
   Bufs<K> b = make_bufs<K>(e);
@@ -1013,8 +1039,9 @@ wg_status solve(wg_engine* e, int query, uint32_t num, const uint64_t* d_offsets
       if (st && st->delta_sizes && st->delta_sizes_cap) st->delta_sizes[0] = 0;
     } else {
       // largest id -> radix field width (Section V-C); the one synchronisation before the loop
-      std::memset(e->h_up, 0, sizeof(Ctrl));
-      hip_check(e, hipMemcpyAsync(e->d_ctrl, e->h_up, sizeof(Ctrl), hipMemcpyHostToDevice, e->stream), "upload");
+      Ctrl zero;
+      std::memset(&zero, 0, sizeof(Ctrl));
+      launch_ctrl_set(e->stream, e->d_ctrl, zero);
       launch_max_id(e->stream, e->grid, e->d_ctrl, d_src, d_dst, m);
       if (num) launch_check_offsets(e->stream, e->grid, e->d_ctrl, d_offsets, num, m);
       hip_check(e, hipMemcpyAsync(&e->h_rb[0].c, e->d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, e->stream),
@@ -1099,7 +1126,14 @@ hipError_t wait_engine(const wg_result* r, hipStream_t s) {
 }
 
 hipError_t mark_engine_use(const wg_result* r, hipStream_t s) {
-  if (!r->engine) return hipSuccess;
+  if (!r->engine) {
+    // an owned result: its free must come after this read, whatever stream it is on
+    hipEvent_t ev = nullptr;
+    hipError_t err = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (err == hipSuccess) err = hipEventRecord(ev, s);
+    if (ev) r->uses.push_back(ev);
+    return err;
+  }
   const hipError_t err = hipEventRecord(r->engine->ev_done, s);
   if (err == hipSuccess) r->engine->done_pending = true;
   return err;
@@ -1209,11 +1243,13 @@ template <typename K>
 void sort_keys_impl(wg_engine* e, K* keys, K* tmp, uint64_t n, uint32_t key_bits, wg_stats* st) {
   const SortCfg c = e->tune[sizeof(K) == 8];
   const int passes = sort_passes((int)key_bits, c.rb);
-  // the passes read their size from the control block and stop on none of its flags
-  Ctrl& c0 = *e->h_up;
+  // the passes read their size from the control block and stop on none of its flags (the
+  // block is written by a kernel whose argument carries it: a later call cannot overwrite a
+  // host staging copy before this one's upload has run)
+  Ctrl c0;
   std::memset(&c0, 0, sizeof(Ctrl));
   c0.m_in = n;
-  hip_check(e, hipMemcpyAsync(e->d_ctrl, e->h_up, sizeof(Ctrl), hipMemcpyHostToDevice, e->stream), "upload");
+  launch_ctrl_set(e->stream, e->d_ctrl, c0);
   Bufs<K> b;
   std::memset(&b, 0, sizeof(b));
   b.cand[0] = keys;
@@ -1239,13 +1275,20 @@ void sort_keys_impl(wg_engine* e, K* keys, K* tmp, uint64_t n, uint32_t key_bits
 
 extern "C" {
 
-wg_status wg_engine_create(int device, wg_engine** out) {
+wg_status wg_engine_create(int device, wg_engine** out) { return wg_engine_create_ex(device, nullptr, out); }
+
+wg_status wg_engine_create_ex(int device, const wg_allocator* allocator, wg_engine** out) {
   if (!out) return WG_ERR_INVALID_ARG;
   *out = nullptr;
+  if (allocator && (!allocator->alloc || !allocator->free)) return WG_ERR_INVALID_ARG;
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return WG_ERR_INVALID_ARG;
   wg_engine* e = new wg_engine();
   e->device = device;
+  if (allocator) {
+    e->alloc = *allocator;
+    e->has_alloc = true;
+  }
   try {
     hip_check(e, hipSetDevice(device), "hipSetDevice");
     hipDeviceProp_t prop;
@@ -1261,22 +1304,27 @@ wg_status wg_engine_create(int device, wg_engine** out) {
       t.blocks = std::min(cu * 4, kRadixBlocksMax);
     }
     e->tune[1].items = 8;
-    hip_check(e, hipMalloc((void**)&e->d_ctrl, sizeof(Ctrl)), "hipMalloc");
-    hip_check(e, hipHostMalloc((void**)&e->h_up, sizeof(Ctrl)), "hipHostMalloc");
+    // the fixed arrays come from the same allocator as the relation buffers, on the null
+    // stream (e->stream is null until the first call)
+    auto fixed = [&](void** p, size_t bytes) {
+      *p = dev_alloc(e, bytes, nullptr);
+      if (!*p) fail(e, WG_ERR_OUT_OF_MEMORY, "device allocation failed");
+    };
+    fixed((void**)&e->d_ctrl, kFixedBytes[0]);
+    fixed((void**)&e->d_jtot, kFixedBytes[1]);
+    fixed((void**)&e->d_bcnt, kFixedBytes[2]);
+    fixed((void**)&e->d_rcnt, kFixedBytes[3]);
+    fixed((void**)&e->d_rtot, kFixedBytes[4]);
+    fixed((void**)&e->d_hits, sizeof(uint64_t) * e->grid.stream);
     hip_check(e, hipHostMalloc((void**)&e->h_rb, 3 * sizeof(Readback)), "hipHostMalloc");
-    hip_check(e, hipMalloc((void**)&e->d_jtot, sizeof(uint64_t) * kScanBlocksMax), "hipMalloc");
-    hip_check(e, hipMalloc((void**)&e->d_bcnt, sizeof(uint64_t) * kScanBlocksMax), "hipMalloc");
-    hip_check(e, hipMalloc((void**)&e->d_rcnt, sizeof(uint32_t) * kRadixMax * kRadixBlocksMax), "hipMalloc");
-    hip_check(e, hipMalloc((void**)&e->d_rtot, sizeof(uint32_t) * kRadixMax), "hipMalloc");
-    hip_check(e, hipMalloc((void**)&e->d_hits, sizeof(uint64_t) * e->grid.stream), "hipMalloc");
-    hip_check(e, hipMemset(e->d_ctrl, 0, sizeof(Ctrl)), "hipMemset");
+    hip_check(e, hipMemsetAsync(e->d_ctrl, 0, sizeof(Ctrl), nullptr), "hipMemsetAsync");
     for (int s = 0; s < 2; ++s)
       hip_check(e, hipEventCreateWithFlags(&e->ev_batch[s], hipEventDisableTiming), "hipEventCreate");
     hip_check(e, hipEventCreateWithFlags(&e->ev_done, hipEventDisableTiming), "hipEventCreate");
     hip_check(e, hipDeviceSynchronize(), "hipDeviceSynchronize");
-  } catch (const Fail&) {
+  } catch (const Fail& f) {
     wg_engine_destroy(e);
-    return WG_ERR_DEVICE;
+    return f.st;
   }
   *out = e;
   return WG_OK;
@@ -1286,8 +1334,10 @@ void wg_engine_destroy(wg_engine* e) {
   if (!e) return;
   (void)hipSetDevice(e->device);
   (void)hipDeviceSynchronize();
+  // everything is idle: the frees go on the null stream
+  e->stream = nullptr;
   auto release = [&](DevBuf& b) {
-    if (b.p) (void)hipFree(b.p);
+    dev_free(e, b.p, b.bytes, nullptr);
     b.p = nullptr;
   };
   for (int s = 0; s < 2; ++s) {
@@ -1305,13 +1355,12 @@ void wg_engine_destroy(wg_engine* e) {
   release(e->off);
   release(e->rec);
   release(e->htab);
-  if (e->d_ctrl) (void)hipFree(e->d_ctrl);
-  if (e->d_jtot) (void)hipFree(e->d_jtot);
-  if (e->d_bcnt) (void)hipFree(e->d_bcnt);
-  if (e->d_rcnt) (void)hipFree(e->d_rcnt);
-  if (e->d_rtot) (void)hipFree(e->d_rtot);
-  if (e->d_hits) (void)hipFree(e->d_hits);
-  if (e->h_up) (void)hipHostFree(e->h_up);
+  dev_free(e, e->d_ctrl, kFixedBytes[0], nullptr);
+  dev_free(e, e->d_jtot, kFixedBytes[1], nullptr);
+  dev_free(e, e->d_bcnt, kFixedBytes[2], nullptr);
+  dev_free(e, e->d_rcnt, kFixedBytes[3], nullptr);
+  dev_free(e, e->d_rtot, kFixedBytes[4], nullptr);
+  dev_free(e, e->d_hits, sizeof(uint64_t) * e->grid.stream, nullptr);
   if (e->h_rb) (void)hipHostFree(e->h_rb);
   if (e->h_rec) (void)hipHostFree(e->h_rec);
   for (int s = 0; s < 2; ++s)
@@ -1320,6 +1369,7 @@ void wg_engine_destroy(wg_engine* e) {
   for (hipEvent_t ev : e->events) (void)hipEventDestroy(ev);
   if (e->graph_exec) (void)hipGraphExecDestroy(e->graph_exec);
   if (e->capture_stream) (void)hipStreamDestroy(e->capture_stream);
+  (void)hipStreamSynchronize(nullptr);
   delete e;
 }
 
@@ -1584,7 +1634,7 @@ wg_status wg_result_offsets(const wg_result* r, uint64_t* offsets_out, uint64_t 
   if (hipSetDevice(result_device(r)) != hipSuccess) return device_error(r, "hipSetDevice");
   const bool host = !is_device_pointer(offsets_out);
   uint64_t* dst = offsets_out;
-  if (host && hipMalloc((void**)&dst, bytes) != hipSuccess) return device_error(r, "hipMalloc");
+  if (host && hipMallocAsync((void**)&dst, bytes, s) != hipSuccess) return device_error(r, "hipMallocAsync");
   const Grid g = result_grid(r);
   if (wait_engine(r, s) != hipSuccess) return device_error(r, "hipStreamWaitEvent");
   if (r->key_bytes == 4)
@@ -1597,8 +1647,8 @@ wg_status wg_result_offsets(const wg_result* r, uint64_t* offsets_out, uint64_t 
   if (err == hipSuccess) err = mark_engine_use(r, s);
   if (host) {
     if (err == hipSuccess) err = hipMemcpyAsync(offsets_out, dst, bytes, hipMemcpyDeviceToHost, s);
+    (void)hipFreeAsync(dst, s);
     if (err == hipSuccess) err = hipStreamSynchronize(s);
-    (void)hipFree(dst);
   }
   return err == hipSuccess ? WG_OK : device_error(r, "result offsets");
 }
@@ -1622,7 +1672,7 @@ wg_status wg_result_copy(const wg_result* r, uint32_t* src_out, uint32_t* dst_ou
   uint32_t* dd = dst_out;
   uint32_t* tmp = nullptr;
   if (host) {
-    if (hipMalloc((void**)&tmp, r->n * 8) != hipSuccess) return device_error(r, "hipMalloc");
+    if (hipMallocAsync((void**)&tmp, r->n * 8, s) != hipSuccess) return device_error(r, "hipMallocAsync");
     ds = tmp;
     dd = tmp + r->n;
   }
@@ -1638,8 +1688,8 @@ wg_status wg_result_copy(const wg_result* r, uint32_t* src_out, uint32_t* dst_ou
   if (host) {
     if (err == hipSuccess) err = hipMemcpyAsync(src_out, tmp, r->n * 4, hipMemcpyDeviceToHost, s);
     if (err == hipSuccess) err = hipMemcpyAsync(dst_out, tmp + r->n, r->n * 4, hipMemcpyDeviceToHost, s);
+    (void)hipFreeAsync(tmp, s);
     if (err == hipSuccess) err = hipStreamSynchronize(s);
-    (void)hipFree(tmp);
   }
   return err == hipSuccess ? WG_OK : device_error(r, "result copy");
 }
@@ -1647,12 +1697,14 @@ wg_status wg_result_copy(const wg_result* r, uint32_t* src_out, uint32_t* dst_ou
 void wg_result_free(wg_result* r) {
   if (!r) return;
   if (r->owned) {
-    // stream-ordered on the null stream: after the copies callers enqueued on blocking
-    // streams, without waiting for the whole device
+    // stream-ordered on the null stream, after every read enqueued on any stream (each
+    // copy recorded an event), without waiting for the whole device
     (void)hipSetDevice(r->device);
+    for (hipEvent_t ev : r->uses) (void)hipStreamWaitEvent(nullptr, ev, 0);
     (void)hipFreeAsync(r->owned, nullptr);
     if (r->release) r->release(r->owned_bytes);
   }
+  for (hipEvent_t ev : r->uses) (void)hipEventDestroy(ev);
   delete r;
 }
 

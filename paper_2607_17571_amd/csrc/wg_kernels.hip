@@ -1081,9 +1081,17 @@ struct RadixShape {
   static constexpr int OWNERS = R >= kBlock ? kBlock : R;
 };
 
+// (a whole tile in range loads without per-key bounds checks, which the compiler would
+// turn into a branch around every load)
 template <typename K, int ITEMS>
 __device__ __forceinline__ void load_tile_striped(const K* __restrict__ in, uint64_t base,
                                                   uint64_t hi, K (&key)[ITEMS]) {
+  if (base + (uint64_t)ITEMS * kBlock <= hi) {
+    const K* p = in + base + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) key[k] = p[k * kBlock];
+    return;
+  }
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
     const uint64_t i = base + (uint64_t)k * kBlock + threadIdx.x;
@@ -1096,6 +1104,12 @@ template <typename K, int ITEMS>
 __device__ __forceinline__ void load_tile_wave(const K* __restrict__ in, uint64_t wbase,
                                                uint64_t hi, K (&key)[ITEMS]) {
   const int lane = lane_id();
+  if (wbase + (uint64_t)ITEMS * kWave <= hi) {
+    const K* p = in + wbase + lane;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) key[k] = p[k * kWave];
+    return;
+  }
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
     const uint64_t i = wbase + (uint64_t)k * kWave + lane;
@@ -1179,6 +1193,19 @@ __global__ __launch_bounds__(kBlock) void k_radix_scan(Ctrl* ctrl, const uint64_
   if (threadIdx.x == 0) tot[blockIdx.x] = carry;
 }
 
+// Digit peers through a per-wave LDS table instead of RB ballots (digits of up to 9 bits,
+// where the table is small): every lane sets its lane bit in the entry of its digit (one
+// LDS atomic OR into the entry's half for its 32-lane half), reads the whole entry back --
+// the mask of the lanes holding the same digit -- and the lowest such lane clears the entry
+// for the next key.  LDS instructions of one wave execute in order, so every OR of an
+// instruction lands before the reads of the next and every read before the clear.  About
+// a dozen VALU instructions per key against four per digit bit for the ballots.
+template <int RB>
+struct PeerTable {
+  static constexpr bool kOn = RB <= 9;
+  static constexpr int kWords = kOn ? 2 * (1 << RB) : 1;  // per wave: low halves, then high
+};
+
 template <typename K, int RB, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(Ctrl* ctrl, const uint64_t* n_ptr,
                                                           const K* __restrict__ in,
@@ -1186,6 +1213,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(Ctrl* ctrl, const uint
                                                           const uint32_t* __restrict__ off,
                                                           const uint32_t* __restrict__ tot) {
   using S = RadixShape<RB>;
+  using PT = PeerTable<RB>;
   constexpr int DPT = S::DPT;
   constexpr uint32_t T = kBlock * ITEMS;
   static_assert(T <= 65535, "tile offsets are kept in 16 bits");
@@ -1194,6 +1222,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(Ctrl* ctrl, const uint
   __shared__ uint16_t s_loc[S::R];                  // first tile position of each digit
   __shared__ uint32_t s_run[S::R];                  // next output position of each digit
   __shared__ uint32_t s_wave[kWavesPerBlock];
+  __shared__ uint32_t s_peer[kWavesPerBlock * PT::kWords];  // peer table of each wave
   if (halted(ctrl) || ctrl->small_sorted) return;
   const uint64_t n = *n_ptr;
   uint64_t lo, hi;
@@ -1204,6 +1233,12 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(Ctrl* ctrl, const uint
   const int lane = lane_id();
   const uint64_t lt = lanemask_lt();
   const bool owner = tid < S::OWNERS;
+  uint32_t* const peer_lo = s_peer + wid * PT::kWords;  // entry d: lanes 0..31 at [d], 32..63 at [R + d]
+  const uint32_t peer_bit = 1u << (lane & 31);
+  const uint32_t peer_half = lane >= 32 ? (uint32_t)S::R : 0u;
+  if (PT::kOn)
+    for (int jj = tid; jj < kWavesPerBlock * PT::kWords; jj += kBlock) s_peer[jj] = 0;  // (before the
+                                                                                        // barrier below)
   {
     // first position of each digit for this block: digit base + earlier blocks' keys
     uint32_t t[DPT];
@@ -1245,6 +1280,22 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(Ctrl* ctrl, const uint
         const uint32_t before = s_cnt[wid][first];
         rank[k] = before + (uint32_t)__popcll(active & lt);
         if (valid && (active & lt) == 0) s_cnt[wid][first] = (uint16_t)(before + __popcll(active));
+      } else if (PT::kOn) {
+        uint64_t peers = 0;
+        uint32_t before = 0;
+        if (valid) {
+          atomicOr(&peer_lo[peer_half + d], peer_bit);
+          peers = ((uint64_t)peer_lo[S::R + d] << 32) | peer_lo[d];
+          before = s_cnt[wid][d];
+        }
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
+        if (valid && below == 0) {
+          s_cnt[wid][d] = (uint16_t)(before + __popcll(peers));
+          peer_lo[d] = 0u;
+          peer_lo[S::R + d] = 0u;
+        }
+        rank[k] = before + below;
       } else {
         const uint64_t peers = digit_peers<RB>(d, active);
         const uint32_t below = __popcll(peers & lt);
@@ -2049,6 +2100,12 @@ __global__ __launch_bounds__(kBlock) void k_offsets2(const K* __restrict__ A, ui
                         : lower_bound<K>(A, na, (K)i << shift) + lower_bound<K>(B, nb, (K)i << shift);
 }
 
+// The control block written from a kernel argument (captured when the launch is enqueued, so
+// no host staging buffer has to outlive the call that queues it).
+__global__ void k_ctrl_set(Ctrl* ctrl, Ctrl v) {
+  if (threadIdx.x == 0) *ctrl = v;
+}
+
 __global__ void k_resume(Ctrl* ctrl, uint64_t cand_cap, uint64_t full_cap, uint32_t clear_hook) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     ctrl->cand_cap = cand_cap;
@@ -2313,6 +2370,10 @@ void launch_unpack(hipStream_t s, const Grid& g, const K* keys, uint64_t n, cons
   }
   hipLaunchKernelGGL((k_unpack_merge<K, kMergeItems>), dim3(stream_blocks(g, (n + n2 + 7) / 8)), dim3(kBlock), 0,
                      s, keys, n, keys2, n2, w, src, dst);
+}
+
+void launch_ctrl_set(hipStream_t s, Ctrl* ctrl, const Ctrl& v) {
+  hipLaunchKernelGGL(k_ctrl_set, dim3(1), dim3(kWave), 0, s, ctrl, v);
 }
 
 void launch_resume(hipStream_t s, Ctrl* ctrl, uint64_t cand_cap, uint64_t full_cap, uint32_t clear_hook) {

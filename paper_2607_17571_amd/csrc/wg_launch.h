@@ -193,4 +193,7 @@ void launch_unpack(hipStream_t s, const Grid& g, const K* keys, uint64_t n, cons
 void launch_resume(hipStream_t s, Ctrl* ctrl, uint64_t cand_cap, uint64_t full_cap,
                    uint32_t clear_hook);
 
+// *ctrl = v, in stream order (v travels as the kernel argument).
+void launch_ctrl_set(hipStream_t s, Ctrl* ctrl, const Ctrl& v);
+
 }  // namespace wg

@@ -67,11 +67,13 @@ struct JobState {
   uint64_t peak_bytes = 0;
 };
 
-// State shared with result handles, which may outlive the server.
+// State shared with result and job handles, which may outlive the server.
 struct Core {
   std::mutex mu;
   std::condition_variable cv;
-  int64_t held = 0;  // resident results + queued inputs (bytes)
+  int64_t held = 0;    // resident results + queued inputs (bytes)
+  bool alive = true;   // false once wg_server_destroy has finished every job
+  double t0 = 0;       // server clock origin
 };
 
 struct Slot {
@@ -102,8 +104,11 @@ struct wg_server {
   std::string err;
 };
 
+// A job handle keeps the shared state alive; it reaches the server itself only while
+// core->alive (after wg_server_destroy every job is done and needs nothing of the server).
 struct wg_job {
   wg_server* server;
+  std::shared_ptr<Core> core;
   std::shared_ptr<JobState> s;
 };
 
@@ -374,6 +379,7 @@ wg_status wg_server_create(int device, const wg_server_config* cfg, wg_server** 
   sv->budget = budget;
   sv->core = std::make_shared<Core>();
   sv->t0 = now_ms();
+  sv->core->t0 = sv->t0;
   sv->st.budget_bytes = budget;
   if (hipStreamCreateWithFlags(&sv->copy_stream, hipStreamNonBlocking) != hipSuccess) {
     delete sv;
@@ -426,6 +432,10 @@ void wg_server_destroy(wg_server* sv) {
   }
   (void)hipStreamSynchronize(sv->copy_stream);
   (void)hipStreamDestroy(sv->copy_stream);
+  {
+    std::lock_guard<std::mutex> g(sv->core->mu);
+    sv->core->alive = false;
+  }
   delete sv;
 }
 
@@ -469,22 +479,22 @@ wg_status wg_submit(wg_server* sv, int query, const uint32_t* src, const uint32_
     sv->st.submitted++;
     sv->core->cv.notify_all();
   }
-  *out = new wg_job{sv, j};
+  *out = new wg_job{sv, sv->core, j};
   return WG_OK;
 }
 
 wg_status wg_poll(wg_job* job, int* done) {
   if (!job || !done) return WG_ERR_INVALID_ARG;
-  std::lock_guard<std::mutex> g(job->server->core->mu);
+  std::lock_guard<std::mutex> g(job->core->mu);
   *done = job->s->phase == kDone;
   return WG_OK;
 }
 
 wg_status wg_wait(wg_job* job, wg_result** out, wg_stats* stats) {
   if (!job) return WG_ERR_INVALID_ARG;
-  std::unique_lock<std::mutex> lk(job->server->core->mu);
+  std::unique_lock<std::mutex> lk(job->core->mu);
   JobState& j = *job->s;
-  job->server->core->cv.wait(lk, [&] { return j.phase == kDone; });
+  job->core->cv.wait(lk, [&] { return j.phase == kDone; });
   if (stats) {
     uint64_t* ds = stats->delta_sizes;
     const uint64_t dc = stats->delta_sizes_cap;
@@ -507,9 +517,10 @@ wg_status wg_wait(wg_job* job, wg_result** out, wg_stats* stats) {
 
 wg_status wg_cancel(wg_job* job) {
   if (!job) return WG_ERR_INVALID_ARG;
-  wg_server* sv = job->server;
-  std::lock_guard<std::mutex> g(sv->core->mu);
+  std::lock_guard<std::mutex> g(job->core->mu);
   JobState& j = *job->s;
+  if (!job->core->alive) return WG_OK;  // the server is gone: the job is done
+  wg_server* sv = job->server;
   j.cancel = true;
   if (j.phase == kQueued) {
     for (auto it = sv->queue.begin(); it != sv->queue.end(); ++it)
@@ -526,9 +537,9 @@ wg_status wg_cancel(wg_job* job) {
 
 wg_status wg_job_get_info(const wg_job* job, wg_job_info* info) {
   if (!job || !info) return WG_ERR_INVALID_ARG;
-  std::lock_guard<std::mutex> g(job->server->core->mu);
+  std::lock_guard<std::mutex> g(job->core->mu);
   const JobState& j = *job->s;
-  const double t0 = job->server->t0;
+  const double t0 = job->core->t0;
   std::memset(info, 0, sizeof(*info));
   info->status = j.status;
   info->phase = (uint32_t)j.phase;
@@ -544,12 +555,12 @@ wg_status wg_job_get_info(const wg_job* job, wg_job_info* info) {
 
 void wg_job_free(wg_job* job) {
   if (!job) return;
-  wg_server* sv = job->server;
   wg_result* leftover = nullptr;
   {
-    std::lock_guard<std::mutex> g(sv->core->mu);
+    std::lock_guard<std::mutex> g(job->core->mu);
     JobState& j = *job->s;
-    if (j.phase != kDone) {
+    wg_server* sv = job->core->alive ? job->server : nullptr;
+    if (j.phase != kDone && sv) {
       j.cancel = true;
       j.abandoned = true;
       if (j.phase == kQueued) {
@@ -561,11 +572,11 @@ void wg_job_free(wg_job* job) {
         free_inputs(sv, j, nullptr);
         finish(sv, j, WG_ERR_CANCELLED);
       }
-    } else if (j.result && !j.result_taken) {
+    } else if (j.phase == kDone && j.result && !j.result_taken) {
       leftover = j.result;
       j.result_taken = true;
     }
-    sv->core->cv.notify_all();
+    job->core->cv.notify_all();
   }
   wg_result_free(leftover);  // a running job's result is freed by the worker's job record
   delete job;

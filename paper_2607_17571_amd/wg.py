@@ -141,6 +141,14 @@ class WgJobInfo(ctypes.Structure):
                 for k, _ in self._fields_}
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, c_uint64, c_void_p, c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_uint64, c_void_p, c_void_p)
+
+
+class WgAllocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", c_void_p)]
+
+
 class WgError(RuntimeError):
     def __init__(self, status: int, detail: str):
         super().__init__(f"{_status_name(status)}: {detail}")
@@ -152,6 +160,7 @@ _lib = None
 # (name, restype, argtypes) of every exported entry point.
 SIGNATURES = [
     ("wg_engine_create", c_int, [c_int, POINTER(c_void_p)]),
+    ("wg_engine_create_ex", c_int, [c_int, POINTER(WgAllocator), POINTER(c_void_p)]),
     ("wg_engine_destroy", None, [c_void_p]),
     ("wg_tc", c_int, [c_void_p, c_void_p, c_void_p, c_uint64, POINTER(WgOptions), c_void_p,
                       POINTER(c_void_p), POINTER(WgStats)]),
@@ -222,6 +231,14 @@ def wg_engine_create(device: int = 0) -> c_void_p:
     st = lib().wg_engine_create(device, byref(eng))
     if st != WG_OK:
         raise WgError(st, f"wg_engine_create(device={device})")
+    return eng
+
+
+def wg_engine_create_ex(device: int = 0, allocator: WgAllocator | None = None) -> c_void_p:
+    eng = c_void_p()
+    st = lib().wg_engine_create_ex(device, byref(allocator) if allocator is not None else None, byref(eng))
+    if st != WG_OK:
+        raise WgError(st, f"wg_engine_create_ex(device={device})")
     return eng
 
 
@@ -433,16 +450,71 @@ def stats_dict(s: WgStats, deltas=None) -> dict:
     return d
 
 
-class Engine:
-    """One engine per device and host thread; results stay valid until its next solve."""
+class TorchAllocator:
+    """wg_allocator hooks that take the engine's device memory from torch's caching allocator.
+
+    The C side calls them on the thread that called into the engine (with the GIL released
+    by ctypes; the callbacks take it back).  A block is returned to torch on the stream it
+    was allocated on; when the engine frees it after using it on another stream, that stream
+    is drained first, since torch would otherwise reuse the block in the allocating stream's
+    order only.  ``allocs`` / ``frees`` / ``live`` count the calls (for tests)."""
 
     def __init__(self, device: int = 0):
+        self.device = device
+        self.allocs = 0
+        self.frees = 0
+        self.failed = 0
+        self.live = {}  # pointer -> (bytes, allocating stream)
+        self._alloc = ALLOC_FN(self._on_alloc)
+        self._free = FREE_FN(self._on_free)
+        self.struct = WgAllocator(self._alloc, self._free, None)
+
+    def _on_alloc(self, nbytes, stream, user):
+        import torch
+
+        try:
+            s = int(stream or 0)
+            p = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, s)
+        except Exception:  # noqa: BLE001 - reported to the engine as a failed allocation
+            self.failed += 1
+            return None
+        self.allocs += 1
+        self.live[int(p)] = (int(nbytes), s)
+        return p
+
+    def _on_free(self, ptr, nbytes, stream, user):
+        import torch
+
+        p = int(ptr or 0)
+        if not p:
+            return
+        _, s_alloc = self.live.pop(p, (0, 0))
+        if int(stream or 0) != s_alloc:
+            torch.cuda.synchronize(self.device)
+        torch.cuda.caching_allocator_delete(p)
+        self.frees += 1
+
+
+class Engine:
+    """One engine per device and host thread; results stay valid until its next solve.
+
+    ``allocator="torch"`` (or a TorchAllocator) routes every device allocation of the
+    engine through torch's caching allocator (wg_engine_create_ex); None takes the
+    library's stream-ordered default."""
+
+    def __init__(self, device: int = 0, allocator=None):
         import torch
 
         if not torch.cuda.is_available():
             raise RuntimeError("the fixpoint engine needs a ROCm GPU")
         self.device = device
-        self.handle = wg_engine_create(device)
+        if allocator == "torch":
+            allocator = TorchAllocator(device)
+        self.allocator = allocator  # kept alive: the C side holds its function pointers
+        if allocator is None:
+            self.handle = wg_engine_create(device)
+        else:
+            self.handle = wg_engine_create_ex(device, allocator.struct)
 
     def close(self):
         if self.handle is not None:

@@ -12,7 +12,9 @@ sha256 of the result bytes (little-endian uint32 src array followed by the dst
 array, lexicographically sorted).  Batched workloads (names with "_batch_") store the
 total size, the largest instance's iteration count, the sha256 of the per-instance
 results concatenated in instance order (local ids; src bytes then dst bytes) and the
-sha256 of the result offsets (num + 1 little-endian int64).
+sha256 of the result offsets (num + 1 little-endian int64).  The served mix
+("served_mix_<requests>_seed<seed>") stores one record per request: query, edges, the
+fixpoint size, the iteration count and the sha256 of its result bytes.
 """
 
 import hashlib
@@ -27,8 +29,8 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import oracle  # noqa: E402
 from paper_2607_17571_amd import inputs  # noqa: E402
 
-DEFAULT = ["tc_er_2000", "sg_er_500k", "tc_rmat_s15", "tc_rmat_s15_ids24", "tc_grid_100",
-           "tc_batch_er_256", "sg_batch_er_256", "tc_batch_er_4096"]
+DEFAULT = ["tc_er_2000", "sg_er_500k", "tc_rmat_s15", "tc_rmat_s16", "tc_rmat_s15_ids24", "tc_grid_100",
+           "tc_batch_er_256", "sg_batch_er_256", "tc_batch_er_4096", "served_mix_120_seed5"]
 
 
 def summarise_batch(results):
@@ -50,10 +52,33 @@ def summarise(r):
             "delta_sizes": r.delta_sizes, "candidates": r.candidates, "sha256": h}
 
 
+def served_mix(name):
+    """Per-request records of the served mix ``served_mix_<requests>_seed<seed>``."""
+    _, _, num, seed = name.split("_")
+    reqs = inputs.served_requests(int(num), seed=int(seed[len("seed"):]))
+    recs = []
+    for i, r in enumerate(reqs):
+        t0 = time.time()
+        f = oracle.tc(r.src, r.dst) if r.query == "tc" else oracle.sg(r.src, r.dst)
+        rec = summarise(f)
+        del rec["delta_sizes"]
+        rec.update(query=r.query, kind=r.kind, n=int(r.n), edges=int(r.src.size))
+        recs.append(rec)
+        print(f"{name}[{i}] {r.query} {r.kind} n={r.n}: |fixpoint|={rec['size']} "
+              f"({time.time() - t0:.1f} s)", flush=True)
+    return {"requests": recs}
+
+
 def main(names):
     path = os.path.join(HERE, "fixpoints.json")
     data = json.load(open(path)) if os.path.exists(path) else {}
     for name in names:
+        if name.startswith("served_mix_"):
+            data[name] = served_mix(name)
+            with open(path, "w") as f:
+                json.dump(data, f, indent=1, sort_keys=True)
+                f.write("\n")
+            continue
         if "_batch_" in name:
             t0 = time.time()
             query, b = inputs.batch_workload(name)

@@ -27,6 +27,10 @@ def _keys(n, bits, dtype, seed):
     (0, 30, np.uint32), (1, 30, np.uint32), (2, 30, np.uint32), (4097, 30, np.uint32),
     (1_000_003, 30, np.uint32), (300_001, 24, np.uint32), (65_537, 32, np.uint32),
     (500_001, 48, np.uint64), (123_457, 38, np.uint64), (70_001, 64, np.uint64),
+    # tile (4,096 / 2,048 keys) and grid (1,024 blocks x one tile) boundaries
+    (4095, 30, np.uint32), (4096, 30, np.uint32), (4097, 30, np.uint32),
+    ((1 << 22) - 1, 30, np.uint32), (1 << 22, 30, np.uint32), ((1 << 22) + 1, 30, np.uint32),
+    (2047, 48, np.uint64), (2048, 48, np.uint64), (2049, 48, np.uint64),
 ])
 def test_sort_keys(engine, n, bits, dtype):
     import torch
@@ -57,6 +61,11 @@ def test_sort_keys_with_duplicates_and_timing(engine):
 @pytest.mark.parametrize("na,nb,bits,dtype", [
     (0, 0, 30, np.uint32), (0, 5, 30, np.uint32), (7, 0, 30, np.uint32), (1, 1, 30, np.uint32),
     (100_003, 77_777, 30, np.uint32), (1_000_000, 3, 32, np.uint32), (250_001, 250_003, 48, np.uint64),
+    # tile (2,048 keys) and grid (2,048 blocks x one tile = 2^22) boundaries, ragged splits
+    (2047, 0, 30, np.uint32), (2000, 48, 30, np.uint32), (1, 2048, 30, np.uint32),
+    (4095, 1, 30, np.uint32), (3000, 1096, 30, np.uint32), (2, 4095, 30, np.uint32),
+    ((1 << 22) - 7, 6, 30, np.uint32), ((1 << 21), 1 << 21, 30, np.uint32),
+    ((1 << 22) - 1, 2, 30, np.uint32), (1024, 1023, 48, np.uint64), (1 << 21, (1 << 21) + 1, 48, np.uint64),
 ])
 def test_merge_keys(engine, na, nb, bits, dtype):
     import torch

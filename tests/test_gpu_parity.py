@@ -147,6 +147,41 @@ def test_hub_skew(engine):
     assert_same(s, d, st, oracle.tc(src, dst))
 
 
+def test_hub_of_a_million(engine):
+    """A row of out-degree 10^6: three tuples each expand it, so one delta tuple's slab spans
+    about 500 emit tiles; the hub's children 1..3 point back to it (a cycle through the hub)."""
+    hub_deg = 1_000_000
+    src = np.concatenate([np.zeros(hub_deg, np.uint32), np.array([1, 2, 3], np.uint32)])
+    dst = np.concatenate([np.arange(1, hub_deg + 1, dtype=np.uint32), np.zeros(3, np.uint32)])
+    s, d, st = run(engine, "tc", src, dst)
+    assert_same(s, d, st, oracle.tc(src, dst))
+
+
+def test_sg_hub(engine):
+    """SG whose base rule crosses a parent of 2,000 children (4 million ordered pairs)."""
+    kids = np.arange(1, 2001, dtype=np.uint32)
+    src = np.concatenate([np.zeros(2000, np.uint32), kids[:40]])
+    dst = np.concatenate([kids, kids[:40] + np.uint32(5000)])
+    s, d, st = run(engine, "sg", src, dst)
+    assert_same(s, d, st, oracle.sg(src, dst))
+
+
+# compaction: 1,024 blocks of 2,048-key tiles; below 2^21 candidates the ranges are spread
+# evenly over the grid, at 2^21 every block owns one whole tile, at 2^22 two
+@pytest.mark.parametrize("a,b", [(49, 42799), (1024, 2048), (3, 699051), (3, 1398101), (4, 1048576),
+                                 (5, 838861)])
+def test_compaction_tile_boundaries(engine, a, b):
+    """Bipartite through one hub: iteration 1 has exactly a*b candidates, all new (2^21 - 1,
+    2^21, 2^21 + 1, 2^22 - 1, 2^22, 2^22 + 1)."""
+    h = a + b
+    src = np.concatenate([np.arange(a, dtype=np.uint32), np.full(b, h, np.uint32)])
+    dst = np.concatenate([np.full(a, h, np.uint32), np.arange(a, a + b, dtype=np.uint32)])
+    s, d, st = run(engine, "tc", src, dst)
+    ref = oracle.tc(src, dst)
+    assert ref.candidates == a * b
+    assert_same(s, d, st, ref)
+
+
 @pytest.mark.parametrize("seed,n,m", [(1, 300, 280), (2, 2000, 1900), (3, 20000, 18000)])
 def test_sg_random_er(engine, seed, n, m):
     src, dst = inputs.erdos_renyi(n, m, seed=seed)
@@ -526,8 +561,8 @@ def test_result_copy_to_host_memory(engine):
 # Full-size workloads against the oracle's stored summaries.
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("name", ["tc_er_2000", "tc_rmat_s15", "tc_rmat_s15_ids24", "sg_er_500k",
-                                  "tc_grid_100"])
+@pytest.mark.parametrize("name", ["tc_er_2000", "tc_rmat_s15", "tc_rmat_s16", "tc_rmat_s15_ids24",
+                                  "sg_er_500k", "tc_grid_100"])
 def test_full_size_against_golden(engine, name):
     _check_golden(engine, name, None)
 

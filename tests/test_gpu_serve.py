@@ -5,6 +5,9 @@ wg_tc / wg_sg, and to the oracle.  Admission under a tight memory budget, requeu
 rejection of an oversize request, cancellation and host-pointer inputs are covered.
 """
 
+import hashlib
+import json
+import os
 import sys
 
 import numpy as np
@@ -17,6 +20,8 @@ from tests.gpu_util import run as run_single
 from tests.gpu_util import to_gpu
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "fixpoints.json")))
 
 
 def served(server, reqs, host=False):
@@ -56,6 +61,7 @@ def test_alone_equals_in_mix(engine):
         assert info["submit_ms"] <= info["start_ms"] <= info["end_ms"]
     assert stats["completed"] == len(reqs) and stats["failed"] == 0
     assert stats["held_bytes"] == 0  # every result freed
+    assert stats["max_running"] >= 2  # the requests did share the device
 
 
 def test_tight_budget_requeues_and_rejects_oversize(engine):
@@ -83,6 +89,7 @@ def test_tight_budget_requeues_and_rejects_oversize(engine):
         np.testing.assert_array_equal(s.cpu().numpy(), ref.src)
         np.testing.assert_array_equal(d.cpu().numpy(), ref.dst)
     assert stats["completed"] == len(reqs) and stats["failed"] == 1
+    assert stats["requeued"] >= 1  # some solve outgrew its reservation and was queued again
 
 
 def test_cancel_queued_request(engine):
@@ -123,3 +130,53 @@ def test_host_pointer_inputs_and_empty_request(engine):
         ref = oracle.tc(r.src, r.dst) if r.query == "tc" else oracle.sg(r.src, r.dst)
         np.testing.assert_array_equal(s, ref.src)
         np.testing.assert_array_equal(d, ref.dst)
+
+
+def _sha(s, d):
+    return hashlib.sha256(np.asarray(s, dtype="<u4").tobytes() + np.asarray(d, dtype="<u4").tobytes()).hexdigest()
+
+
+def test_served_mix_full_size_against_golden(engine):
+    """The served mix at its real sizes (120 requests, n log-uniform in [1k, 1M], R-MAT up to
+    scale 15, 4 slots, the default budget): every result equals the oracle's stored record
+    (size, iterations, sha256) and the same request solved alone, and solves overlapped."""
+    import torch
+
+    g = GOLDEN["served_mix_120_seed5"]["requests"]
+    reqs = inputs.served_requests(len(g), seed=5)
+    print(f"[gpu] served mix of {len(reqs)} at full size", flush=True, file=sys.stderr)
+    srv = wg.Server(0, slots=4)
+    try:
+        jobs = [srv.submit(r.query, to_gpu(r.src), to_gpu(r.dst)) for r in reqs]
+        for i, (r, j, rec) in enumerate(zip(reqs, jobs, g)):
+            s, d, st, info = j.wait()
+            j.close()
+            assert info["status"] == wg.WG_OK
+            assert (r.query, int(r.src.size)) == (rec["query"], rec["edges"])
+            assert st["result_tuples"] == rec["size"] and st["iterations"] == rec["iterations"], i
+            a_s, a_d, a_st = engine.solve(r.query, to_gpu(r.src), to_gpu(r.dst))
+            assert a_st["iterations"] == st["iterations"] and a_st["delta_sizes"] == st["delta_sizes"], i
+            assert torch.equal(a_s, s) and torch.equal(a_d, d), i
+            assert _sha(s.cpu().numpy(), d.cpu().numpy()) == rec["sha256"], i
+            del s, d, a_s, a_d
+        stats = srv.stats()
+    finally:
+        srv.close()
+    assert stats["completed"] == len(reqs) and stats["failed"] == 0
+    assert stats["max_running"] >= 2
+
+
+def test_job_handle_outlives_server(engine):
+    """Job handles freed after the server is gone (e.g. a test that failed before closing
+    them) must neither touch the destroyed server nor leak the unclaimed result."""
+    srv = wg.Server(0, slots=2, mem_budget_bytes=1 << 30)
+    reqs = inputs.served_requests(3, seed=23, n_lo=100, n_hi=400)
+    jobs = [srv.submit(r.query, to_gpu(r.src), to_gpu(r.dst)) for r in reqs]
+    jobs[0].wait(want_result=False)
+    srv.close()
+    for j in jobs:
+        assert j.done()
+        j.cancel()
+        info = j.info()
+        assert info["phase"] == 2
+        j.close()

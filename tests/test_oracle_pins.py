@@ -339,6 +339,93 @@ def test_sg_invariants_er():
 
 
 # ---------------------------------------------------------------------------
+# Batches: each instance's fixpoint, from its own slice of the edges and with local ids,
+# pinned to BFS (TC) and boolean matrices (SG) per instance, never to the oracle's own
+# single-instance path.  Empty instances sit first, in the middle and last.
+# ---------------------------------------------------------------------------
+
+def _ragged_batch(seed):
+    rng = np.random.default_rng(seed)
+    srcs, dsts, sizes, ns = [], [], [], []
+    for i in range(14):
+        n = int(rng.integers(2, 30))
+        if i in (0, 6, 13):
+            s = d = np.empty(0, np.uint32)
+        else:
+            m = int(rng.integers(1, min(2 * n, n * (n - 1)) + 1))
+            s, d = inputs.erdos_renyi(n, m, seed=seed * 100 + i)
+            if i % 4 == 1:  # a self-loop and a duplicate edge inside the instance
+                s = np.concatenate([s, s[:1], s[:1]]).astype(np.uint32)
+                d = np.concatenate([d, s[:1], d[:1]]).astype(np.uint32)
+        srcs.append(s)
+        dsts.append(d)
+        sizes.append(s.size)
+        ns.append(n)
+    offsets = np.zeros(len(sizes) + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(sizes)
+    return np.concatenate(srcs), np.concatenate(dsts), offsets, ns
+
+
+def _check_tc_batch(batch_fn):
+    for seed in (1, 2, 3):
+        src, dst, offs, ns = _ragged_batch(seed)
+        res = batch_fn(src, dst, offs)
+        assert len(res) == len(ns)
+        for i, (r, n) in enumerate(zip(res, ns)):
+            s, d = src[offs[i]:offs[i + 1]], dst[offs[i]:offs[i + 1]]
+            xs, ys, hist = bfs_tc(s, d, n)
+            assert as_set(r) == set(zip(xs.tolist(), ys.tolist())), (seed, i)
+            assert strictly_sorted(r)
+            # |Delta_i| = pairs first reached by a shortest positive walk of length i + 1
+            assert r.delta_sizes == [int(h) for h in hist] + [0], (seed, i)
+            assert r.iterations == hist.size
+
+
+def _check_sg_batch(batch_fn):
+    for seed in (4, 5):
+        src, dst, offs, ns = _ragged_batch(seed)
+        res = batch_fn(src, dst, offs)
+        assert len(res) == len(ns)
+        for i, (r, n) in enumerate(zip(res, ns)):
+            s, d = src[offs[i]:offs[i + 1]], dst[offs[i]:offs[i + 1]]
+            if s.size == 0:
+                assert r.src.size == 0 and r.iterations == 0
+                continue
+            S, rounds, sizes = matrix_sg(s, d, n)
+            xs, ys = S.nonzero()
+            assert as_set(r) == set(zip(xs.tolist(), ys.tolist())), (seed, i)
+            assert r.iterations == rounds and r.full_sizes == sizes
+
+
+def test_tc_batch_matches_bfs_per_instance():
+    _check_tc_batch(oracle.tc_batch)
+
+
+def test_sg_batch_matches_matrices_per_instance():
+    _check_sg_batch(oracle.sg_batch)
+
+
+def _batch_shifted_slices(batch_src, batch_dst, offsets):
+    """Planted mistake: every instance but the first starts one edge late."""
+    return [oracle.tc(batch_src[int(offsets[i]) + (i > 0):int(offsets[i + 1])],
+                      batch_dst[int(offsets[i]) + (i > 0):int(offsets[i + 1])])
+            for i in range(len(offsets) - 1)]
+
+
+def _batch_skips_empty(batch_src, batch_dst, offsets):
+    """Planted mistake: empty instances are dropped from the list of results."""
+    return [oracle.tc(batch_src[int(offsets[i]):int(offsets[i + 1])],
+                      batch_dst[int(offsets[i]):int(offsets[i + 1])])
+            for i in range(len(offsets) - 1) if offsets[i + 1] > offsets[i]]
+
+
+@pytest.mark.parametrize("mistake", [_batch_shifted_slices, _batch_skips_empty])
+def test_batch_pin_catches_planted_mistakes(mistake):
+    with pytest.raises(AssertionError):
+        _check_tc_batch(mistake)
+
+
+# ---------------------------------------------------------------------------
 # Planted mistakes must be caught by the pins above.
 # ---------------------------------------------------------------------------
 
