@@ -264,6 +264,26 @@ wg_status wg_merge_keys(wg_engine* engine, const void* d_a, uint64_t na, const v
                         void* d_out, uint32_t key_bytes, const wg_options* options, void* stream,
                         wg_stats* stats);
 
+/* For callers that cannot allocate device memory -- code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc: wg_sort_keys without an engine and
+ * without any allocation.  Sorts the n keys of d_keys (device; key_bytes 4 or 8 per key,
+ * every key below 2^key_bits) ascending in place with the same LSD passes (8-bit digits,
+ * the engine's default tiles, up to 1,024 blocks); d_tmp (device, n keys, caller-owned) is
+ * the ping-pong buffer, as for wg_sort_keys.  Its scratch (control block, per-block digit
+ * counts, digit totals; WG_SORT_NOALLOC_SCRATCH_BYTES) is a static array of the library,
+ * one per device, held until the process ends: the call itself allocates nothing and only
+ * enqueues kernels (and, for an odd pass count, one device-to-device copy) on `stream`
+ * (NULL: the null stream) of the current device, returning before they run.  Calls on one
+ * device share that scratch: calls whose work overlaps on the device (different streams
+ * not ordered against each other) race and give wrong results; calls in stream order are
+ * safe (each rewrites the whole control block first).
+ * WG_ERR_INVALID_ARG: key_bytes not 4 or 8, key_bits outside 1..8*key_bytes, more than
+ * 2^32 - 16 keys, or a NULL array with n > 0; WG_ERR_DEVICE: no usable current device or a
+ * failed launch.  wg_last_error(NULL) gives the detail (per host thread). */
+#define WG_SORT_NOALLOC_SCRATCH_BYTES 1049856u
+wg_status wg_sort_keys_noalloc(void* d_keys, void* d_tmp, uint64_t n, uint32_t key_bytes, uint32_t key_bits,
+                               void* stream);
+
 /* Number of tuples in the result (for a batch: over all instances). */
 uint64_t wg_result_size(const wg_result* result);
 
@@ -387,7 +407,8 @@ wg_status wg_server_get_stats(const wg_server* server, wg_server_stats* out);
 /* Static text for a status code. */
 const char* wg_status_string(wg_status status);
 
-/* Detail of the most recent failure on the engine ("" if none). */
+/* Detail of the most recent failure on the engine ("" if none); NULL: of the latest call
+ * that takes no engine on this host thread (wg_sort_keys_noalloc). */
 const char* wg_last_error(const wg_engine* engine);
 
 #ifdef __cplusplus

@@ -50,6 +50,8 @@ constexpr size_t kFixedBytes[5] = {sizeof(Ctrl), sizeof(uint64_t) * kScanBlocksM
                                    sizeof(uint64_t) * kScanBlocksMax,
                                    sizeof(uint32_t) * kRadixMax * kRadixBlocksMax, sizeof(uint32_t) * kRadixMax};
 
+thread_local std::string wg_call_error;  // see set_call_error
+
 double now_ms() {
   return std::chrono::duration<double, std::milli>(
              std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -1150,6 +1152,8 @@ wg_status engine_solve(wg_engine* e, int query, uint32_t num, const uint64_t* d_
   return solve(e, query, num, d_offsets, src, dst, m, o, stream, out, st);
 }
 
+void set_call_error(const char* msg) { wg_call_error = msg; }
+
 uint64_t engine_allocated(const wg_engine* e) { return e->allocated; }
 uint64_t engine_peak(const wg_engine* e) { return e->peak; }
 void engine_set_grow_hook(wg_engine* e, GrowHook hook) { e->grow_hook = std::move(hook); }
@@ -1723,6 +1727,6 @@ const char* wg_status_string(wg_status s) {
   return "unknown status";
 }
 
-const char* wg_last_error(const wg_engine* e) { return e ? e->err.c_str() : ""; }
+const char* wg_last_error(const wg_engine* e) { return e ? e->err.c_str() : wg_call_error.c_str(); }
 
 }  // extern "C"

@@ -32,4 +32,8 @@ void engine_set_cancel(wg_engine* e, const std::atomic<bool>* flag);
 wg_status result_detach(const wg_result* r, hipStream_t s, std::function<void(uint64_t)> release,
                         wg_result** out, uint64_t* bytes);
 
+// Detail of the latest failure of a call that takes no engine (wg_last_error(NULL) returns
+// it; one per host thread).
+void set_call_error(const char* msg);
+
 }  // namespace wg

@@ -20,8 +20,13 @@
 
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+#include <cstring>
+#include <mutex>
 #include <type_traits>
 
+#include "../../include/wg.h"
+#include "wg_internal.h"
 #include "wg_launch.h"
 
 namespace wg {
@@ -2413,3 +2418,121 @@ WG_INSTANTIATE(uint32_t)
 WG_INSTANTIATE(uint64_t)
 
 }  // namespace wg
+
+// ---------------------------------------------------------------------------
+// wg_sort_keys_noalloc: the LSD sort on caller arrays with no allocation at all.  Its
+// scratch -- the control block the passes read their size from, the per-block digit
+// counts of one pass and the digit totals -- is the file-scope array below: one copy per
+// device, held until the process ends.  Host code never passes the array's name to a
+// kernel (on the host it is only a stand-in for the symbol): the device address comes from
+// hipGetSymbolAddress, resolved once per device with that device current.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kNoAllocDigitBits = 8;
+constexpr int kNoAllocDigits = 1 << kNoAllocDigitBits;
+constexpr int kNoAllocBlocks = 1024;  // count and scatter blocks (at most)
+constexpr size_t kNoAllocCtrlBytes = 256;
+constexpr size_t kNoAllocCountBytes = sizeof(uint32_t) * kNoAllocDigits * kNoAllocBlocks;
+constexpr size_t kNoAllocTotalBytes = sizeof(uint32_t) * kNoAllocDigits;
+constexpr size_t kNoAllocScratchBytes = kNoAllocCtrlBytes + kNoAllocCountBytes + kNoAllocTotalBytes;
+constexpr uint64_t kNoAllocMaxKeys = 0xFFFFFFF0ull;  // output positions are 32-bit
+constexpr int kNoAllocMaxDevices = 64;
+static_assert(sizeof(wg::Ctrl) <= kNoAllocCtrlBytes, "control block fits its slot");
+static_assert(kNoAllocScratchBytes == WG_SORT_NOALLOC_SCRATCH_BYTES, "header states the scratch size");
+
+std::mutex g_noalloc_mu;
+void* g_noalloc_scratch[kNoAllocMaxDevices];  // device address of `scratch` per device
+int g_noalloc_blocks[kNoAllocMaxDevices];
+
+}  // namespace
+
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+namespace {
+
+template <typename K>
+void sort_noalloc(hipStream_t s, uint8_t* base, int G, K* keys, K* tmp, uint64_t n, uint32_t key_bits) {
+  using namespace wg;
+  Ctrl* ctrl = (Ctrl*)base;
+  Bufs<K> b;
+  std::memset(&b, 0, sizeof(b));
+  b.cand[0] = keys;
+  b.cand[1] = tmp;
+  b.rcnt = (uint32_t*)(base + kNoAllocCtrlBytes);
+  b.rtot = (uint32_t*)(base + kNoAllocCtrlBytes + kNoAllocCountBytes);
+  // every field the passes read: the size, no halting flags, no one-block sort
+  Ctrl c0;
+  std::memset(&c0, 0, sizeof(c0));
+  c0.m_in = n;
+  launch_ctrl_set(s, ctrl, c0);
+  SortCfg c;
+  c.rb = kNoAllocDigitBits;
+  c.items = sizeof(K) == 4 ? 16 : 8;  // the engine's default tiles
+  c.blocks = G;
+  const int passes = sort_passes((int)key_bits, c.rb);
+  for (int p = 0; p < passes; ++p) {
+    launch_sort_pass<K>(s, ctrl, &ctrl->m_in, c, b, p, false, Ev());
+    launch_sort_pass<K>(s, ctrl, &ctrl->m_in, c, b, p, true, Ev());
+  }
+  if (passes & 1) (void)hipMemcpyAsync(keys, tmp, n * sizeof(K), hipMemcpyDeviceToDevice, s);
+}
+
+}  // namespace
+
+extern "C" wg_status wg_sort_keys_noalloc(void* d_keys, void* d_tmp, uint64_t n, uint32_t key_bytes,
+                                          uint32_t key_bits, void* stream) {
+  if (key_bytes != 4 && key_bytes != 8) {
+    wg::set_call_error("wg_sort_keys_noalloc: key_bytes must be 4 or 8");
+    return WG_ERR_INVALID_ARG;
+  }
+  if (key_bits == 0 || key_bits > 8 * key_bytes) {
+    wg::set_call_error("wg_sort_keys_noalloc: key_bits must be 1..8*key_bytes");
+    return WG_ERR_INVALID_ARG;
+  }
+  if (n > kNoAllocMaxKeys) {
+    wg::set_call_error("wg_sort_keys_noalloc: more than 2^32 - 16 keys");
+    return WG_ERR_INVALID_ARG;
+  }
+  if (n > 0 && (!d_keys || !d_tmp)) {
+    wg::set_call_error("wg_sort_keys_noalloc: NULL key array with n > 0");
+    return WG_ERR_INVALID_ARG;
+  }
+  wg::set_call_error("");
+  if (n <= 1) return WG_OK;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNoAllocMaxDevices) {
+    (void)hipGetLastError();
+    wg::set_call_error("wg_sort_keys_noalloc: no usable current device");
+    return WG_ERR_DEVICE;
+  }
+  uint8_t* base = nullptr;
+  int G = 0;
+  {
+    std::lock_guard<std::mutex> g(g_noalloc_mu);
+    if (!g_noalloc_scratch[dev]) {
+      void* p = nullptr;
+      const hipError_t r = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      int cu = 0;
+      if (r != hipSuccess || !p ||
+          hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        wg::set_call_error("wg_sort_keys_noalloc: hipGetSymbolAddress of the scratch array failed");
+        return WG_ERR_DEVICE;
+      }
+      g_noalloc_blocks[dev] = std::max(1, std::min(4 * std::max(cu, 1), kNoAllocBlocks));
+      g_noalloc_scratch[dev] = p;
+    }
+    base = (uint8_t*)g_noalloc_scratch[dev];
+    G = g_noalloc_blocks[dev];
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if (key_bytes == 4) sort_noalloc<uint32_t>(s, base, G, (uint32_t*)d_keys, (uint32_t*)d_tmp, n, key_bits);
+  else sort_noalloc<uint64_t>(s, base, G, (uint64_t*)d_keys, (uint64_t*)d_tmp, n, key_bits);
+  const hipError_t err = hipGetLastError();
+  if (err != hipSuccess) {
+    wg::set_call_error("wg_sort_keys_noalloc: launch failed");
+    return WG_ERR_DEVICE;
+  }
+  return WG_OK;
+}

@@ -174,6 +174,7 @@ SIGNATURES = [
                              POINTER(c_uint64), POINTER(WgStats)]),
     ("wg_sort_keys", c_int, [c_void_p, c_void_p, c_void_p, c_uint64, c_uint32, c_uint32, POINTER(WgOptions),
                              c_void_p, POINTER(WgStats)]),
+    ("wg_sort_keys_noalloc", c_int, [c_void_p, c_void_p, c_uint64, c_uint32, c_uint32, c_void_p]),
     ("wg_merge_keys", c_int, [c_void_p, c_void_p, c_uint64, c_void_p, c_uint64, c_void_p, c_uint32,
                               POINTER(WgOptions), c_void_p, POINTER(WgStats)]),
     ("wg_result_instances", c_uint32, [c_void_p]),
@@ -290,6 +291,11 @@ def wg_sort_keys(engine, d_keys: int, d_tmp: int, n: int, key_bytes: int, key_bi
     return lib().wg_sort_keys(engine, c_void_p(d_keys), c_void_p(d_tmp), n, key_bytes, key_bits,
                               byref(options) if options is not None else None, c_void_p(stream),
                               byref(stats) if stats is not None else None)
+
+
+def wg_sort_keys_noalloc(d_keys: int, d_tmp: int, n: int, key_bytes: int, key_bits: int, stream: int) -> int:
+    return lib().wg_sort_keys_noalloc(c_void_p(d_keys), c_void_p(d_tmp), n, key_bytes, key_bits,
+                                      c_void_p(stream))
 
 
 def wg_merge_keys(engine, d_a: int, na: int, d_b: int, nb: int, d_out: int, key_bytes: int,
