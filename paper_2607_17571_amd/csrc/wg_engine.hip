@@ -235,12 +235,14 @@ void sync_stream(wg_engine* e) {
   ++e->syncs;
 }
 
-// Grow keeping the first `live` bytes (the old buffer is freed in stream order after the copy).
+// Grow keeping the first `live` bytes.  The copy is waited for before the old buffer is
+// freed, so no buffer is ever released with a read of it still pending (growth is rare).
 void grow_keep(wg_engine* e, DevBuf& b, size_t bytes, size_t live) {
   if (b.bytes >= bytes && b.p) return;
   DevBuf nb;
   alloc_buf(e, nb, bytes);
   if (live && b.p) hip_check(e, hipMemcpyAsync(nb.p, b.p, live, hipMemcpyDeviceToDevice, e->stream), "copy");
+  sync_stream(e);
   free_buf(e, b);
   b = nb;
 }
