@@ -45,6 +45,7 @@ STAGE_KERNELS = {
     "radix_hist": "k_radix_count + k_radix_scan", "radix_pass": "k_radix_scatter",
     "dedup_diff": "k_compact_local + k_compact_gather", "merge": "k_merge",
     "prepare": "k_max_id, k_pack, k_index_*, k_unpack", "seg_sort": "k_seg_sort",
+    "row_diff": "k_row_diff + k_compact_gather",
 }
 WORKLOAD_TEXT = {
     "tc_rmat_s15": "TC, R-MAT scale 15 (n=32,768, m=29,491, a,b,c,d=0.57,0.19,0.19,0.05, seed 2); "

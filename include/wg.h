@@ -74,9 +74,10 @@ typedef enum { WG_QUERY_TC = 0, WG_QUERY_SG = 1, WG_QUERY_TRIANGLES = 2 } wg_que
                                  default; on MI355X both take the same time, since a loop
                                  kernel's own latency, not its launch, bounds small iterations) */
 #define WG_LSD_SORT 0x80u     /* TC: sort every iteration's candidates with the LSD passes of
-                                 Section V-C, never with the segmented sort (which sorts only
-                                 each source row's run, the join having emitted the candidates
-                                 grouped by row) */
+                                 Section V-C and take the difference with the compaction of
+                                 Section IV-B, never with the segmented sort or the row pass
+                                 (which sort only each source row's run, the join having
+                                 emitted the candidates grouped by row) */
 
 /* wg_options.loop_mode */
 #define WG_LOOP_AUTO 0u     /* the default: device-resident loop checked by the host every 2
@@ -127,7 +128,11 @@ enum {
   WG_STAGE_MERGE = 5,      /* disjoint merge-path merge (Section IV-C) */
   WG_STAGE_PREPARE = 6,    /* max-id scan, packing, edge index, result unpack */
   WG_STAGE_SEG_SORT = 7,   /* TC: the segmented sort of a join's row-grouped candidates */
-  WG_NUM_STAGES = 8
+  WG_STAGE_ROW_DIFF = 8,   /* TC: the row pass -- sort, dedup and difference of each row of the
+                              join's row-grouped candidates in one LDS bitmap (Sections IV-B,
+                              V-C), which replaces the sort and the compaction of a large
+                              iteration */
+  WG_NUM_STAGES = 9
 };
 
 typedef struct {

@@ -68,6 +68,7 @@ struct Ctrl {
   uint32_t small_sorted;       // the sort in flight fit one block and is done: the radix
                                // passes of that sort are no-ops
   uint32_t seg_long;           // rows the segmented sort in flight left to its long-row pass
+  uint64_t full_n;             // |Full| after the last completed iteration (the seed: |Delta^0|)
 };
 
 // Kernels of the loop take their iteration from the device, so that one iteration's
@@ -91,6 +92,16 @@ __device__ __forceinline__ uint32_t iter_cur(const Ctrl* c, uint32_t j) {
 // A halted loop turns every later kernel of the batch into a no-op.
 __device__ __forceinline__ bool halted(const Ctrl* c) {
   return (c->done | c->overflow | c->limit_hit) != 0;
+}
+
+// An iteration enqueued with both routes (gate 1: the row route, 2: the sort route; 0: no
+// gate): the join's candidate count picks one -- the rows from `row_min` candidates on and
+// while they are at least as many as the tuples of Full (the row pass streams each touched
+// row of Full, the compaction only the windows its candidates span).
+__device__ __forceinline__ bool gated_out(const Ctrl* c, int gate, uint64_t row_min) {
+  if (gate == 0) return false;
+  const bool row = c->cand_n >= row_min && c->cand_n >= c->full_n;
+  return gate == 1 ? !row : row;
 }
 
 constexpr uint64_t kValMask = (1ull << 40) - 1;

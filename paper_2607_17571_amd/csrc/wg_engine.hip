@@ -42,13 +42,19 @@ constexpr uint32_t kSpec = 4;                 // speculative iterations behind e
 constexpr uint32_t kAutoK = 2;                // iterations per host check of the default loop
 constexpr uint64_t kNarrowBelow = 1ull << 21;  // candidates below which the narrow tiles win
 constexpr uint64_t kSegBelow = 1ull << 22;     // ... and the segmented sort beats the LSD passes
-enum : uint8_t { kSortLsd = 0, kSortSmall = 1, kSortOneBlock = 2, kSortSegmented = 3 };
+// kSortDual / kSortDualLsd: both routes, the row pass or the segmented sort / the LSD passes
+enum : uint8_t { kSortLsd = 0, kSortSmall = 1, kSortOneBlock = 2, kSortSegmented = 3, kSortDual = 4,
+                 kSortDualLsd = 5 };
+// iterations expected to reach this many candidates are enqueued with both routes (the row
+// pass and the segmented sort + compaction), the device picking one by kRowMin
+constexpr uint64_t kDualAbove = kRowMin / 8;
 constexpr uint64_t kDenseRowsMax = 1ull << 28;  // largest dense edge index (1 GB)
 // fixed arrays of an engine: control block, join and compaction block totals, radix counts
 // and totals (the triangle hits depend on the grid)
-constexpr size_t kFixedBytes[5] = {sizeof(Ctrl), sizeof(uint64_t) * kScanBlocksMax,
+constexpr size_t kFixedBytes[6] = {sizeof(Ctrl), sizeof(uint64_t) * kScanBlocksMax,
                                    sizeof(uint64_t) * kScanBlocksMax,
-                                   sizeof(uint32_t) * kRadixMax * kRadixBlocksMax, sizeof(uint32_t) * kRadixMax};
+                                   sizeof(uint32_t) * kRadixMax * kRadixBlocksMax, sizeof(uint32_t) * kRadixMax,
+                                   sizeof(uint64_t) * kScanBlocksMax};
 
 thread_local std::string wg_call_error;  // see set_call_error
 
@@ -77,6 +83,7 @@ struct wg_engine {
   bool done_pending = false;
   uint64_t* d_jtot = nullptr;
   uint64_t* d_bcnt = nullptr;
+  uint64_t* d_bstart = nullptr;  // row pass: output start of each block
   uint32_t* d_rcnt = nullptr;
   uint32_t* d_rtot = nullptr;
   uint64_t* d_hits = nullptr;  // triangle probe: hits per emit block (grid.stream entries)
@@ -93,6 +100,10 @@ struct wg_engine {
   // of the LSD passes
   bool seg_sort = false;
   bool seg_long = false;  // the segmented sort hands long rows to its LDS radix pass
+  // TC: the loop's iterations are enqueued with both routes -- the row pass (sort, dedup and
+  // difference per row in an LDS bitmap) and the segmented sort + compaction -- and the
+  // device takes the row pass from kRowMin candidates on
+  bool row_bitmap = false;
   // how each iteration of the solve sorted its candidates (the method of its last
   // enqueue): kSortLsd, kSortSmall (one-block sort alone), kSortOneBlock (join and sort in
   // one block), kSortSegmented
@@ -332,6 +343,7 @@ Bufs<K> make_bufs(wg_engine* e) {
   b.off = (uint32_t*)e->off.p;
   b.jtot = e->d_jtot;
   b.bcnt = e->d_bcnt;
+  b.bstart = e->d_bstart;
   b.rcnt = e->d_rcnt;
   b.rtot = e->d_rtot;
   b.hits = e->d_hits;
@@ -402,6 +414,7 @@ void stage_probe(wg_engine* e, const uint64_t* d_size) {
 uint8_t sort_method(const wg_engine* e, int kind) {
   if (e->small_mode == 3 && !e->hash_slots && !e->stage_sync) return kSortOneBlock;
   if (e->small_mode == 2) return kSortSmall;
+  if (e->row_bitmap && kind == kJoinTC && !e->hash_slots) return e->seg_sort ? kSortDual : kSortDualLsd;
   if (e->seg_sort && kind == kJoinTC && !e->hash_slots) return kSortSegmented;
   return kSortLsd;
 }
@@ -427,6 +440,28 @@ void enqueue_iteration(wg_engine* e, const Bufs<K>& b, int kind, int w, int pass
                         e->narrow);
   }
   if (e->stage_sync) stage_probe(e, &b.rec[j].C);
+  if (method == kSortDual || method == kSortDualLsd) {
+    // both routes, gated on the join's candidate count: the row pass (sort, dedup and
+    // difference of each row in one pass over cand[0]), or the sort the host picked for
+    // this size (segmented, or the LSD passes, which a row pass turns into no-ops) and the
+    // compaction
+    launch_row_diff<K>(e->stream, e->grid, e->d_ctrl, C, b, w, jd, stage(e, WG_STAGE_ROW_DIFF), 1);
+    if (method == kSortDual) {
+      launch_seg_sort<K>(e->stream, e->grid, e->d_ctrl, C, b, w, passes, e->seg_long,
+                         stage(e, WG_STAGE_SEG_SORT), 2);
+    } else {
+      for (int pp = 0; pp < passes; ++pp) {
+        launch_sort_pass<K>(e->stream, e->d_ctrl, C, e->sort, b, pp, false, stage(e, WG_STAGE_RADIX_HIST));
+        launch_sort_pass<K>(e->stream, e->d_ctrl, C, e->sort, b, pp, true, stage(e, WG_STAGE_RADIX_PASS));
+      }
+    }
+    const uint32_t ps = (uint32_t)passes & 1u;
+    launch_compact<K>(e->stream, e->grid, kModeIter | kModeGateSort, e->d_ctrl, C, b.cand[ps], b.cand[ps ^ 1u], b,
+                      w, jd, 0, stage(e, WG_STAGE_DEDUP_DIFF), e->narrow);
+    launch_row_gather<K>(e->stream, e->grid, e->d_ctrl, C, b, jd, stage(e, WG_STAGE_ROW_DIFF), 1);
+    launch_merge<K>(e->stream, e->grid, e->d_ctrl, b, jd, stage(e, WG_STAGE_MERGE));
+    return;
+  }
   if (method == kSortSegmented)
     launch_seg_sort<K>(e->stream, e->grid, e->d_ctrl, C, b, w, passes, e->seg_long, stage(e, WG_STAGE_SEG_SORT));
   else if (!one_block)
@@ -454,7 +489,7 @@ struct IterGraphKey {
   SortCfg sort;
   Grid grid;
   uint64_t hash_slots;
-  int unfused, small_mode, narrow, seg_sort, seg_long;
+  int unfused, small_mode, narrow, seg_sort, seg_long, row_bitmap;
 };
 
 template <typename K>
@@ -474,6 +509,7 @@ hipGraphExec_t iteration_graph(wg_engine* e, const Bufs<K>& b, int kind, int w, 
   key.narrow = e->narrow ? 1 : 0;
   key.seg_sort = e->seg_sort ? 1 : 0;
   key.seg_long = e->seg_long ? 1 : 0;
+  key.row_bitmap = e->row_bitmap ? 1 : 0;
   if (e->graph_exec && e->graph_key.size() == sizeof(key) &&
       std::memcmp(e->graph_key.data(), &key, sizeof(key)) == 0)
     return e->graph_exec;
@@ -602,10 +638,22 @@ void bytes_model(wg_stats* st, int query, uint32_t kb, int passes, uint64_t m,
   for (size_t i = 1; i < rec.size(); ++i) {
     const double D = (double)rec[i - 1].N, c = (double)rec[i].C, n = (double)rec[i].N;
     const double F = (double)rec[i - 1].F;
-    const uint8_t sorted_by = i < how.size() ? how[i] : kSortLsd;
+    uint8_t sorted_by = i < how.size() ? how[i] : kSortLsd;
+    // an iteration enqueued with both routes: the device took the rows when the join found
+    // at least kRowMin candidates and no fewer than Full's tuples
+    const bool rows = (sorted_by == kSortDual || sorted_by == kSortDualLsd) && rec[i].C >= kRowMin &&
+                      rec[i].C >= rec[i - 1].F;
+    if (sorted_by == kSortDual) sorted_by = kSortSegmented;
+    if (sorted_by == kSortDualLsd) sorted_by = kSortLsd;
     if (sorted_by == kSortOneBlock) {
       // one kernel (timed as the emit): read delta and E.dst, write the sorted candidates
       add_bytes(st, WG_STAGE_JOIN_EMIT, D * kb + c * (edst + kb));
+    } else if (rows) {
+      // join as usual; the row pass reads the candidates and the rows of Full they touch
+      // (at most all of Full) and writes the new delta, which the gather moves once more
+      add_bytes(st, WG_STAGE_JOIN_COUNT, D * (kb + 4.0));
+      add_bytes(st, WG_STAGE_JOIN_EMIT, D * (kb + 4.0) + c * (edst + kb));
+      add_bytes(st, WG_STAGE_ROW_DIFF, (c + F + 3.0 * n) * kb);
     } else {
       add_bytes(st, WG_STAGE_JOIN_COUNT, D * (kb + 4.0));
       add_bytes(st, WG_STAGE_JOIN_EMIT, D * (kb + 4.0) + c * (edst + kb));
@@ -618,7 +666,7 @@ void bytes_model(wg_stats* st, int query, uint32_t kb, int passes, uint64_t m,
         add_bytes(st, WG_STAGE_RADIX_PASS, 2.0 * c * kb * passes);
       }
     }
-    add_bytes(st, WG_STAGE_DEDUP_DIFF, (c + n) * kb);
+    if (!rows) add_bytes(st, WG_STAGE_DEDUP_DIFF, (c + n) * kb);
     // the merge: delta into run B, or on a fold B into A plus the delta as the new B
     const double FA = (double)rec[i - 1].FA, FB = F - FA;
     if (rec[i].fold) add_bytes(st, WG_STAGE_MERGE, 2.0 * (FA + FB + n) * kb);
@@ -802,6 +850,10 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   bool small_missed = false;
   // within a quarter of a limit, or half of it and not growing
   bool seg_allowed = query == WG_QUERY_TC && !(o.flags & WG_LSD_SORT);
+  // the row pass: one instance (at most 2^w rows, so a large iteration has long rows), ids
+  // within the LDS bitmap, the fused compaction
+  const bool row_allowed = seg_allowed && e->num_inst <= 1 && w <= kRowBitsMax && !e->unfused &&
+                           !e->stage_sync && !e->hash_slots;
   bool long_forced = false;  // a row outgrew the bitonic network: long-row pass from now on
   auto calm = [&](uint64_t now, uint64_t before, uint64_t limit) {
     return 4 * now <= limit || (2 * now <= limit && now <= before);
@@ -816,7 +868,8 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
     const double ahead = (double)x.C * g * g * g * g;
     e->narrow = ahead < (double)kNarrowBelow;
     e->seg_sort = seg_allowed && ahead < (double)kSegBelow;
-    e->seg_long = e->seg_sort && long_forced;
+    e->row_bitmap = row_allowed && seg_allowed && ahead >= (double)kDualAbove;
+    e->seg_long = (e->seg_sort || e->row_bitmap) && long_forced;
     if (!small_missed && K_batch <= kAutoK && it >= 2 && calm(x.C, y.C, small_keys))
       e->small_mode = calm(x.N, y.N, kSmallJoinTuples) ? 3 : 2;
     else
@@ -830,6 +883,8 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   // LSD passes for the rest of the solve; the first batch, sizes unknown, takes the LSD
   // passes
   e->seg_sort = e->seg_long = false;
+  // (the first batch, sizes unknown, takes both routes where the row pass is allowed)
+  e->row_bitmap = row_allowed;
   enqueue_batch(K_batch, slot);
   for (;;) {
     // While the host waits on this batch, the device runs a short speculative batch
@@ -855,9 +910,9 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
         // beyond even that pass (or a second overflow) leaves the LSD passes
         if (!long_forced) {
           long_forced = true;
-          e->seg_long = e->seg_sort;
+          e->seg_long = e->seg_sort || e->row_bitmap;
         } else {
-          seg_allowed = e->seg_sort = e->seg_long = false;
+          seg_allowed = e->seg_sort = e->seg_long = e->row_bitmap = false;
         }
       }
       grow_and_resume(e, r.c, hooked);
@@ -1322,6 +1377,7 @@ wg_status wg_engine_create_ex(int device, const wg_allocator* allocator, wg_engi
     fixed((void**)&e->d_rcnt, kFixedBytes[3]);
     fixed((void**)&e->d_rtot, kFixedBytes[4]);
     fixed((void**)&e->d_hits, sizeof(uint64_t) * e->grid.stream);
+    fixed((void**)&e->d_bstart, kFixedBytes[5]);
     hip_check(e, hipHostMalloc((void**)&e->h_rb, 3 * sizeof(Readback)), "hipHostMalloc");
     hip_check(e, hipMemsetAsync(e->d_ctrl, 0, sizeof(Ctrl), nullptr), "hipMemsetAsync");
     for (int s = 0; s < 2; ++s)
@@ -1367,6 +1423,7 @@ void wg_engine_destroy(wg_engine* e) {
   dev_free(e, e->d_rcnt, kFixedBytes[3], nullptr);
   dev_free(e, e->d_rtot, kFixedBytes[4], nullptr);
   dev_free(e, e->d_hits, sizeof(uint64_t) * e->grid.stream, nullptr);
+  dev_free(e, e->d_bstart, kFixedBytes[5], nullptr);
   if (e->h_rb) (void)hipHostFree(e->h_rb);
   if (e->h_rec) (void)hipHostFree(e->h_rec);
   for (int s = 0; s < 2; ++s)

@@ -889,7 +889,7 @@ constexpr uint32_t kSegBitonicMax = 2 * kSegTile;  // longest range sorted by th
 constexpr uint32_t kSegLongBytes = 131072;         // LDS of k_seg_long's row (32K / 16K keys)
 
 template <typename K>
-__global__ __launch_bounds__(kSmallSortThreads) void k_seg_sort(Ctrl* ctrl, const uint64_t* n_ptr,
+__global__ __launch_bounds__(kSmallSortThreads) void k_seg_sort(int gate, Ctrl* ctrl, const uint64_t* n_ptr,
                                                                 const K* in, K* out, int w,
                                                                 uint32_t* __restrict__ queue,
                                                                 int long_ok) {
@@ -901,7 +901,7 @@ __global__ __launch_bounds__(kSmallSortThreads) void k_seg_sort(Ctrl* ctrl, cons
   __shared__ K s[CAP];
   __shared__ uint32_t s_first, s_last;
   __shared__ uint64_t s_end;
-  if (halted(ctrl)) return;
+  if (halted(ctrl) || gated_out(ctrl, gate, kRowMin)) return;
   const uint64_t n = *n_ptr;
   const uint64_t ntiles = (n + kSegTile - 1) / kSegTile;
   const uint32_t t = threadIdx.x;
@@ -970,7 +970,7 @@ __global__ __launch_bounds__(kSmallSortThreads) void k_seg_sort(Ctrl* ctrl, cons
 // ranking.  A 32-bit-key row of up to 32K keys thus moves through HBM once instead of
 // through four global passes and their counts.
 template <typename K>
-__global__ __launch_bounds__(kSmallSortThreads) void k_seg_long(Ctrl* ctrl, const K* in, K* out, int w,
+__global__ __launch_bounds__(kSmallSortThreads) void k_seg_long(int gate, Ctrl* ctrl, const K* in, K* out, int w,
                                                                 const uint32_t* __restrict__ queue) {
   constexpr uint32_t TH = kSmallSortThreads;
   constexpr int NW = (int)TH / kWave;
@@ -982,7 +982,7 @@ __global__ __launch_bounds__(kSmallSortThreads) void k_seg_long(Ctrl* ctrl, cons
   __shared__ K s_k[LCAP];
   __shared__ uint32_t s_cnt[NW][R];
   __shared__ uint32_t s_wave[NW];
-  if (halted(ctrl)) return;
+  if (halted(ctrl) || gated_out(ctrl, gate, kRowMin)) return;
   const uint32_t rows = ctrl->seg_long;
   const int passes = w > RB ? (w + RB - 1) / RB : 1;
   const int tid = threadIdx.x;
@@ -1493,6 +1493,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_local(Ctrl* ctrl, int mode, 
   __shared__ uint64_t s_lo[2], s_hi[2];
   const bool filt = (mode & kModeFilter) != 0;
   if (!filt && halted(ctrl)) return;
+  if (gated_out(ctrl, (mode & kModeGateRow) ? 1 : ((mode & kModeGateSort) ? 2 : 0), kRowMin)) return;
   j = iter_cur(ctrl, j);
   const uint64_t n = *n_ptr;
   uint64_t lo, hi;
@@ -1658,6 +1659,231 @@ __global__ __launch_bounds__(kBlock) void k_compact_local(Ctrl* ctrl, int mode, 
   if (threadIdx.x == 0) b.bcnt[blockIdx.x] = running;
 }
 
+// ---------------------------------------------------------------------------
+// Row-bitmap sort + dedup + set difference (TC, ids of at most kRowBitsMax bits): the
+// segmented dst-only sort of Section V-C carried through the difference of Section IV-B.
+// The join writes each delta tuple's slab in delta order and the delta is sorted, so the
+// candidates come grouped by row (key >> w: instance and src) in ascending row order; only
+// their order within a row is open.  A row's keys share their upper bits, so the row is a
+// set of at most 2^w dst values: one bit each in an LDS bitmap.  Block b owns the rows
+// that start in its static range of positions.  For each row it streams the row's
+// candidates into one bitmap (LDS atomic OR: duplicates collapse), the row's keys of Full
+// runs A and B into another, and writes the bits of cand & ~full in bit order -- the row's
+// new tuples, sorted and duplicate-free -- one survivor per thread and step, so writes
+// coalesce.  Full's cursors advance with the rows (a row's keys of A and B are contiguous
+// and rows ascend); a row not right after the previous one is found by a wave search.
+// Survivors go to tmp from the block's first row start on (its rows' candidate span, which
+// no other block's span overlaps), counted in bcnt with the start in bstart, for the
+// gather.  This replaces the LSD passes and the compaction of such an iteration with one
+// streaming pass over its candidates and the rows of Full they touch.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kRowWordsMax = (1u << kRowBitsMax) / 32;
+constexpr uint32_t kRowTile = kBlock * 16;  // keys streamed per round
+
+// Position of the k-th set bit (k = 0 the lowest) of v, which has more than k set bits.
+__device__ __forceinline__ uint32_t nth_set_bit(uint32_t v, uint32_t k) {
+  uint32_t pos = 0;
+  uint32_t c = (uint32_t)__popc(v & 0xFFFFu);
+  if (k >= c) { k -= c; v >>= 16; pos += 16; }
+  c = (uint32_t)__popc(v & 0xFFu);
+  if (k >= c) { k -= c; v >>= 8; pos += 8; }
+  c = (uint32_t)__popc(v & 0xFu);
+  if (k >= c) { k -= c; v >>= 4; pos += 4; }
+  c = (uint32_t)__popc(v & 0x3u);
+  if (k >= c) { k -= c; v >>= 2; pos += 2; }
+  if (k >= (v & 1u)) pos += 1;
+  return pos;
+}
+
+// Set the bits of sorted, distinct keys held by consecutive lanes (bit d of bm for every
+// lane with `valid`): the lanes of one word form a run of at most 32, whose bits a shuffle
+// scan gathers into its last lane, which alone writes -- one LDS atomic per word instead
+// of up to 32 queued on one address (a row of Full late in a fixpoint is long runs of
+// consecutive ids).
+__device__ __forceinline__ void or_sorted_runs(uint32_t* bm, bool valid, uint32_t d) {
+  const int lane = lane_id();
+  const uint32_t word = valid ? (d >> 5) : 0xFFFFFFFFu;
+  uint32_t acc = valid ? (1u << (d & 31u)) : 0u;
+#pragma unroll
+  for (int off = 1; off < 32; off <<= 1) {
+    const uint32_t o = __shfl_up(acc, off, kWave);
+    const uint32_t ow = __shfl_up(word, off, kWave);
+    if (lane >= off && ow == word) acc |= o;
+  }
+  const uint32_t next = __shfl_down(word, 1, kWave);
+  if (valid && (lane == kWave - 1 || next != word)) atomicOr(&bm[word], acc);
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_row_diff(int gate, Ctrl* ctrl, const uint64_t* n_ptr,
+                                                     const K* __restrict__ in, K* __restrict__ tmp, Bufs<K> b,
+                                                     int w, uint32_t j) {
+  __shared__ uint32_t s_cb[kRowWordsMax];   // the row's candidate bits, then its new bits
+  __shared__ uint32_t s_fb[kRowWordsMax];   // the row's bits of Full
+  __shared__ uint32_t s_pre[kRowWordsMax];  // new bits in the words before each word
+  __shared__ uint32_t s_wave[kWavesPerBlock];
+  __shared__ uint64_t s_at[3];              // broadcast of wave searches
+  if (halted(ctrl) || gated_out(ctrl, gate, kRowMin)) return;
+  // this iteration needs no sort: LSD passes enqueued behind (the other route) are no-ops
+  // (the gather clears the flag)
+  if (gate != 0 && blockIdx.x == 0 && threadIdx.x == 0) ctrl->small_sorted = 1;
+  j = iter_cur(ctrl, j);
+  const uint64_t n = *n_ptr;
+  const uint32_t tid = threadIdx.x;
+  const int wid = (int)(tid / kWave);
+  uint64_t lo, hi;
+  // ranges of whole tiles, or a smaller input spread evenly over the grid (each block then
+  // owns the few rows that start in its range)
+  block_range(n, compact_span(n, kRowTile, gridDim.x), lo, hi);
+  // the first row that starts in [lo, hi)
+  uint64_t p = lo;
+  if (lo < hi && lo > 0) {
+    const K before = in[lo - 1] >> w;
+    if ((in[lo] >> w) == before) {
+      if (wid == 0) {
+        const uint64_t v = wave_partition(lo, hi, [&](uint64_t i) { return (in[i] >> w) == before; });
+        if (lane_id() == 0) s_at[0] = v;
+      }
+      __syncthreads();
+      p = s_at[0];
+      __syncthreads();
+    }
+  }
+  const uint64_t out0 = p;
+  uint64_t running = 0;
+  if (p < hi) {
+    const IterRec rp = b.rec[j - 1];
+    const K* __restrict__ runA = b.full[rp.a];
+    const K* __restrict__ runB = b.fullB[rp.b];
+    const uint64_t FA = rp.FA, FB = rp.F - rp.FA;
+    const uint32_t words = w > 5 ? 1u << (w - 5) : 1u;
+    const K fmask = field_mask<K>(w);
+    // Full's cursors at the first row's keys
+    {
+      const K first = (in[p] >> w) << w;
+      if (wid == 0) {
+        const uint64_t v = wave_lower_bound(runA, FA, first);
+        if (lane_id() == 0) s_at[1] = v;
+      } else if (wid == 1) {
+        const uint64_t v = wave_lower_bound(runB, FB, first);
+        if (lane_id() == 0) s_at[2] = v;
+      }
+      __syncthreads();
+    }
+    uint64_t pa = s_at[1], pb = s_at[2];
+    // Set the bits of row rk's keys in X[from, nx) into bm, tile by tile; returns the position
+    // past them.  Rows ascend and X[from] is the row's first key or later, so in every tile
+    // the row's keys are a prefix: the row ends where a tile holds fewer than it could.
+    // `check`: a key whose bit is already set in s_fb or bm (a duplicate, or a tuple of
+    // Full) skips the atomic -- a plain LDS read, which lanes of one word share.
+    auto stream_row = [&](const K* __restrict__ X, uint64_t nx, uint64_t from, K rk, uint32_t* bm,
+                          bool check) -> uint64_t {
+      for (uint64_t q = from;; q += kRowTile) {
+        uint32_t mine = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const uint64_t i = q + (uint64_t)k * kBlock + tid;
+          bool in_row = false;
+          uint32_t d = 0;
+          if (i < nx) {
+            const K key = X[i];
+            in_row = (key >> w) == rk;
+            d = (uint32_t)(key & fmask);
+          }
+          mine += in_row ? 1u : 0u;
+          if (check) {
+            // candidates: a bit already set (a duplicate, or a tuple of Full) costs a read
+            bool want = in_row;
+            if (want) want = !(((s_fb[d >> 5] | bm[d >> 5]) >> (d & 31u)) & 1u);
+            if (want) atomicOr(&bm[d >> 5], 1u << (d & 31u));
+          } else {
+            or_sorted_runs(bm, in_row, d);  // Full: sorted, distinct, in lane order
+          }
+        }
+        uint32_t got;
+        (void)block_excl_scan<uint32_t>(mine, s_wave, got);  // (two barriers)
+        const uint64_t avail = nx > q ? min<uint64_t>(nx - q, kRowTile) : 0;
+        if (got < avail || q + kRowTile >= nx) return q + got;
+      }
+    };
+    while (p < hi) {
+      const K rk = in[p] >> w;
+      for (uint32_t x = tid; x < words; x += kBlock) {
+        s_cb[x] = 0u;
+        s_fb[x] = 0u;
+      }
+      __syncthreads();
+      // Full's keys of this row first: a row not right after a cursor's is found by a wave
+      // search (the keys in between belong to rows without candidates here)
+      const bool seek_a = pa < FA && (runA[pa] >> w) < rk;
+      const bool seek_b = pb < FB && (runB[pb] >> w) < rk;
+      if (seek_a || seek_b) {
+        if (wid == 0 && seek_a) {
+          const uint64_t v = wave_partition(pa, FA, [&](uint64_t i) { return (runA[i] >> w) < rk; });
+          if (lane_id() == 0) s_at[1] = v;
+        } else if (wid == 1 && seek_b) {
+          const uint64_t v = wave_partition(pb, FB, [&](uint64_t i) { return (runB[i] >> w) < rk; });
+          if (lane_id() == 0) s_at[2] = v;
+        }
+        __syncthreads();
+        if (seek_a) pa = s_at[1];
+        if (seek_b) pb = s_at[2];
+      }
+      pa = stream_row(runA, FA, pa, rk, s_fb, false);
+      pb = stream_row(runB, FB, pb, rk, s_fb, false);
+      // then the candidates: only bits in neither bitmap are set
+      const uint64_t row_end = stream_row(in, n, p, rk, s_cb, true);
+      // new bits: candidates not in Full, numbered in bit order (thread t takes wpt
+      // consecutive words, so the scan of the per-thread counts is in word order)
+      const uint32_t wpt = words >= kBlock ? words / kBlock : 1u;
+      uint32_t cnt = 0;
+      for (uint32_t q = 0; q < wpt; ++q) {
+        const uint32_t x = tid * wpt + q;
+        if (x < words) {
+          const uint32_t nw = s_cb[x] & ~s_fb[x];
+          s_cb[x] = nw;
+          cnt += (uint32_t)__popc(nw);
+        }
+      }
+      uint32_t total;
+      uint32_t before = block_excl_scan<uint32_t>(cnt, s_wave, total);
+      for (uint32_t q = 0; q < wpt; ++q) {
+        const uint32_t x = tid * wpt + q;
+        if (x < words) {
+          s_pre[x] = before;
+          before += (uint32_t)__popc(s_cb[x]);
+        }
+      }
+      __syncthreads();
+      const K rlo = rk << w;
+      for (uint32_t idx = tid; idx < total; idx += kBlock) {
+        // the last word whose prefix is <= idx (equal prefixes belong to empty words before
+        // the one holding survivor idx)
+        uint32_t a = 0, len = words;
+        while (len > 0) {
+          const uint32_t half = len >> 1;
+          if (s_pre[a + half] <= idx) {
+            a += half + 1;
+            len -= half + 1;
+          } else {
+            len = half;
+          }
+        }
+        const uint32_t x = a - 1;
+        const uint32_t bit = nth_set_bit(s_cb[x], idx - s_pre[x]);
+        tmp[out0 + running + idx] = rlo | (K)(x * 32u + bit);
+      }
+      running += total;
+      p = row_end;
+      __syncthreads();
+    }
+  }
+  if (tid == 0) {
+    b.bcnt[blockIdx.x] = running;
+    b.bstart[blockIdx.x] = out0;
+  }
+}
+
 template <typename K, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_compact_gather(Ctrl* ctrl, int mode, const uint64_t* n_ptr,
                                                            const K* __restrict__ tmp, Bufs<K> b,
@@ -1667,6 +1893,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_gather(Ctrl* ctrl, int mode,
   __shared__ uint64_t s_wave[kWavesPerBlock];
   const bool filt = (mode & kModeFilter) != 0;
   if (!filt && halted(ctrl)) return;
+  if (gated_out(ctrl, (mode & kModeGateRow) ? 1 : ((mode & kModeGateSort) ? 2 : 0), kRowMin)) return;
   j = iter_cur(ctrl, j);
   // the sort before this compaction is over: a later sort that skips the one-block path
   // must not find its flag (nothing else in this launch reads it)
@@ -1679,6 +1906,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_gather(Ctrl* ctrl, int mode,
   const uint64_t N = block_prefix(b.bcnt, gridDim.x, s_pre, s_wave);
   uint64_t lo, hi;
   block_range(n, compact_span(n, T, gridDim.x), lo, hi);
+  if (mode & kModeRows) lo = b.bstart[blockIdx.x];  // the row pass keeps its own starts
   K* out1 = nullptr;
   K* out2 = nullptr;
   K* out3 = nullptr;
@@ -1737,6 +1965,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_gather(Ctrl* ctrl, int mode,
       r.b = N > 0 ? (rp.b ^ 1u) : rp.b;
       r.fold = fold ? 1u : 0u;
       ctrl->iter = j;
+      ctrl->full_n = F + N;
       if (N == 0) ctrl->done = 1;
       else if (ctrl->max_iter != 0 && j >= ctrl->max_iter) ctrl->limit_hit = 1;
     } else if (mode & (kModeEdges | kModeSeed)) {
@@ -1750,6 +1979,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_gather(Ctrl* ctrl, int mode,
         r.b = 0;
         r.fold = 0;
         ctrl->iter = 0;
+        ctrl->full_n = N;
         if (N == 0) ctrl->done = 1;
       }
     } else if (mode & kModeDedup) {
@@ -2260,16 +2490,16 @@ void sort_pass_impl(hipStream_t s, Ctrl* ctrl, const uint64_t* n_ptr, int G, con
 
 template <typename K>
 void launch_seg_sort(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint64_t* n_ptr, const Bufs<K>& b, int w,
-                     int passes, bool long_rows, Ev ev) {
+                     int passes, bool long_rows, Ev ev, int gate) {
   const int G = std::max(1, g.scan / 2);
   K* out = b.cand[passes & 1];
   const hipEvent_t none = nullptr;
   // the long-row queue lives in b.off, free between the emit that fills it per delta tuple
   // and the next iteration's join count (at most n / kSegBitonicMax rows of three words)
-  WG_LAUNCH_WIDE((k_seg_sort<K>), G, ev.start, long_rows ? none : ev.stop, s, ctrl, n_ptr, (const K*)b.cand[0],
+  WG_LAUNCH_WIDE((k_seg_sort<K>), G, ev.start, long_rows ? none : ev.stop, s, gate, ctrl, n_ptr, (const K*)b.cand[0],
                  out, w, b.off, long_rows ? 1 : 0);
   if (long_rows)
-    WG_LAUNCH_WIDE((k_seg_long<K>), g.scan, none, ev.stop, s, ctrl, (const K*)b.cand[0], out, w,
+    WG_LAUNCH_WIDE((k_seg_long<K>), g.scan, none, ev.stop, s, gate, ctrl, (const K*)b.cand[0], out, w,
                    (const uint32_t*)b.off);
 }
 
@@ -2344,6 +2574,20 @@ void launch_compact(hipStream_t s, const Grid& g, int mode, Ctrl* ctrl, const ui
 }
 
 template <typename K>
+void launch_row_diff(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint64_t* n_ptr, const Bufs<K>& b, int w,
+                     uint32_t j, Ev ev, int gate) {
+  WG_LAUNCH((k_row_diff<K>), g.scan, ev.start, ev.stop, s, gate, ctrl, n_ptr, (const K*)b.cand[0], b.cand[1], b, w,
+            j);
+}
+
+template <typename K>
+void launch_row_gather(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint64_t* n_ptr, const Bufs<K>& b,
+                       uint32_t j, Ev ev, int gate) {
+  WG_LAUNCH((k_compact_gather<K, kDedupItems>), g.scan, ev.start, ev.stop, s, ctrl,
+            kModeIter | kModeRows | (gate == 1 ? kModeGateRow : 0), n_ptr, (const K*)b.cand[1], b, j, 0u);
+}
+
+template <typename K>
 void launch_merge(hipStream_t s, const Grid& g, Ctrl* ctrl, const Bufs<K>& b, uint32_t j, Ev ev) {
   WG_LAUNCH((k_merge<K, kMergeItems>), g.stream, ev.start, ev.stop, s, ctrl, b, j);
 }
@@ -2399,12 +2643,16 @@ void launch_resume(hipStream_t s, Ctrl* ctrl, uint64_t cand_cap, uint64_t full_c
   template void launch_small_sort<K>(hipStream_t, Ctrl*, const uint64_t*, const Bufs<K>&, int, bool, Ev); \
   template void launch_small_join<K>(hipStream_t, int, Ctrl*, const Bufs<K>&, int, uint32_t, int, Ev); \
   template void launch_seg_sort<K>(hipStream_t, const Grid&, Ctrl*, const uint64_t*, const Bufs<K>&, int, int, bool, \
-                                   Ev);                                                            \
+                                   Ev, int);                                                       \
   template void launch_sort_pass<K>(hipStream_t, Ctrl*, const uint64_t*, const SortCfg&,         \
                                     const Bufs<K>&, int, bool, Ev);                                \
   template void launch_compact<K>(hipStream_t, const Grid&, int, Ctrl*, const uint64_t*, const K*, \
                                   K*, const Bufs<K>&, int, uint32_t, uint32_t, Ev, bool);          \
   template void launch_merge<K>(hipStream_t, const Grid&, Ctrl*, const Bufs<K>&, uint32_t, Ev);   \
+  template void launch_row_diff<K>(hipStream_t, const Grid&, Ctrl*, const uint64_t*, const Bufs<K>&, int, \
+                                   uint32_t, Ev, int);                                             \
+  template void launch_row_gather<K>(hipStream_t, const Grid&, Ctrl*, const uint64_t*, const Bufs<K>&,  \
+                                     uint32_t, Ev, int);                                           \
   template void launch_hash_build<K>(hipStream_t, const Grid&, Ctrl*, const Bufs<K>&, int, uint64_t, Ev); \
   template void launch_join_hash<K>(hipStream_t, const Grid&, int, Ctrl*, const Bufs<K>&, int, uint32_t, \
                                     uint64_t, Ev, Ev);                                             \

@@ -22,7 +22,22 @@ enum CompactMode : int {
   // unfused variant: sorted candidates in cand[side] -> deduplicated in place, count ->
   // dedup_n; a kModeIter pass over them then takes the set difference alone
   kModeDedup = 16,
+  // with kModeIter: the survivors come from the row pass (k_row_diff), whose blocks keep
+  // their own output starts in bstart
+  kModeRows = 32,
+  // gates of an iteration enqueued with both routes (see kRowMin): run only on the row route,
+  // or only on the sort route
+  kModeGateRow = 64,
+  kModeGateSort = 128,
 };
+
+// Row pass (TC): ids of at most this many bits get a bitmap per row in LDS.
+constexpr int kRowBitsMax = 16;
+// A TC iteration may be enqueued with both routes -- the row pass, and the segmented sort
+// plus compaction -- when the host cannot tell its size yet: the kernels of each route read
+// the join's candidate count and return at once unless it picks their route (the row pass
+// from kRowMin candidates on).  gate: 0 none, 1 the row route, 2 the sort route.
+constexpr uint64_t kRowMin = 1ull << 21;
 
 // Tile sizes (items per tile) of the static-range kernels.
 constexpr int kJoinItems = 8;
@@ -85,6 +100,7 @@ struct Bufs {
   uint32_t* off;   // per delta tuple: first candidate, relative to its block's range
   uint64_t* jtot;  // per join-count block: candidates of its range
   uint64_t* bcnt;  // per compaction block: survivors of its range
+  uint64_t* bstart; // per row-pass block: first position of its survivors in the scratch
   uint64_t* hits;  // triangle probe: closing edges found per emit block
   uint64_t* htab;  // hash-join variant: open-addressing table of E (power-of-two slots)
   uint32_t* rcnt;  // radix: per-block digit counts, then offsets (digits x blocks)
@@ -152,7 +168,7 @@ void launch_small_join(hipStream_t s, int kind, Ctrl* ctrl, const Bufs<K>& b, in
 // holds sets overflow bit 4.
 template <typename K>
 void launch_seg_sort(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint64_t* n_ptr, const Bufs<K>& b, int w,
-                     int passes, bool long_rows, Ev ev = Ev());
+                     int passes, bool long_rows, Ev ev = Ev(), int gate = 0);
 
 // One LSD pass over *n_ptr keys: pass p reads cand[p & 1] and writes cand[(p + 1) & 1];
 // digit p covers bits [p * c.rb, (p + 1) * c.rb).  `scatter` false: the count and scan
@@ -168,6 +184,18 @@ template <typename K>
 void launch_compact(hipStream_t s, const Grid& g, int mode, Ctrl* ctrl, const uint64_t* n_ptr,
                     const K* in, K* tmp, const Bufs<K>& b, int w, uint32_t j, uint32_t side,
                     Ev ev = Ev(), bool narrow = false);
+
+// Row pass of TC iteration j: the join's candidates in cand[0], grouped by row, each row
+// deduplicated and set-differenced against Full in an LDS bitmap and written sorted to
+// delta[j & 1] (with the gather; w <= kRowBitsMax), record j as the compaction writes it.
+template <typename K>
+void launch_row_diff(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint64_t* n_ptr, const Bufs<K>& b, int w,
+                     uint32_t j, Ev ev = Ev(), int gate = 0);
+// ... and its gather (survivors to delta[j & 1], record j); with gate 1 a row pass leaves the
+// LSD passes enqueued between the two as no-ops
+template <typename K>
+void launch_row_gather(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint64_t* n_ptr, const Bufs<K>& b,
+                       uint32_t j, Ev ev = Ev(), int gate = 0);
 
 // Merge of iteration j: B' = merge(B, delta), or on a fold A' = merge(A, B) and B' = delta.
 template <typename K>

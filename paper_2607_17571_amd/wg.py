@@ -45,7 +45,7 @@ WG_LOOP_HOST = 2
 WG_LOOP_STAGE = 3
 
 STAGES = ["join_count", "join_emit", "radix_hist", "radix_pass", "dedup_diff", "merge", "prepare",
-          "seg_sort"]
+          "seg_sort", "row_diff"]
 WG_NUM_STAGES = len(STAGES)
 
 
