@@ -68,7 +68,7 @@ struct Ctrl {
   uint32_t small_sorted;       // the sort in flight fit one block and is done: the radix
                                // passes of that sort are no-ops
   uint32_t seg_long;           // rows the segmented sort in flight left to its long-row pass
-  uint64_t full_n;             // |Full| after the last completed iteration (the seed: |Delta^0|)
+  uint64_t full_n;             // |Full| after the last merged iteration (the seed: |Delta^0|)
 };
 
 // Kernels of the loop take their iteration from the device, so that one iteration's

@@ -1965,7 +1965,6 @@ __global__ __launch_bounds__(kBlock) void k_compact_gather(Ctrl* ctrl, int mode,
       r.b = N > 0 ? (rp.b ^ 1u) : rp.b;
       r.fold = fold ? 1u : 0u;
       ctrl->iter = j;
-      ctrl->full_n = F + N;
       if (N == 0) ctrl->done = 1;
       else if (ctrl->max_iter != 0 && j >= ctrl->max_iter) ctrl->limit_hit = 1;
     } else if (mode & (kModeEdges | kModeSeed)) {
@@ -2139,6 +2138,9 @@ __global__ __launch_bounds__(kBlock) void k_merge(Ctrl* ctrl, Bufs<K> b, uint32_
   j = iter_cur(ctrl, j);
   const IterRec rp = b.rec[j - 1];
   const IterRec rj = b.rec[j];
+  // |Full| for the route gates of the next iteration; set here, not by the gather that
+  // records the iteration, whose other blocks read it in their own gate
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->full_n = rj.F;
   const uint64_t fb = rp.F - rp.FA;
   const K* __restrict__ delta = b.delta[j & 1u];
   K* __restrict__ outB = b.fullB[rp.b ^ 1u];

@@ -182,6 +182,32 @@ def test_compaction_tile_boundaries(engine, a, b):
     assert_same(s, d, st, ref)
 
 
+def test_row_pass_on_uneven_rows(engine):
+    """3,000 sources reach 1,000 mid vertices (out-degree 1..9) that reach ids up to 65,535
+    (out-degree 1..300): iteration 1 has about 2.25M candidates, far more than Full's tuples,
+    so the device takes the row pass (16-bit ids, 8 KB bitmaps), with rows of very uneven
+    length and duplicates through shared mid vertices."""
+    rng = np.random.default_rng(31)
+    src, dst = [], []
+    for s_ in range(3000):
+        for m_ in rng.choice(1000, size=int(rng.integers(1, 10)), replace=False):
+            src.append(s_)
+            dst.append(3000 + m_)
+    for m_ in range(1000):
+        for t_ in rng.choice(np.arange(4000, 65536), size=int(rng.integers(1, 301)), replace=False):
+            src.append(3000 + m_)
+            dst.append(int(t_))
+    src = np.array(src, np.uint32)
+    dst = np.array(dst, np.uint32)
+    s, d, st = run(engine, "tc", src, dst)
+    ref = oracle.tc(src, dst)
+    assert ref.candidates > (1 << 21)
+    assert_same(s, d, st, ref)
+    # the same through the paper's sort and compaction alone
+    s2, d2, st2 = run(engine, "tc", src, dst, wg.make_options(flags=wg.WG_LSD_SORT))
+    assert_same(s2, d2, st2, ref)
+
+
 @pytest.mark.parametrize("seed,n,m", [(1, 300, 280), (2, 2000, 1900), (3, 20000, 18000)])
 def test_sg_random_er(engine, seed, n, m):
     src, dst = inputs.erdos_renyi(n, m, seed=seed)
@@ -565,6 +591,12 @@ def test_result_copy_to_host_memory(engine):
                                   "sg_er_500k", "tc_grid_100"])
 def test_full_size_against_golden(engine, name):
     _check_golden(engine, name, None)
+
+
+def test_full_size_lsd_sort_only(engine):
+    """R-MAT-15 with the LSD passes and the compaction on every iteration (no segmented sort,
+    no row pass): the paper's own sort path at full size."""
+    _check_golden(engine, "tc_rmat_s15", wg.make_options(flags=wg.WG_LSD_SORT))
 
 
 @pytest.mark.parametrize("name,rb,items", [("tc_rmat_s15", 11, 16), ("tc_rmat_s15", 9, 8),
