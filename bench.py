@@ -23,7 +23,13 @@ The JSON line also carries the roofline of the dominant kernel: its algorithmic 
 second run of the same K solves with events around that kernel only (events cost launch
 overlap, so the throughput figure comes from the run without them), against 8 TB/s of
 HBM; and the CPU oracle timed on the host (test infrastructure, used only for this
-baseline).
+baseline), with the CPU model and core counts.  The oracle is single-threaded; a batch
+also gets an all-core figure, its instances spread over worker processes.
+
+The default run (no --workload) adds under "extra" the same measurement of the batched
+workload (tc_batch_er_4096, 3 solves, with the plain one-by-one path) and of SG on
+sg_er_500k, each with its own roofline and CPU baseline.  CPU baselines run first,
+before anything touches the GPU, because the all-core leg forks worker processes.
 """
 
 from __future__ import annotations
@@ -45,7 +51,7 @@ STAGE_KERNELS = {
     "radix_hist": "k_radix_count + k_radix_scan", "radix_pass": "k_radix_scatter",
     "dedup_diff": "k_compact_local + k_compact_gather", "merge": "k_merge",
     "prepare": "k_max_id, k_pack, k_index_*, k_unpack", "seg_sort": "k_seg_sort",
-    "row_diff": "k_row_diff + k_compact_gather",
+    "row_diff": "k_row_diff + k_row_gather",
 }
 WORKLOAD_TEXT = {
     "tc_rmat_s15": "TC, R-MAT scale 15 (n=32,768, m=29,491, a,b,c,d=0.57,0.19,0.19,0.05, seed 2); "
@@ -87,9 +93,12 @@ def measured_traffic(kernel: str, workload: str, digit_bits: int, tile_items: in
             continue
         with open(os.path.join(prof, name)) as f:
             rec = json.load(f)
+        # the sort's digit width and tile matter only to the sort's own kernels
+        sort_kernel = "k_radix" in kernel
         if (rec.get("kernel") == kernel and rec.get("workload") == workload
                 and rec.get("kernel_source_sha256") == digest
-                and rec.get("digit_bits") == digit_bits and rec.get("tile_items") == tile_items):
+                and (not sort_kernel or (rec.get("digit_bits") == digit_bits
+                                         and rec.get("tile_items") == tile_items))):
             return rec
     return None
 
@@ -99,7 +108,10 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="tc_rmat_s15")
+    p.add_argument("--workload", default=None,
+                   help="workload name (default tc_rmat_s15, with the batched and SG extras)")
+    p.add_argument("--no-extras", action="store_true",
+                   help="default run: skip the batched and SG measurements beside the headline")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-timing", action="store_true", help="time steps without per-kernel events")
     p.add_argument("--digit-bits", type=int, default=0, help="radix digit bits (0: engine's choice)")
@@ -113,6 +125,9 @@ def parse():
                    help="run only the instrumented steps (value then comes from them); for profiling")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="only copy MIB MiB device to device 10 times (counter calibration) and exit")
+    p.add_argument("--gather-calibration", type=int, default=0, metavar="MIB",
+                   help="only gather MIB MiB of 4-byte values through a random permutation 10 times "
+                        "(scattered-read counter calibration) and exit")
     p.add_argument("--requests", type=int, default=120, help="served_mix: number of requests")
     p.add_argument("--slots", type=int, default=4, help="served_mix: concurrent solves")
     p.add_argument("--load", type=float, default=0.7, help="served_mix: offered load / capacity")
@@ -124,19 +139,95 @@ def parse():
                    help="time the variants of one design choice instead of the headline line")
     p.add_argument("--ablation-workloads", default=None,
                    help="comma-separated workload names for --ablation (default: per ablation)")
-    return p.parse_args()
+    a = p.parse_args()
+    a.workload_given = a.workload is not None
+    if a.workload is None:
+        a.workload = "tc_rmat_s15"
+    return a
+
+
+SG_EXTRA = "sg_er_500k"
+BATCH_EXTRA = "tc_batch_er_4096"
 
 
 def is_batch(name: str) -> bool:
     return "_batch_" in name
 
 
-def cpu_baseline(name: str):
+def cpu_info() -> dict:
+    """The host the CPU baseline ran on: CPU model, logical CPUs, and those this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+_POOL_BATCH = None  # (query, Batch) of the all-core leg, set before the workers fork
+
+
+def _oracle_chunk(lo: int, hi: int):
+    import oracle
+
+    query, b = _POOL_BATCH
+    fn = oracle.tc if query == "tc" else oracle.sg
+    return sum(int(fn(*b.instance(i)).src.size) for i in range(lo, hi))
+
+
+def _all_core(name: str, seconds: float = 15.0, max_workers: int = 16):
+    """The unchanged oracle over a batch's instances in worker processes (one instance at a
+    time per worker, chunks of 8 handed out in order until `seconds` have passed)."""
+    import multiprocessing
+    from concurrent.futures import FIRST_COMPLETED, ProcessPoolExecutor, wait
+
+    from paper_2607_17571_amd import inputs
+
+    global _POOL_BATCH
+    _POOL_BATCH = inputs.batch_workload(name)
+    num = _POOL_BATCH[1].num
+    workers = max(1, min(cpu_info()["usable_cpus"] or 1, max_workers))
+    chunk = 8
+    with ProcessPoolExecutor(workers, mp_context=multiprocessing.get_context("fork")) as ex:
+        list(ex.map(time.sleep, [0.05] * (2 * workers)))  # every worker started before the clock
+        t0 = time.perf_counter()
+        nxt = 0
+        pending = set()
+        tuples = 0
+        while nxt < num and len(pending) < 2 * workers:
+            pending.add(ex.submit(_oracle_chunk, nxt, min(nxt + chunk, num)))
+            nxt = min(nxt + chunk, num)
+        while pending:
+            done, pending = wait(pending, return_when=FIRST_COMPLETED)
+            tuples += sum(f.result() for f in done)
+            for _ in done:
+                if nxt < num and time.perf_counter() - t0 < seconds:
+                    pending.add(ex.submit(_oracle_chunk, nxt, min(nxt + chunk, num)))
+                    nxt = min(nxt + chunk, num)
+        dt = time.perf_counter() - t0
+    _POOL_BATCH = None
+    return {"value": tuples / dt, "unit": "tuples/s", "cores": workers, "kind": "oracle",
+            "sample": f"instances 0..{nxt - 1} of {name} ({tuples} tuples) in {dt:.2f} s over {workers} "
+                      f"worker processes, each running the single-threaded oracle on one instance at a time"}
+
+
+def cpu_baseline(name: str, all_core: bool = False):
     """The oracle as it stands, timed on the host: one whole solve, or for a batch the
-    instances in order until about 15 s of work."""
+    instances in order until about 15 s of work.  The oracle is plain single-threaded numpy
+    (nothing in it is parallel); for a batch, `all_core` adds the same oracle over the
+    instances in worker processes."""
     import oracle
     from paper_2607_17571_amd import inputs
 
+    host = cpu_info()
     if is_batch(name):
         query, b = inputs.batch_workload(name)
         fn = oracle.tc if query == "tc" else oracle.sg
@@ -146,16 +237,20 @@ def cpu_baseline(name: str):
             tuples += fn(*b.instance(done)).src.size
             done += 1
         dt = time.perf_counter() - t0
-        return {"value": tuples / dt, "unit": "tuples/s", "cores": 1, "kind": "oracle",
-                "sample": f"instances 0..{done - 1} of {name} ({tuples} tuples) solved one by one "
-                          f"in {dt:.2f} s, single-threaded numpy"}, None
+        out = {"value": tuples / dt, "unit": "tuples/s", "cores": 1, "kind": "oracle",
+               "sample": f"instances 0..{done - 1} of {name} ({tuples} tuples) solved one by one "
+                         f"in {dt:.2f} s, single-threaded numpy", **host}
+        if all_core:
+            out["all_core"] = _all_core(name)
+        return out, None
     w = inputs.workload(name)
     t0 = time.perf_counter()
     r = oracle.tc(w.src, w.dst) if w.query == "tc" else oracle.sg(w.src, w.dst)
     dt = time.perf_counter() - t0
     return {"value": r.src.size / dt, "unit": "tuples/s", "cores": 1, "kind": "oracle",
             "sample": f"one full solve of {name} ({r.src.size} tuples, {r.iterations} iterations) "
-                      f"in {dt:.2f} s, single-threaded numpy"}, r
+                      f"in {dt:.2f} s, single-threaded numpy (one solve has no natural split)",
+            **host}, r
 
 
 def percentile(xs, q):
@@ -534,45 +629,18 @@ def run_ablation(args):
     print(json.dumps(out), flush=True)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "the benchmark runs on one GPU (the engine is single-device); --gpus must be 1",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
+def measure(args, name: str) -> dict:
+    """K timed solves of one workload (after the autotuner and W warm-ups), then the same K
+    with events on the dominant kernel kind: the bench line without its CPU baseline."""
     import numpy as np
     import torch
 
     from paper_2607_17571_amd import inputs, wg
 
-    if not torch.cuda.is_available():
-        print(json.dumps({"error": "no GPU visible"}))
-        sys.exit(2)
-    if args.copy_calibration:
-        # a plain device-to-device copy of known size: what FETCH_SIZE / WRITE_SIZE read for
-        # it calibrates the counters against known bytes
-        n = args.copy_calibration << 20
-        a = torch.empty(n, dtype=torch.uint8, device="cuda")
-        b = torch.empty(n, dtype=torch.uint8, device="cuda")
-        a.fill_(1)
-        for _ in range(10):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_calibration_bytes": n, "copies": 10}), flush=True)
-        return
-    if args.kernel_sweep:
-        run_kernel_sweep(args)
-        return
-    if args.ablation:
-        run_ablation(args)
-        return
-    if args.workload == "served_mix":
-        run_served(args)
-        return
     eng = wg.Engine(0)
     extra = {}
-    if is_batch(args.workload):
-        query, b = inputs.batch_workload(args.workload)
+    if is_batch(name):
+        query, b = inputs.batch_workload(name)
         src = torch.from_numpy(b.src).cuda()
         dst = torch.from_numpy(b.dst).cuda()
         offs = torch.from_numpy(b.offsets.astype(np.int64)).cuda()
@@ -587,7 +655,7 @@ def main():
             _, _, _, st = eng.solve_batch(query, src, dst, offs, opts)
             return st
     else:
-        w = inputs.workload(args.workload)
+        w = inputs.workload(name)
         query = w.query
         src = torch.from_numpy(w.src).cuda()
         dst = torch.from_numpy(w.dst).cuda()
@@ -665,7 +733,7 @@ def main():
         achieved = nbytes / (ms / 1e3) / 1e9 if ms > 0 else 0.0
         tile = args.tile_items or (extra["autotune"]["best"]["tile_items"] if "autotune" in extra
                                    else eng.sort_config(st["key_bytes"])["tile_items"])
-        tr = measured_traffic(STAGE_KERNELS[dom], args.workload, st["digit_bits"], tile)
+        tr = measured_traffic(STAGE_KERNELS[dom], name, st["digit_bits"], tile)
         roofline = {"bound": "hbm", "kernel": STAGE_KERNELS[dom], "stage": dom,
                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -675,7 +743,7 @@ def main():
                     "launches_per_step": launches // args.steps,
                     "instrumented_ms_per_step": round(inst_ms, 3)}
 
-    if is_batch(args.workload) and not args.no_plain:
+    if is_batch(name) and not args.no_plain:
         # the plain single-instance path over the same inputs: one wg_tc / wg_sg per instance
         plain_tuples = 0
         torch.cuda.synchronize()
@@ -704,7 +772,7 @@ def main():
         "vs_baseline": None,
         "dtype": "u32" if st["key_bytes"] == 4 else "u64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD_TEXT.get(args.workload, args.workload), "name": args.workload,
+        "config": {"workload": WORKLOAD_TEXT.get(name, name), "name": name,
                    "query": query, "edges": edges, "fixpoint_tuples": st["result_tuples"],
                    "iterations": st["iterations"], "join_candidates": st["join_candidates"],
                    "radix_field_bits": st["field_bits"], "radix_digit_bits": st["digit_bits"],
@@ -719,11 +787,94 @@ def main():
         out["instrumented"] = True
     out.update(extra)
     eng.close()
-    if not args.no_cpu_baseline:
-        cb, ref = cpu_baseline(args.workload)
-        if ref is not None and (ref.src.size != st["result_tuples"] or ref.iterations != st["iterations"]):
-            out["cpu_baseline_mismatch"] = True
-        out["cpu_baseline"] = cb
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "the benchmark runs on one GPU (the engine is single-device); --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    special = args.kernel_sweep or args.ablation or args.copy_calibration or args.gather_calibration
+    default_run = not args.workload_given and not special
+    # CPU baselines first: the all-core leg forks worker processes, which must not inherit an
+    # initialised GPU runtime (nothing below has touched the GPU yet)
+    cpu = {}
+    if not args.no_cpu_baseline and not special and args.workload != "served_mix":
+        cpu[args.workload] = cpu_baseline(args.workload)
+        if default_run and not args.no_extras:
+            cpu[SG_EXTRA] = cpu_baseline(SG_EXTRA)
+            cpu[BATCH_EXTRA] = cpu_baseline(BATCH_EXTRA, all_core=True)
+    import torch
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(2)
+    if args.copy_calibration:
+        # a plain device-to-device copy of known size: what FETCH_SIZE / WRITE_SIZE read for
+        # it calibrates the counters against known bytes
+        n = args.copy_calibration << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty(n, dtype=torch.uint8, device="cuda")
+        a.fill_(1)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n, "copies": 10}), flush=True)
+        return
+    if args.gather_calibration:
+        # 4-byte reads at random positions (each value read once): with the streamed index
+        # (8 B) and output (4 B) it calibrates the counters for scattered reads
+        n = (args.gather_calibration << 20) // 4
+        g = torch.Generator(device="cuda").manual_seed(11)
+        a = torch.arange(n, dtype=torch.int32, device="cuda")
+        idx = torch.randperm(n, generator=g, device="cuda")
+        out = torch.empty(n, dtype=torch.int32, device="cuda")
+        for _ in range(10):
+            torch.index_select(a, 0, idx, out=out)
+        torch.cuda.synchronize()
+        print(json.dumps({"gather_calibration_values": n, "value_bytes": 4, "index_bytes": 8,
+                          "algorithmic_read_bytes": 12 * n, "algorithmic_write_bytes": 4 * n,
+                          "gathers": 10}), flush=True)
+        return
+    if args.kernel_sweep:
+        run_kernel_sweep(args)
+        return
+    if args.ablation:
+        run_ablation(args)
+        return
+    if args.workload == "served_mix":
+        run_served(args)
+        return
+
+    def with_cpu(out, name):
+        if name in cpu:
+            cb, ref = cpu[name]
+            if ref is not None and (ref.src.size != out["config"]["fixpoint_tuples"]
+                                    or ref.iterations != out["config"]["iterations"]):
+                out["cpu_baseline_mismatch"] = True
+            out["cpu_baseline"] = cb
+        return out
+
+    out = with_cpu(measure(args, args.workload), args.workload)
+    if default_run and not args.no_extras:
+        # the batched and SG configurations beside the headline, each with its own roofline
+        # and CPU baseline (the served mix is not part of this line)
+        sub = argparse.Namespace(**vars(args))
+        sub.dominant = None
+        sub.roofline_only = False
+        extra = {}
+        _progress(f"extra: {BATCH_EXTRA}")
+        sub.steps, sub.warmup = min(args.steps, 3), 1
+        extra["batched"] = with_cpu(measure(sub, BATCH_EXTRA), BATCH_EXTRA)
+        _progress(f"extra: {SG_EXTRA}")
+        sub.steps, sub.warmup = args.steps, min(args.warmup, 3)
+        extra["sg"] = with_cpu(measure(sub, SG_EXTRA), SG_EXTRA)
+        extra["served"] = None
+        extra["served_note"] = ("not measured in this line: the full-size served mix is held back "
+                                "after an unexplained GPU fault (run it with --workload served_mix)")
+        out["extra"] = extra
     print(json.dumps(out), flush=True)
 
 

@@ -1885,12 +1885,10 @@ __global__ __launch_bounds__(kBlock) void k_row_diff(int gate, Ctrl* ctrl, const
 }
 
 template <typename K, int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_compact_gather(Ctrl* ctrl, int mode, const uint64_t* n_ptr,
-                                                           const K* __restrict__ tmp, Bufs<K> b,
-                                                           uint32_t j, uint32_t side) {
+__device__ __forceinline__ void compact_gather(Ctrl* ctrl, int mode, const uint64_t* n_ptr, const K* __restrict__ tmp,
+                                               Bufs<K> b, uint32_t j, uint32_t side, uint64_t* s_pre,
+                                               uint64_t* s_wave) {
   constexpr uint32_t T = kBlock * ITEMS;  // the tile of the local pass it follows
-  __shared__ uint64_t s_pre[kScanBlocksMax];
-  __shared__ uint64_t s_wave[kWavesPerBlock];
   const bool filt = (mode & kModeFilter) != 0;
   if (!filt && halted(ctrl)) return;
   if (gated_out(ctrl, (mode & kModeGateRow) ? 1 : ((mode & kModeGateSort) ? 2 : 0), kRowMin)) return;
@@ -1987,6 +1985,25 @@ __global__ __launch_bounds__(kBlock) void k_compact_gather(Ctrl* ctrl, int mode,
       ctrl->filtered = N;
     }
   }
+}
+
+template <typename K, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_compact_gather(Ctrl* ctrl, int mode, const uint64_t* n_ptr,
+                                                           const K* __restrict__ tmp, Bufs<K> b,
+                                                           uint32_t j, uint32_t side) {
+  __shared__ uint64_t s_pre[kScanBlocksMax];
+  __shared__ uint64_t s_wave[kWavesPerBlock];
+  compact_gather<K, ITEMS>(ctrl, mode, n_ptr, tmp, b, j, side, s_pre, s_wave);
+}
+
+// The row pass's gather: the same code as the compaction's (kModeRows), under a name of its
+// own so that profiles tell the two apart.
+template <typename K, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_row_gather(Ctrl* ctrl, int mode, const uint64_t* n_ptr,
+                                                       const K* __restrict__ tmp, Bufs<K> b, uint32_t j) {
+  __shared__ uint64_t s_pre[kScanBlocksMax];
+  __shared__ uint64_t s_wave[kWavesPerBlock];
+  compact_gather<K, ITEMS>(ctrl, mode | kModeRows, n_ptr, tmp, b, j, 0u, s_pre, s_wave);
 }
 
 // ---------------------------------------------------------------------------
@@ -2585,8 +2602,8 @@ void launch_row_diff(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint64_t* n
 template <typename K>
 void launch_row_gather(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint64_t* n_ptr, const Bufs<K>& b,
                        uint32_t j, Ev ev, int gate) {
-  WG_LAUNCH((k_compact_gather<K, kDedupItems>), g.scan, ev.start, ev.stop, s, ctrl,
-            kModeIter | kModeRows | (gate == 1 ? kModeGateRow : 0), n_ptr, (const K*)b.cand[1], b, j, 0u);
+  WG_LAUNCH((k_row_gather<K, kDedupItems>), g.scan, ev.start, ev.stop, s, ctrl,
+            kModeIter | (gate == 1 ? kModeGateRow : 0), n_ptr, (const K*)b.cand[1], b, j);
 }
 
 template <typename K>
