@@ -94,6 +94,19 @@ __device__ __forceinline__ bool halted(const Ctrl* c) {
   return (c->done | c->overflow | c->limit_hit) != 0;
 }
 
+// Early exit of a launch, decided once per block: thread 0's `stop` is the whole block's.
+// The flags behind it can be set by another block of the same launch (an overflow, the
+// fixpoint, the iteration limit); waves of one block that read them at different moments
+// would split, and the waves that stay would meet barriers and block-wide scans whose
+// partial sums the others never wrote.  (Blocks may still differ: a block that returns
+// because of such a flag has nothing left to contribute once it is set.)
+__device__ __forceinline__ bool block_stop(bool stop) {
+  __shared__ int s_stop;
+  if (threadIdx.x == 0) s_stop = stop ? 1 : 0;
+  __syncthreads();
+  return s_stop != 0;
+}
+
 // An iteration enqueued with both routes (gate 1: the row route, 2: the sort route; 0: no
 // gate): the join's candidate count picks one -- the rows from `row_min` candidates on and
 // while they are at least as many as the tuples of Full (the row pass streams each touched

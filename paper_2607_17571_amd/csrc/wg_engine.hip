@@ -868,7 +868,9 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
     const double ahead = (double)x.C * g * g * g * g;
     e->narrow = ahead < (double)kNarrowBelow;
     e->seg_sort = seg_allowed && ahead < (double)kSegBelow;
-    e->row_bitmap = row_allowed && seg_allowed && ahead >= (double)kDualAbove;
+    // (the row route needs at least as many candidates as Full has tuples, and Full only
+    // grows: below that the row launches would all be gated off)
+    e->row_bitmap = row_allowed && seg_allowed && ahead >= std::max((double)kDualAbove, (double)x.F);
     e->seg_long = (e->seg_sort || e->row_bitmap) && long_forced;
     if (!small_missed && K_batch <= kAutoK && it >= 2 && calm(x.C, y.C, small_keys))
       e->small_mode = calm(x.N, y.N, kSmallJoinTuples) ? 3 : 2;

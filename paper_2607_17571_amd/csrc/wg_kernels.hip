@@ -103,7 +103,7 @@ template <typename K, int Q, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_join_count(Ctrl* ctrl, Bufs<K> b, int w, uint32_t j) {
   constexpr uint32_t T = kBlock * ITEMS;
   __shared__ uint64_t s_wave[kWavesPerBlock];
-  if (halted(ctrl)) return;
+  if (block_stop(halted(ctrl))) return;
   j = iter_begin(ctrl, j);
   const uint64_t n = (Q == kJoinSGBase) ? ctrl->nu : b.rec[j - 1].N;
   const uint64_t nu = ctrl->nu;
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int
   __shared__ uint32_t s_len[kSG ? T : 1];   // SG: divisor of the pair index
   __shared__ K s_head[T];                   // per staged tuple: key bits passed on
   __shared__ uint64_t s_i0, s_i1;
-  if (halted(ctrl)) return;
+  if (block_stop(halted(ctrl))) return;
   j = iter_cur(ctrl, j);
   const uint64_t n = (Q == kJoinSGBase) ? ctrl->nu : b.rec[j - 1].N;
   const uint64_t C = block_prefix(b.jtot, gc, s_pre, s_wave);
@@ -473,7 +473,7 @@ __global__ __launch_bounds__(kBlock) void k_join_count_hash(Ctrl* ctrl, Bufs<K> 
                                                             uint32_t mask) {
   constexpr uint32_t T = kBlock * ITEMS;
   __shared__ uint64_t s_wave[kWavesPerBlock];
-  if (halted(ctrl)) return;
+  if (block_stop(halted(ctrl))) return;
   j = iter_begin(ctrl, j);
   const uint64_t n = b.rec[j - 1].N;
   const K* __restrict__ delta = b.delta[(j - 1) & 1u];
@@ -520,7 +520,7 @@ __global__ __launch_bounds__(kBlock) void k_join_emit_hash(Ctrl* ctrl, Bufs<K> b
   constexpr uint32_t T = kBlock * ITEMS;
   __shared__ uint64_t s_pre[kScanBlocksMax];
   __shared__ uint64_t s_wave[kWavesPerBlock];
-  if (halted(ctrl)) return;
+  if (block_stop(halted(ctrl))) return;
   j = iter_cur(ctrl, j);
   const uint64_t n = b.rec[j - 1].N;
   const uint64_t C = block_prefix(b.jtot, gridDim.x, s_pre, s_wave);
@@ -683,7 +683,7 @@ __global__ __launch_bounds__(kSmallSortThreads) void k_small_sort(Ctrl* ctrl, co
                                                                   uint32_t alone) {
   constexpr uint32_t CAP = kSmallSortBytes / sizeof(K);
   __shared__ K s[CAP];
-  if (halted(ctrl)) return;
+  if (block_stop(halted(ctrl))) return;
   const uint64_t n = *n_ptr;
   if (n > CAP) {
     if (threadIdx.x == 0) {
@@ -726,7 +726,7 @@ __global__ __launch_bounds__(kSmallSortThreads) void k_small_join(Ctrl* ctrl, Bu
   __shared__ uint32_t s_aux[kSG ? TH : 1];  // SG: first edge of the head row
   __shared__ uint32_t s_len[kSG ? TH : 1];  // SG: length of the join row
   __shared__ uint64_t s_wave[TH / kWave];
-  if (halted(ctrl)) return;
+  if (block_stop(halted(ctrl))) return;
   j = iter_begin(ctrl, j);
   const uint64_t n = b.rec[j - 1].N;
   const uint32_t t = threadIdx.x;
@@ -901,7 +901,7 @@ __global__ __launch_bounds__(kSmallSortThreads) void k_seg_sort(int gate, Ctrl* 
   __shared__ K s[CAP];
   __shared__ uint32_t s_first, s_last;
   __shared__ uint64_t s_end;
-  if (halted(ctrl) || gated_out(ctrl, gate, kRowMin)) return;
+  if (block_stop(halted(ctrl) || gated_out(ctrl, gate, kRowMin))) return;
   const uint64_t n = *n_ptr;
   const uint64_t ntiles = (n + kSegTile - 1) / kSegTile;
   const uint32_t t = threadIdx.x;
@@ -982,7 +982,7 @@ __global__ __launch_bounds__(kSmallSortThreads) void k_seg_long(int gate, Ctrl* 
   __shared__ K s_k[LCAP];
   __shared__ uint32_t s_cnt[NW][R];
   __shared__ uint32_t s_wave[NW];
-  if (halted(ctrl) || gated_out(ctrl, gate, kRowMin)) return;
+  if (block_stop(halted(ctrl) || gated_out(ctrl, gate, kRowMin))) return;
   const uint32_t rows = ctrl->seg_long;
   const int passes = w > RB ? (w + RB - 1) / RB : 1;
   const int tid = threadIdx.x;
@@ -1134,7 +1134,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_count(Ctrl* ctrl, const uint64
   constexpr int COPIES = RB <= 8 ? 8 : (RB == 9 ? 4 : (RB == 10 ? 2 : 1));
   constexpr int STRIDE = S::R + 1;
   __shared__ uint32_t s_cnt[COPIES * STRIDE];
-  if (halted(ctrl) || ctrl->small_sorted) return;
+  if (block_stop(halted(ctrl) || ctrl->small_sorted)) return;
   const uint64_t n = *n_ptr;
   uint64_t lo, hi;
   block_range(n, T, lo, hi);
@@ -1183,7 +1183,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scan(Ctrl* ctrl, const uint64_
                                                        uint32_t* __restrict__ cnt,
                                                        uint32_t* __restrict__ tot, int G) {
   __shared__ uint32_t s_wave[kWavesPerBlock];
-  if (halted(ctrl) || ctrl->small_sorted) return;
+  if (block_stop(halted(ctrl) || ctrl->small_sorted)) return;
   const int GA = (int)active_blocks(*n_ptr, T, (uint32_t)G);
   uint32_t* row = cnt + (uint64_t)blockIdx.x * G;
   uint32_t carry = 0;
@@ -1228,7 +1228,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(Ctrl* ctrl, const uint
   __shared__ uint32_t s_run[S::R];                  // next output position of each digit
   __shared__ uint32_t s_wave[kWavesPerBlock];
   __shared__ uint32_t s_peer[kWavesPerBlock * PT::kWords];  // peer table of each wave
-  if (halted(ctrl) || ctrl->small_sorted) return;
+  if (block_stop(halted(ctrl) || ctrl->small_sorted)) return;
   const uint64_t n = *n_ptr;
   uint64_t lo, hi;
   block_range(n, T, lo, hi);
@@ -1492,8 +1492,9 @@ __global__ __launch_bounds__(kBlock) void k_compact_local(Ctrl* ctrl, int mode, 
   __shared__ uint32_t s_wave[kWavesPerBlock];
   __shared__ uint64_t s_lo[2], s_hi[2];
   const bool filt = (mode & kModeFilter) != 0;
-  if (!filt && halted(ctrl)) return;
-  if (gated_out(ctrl, (mode & kModeGateRow) ? 1 : ((mode & kModeGateSort) ? 2 : 0), kRowMin)) return;
+  if (block_stop((!filt && halted(ctrl)) ||
+                 gated_out(ctrl, (mode & kModeGateRow) ? 1 : ((mode & kModeGateSort) ? 2 : 0), kRowMin)))
+    return;
   j = iter_cur(ctrl, j);
   const uint64_t n = *n_ptr;
   uint64_t lo, hi;
@@ -1723,7 +1724,7 @@ __global__ __launch_bounds__(kBlock) void k_row_diff(int gate, Ctrl* ctrl, const
   __shared__ uint32_t s_pre[kRowWordsMax];  // new bits in the words before each word
   __shared__ uint32_t s_wave[kWavesPerBlock];
   __shared__ uint64_t s_at[3];              // broadcast of wave searches
-  if (halted(ctrl) || gated_out(ctrl, gate, kRowMin)) return;
+  if (block_stop(halted(ctrl) || gated_out(ctrl, gate, kRowMin))) return;
   // this iteration needs no sort: LSD passes enqueued behind (the other route) are no-ops
   // (the gather clears the flag)
   if (gate != 0 && blockIdx.x == 0 && threadIdx.x == 0) ctrl->small_sorted = 1;
@@ -1890,8 +1891,9 @@ __device__ __forceinline__ void compact_gather(Ctrl* ctrl, int mode, const uint6
                                                uint64_t* s_wave) {
   constexpr uint32_t T = kBlock * ITEMS;  // the tile of the local pass it follows
   const bool filt = (mode & kModeFilter) != 0;
-  if (!filt && halted(ctrl)) return;
-  if (gated_out(ctrl, (mode & kModeGateRow) ? 1 : ((mode & kModeGateSort) ? 2 : 0), kRowMin)) return;
+  if (block_stop((!filt && halted(ctrl)) ||
+                 gated_out(ctrl, (mode & kModeGateRow) ? 1 : ((mode & kModeGateSort) ? 2 : 0), kRowMin)))
+    return;
   j = iter_cur(ctrl, j);
   // the sort before this compaction is over: a later sort that skips the one-block path
   // must not find its flag (nothing else in this launch reads it)
@@ -2151,7 +2153,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(Ctrl* ctrl, Bufs<K> b, uint32_
   __shared__ K s_in[T];
   __shared__ K s_out[T];
   __shared__ uint64_t s_i[4];
-  if (halted(ctrl)) return;
+  if (block_stop(halted(ctrl))) return;
   j = iter_cur(ctrl, j);
   const IterRec rp = b.rec[j - 1];
   const IterRec rj = b.rec[j];
@@ -2208,7 +2210,7 @@ __global__ __launch_bounds__(kBlock) void k_index_dense(Ctrl* ctrl, Bufs<K> b, i
   __shared__ uint32_t s_n;
   __shared__ uint64_t s_from[kBlock], s_to[kBlock];
   __shared__ uint32_t s_val[kBlock];
-  if (halted(ctrl)) return;
+  if (block_stop(halted(ctrl))) return;
   const uint64_t n = ctrl->m_unique;
   const K* __restrict__ E = b.E;
   const K mask = field_mask<K>(w);
@@ -2248,7 +2250,7 @@ template <typename K, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_index_count(Ctrl* ctrl, Bufs<K> b, int w) {
   constexpr uint32_t T = kBlock * ITEMS;
   __shared__ uint64_t s_wave[kWavesPerBlock];
-  if (halted(ctrl)) return;
+  if (block_stop(halted(ctrl))) return;
   const uint64_t n = ctrl->m_unique;
   const K* __restrict__ E = b.E;
   const K mask = field_mask<K>(w);
@@ -2270,7 +2272,7 @@ __global__ __launch_bounds__(kBlock) void k_index_write(Ctrl* ctrl, Bufs<K> b, i
   constexpr uint32_t T = kBlock * ITEMS;
   __shared__ uint64_t s_pre[kScanBlocksMax];
   __shared__ uint64_t s_wave[kWavesPerBlock];
-  if (halted(ctrl)) return;
+  if (block_stop(halted(ctrl))) return;
   const uint64_t n = ctrl->m_unique;
   const K* __restrict__ E = b.E;
   const uint64_t nu = block_prefix(b.bcnt, gridDim.x, s_pre, s_wave);

@@ -1,0 +1,85 @@
+"""Regression test (CPU): the early exit of a launch is decided once per block.
+
+Block 0 of the row pass's gather records the iteration and, for an empty delta, sets the
+fixpoint flag that every block tests at its start; the join's emit and the compaction's
+gather likewise report overflows.  When the threads of one block tested such a flag at
+different moments, part of the block returned and the rest went on into block-wide scans
+whose partial sums the others never wrote (on the GPU: garbage prefix sums, then stores at
+garbage positions).  This runs the current kernel text of the row pass and its gather on
+the CPU SIMT shim under tests/simt (every GPU thread a fiber, blocks concurrently on OS
+threads with their own LDS, AddressSanitizer on), with the fixpoint reached and with a
+non-empty delta, many times: every run must give the plain set difference and no block
+may split.
+"""
+
+import os
+import platform
+import shutil
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SIMT = os.path.join(ROOT, "tests", "simt")
+CSRC = os.path.join(ROOT, "paper_2607_17571_amd", "csrc")
+KERNELS = ["compact_span", "const:kRowWordsMax", "const:kRowTile", "nth_set_bit", "or_sorted_runs", "k_row_diff",
+           "compact_gather", "k_row_gather"]
+
+pytestmark = pytest.mark.skipif(shutil.which("g++") is None or platform.machine() != "x86_64",
+                                reason="needs g++ on x86-64 (the shim switches fibers in x86-64 assembly)")
+
+
+@pytest.fixture(scope="module")
+def harness(tmp_path_factory):
+    d = tmp_path_factory.mktemp("simt")
+    inc = subprocess.run([sys.executable, os.path.join(SIMT, "extract.py"), os.path.join(CSRC, "wg_kernels.hip"),
+                          *KERNELS], capture_output=True, text=True, check=True).stdout
+    (d / "row.inc").write_text(inc)
+    exe = d / "row_harness"
+    subprocess.run(["g++", "-std=c++20", "-O1", "-g", "-fsanitize=address", "-fno-omit-frame-pointer",
+                    f"-I{d}", f"-I{SIMT}", f"-I{CSRC}", f"-I{os.path.join(ROOT, 'include')}", "-pthread",
+                    os.path.join(SIMT, "row_harness.cpp"), "-o", str(exe)], check=True, capture_output=True)
+    return exe
+
+
+def _write(path, cand, a, b, w):
+    with open(path, "wb") as f:
+        np.array([cand.size, a.size, b.size, w, 4], dtype=np.uint64).tofile(f)
+        cand.astype(np.uint32).tofile(f)
+        a.astype(np.uint32).tofile(f)
+        b.astype(np.uint32).tofile(f)
+
+
+def _case(seed, empty_delta):
+    rng = np.random.default_rng(seed)
+    w = 8
+    rows = np.sort(rng.choice(1 << 12, size=300, replace=False)).astype(np.uint64)
+    full = np.unique(np.concatenate([(r << np.uint64(w)) | rng.integers(0, 1 << w, size=int(rng.integers(1, 60)),
+                                                                       dtype=np.uint64) for r in rows]))
+    cand = []
+    for r in rows:
+        mine = full[(full >> np.uint64(w)) == r]
+        if empty_delta:
+            d = rng.choice(mine, size=int(rng.integers(1, 40)))  # every candidate already in Full
+        else:
+            d = (r << np.uint64(w)) | rng.integers(0, 1 << w, size=int(rng.integers(1, 40)), dtype=np.uint64)
+        cand.append(d)
+    cand = np.concatenate(cand)
+    nb = full.size // 5
+    perm = rng.permutation(full.size)
+    return cand, np.sort(full[perm[nb:]]), np.sort(full[perm[:nb]]), w
+
+
+@pytest.mark.parametrize("empty_delta", [True, False], ids=["fixpoint", "delta"])
+def test_row_gather_blocks_never_split(harness, tmp_path, empty_delta):
+    cand, a, b, w = _case(7 if empty_delta else 8, empty_delta)
+    path = tmp_path / "in.bin"
+    _write(path, cand, a, b, w)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
+    r = subprocess.run([str(harness), str(path), "64", "8", "20"], capture_output=True, text=True, env=env,
+                       timeout=300)
+    assert "simt:" not in r.stderr, r.stderr[-2000:]
+    assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-2000:])
+    assert r.stdout.count("ok ") == 20

@@ -136,9 +136,6 @@ def _sha(s, d):
     return hashlib.sha256(np.asarray(s, dtype="<u4").tobytes() + np.asarray(d, dtype="<u4").tobytes()).hexdigest()
 
 
-@pytest.mark.skip(reason="faulted the GPU once (memory aperture violation reported in k_join_emit while four "
-                         "slots solved the mix concurrently) after passing twice; the cause is not shown yet, so "
-                         "the case stays off the GPU until it is")
 def test_served_mix_full_size_against_golden(engine):
     """The served mix at its real sizes (120 requests, n log-uniform in [1k, 1M], R-MAT up to
     scale 15, 4 slots, the default budget): every result equals the oracle's stored record
