@@ -28,7 +28,10 @@ also gets an all-core figure, its instances spread over worker processes.
 
 The default run (no --workload) adds under "extra" the same measurement of the batched
 workload (tc_batch_er_4096, 3 solves, with the plain one-by-one path) and of SG on
-sg_er_500k, each with its own roofline and CPU baseline.  CPU baselines run first,
+sg_er_500k, each with its own roofline and CPU baseline, and the served mix (120 requests,
+4 slots) at 0.7x, 1.0x and 1.5x the plain path's capacity: p50/p99 latency and tuples/s of
+the server and of the plain path, both measured under the same Poisson arrivals, with
+every served result checked against the oracle's record.  CPU baselines run first,
 before anything touches the GPU, because the all-core leg forks worker processes.
 """
 
@@ -131,6 +134,8 @@ def parse():
     p.add_argument("--requests", type=int, default=120, help="served_mix: number of requests")
     p.add_argument("--slots", type=int, default=4, help="served_mix: concurrent solves")
     p.add_argument("--load", type=float, default=0.7, help="served_mix: offered load / capacity")
+    p.add_argument("--hold-after-us", type=int, default=0,
+                   help="served_mix: long-solve hold of the server (0: its default, 4294967295: never)")
     p.add_argument("--kernel-sweep", action="store_true",
                    help="sort and merge kernels alone on 2^20..2^28 synthetic keys")
     p.add_argument("--sweep-min-log2", type=int, default=20)
@@ -323,8 +328,29 @@ def run_kernel_sweep(args):
     print(json.dumps({"kernel_sweep": rows, "peak_gbs": HBM_PEAK_GBS, "sort_config": cfg}), flush=True)
 
 
-def run_served(args):
-    """Continuous batching under Poisson arrivals vs the plain one-at-a-time path."""
+def _golden_served():
+    """Per-request records of the served mix (size, iterations, sha256 of the lex-sorted
+    pairs), written from the oracle by tests/golden/make_golden.py."""
+    path = os.path.join(ROOT, "tests", "golden", "fixpoints.json")
+    with open(path) as f:
+        return json.load(f)["served_mix_120_seed5"]["requests"]
+
+
+def _pairs_sha(s, d) -> str:
+    import hashlib
+
+    import numpy as np
+
+    return hashlib.sha256(np.ascontiguousarray(s.cpu().numpy(), dtype="<u4").tobytes() +
+                          np.ascontiguousarray(d.cpu().numpy(), dtype="<u4").tobytes()).hexdigest()
+
+
+def measure_served(args):
+    """The served mix under Poisson arrivals at 0.7x, 1.0x and 1.5x the plain path's capacity:
+    continuous batching on the server against the plain path (one engine, one request at a
+    time in arrival order), both measured under the same arrivals.  Every served result is
+    checked against the oracle's record: size and iterations at every load, the sha256 of
+    the pairs at the first load."""
     import numpy as np
     import torch
 
@@ -334,10 +360,11 @@ def run_served(args):
         print(f"[served] {msg}", file=sys.stderr, flush=True)
 
     reqs = inputs.served_requests(args.requests, seed=5)
+    golden = _golden_served() if args.requests == 120 else None
     dev = [(torch.from_numpy(r.src).cuda(), torch.from_numpy(r.dst).cuda()) for r in reqs]
     torch.cuda.synchronize()
     progress(f"{len(reqs)} requests staged on the device")
-    # plain path: each request alone through wg_tc / wg_sg, one after another
+    # the plain path's service times, back to back (they set the offered rates)
     eng = wg.Engine(0)
     for (s, d), r in list(zip(dev, reqs))[:4]:
         eng.solve(r.query, s, d, None)
@@ -345,31 +372,41 @@ def run_served(args):
     for (s, d), r in zip(dev, reqs):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        _, _, st = eng.solve(r.query, s, d, None)
+        _, _, st = eng.solve(r.query, s, d, None, want_result=False)
         torch.cuda.synchronize()
         service.append(time.perf_counter() - t)
         plain_tuples += st["result_tuples"]
-        if len(service) % 20 == 0:
-            progress(f"plain path: {len(service)} solved, {sum(service):.2f} s of service")
-    eng.close()
     capacity = len(reqs) / sum(service)
-    progress(f"plain path done: capacity {capacity:.1f} req/s")
-    srv = wg.Server(0, slots=args.slots)
+    progress(f"plain path: capacity {capacity:.1f} req/s ({sum(service):.2f} s of service)")
+    srv = wg.Server(0, slots=args.slots, hold_after_us=getattr(args, "hold_after_us", 0))
     for (s, d), r in list(zip(dev, reqs))[:2 * args.slots]:
         srv.submit(r.query, s, d).wait(want_result=False)
     progress("server warm")
+    checks = {"size_iterations": 0, "sha256": 0, "mismatches": 0}
 
-    def at_load(load):
-        rate = load * capacity
+    def arrivals_at(load):
         rng = np.random.default_rng(5)
-        gaps = rng.exponential(1.0 / rate, size=len(reqs))
-        arrivals = np.cumsum(gaps) - gaps[0]
-        # the plain path as one FIFO server under the same arrivals
-        fin, plain_lat = 0.0, []
-        for a, sv in zip(arrivals, service):
-            fin = max(fin, a) + sv
-            plain_lat.append(fin - a)
-        # served: submit at the arrival times; results stay on the device until waited
+        gaps = rng.exponential(1.0 / (load * capacity), size=len(reqs))
+        return np.cumsum(gaps) - gaps[0]
+
+    def plain_at(arrivals):
+        # one engine, requests in arrival order, each started when it has arrived and the
+        # previous one is done (a FIFO queue in front of the plain path)
+        lat, tuples = [], 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for (s, d), r, a in zip(dev, reqs, arrivals):
+            delay = t0 + a - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            _, _, st = eng.solve(r.query, s, d, None, want_result=False)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t0 - a)
+            tuples += st["result_tuples"]
+        span = time.perf_counter() - t0
+        return lat, tuples, span
+
+    def served_at(arrivals, hash_results):
         jobs = []
         t0 = time.perf_counter()
         for (s, d), r, a in zip(dev, reqs, arrivals):
@@ -378,42 +415,53 @@ def run_served(args):
                 time.sleep(delay)
             jobs.append(srv.submit(r.query, s, d))
         lat, tuples, first, last = [], 0, None, None
-        for j in jobs:
-            _, _, st, info = j.wait(want_result=False)
+        for i, j in enumerate(jobs):
+            s_, d_, st, info = j.wait(want_result=hash_results)
             lat.append((info["end_ms"] - info["submit_ms"]) / 1e3)
             tuples += st["result_tuples"]
             first = info["submit_ms"] if first is None else min(first, info["submit_ms"])
             last = info["end_ms"] if last is None else max(last, info["end_ms"])
             j.close()
-        span = (last - first) / 1e3
-        res = {"load": load, "offered_req_per_s": round(rate, 2),
+            if golden is not None:
+                rec = golden[i]
+                checks["size_iterations"] += 1
+                if st["result_tuples"] != rec["size"] or st["iterations"] != rec["iterations"]:
+                    checks["mismatches"] += 1
+                if hash_results:
+                    checks["sha256"] += 1
+                    if _pairs_sha(s_, d_) != rec["sha256"]:
+                        checks["mismatches"] += 1
+            del s_, d_
+        return lat, tuples, (last - first) / 1e3
+
+    sweep = []
+    loads = sorted(set([args.load, 0.7, 1.0, 1.5]))
+    for k, load in enumerate(loads):
+        arr = arrivals_at(load)
+        lat, tuples, span = served_at(arr, hash_results=(k == 0))
+        plat, ptuples, pspan = plain_at(arr)
+        res = {"load": load, "offered_req_per_s": round(load * capacity, 2),
                "served": {"p50_ms": round(1e3 * percentile(lat, 50), 3),
                           "p99_ms": round(1e3 * percentile(lat, 99), 3),
                           "tuples_per_s": round(tuples / span, 1), "span_ms": round(1e3 * span, 3)},
-               "single_instance_path": {"p50_ms": round(1e3 * percentile(plain_lat, 50), 3),
-                                        "p99_ms": round(1e3 * percentile(plain_lat, 99), 3),
-                                        "tuples_per_s": round(plain_tuples / fin, 1),
-                                        "span_ms": round(1e3 * fin, 3)}}
+               "single_instance_path": {"p50_ms": round(1e3 * percentile(plat, 50), 3),
+                                        "p99_ms": round(1e3 * percentile(plat, 99), 3),
+                                        "tuples_per_s": round(ptuples / pspan, 1), "span_ms": round(1e3 * pspan, 3),
+                                        "measured": True}}
         progress(f"load {load}: {res}")
-        return res, tuples, span
-
-    sweep = []
-    for load in sorted(set([args.load, 1.0, 1.5])):
-        res, tuples_l, span_l = at_load(load)
         sweep.append(res)
-        if load == args.load:
-            head, tuples, span = res, tuples_l, span_l
+    eng.close()
     stats = srv.stats()
     srv.close()
-    rate = head["offered_req_per_s"]
-    out = {
+    head = next(x for x in sweep if x["load"] == args.load)
+    return {
         "metric": "derived tuples/sec per TC/SG fixpoint; p50/p99 served latency",
-        "value": round(tuples / span, 1),
+        "value": head["served"]["tuples_per_s"],
         "unit": "tuples/s",
         "n_gpus": 1,
         "steps": 1,
         "warmup": 2 * args.slots,
-        "ms_per_step": round(1e3 * span, 3),
+        "ms_per_step": head["served"]["span_ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -422,7 +470,7 @@ def run_served(args):
         "config": {"workload": WORKLOAD_TEXT["served_mix"], "name": "served_mix",
                    "requests": len(reqs), "slots": args.slots, "edges": int(sum(len(r.src) for r in reqs)),
                    "tc_requests": sum(r.query == "tc" for r in reqs),
-                   "offered_rate_per_s": round(rate, 2), "load": args.load},
+                   "offered_rate_per_s": head["offered_req_per_s"], "load": args.load},
         "served": dict(head["served"], max_running=stats["max_running"], requeued=stats["requeued"],
                        failed=stats["failed"]),
         "single_instance_path": dict(head["single_instance_path"],
@@ -430,9 +478,22 @@ def run_served(args):
                                      service_ms_p50=round(1e3 * percentile(service, 50), 3),
                                      service_ms_max=round(1e3 * max(service), 3)),
         "load_sweep": sweep,
+        "golden_checks": checks if golden is not None else None,
         "roofline": None,
-        "cpu_baseline": None if args.no_cpu_baseline else served_cpu_baseline(reqs),
     }
+
+
+def run_served(args):
+    """Continuous batching under Poisson arrivals vs the plain one-at-a-time path."""
+    import torch  # noqa: F401
+
+    from paper_2607_17571_amd import inputs
+
+    cb = None
+    if not args.no_cpu_baseline:
+        cb = served_cpu_baseline(inputs.served_requests(args.requests, seed=5))
+    out = measure_served(args)
+    out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 
@@ -871,9 +932,11 @@ def main():
         _progress(f"extra: {SG_EXTRA}")
         sub.steps, sub.warmup = args.steps, min(args.warmup, 3)
         extra["sg"] = with_cpu(measure(sub, SG_EXTRA), SG_EXTRA)
-        extra["served"] = None
-        extra["served_note"] = ("not measured in this line: the full-size served mix is held back "
-                                "after an unexplained GPU fault (run it with --workload served_mix)")
+        _progress("extra: served_mix")
+        sub.requests, sub.slots, sub.load, sub.hold_after_us = 120, 4, 0.7, 0
+        sv = measure_served(sub)
+        extra["served"] = {k: sv[k] for k in ("value", "unit", "served", "single_instance_path", "load_sweep",
+                                              "golden_checks", "config")}
         out["extra"] = extra
     print(json.dumps(out), flush=True)
 

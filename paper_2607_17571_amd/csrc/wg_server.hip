@@ -100,6 +100,7 @@ struct wg_server {
   double alpha[2] = {8192.0, 8192.0};  // reservation bytes per edge (TC, SG)
   bool stop = false;
   double t0 = 0;
+  double hold_after_ms = 8.0;  // a solve running longer holds back admissions (< 0: never)
   wg_server_stats st{};
   std::string err;
 };
@@ -152,11 +153,15 @@ uint64_t estimate(const wg_server* sv, const JobState& j) {
 std::shared_ptr<JobState> pick(wg_server* sv, size_t i, uint64_t* grant) {
   Slot& me = *sv->slots[i];
   bool others_run = false;
+  const double now = now_ms();
   for (size_t k = 0; k < sv->slots.size(); ++k) {
     const Slot& o = *sv->slots[k];
     if (k == i || !o.job) continue;
     others_run = true;
     if (o.waiting_memory) return nullptr;  // memory that frees up goes to waiting solves first
+    // a long solve (the heavy tail of the mix) finishes faster alone than beside new
+    // arrivals; those wait until it ends (its slot notifies at the end)
+    if (sv->hold_after_ms >= 0 && now - o.busy_since > sv->hold_after_ms) return nullptr;
   }
   const uint64_t others = usage_except(sv, i);
   const uint64_t held = (uint64_t)std::max<int64_t>(sv->core->held, 0);
@@ -381,6 +386,8 @@ wg_status wg_server_create(int device, const wg_server_config* cfg, wg_server** 
   sv->t0 = now_ms();
   sv->core->t0 = sv->t0;
   sv->st.budget_bytes = budget;
+  const uint32_t hold = cfg ? cfg->hold_after_us : 0;
+  sv->hold_after_ms = hold == 0xFFFFFFFFu ? -1.0 : (hold == 0 ? 8.0 : hold / 1000.0);
   if (hipStreamCreateWithFlags(&sv->copy_stream, hipStreamNonBlocking) != hipSuccess) {
     delete sv;
     return WG_ERR_DEVICE;

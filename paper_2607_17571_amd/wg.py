@@ -117,7 +117,7 @@ class WgTuneReport(ctypes.Structure):
 
 
 class WgServerConfig(ctypes.Structure):
-    _fields_ = [("slots", c_uint32), ("reserved", c_uint32), ("mem_budget_bytes", c_uint64)]
+    _fields_ = [("slots", c_uint32), ("hold_after_us", c_uint32), ("mem_budget_bytes", c_uint64)]
 
 
 class WgServerStats(ctypes.Structure):
@@ -343,9 +343,9 @@ def wg_autotune(engine, query: int, num: int, d_offsets: int, d_src: int, d_dst:
     return st, rep
 
 
-def wg_server_create(device: int = 0, slots: int = 0, mem_budget_bytes: int = 0) -> c_void_p:
+def wg_server_create(device: int = 0, slots: int = 0, mem_budget_bytes: int = 0, hold_after_us: int = 0) -> c_void_p:
     srv = c_void_p()
-    st = lib().wg_server_create(device, byref(WgServerConfig(slots, 0, mem_budget_bytes)), byref(srv))
+    st = lib().wg_server_create(device, byref(WgServerConfig(slots, hold_after_us, mem_budget_bytes)), byref(srv))
     if st != WG_OK:
         raise WgError(st, f"wg_server_create(device={device})")
     return srv
@@ -760,13 +760,15 @@ class Job:
 class Server:
     """Continuous-batching request server (wg_server_*) on one device."""
 
-    def __init__(self, device: int = 0, slots: int = 0, mem_budget_bytes: int = 0):
+    def __init__(self, device: int = 0, slots: int = 0, mem_budget_bytes: int = 0, hold_after_us: int = 0):
+        """hold_after_us: a solve running this long holds back admissions until it ends
+        (0: the server's default, 0xFFFFFFFF: never)."""
         import torch
 
         if not torch.cuda.is_available():
             raise RuntimeError("the request server needs a ROCm GPU")
         self.device = device
-        self.handle = wg_server_create(device, slots, mem_budget_bytes)
+        self.handle = wg_server_create(device, slots, mem_budget_bytes, hold_after_us)
 
     def submit(self, query: str, src, dst, options: WgOptions | None = None) -> Job:
         """src / dst: torch tensors (GPU or CPU) or numpy arrays of uint32 ids."""

@@ -64,6 +64,28 @@ def test_alone_equals_in_mix(engine):
     assert stats["max_running"] >= 2  # the requests did share the device
 
 
+@pytest.mark.parametrize("hold_after_us", [1, 0xFFFFFFFF], ids=["hold-1us", "never-hold"])
+def test_long_solve_hold_keeps_results(engine, hold_after_us):
+    """The long-solve hold changes only when requests start: with a 1 us hold (every running
+    solve holds back the queue: nearly one at a time) and with no hold, every result equals
+    the request solved alone."""
+    reqs = inputs.served_requests(12, seed=22, n_lo=100, n_hi=3000)
+    print(f"[gpu] serve mix of {len(reqs)}, hold {hold_after_us} us", flush=True, file=sys.stderr)
+    srv = wg.Server(0, slots=4, mem_budget_bytes=8 << 30, hold_after_us=hold_after_us)
+    try:
+        mix = served(srv, reqs)
+        stats = srv.stats()
+    finally:
+        srv.close()
+    for r, (s, d, st, info) in zip(reqs, mix):
+        a_s, a_d, a_st = run_single(engine, r.query, r.src, r.dst)
+        np.testing.assert_array_equal(s, a_s)
+        np.testing.assert_array_equal(d, a_d)
+        assert st["iterations"] == a_st["iterations"]
+        assert info["phase"] == 2 and info["status"] == wg.WG_OK
+    assert stats["completed"] == len(reqs) and stats["failed"] == 0
+
+
 def test_tight_budget_requeues_and_rejects_oversize(engine):
     """A 320 MB budget: medium requests must share it; one request needs far more."""
     reqs = [inputs.Request("tc", "rmat", 1 << 12, *inputs.rmat(12, 3800, *inputs.RMAT_ABCD, seed=s))
