@@ -1732,31 +1732,52 @@ __global__ __launch_bounds__(kBlock) void k_row_diff(int gate, Ctrl* ctrl, const
   const uint64_t n = *n_ptr;
   const uint32_t tid = threadIdx.x;
   const int wid = (int)(tid / kWave);
-  uint64_t lo, hi;
-  // ranges of whole tiles, or a smaller input spread evenly over the grid (each block then
-  // owns the few rows that start in its range)
-  block_range(n, compact_span(n, kRowTile, gridDim.x), lo, hi);
-  // the first row that starts in [lo, hi)
-  uint64_t p = lo;
-  if (lo < hi && lo > 0) {
-    const K before = in[lo - 1] >> w;
-    if ((in[lo] >> w) == before) {
-      if (wid == 0) {
-        const uint64_t v = wave_partition(lo, hi, [&](uint64_t i) { return (in[i] >> w) == before; });
-        if (lane_id() == 0) s_at[0] = v;
-      }
-      __syncthreads();
-      p = s_at[0];
-      __syncthreads();
+  const IterRec rp = b.rec[j - 1];
+  const K* __restrict__ runA = b.full[rp.a];
+  const K* __restrict__ runB = b.fullB[rp.b];
+  const uint64_t FA = rp.FA, FB = rp.F - rp.FA;
+  // Rows for this block: a row costs its candidates and its keys of Full, so the blocks
+  // split the rows by rank in the merge (by row) of the candidates and the larger run of
+  // Full -- equal shares of both -- rather than by candidate position alone.  Block b owns
+  // the rows from the row at merged rank b*T/G up to the one at rank (b+1)*T/G; a row
+  // spanning several boundaries goes to the last block whose boundary falls in it.
+  {
+    const bool xa = FA >= FB;
+    const K* __restrict__ X = xa ? runA : runB;
+    const uint64_t nx = xa ? FA : FB;
+    const uint64_t total = n + nx;
+    constexpr uint64_t kInf = ~0ull;
+    // row of the element at merged rank d (rows of Full first on ties); kInf past the end
+    auto row_at = [&](uint64_t d) -> uint64_t {
+      if (d >= total) return kInf;
+      const uint64_t ilo = d > nx ? d - nx : 0, ihi = d < n ? d : n;
+      // candidates among the first d merged elements: C[i] precedes X[d-1-i] while its row
+      // is smaller (true for a prefix of i)
+      const uint64_t i = wave_partition(ilo, ihi, [&](uint64_t q) {
+        return (uint64_t)(in[q] >> w) < (uint64_t)(X[d - 1 - q] >> w);
+      });
+      const uint64_t rc = i < n ? (uint64_t)(in[i] >> w) : kInf;
+      const uint64_t rx = d - i < nx ? (uint64_t)(X[d - i] >> w) : kInf;
+      return rc < rx ? rc : rx;
+    };
+    // first candidate position whose row is at least r
+    auto row_pos = [&](uint64_t r) -> uint64_t {
+      if (r == kInf) return n;
+      return wave_partition(0, n, [&](uint64_t q) { return (uint64_t)(in[q] >> w) < r; });
+    };
+    if (wid < 2) {
+      const uint64_t d = (total * (uint64_t)(blockIdx.x + wid)) / gridDim.x;
+      const uint64_t v = row_pos(blockIdx.x + wid == 0 ? 0 : row_at(d));
+      if (lane_id() == 0) s_at[wid] = v;
     }
+    __syncthreads();
   }
+  const uint64_t lo = s_at[0], hi = s_at[1];
+  __syncthreads();
+  uint64_t p = lo;
   const uint64_t out0 = p;
   uint64_t running = 0;
   if (p < hi) {
-    const IterRec rp = b.rec[j - 1];
-    const K* __restrict__ runA = b.full[rp.a];
-    const K* __restrict__ runB = b.fullB[rp.b];
-    const uint64_t FA = rp.FA, FB = rp.F - rp.FA;
     const uint32_t words = w > 5 ? 1u << (w - 5) : 1u;
     const K fmask = field_mask<K>(w);
     // Full's cursors at the first row's keys
