@@ -1,4 +1,7 @@
-"""Regression test (CPU): the early exit of a launch is decided once per block.
+"""Kernel text on the CPU SIMT shim (tests/simt): concurrency and bounds checks that a
+GPU run cannot give.
+
+Regression test: the early exit of a launch is decided once per block.
 
 Block 0 of the row pass's gather records the iteration and, for an empty delta, sets the
 fixpoint flag that every block tests at its start; the join's emit and the compaction's
@@ -31,17 +34,20 @@ pytestmark = pytest.mark.skipif(shutil.which("g++") is None or platform.machine(
                                 reason="needs g++ on x86-64 (the shim switches fibers in x86-64 assembly)")
 
 
-@pytest.fixture(scope="module")
-def harness(tmp_path_factory):
-    d = tmp_path_factory.mktemp("simt")
+def _build(d, harness_src, inc_name, names):
     inc = subprocess.run([sys.executable, os.path.join(SIMT, "extract.py"), os.path.join(CSRC, "wg_kernels.hip"),
-                          *KERNELS], capture_output=True, text=True, check=True).stdout
-    (d / "row.inc").write_text(inc)
-    exe = d / "row_harness"
+                          *names], capture_output=True, text=True, check=True).stdout
+    (d / inc_name).write_text(inc)
+    exe = d / os.path.splitext(harness_src)[0]
     subprocess.run(["g++", "-std=c++20", "-O1", "-g", "-fsanitize=address", "-fno-omit-frame-pointer",
                     f"-I{d}", f"-I{SIMT}", f"-I{CSRC}", f"-I{os.path.join(ROOT, 'include')}", "-pthread",
-                    os.path.join(SIMT, "row_harness.cpp"), "-o", str(exe)], check=True, capture_output=True)
+                    os.path.join(SIMT, harness_src), "-o", str(exe)], check=True, capture_output=True)
     return exe
+
+
+@pytest.fixture(scope="module")
+def harness(tmp_path_factory):
+    return _build(tmp_path_factory.mktemp("simt"), "row_harness.cpp", "row.inc", KERNELS)
 
 
 def _write(path, cand, a, b, w):
@@ -83,3 +89,46 @@ def test_row_gather_blocks_never_split(harness, tmp_path, empty_delta):
     assert "simt:" not in r.stderr, r.stderr[-2000:]
     assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-2000:])
     assert r.stdout.count("ok ") == 20
+
+
+COMPACT = ["drop_present", "drop_present_sampled", "compact_span", "k_compact_local", "compact_gather",
+           "k_compact_gather"]
+
+
+@pytest.fixture(scope="module")
+def compact_harness(tmp_path_factory):
+    return _build(tmp_path_factory.mktemp("simt_c"), "compact_harness.cpp", "compact.inc", COMPACT)
+
+
+def _compact_case(seed, key_bytes, per_item):
+    """Sorted candidates (half of them keys of Full, with duplicates) against Full split into
+    runs A and B; about `per_item` keys of Full per candidate, so that the tiles' windows are
+    staged whole (< 1) or searched through staged samples (more)."""
+    rng = np.random.default_rng(seed)
+    bits = 30 if key_bytes == 4 else 48
+    full = np.unique(rng.integers(0, 1 << bits, size=300_000, dtype=np.uint64))
+    nc = max(2, int(full.size / per_item))
+    new = rng.integers(0, 1 << bits, size=nc - nc // 2, dtype=np.uint64)
+    cand = np.sort(np.concatenate([rng.choice(full, size=nc // 2), new, rng.choice(new, size=nc // 8)]))
+    rng.shuffle(full)
+    nb = full.size // 4
+    return cand, np.sort(full[nb:]), np.sort(full[:nb])
+
+
+@pytest.mark.parametrize("key_bytes,per_item,items", [(4, 0.5, 8), (4, 6, 8), (8, 6, 4), (8, 300, 8)],
+                         ids=["u32-staged", "u32-sampled", "u64-sampled-narrow", "u64-sampled-sparse"])
+def test_compaction_windows(compact_harness, tmp_path, key_bytes, per_item, items):
+    cand, a, b = _compact_case(11 + items, key_bytes, per_item)
+    path = tmp_path / "in.bin"
+    dt = np.uint32 if key_bytes == 4 else np.uint64
+    with open(path, "wb") as f:
+        np.array([cand.size, a.size, b.size, 15 if key_bytes == 4 else 24, key_bytes], dtype=np.uint64).tofile(f)
+        cand.astype(dt).tofile(f)
+        a.astype(dt).tofile(f)
+        b.astype(dt).tofile(f)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
+    r = subprocess.run([str(compact_harness), str(path), "64", "8", "3", str(items)], capture_output=True, text=True,
+                       env=env, timeout=300)
+    assert "simt:" not in r.stderr, r.stderr[-2000:]
+    assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-2000:])
+    assert r.stdout.count("ok ") == 3
