@@ -71,7 +71,10 @@ inline thread_local uint64_t wbar_gen[16];
 inline thread_local uint32_t wbar_count[16];
 inline thread_local uint64_t xch[16][64];
 inline thread_local uint64_t switches = 0;
-constexpr size_t kStack = 256 * 1024;
+#ifndef SIMT_STACK
+#define SIMT_STACK (256 * 1024)
+#endif
+constexpr size_t kStack = SIMT_STACK;
 
 inline void to_sched() {
   void* fake = nullptr;

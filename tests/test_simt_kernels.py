@@ -39,7 +39,8 @@ def _build(d, harness_src, inc_name, names):
                           *names], capture_output=True, text=True, check=True).stdout
     (d / inc_name).write_text(inc)
     exe = d / os.path.splitext(harness_src)[0]
-    subprocess.run(["g++", "-std=c++20", "-O1", "-g", "-fsanitize=address", "-fno-omit-frame-pointer",
+    subprocess.run(["g++", "-std=c++20", "-O1", "-g", "-DSIMT_STACK=131072", "-fsanitize=address",
+                    "-fno-omit-frame-pointer",
                     f"-I{d}", f"-I{SIMT}", f"-I{CSRC}", f"-I{os.path.join(ROOT, 'include')}", "-pthread",
                     os.path.join(SIMT, harness_src), "-o", str(exe)], check=True, capture_output=True)
     return exe
@@ -132,3 +133,36 @@ def test_compaction_windows(compact_harness, tmp_path, key_bytes, per_item, item
     assert "simt:" not in r.stderr, r.stderr[-2000:]
     assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-2000:])
     assert r.stdout.count("ok ") == 3
+
+
+SEG = ["const:kSmallSortThreads", "shfl_xor_key", "bitonic_keep", "block_bitonic_sort", "const:kSegTile",
+       "const:kSegBitonicMax", "const:kSegLongBytes", "k_seg_sort"]
+
+
+@pytest.fixture(scope="module")
+def seg_harness(tmp_path_factory):
+    return _build(tmp_path_factory.mktemp("simt_s"), "seg_harness.cpp", "seg.inc", SEG)
+
+
+@pytest.mark.parametrize("key_bytes,lens", [(4, (1, 6)), (4, (1, 400)), (8, (1, 2000))],
+                         ids=["u32-short-rows", "u32-rows-to-400", "u64-rows-to-2000"])
+def test_segmented_sort(seg_harness, tmp_path, key_bytes, lens):
+    """The segmented sort of row-grouped candidates (rows ascending, each row's keys in any
+    order), 1,024 threads a block, blocks concurrent: the output is the keys sorted.  (A tile
+    plus the tail of its last row stays within the one-block network here; longer rows are
+    the long-row pass's.)"""
+    rng = np.random.default_rng(31 + lens[1])
+    w = 15 if key_bytes == 4 else 24
+    rows = np.sort(rng.choice(1 << 16, size=400, replace=False)).astype(np.uint64)
+    keys = np.concatenate([(r << np.uint64(w)) | rng.integers(0, 1 << w, size=int(rng.integers(*lens)),
+                                                              dtype=np.uint64) for r in rows])
+    path = tmp_path / "in.bin"
+    with open(path, "wb") as f:
+        np.array([keys.size, w, key_bytes], dtype=np.uint64).tofile(f)
+        keys.astype(np.uint32 if key_bytes == 4 else np.uint64).tofile(f)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
+    r = subprocess.run([str(seg_harness), str(path), "64", "8", "2"], capture_output=True, text=True, env=env,
+                       timeout=300)
+    assert "simt:" not in r.stderr, r.stderr[-2000:]
+    assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-2000:])
+    assert r.stdout.count("ok ") == 2
