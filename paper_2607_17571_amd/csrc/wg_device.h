@@ -109,11 +109,11 @@ __device__ __forceinline__ bool block_stop(bool stop) {
 
 // An iteration enqueued with both routes (gate 1: the row route, 2: the sort route; 0: no
 // gate): the join's candidate count picks one -- the rows from `row_min` candidates on and
-// while they are at least as many as the tuples of Full (the row pass streams each touched
-// row of Full, the compaction only the windows its candidates span).
-__device__ __forceinline__ bool gated_out(const Ctrl* c, int gate, uint64_t row_min) {
+// while Full has at most `full_per_cand` tuples per candidate (the row pass streams each
+// touched row of Full; the sort route moves every candidate through the sort passes).
+__device__ __forceinline__ bool gated_out(const Ctrl* c, int gate, uint64_t row_min, uint64_t full_per_cand) {
   if (gate == 0) return false;
-  const bool row = c->cand_n >= row_min && c->cand_n >= c->full_n;
+  const bool row = c->cand_n >= row_min && c->cand_n * full_per_cand >= c->full_n;
   return gate == 1 ? !row : row;
 }
 

@@ -640,9 +640,9 @@ void bytes_model(wg_stats* st, int query, uint32_t kb, int passes, uint64_t m,
     const double F = (double)rec[i - 1].F;
     uint8_t sorted_by = i < how.size() ? how[i] : kSortLsd;
     // an iteration enqueued with both routes: the device took the rows when the join found
-    // at least kRowMin candidates and no fewer than Full's tuples
+    // at least kRowMin candidates and Full had at most kRowFullPerCand tuples per candidate
     const bool rows = (sorted_by == kSortDual || sorted_by == kSortDualLsd) && rec[i].C >= kRowMin &&
-                      rec[i].C >= rec[i - 1].F;
+                      rec[i].C * kRowFullPerCand >= rec[i - 1].F;
     if (sorted_by == kSortDual) sorted_by = kSortSegmented;
     if (sorted_by == kSortDualLsd) sorted_by = kSortLsd;
     if (sorted_by == kSortOneBlock) {
@@ -868,9 +868,10 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
     const double ahead = (double)x.C * g * g * g * g;
     e->narrow = ahead < (double)kNarrowBelow;
     e->seg_sort = seg_allowed && ahead < (double)kSegBelow;
-    // (the row route needs at least as many candidates as Full has tuples, and Full only
-    // grows: below that the row launches would all be gated off)
-    e->row_bitmap = row_allowed && seg_allowed && ahead >= std::max((double)kDualAbove, (double)x.F);
+    // (the row route needs at least a kRowFullPerCand-th of Full's tuples as candidates, and
+    // Full only grows: below that the row launches would all be gated off)
+    e->row_bitmap = row_allowed && seg_allowed && ahead >= (double)kDualAbove &&
+                    ahead * (double)kRowFullPerCand >= (double)x.F;
     e->seg_long = (e->seg_sort || e->row_bitmap) && long_forced;
     if (!small_missed && K_batch <= kAutoK && it >= 2 && calm(x.C, y.C, small_keys))
       e->small_mode = calm(x.N, y.N, kSmallJoinTuples) ? 3 : 2;

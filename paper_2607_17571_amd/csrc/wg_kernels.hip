@@ -901,7 +901,7 @@ __global__ __launch_bounds__(kSmallSortThreads) void k_seg_sort(int gate, Ctrl* 
   __shared__ K s[CAP];
   __shared__ uint32_t s_first, s_last;
   __shared__ uint64_t s_end;
-  if (block_stop(halted(ctrl) || gated_out(ctrl, gate, kRowMin))) return;
+  if (block_stop(halted(ctrl) || gated_out(ctrl, gate, kRowMin, kRowFullPerCand))) return;
   const uint64_t n = *n_ptr;
   const uint64_t ntiles = (n + kSegTile - 1) / kSegTile;
   const uint32_t t = threadIdx.x;
@@ -982,7 +982,7 @@ __global__ __launch_bounds__(kSmallSortThreads) void k_seg_long(int gate, Ctrl* 
   __shared__ K s_k[LCAP];
   __shared__ uint32_t s_cnt[NW][R];
   __shared__ uint32_t s_wave[NW];
-  if (block_stop(halted(ctrl) || gated_out(ctrl, gate, kRowMin))) return;
+  if (block_stop(halted(ctrl) || gated_out(ctrl, gate, kRowMin, kRowFullPerCand))) return;
   const uint32_t rows = ctrl->seg_long;
   const int passes = w > RB ? (w + RB - 1) / RB : 1;
   const int tid = threadIdx.x;
@@ -1493,7 +1493,8 @@ __global__ __launch_bounds__(kBlock) void k_compact_local(Ctrl* ctrl, int mode, 
   __shared__ uint64_t s_lo[2], s_hi[2];
   const bool filt = (mode & kModeFilter) != 0;
   if (block_stop((!filt && halted(ctrl)) ||
-                 gated_out(ctrl, (mode & kModeGateRow) ? 1 : ((mode & kModeGateSort) ? 2 : 0), kRowMin)))
+                 gated_out(ctrl, (mode & kModeGateRow) ? 1 : ((mode & kModeGateSort) ? 2 : 0), kRowMin,
+                           kRowFullPerCand)))
     return;
   j = iter_cur(ctrl, j);
   const uint64_t n = *n_ptr;
@@ -1724,7 +1725,7 @@ __global__ __launch_bounds__(kBlock) void k_row_diff(int gate, Ctrl* ctrl, const
   __shared__ uint32_t s_pre[kRowWordsMax];  // new bits in the words before each word
   __shared__ uint32_t s_wave[kWavesPerBlock];
   __shared__ uint64_t s_at[3];              // broadcast of wave searches
-  if (block_stop(halted(ctrl) || gated_out(ctrl, gate, kRowMin))) return;
+  if (block_stop(halted(ctrl) || gated_out(ctrl, gate, kRowMin, kRowFullPerCand))) return;
   // this iteration needs no sort: LSD passes enqueued behind (the other route) are no-ops
   // (the gather clears the flag)
   if (gate != 0 && blockIdx.x == 0 && threadIdx.x == 0) ctrl->small_sorted = 1;
@@ -1913,7 +1914,8 @@ __device__ __forceinline__ void compact_gather(Ctrl* ctrl, int mode, const uint6
   constexpr uint32_t T = kBlock * ITEMS;  // the tile of the local pass it follows
   const bool filt = (mode & kModeFilter) != 0;
   if (block_stop((!filt && halted(ctrl)) ||
-                 gated_out(ctrl, (mode & kModeGateRow) ? 1 : ((mode & kModeGateSort) ? 2 : 0), kRowMin)))
+                 gated_out(ctrl, (mode & kModeGateRow) ? 1 : ((mode & kModeGateSort) ? 2 : 0), kRowMin,
+                           kRowFullPerCand)))
     return;
   j = iter_cur(ctrl, j);
   // the sort before this compaction is over: a later sort that skips the one-block path

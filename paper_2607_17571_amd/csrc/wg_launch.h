@@ -38,6 +38,12 @@ constexpr int kRowBitsMax = 16;
 // the join's candidate count and return at once unless it picks their route (the row pass
 // from kRowMin candidates on).  gate: 0 none, 1 the row route, 2 the sort route.
 constexpr uint64_t kRowMin = 1ull << 21;
+// ... and while Full has at most this many tuples per candidate: the row pass costs about
+// the candidates plus the touched rows of Full, the sort route (LSD passes and compaction)
+// about five times the candidates plus the windows of Full, so the rows win up to a Full of
+// some four times the candidates (measured on R-MAT 15: its fifth iteration, 27M candidates
+// against 44M tuples of Full, runs twice as fast on the rows).
+constexpr uint64_t kRowFullPerCand = 4;
 
 // Tile sizes (items per tile) of the static-range kernels.
 constexpr int kJoinItems = 8;
