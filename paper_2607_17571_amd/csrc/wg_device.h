@@ -224,10 +224,10 @@ __device__ __forceinline__ T block_excl_scan(T v, T* s_wave, T& total) {
 }
 
 // Exclusive prefix sums of the per-block totals vals[0..G) of a producer launch, into
-// LDS s_pre[0..G); returns the grand total in every thread.  G <= 4 * kBlock.
+// LDS s_pre[0..G); returns the grand total in every thread.  G <= PER * kBlock.
+template <int PER = 4>
 __device__ __forceinline__ uint64_t block_prefix(const uint64_t* __restrict__ vals, int G,
                                                  uint64_t* s_pre, uint64_t* s_wave) {
-  constexpr int PER = 4;
   uint64_t v[PER];
   uint64_t sum = 0;
 #pragma unroll

@@ -52,9 +52,9 @@ constexpr uint64_t kDenseRowsMax = 1ull << 28;  // largest dense edge index (1 G
 // fixed arrays of an engine: control block, join and compaction block totals, radix counts
 // and totals (the triangle hits depend on the grid)
 constexpr size_t kFixedBytes[6] = {sizeof(Ctrl), sizeof(uint64_t) * kScanBlocksMax,
-                                   sizeof(uint64_t) * kScanBlocksMax,
+                                   sizeof(uint64_t) * std::max<size_t>(kScanBlocksMax, kRowBlocks),
                                    sizeof(uint32_t) * kRadixMax * kRadixBlocksMax, sizeof(uint32_t) * kRadixMax,
-                                   sizeof(uint64_t) * kScanBlocksMax};
+                                   sizeof(uint64_t) * kRowBlocks};
 
 thread_local std::string wg_call_error;  // see set_call_error
 

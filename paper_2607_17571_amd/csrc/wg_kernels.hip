@@ -1680,7 +1680,8 @@ __global__ __launch_bounds__(kBlock) void k_compact_local(Ctrl* ctrl, int mode, 
 // streaming pass over its candidates and the rows of Full they touch.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kRowWordsMax = (1u << kRowBitsMax) / 32;
-constexpr uint32_t kRowTile = kBlock * 16;  // keys streamed per round
+constexpr int kRowItems = 8;                      // keys per thread per round
+constexpr uint32_t kRowTile = kBlock * kRowItems;  // keys streamed per round
 
 // Position of the k-th set bit (k = 0 the lowest) of v, which has more than k set bits.
 __device__ __forceinline__ uint32_t nth_set_bit(uint32_t v, uint32_t k) {
@@ -1804,7 +1805,7 @@ __global__ __launch_bounds__(kBlock) void k_row_diff(int gate, Ctrl* ctrl, const
       for (uint64_t q = from;; q += kRowTile) {
         uint32_t mine = 0;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
+        for (int k = 0; k < kRowItems; ++k) {
           const uint64_t i = q + (uint64_t)k * kBlock + tid;
           bool in_row = false;
           uint32_t d = 0;
@@ -1907,6 +1908,29 @@ __global__ __launch_bounds__(kBlock) void k_row_diff(int gate, Ctrl* ctrl, const
   }
 }
 
+// Where the merge of iteration j puts Full, and record j: the delta goes into B (the other B
+// buffer), or, when B would outgrow A / kFoldRatio, B folds into A (the other A buffer) and
+// the delta alone becomes B.  With an empty delta nothing is merged and both runs stay
+// where they are.  (One thread, after the delta of N tuples is in place; F = |Full| before.
+// |Full| for the route gates is updated by the merge.)
+template <typename K>
+__device__ __forceinline__ void record_iteration(Ctrl* ctrl, const Bufs<K>& b, uint32_t j, uint64_t N,
+                                                 uint64_t F) {
+  const IterRec rp = b.rec[j - 1];
+  const uint64_t fb = rp.F - rp.FA;
+  const bool fold = N > 0 && fb > 0 && (fb + N) * kFoldRatio > rp.FA;
+  IterRec& r = b.rec[j];
+  r.N = N;
+  r.F = F + N;
+  r.FA = fold ? F : rp.FA;
+  r.a = fold ? (rp.a ^ 1u) : rp.a;
+  r.b = N > 0 ? (rp.b ^ 1u) : rp.b;
+  r.fold = fold ? 1u : 0u;
+  ctrl->iter = j;
+  if (N == 0) ctrl->done = 1;
+  else if (ctrl->max_iter != 0 && j >= ctrl->max_iter) ctrl->limit_hit = 1;
+}
+
 template <typename K, int ITEMS>
 __device__ __forceinline__ void compact_gather(Ctrl* ctrl, int mode, const uint64_t* n_ptr, const K* __restrict__ tmp,
                                                Bufs<K> b, uint32_t j, uint32_t side, uint64_t* s_pre,
@@ -1929,7 +1953,6 @@ __device__ __forceinline__ void compact_gather(Ctrl* ctrl, int mode, const uint6
   const uint64_t N = block_prefix(b.bcnt, gridDim.x, s_pre, s_wave);
   uint64_t lo, hi;
   block_range(n, compact_span(n, T, gridDim.x), lo, hi);
-  if (mode & kModeRows) lo = b.bstart[blockIdx.x];  // the row pass keeps its own starts
   K* out1 = nullptr;
   K* out2 = nullptr;
   K* out3 = nullptr;
@@ -1973,23 +1996,7 @@ __device__ __forceinline__ void compact_gather(Ctrl* ctrl, int mode, const uint6
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (mode & kModeIter) {
-      // where the merge of iteration j puts Full: the delta goes into B (the other B
-      // buffer), or, when B would outgrow A / kFoldRatio, B folds into A (the other A
-      // buffer) and the delta alone becomes B.  With an empty delta nothing is merged
-      // and both runs stay where they are.
-      const IterRec rp = b.rec[j - 1];
-      const uint64_t fb = rp.F - rp.FA;
-      const bool fold = N > 0 && fb > 0 && (fb + N) * kFoldRatio > rp.FA;
-      IterRec& r = b.rec[j];
-      r.N = N;
-      r.F = F + N;
-      r.FA = fold ? F : rp.FA;
-      r.a = fold ? (rp.a ^ 1u) : rp.a;
-      r.b = N > 0 ? (rp.b ^ 1u) : rp.b;
-      r.fold = fold ? 1u : 0u;
-      ctrl->iter = j;
-      if (N == 0) ctrl->done = 1;
-      else if (ctrl->max_iter != 0 && j >= ctrl->max_iter) ctrl->limit_hit = 1;
+      record_iteration<K>(ctrl, b, j, N, F);
     } else if (mode & (kModeEdges | kModeSeed)) {
       if (mode & kModeEdges) ctrl->m_unique = N;
       if (mode & kModeSeed) {
@@ -2021,14 +2028,41 @@ __global__ __launch_bounds__(kBlock) void k_compact_gather(Ctrl* ctrl, int mode,
   compact_gather<K, ITEMS>(ctrl, mode, n_ptr, tmp, b, j, side, s_pre, s_wave);
 }
 
-// The row pass's gather: the same code as the compaction's (kModeRows), under a name of its
-// own so that profiles tell the two apart.
-template <typename K, int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_row_gather(Ctrl* ctrl, int mode, const uint64_t* n_ptr,
-                                                       const K* __restrict__ tmp, Bufs<K> b, uint32_t j) {
-  __shared__ uint64_t s_pre[kScanBlocksMax];
+// The row pass's gather: the survivors of every row-pass block (kRowBlocks of them), in block
+// order, to delta[j & 1], and record j as the compaction's gather does.  Each block adds up
+// all kRowBlocks totals and copies blocks b, b + G, ...
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_row_gather(int gate, Ctrl* ctrl, const K* __restrict__ tmp, Bufs<K> b,
+                                                       uint32_t j) {
+  __shared__ uint64_t s_pre[kRowBlocks];
   __shared__ uint64_t s_wave[kWavesPerBlock];
-  compact_gather<K, ITEMS>(ctrl, mode | kModeRows, n_ptr, tmp, b, j, 0u, s_pre, s_wave);
+  if (block_stop(halted(ctrl) || gated_out(ctrl, gate, kRowMin, kRowFullPerCand))) return;
+  j = iter_cur(ctrl, j);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctrl->small_sorted = 0;
+    ctrl->seg_long = 0;
+  }
+  static_assert(kRowBlocks % kBlock == 0, "");
+  const uint64_t N = block_prefix<kRowBlocks / kBlock>(b.bcnt, (int)kRowBlocks, s_pre, s_wave);
+  const uint64_t F = b.rec[j - 1].F;
+  uint32_t ovf = 0;
+  if (F + N > ctrl->full_cap) ovf |= 2u;
+  if (N > ctrl->cand_cap) ovf |= 4u;
+  if (ovf) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      b.rec[j].N = N;
+      atomicOr(&ctrl->overflow, ovf);
+    }
+    return;
+  }
+  K* __restrict__ out = b.delta[j & 1u];
+  for (uint32_t r = blockIdx.x; r < kRowBlocks; r += gridDim.x) {
+    const uint64_t cnt = b.bcnt[r];
+    const uint64_t src = b.bstart[r];
+    const uint64_t dst = s_pre[r];
+    for (uint64_t t = threadIdx.x; t < cnt; t += kBlock) out[dst + t] = tmp[src + t];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) record_iteration<K>(ctrl, b, j, N, F);
 }
 
 // ---------------------------------------------------------------------------
@@ -2620,15 +2654,16 @@ void launch_compact(hipStream_t s, const Grid& g, int mode, Ctrl* ctrl, const ui
 template <typename K>
 void launch_row_diff(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint64_t* n_ptr, const Bufs<K>& b, int w,
                      uint32_t j, Ev ev, int gate) {
-  WG_LAUNCH((k_row_diff<K>), g.scan, ev.start, ev.stop, s, gate, ctrl, n_ptr, (const K*)b.cand[0], b.cand[1], b, w,
-            j);
+  (void)g;
+  WG_LAUNCH((k_row_diff<K>), kRowBlocks, ev.start, ev.stop, s, gate, ctrl, n_ptr, (const K*)b.cand[0], b.cand[1], b,
+            w, j);
 }
 
 template <typename K>
 void launch_row_gather(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint64_t* n_ptr, const Bufs<K>& b,
                        uint32_t j, Ev ev, int gate) {
-  WG_LAUNCH((k_row_gather<K, kDedupItems>), g.scan, ev.start, ev.stop, s, ctrl,
-            kModeIter | (gate == 1 ? kModeGateRow : 0), n_ptr, (const K*)b.cand[1], b, j);
+  (void)n_ptr;
+  WG_LAUNCH((k_row_gather<K>), g.scan, ev.start, ev.stop, s, gate, ctrl, (const K*)b.cand[1], b, j);
 }
 
 template <typename K>

@@ -22,9 +22,6 @@ enum CompactMode : int {
   // unfused variant: sorted candidates in cand[side] -> deduplicated in place, count ->
   // dedup_n; a kModeIter pass over them then takes the set difference alone
   kModeDedup = 16,
-  // with kModeIter: the survivors come from the row pass (k_row_diff), whose blocks keep
-  // their own output starts in bstart
-  kModeRows = 32,
   // gates of an iteration enqueued with both routes (see kRowMin): run only on the row route,
   // or only on the sort route
   kModeGateRow = 64,
@@ -44,6 +41,10 @@ constexpr uint64_t kRowMin = 1ull << 21;
 // some four times the candidates (measured on R-MAT 15: its fifth iteration, 27M candidates
 // against 44M tuples of Full, runs twice as fast on the rows).
 constexpr uint64_t kRowFullPerCand = 4;
+// Blocks of the row pass (twice the compaction's grid: rows are streamed with a barrier per
+// round, so more blocks in flight hide more latency; measured 1,024 -> 2,048 blocks:
+// 752 -> 486 us on R-MAT 15's largest iteration).  Its gather sums this many block totals.
+constexpr uint32_t kRowBlocks = 2048;
 
 // Tile sizes (items per tile) of the static-range kernels.
 constexpr int kJoinItems = 8;
@@ -107,6 +108,7 @@ struct Bufs {
   uint64_t* jtot;  // per join-count block: candidates of its range
   uint64_t* bcnt;  // per compaction block: survivors of its range
   uint64_t* bstart; // per row-pass block: first position of its survivors in the scratch
+                    // (kRowBlocks entries; bcnt has as many)
   uint64_t* hits;  // triangle probe: closing edges found per emit block
   uint64_t* htab;  // hash-join variant: open-addressing table of E (power-of-two slots)
   uint32_t* rcnt;  // radix: per-block digit counts, then offsets (digits x blocks)

@@ -1,7 +1,7 @@
 // The row pass and its gather (k_row_diff + k_row_gather, the current kernel text) on the
 // CPU SIMT shim, over one input file, `reps` times: the delta must equal the plain set
 // difference every time, and no block may split (the shim aborts if it does).
-//   row_harness <file> <grid> <workers> <reps>
+//   row_harness <file> <gather grid> <workers> <reps>
 // file: u64 header (candidates, |A|, |B|, w, key bytes), then the three key arrays.
 #include <hip/hip_runtime.h>
 #include "wg_launch.h"
@@ -18,7 +18,8 @@ int run(const std::vector<K>& C, const std::vector<K>& A, const std::vector<K>& 
   const uint64_t n = C.size();
   std::vector<K> cand0(C), cand1(std::max<uint64_t>(n, 1), (K)0x5A5A5A5A), fa(A), fb(B);
   std::vector<K> d0(std::max<uint64_t>(n, 1)), d1(std::max<uint64_t>(n, 1), (K)0x77777777);
-  std::vector<uint64_t> bcnt(G, 0xDEADBEEFull), bstart(G, 0xFEEDFACEull);
+  std::vector<uint64_t> bcnt(std::max<uint32_t>(G, kRowBlocks), 0xDEADBEEFull);
+  std::vector<uint64_t> bstart(std::max<uint32_t>(G, kRowBlocks), 0xFEEDFACEull);
   std::vector<IterRec> rec(4);
   std::memset(rec.data(), 0, sizeof(IterRec) * 4);
   rec[0].F = A.size() + B.size();
@@ -41,10 +42,10 @@ int run(const std::vector<K>& C, const std::vector<K>& A, const std::vector<K>& 
   b.bcnt = bcnt.data();
   b.bstart = bstart.data();
   b.rec = rec.data();
-  simt::launch(G, kBlock, [&] { k_row_diff<K>(0, ctrl, &ctrl->cand_n, cand0.data(), cand1.data(), b, w, kIterDevice); },
-               workers);
-  simt::launch(G, kBlock, [&] { k_row_gather<K, kDedupItems>(ctrl, kModeIter, &ctrl->cand_n, cand1.data(), b, kIterDevice); },
-               workers);
+  // the row pass on its own grid (kRowBlocks, every total the gather adds up), the gather on G
+  simt::launch(kRowBlocks, kBlock,
+               [&] { k_row_diff<K>(0, ctrl, &ctrl->cand_n, cand0.data(), cand1.data(), b, w, kIterDevice); }, workers);
+  simt::launch(G, kBlock, [&] { k_row_gather<K>(0, ctrl, cand1.data(), b, kIterDevice); }, workers);
   std::vector<K> u(C);
   std::sort(u.begin(), u.end());
   u.erase(std::unique(u.begin(), u.end()), u.end());

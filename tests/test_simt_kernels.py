@@ -27,8 +27,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SIMT = os.path.join(ROOT, "tests", "simt")
 CSRC = os.path.join(ROOT, "paper_2607_17571_amd", "csrc")
-KERNELS = ["compact_span", "const:kRowWordsMax", "const:kRowTile", "nth_set_bit", "or_sorted_runs", "k_row_diff",
-           "compact_gather", "k_row_gather"]
+KERNELS = ["const:kRowWordsMax", "const:kRowItems", "const:kRowTile", "nth_set_bit", "or_sorted_runs", "k_row_diff",
+           "record_iteration", "k_row_gather"]
 
 pytestmark = pytest.mark.skipif(shutil.which("g++") is None or platform.machine() != "x86_64",
                                 reason="needs g++ on x86-64 (the shim switches fibers in x86-64 assembly)")
@@ -92,7 +92,7 @@ def test_row_gather_blocks_never_split(harness, tmp_path, empty_delta):
     assert r.stdout.count("ok ") == 20
 
 
-COMPACT = ["drop_present", "drop_present_sampled", "compact_span", "k_compact_local", "compact_gather",
+COMPACT = ["drop_present", "drop_present_sampled", "compact_span", "k_compact_local", "record_iteration", "compact_gather",
            "k_compact_gather"]
 
 
