@@ -1680,7 +1680,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_local(Ctrl* ctrl, int mode, 
 // streaming pass over its candidates and the rows of Full they touch.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kRowWordsMax = (1u << kRowBitsMax) / 32;
-constexpr int kRowItems = 8;                      // keys per thread per round
+constexpr int kRowItems = 4;                      // keys per thread per round
 constexpr uint32_t kRowTile = kBlock * kRowItems;  // keys streamed per round
 
 // Position of the k-th set bit (k = 0 the lowest) of v, which has more than k set bits.

@@ -41,10 +41,11 @@ constexpr uint64_t kRowMin = 1ull << 21;
 // some four times the candidates (measured on R-MAT 15: its fifth iteration, 27M candidates
 // against 44M tuples of Full, runs twice as fast on the rows).
 constexpr uint64_t kRowFullPerCand = 4;
-// Blocks of the row pass (twice the compaction's grid: rows are streamed with a barrier per
-// round, so more blocks in flight hide more latency; measured 1,024 -> 2,048 blocks:
-// 752 -> 486 us on R-MAT 15's largest iteration).  Its gather sums this many block totals.
-constexpr uint32_t kRowBlocks = 2048;
+// Blocks of the row pass (four times the compaction's grid: rows are streamed with a barrier
+// per round, so more and smaller blocks in flight hide more latency and even out the rows;
+// measured on R-MAT 15's largest iteration: 1,024 blocks 752 us, 2,048 451 us, 4,096 blocks
+// with half the keys per round 399 us).  Its gather sums this many block totals.
+constexpr uint32_t kRowBlocks = 4096;
 
 // Tile sizes (items per tile) of the static-range kernels.
 constexpr int kJoinItems = 8;
