@@ -610,7 +610,7 @@ def run_ablation(args):
             scale, m = TRIANGLE_GRAPHS[name]
             s_np, d_np = inputs.rmat(scale, m, *inputs.RMAT_ABCD, seed=scale)
             src, dst = torch.from_numpy(s_np).cuda(), torch.from_numpy(d_np).cuda()
-            variants = {"sorted": 0, "hash": wg.WG_JOIN_HASH}
+            variants = {"sorted": 0, "hash": wg.WG_JOIN_HASH, "hash_rows": wg.WG_JOIN_HASH_ROWS}
             row = {"graph": f"R-MAT scale {scale}, m={len(s_np)}, seed {scale}",
                    "max_out_degree": int(np.bincount(s_np).max())}
             for vname, fl in variants.items():
@@ -624,13 +624,15 @@ def run_ablation(args):
                 _progress(f"{name} {vname}: {row[vname]}")
             row["triangles_per_edge"] = round(row["sorted"]["triangles"] / max(1, len(s_np)), 2)
             row["hash_over_sorted"] = round(row["hash"]["ms"] / row["sorted"]["ms"], 3)
-            row["agree"] = row["sorted"]["triangles"] == row["hash"]["triangles"]
+            row["hash_rows_over_sorted"] = round(row["hash_rows"]["ms"] / row["sorted"]["ms"], 3)
+            row["agree"] = all(row[v]["triangles"] == row["sorted"]["triangles"] for v in variants)
             results[name] = row
             continue
         w = inputs.workload(name)
         src, dst = torch.from_numpy(w.src).cuda(), torch.from_numpy(w.dst).cuda()
         if args.ablation == "join":
-            variants = {"sorted": {}, "hash": dict(flags=wg.WG_JOIN_HASH)}
+            variants = {"sorted": {}, "hash": dict(flags=wg.WG_JOIN_HASH),
+                        "hash_rows": dict(flags=wg.WG_JOIN_HASH_ROWS)}
         elif args.ablation == "sync":
             ns = wg.WG_NO_SPECULATION
             variants = {

@@ -66,6 +66,12 @@ typedef enum { WG_QUERY_TC = 0, WG_QUERY_SG = 1, WG_QUERY_TRIANGLES = 2 } wg_que
 #define WG_UNFUSED_DEDUP 0x10u /* ablation of Section IV-B's fusion: deduplicate the sorted
                                   candidates in one compaction pass, then take the set
                                   difference with Full in a second (same result) */
+#define WG_JOIN_HASH_ROWS 0x100u /* TC and triangles: the sorted join with its row lookups
+                                   through a hash table of E's distinct rows (row -> index of
+                                   its contiguous edges) instead of the index; triangles probe
+                                   each closing edge in a hash set of E's pairs -- the fair hash
+                                   baseline: O(1) expected per lookup, the emit load-balanced as
+                                   the sorted join's (one thread per output, not per tuple) */
 #define WG_SPARSE_INDEX 0x20u /* index the edge rows by bisection over the distinct rows even
                                  where the row ids span a range small enough for the dense
                                  index (one array entry per row id) the engine would use */

@@ -90,6 +90,8 @@ struct wg_engine {
   uint64_t tri_count = 0;      // the latest triangle count
   DevBuf cand[2], full[2], fullB[2], delta[2], E, U, R, Edst, rowa, rowb, off, rec, htab;
   uint64_t hash_slots = 0;  // hash-join variant: table slots of the current solve (0: off)
+  uint32_t hrows_mask = 0;  // fair hash variant: row-table slots - 1 (0: off)
+  uint32_t hpairs_mask = 0; // ... and pair-set slots - 1 (triangles; 0: none)
   uint64_t dense_rows = 0;  // rows of the dense edge index of the current solve (0: U + search)
   // how the loop's iterations join and sort: 0 the LSD passes; 1 the one-block sort,
   // then the passes (no-ops when it fit); 2 the one-block sort alone; 3 the join and the
@@ -348,6 +350,8 @@ Bufs<K> make_bufs(wg_engine* e) {
   b.rtot = e->d_rtot;
   b.hits = e->d_hits;
   b.htab = (uint64_t*)e->htab.p;
+  b.hrows = e->hrows_mask;
+  b.hpairs = e->hpairs_mask;
   b.rec = (IterRec*)e->rec.p;
   b.dense = (uint32_t)e->dense_rows;
   return b;
@@ -412,7 +416,7 @@ void stage_probe(wg_engine* e, const uint64_t* d_size) {
 
 // How the next enqueued iteration sorts its candidates (see iter_sort).
 uint8_t sort_method(const wg_engine* e, int kind) {
-  if (e->small_mode == 3 && !e->hash_slots && !e->stage_sync) return kSortOneBlock;
+  if (e->small_mode == 3 && !e->hash_slots && !e->hrows_mask && !e->stage_sync) return kSortOneBlock;
   if (e->small_mode == 2) return kSortSmall;
   if (e->row_bitmap && kind == kJoinTC && !e->hash_slots) return e->seg_sort ? kSortDual : kSortDualLsd;
   if (e->seg_sort && kind == kJoinTC && !e->hash_slots) return kSortSegmented;
@@ -703,6 +707,9 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   launch_ctrl_set(e->stream, e->d_ctrl, c0);
 
   // ---- prepare: sort + dedup E, edge index, seed (Section IV-A: E sorted once)
+  // (the join variants of an earlier solve are cleared before the buffers are described)
+  e->hash_slots = 0;
+  e->hrows_mask = e->hpairs_mask = 0;
   Bufs<K> b = make_bufs<K>(e);
   if (e->num_inst)
     launch_pack_batch<K>(e->stream, e->grid, src, dst, m, w, e->d_offsets, e->num_inst, b.cand[0],
@@ -715,7 +722,6 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   launch_compact<K>(e->stream, e->grid, mode, e->d_ctrl, &e->d_ctrl->m_in, b.cand[passes & 1],
                     b.cand[(passes & 1) ^ 1], b, w, 0, 0, stage(e, WG_STAGE_DEDUP_DIFF));
   launch_edge_index<K>(e->stream, e->grid, e->d_ctrl, b, w, stage(e, WG_STAGE_PREPARE));
-  e->hash_slots = 0;
   e->unfused = (o.flags & WG_UNFUSED_DEDUP) != 0;
   e->stage_sync = false;
   if (o.flags & WG_JOIN_HASH) {
@@ -727,6 +733,19 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
     e->hash_slots = slots;
     b = make_bufs<K>(e);
     launch_hash_build<K>(e->stream, e->grid, e->d_ctrl, b, w, slots, stage(e, WG_STAGE_PREPARE));
+  }
+  if (o.flags & WG_JOIN_HASH_ROWS) {
+    // fair hash variant: a table of E's distinct rows (row -> index of its edges) and, for
+    // triangles, a set of E's pairs, each with at least twice as many slots as edges
+    uint64_t slots = 1024;
+    while (slots < 2 * m) slots <<= 1;
+    if (slots > (1ull << 31)) fail(e, WG_ERR_CAPACITY, "hash table beyond 2^31 slots");
+    const uint64_t pairs = query == WG_QUERY_TRIANGLES ? slots : 0;
+    ensure(e, e->htab, (slots + pairs) * sizeof(uint64_t));
+    e->hrows_mask = (uint32_t)(slots - 1);
+    e->hpairs_mask = pairs ? (uint32_t)(pairs - 1) : 0u;
+    b = make_bufs<K>(e);
+    launch_hash_rows<K>(e->stream, e->grid, e->d_ctrl, b, stage(e, WG_STAGE_PREPARE));
   }
 
   if (query == WG_QUERY_TRIANGLES) {
@@ -1056,13 +1075,17 @@ wg_status solve(wg_engine* e, int query, uint32_t num, const uint64_t* d_offsets
     e->err = "tile_items must be 0, 8, 12 or 16";
     return WG_ERR_INVALID_ARG;
   }
-  if ((o.flags & WG_JOIN_HASH) && query == WG_QUERY_SG) {
-    e->err = "WG_JOIN_HASH applies to TC and triangle counting";
+  if ((o.flags & (WG_JOIN_HASH | WG_JOIN_HASH_ROWS)) && query == WG_QUERY_SG) {
+    e->err = "WG_JOIN_HASH and WG_JOIN_HASH_ROWS apply to TC and triangle counting";
+    return WG_ERR_INVALID_ARG;
+  }
+  if ((o.flags & WG_JOIN_HASH) && (o.flags & WG_JOIN_HASH_ROWS)) {
+    e->err = "WG_JOIN_HASH and WG_JOIN_HASH_ROWS exclude each other";
     return WG_ERR_INVALID_ARG;
   }
   if (o.loop_mode > WG_LOOP_STAGE ||
       (o.flags & ~(WG_SG_IRREFLEXIVE | WG_STAGE_TIMING | WG_NO_SPECULATION | WG_JOIN_HASH | WG_UNFUSED_DEDUP |
-                   WG_SPARSE_INDEX | WG_ITER_GRAPH | WG_LSD_SORT))) {
+                   WG_SPARSE_INDEX | WG_ITER_GRAPH | WG_LSD_SORT | WG_JOIN_HASH_ROWS))) {
     e->err = "unknown loop_mode or flag";
     return WG_ERR_INVALID_ARG;
   }
@@ -1130,7 +1153,9 @@ wg_status solve(wg_engine* e, int query, uint32_t num, const uint64_t* d_offsets
       // graph, the edge index is a dense array over that range (two loads per lookup);
       // otherwise a sorted array of the distinct rows searched by bisection.
       const uint64_t space = (num > 1 ? ((uint64_t)(num - 1) << w) : 0) + e->h_rb[0].c.maxid + 1;
-      e->dense_rows = (!(o.flags & WG_SPARSE_INDEX) && space <= kDenseRowsMax && space <= 16 * m + (1u << 20))
+      // (the fair hash variant looks rows up through its table: it keeps the rows' list)
+      e->dense_rows = (!(o.flags & (WG_SPARSE_INDEX | WG_JOIN_HASH_ROWS)) && space <= kDenseRowsMax &&
+                       space <= 16 * m + (1u << 20))
                           ? space
                           : 0;
       wg_status r = (ib + 2 * w <= 32) ? run<uint32_t>(e, query, d_src, d_dst, m, o, w, ib, st)

@@ -99,7 +99,73 @@ __device__ __forceinline__ bool row_found(const uint32_t* __restrict__ U, uint64
   return j < nu && U[j] == v;
 }
 
-template <typename K, int Q, int ITEMS>
+// ---------------------------------------------------------------------------
+// Fair hash variant of the join (WG_JOIN_HASH_ROWS): the sorted join's structure with its row
+// lookups through hash tables instead of the index.  The row table maps each distinct row
+// of E to its index among the rows (its edges are contiguous in E: R[index] .. R[index+1]),
+// so a lookup is one expected probe, and the emit stays load-balanced over the outputs; the
+// pair set holds every key of E, for triangle counting's closing-edge test.  Open
+// addressing, linear probing, load at most 1/2; a slot holds (row << 32 | index), or a key,
+// and kHashVacant never equals either (indices stay below 2^32 - 16, keys below 2^63).
+// ---------------------------------------------------------------------------
+constexpr uint64_t kHashVacant = ~0ull;
+
+__device__ __forceinline__ uint32_t mix_slot(uint64_t x, uint32_t mask) {
+  x ^= x >> 33;
+  x *= 0xFF51AFD7ED558CCDull;
+  x ^= x >> 33;
+  x *= 0xC4CEB9FE1A85EC53ull;
+  x ^= x >> 33;
+  return (uint32_t)x & mask;
+}
+
+// Index of `row` among E's distinct rows, or kNoRow.
+__device__ __forceinline__ uint32_t hash_row_find(const uint64_t* __restrict__ t, uint32_t mask, uint32_t row) {
+  for (uint32_t slot = mix_slot(row, mask);; slot = (slot + 1) & mask) {
+    const uint64_t e = t[slot];
+    if (e == kHashVacant) return 0xFFFFFFFFu;
+    if ((uint32_t)(e >> 32) == row) return (uint32_t)e;
+  }
+}
+
+// Whether `key` is in the pair set.
+__device__ __forceinline__ bool hash_pair_has(const uint64_t* __restrict__ t, uint32_t mask, uint64_t key) {
+  for (uint32_t slot = mix_slot(key, mask);; slot = (slot + 1) & mask) {
+    const uint64_t e = t[slot];
+    if (e == kHashVacant) return false;
+    if (e == key) return true;
+  }
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_hash_rows_build(Ctrl* ctrl, Bufs<K> b) {
+  if (block_stop(halted(ctrl))) return;
+  const uint64_t nu = ctrl->nu;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < nu; i += (uint64_t)gridDim.x * kBlock) {
+    const uint32_t row = b.U[i];
+    const uint64_t entry = ((uint64_t)row << 32) | i;
+    uint32_t slot = mix_slot(row, b.hrows);
+    while (atomicCAS((unsigned long long*)&b.htab[slot], (unsigned long long)kHashVacant,
+                     (unsigned long long)entry) != (unsigned long long)kHashVacant)
+      slot = (slot + 1) & b.hrows;
+  }
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_hash_pairs_build(Ctrl* ctrl, Bufs<K> b) {
+  if (block_stop(halted(ctrl))) return;
+  const uint64_t mu = ctrl->m_unique;
+  uint64_t* __restrict__ t = b.htab + (uint64_t)b.hrows + 1;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < mu; i += (uint64_t)gridDim.x * kBlock) {
+    const uint64_t key = (uint64_t)b.E[i];
+    uint32_t slot = mix_slot(key, b.hpairs);
+    while (atomicCAS((unsigned long long*)&t[slot], (unsigned long long)kHashVacant, (unsigned long long)key) !=
+           (unsigned long long)kHashVacant)
+      slot = (slot + 1) & b.hpairs;
+  }
+}
+
+template <typename K, int Q, int ITEMS, bool HR = false>
 __global__ __launch_bounds__(kBlock) void k_join_count(Ctrl* ctrl, Bufs<K> b, int w, uint32_t j) {
   constexpr uint32_t T = kBlock * ITEMS;
   __shared__ uint64_t s_wave[kWavesPerBlock];
@@ -138,8 +204,13 @@ __global__ __launch_bounds__(kBlock) void k_join_count(Ctrl* ctrl, Bufs<K> b, in
       }
       uint64_t jb[ITEMS], ja[ITEMS];
       if (!dense) {
-        multi_lower_bound<uint32_t, ITEMS>(U, nu, vb, jb);
-        if (Q == kJoinSG) multi_lower_bound<uint32_t, ITEMS>(U, nu, va, ja);
+        if constexpr (HR) {
+#pragma unroll
+          for (int k = 0; k < ITEMS; ++k) jb[k] = hash_row_find(b.htab, b.hrows, vb[k]);
+        } else {
+          multi_lower_bound<uint32_t, ITEMS>(U, nu, vb, jb);
+          if (Q == kJoinSG) multi_lower_bound<uint32_t, ITEMS>(U, nu, va, ja);
+        }
       }
 #pragma unroll
       for (int k = 0; k < ITEMS; ++k) {
@@ -147,7 +218,9 @@ __global__ __launch_bounds__(kBlock) void k_join_count(Ctrl* ctrl, Bufs<K> b, in
         uint64_t c = 0;
         if (i < hi) {
           // dense index: the row id is the vertex id itself (every id below b.dense)
-          const uint32_t rb = dense ? vb[k] : (row_found(U, nu, jb[k], vb[k]) ? (uint32_t)jb[k] : kNoRow);
+          const uint32_t rb = dense ? vb[k]
+                                    : (HR ? (uint32_t)jb[k]
+                                          : (row_found(U, nu, jb[k], vb[k]) ? (uint32_t)jb[k] : kNoRow));
           if (!dense) b.rowb[i] = rb;
           if (Q == kJoinTC) {
             c = (rb == kNoRow) ? 0 : (uint64_t)(R[rb + 1] - R[rb]);
@@ -195,7 +268,7 @@ __global__ __launch_bounds__(kBlock) void k_join_count(Ctrl* ctrl, Bufs<K> b, in
 // load-balanced expansion: a hub tuple with thousands of matches is spread over many
 // threads instead of serialising one), and reads one edge.  Writes are coalesced.
 // ---------------------------------------------------------------------------
-template <typename K, int Q, int ITEMS>
+template <typename K, int Q, int ITEMS, bool HR = false>
 __global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int w, uint32_t j,
                                                       int gc) {
   constexpr uint32_t T = kBlock * ITEMS;
@@ -246,6 +319,9 @@ __global__ __launch_bounds__(kBlock) void k_join_emit(Ctrl* ctrl, Bufs<K> b, int
   auto closes = [&](K dk, K c) -> bool {
     const K a = (dk >> w) & mask;
     const K inst = (dk >> w) >> w;
+    if constexpr (HR) {
+      return hash_pair_has(b.htab + (uint64_t)b.hrows + 1, b.hpairs, (uint64_t)((((inst << w) | c) << w) | a));
+    }
     if (dense) {
       const uint32_t rc = (uint32_t)((inst << w) | c);
       uint32_t lo = R[rc];
@@ -2496,7 +2572,9 @@ void launch_pack(hipStream_t s, const Grid& g, const uint32_t* src, const uint32
 template <typename K>
 void launch_join_count(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w,
                        uint32_t j, Ev ev) {
-  if (kind == kJoinTC)
+  if ((kind == kJoinTC || kind == kJoinTri) && b.hrows)
+    WG_LAUNCH((k_join_count<K, kJoinTC, kJoinItems, true>), g.scan, ev.start, ev.stop, s, ctrl, b, w, j);
+  else if (kind == kJoinTC)
     WG_LAUNCH((k_join_count<K, kJoinTC, kJoinItems>), g.scan, ev.start, ev.stop, s, ctrl, b, w, j);
   else if (kind == kJoinSG)
     WG_LAUNCH((k_join_count<K, kJoinSG, kJoinItems>), g.scan, ev.start, ev.stop, s, ctrl, b, w, j);
@@ -2504,6 +2582,15 @@ void launch_join_count(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const
     WG_LAUNCH((k_join_count<K, kJoinTC, kJoinItems>), g.scan, ev.start, ev.stop, s, ctrl, b, w, j);
   else
     WG_LAUNCH((k_join_count<K, kJoinSGBase, kJoinItems>), g.scan, ev.start, ev.stop, s, ctrl, b, w, j);
+}
+
+template <typename K>
+void launch_hash_rows(hipStream_t s, const Grid& g, Ctrl* ctrl, const Bufs<K>& b, Ev ev) {
+  const uint64_t slots = (uint64_t)b.hrows + 1 + (b.hpairs ? (uint64_t)b.hpairs + 1 : 0);
+  const hipEvent_t none = nullptr;
+  WG_LAUNCH(k_fill_u64, g.stream, ev.start, none, s, b.htab, slots, kHashVacant);
+  WG_LAUNCH((k_hash_rows_build<K>), g.stream, none, b.hpairs ? none : ev.stop, s, ctrl, b);
+  if (b.hpairs) WG_LAUNCH((k_hash_pairs_build<K>), g.stream, none, ev.stop, s, ctrl, b);
 }
 
 template <typename K>
@@ -2535,6 +2622,8 @@ void join_emit_impl(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bu
     WG_LAUNCH((k_join_emit<K, kJoinTC, ITEMS>), g.stream, ev.start, ev.stop, s, ctrl, b, w, j, g.scan);
   else if (kind == kJoinSG)
     WG_LAUNCH((k_join_emit<K, kJoinSG, ITEMS>), g.stream, ev.start, ev.stop, s, ctrl, b, w, j, g.scan);
+  else if (kind == kJoinTri && b.hpairs)
+    WG_LAUNCH((k_join_emit<K, kJoinTri, ITEMS, true>), g.stream, ev.start, ev.stop, s, ctrl, b, w, j, g.scan);
   else if (kind == kJoinTri)
     WG_LAUNCH((k_join_emit<K, kJoinTri, ITEMS>), g.stream, ev.start, ev.stop, s, ctrl, b, w, j, g.scan);
   else
@@ -2733,6 +2822,7 @@ void launch_resume(hipStream_t s, Ctrl* ctrl, uint64_t cand_cap, uint64_t full_c
   template void launch_row_gather<K>(hipStream_t, const Grid&, Ctrl*, const uint64_t*, const Bufs<K>&,  \
                                      uint32_t, Ev, int);                                           \
   template void launch_hash_build<K>(hipStream_t, const Grid&, Ctrl*, const Bufs<K>&, int, uint64_t, Ev); \
+  template void launch_hash_rows<K>(hipStream_t, const Grid&, Ctrl*, const Bufs<K>&, Ev);             \
   template void launch_join_hash<K>(hipStream_t, const Grid&, int, Ctrl*, const Bufs<K>&, int, uint32_t, \
                                     uint64_t, Ev, Ev);                                             \
   template void launch_merge_pair<K>(hipStream_t, const Grid&, const K*, uint64_t, const K*,     \

@@ -117,6 +117,8 @@ struct Bufs {
   IterRec* rec;    // per-iteration sizes
   uint32_t dense;  // > 0: R is a dense index over the row ids [0, dense) (R[v] = first edge
                    // of row v, R[dense] = |E|) and U is unused; 0: rows are U's entries
+  uint32_t hrows;  // fair hash variant: row table htab[0, hrows] (slots - 1), 0 = off
+  uint32_t hpairs; // ... and E's pair set htab[hrows + 1, hrows + 1 + hpairs], 0 = none
 };
 
 void launch_max_id(hipStream_t s, const Grid& g, Ctrl* ctrl, const uint32_t* src,
@@ -152,6 +154,9 @@ void launch_join_emit(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const 
 template <typename K>
 void launch_hash_build(hipStream_t s, const Grid& g, Ctrl* ctrl, const Bufs<K>& b, int w, uint64_t slots,
                        Ev ev = Ev());
+// Fair hash variant: fill and build the row table (and the pair set when b.hpairs) of b.htab.
+template <typename K>
+void launch_hash_rows(hipStream_t s, const Grid& g, Ctrl* ctrl, const Bufs<K>& b, Ev ev = Ev());
 template <typename K>
 void launch_join_hash(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w,
                       uint32_t j, uint64_t slots, Ev ev_count = Ev(), Ev ev_emit = Ev());

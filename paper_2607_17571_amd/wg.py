@@ -30,6 +30,7 @@ WG_SG_IRREFLEXIVE = 0x1
 WG_STAGE_TIMING = 0x2
 WG_NO_SPECULATION = 0x4
 WG_JOIN_HASH = 0x8
+WG_JOIN_HASH_ROWS = 0x100
 WG_UNFUSED_DEDUP = 0x10
 WG_SPARSE_INDEX = 0x20
 WG_ITER_GRAPH = 0x40

@@ -250,6 +250,7 @@ def test_sg_irreflexive(engine):
     dict(flags=wg.WG_ITER_GRAPH), dict(flags=wg.WG_ITER_GRAPH | wg.WG_NO_SPECULATION, batch_k=5),
     dict(flags=wg.WG_UNFUSED_DEDUP, force_overflow_at_iter=2),
     dict(flags=wg.WG_UNFUSED_DEDUP | wg.WG_JOIN_HASH, loop_mode=wg.WG_LOOP_STAGE),
+    dict(flags=wg.WG_JOIN_HASH_ROWS | wg.WG_ITER_GRAPH), dict(flags=wg.WG_JOIN_HASH_ROWS, loop_mode=wg.WG_LOOP_HOST),
 ])
 def test_result_independent_of_loop_policy(engine, opts):
     src, dst = inputs.rmat(11, 1800, *inputs.RMAT_ABCD, seed=9)
@@ -391,6 +392,31 @@ def test_hash_join_variant_tc(engine, make):
 
 def test_hash_join_variant_full_size(engine):
     _check_golden(engine, "tc_rmat_s15", wg.make_options(flags=wg.WG_JOIN_HASH))
+
+
+@pytest.mark.parametrize("make", [
+    lambda: inputs.rmat(11, 1800, *inputs.RMAT_ABCD, seed=9), lambda: inputs.chain(300),
+    lambda: inputs.cycle(40), lambda: inputs.out_star(500),
+    lambda: inputs.scatter_ids(*inputs.rmat(10, 900, *inputs.RMAT_ABCD, seed=4), 30, seed=5),
+])
+def test_fair_hash_join_variant_tc(engine, make):
+    """The fair hash baseline (hashed row lookups, load-balanced emit) gives the same fixpoint,
+    every iteration's delta included."""
+    src, dst = make()
+    s, d, st = run(engine, "tc", src, dst, wg.make_options(flags=wg.WG_JOIN_HASH_ROWS))
+    assert_same(s, d, st, oracle.tc(src, dst))
+
+
+def test_fair_hash_join_variant_full_size(engine):
+    _check_golden(engine, "tc_rmat_s15", wg.make_options(flags=wg.WG_JOIN_HASH_ROWS))
+
+
+@pytest.mark.parametrize("flags", [wg.WG_JOIN_HASH_ROWS, wg.WG_JOIN_HASH | wg.WG_JOIN_HASH_ROWS])
+def test_fair_hash_join_rejected_for_sg_and_with_the_other_hash(engine, flags):
+    a, b = inputs.chain(6)
+    with pytest.raises(wg.WgError) as ei:
+        run(engine, "sg" if flags == wg.WG_JOIN_HASH_ROWS else "tc", a, b, wg.make_options(flags=flags))
+    assert ei.value.status == wg.WG_ERR_INVALID_ARG
 
 
 def test_hash_join_rejected_for_sg(engine):

@@ -13,7 +13,7 @@ import pytest
 import oracle
 from paper_2607_17571_amd import inputs
 from paper_2607_17571_amd import wg
-from tests.gpu_util import to_gpu
+from tests.gpu_util import assert_same, run, to_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -76,6 +76,40 @@ def test_hash_join_variant(engine, scale, m):
     count, st = gpu_triangles(engine, src, dst, wg.make_options(flags=wg.WG_JOIN_HASH))
     ref, two = oracle.triangles(src, dst)
     assert count == ref and st["join_candidates"] == two
+
+
+@pytest.mark.parametrize("scale,m", [(10, 4000), (13, 40000)])
+def test_fair_hash_join_variant(engine, scale, m):
+    """Hashed row lookups and a pair set for the closing edges: the same counts."""
+    src, dst = inputs.rmat(scale, m, *inputs.RMAT_ABCD, seed=scale)
+    count, st = gpu_triangles(engine, src, dst, wg.make_options(flags=wg.WG_JOIN_HASH_ROWS))
+    ref, two = oracle.triangles(src, dst)
+    assert count == ref and st["join_candidates"] == two
+
+
+def test_fair_hash_join_self_loops_and_wide_ids(engine):
+    src, dst = inputs.scatter_ids(*inputs.rmat(10, 3000, *inputs.RMAT_ABCD, seed=3), 30, seed=6)
+    src = np.concatenate([src, src[:50]])
+    dst = np.concatenate([dst, src[:50]])  # self-loops
+    count, st = gpu_triangles(engine, src, dst, wg.make_options(flags=wg.WG_JOIN_HASH_ROWS))
+    ref, two = oracle.triangles(src, dst)
+    assert count == ref and st["join_candidates"] == two
+
+
+def test_variant_does_not_leak_into_the_next_solve(engine):
+    """A solve without a join flag after one with the fair hash (and the other way round)
+    probes the index it built itself, not the previous solve's table."""
+    src, dst = inputs.rmat(10, 4000, *inputs.RMAT_ABCD, seed=11)
+    ref, two = oracle.triangles(src, dst)
+    for flags in (wg.WG_JOIN_HASH_ROWS, wg.WG_SPARSE_INDEX, wg.WG_JOIN_HASH_ROWS, 0, wg.WG_JOIN_HASH,
+                  wg.WG_JOIN_HASH_ROWS, 0):
+        count, st = gpu_triangles(engine, src, dst, wg.make_options(flags=flags))
+        assert (count, st["join_candidates"]) == (ref, two), flags
+    a, b = inputs.rmat(11, 1800, *inputs.RMAT_ABCD, seed=9)
+    want = oracle.tc(a, b)
+    for flags in (wg.WG_JOIN_HASH_ROWS, 0, wg.WG_JOIN_HASH_ROWS | wg.WG_ITER_GRAPH, wg.WG_ITER_GRAPH):
+        s, d, st = run(engine, "tc", a, b, wg.make_options(flags=flags))
+        assert_same(s, d, st, want)
 
 
 @pytest.mark.parametrize("scale,m", [(10, 4000), (12, 20000)])
