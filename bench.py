@@ -644,6 +644,7 @@ def run_ablation(args):
                 "paper_adaptive_speculative": dict(loop_mode=wg.WG_LOOP_BATCHED),
                 "default": {},
                 "default_graph_replay": dict(flags=wg.WG_ITER_GRAPH),
+                "device_tail_loop": dict(loop_mode=wg.WG_LOOP_DEVICE),
             }
             if w.query == "tc":
                 for k in (2, 5, 20, 40, 50):
@@ -677,7 +678,8 @@ def run_ablation(args):
             elif st["result_tuples"] != tuples:
                 raise SystemExit(f"{name} {vname}: {st['result_tuples']} tuples, expected {tuples}")
             row[vname] = {"ms_per_step": round(ms, 3), "host_syncs": st["host_syncs"],
-                          "iterations": st["iterations"], "sort_passes": st["sort_passes"],
+                          "iterations": st["iterations"], "tail_iterations": st["tail_iterations"],
+                          "sort_passes": st["sort_passes"],
                           "stage_ms": {k: round(v, 3) for k, v in pr["stage_ms"].items()}}
             _progress(f"{name} {vname}: {ms:.3f} ms, {st['host_syncs']} host syncs")
         row["fixpoint_tuples"] = tuples

@@ -98,6 +98,15 @@ typedef enum { WG_QUERY_TC = 0, WG_QUERY_SG = 1, WG_QUERY_TRIANGLES = 2 } wg_que
                                size after the compaction, as a loop that sizes each stage
                                from the host would do (three host round trips per
                                iteration; the kernels still size themselves on the device) */
+#define WG_LOOP_DEVICE 4u   /* WG_LOOP_AUTO, and once the delta (at most 1,024 tuples) and an
+                               iteration's candidates fit one block, one launch runs the
+                               fixpoint's tail: a single workgroup loops over whole
+                               iterations (join, sort, dedup + difference, merge) until the
+                               fixpoint, the iteration limit or an iteration that outgrows
+                               it, which goes back to the multi-block launches (Section V-B's
+                               device-resident loop carried into one launch).  TC and SG;
+                               not with WG_JOIN_HASH, WG_JOIN_HASH_ROWS or WG_UNFUSED_DEDUP
+                               (which keep WG_LOOP_AUTO's launches) */
 
 typedef struct {
   uint32_t struct_size;      /* sizeof(wg_options); older sizes are accepted */
@@ -138,7 +147,9 @@ enum {
                               join's row-grouped candidates in one LDS bitmap (Sections IV-B,
                               V-C), which replaces the sort and the compaction of a large
                               iteration */
-  WG_NUM_STAGES = 9
+  WG_STAGE_TAIL_LOOP = 9,  /* WG_LOOP_DEVICE: the one-block launch that runs the fixpoint's tail
+                              (its fold into run B is timed as WG_STAGE_MERGE) */
+  WG_NUM_STAGES = 10
 };
 
 typedef struct {
@@ -158,6 +169,7 @@ typedef struct {
   uint64_t delta_sizes_cap; /* its capacity in entries (filled up to the capacity) */
   uint32_t digit_bits;      /* radix digit bits per LSD pass used */
   uint32_t sort_passes;     /* LSD passes per sort: ceil(key bits / digit_bits) */
+  uint64_t tail_iterations; /* WG_LOOP_DEVICE: iterations run inside tail-loop launches */
 } wg_stats;
 
 typedef struct wg_engine wg_engine; /* per device: buffers, control block, sort tuning table */

@@ -40,7 +40,8 @@ struct IterRec {
   uint32_t a;   // buffer side of A after iteration j
   uint32_t b;   // buffer side of B after iteration j
   uint32_t fold;  // iteration j folded B into A (and its delta became B)
-  uint32_t pad;
+  uint32_t tail;  // 1: run by the one-block tail loop; 2: the last of such a launch, whose
+                  // new tuples the fold after it merged into B
 };
 
 constexpr uint32_t kFoldRatio = 8;  // fold B into A once |B| > |A| / kFoldRatio
@@ -69,7 +70,15 @@ struct Ctrl {
                                // passes of that sort are no-ops
   uint32_t seg_long;           // rows the segmented sort in flight left to its long-row pass
   uint64_t full_n;             // |Full| after the last merged iteration (the seed: |Delta^0|)
+  uint64_t tail_n;             // tail loop: size of its run T (0: nothing for the fold)
+  uint32_t tail_b;             // ... B's side before the fold (the fold writes the other)
+  uint32_t tail_exit;          // ... why it stopped (kTail*)
 };
+
+// Why a tail loop stopped: the fixpoint or the iteration limit; the next iteration does
+// not fit one block (or the buffers, or is the overflow hook's); run T is full; the
+// records the host allotted are used up.
+enum : uint32_t { kTailFixpoint = 0, kTailSizes = 1, kTailRun = 2, kTailRecords = 3 };
 
 // Kernels of the loop take their iteration from the device, so that one iteration's
 // launches are the same for every iteration (and can be recorded once as a graph): the
@@ -330,10 +339,12 @@ __device__ __forceinline__ uint64_t wave_upper_bound(const T* a, uint64_t n, T v
 }
 
 // Branchless lower bounds of ITEMS keys at once over the same sorted array: every
-// probe step issues ITEMS independent loads, so their latencies overlap.
+// probe step issues ITEMS independent loads, so their latencies overlap.  Only the first
+// `nk` keys are searched (a count the whole block agrees on; the others get 0).
 template <typename T, int ITEMS>
 __device__ __forceinline__ void multi_lower_bound(const T* __restrict__ a, uint64_t n,
-                                                  const T (&v)[ITEMS], uint64_t (&out)[ITEMS]) {
+                                                  const T (&v)[ITEMS], uint64_t (&out)[ITEMS],
+                                                  int nk = ITEMS) {
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) out[k] = 0;
   if (n == 0) return;
@@ -341,16 +352,19 @@ __device__ __forceinline__ void multi_lower_bound(const T* __restrict__ a, uint6
   while (len > 1) {
     const uint64_t half = len >> 1;
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) out[k] = (a[out[k] + half - 1] < v[k]) ? out[k] + half : out[k];
+    for (int k = 0; k < ITEMS; ++k)
+      if (k < nk) out[k] = (a[out[k] + half - 1] < v[k]) ? out[k] + half : out[k];
     len -= half;
   }
 #pragma unroll
-  for (int k = 0; k < ITEMS; ++k) out[k] += (a[out[k]] < v[k]) ? 1 : 0;
+  for (int k = 0; k < ITEMS; ++k)
+    if (k < nk) out[k] += (a[out[k]] < v[k]) ? 1 : 0;
 }
 
 template <typename T, int ITEMS>
 __device__ __forceinline__ void multi_upper_bound(const T* __restrict__ a, uint64_t n,
-                                                  const T (&v)[ITEMS], uint64_t (&out)[ITEMS]) {
+                                                  const T (&v)[ITEMS], uint64_t (&out)[ITEMS],
+                                                  int nk = ITEMS) {
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) out[k] = 0;
   if (n == 0) return;
@@ -358,11 +372,13 @@ __device__ __forceinline__ void multi_upper_bound(const T* __restrict__ a, uint6
   while (len > 1) {
     const uint64_t half = len >> 1;
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) out[k] = (a[out[k] + half - 1] <= v[k]) ? out[k] + half : out[k];
+    for (int k = 0; k < ITEMS; ++k)
+      if (k < nk) out[k] = (a[out[k] + half - 1] <= v[k]) ? out[k] + half : out[k];
     len -= half;
   }
 #pragma unroll
-  for (int k = 0; k < ITEMS; ++k) out[k] += (a[out[k]] <= v[k]) ? 1 : 0;
+  for (int k = 0; k < ITEMS; ++k)
+    if (k < nk) out[k] += (a[out[k]] <= v[k]) ? 1 : 0;
 }
 
 // multi_upper_bound over a virtual sorted array given by an accessor at(i).

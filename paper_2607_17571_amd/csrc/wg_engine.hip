@@ -40,6 +40,7 @@ constexpr uint64_t kMaxKeys = 0xFFFFFFF0ull;  // slab offsets are 32-bit
 constexpr uint32_t kMaxEvents = 1u << 16;
 constexpr uint32_t kSpec = 4;                 // speculative iterations behind each batch (<= K)
 constexpr uint32_t kAutoK = 2;                // iterations per host check of the default loop
+constexpr uint32_t kTailIters = 512;          // iterations one tail launch may run at most
 constexpr uint64_t kNarrowBelow = 1ull << 21;  // candidates below which the narrow tiles win
 constexpr uint64_t kSegBelow = 1ull << 22;     // ... and the segmented sort beats the LSD passes
 // kSortDual / kSortDualLsd: both routes, the row pass or the segmented sort / the LSD passes
@@ -88,7 +89,7 @@ struct wg_engine {
   uint32_t* d_rtot = nullptr;
   uint64_t* d_hits = nullptr;  // triangle probe: hits per emit block (grid.stream entries)
   uint64_t tri_count = 0;      // the latest triangle count
-  DevBuf cand[2], full[2], fullB[2], delta[2], E, U, R, Edst, rowa, rowb, off, rec, htab;
+  DevBuf cand[2], full[2], fullB[2], delta[2], E, U, R, Edst, rowa, rowb, off, rec, htab, tailrun;
   uint64_t hash_slots = 0;  // hash-join variant: table slots of the current solve (0: off)
   uint32_t hrows_mask = 0;  // fair hash variant: row-table slots - 1 (0: off)
   uint32_t hpairs_mask = 0; // ... and pair-set slots - 1 (triangles; 0: none)
@@ -284,6 +285,7 @@ void size_buffers(wg_engine* e, bool keep, uint32_t iter, const IterRec* last) {
   ensure(e, e->rowa, e->row_cap * 4);
   ensure(e, e->rowb, e->row_cap * 4);
   ensure(e, e->off, e->row_cap * 4);
+  ensure(e, e->tailrun, kTailRunBytes);
 }
 
 // Free every relation buffer (the engine stays usable; the next solve starts small).
@@ -295,7 +297,7 @@ void release_relations(wg_engine* e) {
     free_buf(e, e->fullB[s]);
     free_buf(e, e->delta[s]);
   }
-  for (DevBuf* b : {&e->E, &e->U, &e->R, &e->Edst, &e->rowa, &e->rowb, &e->off, &e->rec, &e->htab})
+  for (DevBuf* b : {&e->E, &e->U, &e->R, &e->Edst, &e->rowa, &e->rowb, &e->off, &e->rec, &e->htab, &e->tailrun})
     free_buf(e, *b);
   e->cand_cap = e->full_cap = e->edge_cap = e->row_cap = e->rec_cap = 0;
 }
@@ -353,6 +355,7 @@ Bufs<K> make_bufs(wg_engine* e) {
   b.hrows = e->hrows_mask;
   b.hpairs = e->hpairs_mask;
   b.rec = (IterRec*)e->rec.p;
+  b.tail = (K*)e->tailrun.p;
   b.dense = (uint32_t)e->dense_rows;
   return b;
 }
@@ -642,6 +645,14 @@ void bytes_model(wg_stats* st, int query, uint32_t kb, int passes, uint64_t m,
   for (size_t i = 1; i < rec.size(); ++i) {
     const double D = (double)rec[i - 1].N, c = (double)rec[i].C, n = (double)rec[i].N;
     const double F = (double)rec[i - 1].F;
+    if (rec[i].tail) {
+      // the tail loop: the edges the join reads and the delta it writes (the first delta
+      // comes from HBM, the later ones stay in LDS; the probes of A and B are search
+      // lines, not counted); the fold after the launch reads B and T and writes B + T
+      add_bytes(st, WG_STAGE_TAIL_LOOP, c * edst + n * kb);
+      if (rec[i].tail == 2) add_bytes(st, WG_STAGE_MERGE, 2.0 * (double)(rec[i].F - rec[i].FA) * kb);
+      continue;
+    }
     uint8_t sorted_by = i < how.size() ? how[i] : kSortLsd;
     // an iteration enqueued with both routes: the device took the rows when the join found
     // at least kRowMin candidates and Full had at most kRowFullPerCand tuples per candidate
@@ -789,6 +800,7 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
     return WG_OK;
   }
 
+  uint64_t seed_n = m;  // |Delta^0| (TC: at most m; SG: read back below)
   if (query == WG_QUERY_SG) {
     // base rule: Delta^0 = Full = {(x, y) : E(p, x), E(p, y), x != y}, sorted + deduplicated
     for (;;) {
@@ -800,6 +812,7 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
                         b.cand[(passes & 1) ^ 1], b, w, 0, 0, stage(e, WG_STAGE_DEDUP_DIFF));
       read_back(e, 0, 0, 0);
       const Readback r = wait_back(e, 0);
+      seed_n = r.last.N;
       if (!r.c.overflow) break;
       if (r.c.overflow & 1u) e->cand_cap = std::max(e->cand_cap * 2, r.last.C + r.last.C / 4);
       if (r.c.overflow & 2u) {
@@ -866,6 +879,8 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   // for the rest of the solve.  Batches of many iterations (the paper's policy) never go
   // alone.
   const uint64_t small_keys = kSmallSortBytes / sizeof(K);
+  const uint64_t tail_n_max = tail_tuples(sizeof(K), kind == kJoinSG);
+  bool tail_ok = false;  // WG_LOOP_DEVICE: the last check's sizes (and their rate) fit the tail loop
   bool small_missed = false;
   // within a quarter of a limit, or half of it and not growing
   bool seg_allowed = query == WG_QUERY_TC && !(o.flags & WG_LSD_SORT);
@@ -896,6 +911,8 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
       e->small_mode = calm(x.N, y.N, kSmallJoinTuples) ? 3 : 2;
     else
       e->small_mode = x.C <= 4 * small_keys ? 1 : 0;
+    // (the tail loop checks every iteration's sizes itself: a wrong guess costs one launch)
+    tail_ok = it >= 1 && calm(x.C, y.C, kTailKeys) && calm(x.N, y.N, tail_n_max);
   };
   e->small_mode = 1;
   e->narrow = false;  // (no size yet: the first iterations can already be large)
@@ -905,16 +922,53 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   // LSD passes for the rest of the solve; the first batch, sizes unknown, takes the LSD
   // passes
   e->seg_sort = e->seg_long = false;
+  // WG_LOOP_DEVICE: where the host would enqueue the one-block join alone (the delta and
+  // the candidates, at the last check and at their rate of change, fit one block), it
+  // launches the tail loop instead -- one block running iterations up to the fixpoint or
+  // until one outgrows it -- and the fold after it, with nothing behind them, and waits.
+  // A tail loop stopped by an iteration that does not fit hands that iteration to a batch.
+  const bool tail_allowed = o.loop_mode == WG_LOOP_DEVICE && !e->hash_slots && !e->hrows_mask && !e->unfused;
+  bool in_tail = false;  // the launch waited on is a tail loop
+  auto enqueue_tail = [&](int sl) {
+    const uint32_t jmax = next_j + kTailIters - 1;
+    ensure_records(e, (uint64_t)jmax + 2);
+    b = make_bufs<K>(e);
+    launch_tail_loop<K>(e->stream, e->grid, kind, e->d_ctrl, b, w, jmax, stage(e, WG_STAGE_TAIL_LOOP),
+                        stage(e, WG_STAGE_MERGE));
+    next_j = jmax + 1;
+    read_back(e, sl, batch_first - 1, next_j - 1);
+    batch_first = next_j;
+  };
   // (the first batch, sizes unknown, takes both routes where the row pass is allowed)
   e->row_bitmap = row_allowed;
-  enqueue_batch(K_batch, slot);
+  if (tail_allowed && seed_n <= tail_n_max && seed_n <= kTailKeys) {
+    // a small seed: the tail loop from the first iteration (it stops at once if the
+    // first join is beyond it)
+    enqueue_tail(slot);
+    in_tail = true;
+  } else {
+    enqueue_batch(K_batch, slot);
+  }
   for (;;) {
     // While the host waits on this batch, the device runs a short speculative batch
     // behind it (Section V-B overlaps the next batch with the host check); after the
     // fixpoint its launches are no-ops, so it is kept short.
-    if (speculate) enqueue_iters(std::min(K_batch, kSpec));
+    if (speculate && !in_tail) enqueue_iters(std::min(K_batch, kSpec));
     r = wait_back(e, slot);
+    if (in_tail) {
+      // nothing ran behind the tail loop: the host's count resumes from the device's
+      next_j = r.c.iter + 1;
+      batch_first = next_j;
+    }
+    const bool tail_stuck = in_tail && r.c.tail_exit == kTailSizes;
+    in_tail = false;
     pick_small_mode(r.c.iter);
+    if (tail_stuck && r.c.iter == 0) {
+      // the first iteration was beyond the tail loop: sizes still unknown, as at the start
+      e->small_mode = 1;
+      e->narrow = e->seg_sort = e->seg_long = false;
+      e->row_bitmap = row_allowed;
+    }
     // (at the fixpoint the speculative batch still drains behind the final launches;
     // everything after this is stream-ordered and reads the host mirror of the records)
     if (r.c.overflow | r.c.limit_hit) sync_stream(e);
@@ -949,6 +1003,13 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
     if (adaptive && r.first.N > 0 && (double)r.last.N / (double)r.first.N < 0.1)
       K_batch = std::max(1u, K_batch / 2);
     slot ^= 1;
+    if (tail_allowed && tail_ok && !tail_stuck) {
+      enqueue_tail(slot);
+      in_tail = true;
+      continue;
+    }
+    // (an iteration the tail loop left over does not fit the one-block join)
+    if (tail_stuck && e->small_mode == 3) e->small_mode = 1;
     enqueue_batch(K_batch, slot);
   }
   if (r.c.limit_hit && !r.c.done) fail(e, WG_ERR_ITER_LIMIT, "max_iterations reached before the fixpoint");
@@ -998,6 +1059,7 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
     // every record up to the fixpoint came back with some batch readback
     const std::vector<IterRec> recs(e->h_rec, e->h_rec + iters + 1);
     st->base_tuples = recs[0].N;
+    for (const IterRec& x : recs) st->tail_iterations += x.tail ? 1u : 0u;
     uint64_t cand_total = 0;
     for (size_t i = 1; i < recs.size(); ++i) cand_total += recs[i].C;
     st->join_candidates = cand_total;
@@ -1083,7 +1145,7 @@ wg_status solve(wg_engine* e, int query, uint32_t num, const uint64_t* d_offsets
     e->err = "WG_JOIN_HASH and WG_JOIN_HASH_ROWS exclude each other";
     return WG_ERR_INVALID_ARG;
   }
-  if (o.loop_mode > WG_LOOP_STAGE ||
+  if (o.loop_mode > WG_LOOP_DEVICE ||
       (o.flags & ~(WG_SG_IRREFLEXIVE | WG_STAGE_TIMING | WG_NO_SPECULATION | WG_JOIN_HASH | WG_UNFUSED_DEDUP |
                    WG_SPARSE_INDEX | WG_ITER_GRAPH | WG_LSD_SORT | WG_JOIN_HASH_ROWS))) {
     e->err = "unknown loop_mode or flag";
@@ -1445,6 +1507,7 @@ void wg_engine_destroy(wg_engine* e) {
   release(e->off);
   release(e->rec);
   release(e->htab);
+  release(e->tailrun);
   dev_free(e, e->d_ctrl, kFixedBytes[0], nullptr);
   dev_free(e, e->d_jtot, kFixedBytes[1], nullptr);
   dev_free(e, e->d_bcnt, kFixedBytes[2], nullptr);

@@ -690,16 +690,19 @@ __device__ __forceinline__ K bitonic_keep(K a, K c, uint32_t i, uint32_t jj, uin
 }
 
 // Sorts s[0, n) (LDS, n <= CAP) ascending with all kSmallSortThreads threads of the block
-// and writes the result to out[0, n) (global).  s is clobbered.
-template <typename K>
+// and writes the result to out[0, n) (global; s is clobbered), or with IN_LDS back to
+// s[0, n) (out unused; barriers on both sides of the stores).
+template <typename K, bool IN_LDS = false, uint32_t CAP = kSmallSortBytes / sizeof(K)>
 __device__ __forceinline__ void block_bitonic_sort(K* s, uint32_t n, K* __restrict__ out) {
   constexpr uint32_t TH = kSmallSortThreads;
-  constexpr uint32_t CAP = kSmallSortBytes / sizeof(K);
   constexpr int EMAX = (int)(CAP / TH);  // keys per thread at most
   const uint32_t t = threadIdx.x;
   uint32_t P = 1;
   while (P < n) P <<= 1;
   const int E = P > TH ? (int)(P / TH) : 1;
+  // a wave whose positions are all padding (P below the block) only meets the barriers:
+  // the positions below P exchange among themselves (i ^ jj < P for i < P)
+  const bool idle = (t & ~(uint32_t)(kWave - 1)) >= P;
   K v[EMAX];
 #pragma unroll
   for (int r = 0; r < EMAX; ++r) {
@@ -726,17 +729,21 @@ __device__ __forceinline__ void block_bitonic_sort(K* s, uint32_t n, K* __restri
         }
       } else if (jj >= (uint32_t)kWave) {
         __syncthreads();  // the previous exchange's loads are done
+        if (!idle) {
 #pragma unroll
-        for (int r = 0; r < EMAX; ++r)
-          if (r < E) s[(uint32_t)r * TH + t] = v[r];
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < EMAX; ++r) {
-          if (r >= E) continue;
-          const uint32_t i = (uint32_t)r * TH + t;
-          if (i < P) v[r] = bitonic_keep(v[r], s[i ^ jj], i, jj, k);
+          for (int r = 0; r < EMAX; ++r)
+            if (r < E) s[(uint32_t)r * TH + t] = v[r];
         }
-      } else {
+        __syncthreads();
+        if (!idle) {
+#pragma unroll
+          for (int r = 0; r < EMAX; ++r) {
+            if (r >= E) continue;
+            const uint32_t i = (uint32_t)r * TH + t;
+            if (i < P) v[r] = bitonic_keep(v[r], s[i ^ jj], i, jj, k);
+          }
+        }
+      } else if (!idle) {
 #pragma unroll
         for (int r = 0; r < EMAX; ++r) {
           if (r >= E) continue;
@@ -746,10 +753,20 @@ __device__ __forceinline__ void block_bitonic_sort(K* s, uint32_t n, K* __restri
       }
     }
   }
+  if constexpr (IN_LDS) {
+    __syncthreads();  // the last exchange through LDS has been read
 #pragma unroll
-  for (int r = 0; r < EMAX; ++r) {
-    const uint32_t i = (uint32_t)r * TH + t;
-    if (r < E && i < n) out[i] = v[r];
+    for (int r = 0; r < EMAX; ++r) {
+      const uint32_t i = (uint32_t)r * TH + t;
+      if (r < E && i < n) s[i] = v[r];
+    }
+    __syncthreads();
+  } else {
+#pragma unroll
+    for (int r = 0; r < EMAX; ++r) {
+      const uint32_t i = (uint32_t)r * TH + t;
+      if (r < E && i < n) out[i] = v[r];
+    }
   }
 }
 
@@ -787,108 +804,147 @@ __global__ __launch_bounds__(kSmallSortThreads) void k_small_sort(Ctrl* ctrl, co
 // multi-block launches); the capacity check and the overflow test hook act as in the
 // emit phase.
 // ---------------------------------------------------------------------------
-template <typename K, int Q>
-__global__ __launch_bounds__(kSmallSortThreads) void k_small_join(Ctrl* ctrl, Bufs<K> b, int w, uint32_t j,
-                                                                  K* __restrict__ out) {
-  constexpr uint32_t TH = kSmallSortThreads;
-  constexpr uint32_t CAP = kSmallSortBytes / sizeof(K);
-  constexpr int EMAX = (int)(CAP / TH);
-  constexpr bool kSG = Q == kJoinSG;
-  static_assert(Q == kJoinTC || Q == kJoinSG, "recursive joins only");
-  __shared__ K s_keys[CAP];
-  __shared__ uint32_t s_off[TH];   // per tuple: first candidate
-  __shared__ uint32_t s_base[TH];  // per tuple: first edge of the join row
-  __shared__ K s_head[TH];         // per tuple: key bits passed on (SG: the instance)
-  __shared__ uint32_t s_aux[kSG ? TH : 1];  // SG: first edge of the head row
-  __shared__ uint32_t s_len[kSG ? TH : 1];  // SG: length of the join row
-  __shared__ uint64_t s_wave[TH / kWave];
-  if (block_stop(halted(ctrl))) return;
-  j = iter_begin(ctrl, j);
-  const uint64_t n = b.rec[j - 1].N;
-  const uint32_t t = threadIdx.x;
-  if (n > TH) {
-    if (t == 0) atomicOr(&ctrl->overflow, 8u);
-    return;
+// Lower / upper bounds of ITEMS keys at once in a sorted LDS array s[0, n) (n < 2^32), the
+// first nk of them (nk the same in the whole block), stepping together: 32-bit results,
+// for kernels whose registers are tight.
+template <typename K, int ITEMS, bool UPPER>
+__device__ __forceinline__ void lds_bounds(const K* s, uint32_t n, const K (&v)[ITEMS], uint32_t (&out)[ITEMS],
+                                           int nk) {
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) out[k] = 0;
+  if (n == 0) return;
+  uint32_t len = n;
+  while (len > 1) {
+    const uint32_t half = len >> 1;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k)
+      if (k < nk) {
+        const K x = s[out[k] + half - 1];
+        out[k] = (UPPER ? x <= v[k] : x < v[k]) ? out[k] + half : out[k];
+      }
+    len -= half;
   }
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k)
+    if (k < nk) {
+      const K x = s[out[k]];
+      out[k] += (UPPER ? x <= v[k] : x < v[k]) ? 1u : 0u;
+    }
+}
+template <typename K, int ITEMS>
+__device__ __forceinline__ void lds_lower_bounds(const K* s, uint32_t n, const K (&v)[ITEMS],
+                                                 uint32_t (&out)[ITEMS], int nk) {
+  lds_bounds<K, ITEMS, false>(s, n, v, out, nk);
+}
+template <typename K, int ITEMS>
+__device__ __forceinline__ void lds_upper_bounds(const K* s, uint32_t n, const K (&v)[ITEMS],
+                                                 uint32_t (&out)[ITEMS], int nk) {
+  lds_bounds<K, ITEMS, true>(s, n, v, out, nk);
+}
+
+// Per-tuple state of a one-block join of at most NT tuples (a multiple of
+// kSmallSortThreads), in LDS.
+template <typename K, bool SG, uint32_t NT = kSmallSortThreads>
+struct OneBlockJoin {
+  uint32_t off[NT];           // first candidate
+  uint32_t base[NT];          // first edge of the join row
+  K head[NT];                 // key bits passed on (SG: the instance)
+  uint32_t aux[SG ? NT : 1];  // SG: first edge of the head row
+  uint32_t len[SG ? NT : 1];  // SG: length of the join row
+};
+
+// Count phase of a one-block join of delta[0, n) (n <= NT; global memory or LDS): thread t
+// counts the candidates of tuples [t * NT / kSmallSortThreads, ...) as the count phase
+// does and a block scan lays out the slabs.  Returns the candidate total in every thread;
+// L.off is complete after the next barrier.
+template <typename K, int Q, uint32_t NT = kSmallSortThreads>
+__device__ __forceinline__ uint64_t one_block_count(const Ctrl* ctrl, const Bufs<K>& b, int w,
+                                                    const K* delta, uint32_t n,
+                                                    OneBlockJoin<K, Q == kJoinSG, NT>& L, uint64_t* s_wave) {
+  constexpr uint32_t TH = kSmallSortThreads;
+  constexpr uint32_t TUP = NT / TH;  // tuples per thread
+  static_assert(NT % TH == 0, "");
+  constexpr bool kSG = Q == kJoinSG;
   const bool dense = b.dense != 0;
   const uint32_t* __restrict__ R = b.R;
-  const uint32_t* __restrict__ Edst = b.Edst;
-  uint64_t c = 0;
-  if (t < n) {
-    const K key = b.delta[(j - 1) & 1u][t];
-    uint32_t rb = tc_join_row<K>(key, w);
-    uint32_t ra = head_row<K>(key, w);
-    if (!dense) {
-      const uint64_t nu = ctrl->nu;
-      const uint64_t jb = lower_bound<uint32_t>(b.U, nu, rb);
-      rb = (jb < nu && b.U[jb] == rb) ? (uint32_t)jb : kNoRow;
-      if (kSG) {
-        const uint64_t ja = lower_bound<uint32_t>(b.U, nu, ra);
-        ra = (ja < nu && b.U[ja] == ra) ? (uint32_t)ja : kNoRow;
+  uint64_t cs[TUP];
+  uint64_t csum = 0;
+#pragma unroll
+  for (int u = 0; u < (int)TUP; ++u) {
+    const uint32_t t = threadIdx.x * TUP + (uint32_t)u;
+    uint64_t c = 0;
+    if (t < n) {
+      const K key = delta[t];
+      uint32_t rb = tc_join_row<K>(key, w);
+      uint32_t ra = head_row<K>(key, w);
+      if (!dense) {
+        const uint64_t nu = ctrl->nu;
+        const uint64_t jb = lower_bound<uint32_t>(b.U, nu, rb);
+        rb = (jb < nu && b.U[jb] == rb) ? (uint32_t)jb : kNoRow;
+        if (kSG) {
+          const uint64_t ja = lower_bound<uint32_t>(b.U, nu, ra);
+          ra = (ja < nu && b.U[ja] == ra) ? (uint32_t)ja : kNoRow;
+        }
+      }
+      if (rb != kNoRow && (!kSG || ra != kNoRow)) {
+        const uint32_t base = R[rb];
+        const uint32_t lb = R[rb + 1] - base;
+        L.base[t] = base;
+        if (kSG) {
+          const uint32_t aux = R[ra];
+          c = (uint64_t)(R[ra + 1] - aux) * lb;
+          L.aux[t] = aux;
+          L.len[t] = lb;
+          L.head[t] = (key >> w) >> w;
+        } else {
+          c = lb;
+          L.head[t] = (key >> w) << w;
+        }
       }
     }
-    if (rb != kNoRow && (!kSG || ra != kNoRow)) {
-      const uint32_t base = R[rb];
-      const uint32_t lb = R[rb + 1] - base;
-      s_base[t] = base;
-      if (kSG) {
-        const uint32_t aux = R[ra];
-        c = (uint64_t)(R[ra + 1] - aux) * lb;
-        s_aux[t] = aux;
-        s_len[t] = lb;
-        s_head[t] = (key >> w) >> w;
-      } else {
-        c = lb;
-        s_head[t] = (key >> w) << w;
-      }
-    }
+    cs[u] = c;
+    csum += c;
   }
   uint64_t C;
-  const uint64_t ex = block_excl_scan<uint64_t, TH / kWave>(c, s_wave, C);
-  if (t < n) s_off[t] = (uint32_t)min<uint64_t>(ex, 0xFFFFFFFFull);
-  const uint32_t hook = ctrl->force_overflow_at;
-  if (C > ctrl->cand_cap || (hook != 0 && hook == j)) {
-    if (t == 0) {
-      b.rec[j].C = C;
-      atomicOr(&ctrl->overflow, 1u);
-    }
-    return;
+  uint64_t ex = block_excl_scan<uint64_t, TH / kWave>(csum, s_wave, C);
+#pragma unroll
+  for (int u = 0; u < (int)TUP; ++u) {
+    const uint32_t t = threadIdx.x * TUP + (uint32_t)u;
+    if (t < n) L.off[t] = (uint32_t)min<uint64_t>(ex, 0xFFFFFFFFull);
+    ex += cs[u];
   }
-  if (C > CAP) {
-    if (t == 0) {
-      b.rec[j].C = C;
-      atomicOr(&ctrl->overflow, 8u);
-    }
-    return;
-  }
-  if (t == 0) {
-    b.rec[j].C = C;
-    ctrl->cand_n = C;
-  }
+  return C;
+}
+
+// Emit phase of a one-block join counted by one_block_count (C <= the one-block sort's
+// capacity): every candidate position finds its tuple by bisection over the slab starts
+// and reads one edge (two for SG); the candidates go to s_keys[0, C).  Barriers on both
+// sides.
+template <typename K, int Q, uint32_t NT = kSmallSortThreads, uint32_t CAP = kSmallSortBytes / sizeof(K)>
+__device__ __forceinline__ void one_block_emit(const Bufs<K>& b, int w, uint32_t n, uint32_t C,
+                                               const OneBlockJoin<K, Q == kJoinSG, NT>& L, K* s_keys) {
+  constexpr uint32_t TH = kSmallSortThreads;
+  constexpr int EMAX = (int)(CAP / TH);
+  constexpr bool kSG = Q == kJoinSG;
+  const uint32_t t = threadIdx.x;
+  const uint32_t* __restrict__ Edst = b.Edst;
+  const uint32_t* s_off = L.off;
+  const uint32_t* s_base = L.base;
+  const K* s_head = L.head;
+  const uint32_t* s_aux = L.aux;
+  const uint32_t* s_len = L.len;
   __syncthreads();
   // positions r * TH + t: their tuples (the last slab start at or before the position;
   // tuples without candidates share the next start, so the last one holding it has
   // candidates), then every edge load at once
-  const uint32_t nn = (uint32_t)n;
-  uint32_t e0[EMAX], e1[EMAX], tu[EMAX];
+  // (the bisections of all of a thread's positions step together, so their LDS latencies
+  // overlap)
+  uint32_t e0[EMAX], e1[EMAX], tu[EMAX], pv[EMAX], up[EMAX];
 #pragma unroll
-  for (int r = 0; r < EMAX; ++r) {
-    const uint32_t p = (uint32_t)r * TH + t;
-    tu[r] = 0;
-    if (p < C) {
-      uint32_t lo = 0, len = nn;
-      while (len > 0) {
-        const uint32_t half = len >> 1;
-        if (s_off[lo + half] <= p) {
-          lo += half + 1;
-          len -= half + 1;
-        } else {
-          len = half;
-        }
-      }
-      tu[r] = lo - 1;
-    }
-  }
+  for (int r = 0; r < EMAX; ++r) pv[r] = (uint32_t)r * TH + t;
+  lds_upper_bounds<uint32_t, EMAX>(s_off, n, pv, up, (int)((C + TH - 1) / TH));
+#pragma unroll
+  for (int r = 0; r < EMAX; ++r) tu[r] = pv[r] < C ? up[r] - 1 : 0u;
 #pragma unroll
   for (int r = 0; r < EMAX; ++r) {
     const uint32_t p = (uint32_t)r * TH + t;
@@ -914,8 +970,275 @@ __global__ __launch_bounds__(kSmallSortThreads) void k_small_join(Ctrl* ctrl, Bu
     }
   }
   __syncthreads();
+}
+
+template <typename K, int Q>
+__global__ __launch_bounds__(kSmallSortThreads) void k_small_join(Ctrl* ctrl, Bufs<K> b, int w, uint32_t j,
+                                                                  K* __restrict__ out) {
+  constexpr uint32_t TH = kSmallSortThreads;
+  constexpr uint32_t CAP = kSmallSortBytes / sizeof(K);
+  static_assert(Q == kJoinTC || Q == kJoinSG, "recursive joins only");
+  __shared__ K s_keys[CAP];
+  __shared__ OneBlockJoin<K, Q == kJoinSG> L;
+  __shared__ uint64_t s_wave[TH / kWave];
+  if (block_stop(halted(ctrl))) return;
+  j = iter_begin(ctrl, j);
+  const uint64_t n = b.rec[j - 1].N;
+  const uint32_t t = threadIdx.x;
+  if (n > TH) {
+    if (t == 0) atomicOr(&ctrl->overflow, 8u);
+    return;
+  }
+  const uint64_t C = one_block_count<K, Q>(ctrl, b, w, b.delta[(j - 1) & 1u], (uint32_t)n, L, s_wave);
+  const uint32_t hook = ctrl->force_overflow_at;
+  if (C > ctrl->cand_cap || (hook != 0 && hook == j)) {
+    if (t == 0) {
+      b.rec[j].C = C;
+      atomicOr(&ctrl->overflow, 1u);
+    }
+    return;
+  }
+  if (C > CAP) {
+    if (t == 0) {
+      b.rec[j].C = C;
+      atomicOr(&ctrl->overflow, 8u);
+    }
+    return;
+  }
+  if (t == 0) {
+    b.rec[j].C = C;
+    ctrl->cand_n = C;
+  }
+  one_block_emit<K, Q>(b, w, (uint32_t)n, (uint32_t)C, L, s_keys);
   block_bitonic_sort<K>(s_keys, (uint32_t)C, out);
 }
+
+// ---------------------------------------------------------------------------
+// The fixpoint's tail in one launch.  Section V-B keeps the loop on the device and checks
+// it from the host once per batch; here, once the delta and an iteration's candidates fit
+// one block, a single block runs whole iterations back to back without returning: the
+// one-block join and sort above, then dedup and the set difference against Full, then the
+// new delta's merge, as the multi-block launches of an iteration do.  Full is A + B + T:
+// runs A and B stay as the last multi-block iteration left them (searched through fences
+// sampled into LDS, then by bisection in HBM) and the new tuples of the loop gather in a
+// sorted run T in LDS (each delta is disjoint from Full, so T's merge is a merge of
+// disjoint runs, Section IV-C).  Every iteration writes its delta and its record as the
+// multi-block path does; the record's B side is the one the fold after the launch writes
+// B + T to (k_tail_fold), and its `tail` field marks it.
+//
+// The loop ends at the fixpoint or the iteration limit, and leaves the next iteration to
+// the multi-block launches when its delta or candidates outgrow one block or could
+// overflow the candidate or Full buffers (that path grows them), at the overflow test
+// hook, when T could overflow, or past record jmax; ctrl->tail_exit says which.  One block
+// of kSmallSortThreads threads, no grid-wide wait.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kTailFenceBytes = 8192;  // of each of A and B sampled into LDS
+
+// Clears live[k] where v[k] is in the sorted run a[0, n): the last of the nf fences
+// (fence f = a[f * step], in LDS) at or below v[k], then a bisection of the step keys it
+// starts in HBM, for all keys at once (their loads overlap); dead keys load nothing.
+template <typename K, int ITEMS>
+__device__ __forceinline__ void drop_found(const K* __restrict__ a, uint64_t n, uint64_t step, uint32_t nf,
+                                           const K* fence, const K (&v)[ITEMS], bool (&live)[ITEMS],
+                                           int nk = ITEMS) {
+  if (n == 0) return;
+  uint32_t f[ITEMS];
+  uint64_t pos[ITEMS];
+  bool act[ITEMS];
+  lds_upper_bounds<K, ITEMS>(fence, nf, v, f, nk);  // fences at or below v[k] (first nk keys)
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    act[k] = k < nk && live[k] && f[k] > 0;  // (below the first fence: below a[0])
+    pos[k] = act[k] ? (uint64_t)(f[k] - 1) * step : 0;
+  }
+  // invariant: a[pos] <= v and the last such index lies in [pos, pos + len)
+  for (uint64_t len = step; len > 1;) {
+    const uint64_t half = len >> 1;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint64_t q = pos[k] + half;
+      if (act[k] && q < n && a[q] <= v[k]) pos[k] = q;
+    }
+    len -= half;
+  }
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k)
+    if (act[k] && a[pos[k]] == v[k]) live[k] = false;
+}
+
+template <typename K, int Q>
+__global__ __launch_bounds__(kSmallSortThreads) void k_tail_loop(Ctrl* ctrl, Bufs<K> b, int w, uint32_t jmax) {
+  constexpr uint32_t TH = kSmallSortThreads;
+  constexpr uint32_t CAP = kTailKeys;  // candidates of one iteration
+  constexpr uint32_t TCAP = kTailRunBytes / sizeof(K);
+  constexpr uint32_t NT = tail_tuples(sizeof(K), Q == kJoinSG);  // delta capacity
+  constexpr uint32_t kTailFences = kTailFenceBytes / sizeof(K);
+  constexpr int EMAX = (int)(CAP / TH);
+  constexpr int TMAX = (int)(TCAP / TH);
+  static_assert(Q == kJoinTC || Q == kJoinSG, "recursive joins only");
+  __shared__ K s_keys[CAP];                 // the iteration's candidates, then its delta
+  __shared__ K s_run[TCAP];                 // T
+  __shared__ K s_delta[NT];                 // the delta the next join reads
+  __shared__ K s_fence[2][kTailFences];     // samples of A and B
+  __shared__ OneBlockJoin<K, Q == kJoinSG, NT> L;
+  __shared__ uint64_t s_wave[TH / kWave];
+  const uint32_t t = threadIdx.x;
+  if (t == 0) ctrl->tail_n = 0;  // (also when halted: the fold after this launch reads it)
+  if (block_stop(halted(ctrl))) return;
+  uint32_t j = ctrl->iter + 1;
+  const IterRec r0 = b.rec[j - 1];
+  if (r0.N > NT) {
+    if (t == 0) ctrl->tail_exit = kTailSizes;
+    return;
+  }
+  const K* __restrict__ run[2] = {b.full[r0.a], b.fullB[r0.b]};
+  const uint64_t rn[2] = {r0.FA, r0.F - r0.FA};
+  uint64_t step[2];
+  uint32_t nf[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    step[q] = rn[q] > kTailFences ? (rn[q] + kTailFences - 1) / kTailFences : 1;
+    nf[q] = (uint32_t)((rn[q] + step[q] - 1) / step[q]);
+    for (uint32_t f = t; f < nf[q]; f += TH) s_fence[q][f] = run[q][(uint64_t)f * step[q]];
+  }
+  uint32_t n = (uint32_t)r0.N;
+  for (uint32_t i = t; i < n; i += TH) s_delta[i] = b.delta[(j - 1) & 1u][i];
+  const uint64_t cand_cap = ctrl->cand_cap, full_cap = ctrl->full_cap;
+  const uint32_t hook = ctrl->force_overflow_at, max_iter = ctrl->max_iter;
+  uint64_t F = r0.F;
+  uint32_t tn = 0;  // |T|
+  uint32_t last = 0;  // the last iteration this launch completed
+  uint32_t why = kTailFixpoint;
+  __syncthreads();
+  for (;; ++j) {
+    if (j > jmax) {
+      why = kTailRecords;
+      break;
+    }
+    const uint64_t C = one_block_count<K, Q, NT>(ctrl, b, w, s_delta, n, L, s_wave);
+    if (C > CAP || C > cand_cap || (hook != 0 && hook == j) || F + C > full_cap) {
+      why = kTailSizes;
+      break;
+    }
+    if (tn + C > TCAP) {
+      why = kTailRun;
+      break;
+    }
+    one_block_emit<K, Q, NT, CAP>(b, w, n, (uint32_t)C, L, s_keys);
+    block_bitonic_sort<K, true, CAP>(s_keys, (uint32_t)C, nullptr);
+    // dedup + difference (Section IV-B): thread t takes positions r * TH + t; a key stays
+    // if it differs from the key before it and is in none of T, A and B (the searches of
+    // all of a thread's keys step together, so their latencies overlap)
+    // (rounds r < R hold positions; R is the same in every thread, so the bounds below
+    // are scalar branches)
+    const int R = (int)((C + TH - 1) / TH);
+    K v[EMAX];
+    bool live[EMAX];
+    uint32_t x[EMAX];
+#pragma unroll
+    for (int r = 0; r < EMAX; ++r) {
+      const uint32_t p = (uint32_t)r * TH + t;
+      live[r] = r < R && p < C;
+      v[r] = live[r] ? s_keys[p] : ~K(0);
+      if (live[r] && p > 0 && s_keys[p - 1] == v[r]) live[r] = false;
+    }
+    lds_lower_bounds<K, EMAX>(s_run, tn, v, x, R);
+#pragma unroll
+    for (int r = 0; r < EMAX; ++r)
+      if (live[r] && x[r] < tn && s_run[x[r]] == v[r]) live[r] = false;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) drop_found<K, EMAX>(run[q], rn[q], step[q], nf[q], s_fence[q], v, live, R);
+    // output places in position order, (r, t): one block scan of the per-round flags packed
+    // into 16-bit fields (four rounds per 64-bit word; a field's sum is at most TH)
+    constexpr int W64 = (EMAX + 3) / 4;
+    uint64_t packed[W64], before[W64], tot[W64];
+#pragma unroll
+    for (int q = 0; q < W64; ++q) packed[q] = 0;
+#pragma unroll
+    for (int r = 0; r < EMAX; ++r) packed[r / 4] |= (uint64_t)(live[r] ? 1u : 0u) << (16 * (r % 4));
+#pragma unroll
+    for (int q = 0; q < W64; ++q) {
+      before[q] = tot[q] = 0;
+      if (4 * q < R) before[q] = block_excl_scan<uint64_t, TH / kWave>(packed[q], s_wave, tot[q]);
+    }
+    // (the scans' barriers order every read of s_keys above before these writes)
+    K* __restrict__ dout = b.delta[j & 1u];
+    uint32_t N = 0;
+#pragma unroll
+    for (int r = 0; r < EMAX; ++r) {
+      const uint32_t o = N + (uint32_t)((before[r / 4] >> (16 * (r % 4))) & 0xFFFFu);
+      if (live[r]) {
+        s_keys[o] = v[r];
+        dout[o] = v[r];
+      }
+      N += (uint32_t)((tot[r / 4] >> (16 * (r % 4))) & 0xFFFFu);
+    }
+    __syncthreads();
+    // T' = merge(T, delta): every key's place is its index plus its rank in the other run
+    K tv[TMAX], dv[EMAX];
+    uint32_t tp[TMAX], dp[EMAX];
+#pragma unroll
+    for (int r = 0; r < TMAX; ++r) {
+      const uint32_t i = (uint32_t)r * TH + t;
+      tv[r] = i < tn ? s_run[i] : ~K(0);
+    }
+#pragma unroll
+    for (int r = 0; r < EMAX; ++r) {
+      const uint32_t i = (uint32_t)r * TH + t;
+      dv[r] = i < N ? s_keys[i] : ~K(0);
+      if (i < N && N <= NT) s_delta[i] = dv[r];
+    }
+    lds_lower_bounds<K, TMAX>(s_keys, N, tv, tp, (int)((tn + TH - 1) / TH));
+    lds_lower_bounds<K, EMAX>(s_run, tn, dv, dp, (int)((N + TH - 1) / TH));
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < TMAX; ++r) {
+      const uint32_t i = (uint32_t)r * TH + t;
+      if (i < tn) s_run[i + tp[r]] = tv[r];
+    }
+#pragma unroll
+    for (int r = 0; r < EMAX; ++r) {
+      const uint32_t i = (uint32_t)r * TH + t;
+      if (i < N) s_run[i + dp[r]] = dv[r];
+    }
+    tn += N;
+    const bool at_limit = N > 0 && max_iter != 0 && j >= max_iter;
+    if (t == 0) {
+      IterRec& rj = b.rec[j];
+      rj.N = N;
+      rj.C = C;
+      rj.F = F + N;
+      rj.FA = r0.FA;
+      rj.a = r0.a;
+      rj.b = tn > 0 ? (r0.b ^ 1u) : r0.b;
+      rj.fold = 0;
+      rj.tail = 1;
+      ctrl->iter = j;
+      ctrl->cand_n = C;
+      if (N == 0) ctrl->done = 1;
+      else if (at_limit) ctrl->limit_hit = 1;
+    }
+    F += N;
+    n = N;
+    last = j;
+    __syncthreads();  // T and the next delta are in place
+    if (N == 0 || at_limit) break;
+    if (N > NT) {
+      why = kTailSizes;
+      break;
+    }
+  }
+  // T goes out for the fold; tn > 0 means at least one iteration completed
+  for (uint32_t i = t; i < tn; i += TH) b.tail[i] = s_run[i];
+  if (t == 0) {
+    if (tn > 0) b.rec[last].tail = 2;
+    ctrl->tail_n = tn;
+    ctrl->tail_b = r0.b;
+    ctrl->tail_exit = why;
+    ctrl->full_n = F;
+  }
+}
+
 
 // Lanes of the wave (within `active`) whose RB-bit digit equals this lane's: one ballot
 // per bit.  For bit b, sb is 0 or all ones (the lane's bit, sign-extended); the lanes that
@@ -2313,6 +2636,22 @@ __global__ __launch_bounds__(kBlock) void k_merge(Ctrl* ctrl, Bufs<K> b, uint32_
                           gridDim.x - ga);
 }
 
+// After a tail loop: B' = merge(B, T) into the other B buffer, the side the loop's records
+// name (nothing when T is empty).
+template <typename K, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_tail_fold(Ctrl* ctrl, Bufs<K> b) {
+  constexpr uint32_t T = kBlock * ITEMS;
+  __shared__ K s_in[T];
+  __shared__ K s_out[T];
+  __shared__ uint64_t s_i[4];
+  const uint64_t tn = ctrl->tail_n;
+  if (block_stop(tn == 0)) return;
+  const uint32_t side = ctrl->tail_b;
+  const IterRec r = b.rec[ctrl->iter];
+  merge_tiles<K, ITEMS>(b.fullB[side], r.F - r.FA - tn, b.tail, tn, b.fullB[side ^ 1u], s_in, s_out, s_i,
+                        blockIdx.x, gridDim.x);
+}
+
 // O = merge(A, B), sizes from the host (the final union of the two runs).
 template <typename K, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_merge_pair(const K* __restrict__ A, uint64_t na,
@@ -2761,6 +3100,16 @@ void launch_merge(hipStream_t s, const Grid& g, Ctrl* ctrl, const Bufs<K>& b, ui
 }
 
 template <typename K>
+void launch_tail_loop(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w, uint32_t jmax,
+                      Ev ev, Ev ev_fold) {
+  if (kind == kJoinTC)
+    WG_LAUNCH_WIDE((k_tail_loop<K, kJoinTC>), 1, ev.start, ev.stop, s, ctrl, b, w, jmax);
+  else
+    WG_LAUNCH_WIDE((k_tail_loop<K, kJoinSG>), 1, ev.start, ev.stop, s, ctrl, b, w, jmax);
+  WG_LAUNCH((k_tail_fold<K, kMergeItems>), g.stream, ev_fold.start, ev_fold.stop, s, ctrl, b);
+}
+
+template <typename K>
 void launch_merge_pair(hipStream_t s, const Grid& g, const K* A, uint64_t na, const K* B, uint64_t nb,
                        K* O, Ev ev) {
   WG_LAUNCH((k_merge_pair<K, kMergeItems>), stream_blocks(g, (na + nb + 7) / 8), ev.start, ev.stop, s, A,
@@ -2817,6 +3166,7 @@ void launch_resume(hipStream_t s, Ctrl* ctrl, uint64_t cand_cap, uint64_t full_c
   template void launch_compact<K>(hipStream_t, const Grid&, int, Ctrl*, const uint64_t*, const K*, \
                                   K*, const Bufs<K>&, int, uint32_t, uint32_t, Ev, bool);          \
   template void launch_merge<K>(hipStream_t, const Grid&, Ctrl*, const Bufs<K>&, uint32_t, Ev);   \
+  template void launch_tail_loop<K>(hipStream_t, const Grid&, int, Ctrl*, const Bufs<K>&, int, uint32_t, Ev, Ev); \
   template void launch_row_diff<K>(hipStream_t, const Grid&, Ctrl*, const uint64_t*, const Bufs<K>&, int, \
                                    uint32_t, Ev, int);                                             \
   template void launch_row_gather<K>(hipStream_t, const Grid&, Ctrl*, const uint64_t*, const Bufs<K>&,  \

@@ -114,6 +114,7 @@ struct Bufs {
   uint64_t* htab;  // hash-join variant: open-addressing table of E (power-of-two slots)
   uint32_t* rcnt;  // radix: per-block digit counts, then offsets (digits x blocks)
   uint32_t* rtot;  // radix: digit totals
+  K* tail;         // run T of a tail loop, handed to the fold after it (kTailRunBytes)
   IterRec* rec;    // per-iteration sizes
   uint32_t dense;  // > 0: R is a dense index over the row ids [0, dense) (R[v] = first edge
                    // of row v, R[dense] = |E|) and U is unused; 0: rows are U's entries
@@ -174,6 +175,21 @@ void launch_small_sort(hipStream_t s, Ctrl* ctrl, const uint64_t* n_ptr, const B
 template <typename K>
 void launch_small_join(hipStream_t s, int kind, Ctrl* ctrl, const Bufs<K>& b, int w, uint32_t j, int passes,
                        Ev ev = Ev());
+
+// The fixpoint's tail in one block (kind kJoinTC or kJoinSG): whole iterations from
+// ctrl->iter + 1 on, at most up to record jmax, while they fit one block; then the
+// fold of the loop's new tuples into run B (a multi-block launch; `ev_fold` times it).
+template <typename K>
+void launch_tail_loop(hipStream_t s, const Grid& g, int kind, Ctrl* ctrl, const Bufs<K>& b, int w, uint32_t jmax,
+                      Ev ev = Ev(), Ev ev_fold = Ev());
+constexpr uint32_t kTailRunBytes = 32768;  // run T of a tail loop, in LDS and in b.tail (8,192 / 4,096 keys)
+constexpr uint32_t kTailKeys = 4096;       // candidates of one tail-loop iteration (sorted in LDS)
+// Delta tuples a tail loop takes (its LDS: candidates, T, delta, per-tuple join state and
+// the fences of A and B within the 160 KB of one workgroup): 32-bit keys 4,096 (TC) or
+// 2,048 (SG), 64-bit keys 2,048 or 1,024.
+constexpr uint32_t tail_tuples(size_t key_bytes, bool sg) {
+  return (key_bytes == 4 ? 4096u : 2048u) >> (sg ? 1 : 0);
+}
 
 // Segmented sort of the TC join's *n_ptr candidates (grouped by row, each row's run
 // unsorted) from cand[0] into cand[passes & 1]: each run sorted in LDS by one block.

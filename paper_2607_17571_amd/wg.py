@@ -44,9 +44,10 @@ WG_LOOP_AUTO = 0
 WG_LOOP_BATCHED = 1
 WG_LOOP_HOST = 2
 WG_LOOP_STAGE = 3
+WG_LOOP_DEVICE = 4
 
 STAGES = ["join_count", "join_emit", "radix_hist", "radix_pass", "dedup_diff", "merge", "prepare",
-          "seg_sort", "row_diff"]
+          "seg_sort", "row_diff", "tail_loop"]
 WG_NUM_STAGES = len(STAGES)
 
 
@@ -84,6 +85,7 @@ class WgStats(ctypes.Structure):
         ("delta_sizes_cap", c_uint64),
         ("digit_bits", c_uint32),
         ("sort_passes", c_uint32),
+        ("tail_iterations", c_uint64),
     ]
 
 
@@ -447,7 +449,7 @@ def stats_dict(s: WgStats, deltas=None) -> dict:
         "host_syncs": int(s.host_syncs), "resumes": int(s.resumes),
         "field_bits": int(s.field_bits), "key_bytes": int(s.key_bytes),
         "digit_bits": int(s.digit_bits), "sort_passes": int(s.sort_passes),
-        "solve_ms": float(s.solve_ms),
+        "tail_iterations": int(s.tail_iterations), "solve_ms": float(s.solve_ms),
         "stage_ms": {k: float(s.stage_ms[i]) for i, k in enumerate(STAGES)},
         "stage_launches": {k: int(s.stage_launches[i]) for i, k in enumerate(STAGES)},
         "stage_bytes": {k: int(s.stage_bytes[i]) for i, k in enumerate(STAGES)},

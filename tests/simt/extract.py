@@ -1,5 +1,6 @@
-"""Copy top-level definitions (functions by name, `const:NAME` for constexpr lines) out of a
-kernel source file, so that the CPU harness compiles the current kernel text.
+"""Copy top-level definitions (functions by name, `const:NAME` for constexpr lines,
+`struct:NAME` for a struct or struct template) out of a kernel source file, so that the CPU
+harness compiles the current kernel text.
 
     python extract.py <source.hip> NAME... > out.inc
 """
@@ -26,8 +27,19 @@ def grab_function(name):
                     if depth == 0:
                         return text[:q + 1]
     raise SystemExit(f"not found: {name}")
+def grab_struct(name):
+    for i, l in enumerate(lines):
+        if re.match(r"^struct " + re.escape(name) + r"\b", l):
+            start = i - 1 if i > 0 and lines[i - 1].startswith("template") else i
+            end = i
+            while not lines[end].startswith("};"):
+                end += 1
+            return "\n".join(lines[start:end + 1])
+    raise SystemExit(f"struct not found: {name}")
 for n in names:
-    if n.startswith("const:"):
+    if n.startswith("struct:"):
+        out.append(grab_struct(n[7:]))
+    elif n.startswith("const:"):
         nm = n[6:]
         hit = [l for l in lines if re.match(r"^constexpr .*\b" + re.escape(nm) + r"\b\s*=", l)]
         if not hit: raise SystemExit(f"const not found: {nm}")

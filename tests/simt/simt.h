@@ -62,7 +62,13 @@ struct Fiber {
 inline thread_local void* sched_sp = nullptr;
 inline thread_local const void* sched_bottom = nullptr;
 inline thread_local size_t sched_size = 0;
-inline thread_local std::vector<Fiber> fibers;
+// (the stacks go with the OS thread that ran the fibers)
+struct Fibers : std::vector<Fiber> {
+  ~Fibers() {
+    for (auto& f : *this) std::free(f.stack);
+  }
+};
+inline thread_local Fibers fibers;
 inline thread_local int cur = 0;
 inline std::function<void()>* body = nullptr;  // shared by the block threads (read only)
 inline thread_local uint64_t bar_gen = 0;

@@ -120,12 +120,12 @@ def test_batch_rejects_bad_offsets(engine):
     assert ei.value.status == wg.WG_ERR_INVALID_ARG
 
 
-def _golden_batch(engine, name, sample):
+def _golden_batch(engine, name, sample, options=None):
     if name not in GOLDEN:
         pytest.fail(f"no golden record for {name}; run tests/golden/make_golden.py {name}")
     g = GOLDEN[name]
     query, b = inputs.batch_workload(name)
-    s, d, offs, st = run_batch(engine, query, b.src, b.dst, b.offsets)
+    s, d, offs, st = run_batch(engine, query, b.src, b.dst, b.offsets, options)
     assert s.size == g["size"]
     assert st["iterations"] == g["iterations"]
     assert hashlib.sha256(offs.astype("<i8").tobytes()).hexdigest() == g["offsets_sha256"]

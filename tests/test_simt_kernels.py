@@ -166,3 +166,81 @@ def test_segmented_sort(seg_harness, tmp_path, key_bytes, lens):
     assert "simt:" not in r.stderr, r.stderr[-2000:]
     assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-2000:])
     assert r.stdout.count("ok ") == 2
+
+
+# ---------------------------------------------------------------------------
+# The tail loop (one block looping over whole iterations) and the fold after it.
+# ---------------------------------------------------------------------------
+TAIL = ["const:kNoRow", "const:kSmallSortThreads", "shfl_xor_key", "bitonic_keep", "block_bitonic_sort", "struct:OneBlockJoin",
+        "lds_bounds", "lds_lower_bounds", "lds_upper_bounds",
+        "one_block_count", "one_block_emit", "const:kTailFenceBytes", "drop_found", "k_tail_loop",
+        "wave_merge_path", "merge_tiles_to", "merge_tiles", "k_tail_fold"]
+
+
+@pytest.fixture(scope="module")
+def tail_harness(tmp_path_factory):
+    return _build(tmp_path_factory.mktemp("simt_tail"), "tail_harness.cpp", "tail.inc", TAIL)
+
+
+def _tail_case(tail_harness, tmp_path, query, src, dst, kb, split, jstep, grid=7):
+    """Runs the tail loop from the seed to the fixpoint (the seed's Full split at random into
+    runs A and B) and compares every iteration's delta size, the candidate total and the
+    result with the oracle."""
+    import oracle
+    from oracle import seminaive as sn
+
+    w = max(1, int(max(src.max(), dst.max())).bit_length())
+    assert 2 * w <= 8 * kb
+    E = sn.sort_unique(sn.pack(src, dst))
+    seed = E if query == 0 else sn.sort_unique(sn.sg_base(*sn.edge_index(E)))
+    ref = oracle.tc(src, dst) if query == 0 else oracle.sg(src, dst)
+
+    def rekey(k):  # the oracle's 32-bit fields -> w-bit fields
+        return ((k >> np.uint64(32)) << np.uint64(w)) | (k & np.uint64(0xFFFFFFFF))
+    E, seed = rekey(E), rekey(seed)
+    rng = np.random.default_rng(len(seed))
+    pick = rng.random(seed.size) < split
+    A, B = np.sort(seed[~pick]), np.sort(seed[pick])
+    inp, out = tmp_path / "in.bin", tmp_path / "out.bin"
+    with open(inp, "wb") as f:
+        np.array([query, w, kb, E.size, A.size, B.size], dtype=np.uint64).tofile(f)
+        for a in (E, A, B):
+            a.astype(np.uint64).tofile(f)
+    r = subprocess.run([str(tail_harness), str(inp), str(out), str(grid), "8", str(jstep)], capture_output=True,
+                       text=True, timeout=600)
+    assert r.returncode == 0, r.stdout + r.stderr
+    got = np.fromfile(out, dtype=np.uint64)
+    iters = int(got[0])
+    NC = got[1:1 + 2 * iters].reshape(iters, 2)
+    nf = int(got[1 + 2 * iters])
+    full = got[2 + 2 * iters:2 + 2 * iters + nf]
+    launches, at_records, at_run = (int(x) for x in got[2 + 2 * iters + nf:])
+    assert iters == ref.iterations
+    assert [int(x) for x in NC[:, 0]] == list(ref.delta_sizes[1:])
+    assert int(NC[:, 1].sum()) == ref.candidates
+    want = (ref.src.astype(np.uint64) << np.uint64(w)) | ref.dst.astype(np.uint64)
+    np.testing.assert_array_equal(full, np.sort(want))
+    return launches, at_records, at_run
+
+
+@pytest.mark.parametrize("kb", [4, 8])
+def test_tail_loop_tc_to_the_fixpoint(tail_harness, tmp_path, kb):
+    from paper_2607_17571_amd import inputs
+    src, dst = inputs.erdos_renyi(60, 75, seed=3)
+    launches, at_records, _ = _tail_case(tail_harness, tmp_path, 0, src, dst, kb, split=0.3, jstep=3)
+    assert launches > 1 and at_records > 0  # the record bound stopped it and it went on
+
+
+def test_tail_loop_tc_fills_its_run(tail_harness, tmp_path):
+    """A closure beyond run T's capacity: T fills, the fold merges it into B, the next
+    launch starts from there."""
+    from paper_2607_17571_amd import inputs
+    src, dst = inputs.chain(150)  # 11,175 tuples, a few hundred new per iteration
+    launches, _, at_run = _tail_case(tail_harness, tmp_path, 0, src, dst, 4, split=0.0, jstep=400)
+    assert at_run > 0
+
+
+def test_tail_loop_sg(tail_harness, tmp_path):
+    from paper_2607_17571_amd import inputs
+    src, dst = inputs.erdos_renyi(40, 60, seed=5)
+    _tail_case(tail_harness, tmp_path, 1, src, dst, 4, split=0.5, jstep=2)
