@@ -54,7 +54,7 @@ STAGE_KERNELS = {
     "radix_hist": "k_radix_count + k_radix_scan", "radix_pass": "k_radix_scatter",
     "dedup_diff": "k_compact_local + k_compact_gather", "merge": "k_merge",
     "prepare": "k_max_id, k_pack, k_index_*, k_unpack", "seg_sort": "k_seg_sort",
-    "row_diff": "k_row_diff + k_row_gather",
+    "row_diff": "k_row_diff + k_row_gather", "tail_loop": "k_tail_loop",
 }
 WORKLOAD_TEXT = {
     "tc_rmat_s15": "TC, R-MAT scale 15 (n=32,768, m=29,491, a,b,c,d=0.57,0.19,0.19,0.05, seed 2); "
@@ -123,6 +123,7 @@ def parse():
     p.add_argument("--no-autotune", action="store_true", help="skip the sort autotuner (run before timing)")
     p.add_argument("--no-plain", action="store_true", help="batched workloads: skip the one-by-one path")
     p.add_argument("--no-spec", action="store_true", help="no speculative batch behind host checks")
+    p.add_argument("--no-tail-loop", action="store_true", help="no one-block tail loop (every iteration multi-block)")
     p.add_argument("--dominant", default=None, help="kernel kind to take the roofline of (skips the probe)")
     p.add_argument("--roofline-only", action="store_true",
                    help="run only the instrumented steps (value then comes from them); for profiling")
@@ -644,7 +645,7 @@ def run_ablation(args):
                 "paper_adaptive_speculative": dict(loop_mode=wg.WG_LOOP_BATCHED),
                 "default": {},
                 "default_graph_replay": dict(flags=wg.WG_ITER_GRAPH),
-                "device_tail_loop": dict(loop_mode=wg.WG_LOOP_DEVICE),
+                "no_tail_loop": dict(flags=wg.WG_NO_TAIL_LOOP),
             }
             if w.query == "tc":
                 for k in (2, 5, 20, 40, 50):
@@ -738,7 +739,7 @@ def measure(args, name: str) -> dict:
 
     sort_opts = dict(radix_digit_bits=args.digit_bits, tile_items=args.tile_items,
                      radix_field_bits=args.field_bits)
-    base_flags = wg.WG_NO_SPECULATION if args.no_spec else 0
+    base_flags = (wg.WG_NO_SPECULATION if args.no_spec else 0) | (wg.WG_NO_TAIL_LOOP if args.no_tail_loop else 0)
     for _ in range(args.warmup):
         solve(wg.make_options(flags=base_flags, **sort_opts))
     torch.cuda.synchronize()

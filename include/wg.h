@@ -84,11 +84,23 @@ typedef enum { WG_QUERY_TC = 0, WG_QUERY_SG = 1, WG_QUERY_TRIANGLES = 2 } wg_que
                                  Section IV-B, never with the segmented sort or the row pass
                                  (which sort only each source row's run, the join having
                                  emitted the candidates grouped by row) */
+#define WG_NO_TAIL_LOOP 0x200u /* WG_LOOP_AUTO without its tail loop: every iteration from the
+                                  host-enqueued multi-block launches (ablation) */
 
 /* wg_options.loop_mode */
 #define WG_LOOP_AUTO 0u     /* the default: device-resident loop checked by the host every 2
                                iterations (batch_k overrides), with a speculative batch
-                               enqueued behind every check */
+                               enqueued behind every check; and once the delta (at most
+                               1,024-4,096 tuples by key width and query) and an
+                               iteration's candidates (at most 4,096) fit one block, one
+                               launch runs the fixpoint's tail: a single workgroup loops
+                               over whole iterations (join, sort, dedup + difference,
+                               merge) until the fixpoint, the iteration limit or an
+                               iteration that outgrows it, which goes back to the
+                               multi-block launches (Section V-B's device-resident loop
+                               carried into one launch).  TC and SG; not with
+                               WG_JOIN_HASH, WG_JOIN_HASH_ROWS, WG_UNFUSED_DEDUP or
+                               WG_NO_TAIL_LOOP */
 #define WG_LOOP_BATCHED 1u  /* K iterations per host check (Section V-B, batched recording);
                                batch_k = 0 takes the paper's policy: K = 30 halving for
                                TC, 10 for SG */
@@ -98,15 +110,6 @@ typedef enum { WG_QUERY_TC = 0, WG_QUERY_SG = 1, WG_QUERY_TRIANGLES = 2 } wg_que
                                size after the compaction, as a loop that sizes each stage
                                from the host would do (three host round trips per
                                iteration; the kernels still size themselves on the device) */
-#define WG_LOOP_DEVICE 4u   /* WG_LOOP_AUTO, and once the delta (at most 1,024 tuples) and an
-                               iteration's candidates fit one block, one launch runs the
-                               fixpoint's tail: a single workgroup loops over whole
-                               iterations (join, sort, dedup + difference, merge) until the
-                               fixpoint, the iteration limit or an iteration that outgrows
-                               it, which goes back to the multi-block launches (Section V-B's
-                               device-resident loop carried into one launch).  TC and SG;
-                               not with WG_JOIN_HASH, WG_JOIN_HASH_ROWS or WG_UNFUSED_DEDUP
-                               (which keep WG_LOOP_AUTO's launches) */
 
 typedef struct {
   uint32_t struct_size;      /* sizeof(wg_options); older sizes are accepted */
@@ -147,7 +150,7 @@ enum {
                               join's row-grouped candidates in one LDS bitmap (Sections IV-B,
                               V-C), which replaces the sort and the compaction of a large
                               iteration */
-  WG_STAGE_TAIL_LOOP = 9,  /* WG_LOOP_DEVICE: the one-block launch that runs the fixpoint's tail
+  WG_STAGE_TAIL_LOOP = 9,  /* the one-block launch that runs the fixpoint's tail
                               (its fold into run B is timed as WG_STAGE_MERGE) */
   WG_NUM_STAGES = 10
 };
@@ -169,7 +172,7 @@ typedef struct {
   uint64_t delta_sizes_cap; /* its capacity in entries (filled up to the capacity) */
   uint32_t digit_bits;      /* radix digit bits per LSD pass used */
   uint32_t sort_passes;     /* LSD passes per sort: ceil(key bits / digit_bits) */
-  uint64_t tail_iterations; /* WG_LOOP_DEVICE: iterations run inside tail-loop launches */
+  uint64_t tail_iterations; /* iterations run inside tail-loop launches */
 } wg_stats;
 
 typedef struct wg_engine wg_engine; /* per device: buffers, control block, sort tuning table */

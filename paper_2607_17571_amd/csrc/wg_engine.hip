@@ -880,7 +880,7 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   // alone.
   const uint64_t small_keys = kSmallSortBytes / sizeof(K);
   const uint64_t tail_n_max = tail_tuples(sizeof(K), kind == kJoinSG);
-  bool tail_ok = false;  // WG_LOOP_DEVICE: the last check's sizes (and their rate) fit the tail loop
+  bool tail_ok = false;  // the last check's sizes (and their rate) fit the tail loop
   bool small_missed = false;
   // within a quarter of a limit, or half of it and not growing
   bool seg_allowed = query == WG_QUERY_TC && !(o.flags & WG_LSD_SORT);
@@ -922,12 +922,13 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
   // LSD passes for the rest of the solve; the first batch, sizes unknown, takes the LSD
   // passes
   e->seg_sort = e->seg_long = false;
-  // WG_LOOP_DEVICE: where the host would enqueue the one-block join alone (the delta and
-  // the candidates, at the last check and at their rate of change, fit one block), it
-  // launches the tail loop instead -- one block running iterations up to the fixpoint or
-  // until one outgrows it -- and the fold after it, with nothing behind them, and waits.
-  // A tail loop stopped by an iteration that does not fit hands that iteration to a batch.
-  const bool tail_allowed = o.loop_mode == WG_LOOP_DEVICE && !e->hash_slots && !e->hrows_mask && !e->unfused;
+  // The tail loop (WG_LOOP_AUTO): where the delta and the candidates, at the last check
+  // and at their rate of change, fit one block, the host launches one block running
+  // iterations up to the fixpoint or until one outgrows it, and the fold after it, with
+  // nothing behind them, and waits.  A tail loop stopped by an iteration that does not
+  // fit hands that iteration to a batch.
+  const bool tail_allowed = o.loop_mode == WG_LOOP_AUTO && !(o.flags & WG_NO_TAIL_LOOP) && !e->hash_slots &&
+                            !e->hrows_mask && !e->unfused;
   bool in_tail = false;  // the launch waited on is a tail loop
   auto enqueue_tail = [&](int sl) {
     const uint32_t jmax = next_j + kTailIters - 1;
@@ -1145,9 +1146,9 @@ wg_status solve(wg_engine* e, int query, uint32_t num, const uint64_t* d_offsets
     e->err = "WG_JOIN_HASH and WG_JOIN_HASH_ROWS exclude each other";
     return WG_ERR_INVALID_ARG;
   }
-  if (o.loop_mode > WG_LOOP_DEVICE ||
+  if (o.loop_mode > WG_LOOP_STAGE ||
       (o.flags & ~(WG_SG_IRREFLEXIVE | WG_STAGE_TIMING | WG_NO_SPECULATION | WG_JOIN_HASH | WG_UNFUSED_DEDUP |
-                   WG_SPARSE_INDEX | WG_ITER_GRAPH | WG_LSD_SORT | WG_JOIN_HASH_ROWS))) {
+                   WG_SPARSE_INDEX | WG_ITER_GRAPH | WG_LSD_SORT | WG_JOIN_HASH_ROWS | WG_NO_TAIL_LOOP))) {
     e->err = "unknown loop_mode or flag";
     return WG_ERR_INVALID_ARG;
   }

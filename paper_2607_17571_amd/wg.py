@@ -31,6 +31,7 @@ WG_STAGE_TIMING = 0x2
 WG_NO_SPECULATION = 0x4
 WG_JOIN_HASH = 0x8
 WG_JOIN_HASH_ROWS = 0x100
+WG_NO_TAIL_LOOP = 0x200
 WG_UNFUSED_DEDUP = 0x10
 WG_SPARSE_INDEX = 0x20
 WG_ITER_GRAPH = 0x40
@@ -44,7 +45,6 @@ WG_LOOP_AUTO = 0
 WG_LOOP_BATCHED = 1
 WG_LOOP_HOST = 2
 WG_LOOP_STAGE = 3
-WG_LOOP_DEVICE = 4
 
 STAGES = ["join_count", "join_emit", "radix_hist", "radix_pass", "dedup_diff", "merge", "prepare",
           "seg_sort", "row_diff", "tail_loop"]

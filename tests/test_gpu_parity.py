@@ -251,6 +251,7 @@ def test_sg_irreflexive(engine):
     dict(flags=wg.WG_UNFUSED_DEDUP, force_overflow_at_iter=2),
     dict(flags=wg.WG_UNFUSED_DEDUP | wg.WG_JOIN_HASH, loop_mode=wg.WG_LOOP_STAGE),
     dict(flags=wg.WG_JOIN_HASH_ROWS | wg.WG_ITER_GRAPH), dict(flags=wg.WG_JOIN_HASH_ROWS, loop_mode=wg.WG_LOOP_HOST),
+    dict(flags=wg.WG_NO_TAIL_LOOP), dict(flags=wg.WG_NO_TAIL_LOOP | wg.WG_ITER_GRAPH),
 ])
 def test_result_independent_of_loop_policy(engine, opts):
     src, dst = inputs.rmat(11, 1800, *inputs.RMAT_ABCD, seed=9)

@@ -1,4 +1,5 @@
-"""WG_LOOP_DEVICE: the fixpoint's tail run by one block in one launch, against the oracle.
+"""The default loop's tail loop: the fixpoint's tail run by one block in one launch,
+against the oracle.
 
 Once the delta and an iteration's candidates fit one block, a single workgroup loops over
 whole iterations (join, sort, dedup + difference, merge into a run held in LDS) and a
@@ -20,13 +21,13 @@ from tests.test_gpu_batch import _golden_batch, check_instances, run_batch
 
 pytestmark = pytest.mark.gpu
 
-DEV = wg.WG_LOOP_DEVICE
+NO_TAIL = wg.WG_NO_TAIL_LOOP
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "fixpoints.json")))
 
 
 def timed(**kw):
     kw["flags"] = kw.get("flags", 0) | wg.WG_STAGE_TIMING
-    return wg.make_options(loop_mode=DEV, **kw)
+    return wg.make_options(**kw)
 
 
 TC_GRAPHS = {
@@ -94,7 +95,7 @@ def test_long_chain_many_launches(engine):
 ])
 def test_with_other_options(engine, opts):
     src, dst = inputs.rmat(11, 1800, *inputs.RMAT_ABCD, seed=9)
-    s, d, st = run(engine, "tc", src, dst, wg.make_options(loop_mode=DEV, **opts))
+    s, d, st = run(engine, "tc", src, dst, wg.make_options(**opts))
     assert_same(s, d, st, oracle.tc(src, dst))
 
 
@@ -102,7 +103,7 @@ def test_with_other_options(engine, opts):
 def test_forced_overflow(engine, at):
     """The overflow hook's iteration goes back to the multi-block path, which reports it."""
     src, dst = inputs.rmat(11, 1800, *inputs.RMAT_ABCD, seed=9)
-    s, d, st = run(engine, "tc", src, dst, wg.make_options(loop_mode=DEV, force_overflow_at_iter=at))
+    s, d, st = run(engine, "tc", src, dst, wg.make_options(force_overflow_at_iter=at))
     assert_same(s, d, st, oracle.tc(src, dst))
     assert st["resumes"] >= 1
 
@@ -110,10 +111,10 @@ def test_forced_overflow(engine, at):
 def test_iteration_limit(engine):
     a, b = inputs.chain(100)
     with pytest.raises(wg.WgError) as ei:
-        run(engine, "tc", a, b, wg.make_options(loop_mode=DEV, max_iterations=40))
+        run(engine, "tc", a, b, wg.make_options(max_iterations=40))
     assert ei.value.status == wg.WG_ERR_ITER_LIMIT
     ref = oracle.tc(a, b)
-    s, d, st = run(engine, "tc", a, b, wg.make_options(loop_mode=DEV, max_iterations=ref.iterations))
+    s, d, st = run(engine, "tc", a, b, wg.make_options(max_iterations=ref.iterations))
     assert_same(s, d, st, ref)
 
 
@@ -133,17 +134,20 @@ def test_alternating_with_other_loops(engine):
     for _ in range(2):
         for q, (src, dst) in cases:
             ref = oracle.tc(src, dst) if q == "tc" else oracle.sg(src, dst)
-            for mode in (DEV, wg.WG_LOOP_AUTO, DEV, wg.WG_LOOP_HOST):
-                s, d, st = run(engine, q, src, dst, wg.make_options(loop_mode=mode))
+            for opts in (wg.make_options(), wg.make_options(flags=NO_TAIL), wg.make_options(),
+                         wg.make_options(loop_mode=wg.WG_LOOP_HOST)):
+                s, d, st = run(engine, q, src, dst, opts)
                 assert_same(s, d, st, ref)
 
 
 @pytest.mark.parametrize("name", ["tc_er_2000", "tc_rmat_s15", "tc_rmat_s16", "tc_rmat_s15_ids24",
                                   "sg_er_500k", "tc_grid_100"])
-def test_full_size_against_golden(engine, name):
+def test_full_size_without_tail_loop(engine, name):
+    """The multi-block launches alone (the tail loop is the default's; the default runs
+    against these summaries with the other full-size tests)."""
     g = GOLDEN[name]
     w = inputs.workload(name)
-    s, d, st = run(engine, w.query, w.src, w.dst, wg.make_options(loop_mode=DEV))
+    s, d, st = run(engine, w.query, w.src, w.dst, wg.make_options(flags=NO_TAIL))
     assert s.size == g["size"]
     assert st["iterations"] == g["iterations"]
     assert st["delta_sizes"] == g["delta_sizes"]
@@ -163,5 +167,5 @@ def test_batches(engine):
 
 
 @pytest.mark.parametrize("name", ["tc_batch_er_256", "sg_batch_er_256", "tc_batch_er_4096"])
-def test_batch_against_golden(engine, name):
-    _golden_batch(engine, name, [0, 1, 100, 255], wg.make_options(loop_mode=DEV))
+def test_batch_without_tail_loop_against_golden(engine, name):
+    _golden_batch(engine, name, [0, 1, 100, 255], wg.make_options(flags=NO_TAIL))
