@@ -680,6 +680,31 @@ __device__ __forceinline__ K shfl_xor_key(K v, int lane_mask) {
   }
 }
 
+// The key of lane (this lane ^ M), M a power of two below the wave: a DPP quad permutation
+// for M = 1 and 2 (no LDS), a swizzle within 32 lanes for 4, 8 and 16, a permute for 32.
+template <int M>
+__device__ __forceinline__ uint32_t xor_lanes32(uint32_t v) {
+  static_assert(M >= 1 && M <= 32 && (M & (M - 1)) == 0, "");
+  if constexpr (M == 1)
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1 /* quad_perm 1,0,3,2 */, 0xF, 0xF, false);
+  else if constexpr (M == 2)
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E /* quad_perm 2,3,0,1 */, 0xF, 0xF, false);
+  else if constexpr (M < 32)
+    return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (M << 10) /* and 31, or 0, xor M */);
+  else
+    return (uint32_t)__shfl_xor((int)v, M, kWave);
+}
+template <int M, typename K>
+__device__ __forceinline__ K xor_lanes(K v) {
+  if constexpr (sizeof(K) == 4) {
+    return (K)xor_lanes32<M>((uint32_t)v);
+  } else {
+    const uint32_t lo = xor_lanes32<M>((uint32_t)v);
+    const uint32_t hi = xor_lanes32<M>((uint32_t)(v >> 32));
+    return ((K)hi << 32) | (K)lo;
+  }
+}
+
 // Key at position i after its compare-exchange with position i ^ jj (partner key c) in
 // the merge of bitonic runs of length k: the lower position keeps the smaller key in an
 // ascending run ((i & k) == 0) and the larger one in a descending run.
@@ -687,6 +712,19 @@ template <typename K>
 __device__ __forceinline__ K bitonic_keep(K a, K c, uint32_t i, uint32_t jj, uint32_t k) {
   const bool take_min = ((i & jj) == 0) == ((i & k) == 0);
   return take_min ? (c < a ? c : a) : (c < a ? a : c);
+}
+
+// The compare-exchanges at partner distance M (< one wave) of the merge of bitonic runs of
+// length k, for a thread's slots r < E (positions r * kSmallSortThreads + t).
+template <int M, typename K, int EMAX>
+__device__ __forceinline__ void wave_stage(K (&v)[EMAX], int E, uint32_t k, uint32_t t) {
+  if ((uint32_t)M >= k) return;
+#pragma unroll
+  for (int r = 0; r < EMAX; ++r) {
+    if (r >= E) continue;
+    const uint32_t i = (uint32_t)r * kSmallSortThreads + t;
+    v[r] = bitonic_keep(v[r], xor_lanes<M>(v[r]), i, (uint32_t)M, k);
+  }
 }
 
 // Sorts s[0, n) (LDS, n <= CAP) ascending with all kSmallSortThreads threads of the block
@@ -710,7 +748,7 @@ __device__ __forceinline__ void block_bitonic_sort(K* s, uint32_t n, K* __restri
     v[r] = (r < E && i < n) ? s[i] : ~K(0);  // padding sorts last
   }
   for (uint32_t k = 2; k <= P; k <<= 1) {
-    for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+    for (uint32_t jj = k >> 1; jj >= (uint32_t)kWave; jj >>= 1) {
       if (jj >= TH) {
         // both keys in this thread: slots r and r ^ (jj / TH) (static indices)
 #pragma unroll
@@ -743,14 +781,16 @@ __device__ __forceinline__ void block_bitonic_sort(K* s, uint32_t n, K* __restri
             if (i < P) v[r] = bitonic_keep(v[r], s[i ^ jj], i, jj, k);
           }
         }
-      } else if (!idle) {
-#pragma unroll
-        for (int r = 0; r < EMAX; ++r) {
-          if (r >= E) continue;
-          const uint32_t i = (uint32_t)r * TH + t;
-          v[r] = bitonic_keep(v[r], shfl_xor_key(v[r], (int)jj), i, jj, k);
-        }
       }
+    }
+    // partners within a wave: each distance a constant, no barrier
+    if (!idle) {
+      wave_stage<32>(v, E, k, t);
+      wave_stage<16>(v, E, k, t);
+      wave_stage<8>(v, E, k, t);
+      wave_stage<4>(v, E, k, t);
+      wave_stage<2>(v, E, k, t);
+      wave_stage<1>(v, E, k, t);
     }
   }
   if constexpr (IN_LDS) {
@@ -1034,36 +1074,47 @@ __global__ __launch_bounds__(kSmallSortThreads) void k_small_join(Ctrl* ctrl, Bu
 // ---------------------------------------------------------------------------
 constexpr uint32_t kTailFenceBytes = 8192;  // of each of A and B sampled into LDS
 
-// Clears live[k] where v[k] is in the sorted run a[0, n): the last of the nf fences
-// (fence f = a[f * step], in LDS) at or below v[k], then a bisection of the step keys it
-// starts in HBM, for all keys at once (their loads overlap); dead keys load nothing.
+// Clears live[k] where v[k] is in either sorted run a[q][0, n[q]) (runs A and B of Full):
+// in each run the last of the nf[q] fences (fence f = a[q][f * step[q]], in LDS) at or
+// below v[k], then a bisection of the step[q] keys it starts in HBM.  The bisections of
+// all keys in both runs step together, so their loads overlap (the dependent round trips
+// are those of the longer span only); dead keys load nothing.
 template <typename K, int ITEMS>
-__device__ __forceinline__ void drop_found(const K* __restrict__ a, uint64_t n, uint64_t step, uint32_t nf,
-                                           const K* fence, const K (&v)[ITEMS], bool (&live)[ITEMS],
-                                           int nk = ITEMS) {
-  if (n == 0) return;
-  uint32_t f[ITEMS];
-  uint64_t pos[ITEMS];
-  bool act[ITEMS];
-  lds_upper_bounds<K, ITEMS>(fence, nf, v, f, nk);  // fences at or below v[k] (first nk keys)
+__device__ __forceinline__ void drop_found(const K* __restrict__ const (&a)[2], const uint64_t (&n)[2], const uint64_t (&step)[2],
+                                           const uint32_t (&nf)[2], K (*fence)[kTailFenceBytes / sizeof(K)],
+                                           const K (&v)[ITEMS], bool (&live)[ITEMS], int nk) {
+  uint64_t pos[2][ITEMS];
+  bool act[2][ITEMS];
 #pragma unroll
-  for (int k = 0; k < ITEMS; ++k) {
-    act[k] = k < nk && live[k] && f[k] > 0;  // (below the first fence: below a[0])
-    pos[k] = act[k] ? (uint64_t)(f[k] - 1) * step : 0;
-  }
-  // invariant: a[pos] <= v and the last such index lies in [pos, pos + len)
-  for (uint64_t len = step; len > 1;) {
-    const uint64_t half = len >> 1;
+  for (int q = 0; q < 2; ++q) {
+    uint32_t f[ITEMS];
+    lds_upper_bounds<K, ITEMS>(fence[q], n[q] ? nf[q] : 0u, v, f, nk);  // fences at or below v[k]
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
-      const uint64_t q = pos[k] + half;
-      if (act[k] && q < n && a[q] <= v[k]) pos[k] = q;
+      act[q][k] = k < nk && live[k] && f[k] > 0;  // (below the first fence: below a[q][0])
+      pos[q][k] = act[q][k] ? (uint64_t)(f[k] - 1) * step[q] : 0;
     }
-    len -= half;
+  }
+  // invariant per run: a[pos] <= v and the last such index lies in [pos, pos + len)
+  uint64_t len[2] = {step[0], step[1]};
+  while (len[0] > 1 || len[1] > 1) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (len[q] <= 1) continue;
+      const uint64_t half = len[q] >> 1;
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint64_t x = pos[q][k] + half;
+        if (act[q][k] && x < n[q] && a[q][x] <= v[k]) pos[q][k] = x;
+      }
+      len[q] -= half;
+    }
   }
 #pragma unroll
-  for (int k = 0; k < ITEMS; ++k)
-    if (act[k] && a[pos[k]] == v[k]) live[k] = false;
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k)
+      if (act[q][k] && a[q][pos[q][k]] == v[k]) live[k] = false;
 }
 
 template <typename K, int Q>
@@ -1146,8 +1197,7 @@ __global__ __launch_bounds__(kSmallSortThreads) void k_tail_loop(Ctrl* ctrl, Buf
 #pragma unroll
     for (int r = 0; r < EMAX; ++r)
       if (live[r] && x[r] < tn && s_run[x[r]] == v[r]) live[r] = false;
-#pragma unroll
-    for (int q = 0; q < 2; ++q) drop_found<K, EMAX>(run[q], rn[q], step[q], nf[q], s_fence[q], v, live, R);
+    drop_found<K, EMAX>(run, rn, step, nf, s_fence, v, live, R);
     // output places in position order, (r, t): one block scan of the per-round flags packed
     // into 16-bit fields (four rounds per 64-bit word; a field's sum is at most TH)
     constexpr int W64 = (EMAX + 3) / 4;

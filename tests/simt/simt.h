@@ -236,6 +236,21 @@ inline uint64_t __builtin_amdgcn_ballot_w64(bool p) {
   return m;
 }
 template <typename T> inline T __builtin_amdgcn_readfirstlane(T v) { return simt::exch(v, 0); }
+// DPP quad permutation (controls below 0x100: lane 4q + i reads lane 4q + ctrl[2i+1:2i])
+inline int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int, int, bool) {
+  if (ctrl < 0 || ctrl > 0xFF) std::abort();  // only quad_perm is emulated
+  (void)old;
+  const int lane = simt::lane_of();
+  return simt::exch(src, (lane & ~3) | ((ctrl >> (2 * (lane & 3))) & 3));
+}
+// ds_swizzle in its bit mode (offset bit 15 clear): within each 32 lanes, lane i reads
+// ((i & and) | or) ^ xor
+inline int __builtin_amdgcn_ds_swizzle(int v, int pattern) {
+  if (pattern & 0x8000) std::abort();  // only the bit mode is emulated
+  const int lane = simt::lane_of();
+  const int am = pattern & 0x1F, om = (pattern >> 5) & 0x1F, xm = (pattern >> 10) & 0x1F;
+  return simt::exch(v, (lane & 32) | (((lane & 31 & am) | om) ^ xm));
+}
 inline void __builtin_amdgcn_wave_barrier() {}
 inline void __builtin_amdgcn_s_sleep(int) {}
 inline int __popc(uint32_t v) { return __builtin_popcount(v); }

@@ -135,7 +135,7 @@ def test_compaction_windows(compact_harness, tmp_path, key_bytes, per_item, item
     assert r.stdout.count("ok ") == 3
 
 
-SEG = ["const:kSmallSortThreads", "shfl_xor_key", "bitonic_keep", "block_bitonic_sort", "const:kSegTile",
+SEG = ["const:kSmallSortThreads", "shfl_xor_key", "bitonic_keep", "xor_lanes32", "xor_lanes", "wave_stage", "block_bitonic_sort", "const:kSegTile",
        "const:kSegBitonicMax", "const:kSegLongBytes", "k_seg_sort"]
 
 
@@ -171,7 +171,7 @@ def test_segmented_sort(seg_harness, tmp_path, key_bytes, lens):
 # ---------------------------------------------------------------------------
 # The tail loop (one block looping over whole iterations) and the fold after it.
 # ---------------------------------------------------------------------------
-TAIL = ["const:kNoRow", "const:kSmallSortThreads", "shfl_xor_key", "bitonic_keep", "block_bitonic_sort", "struct:OneBlockJoin",
+TAIL = ["const:kNoRow", "const:kSmallSortThreads", "shfl_xor_key", "bitonic_keep", "xor_lanes32", "xor_lanes", "wave_stage", "block_bitonic_sort", "struct:OneBlockJoin",
         "lds_bounds", "lds_lower_bounds", "lds_upper_bounds",
         "one_block_count", "one_block_emit", "const:kTailFenceBytes", "drop_found", "k_tail_loop",
         "wave_merge_path", "merge_tiles_to", "merge_tiles", "k_tail_fold"]
