@@ -2166,6 +2166,18 @@ __device__ __forceinline__ void or_sorted_runs(uint32_t* bm, bool valid, uint32_
   if (valid && (lane == kWave - 1 || next != word)) atomicOr(&bm[word], acc);
 }
 
+// The row pass's searches (its rows' range, Full's cursors): rounds of kRowFan probes until
+// the span fits one 64-lane round (0: every round 64 probes).  A round of 64 probes touches
+// 64 scattered lines; thousands of blocks search at their start.
+constexpr int kRowFan = 8;
+template <typename Pred>
+__device__ __forceinline__ uint64_t row_search(uint64_t lo, uint64_t hi, Pred pred) {
+  if constexpr (kRowFan > 0)
+    return wave_partition_fan<kRowFan>(lo, hi, pred);
+  else
+    return wave_partition(lo, hi, pred);
+}
+
 template <typename K>
 __global__ __launch_bounds__(kBlock) void k_row_diff(int gate, Ctrl* ctrl, const uint64_t* n_ptr,
                                                      const K* __restrict__ in, K* __restrict__ tmp, Bufs<K> b,
@@ -2204,7 +2216,7 @@ __global__ __launch_bounds__(kBlock) void k_row_diff(int gate, Ctrl* ctrl, const
       const uint64_t ilo = d > nx ? d - nx : 0, ihi = d < n ? d : n;
       // candidates among the first d merged elements: C[i] precedes X[d-1-i] while its row
       // is smaller (true for a prefix of i)
-      const uint64_t i = wave_partition(ilo, ihi, [&](uint64_t q) {
+      const uint64_t i = row_search(ilo, ihi, [&](uint64_t q) {
         return (uint64_t)(in[q] >> w) < (uint64_t)(X[d - 1 - q] >> w);
       });
       const uint64_t rc = i < n ? (uint64_t)(in[i] >> w) : kInf;
@@ -2214,7 +2226,7 @@ __global__ __launch_bounds__(kBlock) void k_row_diff(int gate, Ctrl* ctrl, const
     // first candidate position whose row is at least r
     auto row_pos = [&](uint64_t r) -> uint64_t {
       if (r == kInf) return n;
-      return wave_partition(0, n, [&](uint64_t q) { return (uint64_t)(in[q] >> w) < r; });
+      return row_search(0, n, [&](uint64_t q) { return (uint64_t)(in[q] >> w) < r; });
     };
     if (wid < 2) {
       const uint64_t d = (total * (uint64_t)(blockIdx.x + wid)) / gridDim.x;
@@ -2235,10 +2247,10 @@ __global__ __launch_bounds__(kBlock) void k_row_diff(int gate, Ctrl* ctrl, const
     {
       const K first = (in[p] >> w) << w;
       if (wid == 0) {
-        const uint64_t v = wave_lower_bound(runA, FA, first);
+        const uint64_t v = row_search(0, FA, [&](uint64_t i) { return runA[i] < first; });
         if (lane_id() == 0) s_at[1] = v;
       } else if (wid == 1) {
-        const uint64_t v = wave_lower_bound(runB, FB, first);
+        const uint64_t v = row_search(0, FB, [&](uint64_t i) { return runB[i] < first; });
         if (lane_id() == 0) s_at[2] = v;
       }
       __syncthreads();
@@ -2292,10 +2304,10 @@ __global__ __launch_bounds__(kBlock) void k_row_diff(int gate, Ctrl* ctrl, const
       const bool seek_b = pb < FB && (runB[pb] >> w) < rk;
       if (seek_a || seek_b) {
         if (wid == 0 && seek_a) {
-          const uint64_t v = wave_partition(pa, FA, [&](uint64_t i) { return (runA[i] >> w) < rk; });
+          const uint64_t v = row_search(pa, FA, [&](uint64_t i) { return (runA[i] >> w) < rk; });
           if (lane_id() == 0) s_at[1] = v;
         } else if (wid == 1 && seek_b) {
-          const uint64_t v = wave_partition(pb, FB, [&](uint64_t i) { return (runB[i] >> w) < rk; });
+          const uint64_t v = row_search(pb, FB, [&](uint64_t i) { return (runB[i] >> w) < rk; });
           if (lane_id() == 0) s_at[2] = v;
         }
         __syncthreads();

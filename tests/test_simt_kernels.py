@@ -27,7 +27,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SIMT = os.path.join(ROOT, "tests", "simt")
 CSRC = os.path.join(ROOT, "paper_2607_17571_amd", "csrc")
-KERNELS = ["const:kRowWordsMax", "const:kRowItems", "const:kRowTile", "nth_set_bit", "or_sorted_runs", "k_row_diff",
+KERNELS = ["const:kRowWordsMax", "const:kRowItems", "const:kRowTile", "nth_set_bit", "or_sorted_runs", "const:kRowFan",
+           "row_search", "k_row_diff",
            "record_iteration", "k_row_gather"]
 
 pytestmark = pytest.mark.skipif(shutil.which("g++") is None or platform.machine() != "x86_64",
