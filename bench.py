@@ -29,7 +29,7 @@ also gets an all-core figure, its instances spread over worker processes.
 The default run (no --workload) adds under "extra" the same measurement of the batched
 workload (tc_batch_er_4096, 3 solves, with the plain one-by-one path) and of SG on
 sg_er_500k, each with its own roofline and CPU baseline, and the served mix (120 requests,
-4 slots) at 0.7x, 1.0x and 1.5x the plain path's capacity: p50/p99 latency and tuples/s of
+2 slots) at 0.7x, 1.0x and 1.5x the plain path's capacity: p50/p99 latency and tuples/s of
 the server and of the plain path, both measured under the same Poisson arrivals, with
 every served result checked against the oracle's record.  CPU baselines run first,
 before anything touches the GPU, because the all-core leg forks worker processes.
@@ -133,7 +133,8 @@ def parse():
                    help="only gather MIB MiB of 4-byte values through a random permutation 10 times "
                         "(scattered-read counter calibration) and exit")
     p.add_argument("--requests", type=int, default=120, help="served_mix: number of requests")
-    p.add_argument("--slots", type=int, default=4, help="served_mix: concurrent solves")
+    p.add_argument("--slots", type=int, default=2,
+                   help="served_mix: concurrent solves (2 measured ahead of 3 and 4 on this mix)")
     p.add_argument("--load", type=float, default=0.7, help="served_mix: offered load / capacity")
     p.add_argument("--hold-after-us", type=int, default=0,
                    help="served_mix: long-solve hold of the server (0: its default, 4294967295: never)")
