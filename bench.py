@@ -939,7 +939,7 @@ def main():
         sub.steps, sub.warmup = args.steps, min(args.warmup, 3)
         extra["sg"] = with_cpu(measure(sub, SG_EXTRA), SG_EXTRA)
         _progress("extra: served_mix")
-        sub.requests, sub.slots, sub.load, sub.hold_after_us = 120, 4, 0.7, 0
+        sub.requests, sub.slots, sub.load, sub.hold_after_us = 120, args.slots, 0.7, 0
         sv = measure_served(sub)
         extra["served"] = {k: sv[k] for k in ("value", "unit", "served", "single_instance_path", "load_sweep",
                                               "golden_checks", "config")}
