@@ -381,9 +381,10 @@ typedef struct wg_job wg_job;
 
 typedef struct {
   uint32_t slots;            /* concurrent solves, 1..16; 0 = 4 */
-  /* Long-solve hold: while a solve has run longer than this (microseconds), no further
-   * request is admitted until it ends, so that the heavy tail of a mix runs nearly alone
-   * instead of slowing down beside new arrivals (tail latency); 0 = the default, 8000;
+  /* Long-solve hold: while a solve has run longer than this (microseconds), or has shown
+   * an iteration of 2^21 candidates or more at one of its host checks, no further request
+   * is admitted until it ends, so that the heavy tail of a mix runs nearly alone instead
+   * of slowing down beside new arrivals (tail latency); 0 = the default, 8000;
    * 0xFFFFFFFF = never hold. */
   uint32_t hold_after_us;
   uint64_t mem_budget_bytes; /* device memory of all slots, results and inputs; 0 = 80% of free */

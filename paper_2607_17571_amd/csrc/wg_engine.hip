@@ -125,6 +125,7 @@ struct wg_engine {
   uint64_t budget = 0;
   GrowHook grow_hook;  // request server: asked for more budget before a solve fails
   const std::atomic<bool>* cancel = nullptr;  // request server: stop at the next host check
+  std::atomic<uint64_t> seen_cand{0};         // largest candidate count read back in this solve
   uint64_t generation = 0;
   std::string err;
   // per-solve
@@ -695,6 +696,7 @@ template <typename K>
 wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst, uint64_t m,
               const wg_options& o, int w, int ib, wg_stats* st) {
   e->key_bits = ib + 2 * w;
+  e->seen_cand.store(0, std::memory_order_relaxed);
   e->sort = e->trial ? *e->trial : e->tune[sizeof(K) == 8];
   if (o.radix_digit_bits) e->sort.rb = (int)o.radix_digit_bits;
   if (o.tile_items) e->sort.items = (int)o.tile_items;
@@ -961,6 +963,8 @@ wg_status run(wg_engine* e, int query, const uint32_t* src, const uint32_t* dst,
       next_j = r.c.iter + 1;
       batch_first = next_j;
     }
+    if (r.c.cand_n > e->seen_cand.load(std::memory_order_relaxed))
+      e->seen_cand.store(r.c.cand_n, std::memory_order_relaxed);
     const bool tail_stuck = in_tail && r.c.tail_exit == kTailSizes;
     in_tail = false;
     pick_small_mode(r.c.iter);
@@ -1306,6 +1310,7 @@ uint64_t engine_allocated(const wg_engine* e) { return e->allocated; }
 uint64_t engine_peak(const wg_engine* e) { return e->peak; }
 void engine_set_grow_hook(wg_engine* e, GrowHook hook) { e->grow_hook = std::move(hook); }
 void engine_set_cancel(wg_engine* e, const std::atomic<bool>* flag) { e->cancel = flag; }
+uint64_t engine_seen_candidates(const wg_engine* e) { return e->seen_cand.load(std::memory_order_relaxed); }
 
 void engine_trim(wg_engine* e) {
   try {

@@ -26,6 +26,9 @@ void engine_trim(wg_engine* e);            // free the relation buffers; results
 void engine_set_grow_hook(wg_engine* e, GrowHook hook);
 // While set, the solve stops at its next host check with WG_ERR_CANCELLED once *flag holds.
 void engine_set_cancel(wg_engine* e, const std::atomic<bool>* flag);
+// The largest per-iteration candidate count the solve in progress has read back at its
+// host checks (0 before the first; reset when a solve starts).  Any thread may read it.
+uint64_t engine_seen_candidates(const wg_engine* e);
 
 // Copy a result's keys (stream-ordered, then waits) into a device buffer owned by a new
 // handle.  `release(bytes)` runs when that handle is freed.

@@ -42,6 +42,7 @@ enum JobPhase : int { kQueued = 0, kRunning = 1, kDone = 2 };
 
 constexpr uint64_t kMinReservation = 64ull << 20;
 constexpr uint32_t kMaxPassOver = 16;  // later requests may pass a waiting one this often
+constexpr uint64_t kHoldCandidates = 1ull << 21;  // an iteration this large marks a long solve
 constexpr double kMaxMemoryWaitMs = 5000.0;  // a growing solve waits this long for memory
 
 struct JobState {
@@ -160,8 +161,13 @@ std::shared_ptr<JobState> pick(wg_server* sv, size_t i, uint64_t* grant) {
     others_run = true;
     if (o.waiting_memory) return nullptr;  // memory that frees up goes to waiting solves first
     // a long solve (the heavy tail of the mix) finishes faster alone than beside new
-    // arrivals; those wait until it ends (its slot notifies at the end)
-    if (sv->hold_after_ms >= 0 && now - o.busy_since > sv->hold_after_ms) return nullptr;
+    // arrivals; those wait until it ends (its slot notifies at the end).  A solve is long
+    // once it has run hold_after, or as soon as one of its host checks has read back an
+    // iteration of kHoldCandidates candidates or more (a large fixpoint, known a few
+    // milliseconds before the clock would tell)
+    if (sv->hold_after_ms >= 0 &&
+        (now - o.busy_since > sv->hold_after_ms || wg::engine_seen_candidates(o.engine) >= kHoldCandidates))
+      return nullptr;
   }
   const uint64_t others = usage_except(sv, i);
   const uint64_t held = (uint64_t)std::max<int64_t>(sv->core->held, 0);
