@@ -1311,6 +1311,7 @@ uint64_t engine_peak(const wg_engine* e) { return e->peak; }
 void engine_set_grow_hook(wg_engine* e, GrowHook hook) { e->grow_hook = std::move(hook); }
 void engine_set_cancel(wg_engine* e, const std::atomic<bool>* flag) { e->cancel = flag; }
 uint64_t engine_seen_candidates(const wg_engine* e) { return e->seen_cand.load(std::memory_order_relaxed); }
+void engine_clear_seen(wg_engine* e) { e->seen_cand.store(0, std::memory_order_relaxed); }
 
 void engine_trim(wg_engine* e) {
   try {

@@ -29,6 +29,9 @@ void engine_set_cancel(wg_engine* e, const std::atomic<bool>* flag);
 // The largest per-iteration candidate count the solve in progress has read back at its
 // host checks (0 before the first; reset when a solve starts).  Any thread may read it.
 uint64_t engine_seen_candidates(const wg_engine* e);
+// Forget the previous solve's sizes now, before the next solve starts (a caller that hands
+// the engine a new job reads engine_seen_candidates of that job from then on).
+void engine_clear_seen(wg_engine* e);
 
 // Copy a result's keys (stream-ordered, then waits) into a device buffer owned by a new
 // handle.  `release(bytes)` runs when that handle is freed.

@@ -252,6 +252,9 @@ void worker(wg_server* sv, size_t i) {
     }
     JobState& j = *job;
     me.job = job;
+    // (under the lock: until the solve itself starts, the engine still reports the previous
+    // solve's candidates, which would hold the other slots' admissions as a long solve)
+    wg::engine_clear_seen(me.engine);
     me.reservation = grant;
     me.busy_since = now_ms();
     j.phase = kRunning;
