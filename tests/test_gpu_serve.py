@@ -202,3 +202,40 @@ def test_job_handle_outlives_server(engine):
         info = j.info()
         assert info["phase"] == 2
         j.close()
+
+
+def test_small_request_starts_beside_the_job_after_a_large_solve(engine):
+    """The long-solve hold looks at the candidate counts a running solve has read back.  A
+    slot that has just finished a large solve must not pass that count on to the job it
+    takes next: here a long solve that never reaches 2^21 candidates (TC on a 1,500-vertex
+    chain: 1,500 small iterations) and a small request wait behind a large solve's hold;
+    when it ends, its slot takes the chain and the other slot must start the small request
+    at once, which therefore ends first (instead of waiting for the chain)."""
+    import time
+
+    w = inputs.workload("tc_rmat_s15")
+    big = (to_gpu(w.src), to_gpu(w.dst))
+    chain = [to_gpu(x) for x in inputs.chain(1500)]
+    tiny = inputs.erdos_renyi(300, 280, seed=1)
+    tiny_gpu = [to_gpu(x) for x in tiny]
+    srv = wg.Server(0, slots=2)  # the default 8 ms / 2^21-candidate hold
+    try:
+        srv.submit("tc", *big).wait(want_result=False)  # (warm-up)
+        print("[gpu] serve: chain and small request behind a large solve", flush=True, file=sys.stderr)
+        jl = srv.submit("tc", *big)
+        time.sleep(0.003)  # past its first host check: a large iteration holds admissions
+        jx = srv.submit("tc", *chain)
+        jy = srv.submit("tc", *tiny_gpu)
+        ys, yd, _, yi = jy.wait()
+        _, _, xst, xi = jx.wait(want_result=False)
+        _, _, lst, li = jl.wait(want_result=False)
+        for j in (jl, jx, jy):
+            j.close()
+    finally:
+        srv.close()
+    assert max(lst["delta_sizes"]) >= 1 << 21
+    assert xst["result_tuples"] == 1500 * 1499 // 2
+    ref = oracle.tc(*tiny)
+    np.testing.assert_array_equal(ys.cpu().numpy(), ref.src)
+    np.testing.assert_array_equal(yd.cpu().numpy(), ref.dst)
+    assert yi["end_ms"] < xi["end_ms"], (li, xi, yi)
