@@ -9,6 +9,7 @@ import hashlib
 import json
 import os
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -211,8 +212,6 @@ def test_small_request_starts_beside_the_job_after_a_large_solve(engine):
     chain: 1,500 small iterations) and a small request wait behind a large solve's hold;
     when it ends, its slot takes the chain and the other slot must start the small request
     at once, which therefore ends first (instead of waiting for the chain)."""
-    import time
-
     w = inputs.workload("tc_rmat_s15")
     big = (to_gpu(w.src), to_gpu(w.dst))
     chain = [to_gpu(x) for x in inputs.chain(1500)]
