@@ -138,6 +138,8 @@ def parse():
     p.add_argument("--load", type=float, default=0.7, help="served_mix: offered load / capacity")
     p.add_argument("--hold-after-us", type=int, default=0,
                    help="served_mix: long-solve hold of the server (0: its default, 4294967295: never)")
+    p.add_argument("--sync-probe", action="store_true",
+                   help="cost of a grid-wide barrier in one cooperative launch against a dependent launch")
     p.add_argument("--kernel-sweep", action="store_true",
                    help="sort and merge kernels alone on 2^20..2^28 synthetic keys")
     p.add_argument("--sweep-min-log2", type=int, default=20)
@@ -868,7 +870,8 @@ def main():
         print(json.dumps({"error": "the benchmark runs on one GPU (the engine is single-device); --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
-    special = args.kernel_sweep or args.ablation or args.copy_calibration or args.gather_calibration
+    special = (args.kernel_sweep or args.ablation or args.copy_calibration or args.gather_calibration
+               or args.sync_probe)
     default_run = not args.workload_given and not special
     # CPU baselines first: the all-core leg forks worker processes, which must not inherit an
     # initialised GPU runtime (nothing below has touched the GPU yet)
@@ -909,6 +912,23 @@ def main():
         print(json.dumps({"gather_calibration_values": n, "value_bytes": 4, "index_bytes": 8,
                           "algorithmic_read_bytes": 12 * n, "algorithmic_write_bytes": 4 * n,
                           "gathers": 10}), flush=True)
+        return
+    if args.sync_probe:
+        # the two ways to separate the stages of an iteration (Section V-B): a grid-wide
+        # barrier inside one persistent launch, or the boundary between two launches
+        from paper_2607_17571_amd import wg
+        rows = []
+        for blocks in (256, 512, 1024, 2048):
+            try:
+                bar, bar2, bcg, lau = wg.wg_probe_sync_costs(0, blocks, 2000)
+            except wg.WgError as e:
+                rows.append({"blocks": blocks, "error": str(e)})
+                continue
+            rows.append({"blocks": blocks, "barrier_us": round(bar, 3), "barrier_two_level_us": round(bar2, 3),
+                         "grid_sync_us": round(bcg, 3), "launch_us": round(lau, 3)})
+            _progress(f"sync probe: {blocks} blocks: barrier {bar:.3f} us (two-level {bar2:.3f} us, grid sync "
+                      f"{bcg:.3f} us), launch {lau:.3f} us")
+        print(json.dumps({"sync_probe": rows, "threads_per_block": 256, "rounds": 2000}), flush=True)
         return
     if args.kernel_sweep:
         run_kernel_sweep(args)

@@ -310,6 +310,27 @@ wg_status wg_merge_keys(wg_engine* engine, const void* d_a, uint64_t na, const v
 wg_status wg_sort_keys_noalloc(void* d_keys, void* d_tmp, uint64_t n, uint32_t key_bytes, uint32_t key_bits,
                                void* stream);
 
+/* Synchronisation costs behind the loop policies of Section V-B, for the ablation that
+ * weighs a persistent launch against launches per stage.  barrier_us: one grid-wide barrier
+ * inside a single cooperative launch of `blocks` workgroups of 256 threads, every block
+ * arriving on one counter (a launch with `rounds` barriers against one with none);
+ * barrier2_us: the same with two levels, blocks arriving on one of 8 group counters (the
+ * device's XCDs, to which consecutive blocks are dealt in turn) and each group's last block
+ * on the top counter; barrier_cg_us: the runtime's own grid synchronisation for
+ * cooperative launches (cooperative groups' grid sync); launch_us: one kernel boundary (min(rounds, 512) empty launches of
+ * the same shape back to back on one in-order stream, all queued behind a 20 ms delay
+ * kernel before the timed window opens, so that the host's launch rate does not enter it).
+ * Microseconds per event, timed with HIP events on a stream of the call's own on `device`.
+ * The call allocates a few KB of device memory, waits for its work (about 20 ms longer than
+ * the events it times) and frees everything.
+ * WG_ERR_INVALID_ARG: a NULL output, blocks outside 1..2048 or beyond what can be resident
+ * at once on the device, rounds outside 1..1,000,000, or no such device;
+ * WG_ERR_DEVICE: no cooperative launch on the device, a failed launch, or a wait of the
+ * probe's own barriers that gave up (those waits are bounded, so their launches always end).
+ */
+wg_status wg_probe_sync_costs(int device, uint32_t blocks, uint32_t rounds, double* barrier_us,
+                              double* barrier2_us, double* barrier_cg_us, double* launch_us);
+
 /* Number of tuples in the result (for a batch: over all instances). */
 uint64_t wg_result_size(const wg_result* result);
 

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libwg.so")
-SOURCES = ["wg_kernels.hip", "wg_engine.hip", "wg_server.hip"]
+SOURCES = ["wg_kernels.hip", "wg_engine.hip", "wg_server.hip", "wg_probe.hip"]
 ARCH = os.environ.get("WG_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

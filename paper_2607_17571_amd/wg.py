@@ -196,6 +196,8 @@ SIGNATURES = [
     ("wg_job_get_info", c_int, [c_void_p, POINTER(WgJobInfo)]),
     ("wg_job_free", None, [c_void_p]),
     ("wg_server_get_stats", c_int, [c_void_p, POINTER(WgServerStats)]),
+    ("wg_probe_sync_costs", c_int, [c_int, c_uint32, c_uint32, POINTER(c_double), POINTER(c_double),
+                                    POINTER(c_double), POINTER(c_double)]),
     ("wg_result_size", c_uint64, [c_void_p]),
     ("wg_result_copy", c_int, [c_void_p, c_void_p, c_void_p, c_uint64, c_void_p]),
     ("wg_result_free", None, [c_void_p]),
@@ -299,6 +301,17 @@ def wg_sort_keys(engine, d_keys: int, d_tmp: int, n: int, key_bytes: int, key_bi
 def wg_sort_keys_noalloc(d_keys: int, d_tmp: int, n: int, key_bytes: int, key_bits: int, stream: int) -> int:
     return lib().wg_sort_keys_noalloc(c_void_p(d_keys), c_void_p(d_tmp), n, key_bytes, key_bits,
                                       c_void_p(stream))
+
+
+def wg_probe_sync_costs(device: int, blocks: int, rounds: int) -> tuple:
+    """wg_probe_sync_costs: microseconds per grid-wide barrier in one cooperative launch
+    (flat, two-level, the runtime's grid sync) and per dependent launch of an empty kernel
+    of the same shape."""
+    bar, bar2, bcg, lau = c_double(0.0), c_double(0.0), c_double(0.0), c_double(0.0)
+    st = lib().wg_probe_sync_costs(device, blocks, rounds, byref(bar), byref(bar2), byref(bcg), byref(lau))
+    if st != WG_OK:
+        raise WgError(st, "wg_probe_sync_costs")
+    return bar.value, bar2.value, bcg.value, lau.value
 
 
 def wg_merge_keys(engine, d_a: int, na: int, d_b: int, nb: int, d_out: int, key_bytes: int,

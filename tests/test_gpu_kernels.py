@@ -100,3 +100,18 @@ def test_kernel_calls_leave_the_result_valid(engine):
     k = torch.from_numpy(_keys(100_000, 30, np.uint32, 9)).cuda()
     engine.sort_keys(k, torch.empty_like(k), 30)
     assert np.array_equal(s.cpu().numpy(), ref.src) and np.array_equal(d.cpu().numpy(), ref.dst)
+
+
+def test_sync_probe():
+    """The synchronisation probe (grid-wide barrier in one cooperative launch against a
+    dependent launch) returns positive costs and rejects bad arguments."""
+    print("[gpu] sync probe 256 blocks", flush=True)
+    bar, bar2, bcg, lau = wg.wg_probe_sync_costs(0, 256, 200)
+    assert 0 < bar < 1000 and 0 < bar2 < 1000 and 0 < bcg < 1000 and 0 < lau < 1000
+    # one block: every barrier is a single arrival
+    bar, bar2, bcg, lau = wg.wg_probe_sync_costs(0, 1, 50)
+    assert bar < 1000 and bar2 < 1000 and bcg < 1000 and 0 < lau < 1000
+    for blocks, rounds in ((0, 10), (4096, 10), (256, 0)):
+        with pytest.raises(wg.WgError) as ei:
+            wg.wg_probe_sync_costs(0, blocks, rounds)
+        assert ei.value.status == wg.WG_ERR_INVALID_ARG
