@@ -14,7 +14,7 @@ namespace {
 constexpr uint32_t kProbeThreads = 256;
 constexpr uint32_t kProbeSpinLimit = 1u << 20;  // polls of one wait before it gives up
 constexpr uint32_t kProbeLaunchesMax = 512;     // empty launches timed (queued ahead of time)
-constexpr uint64_t kProbeDelayTicks = 2000000;  // 20 ms of the 100 MHz real-time clock
+constexpr uint64_t kProbeDelayUs = 20000;        // delay ahead of the timed launches
 
 // `rounds` grid-wide barriers.  state[0] counts the arrivals of the current round at the
 // top level, GEN is the round's generation, FAIL is set by a wait that gave up (every block
@@ -110,8 +110,9 @@ extern "C" wg_status wg_probe_sync_costs(int device, uint32_t blocks, uint32_t r
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return WG_ERR_INVALID_ARG;
   if (hipSetDevice(device) != hipSuccess) return WG_ERR_DEVICE;
-  int coop = 0, cus = 0, per_cu = 0;
+  int coop = 0, cus = 0, per_cu = 0, clock_khz = 0;
   if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess || !coop ||
+      hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || clock_khz <= 0 ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_grid_barrier_probe<1>, (int)kProbeThreads, 0) !=
           hipSuccess)
@@ -154,7 +155,8 @@ extern "C" wg_status wg_probe_sync_costs(int device, uint32_t blocks, uint32_t r
   // queued behind a delay so that the host's launch rate does not enter the window
   const uint32_t nl = rounds < kProbeLaunchesMax ? rounds : kProbeLaunchesMax;
   hipLaunchKernelGGL(k_empty_probe, dim3(blocks), dim3(kProbeThreads), 0, p.s, p.state);
-  hipLaunchKernelGGL(k_delay_probe, dim3(1), dim3(kProbeThreads), 0, p.s, kProbeDelayTicks);
+  const uint64_t delay_ticks = kProbeDelayUs * (uint64_t)clock_khz / 1000;  // (the real-time clock's rate)
+  hipLaunchKernelGGL(k_delay_probe, dim3(1), dim3(kProbeThreads), 0, p.s, delay_ticks);
   if (hipEventRecord(p.ev[4], p.s) != hipSuccess) return WG_ERR_DEVICE;
   for (uint32_t r = 0; r < nl; ++r) hipLaunchKernelGGL(k_empty_probe, dim3(blocks), dim3(kProbeThreads), 0, p.s, p.state);
   if (hipEventRecord(p.ev[5], p.s) != hipSuccess || hipGetLastError() != hipSuccess ||
