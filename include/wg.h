@@ -322,7 +322,8 @@ wg_status wg_sort_keys_noalloc(void* d_keys, void* d_tmp, uint64_t n, uint32_t k
  * kernel before the timed window opens, so that the host's launch rate does not enter it).
  * Microseconds per event, timed with HIP events on a stream of the call's own on `device`.
  * The call allocates a few KB of device memory, waits for its work (about 20 ms longer than
- * the events it times) and frees everything.
+ * the events it times), frees everything and leaves the calling thread's current device as
+ * it found it.
  * WG_ERR_INVALID_ARG: a NULL output, blocks outside 1..2048 or beyond what can be resident
  * at once on the device, rounds outside 1..1,000,000, or no such device;
  * WG_ERR_DEVICE: no cooperative launch on the device, a failed launch, or a wait of the

@@ -89,6 +89,17 @@ __global__ __launch_bounds__(kProbeThreads) void k_delay_probe(uint64_t ticks) {
   while (wall_clock64() - t0 < ticks) __builtin_amdgcn_s_sleep(8);
 }
 
+// The caller's current device, made current again when the call returns.
+struct DeviceRestore {
+  int prev = -1;
+  DeviceRestore() {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+  }
+  ~DeviceRestore() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
 struct ProbeRes {
   hipStream_t s = nullptr;
   hipEvent_t ev[6] = {};
@@ -109,6 +120,7 @@ extern "C" wg_status wg_probe_sync_costs(int device, uint32_t blocks, uint32_t r
     return WG_ERR_INVALID_ARG;
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return WG_ERR_INVALID_ARG;
+  const DeviceRestore restore;  // (destroyed last: after the probe's resources are freed)
   if (hipSetDevice(device) != hipSuccess) return WG_ERR_DEVICE;
   int coop = 0, cus = 0, per_cu = 0, clock_khz = 0;
   if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess || !coop ||
