@@ -241,6 +241,17 @@ def test_tail_loop_tc_fills_its_run(tail_harness, tmp_path):
     assert at_run > 0
 
 
+@pytest.mark.parametrize("kb,n,m", [(4, 4000, 3000), (8, 2400, 1800)])
+def test_tail_loop_tc_run_a_beyond_its_fences(tail_harness, tmp_path, kb, n, m):
+    """About 90% of the seed in run A: more keys than its LDS fences hold (2,048 32-bit or
+    1,024 64-bit samples), so every search of A takes the fences and then bisects a stretch
+    in HBM; the seed delta and every iteration still fit one block."""
+    from paper_2607_17571_amd import inputs
+    src, dst = inputs.erdos_renyi(n, m, seed=8)
+    assert 0.9 * np.unique((src.astype(np.uint64) << np.uint64(32)) | dst).size > (8192 // kb)
+    _tail_case(tail_harness, tmp_path, 0, src, dst, kb, split=0.1, jstep=40)
+
+
 def test_tail_loop_sg(tail_harness, tmp_path):
     from paper_2607_17571_amd import inputs
     src, dst = inputs.erdos_renyi(40, 60, seed=5)
